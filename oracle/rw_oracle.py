@@ -1,0 +1,617 @@
+"""Plain FP64 CPU oracle of the differentiable ray-wave hybrid PSF.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or
+links this module: it exists so that tests, the smoke check and the CPU
+baseline of the benchmark can compare the GPU library against a slow,
+obviously correct implementation written directly from the paper
+(arXiv 2605.15418, "A general differentiable ray-wave framework for hybrid
+refractive-diffractive system modeling and optimization").
+
+Everything is float64 / complex128 (NumPy for integer work, PyTorch CPU for
+the differentiable arithmetic so that torch.autograd supplies the oracle's
+gradients).  Each function names the passage of the paper it follows.
+Readings of passages that the paper leaves open are marked READING and are
+listed together in the design notes of the repository.
+
+Units: lengths in mm, wavelengths in mm, k0 = 2*pi/lambda in rad/mm.
+
+Pipeline for one (wavelength, field) pair  -- Results, "Ray-Wave Simulator
+Formalism", Fig. 1b/c, Eqs. 1-3:
+  launch -> conventional refractive trace to the DOE -> tangent frame ->
+  square patch of the complex transmission -> zero-padded FFT (angular
+  spectrum) -> propagating-mode cut -> sampling density p -> N secondary
+  wavevectors -> weights a = U~/p (Eq. 1) -> conventional trace to the sensor
+  -> coherent wavelet sum (Eq. 2) -> |U|^2 -> normalised least squares (Eq. 3).
+"""
+import math
+
+import numpy as np
+import torch
+
+from .philox import draw_uniforms
+
+DT = torch.float64
+CT = torch.complex128
+TWO_PI = 2.0 * math.pi
+
+
+def _t(x):
+    return torch.as_tensor(x, dtype=DT)
+
+
+# ----------------------------------------------------------------------------
+# Materials.  READING: the paper gives catalogue glasses only (N-BK7,
+# Benchmark section); a two-term Cauchy law n = A + B / lambda_um^2 stands in.
+# ----------------------------------------------------------------------------
+def cauchy_index(nA, nB, lam_mm):
+    lam_um = lam_mm * 1e3
+    return nA + nB / (lam_um * lam_um)
+
+
+# ----------------------------------------------------------------------------
+# System description with differentiable lens parameters.
+# A lens parameter value v maps to the physical quantity scale * v.  Fields:
+#   curv -> surface curvature c;  conic -> conic constant;
+#   A4..A10 -> even asphere coefficients;  gap -> axial distance from the
+#   surface to the next surface (or to the sensor after the last surface).
+# ----------------------------------------------------------------------------
+_FIELDS = ("curv", "conic", "A4", "A6", "A8", "A10", "gap")
+
+
+def build_surfaces(system, values=None):
+    surfs = system["surfaces"]
+    S = len(surfs)
+    c = [_t(s["c"]) for s in surfs]
+    kk = [_t(s["k"]) for s in surfs]
+    A = [[_t(a) for a in s["A"]] for s in surfs]
+    gaps = [_t(surfs[i + 1]["z"] - surfs[i]["z"]) for i in range(S - 1)]
+    gaps.append(_t(system["sensor_z"] - surfs[-1]["z"]))
+    if values is not None:
+        for ref, v in zip(system["params"], values):
+            s, f = ref["surface"], ref["field"]
+            phys = ref["scale"] * v
+            if f == "curv":
+                c[s] = phys
+            elif f == "conic":
+                kk[s] = phys
+            elif f in ("A4", "A6", "A8", "A10"):
+                A[s][("A4", "A6", "A8", "A10").index(f)] = phys
+            elif f == "gap":
+                gaps[s] = phys
+            else:
+                raise ValueError(f)
+    z = [_t(surfs[0]["z"])]
+    for i in range(S - 1):
+        z.append(z[-1] + gaps[i])
+    sensor_z = z[-1] + gaps[-1]
+    out = []
+    for i, s in enumerate(surfs):
+        out.append(dict(kind=s["kind"], z=z[i], c=c[i], k=kk[i], A=A[i],
+                        semi_ap=s["semi_ap"], nA=s["nA"], nB=s["nB"],
+                        doe=bool(s.get("doe", False))))
+    return out, sensor_z
+
+
+def initial_param_values(system):
+    """Normalised values reproducing the nominal prescription."""
+    surfs = system["surfaces"]
+    vals = []
+    for ref in system["params"]:
+        s, f = ref["surface"], ref["field"]
+        if f == "curv":
+            phys = surfs[s]["c"]
+        elif f == "conic":
+            phys = surfs[s]["k"]
+        elif f in ("A4", "A6", "A8", "A10"):
+            phys = surfs[s]["A"][("A4", "A6", "A8", "A10").index(f)]
+        else:
+            znext = surfs[s + 1]["z"] if s + 1 < len(surfs) else system["sensor_z"]
+            phys = znext - surfs[s]["z"]
+        vals.append(phys / ref["scale"])
+    return np.array(vals, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------
+# Even-asphere sag z(r) = c r^2 / (1 + sqrt(1 - (1+k) c^2 r^2)) + A4 r^4 + ...
+# Conventional ray tracing of refractive surfaces (Formalism, first paragraph;
+# Benchmark section, "propagated ... via conventional ray tracing").
+# ----------------------------------------------------------------------------
+def sag_and_grad(surf, x, y):
+    """Returns (sag, dsag/dx, dsag/dy, valid)."""
+    rho = x * x + y * y
+    c, k = surf["c"], surf["k"]
+    A4, A6, A8, A10 = surf["A"]
+    arg = 1.0 - (1.0 + k) * c * c * rho
+    valid = arg > 0
+    arg_s = torch.where(valid, arg, torch.ones_like(arg))
+    sq = torch.sqrt(arg_s)
+    sag = c * rho / (1.0 + sq) + A4 * rho ** 2 + A6 * rho ** 3 + A8 * rho ** 4 + A10 * rho ** 5
+    dsdrho = c / (2.0 * sq) + 2.0 * A4 * rho + 3.0 * A6 * rho ** 2 + 4.0 * A8 * rho ** 3 \
+        + 5.0 * A10 * rho ** 4
+    return sag, 2.0 * x * dsdrho, 2.0 * y * dsdrho, valid
+
+
+def intersect(surf, p, d, tol=1e-13, max_iter=30):
+    """Ray-sag intersection by Newton's method on f(t) = p_z + t d_z - z_v - sag(x(t), y(t)).
+
+    The iteration starts at the vertex plane and runs without autograd; one
+    final Newton step with autograd gives the exact first-order derivative of
+    the root (implicit function theorem).  Returns (t, valid).
+    """
+    zv = surf["z"]
+    with torch.no_grad():
+        pd, dd, zvd = p.detach(), d.detach(), zv.detach() if torch.is_tensor(zv) else zv
+        sd = {kk: (v.detach() if torch.is_tensor(v) else v) for kk, v in surf.items() if kk != "A"}
+        sd["A"] = [a.detach() for a in surf["A"]]
+        t = (zvd - pd[:, 2]) / dd[:, 2]
+        ok = torch.ones_like(t, dtype=torch.bool)
+        conv = torch.zeros_like(ok)
+        for _ in range(max_iter):
+            x = pd[:, 0] + t * dd[:, 0]
+            y = pd[:, 1] + t * dd[:, 1]
+            s, sx, sy, v = sag_and_grad(sd, x, y)
+            f = pd[:, 2] + t * dd[:, 2] - zvd - s
+            fp = dd[:, 2] - sx * dd[:, 0] - sy * dd[:, 1]
+            ok = ok & v & (fp.abs() > 1e-300)
+            step = torch.where(ok, f / torch.where(ok, fp, torch.ones_like(fp)), torch.zeros_like(f))
+            t = t - step
+            conv = step.abs() < tol
+            if bool(torch.all(conv | ~ok)):
+                break
+        ok = ok & conv
+    t0 = t
+    x = p[:, 0] + t0 * d[:, 0]
+    y = p[:, 1] + t0 * d[:, 1]
+    s, sx, sy, v = sag_and_grad(surf, x, y)
+    f = p[:, 2] + t0 * d[:, 2] - zv - s
+    fp = d[:, 2] - sx * d[:, 0] - sy * d[:, 1]
+    fp = torch.where(ok, fp, torch.ones_like(fp))
+    t = t0 - torch.where(ok, f, torch.zeros_like(f)) / fp
+    return t, ok & v
+
+
+def surface_normal(surf, x, y):
+    """Unit normal (-s_x, -s_y, 1)/|.|, oriented along +z (propagation side)."""
+    _, sx, sy, _ = sag_and_grad(surf, x, y)
+    n = torch.stack([-sx, -sy, torch.ones_like(sx)], dim=-1)
+    return n / torch.linalg.norm(n, dim=-1, keepdim=True)
+
+
+def refract(d, nrm, n1, n2):
+    """Vector Snell law, normal oriented with the ray: d' = mu d + (cos_t - mu cos_i) N."""
+    mu = n1 / n2
+    cos_i = (d * nrm).sum(-1)
+    rad = 1.0 - mu * mu * (1.0 - cos_i * cos_i)
+    ok = rad > 0
+    cos_t = torch.sqrt(torch.where(ok, rad, torch.ones_like(rad)))
+    dn = mu * d + (cos_t - mu * cos_i)[:, None] * nrm
+    return dn, ok
+
+
+def medium_index(surfs, s, lam):
+    """Index of the medium after surface s (s = -1: the object-side air)."""
+    if s < 0:
+        return 1.0
+    return cauchy_index(surfs[s]["nA"], surfs[s]["nB"], lam)
+
+
+# ----------------------------------------------------------------------------
+# Launch.  READING: rays uniformly sampled over the entrance pupil (Benchmark
+# section, Systems 1 and 3 and the conformal DOE) as an R x R grid on the
+# launch plane; a flat incident wavefront, OPL_0 = d . P_0.
+# ----------------------------------------------------------------------------
+def launch(cfg, f_idx):
+    R = cfg["rays_side"]
+    tx, ty = cfg["fields"][f_idx]
+    cx, cy = cfg["launch_center"][f_idx]
+    h = cfg["launch_half"]
+    g = (np.arange(R) + 0.5) / R * 2.0 - 1.0
+    X = cx + g[None, :] * h
+    Y = cy + g[:, None] * h
+    P0 = np.stack([np.broadcast_to(X, (R, R)), np.broadcast_to(Y, (R, R)),
+                   np.full((R, R), cfg["launch_z"])], axis=-1).reshape(-1, 3)
+    d = np.array([tx, ty, 1.0])
+    d = d / np.linalg.norm(d)
+    D = np.broadcast_to(d, P0.shape).copy()
+    opl = P0 @ d
+    return _t(P0), _t(D), _t(opl)
+
+
+def trace_to_doe(surfs, lam, p, d, opl):
+    """Sequential trace through the surfaces before the DOE, then the DOE hit.
+
+    Each refractive surface: Newton intersection, aperture clip, OPL += n t,
+    vector Snell.  The DOE surface: intersection and OPL only (its refraction
+    is part of the emission of secondary rays).  Returns p, d, opl, alive,
+    index of the DOE surface.
+    """
+    alive = torch.ones(p.shape[0], dtype=torch.bool)
+    n_before = 1.0
+    for s, surf in enumerate(surfs):
+        t, ok = intersect(surf, p, d)
+        alive = alive & ok
+        t = torch.where(alive, t, torch.zeros_like(t))
+        p = p + t[:, None] * d
+        opl = opl + n_before * t
+        if surf["semi_ap"] > 0:
+            alive = alive & ((p[:, 0] ** 2 + p[:, 1] ** 2) <= surf["semi_ap"] ** 2)
+        if surf["doe"]:
+            return p, d, opl, alive, s
+        n_after = medium_index(surfs, s, lam)
+        nrm = surface_normal(surf, p[:, 0], p[:, 1])
+        dn, ok = refract(d, nrm, n_before, n_after)
+        alive = alive & ok
+        d = torch.where(alive[:, None], dn, d)
+        n_before = n_after
+    raise ValueError("system has no DOE surface")
+
+
+# ----------------------------------------------------------------------------
+# Tangent frame at the ray-DOE intersection (Formalism, second paragraph).
+# READING: u = normalised projection of the global x axis on the tangent
+# plane, v = n x u; a planar DOE gives u = x, v = y, n = z.
+# ----------------------------------------------------------------------------
+def tangent_frame(surf, p):
+    n = surface_normal(surf, p[:, 0], p[:, 1])
+    ex = torch.zeros_like(n)
+    ex[:, 0] = 1.0
+    u = ex - (ex * n).sum(-1, keepdim=True) * n
+    u = u / torch.linalg.norm(u, dim=-1, keepdim=True)
+    v = torch.cross(n, u, dim=-1)
+    return u, v, n
+
+
+# ----------------------------------------------------------------------------
+# DOE patch (Formalism, second paragraph; conformal DOE defined "as projected
+# to a flat xy-plane", last demonstration).  READING: P x P samples at the DOE
+# pitch centred on the hit, s_m = (m - (P-1)/2) pitch; bilinear interpolation
+# of the complex transmission t = A exp(i phi) at the xy projection of each
+# sample point; t = 0 outside the map.
+# ----------------------------------------------------------------------------
+def cis(x):
+    """exp(i x) for real x, differentiable."""
+    return torch.complex(torch.cos(x), torch.sin(x))
+
+
+def transmission(phase, amp):
+    return torch.complex(amp * torch.cos(phase), amp * torch.sin(phase))
+
+
+def bilinear_complex(tmap, doe, qx, qy):
+    H, W = tmap.shape
+    fx = (qx - doe["x0"]) / doe["pitch"]
+    fy = (qy - doe["y0"]) / doe["pitch"]
+    ix = torch.floor(fx.detach())
+    iy = torch.floor(fy.detach())
+    wx = fx - ix
+    wy = fy - iy
+    ix = ix.long()
+    iy = iy.long()
+    out = torch.zeros(qx.shape, dtype=CT)
+    for dy, wyv in ((0, 1.0 - wy), (1, wy)):
+        for dx, wxv in ((0, 1.0 - wx), (1, wx)):
+            jx = ix + dx
+            jy = iy + dy
+            inside = (jx >= 0) & (jx < W) & (jy >= 0) & (jy < H)
+            val = tmap[jy.clamp(0, H - 1), jx.clamp(0, W - 1)]
+            val = torch.where(inside, val, torch.zeros_like(val))
+            out = out + (wxv * wyv) * val
+    return out
+
+
+def patch_field(tmap, doe, p, u, v, P):
+    """U[r, n, m] = t(xy(p + s_m u + s_n v)) -- rows along v, columns along u."""
+    pitch = doe["pitch"]
+    s = (torch.arange(P, dtype=DT) - (P - 1) / 2.0) * pitch
+    q = p[:, None, None, :] + s[None, None, :, None] * u[:, None, None, :] \
+        + s[None, :, None, None] * v[:, None, None, :]
+    return bilinear_complex(tmap, doe, q[..., 0], q[..., 1])
+
+
+# ----------------------------------------------------------------------------
+# Local angular spectrum (Formalism, second paragraph; zero padding in the
+# patch-size study and System 3).  Plain definition:
+#   U~[j] = sum_{m,n} U[n,m] exp(-i kappa_j . (s_m, s_n)),
+#   kappa_j = 2 pi j / (M pitch), j in [-M/2, M/2)^2, M = pad * P.
+# Evaluated as a zero-padded FFT times the phase of the patch-centre reference.
+# Output is in shifted order: index (j_y + M/2, j_x + M/2).
+# ----------------------------------------------------------------------------
+def angular_spectrum(U, M):
+    R, P, _ = U.shape
+    X = torch.fft.fft2(U, s=(M, M))
+    j = torch.arange(M) - M // 2
+    idx = torch.remainder(j, M)
+    X = X[:, idx][:, :, idx]
+    ph = math.pi * (P - 1) / M * j.to(DT)
+    ref = cis(ph[:, None] + ph[None, :])
+    return X * ref[None]
+
+
+def angular_spectrum_bruteforce(U, M, pitch=1.0):
+    """The explicit double sum of the definition, for tiny inputs only."""
+    R, P, _ = U.shape
+    s = (np.arange(P) - (P - 1) / 2.0) * pitch
+    kap = 2 * np.pi * (np.arange(M) - M // 2) / (M * pitch)
+    E = np.exp(-1j * kap[:, None] * s[None, :])   # [j, m]
+    Un = U.detach().numpy()
+    # out[r, j_y, j_x] = sum_{n, m} U[r, n, m] E[j_x, m] E[j_y, n]
+    return np.einsum("rnm,am,bn->rba", Un, E, E)
+
+
+def wavevectors(k_in_t, M, pitch):
+    """K_j = k_in,t + kappa_j  (tilt as a continuous shift; READING)."""
+    kap = TWO_PI * (torch.arange(M, dtype=DT) - M // 2) / (M * pitch)
+    Ku = k_in_t[:, 0, None, None] + kap[None, None, :]
+    Kv = k_in_t[:, 1, None, None] + kap[None, :, None]
+    return Ku.expand(-1, M, M), Kv.expand(-1, M, M)
+
+
+# ----------------------------------------------------------------------------
+# Sampling of secondary wavevectors and their weights (Formalism, Eq. 1, the
+# reparameterised sampling of Fig. 1c, and the sampling-density study).
+#   MAG : p_j = |U~_j| / S over propagating bins, S = sum |U~|
+#   UNI : p_j = 1 / |Pi|
+#   FULL: every propagating bin once, weight U~_j / M^2 (the deterministic
+#         limit that the Monte Carlo estimate converges to).
+# Draw by inverse CDF in shifted row-major bin order: J = min{j : C_j > u S},
+# distributionally identical to the arg-max of N Gumbel-perturbed replicas of
+# log p (Gumbel-max theorem).  READING: weight = U~_J / (M^2 N p_J): the
+# Monte Carlo mean of Eq. 1 with the 1/N and 1/M^2 normalisations.
+# ----------------------------------------------------------------------------
+def draw_bins(mag, prop, u, sampling):
+    """mag, prop: [R, M*M] (numpy, shifted row-major bin order); u: [R, N].
+    Returns J [R, N] (int64, -1 where the ray has no propagating weight) and S [R]."""
+    w = np.where(prop, mag if sampling == "mag" else 1.0, 0.0)
+    cdf = np.cumsum(w, axis=1)
+    S = cdf[:, -1]
+    J = np.full(u.shape, -1, dtype=np.int64)
+    for r in range(u.shape[0]):
+        if S[r] > 0:
+            last = int(np.nonzero(w[r] > 0)[0][-1])
+            J[r] = np.minimum(np.searchsorted(cdf[r], u[r] * S[r], side="right"), last)
+    return J, S
+
+
+# ----------------------------------------------------------------------------
+# Conventional trace of secondary rays to the sensor and the coherent sensor
+# field of Eq. 2:  U(x, y) = sum_i a_i exp[i k (OPL_i + dr_i(x, y))] <n, d_i>,
+# READING: dr = n_s d . (X - r_s) (plane-wave tilt across the sensor),
+# <n, d> = |d_z|, point samples at pixel centres X = X_c + (m, n) pitch.
+# ----------------------------------------------------------------------------
+def trace_post_doe(surfs, s_doe, lam, p, d, opl, sensor_z):
+    alive = torch.ones(p.shape[0], dtype=torch.bool)
+    n_before = medium_index(surfs, s_doe, lam)
+    for s in range(s_doe + 1, len(surfs)):
+        surf = surfs[s]
+        t, ok = intersect(surf, p, d)
+        alive = alive & ok
+        t = torch.where(alive, t, torch.zeros_like(t))
+        p = p + t[:, None] * d
+        opl = opl + n_before * t
+        if surf["semi_ap"] > 0:
+            alive = alive & ((p[:, 0] ** 2 + p[:, 1] ** 2) <= surf["semi_ap"] ** 2)
+        n_after = medium_index(surfs, s, lam)
+        nrm = surface_normal(surf, p[:, 0], p[:, 1])
+        dn, ok = refract(d, nrm, n_before, n_after)
+        alive = alive & ok
+        d = torch.where(alive[:, None], dn, d)
+        n_before = n_after
+    t = (sensor_z - p[:, 2]) / d[:, 2]
+    alive = alive & (t > 0)
+    p = p + t[:, None] * d
+    opl = opl + n_before * t
+    return p, d, opl, alive, n_before
+
+
+def sensor_field(amp, phi0, wx, wy, Q, chunk=1 << 15):
+    """Direct Eq. 2 on the Q x Q pixel grid as separable complex128 products:
+    U[n, m] = sum_s c_s exp(i wx_s m) exp(i wy_s n), m, n in [-Q/2, Q/2)."""
+    m = torch.arange(Q, dtype=DT) - Q // 2
+    U = torch.zeros(Q, Q, dtype=CT)
+    Ns = amp.shape[0]
+    for a in range(0, Ns, chunk):
+        b = min(Ns, a + chunk)
+        c = amp[a:b] * cis(phi0[a:b])
+        Ex = cis(wx[a:b, None] * m[None, :])
+        Ey = cis(wy[a:b, None] * m[None, :])
+        U = U + Ey.transpose(0, 1) @ (c[:, None] * Ex)
+    return U
+
+
+# ----------------------------------------------------------------------------
+# One (wavelength, field) pair, end to end.
+# ----------------------------------------------------------------------------
+def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
+                 keep=False, ray_subset=None):
+    """Returns dict with field U [Q, Q] (complex, differentiable), PSF, and
+    (if keep) intermediate quantities for stage-level comparison."""
+    surfs, sensor_z = build_surfaces(system, values)
+    doe = system["doe"]
+    lam = cfg["lambdas"][lam_idx]
+    k0 = TWO_PI / lam
+    P = cfg["patch_p"]
+    M = cfg["pad"] * P
+    Nd = cfg["n_ssr"]
+    Q = cfg["psf_q"]
+    F = len(cfg["fields"])
+    pair = lam_idx * F + f_idx
+    sampling = cfg["sampling"]
+
+    p, d, opl = launch(cfg, f_idx)
+    ray_ids = np.arange(p.shape[0])
+    if ray_subset is not None:
+        ray_ids = np.asarray(ray_subset)
+        p, d, opl = p[ray_ids], d[ray_ids], opl[ray_ids]
+    p, d, opl, alive, s_doe = trace_to_doe(surfs, lam, p, d, opl)
+    # The DOE is the stop: rays outside the map are terminated (READING).
+    H, W = tmap.shape
+    fx = (p[:, 0] - doe["x0"]) / doe["pitch"]
+    fy = (p[:, 1] - doe["y0"]) / doe["pitch"]
+    alive = alive & (fx >= -0.5) & (fx <= W - 0.5) & (fy >= -0.5) & (fy <= H - 0.5)
+    out = {}
+    if keep:
+        out.update(p_doe=p.detach().clone(), d_doe=d.detach().clone(),
+                   opl_doe=opl.detach().clone(), alive=alive.clone(), ray_ids=ray_ids)
+    amp_in = alive.to(DT)          # READING: unit amplitude per live ray
+    surf_doe = surfs[s_doe]
+    n_in = medium_index(surfs, s_doe - 1, lam)
+    n_out = medium_index(surfs, s_doe, lam)
+    k_out = k0 * n_out
+    u, v, nrm = tangent_frame(surf_doe, p)
+    k_in_t = k0 * n_in * torch.stack([(d * u).sum(-1), (d * v).sum(-1)], dim=-1)
+
+    Upatch = patch_field(tmap, doe, p, u, v, P)
+    Ut = angular_spectrum(Upatch, M)                        # [R, M, M]
+    Ku, Kv = wavevectors(k_in_t, M, doe["pitch"])
+    K2 = Ku * Ku + Kv * Kv
+    prop = (K2 < k_out * k_out) & alive[:, None, None]
+    R = p.shape[0]
+    Utf = Ut.reshape(R, M * M)
+    propf = prop.reshape(R, M * M)
+    if sampling == "full":
+        rr, jj = torch.nonzero(propf, as_tuple=True)
+        w = Utf[rr, jj] / (M * M)
+        J = None
+    else:
+        mag = Utf.detach().abs().numpy()
+        pn = propf.numpy()
+        if replay is not None:
+            J = np.asarray(replay, dtype=np.int64).reshape(R, Nd)
+        else:
+            uu = draw_uniforms(cfg["seed"], pair, ray_ids, Nd)
+            J, _ = draw_bins(mag, pn, uu, sampling)
+        rr = torch.arange(R).repeat_interleave(Nd)
+        jj = torch.as_tensor(np.maximum(J, 0).reshape(-1))
+        UJ = Utf[rr, jj]
+        valid = torch.as_tensor((J >= 0).reshape(-1)) & propf[rr, jj]
+        zero = torch.zeros_like(UJ)
+        if sampling == "mag":
+            Sg = torch.where(propf, Utf.abs(), torch.zeros((), dtype=DT)).sum(1)
+            if cfg.get("detach_pdf", False):
+                Sg = Sg.detach()
+            magJ = UJ.abs()
+            ok = valid & (magJ > 0)
+            magJ = torch.where(ok, magJ, torch.ones_like(magJ))
+            w = torch.where(ok, UJ * (Sg[rr] / (M * M * Nd * magJ)), zero)
+        else:
+            nprop = propf.sum(1).to(DT)
+            w = torch.where(valid, UJ * (nprop[rr] / (M * M * Nd)), zero)
+    # Emission: direction from the tangential wavevector (Formalism; READING Q1).
+    jy = jj // M
+    jx = jj % M
+    Kus = Ku[rr, jy, jx]
+    Kvs = Kv[rr, jy, jx]
+    kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs
+    kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
+    ds = (Kus[:, None] * u[rr] + Kvs[:, None] * v[rr] + kz[:, None] * nrm[rr]) / k_out
+    a_s = amp_in[rr] * w
+    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z)
+    a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
+    lc = cfg["psf_center"][lam_idx][f_idx]
+    Xc = torch.stack([_t(lc[0]), _t(lc[1]), sensor_z * torch.ones((), dtype=DT)])
+    phi0 = k0 * (opls + n_s * (dsn * (Xc[None, :] - ps)).sum(-1))
+    wx = k0 * n_s * cfg["psf_pitch"] * dsn[:, 0]
+    wy = k0 * n_s * cfg["psf_pitch"] * dsn[:, 1]
+    amp = a_s * dsn[:, 2].abs()
+    U = sensor_field(amp, phi0, wx, wy, Q)
+    out["U"] = U
+    out["psf"] = (U.real ** 2 + U.imag ** 2)
+    if keep:
+        out.update(spectrum=Ut.detach(), prop=prop, k_in_t=k_in_t.detach(),
+                   J=J, amp=amp.detach(), phi0=phi0.detach(), wx=wx.detach(),
+                   wy=wy.detach(), w=w.detach(), frame=(u.detach(), v.detach(), nrm.detach()))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Whole stack, loss (Eq. 3) and gradients.
+# ----------------------------------------------------------------------------
+def eq3_loss(I, T):
+    """Normalised least squares of Eq. 3 with the closed-form optimal alpha
+    (READING: alpha* = <I,T>/<I,I> per PSF)."""
+    ii = (I * I).sum()
+    it = (I * T).sum()
+    alpha = it / ii
+    return ((alpha * I - T) ** 2).sum()
+
+
+def psf_stack(system, cfg, phase, amp, values=None, replays=None, pairs=None, keep=False):
+    """PSF stack [L, F, Q, Q] (numpy) plus per-pair aux dicts."""
+    L = len(cfg["lambdas"])
+    F = len(cfg["fields"])
+    Q = cfg["psf_q"]
+    tmap = transmission(_t(phase), _t(amp))
+    vals = None if values is None else _t(values)
+    out = np.zeros((L, F, Q, Q))
+    aux = {}
+    with torch.no_grad():
+        for l in range(L):
+            for f in range(F):
+                pr = l * F + f
+                if pairs is not None and pr not in pairs:
+                    continue
+                rep = None if replays is None else replays.get(pr)
+                r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=keep)
+                out[l, f] = r["psf"].numpy()
+                aux[pr] = r
+    return out, aux
+
+
+def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_grad=True):
+    """Eq. 3 summed over all pairs and its gradient w.r.t. the DOE phase map,
+    the amplitude map and the normalised lens parameters (torch autograd in
+    float64; frozen draws, i.e. the a.e. derivative with the index set fixed)."""
+    L = len(cfg["lambdas"])
+    F = len(cfg["fields"])
+    ph = _t(phase).clone().requires_grad_(want_grad)
+    am = _t(amp).clone().requires_grad_(want_grad)
+    vals = _t(values).clone().requires_grad_(want_grad)
+    total = 0.0
+    psfs = np.zeros((L, F, cfg["psf_q"], cfg["psf_q"]))
+    idx = {}
+    for l in range(L):
+        for f in range(F):
+            pr = l * F + f
+            tmap = transmission(ph, am)
+            rep = None if replays is None else replays.get(pr)
+            r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=True)
+            Lp = eq3_loss(r["psf"], _t(target[l, f]))
+            if want_grad:
+                Lp.backward()
+            total += float(Lp.detach())
+            psfs[l, f] = r["psf"].detach().numpy()
+            idx[pr] = r["J"]
+    g = None
+    if want_grad:
+        g = dict(phase=ph.grad.numpy().copy(), amp=am.grad.numpy().copy(),
+                 lens=vals.grad.numpy().copy())
+    return total, g, psfs, idx
+
+
+# ----------------------------------------------------------------------------
+# Figures of merit (patch-size study).
+# ----------------------------------------------------------------------------
+def ncc(I, Igt):
+    I = np.asarray(I, dtype=np.float64)
+    Igt = np.asarray(Igt, dtype=np.float64)
+    return float((Igt * I).sum() / math.sqrt((Igt ** 2).sum() * (I ** 2).sum()))
+
+
+def mse(I, Igt):
+    return float(np.mean((np.asarray(I) - np.asarray(Igt)) ** 2))
+
+
+def curvature_error_bound(D, R):
+    """Upper bound of the curvature-induced angular-spectrum error for a flat
+    patch of side D on a surface of radius R (patch-size study, curvature
+    bound): eps <= arcsin(D / 2R)."""
+    return math.asin(D / (2.0 * R))
+
+
+def largest_patch(candidates_p, pitch, R_loc, eps):
+    """Largest patch side (in samples) whose curvature bound stays below eps."""
+    best = None
+    for P in sorted(candidates_p):
+        if P * pitch <= 2 * R_loc and curvature_error_bound(P * pitch, R_loc) <= eps:
+            best = P
+    return best

@@ -1,0 +1,216 @@
+"""Seeded synthetic inputs for the ray-wave hybrid PSF: optical prescriptions,
+DOE maps, launch grids, sensor windows and targets.
+
+This module holds none of the method's arithmetic: it only lays out inputs
+(shapes, sizes, value distributions) shaped like the systems of the paper's
+benchmark and design demonstrations.  Both the GPU library's tests/benchmark
+and the CPU oracle consume its output; neither is imported here.
+
+A workload is (system, cfg, maps):
+  system: {"surfaces": [...], "sensor_z", "doe": {...}, "params": [...]}
+  cfg:    wavelengths, field tangents, launch grid, patch / sampling / PSF
+          settings, seed
+  maps:   {"phase": float32 [H, W], "amp": float32 [H, W], "target": float32
+          [L, F, Q, Q] or None}
+Lengths are mm; wavelengths are mm.
+"""
+import math
+
+import numpy as np
+from scipy import special
+
+# Two-term Cauchy coefficients (A, B[um^2]) fitted to (n_d, V_d) of the
+# catalogue glasses -- stand-ins, since catalogue dispersion data is not at hand.
+BK7 = (1.504586, 0.0042172)    # n_d 1.5168, V_d 64.17
+F2 = (1.594154, 0.0089237)     # n_d 1.6200, V_d 36.37
+AIR = (1.0, 0.0)
+
+LAM_D = 587.6e-6
+LAM_F = 486.1e-6
+LAM_C = 656.3e-6
+
+PARAM_FIELDS = ("curv", "conic", "A4", "A6", "A8", "A10", "gap")
+
+
+def surface(z, c=0.0, k=0.0, A=(0.0, 0.0, 0.0, 0.0), semi_ap=0.0, medium=AIR, doe=False):
+    return {"kind": "plane" if (c == 0.0 and not any(A)) else "asphere",
+            "z": float(z), "c": float(c), "k": float(k), "A": [float(a) for a in A],
+            "semi_ap": float(semi_ap), "nA": float(medium[0]), "nB": float(medium[1]),
+            "doe": bool(doe)}
+
+
+def doe_desc(H, W, pitch, cx=0.0, cy=0.0):
+    """Map of H x W pixels at `pitch`, centred on (cx, cy); pixel (iy, ix)
+    has its centre at (x0 + ix pitch, y0 + iy pitch)."""
+    return {"H": int(H), "W": int(W), "pitch": float(pitch),
+            "x0": float(cx - (W - 1) / 2.0 * pitch), "y0": float(cy - (H - 1) / 2.0 * pitch)}
+
+
+def bandlimited_uniform(H, W, cutoff, rng):
+    """White Gaussian field -> radial low-pass at `cutoff` cycles/pixel ->
+    standardise -> normal CDF: a band-limited field with uniform marginals."""
+    g = rng.standard_normal((H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.fftfreq(W)[None, :]
+    lp = (fx * fx + fy * fy) <= cutoff * cutoff
+    f = np.real(np.fft.ifft2(np.fft.fft2(g) * lp))
+    f = (f - f.mean()) / max(f.std(), 1e-30)
+    return special.ndtr(f)
+
+
+def kinoform_zone_plate(doe, f, lam0):
+    """phi = mod(-pi r^2 / (lam0 f), 2 pi) on the pixel centres."""
+    x = doe["x0"] + np.arange(doe["W"]) * doe["pitch"]
+    y = doe["y0"] + np.arange(doe["H"]) * doe["pitch"]
+    r2 = x[None, :] ** 2 + y[:, None] ** 2
+    return np.mod(-math.pi * r2 / (lam0 * f), 2 * math.pi)
+
+
+def airy_target(Q, pitch, lam, NA, center_px, rng_off):
+    """Airy intensity (2 J1(v)/v)^2, v = 2 pi NA r / lam, unit sum."""
+    c = np.arange(Q) - Q // 2
+    X = (c[None, :] - center_px[0] - rng_off[0]) * pitch
+    Y = (c[:, None] - center_px[1] - rng_off[1]) * pitch
+    v = 2 * math.pi * NA * np.sqrt(X * X + Y * Y) / lam
+    vs = np.where(v == 0, 1.0, v)
+    I = np.where(v == 0, 1.0, (2 * special.j1(vs) / vs) ** 2)
+    return I / I.sum()
+
+
+def field_grid(max_deg, n):
+    a = np.tan(np.deg2rad(np.linspace(-max_deg, max_deg, n))) if n > 1 else np.zeros(1)
+    return [[float(tx), float(ty)] for ty in a for tx in a]
+
+
+def _launch_centres(fields, z_stop, z_launch):
+    """Straight back-projection of the stop centre along each field direction."""
+    return [[-tx * (z_stop - z_launch), -ty * (z_stop - z_launch)] for tx, ty in fields]
+
+
+def _psf_centres(lambdas, fields, dz):
+    return [[[tx * dz, ty * dz] for tx, ty in fields] for _ in lambdas]
+
+
+def _cfg(lambdas, fields, z_stop, z_launch, launch_half, rays_side, Q, psf_pitch, dz_sensor,
+         P, N, sampling="mag", pad=2, seed=0):
+    return {"lambdas": [float(l) for l in lambdas], "fields": fields,
+            "launch_center": _launch_centres(fields, z_stop, z_launch),
+            "launch_z": float(z_launch), "launch_half": float(launch_half),
+            "rays_side": int(rays_side), "psf_q": int(Q), "psf_pitch": float(psf_pitch),
+            "psf_center": _psf_centres(lambdas, fields, dz_sensor),
+            "patch_p": int(P), "pad": int(pad), "n_ssr": int(N), "sampling": sampling,
+            "seed": int(seed)}
+
+
+# ----------------------------------------------------------------------------
+# Workload 1: BK7 singlet (R1 = +50, R2 = -50, CT 5, semi-aperture 5) followed
+# 1 mm behind its rear vertex by a planar 256 x 256 kinoform zone plate
+# (f = 100 mm at 587.6 nm, 4 um pitch) that is also the stop; 64 x 64 rays,
+# 32 x 32 patches, 128 x 128 PSF at 2 um, one wavelength on axis.
+# Sensor 31.758 mm after the DOE (paraxial focus of lens + zone plate).
+# ----------------------------------------------------------------------------
+def singlet_zoneplate(rays_side=64, H=256, pitch=0.004, P=32, N=256, Q=128, psf_pitch=0.002,
+                      sampling="mag", seed=0):
+    z_doe = 6.0
+    surfs = [surface(0.0, c=1 / 50.0, semi_ap=5.0, medium=BK7),
+             surface(5.0, c=-1 / 50.0, semi_ap=5.0, medium=AIR),
+             surface(z_doe, doe=True)]
+    dz = 31.758
+    system = {"surfaces": surfs, "sensor_z": z_doe + dz, "doe": doe_desc(H, H, pitch),
+              "params": [{"surface": 0, "field": "curv", "scale": 1 / 50.0},
+                         {"surface": 1, "field": "curv", "scale": 1 / 50.0}]}
+    half = 0.5 * (H * pitch) / 1.024
+    cfg = _cfg([LAM_D], [[0.0, 0.0]], z_doe, -1.0, half, rays_side, Q, psf_pitch, dz, P, N,
+               sampling, seed=seed)
+    phase = kinoform_zone_plate(system["doe"], 100.0, LAM_D)
+    maps = {"phase": phase.astype(np.float32), "amp": np.ones_like(phase, dtype=np.float32),
+            "target": None}
+    return system, cfg, maps
+
+
+# ----------------------------------------------------------------------------
+# Workloads 2 and 3: equiconvex BK7 even asphere (R = +-25.14, CT 4, EFL 25)
+# with A4, A6 ~ N(0, 1e-6) per surface, then a planar 1024 x 1024 random
+# holographic complex DOE at 1 um pitch 1 mm behind the rear vertex (the
+# stop).  Phase uniform on [0, 2 pi), amplitude uniform on [0.5, 1], both
+# band-limited to 0.25 cycles/pixel.  3 wavelengths (F, d, C lines), 3 x 3
+# fields up to +-10 deg, 256 x 256 rays per field, 64 x 64 patches, 512 x 512
+# PSF at 1 um.  Workload 3 adds Airy targets for Eq. 3 and six lens
+# parameters (2 curvatures, 4 asphere coefficients).
+# ----------------------------------------------------------------------------
+def asphere_hologram(rays_side=256, H=1024, pitch=0.001, P=64, N=256, Q=512, psf_pitch=0.001,
+                     n_lambda=3, n_field_side=3, max_deg=10.0, sampling="mag", seed=0,
+                     with_target=True, cfg_id=2):
+    rng_a = np.random.default_rng(20260100 + cfg_id)
+    A1 = rng_a.normal(0.0, 1e-6, 2)
+    A2 = rng_a.normal(0.0, 1e-6, 2)
+    R = 25.140
+    z_doe = 5.0
+    surfs = [surface(0.0, c=1 / R, A=(A1[0], A1[1], 0, 0), semi_ap=5.0, medium=BK7),
+             surface(4.0, c=-1 / R, A=(A2[0], A2[1], 0, 0), semi_ap=5.0, medium=AIR),
+             surface(z_doe, doe=True)]
+    # keep the surfaces aspheric in the description even if coefficients are small
+    surfs[0]["kind"] = surfs[1]["kind"] = "asphere"
+    dz = 22.645
+    r_fp = 0.55
+    s4 = LAM_D / r_fp ** 4
+    s6 = LAM_D / r_fp ** 6
+    system = {"surfaces": surfs, "sensor_z": z_doe + dz, "doe": doe_desc(H, H, pitch),
+              "params": [{"surface": 0, "field": "curv", "scale": 1 / R},
+                         {"surface": 1, "field": "curv", "scale": 1 / R},
+                         {"surface": 0, "field": "A4", "scale": s4},
+                         {"surface": 0, "field": "A6", "scale": s6},
+                         {"surface": 1, "field": "A4", "scale": s4},
+                         {"surface": 1, "field": "A6", "scale": s6}]}
+    lambdas = [LAM_F, LAM_D, LAM_C][:n_lambda] if n_lambda <= 3 else \
+        list(np.linspace(400e-6, 700e-6, n_lambda))
+    fields = field_grid(max_deg, n_field_side)
+    half = 0.45 * (H * pitch) / 1.024
+    cfg = _cfg(lambdas, fields, z_doe, -1.0, half, rays_side, Q, psf_pitch, dz, P, N, sampling,
+               seed=seed)
+    rng = np.random.default_rng(20260000 + cfg_id)
+    phase = 2 * math.pi * bandlimited_uniform(H, H, 0.25, rng)
+    amp = 0.5 + 0.5 * bandlimited_uniform(H, H, 0.25, rng)
+    target = None
+    if with_target:
+        rng_t = np.random.default_rng(20260200 + cfg_id)
+        NA = (H * pitch / 2) / dz
+        L, F = len(lambdas), len(fields)
+        target = np.zeros((L, F, Q, Q), dtype=np.float32)
+        for l in range(L):
+            for f in range(F):
+                off = rng_t.uniform(-8, 8, 2)
+                target[l, f] = airy_target(Q, psf_pitch, lambdas[l], NA, (0.0, 0.0), off)
+    maps = {"phase": phase.astype(np.float32), "amp": amp.astype(np.float32),
+            "target": target}
+    return system, cfg, maps
+
+
+# ----------------------------------------------------------------------------
+# Free-space DOE (no refractive surface) for the closed-form pins: a planar
+# DOE at z = 0 under a collimated beam, sensor at `dz`.
+# ----------------------------------------------------------------------------
+def free_space_doe(phase, amp, pitch, dz, lam, rays_side, P, Q, psf_pitch, N=256, pad=2,
+                   sampling="full", field=(0.0, 0.0), launch_half=None, seed=0,
+                   psf_center=(0.0, 0.0)):
+    H, W = phase.shape
+    surfs = [surface(0.0, doe=True)]
+    system = {"surfaces": surfs, "sensor_z": float(dz), "doe": doe_desc(H, W, pitch),
+              "params": []}
+    if launch_half is None:
+        launch_half = 0.5 * W * pitch * (1 - 1.0 / rays_side)
+    cfg = _cfg([lam], [list(field)], 0.0, -1.0, launch_half, rays_side, Q, psf_pitch, dz, P, N,
+               sampling, pad=pad, seed=seed)
+    cfg["psf_center"] = [[list(psf_center)]]
+    maps = {"phase": np.asarray(phase, np.float32), "amp": np.asarray(amp, np.float32),
+            "target": None}
+    return system, cfg, maps
+
+
+def workload(name):
+    """Named full-size workloads."""
+    if name == "singlet_zoneplate":
+        return singlet_zoneplate()
+    if name == "asphere_hologram":
+        return asphere_hologram()
+    raise KeyError(name)
