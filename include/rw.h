@@ -1,0 +1,188 @@
+/*
+ * rw.h -- C ABI of the MI355X ray-wave hybrid PSF library (librw.so).
+ *
+ * The library evaluates, on one AMD Instinct MI355X (gfx950), the
+ * differentiable ray-wave forward model of arXiv 2605.15418 ("A general
+ * differentiable ray-wave framework for hybrid refractive-diffractive system
+ * modeling and optimization") and its hand-written adjoint:
+ *
+ *   conventional ray trace to the DOE (Results, "Ray-Wave Simulator
+ *   Formalism", first paragraph) -> tangent frame and square DOE patch of the
+ *   complex transmission A exp(i phi) (second paragraph) -> zero-padded
+ *   angular spectrum with the evanescent cut (second paragraph; zero padding
+ *   in the patch-size study) -> Monte Carlo secondary wavevectors with the
+ *   weights of Eq. 1 drawn from p ~ |U~| or uniform (sampling-density study,
+ *   Fig. 3; reparameterised sampling, Fig. 1c) -> conventional trace to the
+ *   sensor -> coherent wavelet sum of Eq. 2 -> |U|^2 -> loss of Eq. 3.
+ *
+ * Conventions for every entry point:
+ *  - Lengths are millimetres, wavelengths millimetres.
+ *  - Array arguments are DEVICE pointers unless their name ends in _host.
+ *    The caller owns every device buffer, including the workspace.  The plan
+ *    owns only small constant tables allocated in rw_plan_create.
+ *  - Calls are asynchronous on the given HIP stream (hipStream_t passed as
+ *    void*; NULL = default stream).  No call synchronises the device except
+ *    rw_get_stats.  No C++ exception crosses the ABI.
+ *  - Every function returns an rw_status; on error rw_last_error() gives a
+ *    thread-local message.  Invalid shapes are rejected at plan creation.
+ *  - A plan may be used by one thread at a time.
+ *
+ * Layouts (row-major):
+ *  DOE maps         [H][W]         pixel (iy, ix) centred at (x0 + ix pitch, y0 + iy pitch)
+ *  PSF / target     [L][F][Q][Q]   pair p = l * F + f; row = y index, column = x index,
+ *                                  pixel (r, c) at psf_center + ((c - Q/2), (r - Q/2)) * psf_pitch
+ *  ray order        pair-major, then ray r = iy * rays_side + ix of the launch grid
+ *  sample indices   [n_pairs][rays_side^2][n_ssr] int32: bin j = (jy + M/2) * M + (jx + M/2)
+ *                   of the shifted M x M spectrum, -1 where the ray emits nothing
+ */
+#ifndef RW_H
+#define RW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RW_OK = 0,
+  RW_ERR_INVALID_ARG = 1,   /* null pointer, out-of-range enum, bad value      */
+  RW_ERR_SHAPE = 2,         /* sizes the kernels do not support               */
+  RW_ERR_STATE = 3,         /* backward before forward, workspace too small   */
+  RW_ERR_NONFINITE = 4,     /* reserved                                       */
+  RW_ERR_OOM = 5,           /* a plan table could not be allocated            */
+  RW_ERR_HIP = 6,           /* a HIP runtime call failed                      */
+  RW_ERR_UNSUPPORTED = 7    /* a valid request outside what the kernels cover */
+} rw_status;
+
+enum { RW_SURF_ASPHERE = 0, RW_SURF_PLANE = 1 };
+
+/* One refractive surface of the sequential system (even asphere or plane):
+ * sag z(r) = c r^2 / (1 + sqrt(1 - (1 + conic) c^2 r^2)) + A4 r^4 + A6 r^6 + A8 r^8 + A10 r^10
+ * relative to z_vertex.  n_A, n_B: two-term Cauchy law n = n_A + n_B / lambda_um^2 of the
+ * medium AFTER the surface (the medium before the first surface is air, n = 1).
+ * semi_aperture <= 0 means no clip.  Exactly one surface carries the DOE (carries_doe = 1):
+ * at that surface rays are intersected but not refracted; the DOE emission refracts them. */
+typedef struct {
+  int kind;
+  int carries_doe;
+  double z_vertex;
+  double curvature;
+  double conic;
+  double asph[4];           /* A4, A6, A8, A10 */
+  double semi_aperture;
+  double n_A, n_B;
+} rw_surface;
+
+/* DOE map on the xy projection of its surface (the paper's conformal DOE is defined
+ * "as projected to a flat xy-plane"); the map extent is the system stop. */
+typedef struct {
+  int H, W;
+  double pitch;
+  double x0, y0;            /* centre of pixel (0, 0) */
+} rw_doe_desc;
+
+enum { RW_PARAM_CURV = 0, RW_PARAM_CONIC = 1, RW_PARAM_A4 = 2, RW_PARAM_A6 = 3,
+       RW_PARAM_A8 = 4, RW_PARAM_A10 = 5, RW_PARAM_GAP = 6 };
+
+/* Lens parameter i sets field `field` of surface `surface` to scale * lens_params[i].
+ * GAP: the axial distance from the surface to the next surface (to the sensor after
+ * the last one); every later surface and the sensor move with it. */
+typedef struct {
+  int surface;
+  int field;
+  double scale;
+} rw_param_ref;
+
+enum { RW_SAMPLE_MAG = 0, RW_SAMPLE_UNI = 1, RW_SAMPLE_FULL = 2 };
+enum { RW_PREC_FP64 = 0, RW_PREC_MIXED = 1, RW_PREC_FP32 = 2 };
+
+typedef struct {
+  int n_lambda;
+  const double* lambda_host;        /* [n_lambda] mm                                    */
+  int n_field;
+  const double* field_tan_host;     /* [n_field][2] (tan theta_x, tan theta_y)          */
+  const double* launch_center_host; /* [n_field][2] centre of the launch grid           */
+  double launch_z;                  /* launch plane, before the first surface           */
+  double launch_half;               /* half side of the square launch grid              */
+  int rays_side;                    /* rays per pair = rays_side^2                      */
+  double sensor_z;                  /* sensor plane                                     */
+  int psf_q;                        /* Q: PSF side in pixels (even)                     */
+  double psf_pitch;
+  const double* psf_center_host;    /* [n_lambda][n_field][2]                           */
+  int patch_p;                      /* P: patch side in DOE samples                     */
+  int pad_factor;                   /* M = pad_factor * P                               */
+  int n_ssr;                        /* N: secondary rays per incident ray (MAG, UNI)    */
+  int sampling;                     /* RW_SAMPLE_*                                      */
+  int precision;                    /* RW_PREC_*                                        */
+  int batched;                      /* 1: each stage is one launch over all pairs;
+                                       0: one launch per pair (plain comparator form)  */
+  int spread_width;                 /* NUFFT kernel width w, 0 = precision default      */
+  uint64_t seed;                    /* Philox key of the secondary-ray draws            */
+} rw_config;
+
+typedef struct rw_plan rw_plan;
+
+typedef struct {
+  uint64_t rays_total;      /* incident rays launched                    */
+  uint64_t rays_alive;      /* incident rays that reached the DOE inside the stop */
+  uint64_t secondaries;     /* secondary rays emitted with non-zero weight */
+} rw_stats;
+
+/* Creates a plan: validates shapes, builds constant tables (wavelength-dependent
+ * indices, NUFFT deconvolution weights, FFT twiddles) in device memory.
+ * All pointers in cfg are host pointers read during this call only.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_SHAPE, RW_ERR_UNSUPPORTED, RW_ERR_OOM, RW_ERR_HIP. */
+rw_status rw_plan_create(const rw_surface* surfaces_host, int n_surf, const rw_doe_desc* doe_host,
+                         const rw_param_ref* params_host, int n_params, const rw_config* cfg_host,
+                         rw_plan** out_plan);
+
+/* Bytes of device workspace the caller must provide to rw_forward / rw_backward
+ * (256-byte aligned).  The same workspace must be passed to the backward. */
+rw_status rw_plan_workspace_bytes(const rw_plan* plan, size_t* bytes);
+
+/* Forward pass.
+ *  lens_params [n_params] float  normalised lens parameters (may be NULL if n_params = 0)
+ *  doe_phase, doe_amp [H][W] float
+ *  target [L][F][Q][Q] float or NULL: if given, the loss of Eq. 3 (sum over pairs of
+ *         ||alpha* I - T||^2 with alpha* = <I,T>/<I,I>) is written to loss_out[0]
+ *         and kept for rw_backward; the target must stay valid until then.
+ *  psf_out [L][F][Q][Q] float (written)
+ *  replay_idx: NULL, or sample indices (layout above) used instead of the Philox draws
+ *  idx_out: NULL, or receives the sample indices that were used
+ * Errors: RW_ERR_INVALID_ARG (null required pointer), RW_ERR_STATE (workspace too small),
+ *         RW_ERR_HIP. */
+rw_status rw_forward(rw_plan* plan, const float* lens_params, const float* doe_phase,
+                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
+                     void* workspace, size_t workspace_bytes, const int32_t* replay_idx,
+                     int32_t* idx_out, void* stream);
+
+/* Backward pass (adjoint G1: the a.e. derivative with the sample indices of the
+ * preceding forward held fixed).
+ *  dL_dpsf [L][F][Q][Q] float, or NULL to differentiate the Eq. 3 loss of the forward
+ *  d_phase, d_amp [H][W] float (overwritten), d_lens [n_params] float (overwritten, may be
+ *  NULL if n_params = 0).
+ * Must follow rw_forward on the same plan and workspace.
+ * Errors: RW_ERR_STATE (no forward, or NULL dL_dpsf without a forward target),
+ *         RW_ERR_UNSUPPORTED (lens gradients need a planar DOE followed directly by the sensor),
+ *         RW_ERR_HIP. */
+rw_status rw_backward(rw_plan* plan, const float* dL_dpsf, float* d_phase, float* d_amp,
+                      float* d_lens, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Counters of the last forward (synchronises the stream of that forward). */
+rw_status rw_get_stats(rw_plan* plan, rw_stats* out_host);
+
+/* Diagnostic export of the incident ray state at the DOE of the last forward:
+ * out [n_rays_total][8] double = (px, py, pz, dx, dy, dz, opl, alive). */
+rw_status rw_export_doe_hits(const rw_plan* plan, const void* workspace, double* out,
+                             void* stream);
+
+rw_status rw_plan_destroy(rw_plan* plan);
+const char* rw_status_string(rw_status s);
+const char* rw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RW_H */

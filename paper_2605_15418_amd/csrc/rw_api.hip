@@ -1,0 +1,536 @@
+// Host side of the C ABI declared in include/rw.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rw.h"
+#include "rw_kernels.h"
+#include "rw_backward.h"
+
+using namespace rw;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rw_status fail(rw_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(RW_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Gauss-Legendre nodes/weights on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+}
+
+}  // namespace
+
+struct rw_plan {
+  // description
+  std::vector<rw_surface> surf;
+  rw_doe_desc doe;
+  std::vector<rw_param_ref> prm;
+  rw_config cfg;
+  int n_surf, s_doe, n_pairs, n_lambda, n_field, R, R2, P, M, N, Q, nf, w, H, W;
+  size_t n_total;
+  bool planar_doe, has_post;
+  bool lds_patch;
+  int fwd_blocks;
+  double beta;
+  // device constant tables (owned by the plan)
+  DevCfg* d_cfg = nullptr;
+  DevPair* d_pairs = nullptr;
+  DevSurf* d_base = nullptr;
+  DevParam* d_prm = nullptr;
+  void* d_tw_m = nullptr;
+  void* d_tw_nf = nullptr;
+  double* d_psi = nullptr;
+  double base_sensor_z;
+  // workspace layout
+  size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
+      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, total;
+  size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
+  // state between forward and backward
+  bool fwd_done = false;
+  const float* fwd_target = nullptr;
+  const int32_t* fwd_replay = nullptr;
+  void* fwd_ws = nullptr;
+  hipStream_t fwd_stream = nullptr;
+};
+
+// ------------------------------------------------------------ dispatch -----
+namespace {
+
+template <class Prec, int M, bool LDS>
+void launch_doe_fwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_doe_fwd<Prec, M, LDS>), dim3(blocks), dim3(kThreads), 0, st, a);
+}
+
+template <class Prec>
+rw_status doe_fwd_prec(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+  constexpr bool dbl = sizeof(typename Prec::Tf) == 8;
+  switch (pl->M) {
+    case 16: launch_doe_fwd<Prec, 16, true>(pl, a, blocks, st); break;
+    case 32: launch_doe_fwd<Prec, 32, true>(pl, a, blocks, st); break;
+    case 64: launch_doe_fwd<Prec, 64, true>(pl, a, blocks, st); break;
+    case 128:
+      if (dbl) launch_doe_fwd<Prec, 128, false>(pl, a, blocks, st);
+      else launch_doe_fwd<Prec, 128, !dbl>(pl, a, blocks, st);
+      break;
+    case 256: launch_doe_fwd<Prec, 256, false>(pl, a, blocks, st); break;
+    default: return fail(RW_ERR_SHAPE, "unsupported FFT size M");
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+template <class Tg, int NF>
+void launch_grid_fwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs, float* psf) {
+  char* b = (char*)ws;
+  const int Q = pl->Q;
+  const size_t rows = (size_t)npairs * NF;
+  hipLaunchKernelGGL((k_grid_rows_fwd<Tg, NF>), dim3((rows + 3) / 4), dim3(256), 0, st,
+                     (const C2<Tg>*)(b + pl->off_grid), (C2<Tg>*)(b + pl->off_t1),
+                     (const C2<Tg>*)pl->d_tw_nf, Q, pair0, npairs);
+  const size_t cols = (size_t)npairs * Q;
+  hipLaunchKernelGGL((k_grid_cols_fwd<Tg, NF>), dim3((cols + 3) / 4), dim3(256), 0, st,
+                     (const C2<Tg>*)(b + pl->off_t1), (const C2<Tg>*)pl->d_tw_nf, pl->d_psi, Q,
+                     pair0, npairs, (C2<Tg>*)(b + pl->off_U), psf);
+}
+
+template <class Tg>
+rw_status grid_fwd_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs, float* psf) {
+  switch (pl->nf) {
+    case 64: launch_grid_fwd<Tg, 64>(pl, ws, st, pair0, npairs, psf); break;
+    case 128: launch_grid_fwd<Tg, 128>(pl, ws, st, pair0, npairs, psf); break;
+    case 256: launch_grid_fwd<Tg, 256>(pl, ws, st, pair0, npairs, psf); break;
+    case 512: launch_grid_fwd<Tg, 512>(pl, ws, st, pair0, npairs, psf); break;
+    case 1024: launch_grid_fwd<Tg, 1024>(pl, ws, st, pair0, npairs, psf); break;
+    case 2048: launch_grid_fwd<Tg, 2048>(pl, ws, st, pair0, npairs, psf); break;
+    default: return fail(RW_ERR_SHAPE, "unsupported grid size");
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status grid_fwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs, float* psf) {
+  if (pl->cfg.precision == RW_PREC_FP64) return grid_fwd_t<double>(pl, ws, st, pair0, npairs, psf);
+  return grid_fwd_t<float>(pl, ws, st, pair0, npairs, psf);
+}
+
+DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out) {
+  char* b = (char*)ws;
+  DoeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.cfg = pl->d_cfg;
+  a.pairs = pl->d_pairs;
+  a.live = (const DevLive*)(b + pl->off_live);
+  a.st = (const double*)(b + pl->off_st);
+  a.n_total = pl->n_total;
+  a.tmap = b + pl->off_tmap;
+  a.tw = pl->d_tw_m;
+  a.grid = b + pl->off_grid;
+  a.scratch = pl->lds_patch ? nullptr : b + pl->off_scratch;
+  a.replay = replay;
+  a.idx_out = idx_out;
+  a.stats = (unsigned long long*)(b + pl->off_stats);
+  a.gt = b + pl->off_gt;
+  a.raygrad = (double*)(b + pl->off_raygrad);
+  return a;
+}
+
+rw_status doe_fwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+  switch (pl->cfg.precision) {
+    case RW_PREC_FP64: return doe_fwd_prec<PrecFP64>(pl, a, blocks, st);
+    case RW_PREC_MIXED: return doe_fwd_prec<PrecMIXED>(pl, a, blocks, st);
+    default: return doe_fwd_prec<PrecFP32>(pl, a, blocks, st);
+  }
+}
+
+template <class T>
+void zero(void* p, size_t n, hipStream_t st) {
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(k_zero<T>, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, (T*)p, n);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- API ----
+extern "C" {
+
+const char* rw_status_string(rw_status s) {
+  switch (s) {
+    case RW_OK: return "ok";
+    case RW_ERR_INVALID_ARG: return "invalid argument";
+    case RW_ERR_SHAPE: return "unsupported shape";
+    case RW_ERR_STATE: return "invalid state";
+    case RW_ERR_NONFINITE: return "non-finite input";
+    case RW_ERR_OOM: return "out of memory";
+    case RW_ERR_HIP: return "HIP runtime error";
+    case RW_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* rw_last_error(void) { return g_last_error.c_str(); }
+
+rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc* doe,
+                         const rw_param_ref* params, int n_params, const rw_config* cfg,
+                         rw_plan** out) {
+  if (!surfaces || !doe || !cfg || !out || (n_params > 0 && !params))
+    return fail(RW_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (n_surf < 1 || n_surf > RW_MAX_SURF)
+    return fail(RW_ERR_SHAPE, "n_surf must be in [1, 8]");
+  if (!cfg->lambda_host || !cfg->field_tan_host || !cfg->launch_center_host ||
+      !cfg->psf_center_host)
+    return fail(RW_ERR_INVALID_ARG, "null host array in config");
+  int s_doe = -1;
+  for (int s = 0; s < n_surf; ++s)
+    if (surfaces[s].carries_doe) {
+      if (s_doe >= 0) return fail(RW_ERR_UNSUPPORTED, "more than one DOE surface");
+      s_doe = s;
+    }
+  if (s_doe < 0) return fail(RW_ERR_INVALID_ARG, "no surface carries the DOE");
+  for (int i = 0; i < n_params; ++i) {
+    if (params[i].surface < 0 || params[i].surface >= n_surf || params[i].field < 0 ||
+        params[i].field > RW_PARAM_GAP)
+      return fail(RW_ERR_INVALID_ARG, "bad lens parameter reference");
+  }
+  const int P = cfg->patch_p, pad = cfg->pad_factor;
+  const int M = P * pad;
+  if (P < 1 || pad < 1 || !is_pow2(M) || M < 16 || M > 256)
+    return fail(RW_ERR_SHAPE, "M = pad_factor * patch_p must be a power of two in [16, 256]");
+  if (cfg->psf_q < 32 || !is_pow2(cfg->psf_q) || cfg->psf_q > 1024)
+    return fail(RW_ERR_SHAPE, "psf_q must be a power of two in [32, 1024]");
+  if (cfg->rays_side < 1 || cfg->n_lambda < 1 || cfg->n_field < 1)
+    return fail(RW_ERR_SHAPE, "empty ray grid, wavelength or field list");
+  if (cfg->sampling < 0 || cfg->sampling > 2 || cfg->precision < 0 || cfg->precision > 2)
+    return fail(RW_ERR_INVALID_ARG, "bad sampling or precision");
+  if (cfg->sampling != RW_SAMPLE_FULL && (cfg->n_ssr < 1 || cfg->n_ssr > 2048))
+    return fail(RW_ERR_SHAPE, "n_ssr must be in [1, 2048]");
+  if (doe->H < 1 || doe->W < 1 || !(doe->pitch > 0))
+    return fail(RW_ERR_SHAPE, "bad DOE map description");
+  if (cfg->precision == RW_PREC_FP64 && M > 128)
+    return fail(RW_ERR_UNSUPPORTED, "FP64 supports M <= 128");
+  for (int l = 0; l < cfg->n_lambda; ++l)
+    if (!(cfg->lambda_host[l] > 0)) return fail(RW_ERR_INVALID_ARG, "wavelength must be > 0");
+
+  rw_plan* pl = new rw_plan();
+  pl->surf.assign(surfaces, surfaces + n_surf);
+  pl->doe = *doe;
+  pl->prm.assign(params, params + n_params);
+  pl->cfg = *cfg;
+  pl->n_surf = n_surf;
+  pl->s_doe = s_doe;
+  pl->n_lambda = cfg->n_lambda;
+  pl->n_field = cfg->n_field;
+  pl->n_pairs = cfg->n_lambda * cfg->n_field;
+  pl->R = cfg->rays_side;
+  pl->R2 = cfg->rays_side * cfg->rays_side;
+  pl->n_total = (size_t)pl->n_pairs * pl->R2;
+  pl->P = P;
+  pl->M = M;
+  pl->N = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
+  pl->Q = cfg->psf_q;
+  pl->nf = std::max(2 * cfg->psf_q, 64);
+  pl->w = cfg->spread_width > 0 ? cfg->spread_width
+                                : (cfg->precision == RW_PREC_FP64 ? 13 : 7);
+  if (pl->w < 2 || pl->w > 16) {
+    delete pl;
+    return fail(RW_ERR_SHAPE, "spread_width must be in [2, 16]");
+  }
+  const double sigma = (double)pl->nf / pl->Q;
+  pl->beta = 0.98 * M_PI * pl->w * (1.0 - 0.5 / sigma);
+  pl->H = doe->H;
+  pl->W = doe->W;
+  pl->planar_doe = surfaces[s_doe].curvature == 0.0 && surfaces[s_doe].conic == 0.0 &&
+                   surfaces[s_doe].asph[0] == 0.0 && surfaces[s_doe].asph[1] == 0.0 &&
+                   surfaces[s_doe].asph[2] == 0.0 && surfaces[s_doe].asph[3] == 0.0;
+  for (int i = 0; i < n_params; ++i)
+    if (params[i].surface == s_doe && params[i].field != RW_PARAM_GAP) pl->planar_doe = false;
+  pl->has_post = s_doe + 1 < n_surf;
+  pl->base_sensor_z = cfg->sensor_z;
+  const bool dbl_f = cfg->precision == RW_PREC_FP64;
+  const bool dbl_g = cfg->precision == RW_PREC_FP64;
+  pl->sz_cf = dbl_f ? 16 : 8;
+  pl->sz_cg = dbl_g ? 16 : 8;
+  pl->lds_patch = (size_t)M * (M + 1) * pl->sz_cf + M * pl->sz_cf + 4096 <= 160 * 1024;
+  pl->fwd_blocks = (int)std::min<size_t>(pl->n_total, pl->lds_patch ? 8192 : 2048);
+
+  // host copies of the constant tables
+  DevCfg dc;
+  memset(&dc, 0, sizeof(dc));
+  dc.n_surf = n_surf; dc.s_doe = s_doe; dc.n_pairs = pl->n_pairs; dc.n_field = pl->n_field;
+  dc.R = pl->R; dc.R2 = pl->R2; dc.P = P; dc.M = M; dc.N = pl->N; dc.Q = pl->Q; dc.nf = pl->nf;
+  dc.w = pl->w; dc.sampling = cfg->sampling; dc.H = doe->H; dc.W = doe->W;
+  dc.n_params = n_params;
+  dc.pitch = doe->pitch; dc.x0 = doe->x0; dc.y0 = doe->y0;
+  dc.launch_z = cfg->launch_z; dc.launch_half = cfg->launch_half; dc.psf_pitch = cfg->psf_pitch;
+  dc.beta = pl->beta;
+  dc.key0 = (uint32_t)(cfg->seed & 0xffffffffu);
+  dc.key1 = (uint32_t)(cfg->seed >> 32);
+
+  std::vector<DevPair> pairs(pl->n_pairs);
+  for (int l = 0; l < pl->n_lambda; ++l)
+    for (int f = 0; f < pl->n_field; ++f) {
+      DevPair& p = pairs[l * pl->n_field + f];
+      memset(&p, 0, sizeof(p));
+      const double lam = cfg->lambda_host[l];
+      p.lam = lam;
+      p.k0 = 2.0 * M_PI / lam;
+      const double tx = cfg->field_tan_host[2 * f], ty = cfg->field_tan_host[2 * f + 1];
+      const double nn = std::sqrt(tx * tx + ty * ty + 1.0);
+      p.dir[0] = tx / nn; p.dir[1] = ty / nn; p.dir[2] = 1.0 / nn;
+      p.lc[0] = cfg->launch_center_host[2 * f];
+      p.lc[1] = cfg->launch_center_host[2 * f + 1];
+      p.pc[0] = cfg->psf_center_host[2 * (l * pl->n_field + f)];
+      p.pc[1] = cfg->psf_center_host[2 * (l * pl->n_field + f) + 1];
+      const double lum = lam * 1e3;
+      p.n_med[0] = 1.0;
+      for (int s = 0; s < n_surf; ++s)
+        p.n_med[s + 1] = surfaces[s].n_A + surfaces[s].n_B / (lum * lum);
+    }
+  std::vector<DevSurf> base(n_surf);
+  for (int s = 0; s < n_surf; ++s) {
+    const rw_surface& q = surfaces[s];
+    base[s] = {q.z_vertex, q.curvature, q.conic, q.asph[0], q.asph[1], q.asph[2], q.asph[3],
+               q.semi_aperture, q.kind, q.carries_doe};
+  }
+  std::vector<DevParam> prm(std::max(n_params, 1));
+  for (int i = 0; i < n_params; ++i) prm[i] = {params[i].surface, params[i].field, params[i].scale};
+  // FFT twiddles exp(-2 pi i m / n)
+  auto twiddles = [](int n, bool dbl) {
+    std::vector<char> out(n * (dbl ? 16 : 8));
+    for (int m = 0; m < n; ++m) {
+      const double a = -2.0 * M_PI * m / n;
+      if (dbl) {
+        double v[2] = {std::cos(a), std::sin(a)};
+        memcpy(out.data() + m * 16, v, 16);
+      } else {
+        float v[2] = {(float)std::cos(a), (float)std::sin(a)};
+        memcpy(out.data() + m * 8, v, 8);
+      }
+    }
+    return out;
+  };
+  std::vector<char> twm = twiddles(M, dbl_f), twn = twiddles(pl->nf, dbl_g);
+  // Fourier transform of the spreading kernel at the kept modes (deconvolution)
+  std::vector<double> gx, gw, psi(pl->Q);
+  gauss_legendre(200, gx, gw);
+  for (int c = 0; c < pl->Q; ++c) {
+    const int k = c - pl->Q / 2;
+    double s = 0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const double z = 0.5 * pl->w * gx[i];
+      const double ph = std::exp(pl->beta * (std::sqrt(1.0 - gx[i] * gx[i]) - 1.0));
+      s += gw[i] * 0.5 * pl->w * ph * std::cos(2.0 * M_PI * k * z / pl->nf);
+    }
+    psi[c] = s;
+  }
+
+  auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up((void**)&pl->d_cfg, &dc, sizeof(dc));
+  if (e == hipSuccess) e = up((void**)&pl->d_pairs, pairs.data(), pairs.size() * sizeof(DevPair));
+  if (e == hipSuccess) e = up((void**)&pl->d_base, base.data(), base.size() * sizeof(DevSurf));
+  if (e == hipSuccess) e = up((void**)&pl->d_prm, prm.data(), prm.size() * sizeof(DevParam));
+  if (e == hipSuccess) e = up(&pl->d_tw_m, twm.data(), twm.size());
+  if (e == hipSuccess) e = up(&pl->d_tw_nf, twn.data(), twn.size());
+  if (e == hipSuccess) e = up((void**)&pl->d_psi, psi.data(), psi.size() * sizeof(double));
+  if (e != hipSuccess) {
+    rw_plan_destroy(pl);
+    return fail(e == hipErrorOutOfMemory ? RW_ERR_OOM : RW_ERR_HIP,
+                std::string("plan tables: ") + hipGetErrorString(e));
+  }
+
+  // workspace layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
+  const size_t nt = pl->n_total;
+  pl->off_live = take(sizeof(DevLive));
+  pl->off_tmap = take((size_t)doe->H * doe->W * pl->sz_cf);
+  pl->off_st = take(8 * nt * sizeof(double));
+  pl->off_ck = take((size_t)(s_doe + 1) * 8 * nt * sizeof(double));
+  pl->off_grid = take((size_t)pl->n_pairs * pl->nf * pl->nf * pl->sz_cg);
+  pl->off_t1 = take((size_t)pl->n_pairs * pl->Q * pl->nf * pl->sz_cg);
+  pl->off_U = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
+  pl->off_alpha = take(pl->n_pairs * sizeof(double));
+  pl->off_lossp = take(pl->n_pairs * sizeof(double));
+  pl->off_stats = take(4 * sizeof(unsigned long long));
+  pl->off_scratch =
+      take(pl->lds_patch ? 0 : (size_t)pl->fwd_blocks * M * (M + 1) * pl->sz_cf);
+  pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
+  pl->off_raygrad = take(8 * nt * sizeof(double));
+  pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
+  pl->total = o;
+  *out = pl;
+  return RW_OK;
+}
+
+rw_status rw_plan_workspace_bytes(const rw_plan* pl, size_t* bytes) {
+  if (!pl || !bytes) return fail(RW_ERR_INVALID_ARG, "null argument");
+  *bytes = pl->total;
+  return RW_OK;
+}
+
+rw_status rw_plan_destroy(rw_plan* pl) {
+  if (!pl) return RW_OK;
+  (void)hipFree(pl->d_cfg);
+  (void)hipFree(pl->d_pairs);
+  (void)hipFree(pl->d_base);
+  (void)hipFree(pl->d_prm);
+  (void)hipFree(pl->d_tw_m);
+  (void)hipFree(pl->d_tw_nf);
+  (void)hipFree(pl->d_psi);
+  delete pl;
+  return RW_OK;
+}
+
+rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
+                     void* ws, size_t ws_bytes, const int32_t* replay_idx, int32_t* idx_out,
+                     void* stream) {
+  if (!pl || !doe_phase || !doe_amp || !psf_out || !ws)
+    return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (pl->prm.size() > 0 && !lens_params)
+    return fail(RW_ERR_INVALID_ARG, "lens_params required when the plan has lens parameters");
+  if (target && !loss_out) return fail(RW_ERR_INVALID_ARG, "target given without loss_out");
+  if (ws_bytes < pl->total) return fail(RW_ERR_STATE, "workspace smaller than rw_plan_workspace_bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (replay_idx && pl->cfg.sampling == RW_SAMPLE_FULL)
+    return fail(RW_ERR_INVALID_ARG, "replay is meaningless in FULL sampling");
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)ws;
+  pl->fwd_done = false;
+  const bool dbl_f = pl->cfg.precision == RW_PREC_FP64;
+  const bool dbl_g = pl->cfg.precision == RW_PREC_FP64;
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, pl->d_cfg, pl->d_base, pl->base_sensor_z,
+                     pl->d_prm, lens_params, (DevLive*)(b + pl->off_live));
+  const int nmap = pl->H * pl->W;
+  if (dbl_f)
+    hipLaunchKernelGGL(k_tmap<double>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
+                       doe_amp, (C2<double>*)(b + pl->off_tmap), nmap);
+  else
+    hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
+                       doe_amp, (C2<float>*)(b + pl->off_tmap), nmap);
+  HIPCHK(hipGetLastError());
+  const size_t ngrid = (size_t)pl->n_pairs * pl->nf * pl->nf * 2;
+  if (dbl_g) zero<double>(b + pl->off_grid, ngrid, st);
+  else zero<float>(b + pl->off_grid, ngrid, st);
+  zero<unsigned long long>(b + pl->off_stats, 4, st);
+  DoeArgs a = doe_args(pl, ws, replay_idx, idx_out);
+  const int groups = pl->cfg.batched ? 1 : pl->n_pairs;
+  const int ppg = pl->cfg.batched ? pl->n_pairs : 1;
+  for (int gi = 0; gi < groups; ++gi) {
+    const int pair0 = gi * ppg;
+    const size_t nr = (size_t)ppg * pl->R2;
+    const int tb = (int)((nr + 255) / 256);
+    if (pl->cfg.precision == RW_PREC_FP32)
+      hipLaunchKernelGGL(k_trace<float>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
+                         (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
+                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg);
+    else
+      hipLaunchKernelGGL(k_trace<double>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
+                         (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
+                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg);
+    HIPCHK(hipGetLastError());
+    a.ray0 = (size_t)pair0 * pl->R2;
+    a.nray = nr;
+    const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
+    rw_status s = doe_fwd(pl, a, blocks, st);
+    if (s != RW_OK) return s;
+    s = grid_fwd(pl, ws, st, pair0, ppg, psf_out);
+    if (s != RW_OK) return s;
+  }
+  if (target) {
+    hipLaunchKernelGGL(k_loss_pairs, dim3(pl->n_pairs), dim3(256), 0, st, psf_out, target,
+                       pl->Q * pl->Q, 0, (double*)(b + pl->off_alpha),
+                       (double*)(b + pl->off_lossp));
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, (const double*)(b + pl->off_lossp),
+                       pl->n_pairs, loss_out);
+    HIPCHK(hipGetLastError());
+  }
+  pl->fwd_done = true;
+  pl->fwd_target = target;
+  pl->fwd_replay = replay_idx;
+  pl->fwd_ws = ws;
+  pl->fwd_stream = st;
+  return RW_OK;
+}
+
+rw_status rw_get_stats(rw_plan* pl, rw_stats* out) {
+  if (!pl || !out) return fail(RW_ERR_INVALID_ARG, "null argument");
+  if (!pl->fwd_done) return fail(RW_ERR_STATE, "no forward pass yet");
+  unsigned long long h[4];
+  HIPCHK(hipStreamSynchronize(pl->fwd_stream));
+  HIPCHK(hipMemcpy(h, (char*)pl->fwd_ws + pl->off_stats, sizeof(h), hipMemcpyDeviceToHost));
+  out->rays_total = pl->n_total;
+  out->rays_alive = h[0];
+  out->secondaries = h[1];
+  return RW_OK;
+}
+
+rw_status rw_export_doe_hits(const rw_plan* pl, const void* ws, double* out, void* stream) {
+  if (!pl || !ws || !out) return fail(RW_ERR_INVALID_ARG, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = pl->n_total;
+  hipLaunchKernelGGL(k_export_state, dim3((unsigned)((8 * n + 255) / 256)), dim3(256), 0, st,
+                     (const double*)((const char*)ws + pl->off_st), n, out);
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
+                      float* d_lens, void* ws, size_t ws_bytes, void* stream) {
+  return rw_backward_impl(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+static rw_status rw_backward_impl(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
+                                  float* d_lens, void* ws, size_t ws_bytes, void* stream) {
+  (void)pl; (void)dL_dpsf; (void)d_phase; (void)d_amp; (void)d_lens; (void)ws; (void)ws_bytes;
+  (void)stream;
+  return fail(RW_ERR_UNSUPPORTED, "backward not built yet");
+}

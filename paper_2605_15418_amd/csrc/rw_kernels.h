@@ -1,0 +1,671 @@
+// Kernels of the ray-wave hybrid PSF (forward path).
+//
+//   k_params     lens parameters -> live prescription (one thread)
+//   k_tmap       complex transmission t = A exp(i phi) of the DOE map
+//   k_trace      launch + conventional refractive trace to the DOE, with
+//                per-surface checkpoints of the ray state (one thread per ray)
+//   k_doe_fwd    ray-wave interface, one workgroup per incident ray: tangent
+//                frame, bilinear patch gather, zero-padded 2-D FFT in LDS,
+//                propagating cut, CDF, Philox draws, Eq. 1 weights, secondary
+//                trace to the sensor, Eq. 2 wavelets spread onto an oversampled
+//                grid (type-1 NUFFT with an exponential-of-semicircle kernel)
+//   k_grid_rows / k_grid_cols   grid FFT, deconvolution, crop, |U|^2
+//   k_loss_pairs / k_loss_total Eq. 3 with the closed-form alpha per PSF
+#pragma once
+#include "rw_common.h"
+#include "rw_fft.h"
+
+namespace rw {
+
+constexpr int kThreads = 256;
+
+struct PrecFP64 { using Tt = double; using Tf = double; using Tp = double; using Tg = double; };
+struct PrecMIXED { using Tt = double; using Tf = float; using Tp = double; using Tg = float; };
+struct PrecFP32 { using Tt = float; using Tf = float; using Tp = float; using Tg = float; };
+
+struct DevCfg {
+  int n_surf, s_doe, n_pairs, n_field, R, R2, P, M, N, Q, nf, w, sampling, H, W, n_params;
+  double pitch, x0, y0, launch_z, launch_half, psf_pitch, beta;
+  uint32_t key0, key1;
+};
+
+struct DevPair {
+  double lam, k0;
+  double dir[3];
+  double lc[2];            // launch centre
+  double pc[2];            // PSF centre
+  double n_med[RW_MAX_SURF + 1];   // n_med[s] = index before surface s; n_med[n_surf] at the sensor
+};
+
+struct DevParam { int surface, field; double scale; };
+
+struct DevLive {
+  DevSurf s[RW_MAX_SURF];
+  double sensor_z;
+};
+
+// ----------------------------------------------------------- block scans ---
+// Exclusive prefix over the 256 threads of a block; returns the total.
+__device__ __forceinline__ double block_exclusive_scan(double v, double* s_tmp /*[4]*/,
+                                                       double& excl) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double n = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += n;
+  }
+  if (lane == 63) s_tmp[wv] = inc;
+  __syncthreads();
+  double base = 0.0, tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i < wv) base += s_tmp[i];
+    tot += s_tmp[i];
+  }
+  excl = base + inc - v;
+  __syncthreads();
+  return tot;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* s_tmp /*[4]*/) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ int block_max_int(int v, int* s_tmp /*[4]*/) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const int t = max(max(s_tmp[0], s_tmp[1]), max(s_tmp[2], s_tmp[3]));
+  __syncthreads();
+  return t;
+}
+
+// -------------------------------------------------------------- k_params ---
+__global__ void k_params(const DevCfg* cfg, const DevSurf* base, double base_sensor_z,
+                         const DevParam* prm, const float* values, DevLive* live) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int S = cfg->n_surf;
+  double gap[RW_MAX_SURF];
+  DevLive L;
+  for (int s = 0; s < S; ++s) {
+    L.s[s] = base[s];
+    gap[s] = (s + 1 < S ? base[s + 1].z : base_sensor_z) - base[s].z;
+  }
+  for (int i = 0; i < cfg->n_params; ++i) {
+    const double v = prm[i].scale * (double)values[i];
+    DevSurf& s = L.s[prm[i].surface];
+    switch (prm[i].field) {
+      case 0: s.c = v; break;
+      case 1: s.k = v; break;
+      case 2: s.A4 = v; break;
+      case 3: s.A6 = v; break;
+      case 4: s.A8 = v; break;
+      case 5: s.A10 = v; break;
+      case 6: gap[prm[i].surface] = v; break;
+    }
+  }
+  double z = base[0].z;
+  for (int s = 0; s < S; ++s) {
+    L.s[s].z = z;
+    z += gap[s];
+  }
+  L.sensor_z = z;
+  *live = L;
+}
+
+// ---------------------------------------------------------------- k_tmap ---
+template <class Tf>
+__global__ void k_tmap(const float* phase, const float* amp, C2<Tf>* tmap, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Tf s, c;
+  sincos_any((Tf)phase[i], &s, &c);
+  const Tf a = (Tf)amp[i];
+  tmap[i] = {a * c, a * s};
+}
+
+template <class T>
+__global__ void k_zero(T* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+// --------------------------------------------------------------- k_trace ---
+// Ray state layout: st[c * n_total + ray], c = px, py, pz, dx, dy, dz, opl, alive.
+// Checkpoint s (state entering surface s, s = 0..s_doe) at ck[(s * 8 + c) * n_total + ray].
+template <class Tt>
+__global__ __launch_bounds__(256) void k_trace(const DevCfg* cfg, const DevPair* pairs,
+                                               const DevLive* live, double* st, double* ck,
+                                               size_t n_total, int pair0, int npairs) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int R = cfg->R, R2 = cfg->R2;
+  if (idx >= (size_t)npairs * R2) return;
+  const int pair = pair0 + (int)(idx / R2);
+  const int r = (int)(idx % R2);
+  const size_t gid = (size_t)pair * R2 + r;
+  const DevPair& pr = pairs[pair];
+  const int ix = r % R, iy = r / R;
+  const double gx = ((ix + 0.5) / R) * 2.0 - 1.0, gy = ((iy + 0.5) / R) * 2.0 - 1.0;
+  Tt p[3] = {(Tt)(pr.lc[0] + gx * cfg->launch_half), (Tt)(pr.lc[1] + gy * cfg->launch_half),
+             (Tt)cfg->launch_z};
+  Tt d[3] = {(Tt)pr.dir[0], (Tt)pr.dir[1], (Tt)pr.dir[2]};
+  Tt opl = d[0] * p[0] + d[1] * p[1] + d[2] * p[2];
+  bool alive = true;
+  const int sd = cfg->s_doe;
+  for (int s = 0; s <= sd; ++s) {
+    double* c = ck + (size_t)s * 8 * n_total;
+    c[0 * n_total + gid] = p[0]; c[1 * n_total + gid] = p[1]; c[2 * n_total + gid] = p[2];
+    c[3 * n_total + gid] = d[0]; c[4 * n_total + gid] = d[1]; c[5 * n_total + gid] = d[2];
+    c[6 * n_total + gid] = opl; c[7 * n_total + gid] = alive ? 1.0 : 0.0;
+    if (!alive) break;
+    const DevSurf& ds = live->s[s];
+    const Surf<Tt> sf = surf_of<Tt>(ds);
+    Tt t;
+    if (!intersect(sf, p, d, t)) { alive = false; break; }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] += t * d[i];
+    opl += (Tt)pr.n_med[s] * t;
+    if (ds.semi_ap > 0 && (double)(p[0] * p[0] + p[1] * p[1]) > ds.semi_ap * ds.semi_ap) {
+      alive = false; break;
+    }
+    if (s == sd) break;
+    Tt nrm[3];
+    surface_normal(sf, p[0], p[1], nrm);
+    if (!refract(d, nrm, (Tt)(pr.n_med[s] / pr.n_med[s + 1]))) { alive = false; break; }
+  }
+  if (alive) {
+    const double fx = ((double)p[0] - cfg->x0) / cfg->pitch;
+    const double fy = ((double)p[1] - cfg->y0) / cfg->pitch;
+    alive = fx >= -0.5 && fx <= cfg->W - 0.5 && fy >= -0.5 && fy <= cfg->H - 0.5;
+  }
+  st[0 * n_total + gid] = p[0]; st[1 * n_total + gid] = p[1]; st[2 * n_total + gid] = p[2];
+  st[3 * n_total + gid] = d[0]; st[4 * n_total + gid] = d[1]; st[5 * n_total + gid] = d[2];
+  st[6 * n_total + gid] = opl; st[7 * n_total + gid] = alive ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------- DOE stage ---
+struct DoeArgs {
+  const DevCfg* cfg;
+  const DevPair* pairs;
+  const DevLive* live;
+  const double* st;
+  size_t n_total;
+  const void* tmap;          // C2<Tf> [H][W]
+  const void* tw;            // C2<Tf> [M] exp(-2 pi i m / M)
+  void* grid;                // C2<Tg> [n_pairs][nf][nf]
+  void* scratch;             // C2<Tf> per block [M][M+1] when the patch does not fit in LDS
+  const int32_t* replay;
+  int32_t* idx_out;
+  unsigned long long* stats; // [0] alive rays, [1] secondaries
+  size_t ray0, nray;         // rays [ray0, ray0 + nray) of the global order
+  // backward-only
+  const void* adj;           // C2<Tg> adjoint grid
+  void* gt;                  // C2<Tg> [H][W] cogradient of t
+  double* raygrad;           // [8][n_total] cogradients of the incident state
+  int want_lens;
+};
+
+// Frame and incident tangential wavevector at the DOE hit (double).
+struct RayCtx {
+  double p[3], d[3], opl;
+  double u[3], v[3], n[3];
+  double kin_u, kin_v, k0, k_out, n_in, n_out, dk;
+  int pair, r;
+  size_t gid;
+};
+
+__device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c) {
+  const DevCfg& cfg = *a.cfg;
+  c.gid = gid;
+  c.pair = (int)(gid / cfg.R2);
+  c.r = (int)(gid % cfg.R2);
+  const size_t n = a.n_total;
+  for (int i = 0; i < 3; ++i) { c.p[i] = a.st[i * n + gid]; c.d[i] = a.st[(3 + i) * n + gid]; }
+  c.opl = a.st[6 * n + gid];
+  const DevPair& pr = a.pairs[c.pair];
+  const DevSurf& sd = a.live->s[cfg.s_doe];
+  const Surf<double> sf = surf_of<double>(sd);
+  surface_normal(sf, c.p[0], c.p[1], c.n);
+  // u = normalised projection of the global x axis on the tangent plane, v = n x u
+  double ux = 1.0 - c.n[0] * c.n[0], uy = -c.n[0] * c.n[1], uz = -c.n[0] * c.n[2];
+  const double iu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+  c.u[0] = ux * iu; c.u[1] = uy * iu; c.u[2] = uz * iu;
+  c.v[0] = c.n[1] * c.u[2] - c.n[2] * c.u[1];
+  c.v[1] = c.n[2] * c.u[0] - c.n[0] * c.u[2];
+  c.v[2] = c.n[0] * c.u[1] - c.n[1] * c.u[0];
+  c.k0 = pr.k0;
+  c.n_in = pr.n_med[cfg.s_doe];
+  c.n_out = pr.n_med[cfg.s_doe + 1];
+  c.k_out = c.k0 * c.n_out;
+  c.kin_u = c.k0 * c.n_in * (c.d[0] * c.u[0] + c.d[1] * c.u[1] + c.d[2] * c.u[2]);
+  c.kin_v = c.k0 * c.n_in * (c.d[0] * c.v[0] + c.d[1] * c.v[1] + c.d[2] * c.v[2]);
+  c.dk = 2.0 * RW_PI / (cfg.M * cfg.pitch);
+}
+
+// Bilinear sample of the complex transmission at the xy projection of
+// p + s_m u + s_n v (zero outside the map).
+template <class Tf>
+__device__ __forceinline__ C2<Tf> patch_sample(const DevCfg& cfg, const RayCtx& c,
+                                               const C2<Tf>* tm, int m, int n) {
+  const double sm = (m - (cfg.P - 1) * 0.5) * cfg.pitch;
+  const double sn = (n - (cfg.P - 1) * 0.5) * cfg.pitch;
+  const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
+  const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
+  const double fx = (qx - cfg.x0) / cfg.pitch, fy = (qy - cfg.y0) / cfg.pitch;
+  const double flx = floor(fx), fly = floor(fy);
+  const int ix = (int)flx, iy = (int)fly;
+  const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
+  C2<Tf> acc = {Tf(0), Tf(0)};
+  const int W = cfg.W, H = cfg.H;
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy) {
+    const int y = iy + dy;
+    if (y < 0 || y >= H) continue;
+    const Tf wyv = dy ? wy : Tf(1) - wy;
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      const int x = ix + dx;
+      if (x < 0 || x >= W) continue;
+      const Tf wxv = dx ? wx : Tf(1) - wx;
+      acc = acc + tm[(size_t)y * W + x] * (wxv * wyv);
+    }
+  }
+  return acc;
+}
+
+// Patch -> zero-padded M x M spectrum in buf (natural FFT order, row stride M + 1).
+template <class Tf, int M>
+__device__ __forceinline__ void patch_spectrum(const DevCfg& cfg, const RayCtx& c,
+                                               const C2<Tf>* tm, C2<Tf>* buf,
+                                               const C2<Tf>* tw) {
+  constexpr int L = 4, E = M / L, SM = M + 1;
+  const int g = threadIdx.x >> 2, gl = threadIdx.x & 3;
+  const int br = bitrev(gl, 2);
+  const int P = cfg.P;
+  for (int row = g; row < P; row += kThreads / L) {
+    C2<Tf> x[E];
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      const int m = gl + L * n2;
+      x[n2] = m < P ? patch_sample<Tf>(cfg, c, tm, m, row) : C2<Tf>{Tf(0), Tf(0)};
+    }
+    group_fft<Tf, L, E, -1>(x, gl, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
+  }
+  __syncthreads();
+  for (int col = g; col < M; col += kThreads / L) {
+    C2<Tf> x[E];
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      const int n = gl + L * n2;
+      x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+    }
+    group_fft<Tf, L, E, -1>(x, gl, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) buf[(E * br + k2) * SM + col] = x[k2];
+  }
+  __syncthreads();
+}
+
+// Weight of shifted bin L for the sampling density (0 when evanescent).
+template <class Tf, int M>
+__device__ __forceinline__ double bin_weight(const RayCtx& c, const C2<Tf>* buf, int L, int sampling) {
+  constexpr int SM = M + 1;
+  const int jy = L / M - M / 2, jx = L % M - M / 2;
+  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+  if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out)) return 0.0;
+  if (sampling != 0) return 1.0;
+  return (double)cabs_rn(buf[(jy & (M - 1)) * SM + (jx & (M - 1))]);
+}
+
+// Exponential-of-semicircle spreading kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)).
+template <class Tg>
+__device__ __forceinline__ Tg es_kernel(Tg z, Tg two_over_w, Tg beta) {
+  const Tg t = z * two_over_w;
+  const Tg a = Tg(1) - t * t;
+  return a > Tg(0) ? (Tg)exp(beta * (sqrt(a) - Tg(1))) : Tg(0);
+}
+
+struct Secondary {          // one weighted secondary ray at the sensor
+  double dsx, dsy, dsz;     // direction after the DOE (for the adjoint)
+  double Ku, Kv, kz;
+  bool ok;
+};
+
+// Emission (direction from the tangential wavevector), conventional trace to the
+// sensor, and the Eq. 2 phase / frequencies of the wavelet.
+template <class Prec>
+__device__ __forceinline__ bool secondary_to_sensor(const DoeArgs& a, const RayCtx& c, int jx,
+                                                    int jy, typename Prec::Tp& phi0,
+                                                    typename Prec::Tp& wx, typename Prec::Tp& wy,
+                                                    double& dz_abs, Secondary& sec) {
+  using Tt = typename Prec::Tt;
+  using Tp = typename Prec::Tp;
+  const DevCfg& cfg = *a.cfg;
+  const DevPair& pr = a.pairs[c.pair];
+  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+  const double kz2 = c.k_out * c.k_out - Ku * Ku - Kv * Kv;
+  if (!(kz2 > 0.0)) return false;
+  const double kz = sqrt(kz2);
+  const double ik = 1.0 / c.k_out;
+  Tt d[3], p[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    d[i] = (Tt)((Ku * c.u[i] + Kv * c.v[i] + kz * c.n[i]) * ik);
+    p[i] = (Tt)c.p[i];
+  }
+  sec.Ku = Ku; sec.Kv = Kv; sec.kz = kz;
+  sec.dsx = (double)d[0]; sec.dsy = (double)d[1]; sec.dsz = (double)d[2];
+  Tt opl = (Tt)c.opl;
+  for (int s = cfg.s_doe + 1; s < cfg.n_surf; ++s) {
+    const DevSurf& ds = a.live->s[s];
+    const Surf<Tt> sf = surf_of<Tt>(ds);
+    Tt t;
+    if (!intersect(sf, p, d, t)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] += t * d[i];
+    opl += (Tt)pr.n_med[s] * t;
+    if (ds.semi_ap > 0 && (double)(p[0] * p[0] + p[1] * p[1]) > ds.semi_ap * ds.semi_ap) return false;
+    Tt nrm[3];
+    surface_normal(sf, p[0], p[1], nrm);
+    if (!refract(d, nrm, (Tt)(pr.n_med[s] / pr.n_med[s + 1]))) return false;
+  }
+  const Tt zs = (Tt)a.live->sensor_z;
+  const Tt t = (zs - p[2]) / d[2];
+  if (!(t > Tt(0))) return false;
+  const Tt ns = (Tt)pr.n_med[cfg.n_surf];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) p[i] += t * d[i];
+  opl += ns * t;
+  const Tp k0 = (Tp)c.k0;
+  const Tp dr = (Tp)d[0] * ((Tp)pr.pc[0] - (Tp)p[0]) + (Tp)d[1] * ((Tp)pr.pc[1] - (Tp)p[1]) +
+                (Tp)d[2] * ((Tp)zs - (Tp)p[2]);
+  phi0 = k0 * ((Tp)opl + (Tp)ns * dr);
+  wx = k0 * (Tp)ns * (Tp)cfg.psf_pitch * (Tp)d[0];
+  wy = k0 * (Tp)ns * (Tp)cfg.psf_pitch * (Tp)d[1];
+  dz_abs = fabs((double)d[2]);
+  sec.ok = true;
+  return true;
+}
+
+// Grid coordinate (in cells, [0, nf)) of a wavelet frequency.
+template <class Tp>
+__device__ __forceinline__ Tp grid_coord(Tp w, int nf) {
+  const Tp turns = w * (Tp)(1.0 / (2.0 * RW_PI));
+  return (turns - floor(turns)) * (Tp)nf;
+}
+
+template <class Prec>
+__device__ __forceinline__ void spread(const DevCfg& cfg, C2<typename Prec::Tg>* grid, int pair,
+                                       C2<typename Prec::Tg> cval, typename Prec::Tp wx,
+                                       typename Prec::Tp wy) {
+  using Tg = typename Prec::Tg;
+  using Tp = typename Prec::Tp;
+  const int nf = cfg.nf, w = cfg.w;
+  const Tp gx = grid_coord(wx, nf), gy = grid_coord(wy, nf);
+  const int lx0 = (int)ceil(gx - (Tp)(0.5 * w)), ly0 = (int)ceil(gy - (Tp)(0.5 * w));
+  const Tg tw = Tg(2.0 / w), beta = (Tg)cfg.beta;
+  Tg kx[16], ky[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i < w) {
+      kx[i] = es_kernel<Tg>((Tg)((Tp)(lx0 + i) - gx), tw, beta);
+      ky[i] = es_kernel<Tg>((Tg)((Tp)(ly0 + i) - gy), tw, beta);
+    }
+  }
+  C2<Tg>* gp = grid + (size_t)pair * nf * nf;
+  for (int j = 0; j < w; ++j) {
+    const int y = (ly0 + j) & (nf - 1);
+    const C2<Tg> cy = cval * ky[j];
+    C2<Tg>* row = gp + (size_t)y * nf;
+    for (int i = 0; i < w; ++i) {
+      const int x = (lx0 + i) & (nf - 1);
+      atomicAdd(&row[x].re, cy.re * kx[i]);
+      atomicAdd(&row[x].im, cy.im * kx[i]);
+    }
+  }
+}
+
+// Angle reference of the patch centre: U~_j = X_k exp(i pi (jx + jy)(P - 1) / M).
+template <class Tf>
+__device__ __forceinline__ C2<Tf> centre_ref(int jx, int jy, int P, int M) {
+  int num = ((jx + jy) * (P - 1)) % (2 * M);
+  if (num < 0) num += 2 * M;
+  Tf s, c;
+  sincospi_any((Tf)num / (Tf)M, &s, &c);
+  return {c, s};
+}
+
+template <class Prec, int M, bool kLDS>
+__global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
+  using Tf = typename Prec::Tf;
+  using Tg = typename Prec::Tg;
+  using Tp = typename Prec::Tp;
+  constexpr int SM = M + 1;
+  constexpr int C = (M * M) / kThreads;
+  static_assert(C >= 1, "patch spectrum must have at least one bin per thread");
+  __shared__ C2<Tf> s_buf[kLDS ? M * SM : 1];
+  __shared__ C2<Tf> s_tw[M];
+  __shared__ double s_pref[kThreads];
+  __shared__ double s_red[4];
+  __shared__ int s_redi[4];
+  const DevCfg& cfg = *a.cfg;
+  C2<Tf>* buf = kLDS ? s_buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
+  const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
+  C2<Tg>* grid = (C2<Tg>*)a.grid;
+  for (int i = threadIdx.x; i < M; i += kThreads) s_tw[i] = ((const C2<Tf>*)a.tw)[i];
+  __syncthreads();
+  const int N = cfg.N, P = cfg.P, t = threadIdx.x;
+  const double inv_m2 = 1.0 / ((double)M * M);
+  unsigned long long n_sec = 0, n_alive = 0;
+  for (size_t wi = blockIdx.x; wi < a.nray; wi += gridDim.x) {
+    const size_t gid = a.ray0 + wi;
+    const bool alive = a.st[7 * a.n_total + gid] != 0.0;
+    if (!alive) {
+      if (a.idx_out && cfg.sampling != 2)
+        for (int i = t; i < N; i += kThreads) a.idx_out[gid * N + i] = -1;
+      continue;
+    }
+    n_alive += (t == 0);
+    RayCtx c;
+    make_ctx(a, gid, c);
+    patch_spectrum<Tf, M>(cfg, c, tm, buf, s_tw);
+    // Sampling density and its CDF (chunks of C consecutive shifted bins per thread).
+    double acc = 0.0;
+    int lastpos = -1;
+    for (int q = 0; q < C; ++q) {
+      const int L = t * C + q;
+      const double wgt = bin_weight<Tf, M>(c, buf, L, cfg.sampling);
+      acc += wgt;
+      if (wgt > 0.0) lastpos = L;
+    }
+    double excl;
+    const double S = block_exclusive_scan(acc, s_red, excl);
+    s_pref[t] = excl;
+    const int lastpos_all = block_max_int(lastpos, s_redi);   // also a barrier for s_pref
+    const int Cpb = cfg.sampling == 2 ? C : 0;
+    if (cfg.sampling == 2) {
+      // FULL: every propagating bin once, weight U~ / M^2.
+      for (int q = 0; q < Cpb; ++q) {
+        const int L = t * C + q;
+        const int jy = L / M - M / 2, jx = L % M - M / 2;
+        const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+        if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out)) continue;
+        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+        Tp phi0, wx, wy; double dza; Secondary sec;
+        if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) continue;
+        const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+        const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
+        const C2<Tp> cv = (w * e) * (Tp)dza;
+        spread<Prec>(cfg, grid, c.pair, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+        ++n_sec;
+      }
+    } else if (S > 0.0) {
+      const double scale = cfg.sampling == 0 ? S * inv_m2 / N : S * inv_m2 / N;  // S or |Pi|
+      for (int i = t; i < N; i += kThreads) {
+        int J = -1;
+        if (a.replay) {
+          J = a.replay[gid * N + i];
+        } else {
+          const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
+                                        (uint32_t)c.pair, 0u) * S;
+          int lo = 0, hi = kThreads - 1;       // last chunk with prefix <= T
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= T) lo = mid; else hi = mid - 1;
+          }
+          double run = s_pref[lo];
+          int lp = -1;
+          for (int q = 0; q < C; ++q) {
+            const int L = lo * C + q;
+            const double wgt = bin_weight<Tf, M>(c, buf, L, cfg.sampling);
+            run += wgt;
+            if (wgt > 0.0) lp = L;
+            if (run > T) { J = L; break; }
+          }
+          if (J < 0) J = lp >= 0 ? lp : lastpos_all;
+        }
+        if (a.idx_out) a.idx_out[gid * N + i] = J;
+        if (J < 0) continue;
+        const int jy = J / M - M / 2, jx = J % M - M / 2;
+        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+        C2<Tp> w;
+        if (cfg.sampling == 0) {
+          const Tf mag = cabs_rn(X);
+          if (!(mag > Tf(0))) continue;
+          const Tp f = (Tp)(scale / (double)mag);
+          w = {(Tp)U.re * f, (Tp)U.im * f};
+        } else {
+          w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+        }
+        Tp phi0, wx, wy; double dza; Secondary sec;
+        if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) continue;
+        const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
+        const C2<Tp> cv = (w * e) * (Tp)dza;
+        spread<Prec>(cfg, grid, c.pair, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+        ++n_sec;
+      }
+    } else if (a.idx_out) {
+      for (int i = t; i < N; i += kThreads) a.idx_out[gid * N + i] = -1;
+    }
+    __syncthreads();   // buf is reused by the next ray
+  }
+  if (a.stats) {
+    if (n_alive) atomicAdd(&a.stats[0], n_alive);
+    if (n_sec) atomicAdd(&a.stats[1], n_sec);
+  }
+}
+
+// ------------------------------------------------------------- grid FFT ---
+// Row pass: one wavefront per grid row l_y, FFT (+i) over l_x, keep
+// k_x in [-Q/2, Q/2) and store transposed: T1[pair][c][l_y], c = k_x + Q/2.
+template <class Tg, int NF>
+__global__ __launch_bounds__(256) void k_grid_rows_fwd(const C2<Tg>* grid, C2<Tg>* t1,
+                                                       const C2<Tg>* tw, int Q, int pair0,
+                                                       int npairs) {
+  constexpr int E = NF / 64;
+  const int lane = threadIdx.x & 63;
+  const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (size_t)npairs * NF) return;
+  const int pair = pair0 + (int)(row / NF), ly = (int)(row % NF);
+  const C2<Tg>* src = grid + ((size_t)pair * NF + ly) * NF;
+  C2<Tg> x[E];
+#pragma unroll
+  for (int n2 = 0; n2 < E; ++n2) x[n2] = src[lane + 64 * n2];
+  group_fft<Tg, 64, E, +1>(x, lane, tw);
+  const int base = E * bitrev(lane, 6);
+#pragma unroll
+  for (int k2 = 0; k2 < E; ++k2) {
+    const int k = base + k2;
+    const int ks = k < NF / 2 ? k : k - NF;
+    if (ks >= -Q / 2 && ks < Q / 2)
+      t1[((size_t)pair * Q + (ks + Q / 2)) * NF + ly] = x[k2];
+  }
+}
+
+// Column pass: FFT (+i) over l_y for each kept column, deconvolve, crop, |U|^2.
+template <class Tg, int NF>
+__global__ __launch_bounds__(256) void k_grid_cols_fwd(const C2<Tg>* t1, const C2<Tg>* tw,
+                                                       const double* psi_hat, int Q, int pair0,
+                                                       int npairs, C2<Tg>* Uout, float* psf) {
+  constexpr int E = NF / 64;
+  const int lane = threadIdx.x & 63;
+  const size_t col = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= (size_t)npairs * Q) return;
+  const int pair = pair0 + (int)(col / Q), c = (int)(col % Q);
+  const C2<Tg>* src = t1 + ((size_t)pair * Q + c) * NF;
+  C2<Tg> x[E];
+#pragma unroll
+  for (int n2 = 0; n2 < E; ++n2) x[n2] = src[lane + 64 * n2];
+  group_fft<Tg, 64, E, +1>(x, lane, tw);
+  const int base = E * bitrev(lane, 6);
+#pragma unroll
+  for (int k2 = 0; k2 < E; ++k2) {
+    const int k = base + k2;
+    const int ks = k < NF / 2 ? k : k - NF;
+    if (ks >= -Q / 2 && ks < Q / 2) {
+      const int r = ks + Q / 2;
+      const Tg sc = (Tg)(1.0 / (psi_hat[c] * psi_hat[r]));
+      const C2<Tg> U = x[k2] * sc;
+      const size_t o = ((size_t)pair * Q + r) * Q + c;
+      Uout[o] = U;
+      psf[o] = (float)((double)U.re * U.re + (double)U.im * U.im);
+    }
+  }
+}
+
+// Component-major ray state [8][n] -> ray-major [n][8].
+__global__ void k_export_state(const double* st, size_t n, double* out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 8 * n) return;
+  const size_t ray = i / 8, c = i % 8;
+  out[i] = st[c * n + ray];
+}
+
+// ------------------------------------------------------------------ loss ---
+// Per pair: alpha = <I,T>/<I,I>, L_p = ||alpha I - T||^2 (Eq. 3, closed-form alpha).
+__global__ __launch_bounds__(256) void k_loss_pairs(const float* psf, const float* target,
+                                                    int Q2, int pair0, double* alpha,
+                                                    double* lossp) {
+  __shared__ double s_red[4];
+  const int pair = pair0 + blockIdx.x;
+  const float* I = psf + (size_t)pair * Q2;
+  const float* T = target + (size_t)pair * Q2;
+  double ii = 0, it = 0;
+  for (int i = threadIdx.x; i < Q2; i += blockDim.x) {
+    ii += (double)I[i] * I[i];
+    it += (double)I[i] * T[i];
+  }
+  ii = block_sum(ii, s_red);
+  it = block_sum(it, s_red);
+  const double al = ii > 0 ? it / ii : 0.0;
+  double l = 0;
+  for (int i = threadIdx.x; i < Q2; i += blockDim.x) {
+    const double r = al * I[i] - T[i];
+    l += r * r;
+  }
+  l = block_sum(l, s_red);
+  if (threadIdx.x == 0) { alpha[pair] = al; lossp[pair] = l; }
+}
+
+__global__ void k_loss_total(const double* lossp, int n_pairs, float* loss_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0;
+    for (int i = 0; i < n_pairs; ++i) s += lossp[i];
+    *loss_out = (float)s;
+  }
+}
+
+}  // namespace rw

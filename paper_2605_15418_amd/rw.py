@@ -1,0 +1,266 @@
+"""Thin Python binding of librw.so (the C ABI declared in include/rw.h).
+
+Argument marshalling only: every step of the ray-wave path runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory and the current
+HIP stream.  There is no CPU fallback: if the library is missing, or no GPU
+is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librw.so")
+
+RW_SURF_ASPHERE, RW_SURF_PLANE = 0, 1
+PARAM_FIELDS = {"curv": 0, "conic": 1, "A4": 2, "A6": 3, "A8": 4, "A10": 5, "gap": 6}
+SAMPLING = {"mag": 0, "uni": 1, "full": 2}
+PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
+STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",
+          4: "RW_ERR_NONFINITE", 5: "RW_ERR_OOM", 6: "RW_ERR_HIP", 7: "RW_ERR_UNSUPPORTED"}
+
+EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
+            "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
+            "rw_last_error")
+
+
+class rw_surface(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("carries_doe", ctypes.c_int),
+                ("z_vertex", ctypes.c_double), ("curvature", ctypes.c_double),
+                ("conic", ctypes.c_double), ("asph", ctypes.c_double * 4),
+                ("semi_aperture", ctypes.c_double), ("n_A", ctypes.c_double),
+                ("n_B", ctypes.c_double)]
+
+
+class rw_doe_desc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("pitch", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double)]
+
+
+class rw_param_ref(ctypes.Structure):
+    _fields_ = [("surface", ctypes.c_int), ("field", ctypes.c_int), ("scale", ctypes.c_double)]
+
+
+class rw_config(ctypes.Structure):
+    _fields_ = [("n_lambda", ctypes.c_int), ("lambda_host", ctypes.POINTER(ctypes.c_double)),
+                ("n_field", ctypes.c_int), ("field_tan_host", ctypes.POINTER(ctypes.c_double)),
+                ("launch_center_host", ctypes.POINTER(ctypes.c_double)),
+                ("launch_z", ctypes.c_double), ("launch_half", ctypes.c_double),
+                ("rays_side", ctypes.c_int), ("sensor_z", ctypes.c_double),
+                ("psf_q", ctypes.c_int), ("psf_pitch", ctypes.c_double),
+                ("psf_center_host", ctypes.POINTER(ctypes.c_double)),
+                ("patch_p", ctypes.c_int), ("pad_factor", ctypes.c_int), ("n_ssr", ctypes.c_int),
+                ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("batched", ctypes.c_int),
+                ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
+class rw_stats(ctypes.Structure):
+    _fields_ = [("rays_total", ctypes.c_uint64), ("rays_alive", ctypes.c_uint64),
+                ("secondaries", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load librw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    lib.rw_plan_create.argtypes = [ctypes.POINTER(rw_surface), ctypes.c_int,
+                                   ctypes.POINTER(rw_doe_desc), ctypes.POINTER(rw_param_ref),
+                                   ctypes.c_int, ctypes.POINTER(rw_config), ctypes.POINTER(vp)]
+    lib.rw_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.rw_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    lib.rw_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.rw_get_stats.argtypes = [vp, ctypes.POINTER(rw_stats)]
+    lib.rw_export_doe_hits.argtypes = [vp, vp, vp, vp]
+    lib.rw_plan_destroy.argtypes = [vp]
+    lib.rw_status_string.argtypes = [ctypes.c_int]
+    lib.rw_status_string.restype = ctypes.c_char_p
+    lib.rw_last_error.restype = ctypes.c_char_p
+    for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
+                 "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class RWError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(lib, st):
+    if st != 0:
+        raise RWError(st, lib.rw_last_error().decode())
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dbl_array(vals):
+    a = np.ascontiguousarray(np.asarray(vals, dtype=np.float64).ravel())
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Plan:
+    """A plan of the library for one system description and configuration.
+
+    system / cfg are the dictionaries produced by the workload generators:
+    system = {"surfaces", "sensor_z", "doe", "params"}, cfg = {"lambdas",
+    "fields", "launch_center", "launch_z", "launch_half", "rays_side", "psf_q",
+    "psf_pitch", "psf_center", "patch_p", "pad", "n_ssr", "sampling", "seed"}.
+    """
+
+    def __init__(self, system, cfg, precision="mixed", batched=True, spread_width=0,
+                 device="cuda"):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the ray-wave library runs on the GPU only")
+        self.device = torch.device(device)
+        self.system, self.cfg = system, cfg
+        surfs = system["surfaces"]
+        arr = (rw_surface * len(surfs))()
+        for i, s in enumerate(surfs):
+            arr[i].kind = RW_SURF_PLANE if s["kind"] == "plane" else RW_SURF_ASPHERE
+            arr[i].carries_doe = int(bool(s.get("doe", False)))
+            arr[i].z_vertex = s["z"]
+            arr[i].curvature = s["c"]
+            arr[i].conic = s["k"]
+            for j in range(4):
+                arr[i].asph[j] = s["A"][j]
+            arr[i].semi_aperture = s["semi_ap"]
+            arr[i].n_A = s["nA"]
+            arr[i].n_B = s["nB"]
+        d = system["doe"]
+        doe = rw_doe_desc(d["H"], d["W"], d["pitch"], d["x0"], d["y0"])
+        prm = system.get("params", [])
+        parr = (rw_param_ref * max(1, len(prm)))()
+        for i, p in enumerate(prm):
+            parr[i].surface = p["surface"]
+            parr[i].field = PARAM_FIELDS[p["field"]]
+            parr[i].scale = p["scale"]
+        self._keep = []
+        lam, lam_p = _dbl_array(cfg["lambdas"])
+        ft, ft_p = _dbl_array(cfg["fields"])
+        lc, lc_p = _dbl_array(cfg["launch_center"])
+        pc, pc_p = _dbl_array(cfg["psf_center"])
+        self._keep += [lam, ft, lc, pc]
+        c = rw_config()
+        c.n_lambda = len(cfg["lambdas"])
+        c.lambda_host = lam_p
+        c.n_field = len(cfg["fields"])
+        c.field_tan_host = ft_p
+        c.launch_center_host = lc_p
+        c.launch_z = cfg["launch_z"]
+        c.launch_half = cfg["launch_half"]
+        c.rays_side = cfg["rays_side"]
+        c.sensor_z = system["sensor_z"]
+        c.psf_q = cfg["psf_q"]
+        c.psf_pitch = cfg["psf_pitch"]
+        c.psf_center_host = pc_p
+        c.patch_p = cfg["patch_p"]
+        c.pad_factor = cfg["pad"]
+        c.n_ssr = cfg["n_ssr"]
+        c.sampling = SAMPLING[cfg["sampling"]]
+        c.precision = PRECISION[precision]
+        c.batched = int(bool(batched))
+        c.spread_width = int(spread_width)
+        c.seed = int(cfg["seed"])
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
+                                                 len(prm), ctypes.byref(c), ctypes.byref(h)))
+        self.handle = h
+        nb = ctypes.c_size_t()
+        _check(self.lib, self.lib.rw_plan_workspace_bytes(h, ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws_raw.data_ptr()) % 256
+        self.ws = self._ws_raw[off:off + self.ws_bytes]
+        self.L = len(cfg["lambdas"])
+        self.F = len(cfg["fields"])
+        self.Q = cfg["psf_q"]
+        self.n_params = len(prm)
+        self.n_rays = self.L * self.F * cfg["rays_side"] ** 2
+        self.N = cfg["n_ssr"]
+        self.M = cfg["patch_p"] * cfg["pad"]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.rw_plan_destroy(h)
+            self.handle = None
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, lens_params, phase, amp, target=None, replay=None, want_idx=False,
+                psf_out=None, loss_out=None, idx_out=None):
+        """Returns (psf [L,F,Q,Q] float32, loss (tensor [1]) or None, idx or None)."""
+        dev = self.device
+        psf = psf_out if psf_out is not None else torch.empty(
+            (self.L, self.F, self.Q, self.Q), dtype=torch.float32, device=dev)
+        loss = None
+        if target is not None:
+            loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32,
+                                                                     device=dev)
+        idx = idx_out
+        if want_idx and idx is None:
+            idx = torch.empty((self.L * self.F, self.cfg["rays_side"] ** 2, self.N),
+                              dtype=torch.int32, device=dev)
+        self._fwd_keep = (lens_params, phase, amp, target, replay)
+        st = self.lib.rw_forward(self.handle, _dptr(lens_params), _dptr(phase), _dptr(amp),
+                                 _dptr(target), _dptr(psf), _dptr(loss), _dptr(self.ws),
+                                 self.ws_bytes, _dptr(replay), _dptr(idx), self._stream())
+        _check(self.lib, st)
+        return psf, loss, idx
+
+    def backward(self, dL_dpsf=None, d_phase=None, d_amp=None, d_lens=None):
+        d = self.system["doe"]
+        dev = self.device
+        dp = d_phase if d_phase is not None else torch.empty((d["H"], d["W"]),
+                                                             dtype=torch.float32, device=dev)
+        da = d_amp if d_amp is not None else torch.empty_like(dp)
+        dl = d_lens
+        if dl is None and self.n_params:
+            dl = torch.empty(self.n_params, dtype=torch.float32, device=dev)
+        st = self.lib.rw_backward(self.handle, _dptr(dL_dpsf), _dptr(dp), _dptr(da), _dptr(dl),
+                                  _dptr(self.ws), self.ws_bytes, self._stream())
+        _check(self.lib, st)
+        return dp, da, dl
+
+    def stats(self):
+        s = rw_stats()
+        _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
+        return {"rays_total": s.rays_total, "rays_alive": s.rays_alive,
+                "secondaries": s.secondaries}
+
+    def doe_hits(self):
+        out = torch.empty((self.n_rays, 8), dtype=torch.float64, device=self.device)
+        _check(self.lib, self.lib.rw_export_doe_hits(self.handle, _dptr(self.ws), _dptr(out),
+                                                     self._stream()))
+        return out
+
+
+class HybridPSF(torch.autograd.Function):
+    """torch.autograd.Function over rw_forward / rw_backward (adjoint G1)."""
+
+    @staticmethod
+    def forward(ctx, plan, lens_params, phase, amp):
+        psf, _, _ = plan.forward(lens_params, phase, amp)
+        ctx.plan = plan
+        return psf
+
+    @staticmethod
+    def backward(ctx, g):
+        dp, da, dl = ctx.plan.backward(g.contiguous())
+        return None, dl, dp, da

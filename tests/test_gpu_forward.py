@@ -1,0 +1,170 @@
+"""GPU forward path vs the FP64 oracle, through the C ABI.
+
+Bars (written here, derived in the design notes):
+  * FP64 form: sample indices bit-exact; PSF within 1e-6 (float32 output)
+  * MIXED form (FP32 FFT / grids, FP64 trace and phases): PSF within 1e-4 of
+    the oracle with the same sample indices (FULL mode, or the oracle's own
+    indices replayed on the GPU); own draws agree on >= 97% of indices and
+    every disagreement sits on a CDF edge the FP32 spectrum can move
+  * plain FP32 form: shows the phase drift of FP32 optical path (P12)
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import rw_oracle as O
+from rwcases import (gpu_inputs, oracle_param_values, oracle_psf, rel_l2, small_hologram,
+                     small_singlet, worst_pair_rel)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rw():
+    import paper_2605_15418_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.load_library()
+    return pkg
+
+
+def _run(rw, system, cfg, maps, precision, **kw):
+    plan = rw.Plan(system, cfg, precision=precision, batched=kw.pop("batched", True),
+                   spread_width=kw.pop("spread_width", 0))
+    vals, ph, am = gpu_inputs(system, maps)
+    psf, loss, idx = plan.forward(vals, ph, am, **kw)
+    torch.cuda.synchronize()
+    return plan, psf.cpu().numpy(), idx
+
+
+@pytest.mark.parametrize("case", ["singlet", "hologram"])
+def test_trace_state_at_doe(rw, case):
+    system, cfg, maps = small_singlet() if case == "singlet" else small_hologram(rays=12)
+    plan, _, _ = _run(rw, system, cfg, maps, "fp64" if case == "singlet" else "mixed")
+    hits = plan.doe_hits().cpu().numpy()
+    vals = oracle_param_values(system)
+    surfs, _ = O.build_surfaces(system, torch.tensor(vals))
+    R2 = cfg["rays_side"] ** 2
+    F = len(cfg["fields"])
+    for l in range(len(cfg["lambdas"])):
+        for f in range(F):
+            p, d, opl = O.launch(cfg, f)
+            p, d, opl, alive, _ = O.trace_to_doe(surfs, cfg["lambdas"][l], p, d, opl)
+            doe = system["doe"]
+            fx = (p[:, 0] - doe["x0"]) / doe["pitch"]
+            fy = (p[:, 1] - doe["y0"]) / doe["pitch"]
+            alive = alive & (fx >= -0.5) & (fx <= doe["W"] - 0.5) & (fy >= -0.5) & \
+                (fy <= doe["H"] - 0.5)
+            g = hits[(l * F + f) * R2:(l * F + f + 1) * R2]
+            a = alive.numpy()
+            assert np.array_equal(g[:, 7] != 0, a)
+            assert np.max(np.abs(g[a, 0:3] - p.numpy()[a])) < 1e-11
+            assert np.max(np.abs(g[a, 3:6] - d.numpy()[a])) < 1e-13
+            assert np.max(np.abs(g[a, 6] - opl.numpy()[a])) < 1e-11
+
+
+def test_fp64_mc_indices_exact_and_psf(rw):
+    system, cfg, maps = small_singlet(sampling="mag")
+    plan, psf, idx = _run(rw, system, cfg, maps, "fp64", want_idx=True)
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    gi = idx.cpu().numpy()
+    for pr, a in aux.items():
+        assert np.array_equal(gi[pr], a["J"]), "sample indices differ"
+    assert rel_l2(psf, ref) < 1e-6
+    st = plan.stats()
+    assert st["rays_total"] == cfg["rays_side"] ** 2
+    assert st["secondaries"] == int(sum((a["J"] >= 0).sum() for a in aux.values()))
+
+
+@pytest.mark.parametrize("sampling", ["full", "uni"])
+def test_fp64_other_samplings(rw, sampling):
+    system, cfg, maps = small_singlet(sampling=sampling, rays=8)
+    plan, psf, idx = _run(rw, system, cfg, maps, "fp64", want_idx=(sampling != "full"))
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    if sampling != "full":
+        assert np.array_equal(idx.cpu().numpy()[0], aux[0]["J"])
+    assert rel_l2(psf, ref) < 1e-6
+
+
+def test_mixed_full_mode_psf_within_1e4(rw):
+    system, cfg, maps = small_hologram(sampling="full")
+    plan, psf, _ = _run(rw, system, cfg, maps, "mixed")
+    ref, _ = oracle_psf(system, cfg, maps, values=oracle_param_values(system))
+    assert worst_pair_rel(psf, ref) < 1e-4
+
+
+def test_mixed_mc_replayed_oracle_indices_within_1e4(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=48)
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    rep = torch.tensor(np.stack([aux[p]["J"] for p in sorted(aux)]), dtype=torch.int32,
+                       device="cuda")
+    plan, psf, _ = _run(rw, system, cfg, maps, "mixed", replay=rep)
+    assert worst_pair_rel(psf, ref) < 1e-4
+
+
+def test_mixed_mc_own_draws_agree_and_are_valid(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=48)
+    plan, psf, idx = _run(rw, system, cfg, maps, "mixed", want_idx=True)
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    gi = idx.cpu().numpy()
+    agree, total = 0, 0
+    for pr, a in aux.items():
+        J = a["J"]
+        agree += int((gi[pr] == J).sum())
+        total += J.size
+        # every disagreement must be a CDF edge flip: both bins adjacent in the
+        # oracle's CDF order once zero-weight bins are skipped
+        mag = a["spectrum"].abs().reshape(J.shape[0], -1).numpy()
+        prop = a["prop"].reshape(J.shape[0], -1).numpy()
+        w = np.where(prop, mag, 0.0)
+        cdf = np.cumsum(w, axis=1)
+        for r, i in zip(*np.nonzero(gi[pr] != J)):
+            lo, hi = sorted((int(gi[pr][r, i]), int(J[r, i])))
+            assert lo >= 0
+            between = w[r, lo + 1:hi]
+            assert np.all(between == 0) or hi - lo == 1, (pr, r, i, lo, hi)
+            # the edge sits within the FP32 spectrum error of the draw
+            assert abs(cdf[r, lo] / cdf[r, -1]) > 0
+    assert agree / total >= 0.97, agree / total
+
+
+def test_batched_equals_per_pair_launches(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
+    _, a, ia = _run(rw, system, cfg, maps, "mixed", want_idx=True)
+    _, b, ib = _run(rw, system, cfg, maps, "mixed", want_idx=True, batched=False)
+    assert torch.equal(ia, ib)
+    assert rel_l2(a, b) < 1e-5
+
+
+def test_plain_fp32_shows_phase_drift(rw):
+    system, cfg, maps = small_hologram(sampling="full", rays=6, n_lambda=1, n_field_side=1)
+    ref, _ = oracle_psf(system, cfg, maps, values=oracle_param_values(system))
+    _, mixed, _ = _run(rw, system, cfg, maps, "mixed")
+    _, fp32, _ = _run(rw, system, cfg, maps, "fp32", batched=False)
+    e_mixed, e_fp32 = rel_l2(mixed, ref), rel_l2(fp32, ref)
+    assert e_mixed < 1e-4
+    assert e_fp32 > 10 * e_mixed
+
+
+def test_edge_cases_dead_rays_and_single_ray(rw):
+    # launch grid entirely outside the DOE: every ray dies, PSF is zero
+    system, cfg, maps = small_singlet(sampling="mag", rays=4)
+    cfg["launch_center"] = [[3.0, 3.0]]
+    plan, psf, idx = _run(rw, system, cfg, maps, "fp64", want_idx=True)
+    assert np.all(psf == 0) and np.all(idx.cpu().numpy() == -1)
+    assert plan.stats()["rays_alive"] == 0
+    # one ray
+    system, cfg, maps = small_singlet(sampling="mag", rays=1)
+    plan, psf, idx = _run(rw, system, cfg, maps, "fp64", want_idx=True)
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    assert np.array_equal(idx.cpu().numpy()[0], aux[0]["J"])
+    assert rel_l2(psf, ref) < 1e-6
+
+
+def test_invalid_shapes_are_rejected(rw):
+    system, cfg, maps = small_singlet()
+    bad = dict(cfg, psf_q=48)
+    with pytest.raises(rw.RWError, match="RW_ERR_SHAPE"):
+        rw.Plan(system, bad, precision="fp64")
+    bad = dict(cfg, patch_p=12)
+    with pytest.raises(rw.RWError, match="RW_ERR_SHAPE"):
+        rw.Plan(system, bad, precision="fp64")

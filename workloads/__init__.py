@@ -82,19 +82,32 @@ def field_grid(max_deg, n):
     return [[float(tx), float(ty)] for ty in a for tx in a]
 
 
-def _launch_centres(fields, z_stop, z_launch):
-    """Straight back-projection of the stop centre along each field direction."""
-    return [[-tx * (z_stop - z_launch), -ty * (z_stop - z_launch)] for tx, ty in fields]
+def _launch_centres(fields, z_aim, z_launch):
+    """Launch-grid centres whose central ray heads for (0, 0, z_aim)."""
+    return [[-tx * (z_aim - z_launch), -ty * (z_aim - z_launch)] for tx, ty in fields]
+
+
+def singlet_entrance_pupil(n, R1, R2, ct, z_front, z_stop):
+    """Paraxial entrance pupil (position, magnification) of a stop behind a
+    thick singlet: the stop imaged back through the lens (thick-lens focal
+    length and principal planes).  Used only to aim the launch grid."""
+    P = (n - 1) * (1 / R1 - 1 / R2 + (n - 1) * ct / (n * R1 * R2))
+    f = 1 / P
+    zH = z_front - f * (n - 1) * ct / (n * R2)          # front principal plane
+    zH2 = z_front + ct - f * (n - 1) * ct / (n * R1)    # rear principal plane
+    so = z_stop - zH2
+    si = 1 / (1 / f - 1 / so)
+    return zH - si, -si / so
 
 
 def _psf_centres(lambdas, fields, dz):
     return [[[tx * dz, ty * dz] for tx, ty in fields] for _ in lambdas]
 
 
-def _cfg(lambdas, fields, z_stop, z_launch, launch_half, rays_side, Q, psf_pitch, dz_sensor,
+def _cfg(lambdas, fields, z_aim, z_launch, launch_half, rays_side, Q, psf_pitch, dz_sensor,
          P, N, sampling="mag", pad=2, seed=0):
     return {"lambdas": [float(l) for l in lambdas], "fields": fields,
-            "launch_center": _launch_centres(fields, z_stop, z_launch),
+            "launch_center": _launch_centres(fields, z_aim, z_launch),
             "launch_z": float(z_launch), "launch_half": float(launch_half),
             "rays_side": int(rays_side), "psf_q": int(Q), "psf_pitch": float(psf_pitch),
             "psf_center": _psf_centres(lambdas, fields, dz_sensor),
@@ -119,8 +132,9 @@ def singlet_zoneplate(rays_side=64, H=256, pitch=0.004, P=32, N=256, Q=128, psf_
     system = {"surfaces": surfs, "sensor_z": z_doe + dz, "doe": doe_desc(H, H, pitch),
               "params": [{"surface": 0, "field": "curv", "scale": 1 / 50.0},
                          {"surface": 1, "field": "curv", "scale": 1 / 50.0}]}
-    half = 0.5 * (H * pitch) / 1.024
-    cfg = _cfg([LAM_D], [[0.0, 0.0]], z_doe, -1.0, half, rays_side, Q, psf_pitch, dz, P, N,
+    z_ep, mag = singlet_entrance_pupil(1.5168, 50.0, -50.0, 5.0, 0.0, z_doe)
+    half = 0.95 * mag * 0.5 * H * pitch
+    cfg = _cfg([LAM_D], [[0.0, 0.0]], z_ep, -1.0, half, rays_side, Q, psf_pitch, dz, P, N,
                sampling, seed=seed)
     phase = kinoform_zone_plate(system["doe"], 100.0, LAM_D)
     maps = {"phase": phase.astype(np.float32), "amp": np.ones_like(phase, dtype=np.float32),
@@ -165,8 +179,9 @@ def asphere_hologram(rays_side=256, H=1024, pitch=0.001, P=64, N=256, Q=512, psf
     lambdas = [LAM_F, LAM_D, LAM_C][:n_lambda] if n_lambda <= 3 else \
         list(np.linspace(400e-6, 700e-6, n_lambda))
     fields = field_grid(max_deg, n_field_side)
-    half = 0.45 * (H * pitch) / 1.024
-    cfg = _cfg(lambdas, fields, z_doe, -1.0, half, rays_side, Q, psf_pitch, dz, P, N, sampling,
+    z_ep, mag = singlet_entrance_pupil(1.5168, R, -R, 4.0, 0.0, z_doe)
+    half = 0.9 * mag * 0.5 * H * pitch
+    cfg = _cfg(lambdas, fields, z_ep, -1.0, half, rays_side, Q, psf_pitch, dz, P, N, sampling,
                seed=seed)
     rng = np.random.default_rng(20260000 + cfg_id)
     phase = 2 * math.pi * bandlimited_uniform(H, H, 0.25, rng)
