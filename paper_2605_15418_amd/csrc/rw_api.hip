@@ -84,12 +84,15 @@ struct rw_plan {
   double base_sensor_z;
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
-      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, total;
+      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
   const float* fwd_target = nullptr;
   const int32_t* fwd_replay = nullptr;
+  const float* fwd_phase = nullptr;
+  const float* fwd_psf = nullptr;
+  const float* fwd_amp = nullptr;
   void* fwd_ws = nullptr;
   hipStream_t fwd_stream = nullptr;
 };
@@ -181,6 +184,79 @@ rw_status doe_fwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
     case RW_PREC_MIXED: return doe_fwd_prec<PrecMIXED>(pl, a, blocks, st);
     default: return doe_fwd_prec<PrecFP32>(pl, a, blocks, st);
   }
+}
+
+template <class Prec, int M, bool LDS>
+void launch_doe_bwd(const DoeArgs& a, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((k_doe_bwd<Prec, M, LDS>), dim3(blocks), dim3(kThreads), 0, st, a);
+}
+
+template <class Prec>
+rw_status doe_bwd_prec(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+  constexpr bool dbl = sizeof(typename Prec::Tf) == 8;
+  switch (pl->M) {
+    case 16: launch_doe_bwd<Prec, 16, true>(a, blocks, st); break;
+    case 32: launch_doe_bwd<Prec, 32, true>(a, blocks, st); break;
+    case 64: launch_doe_bwd<Prec, 64, true>(a, blocks, st); break;
+    case 128:
+      if (dbl) launch_doe_bwd<Prec, 128, false>(a, blocks, st);
+      else launch_doe_bwd<Prec, 128, !dbl>(a, blocks, st);
+      break;
+    case 256: launch_doe_bwd<Prec, 256, false>(a, blocks, st); break;
+    default: return fail(RW_ERR_SHAPE, "unsupported FFT size M");
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status doe_bwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+  switch (pl->cfg.precision) {
+    case RW_PREC_FP64: return doe_bwd_prec<PrecFP64>(pl, a, blocks, st);
+    case RW_PREC_MIXED: return doe_bwd_prec<PrecMIXED>(pl, a, blocks, st);
+    default: return doe_bwd_prec<PrecFP32>(pl, a, blocks, st);
+  }
+}
+
+template <class Tg, int NF>
+void launch_grid_bwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
+                     const float* dpsf) {
+  char* b = (char*)ws;
+  const int Q = pl->Q;
+  const size_t nq = (size_t)npairs * Q * Q;
+  hipLaunchKernelGGL((k_psf_cograd<Tg>), dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st,
+                     dpsf, (const float*)pl->fwd_psf, pl->fwd_target,
+                     (const double*)(b + pl->off_alpha), (const C2<Tg>*)(b + pl->off_U),
+                     pl->d_psi, Q, pair0, npairs, (C2<Tg>*)(b + pl->off_G));
+  const size_t cols = (size_t)npairs * Q;
+  hipLaunchKernelGGL((k_grid_cols_bwd<Tg, NF>), dim3((unsigned)((cols + 3) / 4)), dim3(256), 0,
+                     st, (const C2<Tg>*)(b + pl->off_G), (const C2<Tg>*)pl->d_tw_nf, Q, pair0,
+                     npairs, (C2<Tg>*)(b + pl->off_t1));
+  const size_t rows = (size_t)npairs * NF;
+  hipLaunchKernelGGL((k_grid_rows_bwd<Tg, NF>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0,
+                     st, (const C2<Tg>*)(b + pl->off_t1), (const C2<Tg>*)pl->d_tw_nf, Q, pair0,
+                     npairs, (C2<Tg>*)(b + pl->off_grid));
+}
+
+template <class Tg>
+rw_status grid_bwd_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
+                     const float* dpsf) {
+  switch (pl->nf) {
+    case 64: launch_grid_bwd<Tg, 64>(pl, ws, st, pair0, npairs, dpsf); break;
+    case 128: launch_grid_bwd<Tg, 128>(pl, ws, st, pair0, npairs, dpsf); break;
+    case 256: launch_grid_bwd<Tg, 256>(pl, ws, st, pair0, npairs, dpsf); break;
+    case 512: launch_grid_bwd<Tg, 512>(pl, ws, st, pair0, npairs, dpsf); break;
+    case 1024: launch_grid_bwd<Tg, 1024>(pl, ws, st, pair0, npairs, dpsf); break;
+    case 2048: launch_grid_bwd<Tg, 2048>(pl, ws, st, pair0, npairs, dpsf); break;
+    default: return fail(RW_ERR_SHAPE, "unsupported grid size");
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status grid_bwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
+                   const float* dpsf) {
+  if (pl->cfg.precision == RW_PREC_FP64) return grid_bwd_t<double>(pl, ws, st, pair0, npairs, dpsf);
+  return grid_bwd_t<float>(pl, ws, st, pair0, npairs, dpsf);
 }
 
 template <class T>
@@ -403,6 +479,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
   pl->off_raygrad = take(8 * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
+  pl->off_G = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
   pl->total = o;
   *out = pl;
   return RW_OK;
@@ -494,6 +571,9 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   pl->fwd_done = true;
   pl->fwd_target = target;
   pl->fwd_replay = replay_idx;
+  pl->fwd_phase = doe_phase;
+  pl->fwd_psf = psf_out;
+  pl->fwd_amp = doe_amp;
   pl->fwd_ws = ws;
   pl->fwd_stream = st;
   return RW_OK;
@@ -523,14 +603,64 @@ rw_status rw_export_doe_hits(const rw_plan* pl, const void* ws, double* out, voi
 
 rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
                       float* d_lens, void* ws, size_t ws_bytes, void* stream) {
-  return rw_backward_impl(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, ws_bytes, stream);
+  if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
+  if (ws != pl->fwd_ws || ws_bytes < pl->total)
+    return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");
+  if (!dL_dpsf && !pl->fwd_target)
+    return fail(RW_ERR_STATE, "dL_dpsf is NULL and the forward had no target");
+  const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;
+  if (want_lens && (!pl->planar_doe || pl->has_post))
+    return fail(RW_ERR_UNSUPPORTED,
+                "lens-parameter gradients need a planar DOE followed directly by the sensor");
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)ws;
+  const bool dbl = pl->cfg.precision == RW_PREC_FP64;
+  const size_t nmap = (size_t)pl->H * pl->W;
+  if (dbl) zero<double>(b + pl->off_gt, 2 * nmap, st);
+  else zero<float>(b + pl->off_gt, 2 * nmap, st);
+  zero<double>(b + pl->off_lensg, RW_LENSG_SLOTS, st);
+  if (want_lens) zero<double>(b + pl->off_raygrad, 8 * pl->n_total, st);
+  DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
+  a.adj = b + pl->off_grid;
+  a.want_lens = want_lens ? 1 : 0;
+  a.stats = nullptr;
+  const int groups = pl->cfg.batched ? 1 : pl->n_pairs;
+  const int ppg = pl->cfg.batched ? pl->n_pairs : 1;
+  for (int gi = 0; gi < groups; ++gi) {
+    const int pair0 = gi * ppg;
+    rw_status s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
+    if (s != RW_OK) return s;
+    const size_t nr = (size_t)ppg * pl->R2;
+    a.ray0 = (size_t)pair0 * pl->R2;
+    a.nray = nr;
+    const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
+    s = doe_bwd(pl, a, blocks, st);
+    if (s != RW_OK) return s;
+    if (want_lens) {
+      hipLaunchKernelGGL(k_trace_bwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
+                         pl->d_cfg, pl->d_pairs, (const DevLive*)(b + pl->off_live),
+                         (const double*)(b + pl->off_st), (const double*)(b + pl->off_ck),
+                         (const double*)(b + pl->off_raygrad), pl->n_total, a.ray0, nr,
+                         (double*)(b + pl->off_lensg));
+      HIPCHK(hipGetLastError());
+    }
+  }
+  const int n = (int)nmap;
+  if (dbl)
+    hipLaunchKernelGGL(k_dmaps<double>, dim3((n + 255) / 256), dim3(256), 0, st,
+                       (const float*)pl->fwd_phase, (const float*)pl->fwd_amp,
+                       (const C2<double>*)(b + pl->off_gt), d_phase, d_amp, n);
+  else
+    hipLaunchKernelGGL(k_dmaps<float>, dim3((n + 255) / 256), dim3(256), 0, st,
+                       (const float*)pl->fwd_phase, (const float*)pl->fwd_amp,
+                       (const C2<float>*)(b + pl->off_gt), d_phase, d_amp, n);
+  if (want_lens)
+    hipLaunchKernelGGL(k_lens_map, dim3(1), dim3(64), 0, st, pl->d_cfg, pl->d_prm,
+                       (const double*)(b + pl->off_lensg), d_lens);
+  HIPCHK(hipGetLastError());
+  return RW_OK;
 }
 
 }  // extern "C"
 
-static rw_status rw_backward_impl(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
-                                  float* d_lens, void* ws, size_t ws_bytes, void* stream) {
-  (void)pl; (void)dL_dpsf; (void)d_phase; (void)d_amp; (void)d_lens; (void)ws; (void)ws_bytes;
-  (void)stream;
-  return fail(RW_ERR_UNSUPPORTED, "backward not built yet");
-}

@@ -1,0 +1,116 @@
+"""GPU adjoint (G1: sample indices held fixed) vs the FP64 oracle's
+torch.autograd gradient, through the C ABI.
+
+Bars: FP64 form within 1e-6 (float32 outputs); MIXED form within 1e-3 per
+gradient group (d phase, d amplitude, d lens), the gradient tolerance of the
+hot-path target, on the same sample indices as the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import rw_oracle as O
+from rwcases import gpu_inputs, oracle_param_values, rel_l2, small_hologram, small_singlet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rw():
+    import paper_2605_15418_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.load_library()
+    return pkg
+
+
+def _oracle_grad(system, cfg, maps, replays=None):
+    vals = oracle_param_values(system)
+    return O.loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                           maps["amp"].astype(np.float64), vals,
+                           maps["target"].astype(np.float64), replays=replays)
+
+
+def _gpu_grad(rw, system, cfg, maps, precision, replay=None, batched=True):
+    plan = rw.Plan(system, cfg, precision=precision, batched=batched)
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    psf, loss, _ = plan.forward(vals, ph, am, target=tg, replay=replay)
+    dp, da, dl = plan.backward()
+    torch.cuda.synchronize()
+    return loss.item(), dp.cpu().numpy(), da.cpu().numpy(), dl.cpu().numpy()
+
+
+def _check(gpu, ref, tol):
+    L, dp, da, dl = gpu
+    L0, g, _, _ = ref
+    assert abs(L - L0) <= max(tol, 1e-6) * abs(L0)
+    errs = {"phase": rel_l2(dp, g["phase"]), "amp": rel_l2(da, g["amp"]),
+            "lens": rel_l2(dl, g["lens"])}
+    assert max(errs.values()) < tol, errs
+    return errs
+
+
+def test_mixed_full_mode_gradients(rw):
+    system, cfg, maps = small_hologram(sampling="full")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed"), _oracle_grad(system, cfg, maps), 1e-3)
+
+
+def test_mixed_mc_gradients_with_oracle_indices(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=48)
+    ref = _oracle_grad(system, cfg, maps)
+    idx = ref[3]
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed", replay=rep), ref, 1e-3)
+
+
+def test_mixed_uni_gradients_with_oracle_indices(rw):
+    system, cfg, maps = small_hologram(sampling="uni", N=48, n_lambda=1)
+    ref = _oracle_grad(system, cfg, maps)
+    idx = ref[3]
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed", replay=rep), ref, 1e-3)
+
+
+def test_fp64_mc_gradients_own_draws(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=32, n_lambda=1, n_field_side=3)
+    _check(_gpu_grad(rw, system, cfg, maps, "fp64"), _oracle_grad(system, cfg, maps), 1e-5)
+
+
+def test_per_pair_launch_gradients_match_batched(rw):
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=6)
+    a = _gpu_grad(rw, system, cfg, maps, "mixed")
+    b = _gpu_grad(rw, system, cfg, maps, "mixed", batched=False)
+    for x, y in zip(a[1:], b[1:]):
+        assert rel_l2(x, y) < 1e-5
+
+
+def test_explicit_psf_cotangent(rw):
+    """dL_dpsf given by the caller (here: L = sum(W * I) for a fixed W)."""
+    system, cfg, maps = small_hologram(sampling="full", rays=6, n_lambda=1, n_field_side=1)
+    Q = cfg["psf_q"]
+    Wt = np.random.default_rng(3).uniform(size=(1, 1, Q, Q))
+    vals = oracle_param_values(system)
+    ph = torch.tensor(maps["phase"].astype(np.float64), requires_grad=True)
+    am = torch.tensor(maps["amp"].astype(np.float64), requires_grad=True)
+    v = torch.tensor(vals, requires_grad=True)
+    r = O.pair_forward(system, cfg, O.transmission(ph, am), 0, 0, v)
+    (r["psf"] * torch.tensor(Wt[0, 0])).sum().backward()
+    plan = rw.Plan(system, cfg, precision="mixed")
+    gv, gph, gam = gpu_inputs(system, maps)
+    plan.forward(gv, gph, gam)
+    dp, da, dl = plan.backward(torch.tensor(Wt, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    assert rel_l2(dp.cpu().numpy(), ph.grad.numpy()) < 1e-3
+    assert rel_l2(da.cpu().numpy(), am.grad.numpy()) < 1e-3
+    assert rel_l2(dl.cpu().numpy(), v.grad.numpy()) < 1e-3
+
+
+def test_backward_state_errors(rw):
+    system, cfg, maps = small_singlet(rays=4)
+    plan = rw.Plan(system, cfg, precision="fp64")
+    with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
+        plan.backward()
+    vals, ph, am = gpu_inputs(system, maps)
+    plan.forward(vals, ph, am)
+    with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
+        plan.backward()          # no target in the forward and no dL_dpsf
