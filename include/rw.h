@@ -173,6 +173,20 @@ rw_status rw_backward(rw_plan* plan, const float* dL_dpsf, float* d_phase, float
 /* Counters of the last forward (synchronises the stream of that forward). */
 rw_status rw_get_stats(rw_plan* plan, rw_stats* out_host);
 
+/* Stage timing.  While enabled, every launch of a stage is bracketed by HIP
+ * events recorded on the stream of the call, and rw_get_profile sums their
+ * elapsed times (it synchronises those events).  Stages: */
+enum { RW_STAGE_TRACE = 0, RW_STAGE_DOE_FWD = 1, RW_STAGE_BIN = 2, RW_STAGE_SPREAD = 3,
+       RW_STAGE_GRID_FWD = 4, RW_STAGE_GRID_BWD = 5, RW_STAGE_DOE_BWD = 6,
+       RW_STAGE_TRACE_BWD = 7, RW_N_STAGES = 8 };
+typedef struct {
+  double ms[RW_N_STAGES];          /* summed kernel time per stage            */
+  uint64_t launches[RW_N_STAGES];  /* number of timed launches per stage      */
+} rw_profile;
+/* enable = 1 starts (and clears) the accumulation, 0 stops it. */
+rw_status rw_set_profiling(rw_plan* plan, int enable);
+rw_status rw_get_profile(rw_plan* plan, rw_profile* out_host);
+
 /* Diagnostic export of the incident ray state at the DOE of the last forward:
  * out [n_rays_total][8] double = (px, py, pz, dx, dy, dz, opl, alive). */
 rw_status rw_export_doe_hits(const rw_plan* plan, const void* workspace, double* out,

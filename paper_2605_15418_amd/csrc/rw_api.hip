@@ -72,6 +72,10 @@ struct rw_plan {
   bool planar_doe, has_post;
   bool lds_patch;
   int fwd_blocks;
+  int emit;                 // record slots per ray
+  int group_pairs;          // pairs per launch group (memory-bounded)
+  BinGeom bg;
+  int rec_chunk;
   double beta;
   // device constant tables (owned by the plan)
   DevCfg* d_cfg = nullptr;
@@ -84,7 +88,8 @@ struct rw_plan {
   double base_sensor_z;
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
-      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, total;
+      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
+      off_spos, off_sval, off_cnt, off_offs, off_cur, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -95,7 +100,34 @@ struct rw_plan {
   const float* fwd_amp = nullptr;
   void* fwd_ws = nullptr;
   hipStream_t fwd_stream = nullptr;
+  // stage timing
+  bool prof = false;
+  struct Ev { int stage; hipEvent_t a, b; };
+  std::vector<Ev> ev_used;
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t ev_get() {
+    if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
 };
+
+namespace {
+// Brackets the launches of one stage with events when profiling is on.
+struct StageTimer {
+  rw_plan* pl;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(rw_plan* p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
+    if (pl->prof) { a = pl->ev_get(); b = pl->ev_get(); (void)hipEventRecord(a, st); }
+  }
+  ~StageTimer() {
+    if (pl->prof) { (void)hipEventRecord(b, st); pl->ev_used.push_back({stage, a, b}); }
+  }
+};
+}  // namespace
 
 // ------------------------------------------------------------ dispatch -----
 namespace {
@@ -169,6 +201,9 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.tmap = b + pl->off_tmap;
   a.tw = pl->d_tw_m;
   a.grid = b + pl->off_grid;
+  a.rec_pos = b + pl->off_rpos;
+  a.rec_val = b + pl->off_rval;
+  a.emit = pl->emit;
   a.scratch = pl->lds_patch ? nullptr : b + pl->off_scratch;
   a.replay = replay;
   a.idx_out = idx_out;
@@ -257,6 +292,49 @@ rw_status grid_bwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
                    const float* dpsf) {
   if (pl->cfg.precision == RW_PREC_FP64) return grid_bwd_t<double>(pl, ws, st, pair0, npairs, dpsf);
   return grid_bwd_t<float>(pl, ws, st, pair0, npairs, dpsf);
+}
+
+template <class T>
+void zero(void* p, size_t n, hipStream_t st);
+
+template <class Tg>
+rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  char* b = (char*)ws;
+  const BinGeom g = pl->bg;
+  const size_t per_pair = (size_t)pl->R2 * pl->emit;
+  const int chunk = pl->rec_chunk;
+  const dim3 grid((unsigned)((per_pair + chunk - 1) / chunk), (unsigned)npairs);
+  unsigned int* cnt = (unsigned int*)(b + pl->off_cnt) + (size_t)pair0 * g.keys;
+  unsigned long long* offs = (unsigned long long*)(b + pl->off_offs) + (size_t)pair0 * g.keys;
+  unsigned long long* cur = (unsigned long long*)(b + pl->off_cur) + (size_t)pair0 * g.keys;
+  StageTimer* tb_ = new StageTimer(pl, RW_STAGE_BIN, st);
+  zero<unsigned int>(cnt, (size_t)npairs * g.keys, st);
+  hipLaunchKernelGGL(k_rec_hist<Tg>, grid, dim3(256), g.keys * sizeof(unsigned int), st,
+                     (const void*)(b + pl->off_rpos), (const void*)(b + pl->off_rval), per_pair,
+                     chunk, g, pair0, (unsigned int*)(b + pl->off_cnt));
+  hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(1024), 0, st, (const unsigned int*)cnt,
+                     (size_t)npairs * g.keys, offs, cur);
+  const size_t lds_sc = (size_t)((g.keys + 1) & ~1) * 4 + (size_t)g.keys * 8;
+  hipLaunchKernelGGL(k_rec_scatter<Tg>, grid, dim3(256), lds_sc, st,
+                     (const void*)(b + pl->off_rpos), (const void*)(b + pl->off_rval), per_pair,
+                     chunk, g, pair0, (unsigned long long*)(b + pl->off_cur),
+                     (void*)(b + pl->off_spos), (void*)(b + pl->off_sval));
+  delete tb_;
+  const int tile = 4 * g.bin;
+  const int ntiles = (g.nf / tile) * (g.nf / tile);
+  StageTimer ts_(pl, RW_STAGE_SPREAD, st);
+  hipLaunchKernelGGL(k_spread_tiles<Tg>, dim3(ntiles, npairs), dim3(256),
+                     (size_t)tile * tile * sizeof(C2<Tg>), st, (const void*)(b + pl->off_spos),
+                     (const void*)(b + pl->off_sval),
+                     (const unsigned long long*)(b + pl->off_offs), g, pl->w, pl->beta, pair0,
+                     (C2<Tg>*)(b + pl->off_grid));
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status bin_and_spread(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  if (pl->cfg.precision == RW_PREC_FP64) return bin_and_spread_t<double>(pl, ws, st, pair0, npairs);
+  return bin_and_spread_t<float>(pl, ws, st, pair0, npairs);
 }
 
 template <class T>
@@ -368,6 +446,27 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->sz_cf = dbl_f ? 16 : 8;
   pl->sz_cg = dbl_g ? 16 : 8;
   pl->lds_patch = (size_t)M * (M + 1) * pl->sz_cf + M * pl->sz_cf + 4096 <= 160 * 1024;
+  pl->emit = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
+  {
+    const int nb = std::min(64, pl->nf / 8);
+    int shift = 0;
+    while ((1 << shift) < pl->nf / nb) ++shift;
+    pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb};
+    const size_t tile = 4 * (size_t)pl->bg.bin;
+    if (tile * tile * pl->sz_cg > 128 * 1024 || pl->w > 2 * pl->bg.bin) {
+      delete pl;
+      return fail(RW_ERR_UNSUPPORTED, "PSF size too large for this precision");
+    }
+  }
+  pl->rec_chunk = 16384;
+  {
+    // launch groups of whole pairs whose secondary-ray records fit in 96 GiB
+    const size_t rec_bytes = (size_t)pl->R2 * pl->emit * 2 * (pl->sz_cg + (dbl_g ? 16 : 8));
+    const size_t budget = (size_t)96 << 30;
+    size_t gp = std::max<size_t>(1, budget / std::max<size_t>(rec_bytes, 1));
+    pl->group_pairs = (int)std::min<size_t>(gp, (size_t)pl->n_pairs);
+    if (!cfg->batched) pl->group_pairs = 1;
+  }
   pl->fwd_blocks = (int)std::min<size_t>(pl->n_total, pl->lds_patch ? 8192 : 2048);
 
   // host copies of the constant tables
@@ -441,6 +540,18 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     psi[c] = s;
   }
 
+  {
+    // the spreading tile of the largest grids needs more than the default 64 KiB of LDS
+    const int lim = 128 * 1024;
+    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<float>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipError_t eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<double>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (ea != hipSuccess || eb != hipSuccess) {
+      delete pl;
+      return fail(RW_ERR_HIP, "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed");
+    }
+  }
   auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
     hipError_t e = hipMalloc(dst, bytes);
     if (e != hipSuccess) return e;
@@ -480,6 +591,18 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_raygrad = take(8 * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
   pl->off_G = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
+  {
+    const size_t nrec = (size_t)pl->group_pairs * pl->R2 * pl->emit;
+    const size_t psz = dbl_g ? 16 : 8;
+    pl->off_rpos = take(nrec * psz);
+    pl->off_rval = take(nrec * pl->sz_cg);
+    pl->off_spos = take(nrec * psz);
+    pl->off_sval = take(nrec * pl->sz_cg);
+    const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
+    pl->off_cnt = take(nk * sizeof(unsigned int));
+    pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
+    pl->off_cur = take(nk * sizeof(unsigned long long));
+  }
   pl->total = o;
   *out = pl;
   return RW_OK;
@@ -500,6 +623,8 @@ rw_status rw_plan_destroy(rw_plan* pl) {
   (void)hipFree(pl->d_tw_m);
   (void)hipFree(pl->d_tw_nf);
   (void)hipFree(pl->d_psi);
+  for (auto& e : pl->ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+  for (auto& e : pl->ev_pool) (void)hipEventDestroy(e);
   delete pl;
   return RW_OK;
 }
@@ -532,17 +657,14 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
     hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
                        doe_amp, (C2<float>*)(b + pl->off_tmap), nmap);
   HIPCHK(hipGetLastError());
-  const size_t ngrid = (size_t)pl->n_pairs * pl->nf * pl->nf * 2;
-  if (dbl_g) zero<double>(b + pl->off_grid, ngrid, st);
-  else zero<float>(b + pl->off_grid, ngrid, st);
   zero<unsigned long long>(b + pl->off_stats, 4, st);
   DoeArgs a = doe_args(pl, ws, replay_idx, idx_out);
-  const int groups = pl->cfg.batched ? 1 : pl->n_pairs;
-  const int ppg = pl->cfg.batched ? pl->n_pairs : 1;
-  for (int gi = 0; gi < groups; ++gi) {
-    const int pair0 = gi * ppg;
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
     const size_t nr = (size_t)ppg * pl->R2;
     const int tb = (int)((nr + 255) / 256);
+    {
+    StageTimer tm_(pl, RW_STAGE_TRACE, st);
     if (pl->cfg.precision == RW_PREC_FP32)
       hipLaunchKernelGGL(k_trace<float>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
                          (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
@@ -551,13 +673,23 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
       hipLaunchKernelGGL(k_trace<double>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
                          (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
                          (double*)(b + pl->off_ck), pl->n_total, pair0, ppg);
+    }
     HIPCHK(hipGetLastError());
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;
     const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
-    rw_status s = doe_fwd(pl, a, blocks, st);
+    rw_status s;
+    {
+      StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
+      s = doe_fwd(pl, a, blocks, st);
+    }
     if (s != RW_OK) return s;
-    s = grid_fwd(pl, ws, st, pair0, ppg, psf_out);
+    s = bin_and_spread(pl, ws, st, pair0, ppg);
+    if (s != RW_OK) return s;
+    {
+      StageTimer tm_(pl, RW_STAGE_GRID_FWD, st);
+      s = grid_fwd(pl, ws, st, pair0, ppg, psf_out);
+    }
     if (s != RW_OK) return s;
   }
   if (target) {
@@ -576,6 +708,27 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   pl->fwd_amp = doe_amp;
   pl->fwd_ws = ws;
   pl->fwd_stream = st;
+  return RW_OK;
+}
+
+rw_status rw_set_profiling(rw_plan* pl, int enable) {
+  if (!pl) return fail(RW_ERR_INVALID_ARG, "null plan");
+  for (auto& e : pl->ev_used) { pl->ev_pool.push_back(e.a); pl->ev_pool.push_back(e.b); }
+  pl->ev_used.clear();
+  pl->prof = enable != 0;
+  return RW_OK;
+}
+
+rw_status rw_get_profile(rw_plan* pl, rw_profile* out) {
+  if (!pl || !out) return fail(RW_ERR_INVALID_ARG, "null argument");
+  memset(out, 0, sizeof(*out));
+  for (auto& e : pl->ev_used) {
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    out->ms[e.stage] += ms;
+    out->launches[e.stage] += 1;
+  }
   return RW_OK;
 }
 
@@ -625,19 +778,25 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   a.adj = b + pl->off_grid;
   a.want_lens = want_lens ? 1 : 0;
   a.stats = nullptr;
-  const int groups = pl->cfg.batched ? 1 : pl->n_pairs;
-  const int ppg = pl->cfg.batched ? pl->n_pairs : 1;
-  for (int gi = 0; gi < groups; ++gi) {
-    const int pair0 = gi * ppg;
-    rw_status s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    rw_status s;
+    {
+      StageTimer tm_(pl, RW_STAGE_GRID_BWD, st);
+      s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
+    }
     if (s != RW_OK) return s;
     const size_t nr = (size_t)ppg * pl->R2;
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;
     const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
-    s = doe_bwd(pl, a, blocks, st);
+    {
+      StageTimer tm_(pl, RW_STAGE_DOE_BWD, st);
+      s = doe_bwd(pl, a, blocks, st);
+    }
     if (s != RW_OK) return s;
     if (want_lens) {
+      StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
       hipLaunchKernelGGL(k_trace_bwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
                          pl->d_cfg, pl->d_pairs, (const DevLive*)(b + pl->off_live),
                          (const double*)(b + pl->off_st), (const double*)(b + pl->off_ck),

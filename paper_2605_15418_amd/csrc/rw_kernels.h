@@ -202,6 +202,9 @@ struct DoeArgs {
   const void* tmap;          // C2<Tf> [H][W]
   const void* tw;            // C2<Tf> [M] exp(-2 pi i m / M)
   void* grid;                // C2<Tg> [n_pairs][nf][nf]
+  void* rec_pos;             // RecPos<Tg> [n_slots][2]  (n_slots = rays x emit)
+  void* rec_val;             // C2<Tg> [n_slots]
+  int emit;                  // record slots per ray: N, or M*M in FULL sampling
   void* scratch;             // C2<Tf> per block [M][M+1] when the patch does not fit in LDS
   const int32_t* replay;
   int32_t* idx_out;
@@ -405,35 +408,48 @@ __device__ __forceinline__ Tp grid_coord(Tp w, int nf) {
   return (turns - floor(turns)) * (Tp)nf;
 }
 
+// Secondary-ray record for the binned spreading: wavelet value and its grid
+// coordinate as fixed-point turns (2^32 per period; 2^64 in the FP64 form).
+template <class Tg> struct RecPos;
+template <> struct RecPos<float> { using T = uint32_t; };
+template <> struct RecPos<double> { using T = unsigned long long; };
+
+template <class Tp, class U>
+__device__ __forceinline__ U to_turns(Tp w) {
+  const Tp turns = w * (Tp)(1.0 / (2.0 * RW_PI));
+  const Tp frac = turns - floor(turns);                 // [0, 1]
+  if constexpr (sizeof(U) == 4) {
+    const uint64_t v = (uint64_t)((double)frac * 4294967296.0);
+    return (U)(v & 0xffffffffull);
+  } else {
+    // 2^64 fixed point from a double in [0, 1]: 53 significant bits
+    const double hi = (double)frac * 4294967296.0;
+    const uint64_t h = (uint64_t)hi;
+    const uint64_t l = (uint64_t)((hi - (double)h) * 4294967296.0);
+    return (U)((h << 32) + l);
+  }
+}
+
+template <class U> __device__ __forceinline__ double turns_to_cells(U v, int nf) {
+  if constexpr (sizeof(U) == 4) return (double)v * ((double)nf / 4294967296.0);
+  else return ((double)(v >> 11)) * ((double)nf / 9007199254740992.0);
+}
+
 template <class Prec>
-__device__ __forceinline__ void spread(const DevCfg& cfg, C2<typename Prec::Tg>* grid, int pair,
-                                       C2<typename Prec::Tg> cval, typename Prec::Tp wx,
-                                       typename Prec::Tp wy) {
+__device__ __forceinline__ void put_record(const DoeArgs& a, size_t slot,
+                                           C2<typename Prec::Tg> v, typename Prec::Tp wx,
+                                           typename Prec::Tp wy) {
   using Tg = typename Prec::Tg;
-  using Tp = typename Prec::Tp;
-  const int nf = cfg.nf, w = cfg.w;
-  const Tp gx = grid_coord(wx, nf), gy = grid_coord(wy, nf);
-  const int lx0 = (int)ceil(gx - (Tp)(0.5 * w)), ly0 = (int)ceil(gy - (Tp)(0.5 * w));
-  const Tg tw = Tg(2.0 / w), beta = (Tg)cfg.beta;
-  Tg kx[16], ky[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    if (i < w) {
-      kx[i] = es_kernel<Tg>((Tg)((Tp)(lx0 + i) - gx), tw, beta);
-      ky[i] = es_kernel<Tg>((Tg)((Tp)(ly0 + i) - gy), tw, beta);
-    }
-  }
-  C2<Tg>* gp = grid + (size_t)pair * nf * nf;
-  for (int j = 0; j < w; ++j) {
-    const int y = (ly0 + j) & (nf - 1);
-    const C2<Tg> cy = cval * ky[j];
-    C2<Tg>* row = gp + (size_t)y * nf;
-    for (int i = 0; i < w; ++i) {
-      const int x = (lx0 + i) & (nf - 1);
-      atomicAdd(&row[x].re, cy.re * kx[i]);
-      atomicAdd(&row[x].im, cy.im * kx[i]);
-    }
-  }
+  using U = typename RecPos<Tg>::T;
+  U* pos = (U*)a.rec_pos;
+  pos[2 * slot] = to_turns<typename Prec::Tp, U>(wx);
+  pos[2 * slot + 1] = to_turns<typename Prec::Tp, U>(wy);
+  ((C2<Tg>*)a.rec_val)[slot] = v;
+}
+
+template <class Tg>
+__device__ __forceinline__ void put_zero(const DoeArgs& a, size_t slot) {
+  ((C2<Tg>*)a.rec_val)[slot] = {Tg(0), Tg(0)};
 }
 
 // Angle reference of the patch centre: U~_j = X_k exp(i pi (jx + jy)(P - 1) / M).
@@ -462,16 +478,18 @@ __global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
   const DevCfg& cfg = *a.cfg;
   C2<Tf>* buf = kLDS ? s_buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
   const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
-  C2<Tg>* grid = (C2<Tg>*)a.grid;
   for (int i = threadIdx.x; i < M; i += kThreads) s_tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
   const int N = cfg.N, P = cfg.P, t = threadIdx.x;
+  const int emit = a.emit;
   const double inv_m2 = 1.0 / ((double)M * M);
   unsigned long long n_sec = 0, n_alive = 0;
   for (size_t wi = blockIdx.x; wi < a.nray; wi += gridDim.x) {
     const size_t gid = a.ray0 + wi;
+    const size_t slot0 = wi * (size_t)emit;        // records of this launch start at 0
     const bool alive = a.st[7 * a.n_total + gid] != 0.0;
     if (!alive) {
+      for (int i = t; i < emit; i += kThreads) put_zero<Tg>(a, slot0 + i);
       if (a.idx_out && cfg.sampling != 2)
         for (int i = t; i < N; i += kThreads) a.idx_out[gid * N + i] = -1;
       continue;
@@ -480,6 +498,28 @@ __global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
     RayCtx c;
     make_ctx(a, gid, c);
     patch_spectrum<Tf, M>(cfg, c, tm, buf, s_tw);
+    if (cfg.sampling == 2) {
+      // FULL: every propagating bin once, weight U~ / M^2; slot = shifted bin index.
+      for (int q = 0; q < C; ++q) {
+        const int L = t * C + q;
+        const int jy = L / M - M / 2, jx = L % M - M / 2;
+        const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+        Tp phi0, wx, wy; double dza; Secondary sec;
+        if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out) ||
+            !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
+          put_zero<Tg>(a, slot0 + L);
+          continue;
+        }
+        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+        const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+        const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+        put_record<Prec>(a, slot0 + L, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+        ++n_sec;
+      }
+      __syncthreads();
+      continue;
+    }
     // Sampling density and its CDF (chunks of C consecutive shifted bins per thread).
     double acc = 0.0;
     int lastpos = -1;
@@ -493,28 +533,10 @@ __global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
     const double S = block_exclusive_scan(acc, s_red, excl);
     s_pref[t] = excl;
     const int lastpos_all = block_max_int(lastpos, s_redi);   // also a barrier for s_pref
-    const int Cpb = cfg.sampling == 2 ? C : 0;
-    if (cfg.sampling == 2) {
-      // FULL: every propagating bin once, weight U~ / M^2.
-      for (int q = 0; q < Cpb; ++q) {
-        const int L = t * C + q;
-        const int jy = L / M - M / 2, jx = L % M - M / 2;
-        const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
-        if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out)) continue;
-        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
-        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-        Tp phi0, wx, wy; double dza; Secondary sec;
-        if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) continue;
-        const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
-        const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
-        const C2<Tp> cv = (w * e) * (Tp)dza;
-        spread<Prec>(cfg, grid, c.pair, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
-        ++n_sec;
-      }
-    } else if (S > 0.0) {
-      const double scale = cfg.sampling == 0 ? S * inv_m2 / N : S * inv_m2 / N;  // S or |Pi|
-      for (int i = t; i < N; i += kThreads) {
-        int J = -1;
+    const double scale = S * inv_m2 / N;                     // S or |Pi| over M^2 N
+    for (int i = t; i < N; i += kThreads) {
+      int J = -1;
+      if (S > 0.0) {
         if (a.replay) {
           J = a.replay[gid * N + i];
         } else {
@@ -536,29 +558,33 @@ __global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
           }
           if (J < 0) J = lp >= 0 ? lp : lastpos_all;
         }
-        if (a.idx_out) a.idx_out[gid * N + i] = J;
-        if (J < 0) continue;
-        const int jy = J / M - M / 2, jx = J % M - M / 2;
+      }
+      if (a.idx_out) a.idx_out[gid * N + i] = J;
+      bool ok = J >= 0;
+      C2<Tp> w = {Tp(0), Tp(0)};
+      int jx = 0, jy = 0;
+      if (ok) {
+        jy = J / M - M / 2; jx = J % M - M / 2;
         const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
         const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-        C2<Tp> w;
         if (cfg.sampling == 0) {
           const Tf mag = cabs_rn(X);
-          if (!(mag > Tf(0))) continue;
-          const Tp f = (Tp)(scale / (double)mag);
+          ok = mag > Tf(0);
+          const Tp f = ok ? (Tp)(scale / (double)mag) : Tp(0);
           w = {(Tp)U.re * f, (Tp)U.im * f};
         } else {
           w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
         }
-        Tp phi0, wx, wy; double dza; Secondary sec;
-        if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) continue;
-        const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
-        const C2<Tp> cv = (w * e) * (Tp)dza;
-        spread<Prec>(cfg, grid, c.pair, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
-        ++n_sec;
       }
-    } else if (a.idx_out) {
-      for (int i = t; i < N; i += kThreads) a.idx_out[gid * N + i] = -1;
+      Tp phi0, wx, wy; double dza; Secondary sec;
+      if (ok) ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
+      if (!ok) {
+        put_zero<Tg>(a, slot0 + i);
+        continue;
+      }
+      const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+      put_record<Prec>(a, slot0 + i, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+      ++n_sec;
     }
     __syncthreads();   // buf is reused by the next ray
   }
@@ -566,6 +592,182 @@ __global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
     if (n_alive) atomicAdd(&a.stats[0], n_alive);
     if (n_sec) atomicAdd(&a.stats[1], n_sec);
   }
+}
+
+// ------------------------------------------------------- binned spreading ---
+// Records are binned by (pair, BIN x BIN cells of the oversampled grid); one
+// workgroup per TILE x TILE cells (TILE = 4 BIN) gathers the records of its own
+// bins and of a one-bin margin (w / 2 <= BIN), accumulates the ES-kernel taps
+// that fall inside its tile in LDS, and stores the tile: no global atomics.
+struct BinGeom {
+  int nf, bin, shift;      // BIN = 1 << shift cells
+  int nb;                  // bins per axis
+  int keys;                // bins per pair
+};
+
+__device__ __forceinline__ int rec_key(double gx, double gy, const BinGeom& g) {
+  const int cx = min((int)gx, g.nf - 1), cy = min((int)gy, g.nf - 1);
+  return (cy >> g.shift) * g.nb + (cx >> g.shift);
+}
+
+template <class Tg>
+__global__ __launch_bounds__(256) void k_rec_hist(const void* rec_pos, const void* rec_val,
+                                                  size_t per_pair, int chunk, BinGeom g,
+                                                  int pair0, unsigned int* counts) {
+  using U = typename RecPos<Tg>::T;
+  extern __shared__ unsigned int s_h[];
+  const int pair_l = blockIdx.y;
+  const size_t base = (size_t)pair_l * per_pair + (size_t)blockIdx.x * chunk;
+  const size_t end = min(base + (size_t)chunk, (size_t)(pair_l + 1) * per_pair);
+  for (int i = threadIdx.x; i < g.keys; i += blockDim.x) s_h[i] = 0;
+  __syncthreads();
+  const U* pos = (const U*)rec_pos;
+  const C2<Tg>* val = (const C2<Tg>*)rec_val;
+  for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
+    const C2<Tg> v = val[r];
+    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    const int k = rec_key(turns_to_cells(pos[2 * r], g.nf), turns_to_cells(pos[2 * r + 1], g.nf), g);
+    atomicAdd(&s_h[k], 1u);
+  }
+  __syncthreads();
+  unsigned int* out = counts + (size_t)(pair0 + pair_l) * g.keys;
+  for (int i = threadIdx.x; i < g.keys; i += blockDim.x)
+    if (s_h[i]) atomicAdd(&out[i], s_h[i]);
+}
+
+// Exclusive scan of the bin counts (one workgroup); cursors start at the offsets.
+__global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* counts, size_t n,
+                                                   unsigned long long* offsets,
+                                                   unsigned long long* cursor) {
+  __shared__ unsigned long long s_w[16];
+  __shared__ unsigned long long s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (size_t b0 = 0; b0 < n; b0 += 1024) {
+    const size_t i = b0 + threadIdx.x;
+    const unsigned long long v = i < n ? counts[i] : 0ull;
+    unsigned long long inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long x = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += x;
+    }
+    if (lane == 63) s_w[wv] = inc;
+    __syncthreads();
+    unsigned long long pre = s_carry;
+    for (int k = 0; k < wv; ++k) pre += s_w[k];
+    if (i < n) { offsets[i] = pre + inc - v; cursor[i] = pre + inc - v; }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      unsigned long long tot = s_carry;
+      for (int k = 0; k < 16; ++k) tot += s_w[k];
+      s_carry = tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) offsets[n] = s_carry;
+}
+
+template <class Tg>
+__global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const void* rec_val,
+                                                     size_t per_pair, int chunk, BinGeom g,
+                                                     int pair0, unsigned long long* cursor,
+                                                     void* srt_pos, void* srt_val) {
+  using U = typename RecPos<Tg>::T;
+  extern __shared__ unsigned int s_h[];                 // [keys] counts, then [keys] bases
+  unsigned long long* s_base = (unsigned long long*)(s_h + ((g.keys + 1) & ~1));
+  const int pair_l = blockIdx.y;
+  const size_t base = (size_t)pair_l * per_pair + (size_t)blockIdx.x * chunk;
+  const size_t end = min(base + (size_t)chunk, (size_t)(pair_l + 1) * per_pair);
+  for (int i = threadIdx.x; i < g.keys; i += blockDim.x) s_h[i] = 0;
+  __syncthreads();
+  const U* pos = (const U*)rec_pos;
+  const C2<Tg>* val = (const C2<Tg>*)rec_val;
+  for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
+    const C2<Tg> v = val[r];
+    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    const int k = rec_key(turns_to_cells(pos[2 * r], g.nf), turns_to_cells(pos[2 * r + 1], g.nf), g);
+    atomicAdd(&s_h[k], 1u);
+  }
+  __syncthreads();
+  unsigned long long* cur = cursor + (size_t)(pair0 + pair_l) * g.keys;
+  for (int i = threadIdx.x; i < g.keys; i += blockDim.x) {
+    const unsigned int n = s_h[i];
+    s_base[i] = n ? atomicAdd(&cur[i], (unsigned long long)n) : 0ull;
+    s_h[i] = 0;
+  }
+  __syncthreads();
+  U* op = (U*)srt_pos;
+  C2<Tg>* ov = (C2<Tg>*)srt_val;
+  for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
+    const C2<Tg> v = val[r];
+    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    const U px = pos[2 * r], py = pos[2 * r + 1];
+    const int k = rec_key(turns_to_cells(px, g.nf), turns_to_cells(py, g.nf), g);
+    const unsigned long long o = s_base[k] + atomicAdd(&s_h[k], 1u);
+    op[2 * o] = px;
+    op[2 * o + 1] = py;
+    ov[o] = v;
+  }
+}
+
+template <class Tg>
+__global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
+                                                      const unsigned long long* offsets,
+                                                      BinGeom g, int w, double beta, int pair0,
+                                                      C2<Tg>* grid) {
+  using U = typename RecPos<Tg>::T;
+  extern __shared__ unsigned char s_raw[];
+  C2<Tg>* acc = (C2<Tg>*)s_raw;
+  const int tile = 4 * g.bin;                 // cells per tile side
+  const int ntx = g.nf / tile;
+  const int pair = pair0 + blockIdx.y;
+  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  const int x0 = tx * tile, y0 = ty * tile;
+  for (int i = threadIdx.x; i < tile * tile; i += blockDim.x) acc[i] = {Tg(0), Tg(0)};
+  __syncthreads();
+  const U* pos = (const U*)srt_pos;
+  const C2<Tg>* val = (const C2<Tg>*)srt_val;
+  const unsigned long long* off = offsets + (size_t)pair * g.keys;
+  const double two_w = 2.0 / w;
+  // own 4 x 4 bins plus a one-bin margin (periodic; at least 8 bins per axis,
+  // so the 6 x 6 neighbourhood never repeats a bin)
+  for (int by = -1; by <= 4; ++by) {
+    const int bny = (ty * 4 + by + g.nb) % g.nb;
+    for (int bx = -1; bx <= 4; ++bx) {
+      const int bnx = (tx * 4 + bx + g.nb) % g.nb;
+      const int k = bny * g.nb + bnx;
+      const unsigned long long r0 = off[k], r1 = off[k + 1];
+      for (unsigned long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+        const C2<Tg> v = val[r];
+        const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
+        Tg kx[16];
+        int ix[16];
+        for (int i = 0; i < w; ++i) {
+          const int cx = ((lx0 + i) & (g.nf - 1)) - x0;
+          ix[i] = (cx >= 0 && cx < tile) ? cx : -1;
+          kx[i] = ix[i] >= 0 ? es_kernel<Tg>((Tg)((double)(lx0 + i) - gx), (Tg)two_w, (Tg)beta)
+                             : Tg(0);
+        }
+        for (int j = 0; j < w; ++j) {
+          const int cy = ((ly0 + j) & (g.nf - 1)) - y0;
+          if (cy < 0 || cy >= tile) continue;
+          const Tg ky = es_kernel<Tg>((Tg)((double)(ly0 + j) - gy), (Tg)two_w, (Tg)beta);
+          const C2<Tg> vy = v * ky;
+          for (int i = 0; i < w; ++i) {
+            if (ix[i] < 0) continue;
+            atomicAdd(&acc[cy * tile + ix[i]].re, vy.re * kx[i]);
+            atomicAdd(&acc[cy * tile + ix[i]].im, vy.im * kx[i]);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  C2<Tg>* gp = grid + (size_t)pair * g.nf * g.nf;
+  for (int i = threadIdx.x; i < tile * tile; i += blockDim.x)
+    gp[(size_t)(y0 + i / tile) * g.nf + x0 + i % tile] = acc[i];
 }
 
 // ------------------------------------------------------------- grid FFT ---

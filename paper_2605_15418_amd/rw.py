@@ -23,7 +23,8 @@ STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STA
 
 EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
-            "rw_last_error")
+            "rw_last_error", "rw_set_profiling", "rw_get_profile")
+STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd")
 
 
 class rw_surface(ctypes.Structure):
@@ -56,6 +57,10 @@ class rw_config(ctypes.Structure):
                 ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64)]
 
 
+class rw_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
+
+
 class rw_stats(ctypes.Structure):
     _fields_ = [("rays_total", ctypes.c_uint64), ("rays_alive", ctypes.c_uint64),
                 ("secondaries", ctypes.c_uint64)]
@@ -82,11 +87,14 @@ def load_library(path=LIB_PATH):
     lib.rw_get_stats.argtypes = [vp, ctypes.POINTER(rw_stats)]
     lib.rw_export_doe_hits.argtypes = [vp, vp, vp, vp]
     lib.rw_plan_destroy.argtypes = [vp]
+    lib.rw_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.rw_get_profile.argtypes = [vp, ctypes.POINTER(rw_profile)]
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
     for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
-                 "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy"):
+                 "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
+                 "rw_get_profile"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -243,6 +251,15 @@ class Plan:
         _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
         return {"rays_total": s.rays_total, "rays_alive": s.rays_alive,
                 "secondaries": s.secondaries}
+
+    def set_profiling(self, enable=True):
+        _check(self.lib, self.lib.rw_set_profiling(self.handle, int(bool(enable))))
+
+    def profile(self):
+        """Summed kernel milliseconds and launch counts per stage (HIP events)."""
+        p = rw_profile()
+        _check(self.lib, self.lib.rw_get_profile(self.handle, ctypes.byref(p)))
+        return {name: (p.ms[i], p.launches[i]) for i, name in enumerate(STAGES)}
 
     def doe_hits(self):
         out = torch.empty((self.n_rays, 8), dtype=torch.float64, device=self.device)
