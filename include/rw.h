@@ -32,8 +32,9 @@
  *  PSF / target     [L][F][Q][Q]   pair p = l * F + f; row = y index, column = x index,
  *                                  pixel (r, c) at psf_center + ((c - Q/2), (r - Q/2)) * psf_pitch
  *  ray order        pair-major, then ray r = iy * rays_side + ix of the launch grid
- *  sample indices   [n_pairs][rays_side^2][n_ssr] int32: bin j = (jy + M/2) * M + (jx + M/2)
- *                   of the shifted M x M spectrum, -1 where the ray emits nothing
+ *  sample indices   [n_pairs][rays_side^2][n_ssr] int32: bin j = (jx + M/2) * M + (jy + M/2)
+ *                   of the shifted M x M spectrum (the inverse-CDF order), -1 where the ray
+ *                   emits nothing
  */
 #ifndef RW_H
 #define RW_H

@@ -353,13 +353,14 @@ def wavevectors(k_in_t, M, pitch):
 #   UNI : p_j = 1 / |Pi|
 #   FULL: every propagating bin once, weight U~_j / M^2 (the deterministic
 #         limit that the Monte Carlo estimate converges to).
-# Draw by inverse CDF in shifted row-major bin order: J = min{j : C_j > u S},
+# Draw by inverse CDF in shifted column-major bin order, linear bin index
+# J = (j_x + M/2) M + (j_y + M/2), J = min{j : C_j > u S},
 # distributionally identical to the arg-max of N Gumbel-perturbed replicas of
 # log p (Gumbel-max theorem).  READING: weight = U~_J / (M^2 N p_J): the
 # Monte Carlo mean of Eq. 1 with the 1/N and 1/M^2 normalisations.
 # ----------------------------------------------------------------------------
 def draw_bins(mag, prop, u, sampling):
-    """mag, prop: [R, M*M] (numpy, shifted row-major bin order); u: [R, N].
+    """mag, prop: [R, M*M] (numpy, shifted column-major bin order); u: [R, N].
     Returns J [R, N] (int64, -1 where the ray has no propagating weight) and S [R]."""
     w = np.where(prop, mag if sampling == "mag" else 1.0, 0.0)
     cdf = np.cumsum(w, axis=1)
@@ -466,8 +467,9 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     K2 = Ku * Ku + Kv * Kv
     prop = (K2 < k_out * k_out) & alive[:, None, None]
     R = p.shape[0]
-    Utf = Ut.reshape(R, M * M)
-    propf = prop.reshape(R, M * M)
+    # flatten j_x-major: linear bin index J = (j_x + M/2) M + (j_y + M/2)
+    Utf = Ut.transpose(1, 2).reshape(R, M * M)
+    propf = prop.transpose(1, 2).reshape(R, M * M)
     if sampling == "full":
         rr, jj = torch.nonzero(propf, as_tuple=True)
         w = Utf[rr, jj] / (M * M)
@@ -497,8 +499,8 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
             nprop = propf.sum(1).to(DT)
             w = torch.where(valid, UJ * (nprop[rr] / (M * M * Nd)), zero)
     # Emission: direction from the tangential wavevector (Formalism; READING Q1).
-    jy = jj // M
-    jx = jj % M
+    jx = jj // M
+    jy = jj % M
     Kus = Ku[rr, jy, jx]
     Kvs = Kv[rr, jy, jx]
     kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs

@@ -113,8 +113,8 @@ def test_mixed_mc_own_draws_agree_and_are_valid(rw):
         total += J.size
         # every disagreement must be a CDF edge flip: both bins adjacent in the
         # oracle's CDF order once zero-weight bins are skipped
-        mag = a["spectrum"].abs().reshape(J.shape[0], -1).numpy()
-        prop = a["prop"].reshape(J.shape[0], -1).numpy()
+        mag = a["spectrum"].abs().transpose(1, 2).reshape(J.shape[0], -1).numpy()
+        prop = a["prop"].transpose(1, 2).reshape(J.shape[0], -1).numpy()
         w = np.where(prop, mag, 0.0)
         cdf = np.cumsum(w, axis=1)
         for r, i in zip(*np.nonzero(gi[pr] != J)):

@@ -312,8 +312,9 @@ def test_mag_weights_have_constant_modulus_and_sampler_chi2():
                         torch.tensor(maps["amp"], dtype=torch.float64))
     r = O.pair_forward(system, cfg, tm, 0, 0, keep=True)
     M = 32
-    mag = r["spectrum"][0].abs().reshape(-1).numpy()
-    prop = r["prop"][0].reshape(-1).numpy()
+    # bins flattened in the sampler's order: j_x major
+    mag = r["spectrum"][0].abs().transpose(0, 1).reshape(-1).numpy()
+    prop = r["prop"][0].transpose(0, 1).reshape(-1).numpy()
     S = mag[prop].sum()
     w = r["w"].numpy()
     assert np.max(np.abs(np.abs(w) - S / (M * M * N))) < 1e-12 * S / (M * M * N)
