@@ -1,25 +1,45 @@
-"""Build librw.so for gfx950 in-tree with hipcc."""
+"""Build librw.so for gfx950 in-tree with hipcc (translation units in parallel)."""
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "rw_api.hip")
+CSRC = os.path.join(HERE, "csrc")
+UNITS = ["rw_api.hip", "rw_doe_mixed.hip", "rw_doe_fp32.hip", "rw_doe_fp64.hip"]
 OUT = os.path.join(HERE, "librw.so")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+BUILD_DIR = os.path.join(HERE, "_build")
 
 
-def build(verbose=False):
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp, SRC]
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed to build librw.so")
-    if verbose:
-        sys.stderr.write(r.stderr)
+    return r.returncode, r.stdout + r.stderr
+
+
+def build(verbose=False, jobs=None):
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs, cmds = [], []
+    for u in UNITS:
+        o = os.path.join(BUILD_DIR, u.replace(".hip", ".o"))
+        objs.append(o)
+        cmds.append([hipcc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, u)])
+    jobs = jobs or min(len(cmds), max(1, (os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(_run, cmds))
+    for (rc, out), cmd in zip(results, cmds):
+        if rc != 0:
+            sys.stderr.write(out)
+            raise RuntimeError("hipcc failed: " + " ".join(cmd[-1:]))
+        if verbose:
+            sys.stderr.write(out)
+    tmp = OUT + ".tmp"
+    rc, out = _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    if rc != 0:
+        sys.stderr.write(out)
+        raise RuntimeError("hipcc failed to link librw.so")
     os.replace(tmp, OUT)
     return OUT
 

@@ -8,8 +8,8 @@
 #include <vector>
 
 #include "../../include/rw.h"
-#include "rw_kernels.h"
-#include "rw_backward.h"
+#include "rw_doe.h"
+#include "rw_launch.h"
 
 using namespace rw;
 
@@ -71,7 +71,9 @@ struct rw_plan {
   size_t n_total;
   bool planar_doe, has_post;
   bool lds_patch;
-  int fwd_blocks;
+  int doe_blocks;           // persistent workgroups of the ray-wave kernels
+  int ray_block;            // side of the spatial ray blocks (work items)
+  int acc_side;             // side of the block-private dL/dt accumulator
   int emit;                 // record slots per ray
   int group_pairs;          // pairs per launch group (memory-bounded)
   BinGeom bg;
@@ -89,7 +91,7 @@ struct rw_plan {
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
-      off_spos, off_sval, off_cnt, off_offs, off_cur, total;
+      off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -131,29 +133,6 @@ struct StageTimer {
 
 // ------------------------------------------------------------ dispatch -----
 namespace {
-
-template <class Prec, int M, bool LDS>
-void launch_doe_fwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_doe_fwd<Prec, M, LDS>), dim3(blocks), dim3(kThreads), 0, st, a);
-}
-
-template <class Prec>
-rw_status doe_fwd_prec(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
-  constexpr bool dbl = sizeof(typename Prec::Tf) == 8;
-  switch (pl->M) {
-    case 16: launch_doe_fwd<Prec, 16, true>(pl, a, blocks, st); break;
-    case 32: launch_doe_fwd<Prec, 32, true>(pl, a, blocks, st); break;
-    case 64: launch_doe_fwd<Prec, 64, true>(pl, a, blocks, st); break;
-    case 128:
-      if (dbl) launch_doe_fwd<Prec, 128, false>(pl, a, blocks, st);
-      else launch_doe_fwd<Prec, 128, !dbl>(pl, a, blocks, st);
-      break;
-    case 256: launch_doe_fwd<Prec, 256, false>(pl, a, blocks, st); break;
-    default: return fail(RW_ERR_SHAPE, "unsupported FFT size M");
-  }
-  HIPCHK(hipGetLastError());
-  return RW_OK;
-}
 
 template <class Tg, int NF>
 void launch_grid_fwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs, float* psf) {
@@ -210,46 +189,37 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.stats = (unsigned long long*)(b + pl->off_stats);
   a.gt = b + pl->off_gt;
   a.raygrad = (double*)(b + pl->off_raygrad);
+  a.acc = b + pl->off_acc;
+  a.acc_side = pl->acc_side;
   return a;
 }
 
-rw_status doe_fwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
+// Ray-wave interface over whole blocks of rays (persistent workgroups).
+rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npairs,
+                     hipStream_t st) {
+  RayBlockIter it;
+  it.rb = pl->ray_block;
+  it.nbx = (pl->R + it.rb - 1) / it.rb;
+  it.per_pair = it.nbx * it.nbx;
+  it.R = pl->R;
+  const long long n_items = (long long)npairs * it.per_pair;
+  const int blocks = (int)std::min<long long>(n_items, pl->doe_blocks);
+  bool ok = true;
+  hipError_t e;
   switch (pl->cfg.precision) {
-    case RW_PREC_FP64: return doe_fwd_prec<PrecFP64>(pl, a, blocks, st);
-    case RW_PREC_MIXED: return doe_fwd_prec<PrecMIXED>(pl, a, blocks, st);
-    default: return doe_fwd_prec<PrecFP32>(pl, a, blocks, st);
-  }
-}
-
-template <class Prec, int M, bool LDS>
-void launch_doe_bwd(const DoeArgs& a, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_doe_bwd<Prec, M, LDS>), dim3(blocks), dim3(kThreads), 0, st, a);
-}
-
-template <class Prec>
-rw_status doe_bwd_prec(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
-  constexpr bool dbl = sizeof(typename Prec::Tf) == 8;
-  switch (pl->M) {
-    case 16: launch_doe_bwd<Prec, 16, true>(a, blocks, st); break;
-    case 32: launch_doe_bwd<Prec, 32, true>(a, blocks, st); break;
-    case 64: launch_doe_bwd<Prec, 64, true>(a, blocks, st); break;
-    case 128:
-      if (dbl) launch_doe_bwd<Prec, 128, false>(a, blocks, st);
-      else launch_doe_bwd<Prec, 128, !dbl>(a, blocks, st);
+    case RW_PREC_FP64:
+      e = launch_doe_fp64(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
       break;
-    case 256: launch_doe_bwd<Prec, 256, false>(a, blocks, st); break;
-    default: return fail(RW_ERR_SHAPE, "unsupported FFT size M");
+    case RW_PREC_MIXED:
+      e = launch_doe_mixed(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
+      break;
+    default:
+      e = launch_doe_fp32(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
   }
-  HIPCHK(hipGetLastError());
+  if (!ok) return fail(RW_ERR_SHAPE, "unsupported FFT size M for this precision");
+  if (e != hipSuccess)
+    return fail(RW_ERR_HIP, std::string("DOE kernel launch: ") + hipGetErrorString(e));
   return RW_OK;
-}
-
-rw_status doe_bwd(rw_plan* pl, const DoeArgs& a, int blocks, hipStream_t st) {
-  switch (pl->cfg.precision) {
-    case RW_PREC_FP64: return doe_bwd_prec<PrecFP64>(pl, a, blocks, st);
-    case RW_PREC_MIXED: return doe_bwd_prec<PrecMIXED>(pl, a, blocks, st);
-    default: return doe_bwd_prec<PrecFP32>(pl, a, blocks, st);
-  }
 }
 
 template <class Tg, int NF>
@@ -323,11 +293,24 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   const int tile = 4 * g.bin;
   const int ntiles = (g.nf / tile) * (g.nf / tile);
   StageTimer ts_(pl, RW_STAGE_SPREAD, st);
-  hipLaunchKernelGGL(k_spread_tiles<Tg>, dim3(ntiles, npairs), dim3(256),
-                     (size_t)tile * tile * sizeof(C2<Tg>), st, (const void*)(b + pl->off_spos),
-                     (const void*)(b + pl->off_sval),
-                     (const unsigned long long*)(b + pl->off_offs), g, pl->w, pl->beta, pair0,
-                     (C2<Tg>*)(b + pl->off_grid));
+  const dim3 sg(ntiles, npairs);
+  const size_t lds = (size_t)tile * (tile + 1) * sizeof(C2<Tg>);
+  const void* sp = (const void*)(b + pl->off_spos);
+  const void* sv = (const void*)(b + pl->off_sval);
+  const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
+  C2<Tg>* gr = (C2<Tg>*)(b + pl->off_grid);
+  switch (pl->w) {
+#define RW_SPREAD_CASE(W)                                                                     \
+    case W:                                                                                   \
+      hipLaunchKernelGGL((k_spread_tiles<Tg, W>), sg, dim3(256), lds, st, sp, sv, so, g,      \
+                         pl->beta, pair0, gr);                                                \
+      break;
+    RW_SPREAD_CASE(4) RW_SPREAD_CASE(5) RW_SPREAD_CASE(6) RW_SPREAD_CASE(7) RW_SPREAD_CASE(8)
+    RW_SPREAD_CASE(9) RW_SPREAD_CASE(10) RW_SPREAD_CASE(11) RW_SPREAD_CASE(12)
+    RW_SPREAD_CASE(13) RW_SPREAD_CASE(14) RW_SPREAD_CASE(15) RW_SPREAD_CASE(16)
+#undef RW_SPREAD_CASE
+    default: return fail(RW_ERR_SHAPE, "spread_width must be in [4, 16]");
+  }
   HIPCHK(hipGetLastError());
   return RW_OK;
 }
@@ -426,9 +409,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->nf = std::max(2 * cfg->psf_q, 64);
   pl->w = cfg->spread_width > 0 ? cfg->spread_width
                                 : (cfg->precision == RW_PREC_FP64 ? 13 : 7);
-  if (pl->w < 2 || pl->w > 16) {
+  if (pl->w < 4 || pl->w > 16) {
     delete pl;
-    return fail(RW_ERR_SHAPE, "spread_width must be in [2, 16]");
+    return fail(RW_ERR_SHAPE, "spread_width must be in [4, 16]");
   }
   const double sigma = (double)pl->nf / pl->Q;
   pl->beta = 0.98 * M_PI * pl->w * (1.0 - 0.5 / sigma);
@@ -445,7 +428,11 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   const bool dbl_g = cfg->precision == RW_PREC_FP64;
   pl->sz_cf = dbl_f ? 16 : 8;
   pl->sz_cg = dbl_g ? 16 : 8;
-  pl->lds_patch = (size_t)M * (M + 1) * pl->sz_cf + M * pl->sz_cf + 4096 <= 160 * 1024;
+  pl->lds_patch = (size_t)M * (M + 1) * pl->sz_cf + M * pl->sz_cf + (size_t)M * 64 * 8 + 4096 <=
+                  160 * 1024;
+  pl->ray_block = 8;
+  pl->acc_side = 256;
+  pl->doe_blocks = pl->lds_patch ? 1024 : 512;
   pl->emit = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
   {
     const int nb = std::min(64, pl->nf / 8);
@@ -453,7 +440,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     while ((1 << shift) < pl->nf / nb) ++shift;
     pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb};
     const size_t tile = 4 * (size_t)pl->bg.bin;
-    if (tile * tile * pl->sz_cg > 128 * 1024 || pl->w > 2 * pl->bg.bin) {
+    if (tile * (tile + 1) * pl->sz_cg > 128 * 1024 || pl->w > 2 * pl->bg.bin) {
       delete pl;
       return fail(RW_ERR_UNSUPPORTED, "PSF size too large for this precision");
     }
@@ -467,7 +454,6 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     pl->group_pairs = (int)std::min<size_t>(gp, (size_t)pl->n_pairs);
     if (!cfg->batched) pl->group_pairs = 1;
   }
-  pl->fwd_blocks = (int)std::min<size_t>(pl->n_total, pl->lds_patch ? 8192 : 2048);
 
   // host copies of the constant tables
   DevCfg dc;
@@ -477,6 +463,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   dc.w = pl->w; dc.sampling = cfg->sampling; dc.H = doe->H; dc.W = doe->W;
   dc.n_params = n_params;
   dc.pitch = doe->pitch; dc.x0 = doe->x0; dc.y0 = doe->y0;
+  dc.inv_pitch = 1.0 / doe->pitch;
+  dc.planar = pl->planar_doe ? 1 : 0;
   dc.launch_z = cfg->launch_z; dc.launch_half = cfg->launch_half; dc.psf_pitch = cfg->psf_pitch;
   dc.beta = pl->beta;
   dc.key0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -543,10 +531,17 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   {
     // the spreading tile of the largest grids needs more than the default 64 KiB of LDS
     const int lim = 128 * 1024;
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<float>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    hipError_t eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<double>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    hipError_t ea = hipSuccess, eb = hipSuccess;
+#define RW_ATTR(W)                                                                              \
+    if (ea == hipSuccess)                                                                       \
+      ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<float, W>),        \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);                \
+    if (eb == hipSuccess)                                                                       \
+      eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<double, W>),       \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    RW_ATTR(4) RW_ATTR(5) RW_ATTR(6) RW_ATTR(7) RW_ATTR(8) RW_ATTR(9) RW_ATTR(10) RW_ATTR(11)
+    RW_ATTR(12) RW_ATTR(13) RW_ATTR(14) RW_ATTR(15) RW_ATTR(16)
+#undef RW_ATTR
     if (ea != hipSuccess || eb != hipSuccess) {
       delete pl;
       return fail(RW_ERR_HIP, "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed");
@@ -586,7 +581,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_lossp = take(pl->n_pairs * sizeof(double));
   pl->off_stats = take(4 * sizeof(unsigned long long));
   pl->off_scratch =
-      take(pl->lds_patch ? 0 : (size_t)pl->fwd_blocks * M * (M + 1) * pl->sz_cf);
+      take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
+  pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
   pl->off_raygrad = take(8 * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
@@ -677,11 +673,10 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
     HIPCHK(hipGetLastError());
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;
-    const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
     rw_status s;
     {
       StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
-      s = doe_fwd(pl, a, blocks, st);
+      s = doe_launch(pl, true, a, pair0, ppg, st);
     }
     if (s != RW_OK) return s;
     s = bin_and_spread(pl, ws, st, pair0, ppg);
@@ -774,6 +769,11 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   else zero<float>(b + pl->off_gt, 2 * nmap, st);
   zero<double>(b + pl->off_lensg, RW_LENSG_SLOTS, st);
   if (want_lens) zero<double>(b + pl->off_raygrad, 8 * pl->n_total, st);
+  {
+    const size_t nacc = (size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * 2;
+    if (dbl) zero<double>(b + pl->off_acc, nacc, st);
+    else zero<float>(b + pl->off_acc, nacc, st);
+  }
   DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
   a.adj = b + pl->off_grid;
   a.want_lens = want_lens ? 1 : 0;
@@ -789,10 +789,9 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
     const size_t nr = (size_t)ppg * pl->R2;
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;
-    const int blocks = (int)std::min<size_t>(nr, (size_t)pl->fwd_blocks);
     {
       StageTimer tm_(pl, RW_STAGE_DOE_BWD, st);
-      s = doe_bwd(pl, a, blocks, st);
+      s = doe_launch(pl, false, a, pair0, ppg, st);
     }
     if (s != RW_OK) return s;
     if (want_lens) {

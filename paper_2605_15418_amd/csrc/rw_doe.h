@@ -1,0 +1,830 @@
+// Ray-wave interface kernels (forward and adjoint), one workgroup of 512
+// threads per incident ray at a time, persistent over spatial blocks of rays.
+//
+// Per ray (Formalism, second paragraph; Eq. 1; Fig. 1c):
+//   1. tangent frame, incident tangential wavevector
+//   2. stage the DOE map tile under the patch in LDS (coalesced), bilinear
+//      samples of t = A exp(i phi) -> zero-padded M x M patch
+//   3. 2-D FFT: row transforms of the P nonzero rows, then column transforms;
+//      each lane ends the column pass holding E consecutive bins of one column,
+//      which is one chunk of the j_x-major inverse CDF: the chunk sums of the
+//      sampling density come straight from registers
+//   4. block scan of the chunk sums, N Philox draws (binary search over chunk
+//      prefixes, then at most E bins), Eq. 1 weights, emission, trace to the
+//      sensor, Eq. 2 wavelet -> record for the binned spreading
+// The adjoint recomputes 1-4, interpolates the sensor-grid cogradient at every
+// wavelet, forms the spectrum cogradient (drawn bins + the S = sum |U~| term),
+// inverse-transforms it to the patch, and scatters the bilinear adjoint into an
+// LDS tile that is added to a block-private accumulator covering the whole
+// block of rays; the accumulator is flushed to dL/dt once per ray block.
+#pragma once
+#include <climits>
+
+#include "rw_backward.h"
+
+namespace rw {
+
+constexpr int kDoeThreads = 512;
+
+template <int M> struct DoeGeom {
+  static constexpr int NT = kDoeThreads;
+  static constexpr int Lraw = 2 * NT / M;
+  static constexpr int L = Lraw < 2 ? 2 : (Lraw > M / 2 ? M / 2 : Lraw);  // lanes per transform
+  static constexpr int E = M / L;                                          // elements per lane
+  static constexpr int G = NT / L;                                         // transform groups
+  static constexpr int SM = M + 1;                                         // LDS row stride
+  static constexpr int NCH = M * L;                                        // CDF chunks of E bins
+  static constexpr int LB = Log2<L>::v;
+};
+
+// Propagating test of shifted bin (jx, jy): |k_in,t + kappa_j| < k_out (FP64).
+__device__ __forceinline__ bool propagating(const RayCtx& c, int jx, int jy) {
+  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+  return Ku * Ku + Kv * Kv < c.k_out * c.k_out;
+}
+
+// Map tile under the patch: TW x TW pixels from (tx0, ty0); zero outside the map.
+struct TileRef { int tx0, ty0, tw; };
+
+__device__ __forceinline__ TileRef tile_of(const DevCfg& cfg, const RayCtx& c) {
+  const double fx = (c.p[0] - cfg.x0) * cfg.inv_pitch, fy = (c.p[1] - cfg.y0) * cfg.inv_pitch;
+  const int tw = cfg.P + 4;
+  return {(int)floor(fx) - cfg.P / 2 - 1, (int)floor(fy) - cfg.P / 2 - 1, tw};
+}
+
+template <class Tf>
+__device__ __forceinline__ void stage_tile(const DevCfg& cfg, const TileRef& tr, const C2<Tf>* tm,
+                                           C2<Tf>* tile) {
+  for (int i = threadIdx.x; i < tr.tw * tr.tw; i += kDoeThreads) {
+    const int y = tr.ty0 + i / tr.tw, x = tr.tx0 + i % tr.tw;
+    tile[i] = (x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) ? tm[(size_t)y * cfg.W + x]
+                                                           : C2<Tf>{Tf(0), Tf(0)};
+  }
+}
+
+// Bilinear sample (m, n) of the patch; the 2 x 2 stencil is read from the
+// staged tile when it lies inside it, else from the map.
+template <class Tf>
+__device__ __forceinline__ C2<Tf> patch_sample_t(const DevCfg& cfg, const RayCtx& c,
+                                                 const C2<Tf>* tm, const C2<Tf>* tile,
+                                                 const TileRef& tr, int m, int n) {
+  const double sm = (m - (cfg.P - 1) * 0.5) * cfg.pitch;
+  const double sn = (n - (cfg.P - 1) * 0.5) * cfg.pitch;
+  const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
+  const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
+  const double fx = (qx - cfg.x0) * cfg.inv_pitch, fy = (qy - cfg.y0) * cfg.inv_pitch;
+  const double flx = floor(fx), fly = floor(fy);
+  const int ix = (int)flx, iy = (int)fly;
+  const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
+  const int lx = ix - tr.tx0, ly = iy - tr.ty0;
+  C2<Tf> t00, t01, t10, t11;
+  if (tile && lx >= 0 && lx + 1 < tr.tw && ly >= 0 && ly + 1 < tr.tw) {
+    const C2<Tf>* r0 = tile + ly * tr.tw + lx;
+    t00 = r0[0]; t01 = r0[1]; t10 = r0[tr.tw]; t11 = r0[tr.tw + 1];
+  } else {
+    auto at = [&](int y, int x) {
+      return (x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) ? tm[(size_t)y * cfg.W + x]
+                                                          : C2<Tf>{Tf(0), Tf(0)};
+    };
+    t00 = at(iy, ix); t01 = at(iy, ix + 1); t10 = at(iy + 1, ix); t11 = at(iy + 1, ix + 1);
+  }
+  return (t00 * (Tf(1) - wx) + t01 * wx) * (Tf(1) - wy) + (t10 * (Tf(1) - wx) + t11 * wx) * wy;
+}
+
+// Planar DOE: every sample of the patch sits at the same sub-pixel fraction;
+// sample (m, n) interpolates pixels (ix0 + m + {0,1}, iy0 + n + {0,1}).
+template <class Tf> struct PlanarPatch {
+  int ix0, iy0;
+  Tf wx, wy;
+};
+template <class Tf>
+__device__ __forceinline__ PlanarPatch<Tf> planar_patch(const DevCfg& cfg, const RayCtx& c) {
+  const double fx0 = (c.p[0] - cfg.x0) * cfg.inv_pitch - 0.5 * (cfg.P - 1);
+  const double fy0 = (c.p[1] - cfg.y0) * cfg.inv_pitch - 0.5 * (cfg.P - 1);
+  const double flx = floor(fx0), fly = floor(fy0);
+  return {(int)flx, (int)fly, (Tf)(fx0 - flx), (Tf)(fy0 - fly)};
+}
+
+// Shared scratch of one workgroup.
+template <class Tf, int M, bool kLDS> struct DoeLds {
+  C2<Tf> buf[kLDS ? M * DoeGeom<M>::SM : 1];
+  C2<Tf> tw[M];
+  double pref[DoeGeom<M>::NCH + 1];
+  double red[16];
+  int redi[16];
+  double acc[8][16];
+  RayCtx ctx;
+};
+
+// Spectrum of the ray's patch into buf (natural order) and the per-chunk sums of
+// the sampling density into s.pref[chunk] (before the scan).  Returns lastpos
+// candidates through *lastpos (block maximum taken by the caller).
+template <class Tf, int M>
+__device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
+                                             const C2<Tf>* tm, C2<Tf>* buf, const C2<Tf>* tw,
+                                             double* chunk, int sampling, int* lastpos) {
+  using Gm = DoeGeom<M>;
+  constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
+  const int g = threadIdx.x / L, gl = threadIdx.x % L;
+  const int br = bitrev(gl, Gm::LB);
+  const int P = cfg.P;
+  // the map tile goes into rows P.. of buf, which the row pass leaves untouched
+  const TileRef tr = tile_of(cfg, c);
+  C2<Tf>* tile = (M - P) * SM >= tr.tw * tr.tw ? buf + P * SM : nullptr;
+  if (tile) stage_tile<Tf>(cfg, tr, tm, tile);
+  __syncthreads();
+  // bilinear samples of the patch into rows 0..P-1, columns 0..P-1 of buf
+  if (cfg.planar && tile) {
+    const PlanarPatch<Tf> pp = planar_patch<Tf>(cfg, c);
+    const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
+    const Tf w00 = (Tf(1) - pp.wx) * (Tf(1) - pp.wy), w01 = pp.wx * (Tf(1) - pp.wy);
+    const Tf w10 = (Tf(1) - pp.wx) * pp.wy, w11 = pp.wx * pp.wy;
+    for (int i = threadIdx.x; i < P * P; i += kDoeThreads) {
+      const int m = i % P, n = i / P;
+      const C2<Tf>* r0 = tile + (oy + n) * tr.tw + ox + m;
+      buf[n * SM + m] = r0[0] * w00 + r0[1] * w01 + r0[tr.tw] * w10 + r0[tr.tw + 1] * w11;
+    }
+  } else {
+    for (int i = threadIdx.x; i < P * P; i += kDoeThreads) {
+      const int m = i % P, n = i / P;
+      buf[n * SM + m] = patch_sample_t<Tf>(cfg, c, tm, tile, tr, m, n);
+    }
+  }
+  __syncthreads();
+  for (int row = g; row < P; row += G) {
+    C2<Tf> x[E];
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      const int m = gl + L * n2;
+      x[n2] = m < P ? buf[row * SM + m] : C2<Tf>{Tf(0), Tf(0)};
+    }
+    group_fft<Tf, L, E, -1>(x, gl, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
+  }
+  __syncthreads();
+  int lp = -1;
+  for (int col = g; col < M; col += G) {
+    C2<Tf> x[E];
+#pragma unroll
+    for (int n2 = 0; n2 < E; ++n2) {
+      const int n = gl + L * n2;
+      x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+    }
+    group_fft<Tf, L, E, -1>(x, gl, tw);
+    // this lane now holds rows ky = E*br .. E*br + E - 1 of column col
+    const int jx = col < M / 2 ? col : col - M;
+    const int ky0 = E * br;
+    const int jys0 = (ky0 + M / 2) & (M - 1);                  // shifted row of the first bin
+    const int ch = ((jx + M / 2) * M + jys0) / E;              // chunk id (j_x-major)
+    double s = 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) {
+      const int ky = ky0 + k2;
+      const int jy = ky < M / 2 ? ky : ky - M;
+      buf[ky * SM + col] = x[k2];
+      double wgt = 0.0;
+      if (propagating(c, jx, jy)) wgt = sampling == 0 ? (double)cabs_rn(x[k2]) : 1.0;
+      s += wgt;
+      if (wgt > 0.0) lp = max(lp, (jx + M / 2) * M + (jy + M / 2));
+    }
+    chunk[ch] = s;
+  }
+  *lastpos = lp;
+  __syncthreads();
+}
+
+// Exclusive scan of the chunk sums in place; returns the total S.
+template <int M>
+__device__ __forceinline__ double chunk_scan(double* pref, double* red) {
+  using Gm = DoeGeom<M>;
+  constexpr int K = (Gm::NCH + kDoeThreads - 1) / kDoeThreads;
+  const int t = threadIdx.x;
+  double v[K], tot = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k;
+    v[k] = i < Gm::NCH ? pref[i] : 0.0;
+    tot += v[k];
+  }
+  // block exclusive scan of the per-thread totals (8 waves)
+  const int lane = t & 63, wv = t >> 6;
+  double inc = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double n = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += n;
+  }
+  if (lane == 63) red[wv] = inc;
+  __syncthreads();
+  double base = 0.0, S = 0.0;
+#pragma unroll
+  for (int i = 0; i < kDoeThreads / 64; ++i) {
+    if (i < wv) base += red[i];
+    S += red[i];
+  }
+  double run = base + inc - tot;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = t * K + k;
+    if (i < Gm::NCH) pref[i] = run;
+    run += v[k];
+  }
+  if (t == 0) pref[Gm::NCH] = S;
+  __syncthreads();
+  return S;
+}
+
+__device__ __forceinline__ int block_max_i(int v, int* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int m = red[0];
+  for (int i = 1; i < kDoeThreads / 64; ++i) m = max(m, red[i]);
+  __syncthreads();
+  return m;
+}
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int i = 0; i < kDoeThreads / 64; ++i) m += red[i];
+  __syncthreads();
+  return m;
+}
+
+// Inverse-CDF draw: J = min{j : C_j > T} in j_x-major shifted order.
+template <class Tf, int M>
+__device__ __forceinline__ int draw_bin(const RayCtx& c, const C2<Tf>* buf, const double* pref,
+                                        double T, int sampling, int lastpos_all) {
+  using Gm = DoeGeom<M>;
+  constexpr int E = Gm::E, SM = Gm::SM;
+  int lo = 0, hi = Gm::NCH - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pref[mid] <= T) lo = mid; else hi = mid - 1;
+  }
+  double run = pref[lo];
+  const int base = lo * E;                       // linear bin of the chunk's first bin
+  const int jx = base / M - M / 2;
+  const int kx = jx & (M - 1);
+  int lp = -1;
+  for (int q = 0; q < E; ++q) {
+    const int jy = (base % M) + q - M / 2;
+    double wgt = 0.0;
+    if (propagating(c, jx, jy))
+      wgt = sampling == 0 ? (double)cabs_rn(buf[(jy & (M - 1)) * SM + kx]) : 1.0;
+    run += wgt;
+    if (wgt > 0.0) lp = base + q;
+    if (run > T) return base + q;
+  }
+  return lp >= 0 ? lp : lastpos_all;
+}
+
+// Work item = block of rb x rb launch-grid rays of one pair.
+struct RayBlockIter {
+  int rb, nbx, per_pair, R;
+  __device__ __forceinline__ int count() const { return rb * rb; }
+  // global ray id of ray k of item it (or -1 past the grid edge)
+  __device__ __forceinline__ long long ray(long long it, int k, int pair0) const {
+    const int pair = pair0 + (int)(it / per_pair);
+    const int b = (int)(it % per_pair);
+    const int by = b / nbx, bx = b % nbx;
+    const int iy = by * rb + k / rb, ix = bx * rb + k % rb;
+    if (iy >= R || ix >= R) return -1;
+    return (long long)pair * R * R + (long long)iy * R + ix;
+  }
+};
+
+// ------------------------------------------------------------------ forward ---
+template <class Prec, int M, bool kLDS>
+__global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIter itr,
+                                                          long long n_items, int pair0) {
+  using Tf = typename Prec::Tf;
+  using Tg = typename Prec::Tg;
+  using Tp = typename Prec::Tp;
+  using Gm = DoeGeom<M>;
+  constexpr int SM = Gm::SM;
+  __shared__ DoeLds<Tf, M, kLDS> s;
+  const DevCfg& cfg = *a.cfg;
+  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
+  const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
+  for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
+  __syncthreads();
+  const int N = cfg.N, P = cfg.P, t = threadIdx.x, emit = a.emit;
+  const double inv_m2 = 1.0 / ((double)M * M);
+  unsigned long long n_sec = 0, n_alive = 0;
+  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+    for (int k = 0; k < itr.count(); ++k) {
+      const long long gid = itr.ray(it, k, pair0);
+      if (gid < 0) continue;
+      const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
+      if (a.st[7 * a.n_total + gid] == 0.0) {
+        for (int i = t; i < emit; i += kDoeThreads) put_zero<Tg>(a, slot0 + i);
+        if (a.idx_out && cfg.sampling != 2)
+          for (int i = t; i < N; i += kDoeThreads) a.idx_out[gid * N + i] = -1;
+        continue;
+      }
+      n_alive += (t == 0);
+      if (t == 0) make_ctx(a, (size_t)gid, s.ctx);
+      __syncthreads();
+      const RayCtx& c = s.ctx;
+      int lp;
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, cfg.sampling, &lp);
+      if (cfg.sampling == 2) {
+        for (int Lb = t; Lb < M * M; Lb += kDoeThreads) {
+          const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
+          Tp phi0, wx, wy; double dza; Secondary sec;
+          if (!propagating(c, jx, jy) ||
+              !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
+            put_zero<Tg>(a, slot0 + Lb);
+            continue;
+          }
+          const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+          const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+          const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+          const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+          put_record<Prec>(a, slot0 + Lb, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+          ++n_sec;
+        }
+        __syncthreads();
+        continue;
+      }
+      const double S = chunk_scan<M>(s.pref, s.red);
+      const int lastpos_all = block_max_i(lp, s.redi);
+      const double scale = S * inv_m2 / N;               // S or |Pi| over M^2 N
+      for (int i = t; i < N; i += kDoeThreads) {
+        int J = -1;
+        if (S > 0.0) {
+          if (a.replay) {
+            J = a.replay[gid * N + i];
+          } else {
+            const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
+                                          (uint32_t)c.pair, 0u) * S;
+            J = draw_bin<Tf, M>(c, buf, s.pref, T, cfg.sampling, lastpos_all);
+          }
+        }
+        if (a.idx_out) a.idx_out[gid * N + i] = J;
+        bool ok = J >= 0;
+        C2<Tp> w = {Tp(0), Tp(0)};
+        int jx = 0, jy = 0;
+        if (ok) {
+          jx = J / M - M / 2; jy = J % M - M / 2;
+          const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+          const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+          if (cfg.sampling == 0) {
+            const Tf mag = cabs_rn(X);
+            ok = mag > Tf(0);
+            const Tp f = ok ? (Tp)(scale / (double)mag) : Tp(0);
+            w = {(Tp)U.re * f, (Tp)U.im * f};
+          } else {
+            w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+          }
+        }
+        Tp phi0, wx, wy; double dza; Secondary sec;
+        if (ok) ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
+        if (!ok) {
+          put_zero<Tg>(a, slot0 + i);
+          continue;
+        }
+        const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+        put_record<Prec>(a, slot0 + i, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+        ++n_sec;
+      }
+      __syncthreads();   // buf and pref are reused by the next ray
+    }
+  }
+  if (a.stats) {
+    if (n_alive) atomicAdd(&a.stats[0], n_alive);
+    if (n_sec) atomicAdd(&a.stats[1], n_sec);
+  }
+}
+
+// ------------------------------------------------------------------ adjoint ---
+// Type-2 interpolation of the sensor-grid cogradient with the kernel derivative.
+template <class Prec>
+__device__ __forceinline__ void interp_adj2(const DevCfg& cfg, const C2<typename Prec::Tg>* B,
+                                            int pair, typename Prec::Tp gx, typename Prec::Tp gy,
+                                            C2<double>& g0, C2<double>& dx, C2<double>& dy) {
+  using Tg = typename Prec::Tg;
+  using Tp = typename Prec::Tp;
+  const int nf = cfg.nf, w = cfg.w;
+  const int lx0 = (int)ceil(gx - (Tp)(0.5 * w)), ly0 = (int)ceil(gy - (Tp)(0.5 * w));
+  const Tg tw = (Tg)(2.0 / w), beta = (Tg)cfg.beta;
+  Tg kx[16], dkx[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    kx[i] = Tg(0); dkx[i] = Tg(0);
+    if (i < w) {
+      const Tg tx = (Tg)((double)((Tp)(lx0 + i) - gx)) * tw;
+      const Tg ax = Tg(1) - tx * tx;
+      if (ax > Tg(0)) {
+        const Tg sx = sqrt(ax);
+        kx[i] = (Tg)exp(beta * (sx - Tg(1)));
+        dkx[i] = -kx[i] * beta * tx / sx * tw;
+      }
+    }
+  }
+  g0 = {0, 0}; dx = {0, 0}; dy = {0, 0};
+  const C2<Tg>* gp = B + (size_t)pair * nf * nf;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j >= w) break;
+    const Tg ty = (Tg)((double)((Tp)(ly0 + j) - gy)) * tw;
+    const Tg ay = Tg(1) - ty * ty;
+    if (!(ay > Tg(0))) continue;
+    const Tg sy = sqrt(ay);
+    const Tg ky = (Tg)exp(beta * (sy - Tg(1)));
+    const Tg dky = -ky * beta * ty / sy * tw;
+    const C2<Tg>* row = gp + (size_t)((ly0 + j) & (nf - 1)) * nf;
+    Tg s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i < w) {
+        const C2<Tg> b = row[(lx0 + i) & (nf - 1)];
+        s0r += kx[i] * b.re; s0i += kx[i] * b.im;
+        s1r += dkx[i] * b.re; s1i += dkx[i] * b.im;
+      }
+    }
+    g0.re += (double)(ky * s0r); g0.im += (double)(ky * s0i);
+    dx.re += (double)(ky * s1r); dx.im += (double)(ky * s1i);
+    dy.re += (double)(dky * s0r); dy.im += (double)(dky * s0i);
+  }
+}
+
+template <class Prec>
+__device__ __forceinline__ bool wavelet_adjoint2(const DoeArgs& a, const RayCtx& c, int jx,
+                                                 int jy, C2<typename Prec::Tp> w, WaveletAdj& wa,
+                                                 Secondary& sec) {
+  using Tp = typename Prec::Tp;
+  using Tg = typename Prec::Tg;
+  const DevCfg& cfg = *a.cfg;
+  Tp phi0, wx, wy;
+  double dza;
+  if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) return false;
+  const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
+  const C2<Tp> cv = (w * e) * (Tp)dza;
+  C2<double> g0, dx, dy;
+  interp_adj2<Prec>(cfg, (const C2<Tg>*)a.adj, c.pair, grid_coord(wx, cfg.nf),
+                    grid_coord(wy, cfg.nf), g0, dx, dy);
+  const C2<double> cd = {(double)cv.re, (double)cv.im};
+  const double cell = cfg.nf / (2.0 * RW_PI);
+  wa.g_wx = -(cd.re * dx.re + cd.im * dx.im) * cell;
+  wa.g_wy = -(cd.re * dy.re + cd.im * dy.im) * cell;
+  wa.g_phi0 = -(g0.re * cd.im - g0.im * cd.re);
+  wa.g_dz = (g0.re * cd.re + g0.im * cd.im) / dza;
+  const double er = (double)e.re * dza, ei = (double)e.im * dza;
+  wa.g_w = {er * g0.re + ei * g0.im, er * g0.im - ei * g0.re};
+  return true;
+}
+
+template <class Prec, int M, bool kLDS>
+__global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
+                                                          long long n_items, int pair0) {
+  using Tf = typename Prec::Tf;
+  using Tg = typename Prec::Tg;
+  using Tp = typename Prec::Tp;
+  using Gm = DoeGeom<M>;
+  constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
+  constexpr int DPT = (2048 + kDoeThreads - 1) / kDoeThreads;
+  __shared__ DoeLds<Tf, M, kLDS> s;
+  __shared__ int s_box[4];
+  const DevCfg& cfg = *a.cfg;
+  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
+  const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
+  C2<Tg>* gt = (C2<Tg>*)a.gt;
+  // block-private accumulator of dL/dt over one ray block
+  const int AS = a.acc_side;
+  C2<Tg>* accm = (C2<Tg>*)a.acc + (size_t)blockIdx.x * AS * AS;
+  for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
+  __syncthreads();
+  const int N = cfg.N, P = cfg.P, t = threadIdx.x;
+  const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
+  const double inv_m2 = 1.0 / ((double)M * M);
+  const int H = cfg.H, W = cfg.W;
+  const int T = P + 4;                                  // bilinear tile side
+  const bool use_tile = (M - P) * SM >= T * T;
+  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+    // anchor of the accumulator: the first live ray of the block
+    if (t == 0) { s_box[0] = INT_MAX; s_box[1] = INT_MAX; s_box[2] = INT_MIN; s_box[3] = INT_MIN; }
+    int ax0 = 0, ay0 = 0;
+    bool have_anchor = false;
+    for (int k = 0; k < itr.count() && !have_anchor; ++k) {
+      const long long gid = itr.ray(it, k, pair0);
+      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0) continue;
+      const double fx = (a.st[0 * a.n_total + gid] - cfg.x0) * cfg.inv_pitch;
+      const double fy = (a.st[1 * a.n_total + gid] - cfg.y0) * cfg.inv_pitch;
+      ax0 = (int)floor(fx) - AS / 2;
+      ay0 = (int)floor(fy) - AS / 2;
+      have_anchor = true;
+    }
+    __syncthreads();
+    if (!have_anchor) continue;
+    for (int k = 0; k < itr.count(); ++k) {
+      const long long gid = itr.ray(it, k, pair0);
+      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0) continue;
+      if (t == 0) make_ctx(a, (size_t)gid, s.ctx);
+      __syncthreads();
+      const RayCtx& c = s.ctx;
+      int lp;
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, cfg.sampling, &lp);
+      IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
+      double dLdS = 0.0;
+      int kk[DPT];
+      C2<Tf> gX[DPT];
+#pragma unroll
+      for (int q = 0; q < DPT; ++q) kk[q] = -1;
+      if (cfg.sampling != 2) {
+        const double S = chunk_scan<M>(s.pref, s.red);
+        const int lastpos_all = block_max_i(lp, s.redi);
+        if (S > 0.0) {
+          const double scale = S * inv_m2 / N;
+#pragma unroll 1
+          for (int q = 0; q < DPT; ++q) {
+            const int i = t + q * kDoeThreads;
+            if (i >= N) break;
+            int J;
+            if (a.replay) {
+              J = a.replay[gid * N + i];
+            } else {
+              const double Tv = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
+                                             (uint32_t)c.pair, 0u) * S;
+              J = draw_bin<Tf, M>(c, buf, s.pref, Tv, cfg.sampling, lastpos_all);
+            }
+            if (J < 0) continue;
+            const int jx = J / M - M / 2, jy = J % M - M / 2;
+            const int kidx = (jy & (M - 1)) * SM + (jx & (M - 1));
+            const C2<Tf> X = buf[kidx];
+            const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
+            const C2<Tf> U = X * ref;
+            C2<Tp> w;
+            double mag = 0.0;
+            if (cfg.sampling == 0) {
+              const Tf m = cabs_rn(X);
+              if (!(m > Tf(0))) continue;
+              mag = (double)m;
+              const Tp f = (Tp)(scale / mag);
+              w = {(Tp)U.re * f, (Tp)U.im * f};
+            } else {
+              w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+            }
+            WaveletAdj wa;
+            Secondary sec;
+            if (!wavelet_adjoint2<Prec>(a, c, jx, jy, w, wa, sec)) continue;
+            C2<double> gU;
+            if (cfg.sampling == 0) {
+              const double hr = (double)U.re / mag, hi_ = (double)U.im / mag;
+              dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
+              const double gr = wa.g_w.re * scale, gi = wa.g_w.im * scale;
+              const double im = -(gr * hi_ - gi * hr) / mag;
+              gU = {-im * hi_, im * hr};
+            } else {
+              gU = {wa.g_w.re * scale, wa.g_w.im * scale};
+            }
+            const double rr = (double)ref.re, ri = (double)ref.im;
+            kk[q] = kidx;
+            gX[q] = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
+            if (a.want_lens) incident_from_wavelet(a, c, sec, wa, acc);
+          }
+        }
+        dLdS = block_sum_d(dLdS, s.red);     // orders every read of buf before the rewrite
+        // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins
+        for (int idx = t; idx < M * M; idx += kDoeThreads) {
+          const int ky = idx / M, kx = idx % M;
+          const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+          C2<Tf>& X = buf[ky * SM + kx];
+          C2<Tf> v = {Tf(0), Tf(0)};
+          if (cfg.sampling == 0 && propagating(c, jx, jy)) {
+            const Tf m = cabs_rn(X);
+            if (m > Tf(0)) {
+              const Tf f = (Tf)dLdS / m;
+              v = {X.re * f, X.im * f};
+            }
+          }
+          X = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < DPT; ++q) {
+          if (kk[q] >= 0) {
+            atomicAdd(&buf[kk[q]].re, gX[q].re);
+            atomicAdd(&buf[kk[q]].im, gX[q].im);
+          }
+        }
+      } else {
+        for (int idx = t; idx < M * M; idx += kDoeThreads) {
+          const int ky = idx / M, kx = idx % M;
+          const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+          C2<Tf> out = {Tf(0), Tf(0)};
+          if (propagating(c, jx, jy)) {
+            const C2<Tf> X = buf[ky * SM + kx];
+            const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
+            const C2<Tf> U = X * ref;
+            const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+            WaveletAdj wa;
+            Secondary sec;
+            if (wavelet_adjoint2<Prec>(a, c, jx, jy, w, wa, sec)) {
+              const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
+              const double rr = (double)ref.re, ri = (double)ref.im;
+              out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};
+              if (a.want_lens) incident_from_wavelet(a, c, sec, wa, acc);
+            }
+          }
+          buf[ky * SM + kx] = out;
+        }
+      }
+      __syncthreads();
+      // inverse transform: columns (keep rows n < P), then rows n < P (keep m < P)
+      for (int col = g; col < M; col += G) {
+        C2<Tf> x[E];
+#pragma unroll
+        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[(gl + L * n2) * SM + col];
+        group_fft<Tf, L, E, +1>(x, gl, s.tw);
+#pragma unroll
+        for (int k2 = 0; k2 < E; ++k2) {
+          const int n = E * br + k2;
+          if (n < P) buf[n * SM + col] = x[k2];
+        }
+      }
+      __syncthreads();
+      for (int row = g; row < P; row += G) {
+        C2<Tf> x[E];
+#pragma unroll
+        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[row * SM + gl + L * n2];
+        group_fft<Tf, L, E, +1>(x, gl, s.tw);
+#pragma unroll
+        for (int k2 = 0; k2 < E; ++k2) {
+          const int m = E * br + k2;
+          if (m < P) buf[row * SM + m] = x[k2];
+        }
+      }
+      __syncthreads();
+      // bilinear adjoint of the patch gather -> dL/dt, added to the block accumulator
+      double gpx = 0.0, gpy = 0.0;
+      if (cfg.planar && (M - P) * SM >= T * T) {
+        // gather form: pixel (ix0 + a, iy0 + b) collects the (up to) four samples
+        // whose 2 x 2 stencils contain it; no atomics
+        const PlanarPatch<Tf> pp = planar_patch<Tf>(cfg, c);
+        const Tf w00 = (Tf(1) - pp.wx) * (Tf(1) - pp.wy), w01 = pp.wx * (Tf(1) - pp.wy);
+        const Tf w10 = (Tf(1) - pp.wx) * pp.wy, w11 = pp.wx * pp.wy;
+        const int P1 = P + 1;
+        const int lx0 = pp.ix0 - ax0, ly0 = pp.iy0 - ay0;
+        const bool inside = lx0 >= 0 && ly0 >= 0 && lx0 + P1 <= AS && ly0 + P1 <= AS;
+        if (inside && t == 0) {
+          atomicMin(&s_box[0], lx0); atomicMin(&s_box[1], ly0);
+          atomicMax(&s_box[2], lx0 + P1); atomicMax(&s_box[3], ly0 + P1);
+        }
+        auto gu = [&](int n, int m) {
+          return (m >= 0 && m < P && n >= 0 && n < P) ? buf[n * SM + m] : C2<Tf>{Tf(0), Tf(0)};
+        };
+        for (int i = t; i < P1 * P1; i += kDoeThreads) {
+          const int aa = i % P1, bb = i / P1;
+          const int x = pp.ix0 + aa, y = pp.iy0 + bb;
+          if (x < 0 || x >= W || y < 0 || y >= H) continue;
+          const C2<Tf> v = gu(bb, aa) * w00 + gu(bb, aa - 1) * w01 + gu(bb - 1, aa) * w10 +
+                           gu(bb - 1, aa - 1) * w11;
+          if (v.re == Tf(0) && v.im == Tf(0)) continue;
+          if (inside) {
+            C2<Tg>& d = accm[(size_t)(ly0 + bb) * AS + lx0 + aa];
+            d.re += (Tg)v.re;
+            d.im += (Tg)v.im;
+          } else {
+            atomicAdd(&gt[(size_t)y * W + x].re, (Tg)v.re);
+            atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
+          }
+        }
+        if (a.want_lens) {
+          // map tile under the patch (rows P.. of buf are free again)
+          const TileRef tr = tile_of(cfg, c);
+          C2<Tf>* mt = buf + P * SM;
+          stage_tile<Tf>(cfg, tr, tm, mt);
+          __syncthreads();
+          const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
+          for (int smp = t; smp < P * P; smp += kDoeThreads) {
+            const int m = smp % P, n = smp / P;
+            const C2<Tf> g = buf[n * SM + m];
+            const C2<Tf>* r0 = mt + (oy + n) * tr.tw + ox + m;
+            const C2<Tf> t00 = r0[0], t01 = r0[1], t10 = r0[tr.tw], t11 = r0[tr.tw + 1];
+            const C2<Tf> dUx = (t01 - t00) * (Tf(1) - pp.wy) + (t11 - t10) * pp.wy;
+            const C2<Tf> dUy = (t10 - t00) * (Tf(1) - pp.wx) + (t11 - t01) * pp.wx;
+            gpx += (double)(g.re * dUx.re + g.im * dUx.im);
+            gpy += (double)(g.re * dUy.re + g.im * dUy.im);
+          }
+          gpx *= cfg.inv_pitch;
+          gpy *= cfg.inv_pitch;
+        }
+      } else {
+      // general surface: LDS-tiled scatter of every sample's 2 x 2 stencil
+      C2<Tf>* tile = buf + P * SM;
+      const double cfx = (c.p[0] - cfg.x0) * cfg.inv_pitch, cfy = (c.p[1] - cfg.y0) * cfg.inv_pitch;
+      const int tx0 = (int)floor(cfx) - T / 2, ty0 = (int)floor(cfy) - T / 2;
+      if (use_tile) {
+        for (int i = t; i < T * T; i += kDoeThreads) tile[i] = {Tf(0), Tf(0)};
+        __syncthreads();
+      }
+      for (int smp = t; smp < P * P; smp += kDoeThreads) {
+        const int m = smp % P, n = smp / P;
+        const C2<Tf> gu = buf[n * SM + m];
+        const double sm = (m - (P - 1) * 0.5) * cfg.pitch;
+        const double sn = (n - (P - 1) * 0.5) * cfg.pitch;
+        const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
+        const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
+        const double fx = (qx - cfg.x0) * cfg.inv_pitch, fy = (qy - cfg.y0) * cfg.inv_pitch;
+        const double flx = floor(fx), fly = floor(fy);
+        const int ix = (int)flx, iy = (int)fly;
+        const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int x = ix + dx, y = iy + dy;
+            if (!(x >= 0 && x < W && y >= 0 && y < H)) continue;
+            const Tf wgt = (dx ? wx : Tf(1) - wx) * (dy ? wy : Tf(1) - wy);
+            const C2<Tf> v = gu * wgt;
+            const int lx = x - tx0, ly = y - ty0;
+            if (use_tile && lx >= 0 && lx < T && ly >= 0 && ly < T) {
+              atomicAdd(&tile[ly * T + lx].re, v.re);
+              atomicAdd(&tile[ly * T + lx].im, v.im);
+            } else {
+              atomicAdd(&gt[(size_t)y * W + x].re, (Tg)v.re);
+              atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
+            }
+          }
+        }
+      }
+      if (use_tile) {
+        __syncthreads();
+        const int lx0 = tx0 - ax0, ly0 = ty0 - ay0;
+        const bool inside = lx0 >= 0 && ly0 >= 0 && lx0 + T <= AS && ly0 + T <= AS;
+        if (inside && t == 0) {
+          atomicMin(&s_box[0], lx0); atomicMin(&s_box[1], ly0);
+          atomicMax(&s_box[2], lx0 + T); atomicMax(&s_box[3], ly0 + T);
+        }
+        for (int i = t; i < T * T; i += kDoeThreads) {
+          const C2<Tf> v = tile[i];
+          if (v.re == Tf(0) && v.im == Tf(0)) continue;
+          const int x = tx0 + i % T, y = ty0 + i / T;
+          if (x < 0 || x >= W || y < 0 || y >= H) continue;
+          if (inside) {
+            C2<Tg>& d = accm[(size_t)(ly0 + i / T) * AS + lx0 + i % T];
+            d.re += (Tg)v.re;
+            d.im += (Tg)v.im;
+          } else {
+            atomicAdd(&gt[(size_t)y * W + x].re, (Tg)v.re);
+            atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
+          }
+        }
+      }
+      }
+      if (a.want_lens) {
+        double v[7] = {acc.gp[0] + gpx, acc.gp[1] + gpy, acc.gp[2], acc.gkin[0], acc.gkin[1],
+                       acc.gopl, acc.gzs};
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+        if ((t & 63) == 0)
+          for (int q = 0; q < 7; ++q) s.acc[t >> 6][q] = v[q];
+        __syncthreads();
+        if (t == 0) {
+          double r[7];
+          for (int q = 0; q < 7; ++q) {
+            r[q] = 0.0;
+            for (int wv = 0; wv < kDoeThreads / 64; ++wv) r[q] += s.acc[wv][q];
+          }
+          const DevPair& pr = a.pairs[c.pair];
+          const double f = c.k0 * pr.n_med[cfg.s_doe];
+          const size_t n = a.n_total;
+          a.raygrad[0 * n + gid] = r[0];
+          a.raygrad[1 * n + gid] = r[1];
+          a.raygrad[2 * n + gid] = r[2];
+          for (int i = 0; i < 3; ++i)
+            a.raygrad[(3 + i) * n + gid] = f * (r[3] * c.u[i] + r[4] * c.v[i]);
+          a.raygrad[6 * n + gid] = r[5];
+          a.raygrad[7 * n + gid] = r[6];
+        }
+      }
+      __syncthreads();   // buf, tile and pref are reused by the next ray
+    }
+    // flush the accumulator over the touched box, clearing it for the next block
+    const int bx0 = s_box[0], by0 = s_box[1], bx1 = s_box[2], by1 = s_box[3];
+    if (bx0 < bx1 && by0 < by1) {
+      const int bw = bx1 - bx0, bh = by1 - by0;
+      for (int i = t; i < bw * bh; i += kDoeThreads) {
+        const int lx = bx0 + i % bw, ly = by0 + i / bw;
+        C2<Tg>& d = accm[(size_t)ly * AS + lx];
+        const C2<Tg> v = d;
+        if (v.re == Tg(0) && v.im == Tg(0)) continue;
+        d = {Tg(0), Tg(0)};
+        const int x = ax0 + lx, y = ay0 + ly;
+        atomicAdd(&gt[(size_t)y * W + x].re, v.re);
+        atomicAdd(&gt[(size_t)y * W + x].im, v.im);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace rw

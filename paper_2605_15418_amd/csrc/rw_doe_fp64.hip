@@ -1,0 +1,32 @@
+// Ray-wave interface kernels of the FP64 form.
+#include "rw_doe.h"
+#include "rw_launch.h"
+
+namespace rw {
+
+template <int M, bool LDS>
+static void go(bool fwd, const DoeArgs& a, const RayBlockIter& it, long long n, int pair0,
+               int blocks, hipStream_t st) {
+  if (fwd)
+    hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS>), dim3(blocks), dim3(kDoeThreads), 0, st, a, it,
+                       n, pair0);
+  else
+    hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS>), dim3(blocks), dim3(kDoeThreads), 0, st, a, it,
+                       n, pair0);
+}
+
+hipError_t launch_doe_fp64(bool fwd, int M, bool lds, const DoeArgs& a, const RayBlockIter& it,
+                          long long n_items, int pair0, int blocks, hipStream_t st,
+                          bool* supported) {
+  *supported = true;
+  switch (M) {
+    case 16: go<16, true>(fwd, a, it, n_items, pair0, blocks, st); break;
+    case 32: go<32, true>(fwd, a, it, n_items, pair0, blocks, st); break;
+    case 64: go<64, true>(fwd, a, it, n_items, pair0, blocks, st); break;
+    case 128: go<128, false>(fwd, a, it, n_items, pair0, blocks, st); break;
+    default: *supported = false; return hipSuccess;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rw

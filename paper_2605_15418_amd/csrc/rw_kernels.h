@@ -4,11 +4,9 @@
 //   k_tmap       complex transmission t = A exp(i phi) of the DOE map
 //   k_trace      launch + conventional refractive trace to the DOE, with
 //                per-surface checkpoints of the ray state (one thread per ray)
-//   k_doe_fwd    ray-wave interface, one workgroup per incident ray: tangent
-//                frame, bilinear patch gather, zero-padded 2-D FFT in LDS,
-//                propagating cut, CDF, Philox draws, Eq. 1 weights, secondary
-//                trace to the sensor, Eq. 2 wavelets spread onto an oversampled
-//                grid (type-1 NUFFT with an exponential-of-semicircle kernel)
+//   (the ray-wave interface kernels live in rw_doe.h)
+//   k_rec_hist / k_rec_scan / k_rec_scatter / k_spread_tiles   binned type-1
+//                NUFFT spreading of the Eq. 2 wavelets onto the 2x grid
 //   k_grid_rows / k_grid_cols   grid FFT, deconvolution, crop, |U|^2
 //   k_loss_pairs / k_loss_total Eq. 3 with the closed-form alpha per PSF
 #pragma once
@@ -25,7 +23,9 @@ struct PrecFP32 { using Tt = float; using Tf = float; using Tp = float; using Tg
 
 struct DevCfg {
   int n_surf, s_doe, n_pairs, n_field, R, R2, P, M, N, Q, nf, w, sampling, H, W, n_params;
+  int planar;              // DOE surface is a plane z = const: u = x, v = y, n = z
   double pitch, x0, y0, launch_z, launch_half, psf_pitch, beta;
+  double inv_pitch;
   uint32_t key0, key1;
 };
 
@@ -89,7 +89,7 @@ __device__ __forceinline__ int block_max_int(int v, int* s_tmp /*[4]*/) {
 }
 
 // -------------------------------------------------------------- k_params ---
-__global__ void k_params(const DevCfg* cfg, const DevSurf* base, double base_sensor_z,
+static __global__ void k_params(const DevCfg* cfg, const DevSurf* base, double base_sensor_z,
                          const DevParam* prm, const float* values, DevLive* live) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int S = cfg->n_surf;
@@ -215,6 +215,8 @@ struct DoeArgs {
   void* gt;                  // C2<Tg> [H][W] cogradient of t
   double* raygrad;           // [8][n_total] cogradients of the incident state
   int want_lens;
+  void* acc;                 // C2<Tg> [blocks][acc_side][acc_side] block-private dL/dt
+  int acc_side;
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
@@ -283,52 +285,6 @@ __device__ __forceinline__ C2<Tf> patch_sample(const DevCfg& cfg, const RayCtx& 
     }
   }
   return acc;
-}
-
-// Patch -> zero-padded M x M spectrum in buf (natural FFT order, row stride M + 1).
-template <class Tf, int M>
-__device__ __forceinline__ void patch_spectrum(const DevCfg& cfg, const RayCtx& c,
-                                               const C2<Tf>* tm, C2<Tf>* buf,
-                                               const C2<Tf>* tw) {
-  constexpr int L = 4, E = M / L, SM = M + 1;
-  const int g = threadIdx.x >> 2, gl = threadIdx.x & 3;
-  const int br = bitrev(gl, 2);
-  const int P = cfg.P;
-  for (int row = g; row < P; row += kThreads / L) {
-    C2<Tf> x[E];
-#pragma unroll
-    for (int n2 = 0; n2 < E; ++n2) {
-      const int m = gl + L * n2;
-      x[n2] = m < P ? patch_sample<Tf>(cfg, c, tm, m, row) : C2<Tf>{Tf(0), Tf(0)};
-    }
-    group_fft<Tf, L, E, -1>(x, gl, tw);
-#pragma unroll
-    for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
-  }
-  __syncthreads();
-  for (int col = g; col < M; col += kThreads / L) {
-    C2<Tf> x[E];
-#pragma unroll
-    for (int n2 = 0; n2 < E; ++n2) {
-      const int n = gl + L * n2;
-      x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
-    }
-    group_fft<Tf, L, E, -1>(x, gl, tw);
-#pragma unroll
-    for (int k2 = 0; k2 < E; ++k2) buf[(E * br + k2) * SM + col] = x[k2];
-  }
-  __syncthreads();
-}
-
-// Weight of shifted bin L for the sampling density (0 when evanescent).
-template <class Tf, int M>
-__device__ __forceinline__ double bin_weight(const RayCtx& c, const C2<Tf>* buf, int L, int sampling) {
-  constexpr int SM = M + 1;
-  const int jy = L / M - M / 2, jx = L % M - M / 2;
-  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
-  if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out)) return 0.0;
-  if (sampling != 0) return 1.0;
-  return (double)cabs_rn(buf[(jy & (M - 1)) * SM + (jx & (M - 1))]);
 }
 
 // Exponential-of-semicircle spreading kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)).
@@ -462,138 +418,6 @@ __device__ __forceinline__ C2<Tf> centre_ref(int jx, int jy, int P, int M) {
   return {c, s};
 }
 
-template <class Prec, int M, bool kLDS>
-__global__ __launch_bounds__(kThreads) void k_doe_fwd(DoeArgs a) {
-  using Tf = typename Prec::Tf;
-  using Tg = typename Prec::Tg;
-  using Tp = typename Prec::Tp;
-  constexpr int SM = M + 1;
-  constexpr int C = (M * M) / kThreads;
-  static_assert(C >= 1, "patch spectrum must have at least one bin per thread");
-  __shared__ C2<Tf> s_buf[kLDS ? M * SM : 1];
-  __shared__ C2<Tf> s_tw[M];
-  __shared__ double s_pref[kThreads];
-  __shared__ double s_red[4];
-  __shared__ int s_redi[4];
-  const DevCfg& cfg = *a.cfg;
-  C2<Tf>* buf = kLDS ? s_buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
-  const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
-  for (int i = threadIdx.x; i < M; i += kThreads) s_tw[i] = ((const C2<Tf>*)a.tw)[i];
-  __syncthreads();
-  const int N = cfg.N, P = cfg.P, t = threadIdx.x;
-  const int emit = a.emit;
-  const double inv_m2 = 1.0 / ((double)M * M);
-  unsigned long long n_sec = 0, n_alive = 0;
-  for (size_t wi = blockIdx.x; wi < a.nray; wi += gridDim.x) {
-    const size_t gid = a.ray0 + wi;
-    const size_t slot0 = wi * (size_t)emit;        // records of this launch start at 0
-    const bool alive = a.st[7 * a.n_total + gid] != 0.0;
-    if (!alive) {
-      for (int i = t; i < emit; i += kThreads) put_zero<Tg>(a, slot0 + i);
-      if (a.idx_out && cfg.sampling != 2)
-        for (int i = t; i < N; i += kThreads) a.idx_out[gid * N + i] = -1;
-      continue;
-    }
-    n_alive += (t == 0);
-    RayCtx c;
-    make_ctx(a, gid, c);
-    patch_spectrum<Tf, M>(cfg, c, tm, buf, s_tw);
-    if (cfg.sampling == 2) {
-      // FULL: every propagating bin once, weight U~ / M^2; slot = shifted bin index.
-      for (int q = 0; q < C; ++q) {
-        const int L = t * C + q;
-        const int jy = L / M - M / 2, jx = L % M - M / 2;
-        const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
-        Tp phi0, wx, wy; double dza; Secondary sec;
-        if (!(Ku * Ku + Kv * Kv < c.k_out * c.k_out) ||
-            !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
-          put_zero<Tg>(a, slot0 + L);
-          continue;
-        }
-        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
-        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-        const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
-        const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
-        put_record<Prec>(a, slot0 + L, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
-        ++n_sec;
-      }
-      __syncthreads();
-      continue;
-    }
-    // Sampling density and its CDF (chunks of C consecutive shifted bins per thread).
-    double acc = 0.0;
-    int lastpos = -1;
-    for (int q = 0; q < C; ++q) {
-      const int L = t * C + q;
-      const double wgt = bin_weight<Tf, M>(c, buf, L, cfg.sampling);
-      acc += wgt;
-      if (wgt > 0.0) lastpos = L;
-    }
-    double excl;
-    const double S = block_exclusive_scan(acc, s_red, excl);
-    s_pref[t] = excl;
-    const int lastpos_all = block_max_int(lastpos, s_redi);   // also a barrier for s_pref
-    const double scale = S * inv_m2 / N;                     // S or |Pi| over M^2 N
-    for (int i = t; i < N; i += kThreads) {
-      int J = -1;
-      if (S > 0.0) {
-        if (a.replay) {
-          J = a.replay[gid * N + i];
-        } else {
-          const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
-                                        (uint32_t)c.pair, 0u) * S;
-          int lo = 0, hi = kThreads - 1;       // last chunk with prefix <= T
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_pref[mid] <= T) lo = mid; else hi = mid - 1;
-          }
-          double run = s_pref[lo];
-          int lp = -1;
-          for (int q = 0; q < C; ++q) {
-            const int L = lo * C + q;
-            const double wgt = bin_weight<Tf, M>(c, buf, L, cfg.sampling);
-            run += wgt;
-            if (wgt > 0.0) lp = L;
-            if (run > T) { J = L; break; }
-          }
-          if (J < 0) J = lp >= 0 ? lp : lastpos_all;
-        }
-      }
-      if (a.idx_out) a.idx_out[gid * N + i] = J;
-      bool ok = J >= 0;
-      C2<Tp> w = {Tp(0), Tp(0)};
-      int jx = 0, jy = 0;
-      if (ok) {
-        jy = J / M - M / 2; jx = J % M - M / 2;
-        const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
-        const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-        if (cfg.sampling == 0) {
-          const Tf mag = cabs_rn(X);
-          ok = mag > Tf(0);
-          const Tp f = ok ? (Tp)(scale / (double)mag) : Tp(0);
-          w = {(Tp)U.re * f, (Tp)U.im * f};
-        } else {
-          w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
-        }
-      }
-      Tp phi0, wx, wy; double dza; Secondary sec;
-      if (ok) ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
-      if (!ok) {
-        put_zero<Tg>(a, slot0 + i);
-        continue;
-      }
-      const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
-      put_record<Prec>(a, slot0 + i, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
-      ++n_sec;
-    }
-    __syncthreads();   // buf is reused by the next ray
-  }
-  if (a.stats) {
-    if (n_alive) atomicAdd(&a.stats[0], n_alive);
-    if (n_sec) atomicAdd(&a.stats[1], n_sec);
-  }
-}
-
 // ------------------------------------------------------- binned spreading ---
 // Records are binned by (pair, BIN x BIN cells of the oversampled grid); one
 // workgroup per TILE x TILE cells (TILE = 4 BIN) gathers the records of its own
@@ -636,7 +460,7 @@ __global__ __launch_bounds__(256) void k_rec_hist(const void* rec_pos, const voi
 }
 
 // Exclusive scan of the bin counts (one workgroup); cursors start at the offsets.
-__global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* counts, size_t n,
+static __global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* counts, size_t n,
                                                    unsigned long long* offsets,
                                                    unsigned long long* cursor) {
   __shared__ unsigned long long s_w[16];
@@ -711,54 +535,105 @@ __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const 
   }
 }
 
-template <class Tg>
+// Spreading of one tile.  Each of the 4 waves owns a horizontal strip of the
+// tile (tile / 4 rows) that no other wave writes.  Every wave loads 64 records
+// at once (one per lane), keeps those whose footprint meets its strip, then
+// walks them: each record is broadcast with readlane and its taps are added by
+// one lane each with a plain LDS read-modify-write (the taps of one record are
+// distinct cells), so no atomics are needed.
+__device__ __forceinline__ int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ float bcast_f(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double bcast_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float bcast_v(float v, int lane) { return bcast_f(v, lane); }
+__device__ __forceinline__ double bcast_v(double v, int lane) { return bcast_d(v, lane); }
+
+template <class Tg, int w>
 __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
                                                       const unsigned long long* offsets,
-                                                      BinGeom g, int w, double beta, int pair0,
+                                                      BinGeom g, double beta, int pair0,
                                                       C2<Tg>* grid) {
   using U = typename RecPos<Tg>::T;
   extern __shared__ unsigned char s_raw[];
-  C2<Tg>* acc = (C2<Tg>*)s_raw;
   const int tile = 4 * g.bin;                 // cells per tile side
+  const int ts = tile + 1;                    // padded row stride
+  C2<Tg>* acc = (C2<Tg>*)s_raw;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nwaves = blockDim.x >> 6;
   const int ntx = g.nf / tile;
   const int pair = pair0 + blockIdx.y;
   const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
   const int x0 = tx * tile, y0 = ty * tile;
-  for (int i = threadIdx.x; i < tile * tile; i += blockDim.x) acc[i] = {Tg(0), Tg(0)};
-  __syncthreads();
+  for (int i = threadIdx.x; i < tile * ts; i += blockDim.x) acc[i] = {Tg(0), Tg(0)};
   const U* pos = (const U*)srt_pos;
   const C2<Tg>* val = (const C2<Tg>*)srt_val;
   const unsigned long long* off = offsets + (size_t)pair * g.keys;
-  const double two_w = 2.0 / w;
-  // own 4 x 4 bins plus a one-bin margin (periodic; at least 8 bins per axis,
-  // so the 6 x 6 neighbourhood never repeats a bin)
-  for (int by = -1; by <= 4; ++by) {
-    const int bny = (ty * 4 + by + g.nb) % g.nb;
-    for (int bx = -1; bx <= 4; ++bx) {
-      const int bnx = (tx * 4 + bx + g.nb) % g.nb;
-      const int k = bny * g.nb + bnx;
-      const unsigned long long r0 = off[k], r1 = off[k + 1];
-      for (unsigned long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
-        const C2<Tg> v = val[r];
-        const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
-        Tg kx[16];
-        int ix[16];
-        for (int i = 0; i < w; ++i) {
-          const int cx = ((lx0 + i) & (g.nf - 1)) - x0;
-          ix[i] = (cx >= 0 && cx < tile) ? cx : -1;
-          kx[i] = ix[i] >= 0 ? es_kernel<Tg>((Tg)((double)(lx0 + i) - gx), (Tg)two_w, (Tg)beta)
-                             : Tg(0);
-        }
-        for (int j = 0; j < w; ++j) {
-          const int cy = ((ly0 + j) & (g.nf - 1)) - y0;
-          if (cy < 0 || cy >= tile) continue;
-          const Tg ky = es_kernel<Tg>((Tg)((double)(ly0 + j) - gy), (Tg)two_w, (Tg)beta);
-          const C2<Tg> vy = v * ky;
-          for (int i = 0; i < w; ++i) {
-            if (ix[i] < 0) continue;
-            atomicAdd(&acc[cy * tile + ix[i]].re, vy.re * kx[i]);
-            atomicAdd(&acc[cy * tile + ix[i]].im, vy.im * kx[i]);
+  __shared__ unsigned long long s_beg[36], s_pre[37];
+  if (threadIdx.x < 36) {
+    const int by = (int)threadIdx.x / 6 - 1, bx = (int)threadIdx.x % 6 - 1;
+    const int bny = (ty * 4 + by + g.nb) % g.nb, bnx = (tx * 4 + bx + g.nb) % g.nb;
+    const int k = bny * g.nb + bnx;
+    s_beg[threadIdx.x] = off[k];
+    s_pre[threadIdx.x + 1] = off[k + 1] - off[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pre[0] = 0;
+    for (int i = 1; i <= 36; ++i) s_pre[i] += s_pre[i - 1];
+  }
+  __syncthreads();
+  const Tg two_w = Tg(2.0 / w), bet = (Tg)beta;
+  const unsigned long long ntot = s_pre[36];
+  const int strip = tile / nwaves;                // rows owned by this wave
+  const int sy0 = wave * strip;
+  const int ti = lane % w, tj = lane / w;          // this lane's tap (w * w <= 64 for w <= 8)
+  int bin = 0;                                     // monotonic per lane across batches
+  for (unsigned long long base = 0; base < ntot; base += 64) {
+    const unsigned long long j = base + lane;
+    int lx0 = 0, ly0 = 0;
+    double fx = 0.0, fy = 0.0;
+    C2<Tg> v = {Tg(0), Tg(0)};
+    bool hit = false;
+    if (j < ntot) {
+      while (j >= s_pre[bin + 1]) ++bin;
+      const unsigned long long r = s_beg[bin] + (j - s_pre[bin]);
+      const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+      lx0 = (int)ceil(gx - 0.5 * w);
+      ly0 = (int)ceil(gy - 0.5 * w);
+      fx = gx - lx0;
+      fy = gy - ly0;
+      // footprint vs tile columns and vs this wave's strip rows (periodic)
+      const int cx0 = ((lx0 - x0) % g.nf + g.nf) % g.nf;
+      const int cy0 = ((ly0 - y0 - sy0) % g.nf + g.nf) % g.nf;
+      hit = (cx0 < tile || cx0 + w > g.nf) && (cy0 < strip || cy0 + w > g.nf);
+      if (hit) v = val[r];
+    }
+    unsigned long long mask = __ballot(hit);
+    while (mask) {
+      const int k = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const int blx = bcast_i(lx0, k), bly = bcast_i(ly0, k);
+      const double bfx = bcast_d(fx, k), bfy = bcast_d(fy, k);
+      const Tg vr = bcast_v(v.re, k), vi = bcast_v(v.im, k);
+#pragma unroll
+      for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
+        const int tap = tap0 + lane;
+        const int i = tap0 == 0 ? ti : tap % w, jj = tap0 == 0 ? tj : tap / w;
+        if (tap < w * w) {
+          const int cx = ((blx + i) & (g.nf - 1)) - x0;
+          const int cy = ((bly + jj) & (g.nf - 1)) - y0;
+          if (cx >= 0 && cx < tile && cy >= sy0 && cy < sy0 + strip) {
+            const Tg kk = es_kernel<Tg>((Tg)((double)i - bfx), two_w, bet) *
+                          es_kernel<Tg>((Tg)((double)jj - bfy), two_w, bet);
+            C2<Tg>& d = acc[cy * ts + cx];
+            d.re += vr * kk;
+            d.im += vi * kk;
           }
         }
       }
@@ -766,8 +641,10 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   }
   __syncthreads();
   C2<Tg>* gp = grid + (size_t)pair * g.nf * g.nf;
-  for (int i = threadIdx.x; i < tile * tile; i += blockDim.x)
-    gp[(size_t)(y0 + i / tile) * g.nf + x0 + i % tile] = acc[i];
+  for (int i = threadIdx.x; i < tile * tile; i += blockDim.x) {
+    const int cy = i / tile, cx = i % tile;
+    gp[(size_t)(y0 + cy) * g.nf + x0 + cx] = acc[cy * ts + cx];
+  }
 }
 
 // ------------------------------------------------------------- grid FFT ---
@@ -829,7 +706,7 @@ __global__ __launch_bounds__(256) void k_grid_cols_fwd(const C2<Tg>* t1, const C
 }
 
 // Component-major ray state [8][n] -> ray-major [n][8].
-__global__ void k_export_state(const double* st, size_t n, double* out) {
+static __global__ void k_export_state(const double* st, size_t n, double* out) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 8 * n) return;
   const size_t ray = i / 8, c = i % 8;
@@ -838,7 +715,7 @@ __global__ void k_export_state(const double* st, size_t n, double* out) {
 
 // ------------------------------------------------------------------ loss ---
 // Per pair: alpha = <I,T>/<I,I>, L_p = ||alpha I - T||^2 (Eq. 3, closed-form alpha).
-__global__ __launch_bounds__(256) void k_loss_pairs(const float* psf, const float* target,
+static __global__ __launch_bounds__(256) void k_loss_pairs(const float* psf, const float* target,
                                                     int Q2, int pair0, double* alpha,
                                                     double* lossp) {
   __shared__ double s_red[4];
@@ -862,7 +739,7 @@ __global__ __launch_bounds__(256) void k_loss_pairs(const float* psf, const floa
   if (threadIdx.x == 0) { alpha[pair] = al; lossp[pair] = l; }
 }
 
-__global__ void k_loss_total(const double* lossp, int n_pairs, float* loss_out) {
+static __global__ void k_loss_total(const double* lossp, int n_pairs, float* loss_out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double s = 0;
     for (int i = 0; i < n_pairs; ++i) s += lossp[i];
