@@ -5,7 +5,7 @@ Workload (synthetic, seeded): equiconvex BK7 even-asphere singlet (f = 25 mm,
 random A4/A6) followed by a planar 1024 x 1024 random holographic complex DOE
 at 1 um pitch; 3 wavelengths x 3 x 3 field angles (+-10 deg) x 256 x 256
 incident rays per pair; 64 x 64 DOE patches zero-padded to 128 x 128; 256
-secondary rays per incident ray (p ~ |U~|); 512 x 512 PSF per pair; Eq. 3
+secondary rays per incident ray (p ~ |U~|); 512 x 512 PSF per pair; Eq. 5
 loss against seeded Airy targets; gradients w.r.t. the 1024 x 1024 phase and
 amplitude maps and 6 lens parameters.
 
@@ -187,13 +187,13 @@ def main():
         vd = torch.tensor(vals.cpu().numpy().astype(np.float64), requires_grad=True)
         r = O.pair_forward(system, cfg, O.transmission(phd, amd), l_idx, f_idx, vd,
                            ray_subset=subset)
-        loss = O.eq3_loss(r["psf"], torch.tensor(maps["target"][l_idx, f_idx], dtype=torch.float64))
+        loss = O.eq5_loss(r["psf"], torch.tensor(maps["target"][l_idx, f_idx], dtype=torch.float64))
         loss.backward()
         t1 = time.perf_counter()
         cpu = {"value": len(subset) / (t1 - t0), "unit": "rays/s", "cores": nthreads,
                "kind": "oracle",
                "sample": f"1 pair (587.6 nm, on axis) x {len(subset)} central rays of {R * R}, "
-                         f"full P/M/N/Q, forward + Eq. 3 loss + autograd backward, "
+                         f"full P/M/N/Q, forward + Eq. 5 loss + autograd backward, "
                          f"{t1 - t0:.1f} s"}
         log(f"CPU oracle: {cpu['value']:.2f} rays/s on {nthreads} threads")
 
@@ -212,7 +212,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "asphere singlet f=25 mm + 1024^2 random complex DOE @1 um; "
                                "3 lambda x 3x3 fields (+-10 deg) x 256^2 rays; P=64 (M=128), "
-                               "N=256 (p_mag), Q=512; Eq. 3 loss; fwd+bwd (G1)",
+                               "N=256 (p_mag), Q=512; Eq. 5 loss; fwd+bwd (G1)",
                    "form": "batched MIXED (FP32 FFT/grids, FP64 trace and phases)",
                    "incident_rays_per_step": n_rays,
                    "secondary_rays_per_step": records,

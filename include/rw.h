@@ -13,7 +13,7 @@
  *   in the patch-size study) -> Monte Carlo secondary wavevectors with the
  *   weights of Eq. 1 drawn from p ~ |U~| or uniform (sampling-density study,
  *   Fig. 3; reparameterised sampling, Fig. 1c) -> conventional trace to the
- *   sensor -> coherent wavelet sum of Eq. 2 -> |U|^2 -> loss of Eq. 3.
+ *   sensor -> coherent wavelet sum of Eq. 2 -> |U|^2 -> loss of Eq. 5.
  *
  * Conventions for every entry point:
  *  - Lengths are millimetres, wavelengths millimetres.
@@ -146,7 +146,7 @@ rw_status rw_plan_workspace_bytes(const rw_plan* plan, size_t* bytes);
 /* Forward pass.
  *  lens_params [n_params] float  normalised lens parameters (may be NULL if n_params = 0)
  *  doe_phase, doe_amp [H][W] float
- *  target [L][F][Q][Q] float or NULL: if given, the loss of Eq. 3 (sum over pairs of
+ *  target [L][F][Q][Q] float or NULL: if given, the loss of Eq. 5 (sum over pairs of
  *         ||alpha* I - T||^2 with alpha* = <I,T>/<I,I>) is written to loss_out[0]
  *         and kept for rw_backward; the target must stay valid until then.
  *  psf_out [L][F][Q][Q] float (written)
@@ -161,7 +161,7 @@ rw_status rw_forward(rw_plan* plan, const float* lens_params, const float* doe_p
 
 /* Backward pass (adjoint G1: the a.e. derivative with the sample indices of the
  * preceding forward held fixed).
- *  dL_dpsf [L][F][Q][Q] float, or NULL to differentiate the Eq. 3 loss of the forward
+ *  dL_dpsf [L][F][Q][Q] float, or NULL to differentiate the Eq. 5 loss of the forward
  *  d_phase, d_amp [H][W] float (overwritten), d_lens [n_params] float (overwritten, may be
  *  NULL if n_params = 0).
  * Must follow rw_forward on the same plan and workspace.

@@ -16,12 +16,12 @@ listed together in the design notes of the repository.
 Units: lengths in mm, wavelengths in mm, k0 = 2*pi/lambda in rad/mm.
 
 Pipeline for one (wavelength, field) pair  -- Results, "Ray-Wave Simulator
-Formalism", Fig. 1b/c, Eqs. 1-3:
+Formalism", Fig. 1b/c, Eqs. 1, 2 and 5:
   launch -> conventional refractive trace to the DOE -> tangent frame ->
   square patch of the complex transmission -> zero-padded FFT (angular
   spectrum) -> propagating-mode cut -> sampling density p -> N secondary
   wavevectors -> weights a = U~/p (Eq. 1) -> conventional trace to the sensor
-  -> coherent wavelet sum (Eq. 2) -> |U|^2 -> normalised least squares (Eq. 3).
+  -> coherent wavelet sum (Eq. 2) -> |U|^2 -> normalised least squares (Eq. 5).
 """
 import math
 
@@ -526,10 +526,10 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
 
 
 # ----------------------------------------------------------------------------
-# Whole stack, loss (Eq. 3) and gradients.
+# Whole stack, loss (Eq. 5) and gradients.
 # ----------------------------------------------------------------------------
-def eq3_loss(I, T):
-    """Normalised least squares of Eq. 3 with the closed-form optimal alpha
+def eq5_loss(I, T):
+    """Normalised least squares of Eq. 5 with the closed-form optimal alpha
     (READING: alpha* = <I,T>/<I,I> per PSF)."""
     ii = (I * I).sum()
     it = (I * T).sum()
@@ -560,7 +560,7 @@ def psf_stack(system, cfg, phase, amp, values=None, replays=None, pairs=None, ke
 
 
 def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_grad=True):
-    """Eq. 3 summed over all pairs and its gradient w.r.t. the DOE phase map,
+    """Eq. 5 summed over all pairs and its gradient w.r.t. the DOE phase map,
     the amplitude map and the normalised lens parameters (torch autograd in
     float64; frozen draws, i.e. the a.e. derivative with the index set fixed)."""
     L = len(cfg["lambdas"])
@@ -577,7 +577,7 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
             tmap = transmission(ph, am)
             rep = None if replays is None else replays.get(pr)
             r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=True)
-            Lp = eq3_loss(r["psf"], _t(target[l, f]))
+            Lp = eq5_loss(r["psf"], _t(target[l, f]))
             if want_grad:
                 Lp.backward()
             total += float(Lp.detach())
@@ -594,6 +594,7 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
 # Figures of merit (patch-size study).
 # ----------------------------------------------------------------------------
 def ncc(I, Igt):
+    """Normalised cross-correlation of Eq. 3 (patch-size study)."""
     I = np.asarray(I, dtype=np.float64)
     Igt = np.asarray(Igt, dtype=np.float64)
     return float((Igt * I).sum() / math.sqrt((Igt ** 2).sum() * (I ** 2).sum()))
@@ -605,8 +606,7 @@ def mse(I, Igt):
 
 def curvature_error_bound(D, R):
     """Upper bound of the curvature-induced angular-spectrum error for a flat
-    patch of side D on a surface of radius R (patch-size study, curvature
-    bound): eps <= arcsin(D / 2R)."""
+    patch of side D on a surface of radius R (Eq. 4): eps <= arcsin(D / 2R)."""
     return math.asin(D / (2.0 * R))
 
 

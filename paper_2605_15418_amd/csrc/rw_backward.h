@@ -1,7 +1,7 @@
 // Backward (adjoint G1) kernels of the ray-wave hybrid PSF: the a.e.
 // derivative of the forward with the drawn sample indices held fixed.
 //
-//   k_psf_cograd      dL/dI (Eq. 3 with closed-form alpha, or the caller's) ->
+//   k_psf_cograd      dL/dI (Eq. 5 with closed-form alpha, or the caller's) ->
 //                     cogradient of the kept modes 2 dI U / (Psi(kx) Psi(ky))
 //   k_grid_cols_bwd / k_grid_rows_bwd   adjoint of the grid FFT and crop:
 //                     B_l = sum_k exp(-2 pi i k.l / nf) G_k  (full nf x nf grid)

@@ -8,7 +8,7 @@
 //   k_rec_hist / k_rec_scan / k_rec_scatter / k_spread_tiles   binned type-1
 //                NUFFT spreading of the Eq. 2 wavelets onto the 2x grid
 //   k_grid_rows / k_grid_cols   grid FFT, deconvolution, crop, |U|^2
-//   k_loss_pairs / k_loss_total Eq. 3 with the closed-form alpha per PSF
+//   k_loss_pairs / k_loss_total Eq. 5 with the closed-form alpha per PSF
 #pragma once
 #include "rw_common.h"
 #include "rw_fft.h"
@@ -714,7 +714,7 @@ static __global__ void k_export_state(const double* st, size_t n, double* out) {
 }
 
 // ------------------------------------------------------------------ loss ---
-// Per pair: alpha = <I,T>/<I,I>, L_p = ||alpha I - T||^2 (Eq. 3, closed-form alpha).
+// Per pair: alpha = <I,T>/<I,I>, L_p = ||alpha I - T||^2 (Eq. 5, closed-form alpha).
 static __global__ __launch_bounds__(256) void k_loss_pairs(const float* psf, const float* target,
                                                     int Q2, int pair0, double* alpha,
                                                     double* lossp) {

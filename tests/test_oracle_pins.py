@@ -372,14 +372,14 @@ def test_mc_mean_converges_to_full_field_at_inverse_sqrt_n():
 
 
 # ------------------------------------------------------- loss and metrics ----
-def test_eq3_closed_form_alpha_is_optimal_and_envelope_gradient():
+def test_eq5_closed_form_alpha_is_optimal_and_envelope_gradient():
     rng = np.random.default_rng(10)
     I = torch.tensor(rng.uniform(size=(8, 8)), requires_grad=True)
     T = torch.tensor(rng.uniform(size=(8, 8)))
     from scipy.optimize import minimize_scalar
     f = lambda a: float(((a * I.detach() - T) ** 2).sum())
     a_num = minimize_scalar(f).x
-    L = O.eq3_loss(I, T)
+    L = O.eq5_loss(I, T)
     assert abs(L.item() - f(a_num)) < 1e-10
     L.backward()
     a = (I * T).sum().item() / (I * I).sum().item()

@@ -149,7 +149,7 @@ def singlet_zoneplate(rays_side=64, H=256, pitch=0.004, P=32, N=256, Q=128, psf_
 # stop).  Phase uniform on [0, 2 pi), amplitude uniform on [0.5, 1], both
 # band-limited to 0.25 cycles/pixel.  3 wavelengths (F, d, C lines), 3 x 3
 # fields up to +-10 deg, 256 x 256 rays per field, 64 x 64 patches, 512 x 512
-# PSF at 1 um.  Workload 3 adds Airy targets for Eq. 3 and six lens
+# PSF at 1 um.  Workload 3 adds Airy targets for Eq. 5 and six lens
 # parameters (2 curvatures, 4 asphere coefficients).
 # ----------------------------------------------------------------------------
 def asphere_hologram(rays_side=256, H=1024, pitch=0.001, P=64, N=256, Q=512, psf_pitch=0.001,
