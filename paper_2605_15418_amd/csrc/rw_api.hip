@@ -91,7 +91,7 @@ struct rw_plan {
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
-      off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, total;
+      off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -191,6 +191,8 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.raygrad = (double*)(b + pl->off_raygrad);
   a.acc = b + pl->off_acc;
   a.acc_side = pl->acc_side;
+  a.ctx = (RayCtx*)(b + pl->off_ctx);
+  a.dlist = b + pl->off_dlist;
   return a;
 }
 
@@ -583,6 +585,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_scratch =
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
+  pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
+  pl->off_dlist = take(cfg->sampling == RW_SAMPLE_FULL
+                           ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf);
   pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
   pl->off_raygrad = take(8 * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
@@ -673,6 +678,11 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
     HIPCHK(hipGetLastError());
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;
+    {
+      StageTimer tm_(pl, RW_STAGE_TRACE, st);
+      hipLaunchKernelGGL(k_ray_ctx, dim3(tb), dim3(256), 0, st, a);
+    }
+    HIPCHK(hipGetLastError());
     rw_status s;
     {
       StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);

@@ -26,6 +26,15 @@ namespace rw {
 
 constexpr int kDoeThreads = 512;
 
+// threadIdx.x behind an empty asm: index arithmetic derived from it is redone
+// where it is used instead of being hoisted out of the per-ray loops, which
+// would keep dozens of per-lane addresses live across the whole kernel.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <int M> struct DoeGeom {
   static constexpr int NT = kDoeThreads;
   static constexpr int Lraw = 2 * NT / M;
@@ -37,10 +46,37 @@ template <int M> struct DoeGeom {
   static constexpr int LB = Log2<L>::v;
 };
 
-// Propagating test of shifted bin (jx, jy): |k_in,t + kappa_j| < k_out (FP64).
+// Propagating test of shifted bin (jx, jy): |k_in,t + kappa_j| < k_out, in FP64
+// with every rounding explicit, so that all call sites take the same decision.
+// For fixed jx the result is monotone in |K_v|, hence an interval of jy.
 __device__ __forceinline__ bool propagating(const RayCtx& c, int jx, int jy) {
-  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
-  return Ku * Ku + Kv * Kv < c.k_out * c.k_out;
+  const double Ku = __dadd_rn(c.kin_u, __dmul_rn(c.dk, (double)jx));
+  const double Kv = __dadd_rn(c.kin_v, __dmul_rn(c.dk, (double)jy));
+  return __dadd_rn(__dmul_rn(Ku, Ku), __dmul_rn(Kv, Kv)) < c.k2out;
+}
+
+// Propagating rows of column jx: jy in [lo, hi] (empty when lo > hi).  The
+// closed-form ends are corrected with the exact predicate above.
+struct Span { int lo, hi; };
+__device__ __forceinline__ Span prop_span(const RayCtx& c, int jx, int M) {
+  const double Ku = __dadd_rn(c.kin_u, __dmul_rn(c.dk, (double)jx));
+  const double rem = __dsub_rn(c.k2out, __dmul_rn(Ku, Ku));
+  if (!(rem > 0.0)) return {1, 0};
+  const double r = sqrt(rem) / c.dk, mid = -c.kin_v / c.dk;
+  int lo = (int)fmax(ceil(mid - r), (double)(-M / 2));
+  int hi = (int)fmin(floor(mid + r), (double)(M / 2 - 1));
+  if (lo > hi) {                       // rounding may leave one bin between the ends
+    lo = (int)fmin(fmax(floor(mid), (double)(-M / 2)), (double)(M / 2 - 1));
+    hi = lo - 1;
+    if (propagating(c, jx, lo)) hi = lo;
+    else if (lo + 1 <= M / 2 - 1 && propagating(c, jx, lo + 1)) hi = ++lo;
+  }
+  while (lo <= hi && !propagating(c, jx, lo)) ++lo;
+  while (lo <= hi && !propagating(c, jx, hi)) --hi;
+  if (lo > hi) return {1, 0};
+  while (lo > -M / 2 && propagating(c, jx, lo - 1)) --lo;
+  while (hi < M / 2 - 1 && propagating(c, jx, hi + 1)) ++hi;
+  return {lo, hi};
 }
 
 // Map tile under the patch: TW x TW pixels from (tx0, ty0); zero outside the map.
@@ -55,7 +91,7 @@ __device__ __forceinline__ TileRef tile_of(const DevCfg& cfg, const RayCtx& c) {
 template <class Tf>
 __device__ __forceinline__ void stage_tile(const DevCfg& cfg, const TileRef& tr, const C2<Tf>* tm,
                                            C2<Tf>* tile) {
-  for (int i = threadIdx.x; i < tr.tw * tr.tw; i += kDoeThreads) {
+  for (int i = opaque_tid(); i < tr.tw * tr.tw; i += kDoeThreads) {
     const int y = tr.ty0 + i / tr.tw, x = tr.tx0 + i % tr.tw;
     tile[i] = (x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) ? tm[(size_t)y * cfg.W + x]
                                                            : C2<Tf>{Tf(0), Tf(0)};
@@ -113,6 +149,7 @@ template <class Tf, int M, bool kLDS> struct DoeLds {
   double red[16];
   int redi[16];
   double acc[8][16];
+  Span span[M];             // propagating rows of each shifted column
   RayCtx ctx;
 };
 
@@ -122,10 +159,12 @@ template <class Tf, int M, bool kLDS> struct DoeLds {
 template <class Tf, int M>
 __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
                                              const C2<Tf>* tm, C2<Tf>* buf, const C2<Tf>* tw,
-                                             double* chunk, int sampling, int* lastpos) {
+                                             double* chunk, Span* span, int sampling,
+                                             int* lastpos) {
   using Gm = DoeGeom<M>;
   constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
-  const int g = threadIdx.x / L, gl = threadIdx.x % L;
+  const int tid = opaque_tid();
+  const int g = tid / L, gl = tid % L;
   const int br = bitrev(gl, Gm::LB);
   const int P = cfg.P;
   // the map tile goes into rows P.. of buf, which the row pass leaves untouched
@@ -139,13 +178,13 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
     const Tf w00 = (Tf(1) - pp.wx) * (Tf(1) - pp.wy), w01 = pp.wx * (Tf(1) - pp.wy);
     const Tf w10 = (Tf(1) - pp.wx) * pp.wy, w11 = pp.wx * pp.wy;
-    for (int i = threadIdx.x; i < P * P; i += kDoeThreads) {
+    for (int i = tid; i < P * P; i += kDoeThreads) {
       const int m = i % P, n = i / P;
       const C2<Tf>* r0 = tile + (oy + n) * tr.tw + ox + m;
       buf[n * SM + m] = r0[0] * w00 + r0[1] * w01 + r0[tr.tw] * w10 + r0[tr.tw + 1] * w11;
     }
   } else {
-    for (int i = threadIdx.x; i < P * P; i += kDoeThreads) {
+    for (int i = tid; i < P * P; i += kDoeThreads) {
       const int m = i % P, n = i / P;
       buf[n * SM + m] = patch_sample_t<Tf>(cfg, c, tm, tile, tr, m, n);
     }
@@ -162,6 +201,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
   }
+  for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
   __syncthreads();
   int lp = -1;
   for (int col = g; col < M; col += G) {
@@ -177,6 +217,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     const int ky0 = E * br;
     const int jys0 = (ky0 + M / 2) & (M - 1);                  // shifted row of the first bin
     const int ch = ((jx + M / 2) * M + jys0) / E;              // chunk id (j_x-major)
+    const Span sp = span[jx + M / 2];
     double s = 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) {
@@ -184,7 +225,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
       const int jy = ky < M / 2 ? ky : ky - M;
       buf[ky * SM + col] = x[k2];
       double wgt = 0.0;
-      if (propagating(c, jx, jy)) wgt = sampling == 0 ? (double)cabs_rn(x[k2]) : 1.0;
+      if (jy >= sp.lo && jy <= sp.hi) wgt = sampling == 0 ? (double)cabs_rn(x[k2]) : 1.0;
       s += wgt;
       if (wgt > 0.0) lp = max(lp, (jx + M / 2) * M + (jy + M / 2));
     }
@@ -259,7 +300,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
 
 // Inverse-CDF draw: J = min{j : C_j > T} in j_x-major shifted order.
 template <class Tf, int M>
-__device__ __forceinline__ int draw_bin(const RayCtx& c, const C2<Tf>* buf, const double* pref,
+__device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, const Span* span,
                                         double T, int sampling, int lastpos_all) {
   using Gm = DoeGeom<M>;
   constexpr int E = Gm::E, SM = Gm::SM;
@@ -272,11 +313,12 @@ __device__ __forceinline__ int draw_bin(const RayCtx& c, const C2<Tf>* buf, cons
   const int base = lo * E;                       // linear bin of the chunk's first bin
   const int jx = base / M - M / 2;
   const int kx = jx & (M - 1);
+  const Span sp = span[jx + M / 2];
   int lp = -1;
   for (int q = 0; q < E; ++q) {
     const int jy = (base % M) + q - M / 2;
     double wgt = 0.0;
-    if (propagating(c, jx, jy))
+    if (jy >= sp.lo && jy <= sp.hi)
       wgt = sampling == 0 ? (double)cabs_rn(buf[(jy & (M - 1)) * SM + kx]) : 1.0;
     run += wgt;
     if (wgt > 0.0) lp = base + q;
@@ -330,16 +372,18 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
         continue;
       }
       n_alive += (t == 0);
-      if (t == 0) make_ctx(a, (size_t)gid, s.ctx);
+      load_ctx(a, (size_t)gid, s.ctx);
       __syncthreads();
       const RayCtx& c = s.ctx;
+      const int t = opaque_tid();
       int lp;
-      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, cfg.sampling, &lp);
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       if (cfg.sampling == 2) {
         for (int Lb = t; Lb < M * M; Lb += kDoeThreads) {
           const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
           Tp phi0, wx, wy; double dza; Secondary sec;
-          if (!propagating(c, jx, jy) ||
+          const Span sp = s.span[jx + M / 2];
+          if (jy < sp.lo || jy > sp.hi ||
               !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
             put_zero<Tg>(a, slot0 + Lb);
             continue;
@@ -365,7 +409,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           } else {
             const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
                                           (uint32_t)c.pair, 0u) * S;
-            J = draw_bin<Tf, M>(c, buf, s.pref, T, cfg.sampling, lastpos_all);
+            J = draw_bin<Tf, M>(buf, s.pref, s.span, T, cfg.sampling, lastpos_all);
           }
         }
         if (a.idx_out) a.idx_out[gid * N + i] = J;
@@ -405,19 +449,25 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
 }
 
 // ------------------------------------------------------------------ adjoint ---
-// Type-2 interpolation of the sensor-grid cogradient with the kernel derivative.
-template <class Prec>
-__device__ __forceinline__ void interp_adj2(const DevCfg& cfg, const C2<typename Prec::Tg>* B,
-                                            int pair, typename Prec::Tp gx, typename Prec::Tp gy,
-                                            C2<double>& g0, C2<double>& dx, C2<double>& dy) {
+// Type-2 interpolation of the sensor-grid cogradient B at one wavelet's grid
+// coordinate, with the ES-kernel derivative for the two frequencies.  Two
+// adjacent lanes share one wavelet: lane h takes the kernel rows j = h, h + 2,
+// ...; the partial sums are exchanged so both lanes return the totals.  Every
+// row loads WMAX cells unconditionally (indices wrap on the periodic grid) so
+// that the loads of all rows are in flight together.
+template <class Prec, int WMAX>
+__device__ __forceinline__ void interp_adj_pair(const DevCfg& cfg,
+                                                const C2<typename Prec::Tg>* B, int pair,
+                                                typename Prec::Tp gx, typename Prec::Tp gy, int h,
+                                                C2<double>& g0, C2<double>& dx, C2<double>& dy) {
   using Tg = typename Prec::Tg;
   using Tp = typename Prec::Tp;
   const int nf = cfg.nf, w = cfg.w;
   const int lx0 = (int)ceil(gx - (Tp)(0.5 * w)), ly0 = (int)ceil(gy - (Tp)(0.5 * w));
   const Tg tw = (Tg)(2.0 / w), beta = (Tg)cfg.beta;
-  Tg kx[16], dkx[16];
+  Tg kx[WMAX], dkx[WMAX];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < WMAX; ++i) {
     kx[i] = Tg(0); dkx[i] = Tg(0);
     if (i < w) {
       const Tg tx = (Tg)((double)((Tp)(lx0 + i) - gx)) * tw;
@@ -431,35 +481,52 @@ __device__ __forceinline__ void interp_adj2(const DevCfg& cfg, const C2<typename
   }
   g0 = {0, 0}; dx = {0, 0}; dy = {0, 0};
   const C2<Tg>* gp = B + (size_t)pair * nf * nf;
+  constexpr int RH = (WMAX + 1) / 2;                       // rows per lane
+  constexpr int RBr = 16 / WMAX / (int)(sizeof(Tg) / 4);     // rows loaded together
+  constexpr int RB = RBr < 1 ? 1 : (RBr > RH ? RH : RBr);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (j >= w) break;
-    const Tg ty = (Tg)((double)((Tp)(ly0 + j) - gy)) * tw;
-    const Tg ay = Tg(1) - ty * ty;
-    if (!(ay > Tg(0))) continue;
-    const Tg sy = sqrt(ay);
-    const Tg ky = (Tg)exp(beta * (sy - Tg(1)));
-    const Tg dky = -ky * beta * ty / sy * tw;
-    const C2<Tg>* row = gp + (size_t)((ly0 + j) & (nf - 1)) * nf;
-    Tg s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+  for (int r0 = 0; r0 < RH; r0 += RB) {
+    C2<Tg> v[RB][WMAX];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i < w) {
-        const C2<Tg> b = row[(lx0 + i) & (nf - 1)];
-        s0r += kx[i] * b.re; s0i += kx[i] * b.im;
-        s1r += dkx[i] * b.re; s1i += dkx[i] * b.im;
-      }
+    for (int r = 0; r < RB; ++r) {
+      const C2<Tg>* row = gp + (size_t)((ly0 + 2 * (r0 + r) + h) & (nf - 1)) * nf;
+#pragma unroll
+      for (int i = 0; i < WMAX; ++i) v[r][i] = row[(lx0 + i) & (nf - 1)];
     }
-    g0.re += (double)(ky * s0r); g0.im += (double)(ky * s0i);
-    dx.re += (double)(ky * s1r); dx.im += (double)(ky * s1i);
-    dy.re += (double)(dky * s0r); dy.im += (double)(dky * s0i);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int j = 2 * (r0 + r) + h;
+      const Tg ty = (Tg)((double)((Tp)(ly0 + j) - gy)) * tw;
+      const Tg ay = Tg(1) - ty * ty;
+      if (!(j < w && ay > Tg(0))) continue;
+      const Tg sy = sqrt(ay);
+      const Tg ky = (Tg)exp(beta * (sy - Tg(1)));
+      const Tg dky = -ky * beta * ty / sy * tw;
+      Tg s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+#pragma unroll
+      for (int i = 0; i < WMAX; ++i) {
+        s0r += kx[i] * v[r][i].re; s0i += kx[i] * v[r][i].im;
+        s1r += dkx[i] * v[r][i].re; s1i += dkx[i] * v[r][i].im;
+      }
+      g0.re += (double)(ky * s0r); g0.im += (double)(ky * s0i);
+      dx.re += (double)(ky * s1r); dx.im += (double)(ky * s1i);
+      dy.re += (double)(dky * s0r); dy.im += (double)(dky * s0i);
+    }
+    // keep the next group's loads from being scheduled above this point
+    __builtin_amdgcn_sched_barrier(0);
   }
+  g0.re += __shfl_xor(g0.re, 1, 64); g0.im += __shfl_xor(g0.im, 1, 64);
+  dx.re += __shfl_xor(dx.re, 1, 64); dx.im += __shfl_xor(dx.im, 1, 64);
+  dy.re += __shfl_xor(dy.re, 1, 64); dy.im += __shfl_xor(dy.im, 1, 64);
 }
 
+// Cogradients of one wavelet's inputs (its weight w, phase, grid frequencies and
+// obliquity) from the interpolated sensor-grid cogradient; called by both lanes
+// of a pair with identical arguments.
 template <class Prec>
-__device__ __forceinline__ bool wavelet_adjoint2(const DoeArgs& a, const RayCtx& c, int jx,
-                                                 int jy, C2<typename Prec::Tp> w, WaveletAdj& wa,
-                                                 Secondary& sec) {
+__device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const RayCtx& c, int jx,
+                                                     int jy, C2<typename Prec::Tp> w, int h,
+                                                     WaveletAdj& wa, Secondary& sec) {
   using Tp = typename Prec::Tp;
   using Tg = typename Prec::Tg;
   const DevCfg& cfg = *a.cfg;
@@ -469,8 +536,11 @@ __device__ __forceinline__ bool wavelet_adjoint2(const DoeArgs& a, const RayCtx&
   const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
   const C2<Tp> cv = (w * e) * (Tp)dza;
   C2<double> g0, dx, dy;
-  interp_adj2<Prec>(cfg, (const C2<Tg>*)a.adj, c.pair, grid_coord(wx, cfg.nf),
-                    grid_coord(wy, cfg.nf), g0, dx, dy);
+  const Tp gx = grid_coord(wx, cfg.nf), gy = grid_coord(wy, cfg.nf);
+  if (cfg.w <= 8)
+    interp_adj_pair<Prec, 8>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
+  else
+    interp_adj_pair<Prec, 16>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
   const C2<double> cd = {(double)cv.re, (double)cv.im};
   const double cell = cfg.nf / (2.0 * RW_PI);
   wa.g_wx = -(cd.re * dx.re + cd.im * dx.im) * cell;
@@ -482,6 +552,13 @@ __device__ __forceinline__ bool wavelet_adjoint2(const DoeArgs& a, const RayCtx&
   return true;
 }
 
+// Spectrum cogradient of one draw, kept in global memory between the draw pass
+// and the S-term pass (bin index k into the LDS spectrum, -1 for none).
+template <class Tf> struct DrawEnt {
+  C2<Tf> g;
+  int k;
+};
+
 template <class Prec, int M, bool kLDS>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
@@ -490,7 +567,6 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   using Tp = typename Prec::Tp;
   using Gm = DoeGeom<M>;
   constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
-  constexpr int DPT = (2048 + kDoeThreads - 1) / kDoeThreads;
   __shared__ DoeLds<Tf, M, kLDS> s;
   __shared__ int s_box[4];
   const DevCfg& cfg = *a.cfg;
@@ -503,7 +579,6 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
   const int N = cfg.N, P = cfg.P, t = threadIdx.x;
-  const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
   const int T = P + 4;                                  // bilinear tile side
@@ -527,68 +602,72 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
     for (int k = 0; k < itr.count(); ++k) {
       const long long gid = itr.ray(it, k, pair0);
       if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0) continue;
-      if (t == 0) make_ctx(a, (size_t)gid, s.ctx);
+      load_ctx(a, (size_t)gid, s.ctx);
       __syncthreads();
       const RayCtx& c = s.ctx;
+      const int t = opaque_tid();
+      const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
       int lp;
-      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, cfg.sampling, &lp);
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
       double dLdS = 0.0;
-      int kk[DPT];
-      C2<Tf> gX[DPT];
-#pragma unroll
-      for (int q = 0; q < DPT; ++q) kk[q] = -1;
+      const int h = t & 1;                  // lane pairs share one secondary ray
       if (cfg.sampling != 2) {
         const double S = chunk_scan<M>(s.pref, s.red);
         const int lastpos_all = block_max_i(lp, s.redi);
+        DrawEnt<Tf>* dl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
         if (S > 0.0) {
           const double scale = S * inv_m2 / N;
 #pragma unroll 1
-          for (int q = 0; q < DPT; ++q) {
-            const int i = t + q * kDoeThreads;
-            if (i >= N) break;
+          for (int i = t >> 1; i < N; i += kDoeThreads / 2) {
             int J;
             if (a.replay) {
               J = a.replay[gid * N + i];
             } else {
               const double Tv = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
                                              (uint32_t)c.pair, 0u) * S;
-              J = draw_bin<Tf, M>(c, buf, s.pref, Tv, cfg.sampling, lastpos_all);
+              J = draw_bin<Tf, M>(buf, s.pref, s.span, Tv, cfg.sampling, lastpos_all);
             }
-            if (J < 0) continue;
-            const int jx = J / M - M / 2, jy = J % M - M / 2;
-            const int kidx = (jy & (M - 1)) * SM + (jx & (M - 1));
-            const C2<Tf> X = buf[kidx];
-            const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
-            const C2<Tf> U = X * ref;
-            C2<Tp> w;
-            double mag = 0.0;
-            if (cfg.sampling == 0) {
-              const Tf m = cabs_rn(X);
-              if (!(m > Tf(0))) continue;
-              mag = (double)m;
-              const Tp f = (Tp)(scale / mag);
-              w = {(Tp)U.re * f, (Tp)U.im * f};
-            } else {
-              w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+            DrawEnt<Tf> ent = {{Tf(0), Tf(0)}, -1};
+            if (J >= 0) {
+              const int jx = J / M - M / 2, jy = J % M - M / 2;
+              const int kidx = (jy & (M - 1)) * SM + (jx & (M - 1));
+              const C2<Tf> X = buf[kidx];
+              const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
+              const C2<Tf> U = X * ref;
+              C2<Tp> w;
+              double mag = 0.0;
+              bool ok = true;
+              if (cfg.sampling == 0) {
+                const Tf m = cabs_rn(X);
+                ok = m > Tf(0);
+                mag = (double)m;
+                const Tp f = ok ? (Tp)(scale / mag) : Tp(0);
+                w = {(Tp)U.re * f, (Tp)U.im * f};
+              } else {
+                w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+              }
+              WaveletAdj wa;
+              Secondary sec;
+              if (ok) ok = wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, wa, sec);
+              if (ok) {
+                C2<double> gU;
+                if (cfg.sampling == 0) {
+                  const double hr = (double)U.re / mag, hi_ = (double)U.im / mag;
+                  if (h == 0) dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
+                  const double gr = wa.g_w.re * scale, gi = wa.g_w.im * scale;
+                  const double im = -(gr * hi_ - gi * hr) / mag;
+                  gU = {-im * hi_, im * hr};
+                } else {
+                  gU = {wa.g_w.re * scale, wa.g_w.im * scale};
+                }
+                const double rr = (double)ref.re, ri = (double)ref.im;
+                ent.k = kidx;
+                ent.g = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
+                if (a.want_lens && h == 1) incident_from_wavelet(a, c, sec, wa, acc);
+              }
             }
-            WaveletAdj wa;
-            Secondary sec;
-            if (!wavelet_adjoint2<Prec>(a, c, jx, jy, w, wa, sec)) continue;
-            C2<double> gU;
-            if (cfg.sampling == 0) {
-              const double hr = (double)U.re / mag, hi_ = (double)U.im / mag;
-              dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
-              const double gr = wa.g_w.re * scale, gi = wa.g_w.im * scale;
-              const double im = -(gr * hi_ - gi * hr) / mag;
-              gU = {-im * hi_, im * hr};
-            } else {
-              gU = {wa.g_w.re * scale, wa.g_w.im * scale};
-            }
-            const double rr = (double)ref.re, ri = (double)ref.im;
-            kk[q] = kidx;
-            gX[q] = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
-            if (a.want_lens) incident_from_wavelet(a, c, sec, wa, acc);
+            if (h == 0) dl[i] = ent;
           }
         }
         dLdS = block_sum_d(dLdS, s.red);     // orders every read of buf before the rewrite
@@ -596,9 +675,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         for (int idx = t; idx < M * M; idx += kDoeThreads) {
           const int ky = idx / M, kx = idx % M;
           const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+          const Span sp = s.span[jx + M / 2];
           C2<Tf>& X = buf[ky * SM + kx];
           C2<Tf> v = {Tf(0), Tf(0)};
-          if (cfg.sampling == 0 && propagating(c, jx, jy)) {
+          if (cfg.sampling == 0 && jy >= sp.lo && jy <= sp.hi) {
             const Tf m = cabs_rn(X);
             if (m > Tf(0)) {
               const Tf f = (Tf)dLdS / m;
@@ -608,33 +688,41 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           X = v;
         }
         __syncthreads();
+        // draw terms: each entry is re-read by the lane that wrote it
+        if (S > 0.0 && h == 0) {
 #pragma unroll 1
-        for (int q = 0; q < DPT; ++q) {
-          if (kk[q] >= 0) {
-            atomicAdd(&buf[kk[q]].re, gX[q].re);
-            atomicAdd(&buf[kk[q]].im, gX[q].im);
+          for (int i = t >> 1; i < N; i += kDoeThreads / 2) {
+            const DrawEnt<Tf> e = dl[i];
+            if (e.k >= 0) {
+              atomicAdd(&buf[e.k].re, e.g.re);
+              atomicAdd(&buf[e.k].im, e.g.im);
+            }
           }
         }
       } else {
-        for (int idx = t; idx < M * M; idx += kDoeThreads) {
+        // FULL: every bin once; a lane pair per bin (both lanes read the bin
+        // before the first of them writes it)
+#pragma unroll 1
+        for (int idx = t >> 1; idx < M * M; idx += kDoeThreads / 2) {
           const int ky = idx / M, kx = idx % M;
           const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+          const Span sp = s.span[jx + M / 2];
           C2<Tf> out = {Tf(0), Tf(0)};
-          if (propagating(c, jx, jy)) {
+          if (jy >= sp.lo && jy <= sp.hi) {
             const C2<Tf> X = buf[ky * SM + kx];
             const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
             const C2<Tf> U = X * ref;
             const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
             WaveletAdj wa;
             Secondary sec;
-            if (wavelet_adjoint2<Prec>(a, c, jx, jy, w, wa, sec)) {
+            if (wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, wa, sec)) {
               const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
               const double rr = (double)ref.re, ri = (double)ref.im;
               out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};
-              if (a.want_lens) incident_from_wavelet(a, c, sec, wa, acc);
+              if (a.want_lens && h == 1) incident_from_wavelet(a, c, sec, wa, acc);
             }
           }
-          buf[ky * SM + kx] = out;
+          if (h == 0) buf[ky * SM + kx] = out;
         }
       }
       __syncthreads();
@@ -681,18 +769,43 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         auto gu = [&](int n, int m) {
           return (m >= 0 && m < P && n >= 0 && n < P) ? buf[n * SM + m] : C2<Tf>{Tf(0), Tf(0)};
         };
-        for (int i = t; i < P1 * P1; i += kDoeThreads) {
+        auto pix = [&](int i, int& x, int& y) -> C2<Tf> {
           const int aa = i % P1, bb = i / P1;
-          const int x = pp.ix0 + aa, y = pp.iy0 + bb;
-          if (x < 0 || x >= W || y < 0 || y >= H) continue;
-          const C2<Tf> v = gu(bb, aa) * w00 + gu(bb, aa - 1) * w01 + gu(bb - 1, aa) * w10 +
-                           gu(bb - 1, aa - 1) * w11;
-          if (v.re == Tf(0) && v.im == Tf(0)) continue;
-          if (inside) {
-            C2<Tg>& d = accm[(size_t)(ly0 + bb) * AS + lx0 + aa];
-            d.re += (Tg)v.re;
-            d.im += (Tg)v.im;
-          } else {
+          x = pp.ix0 + aa; y = pp.iy0 + bb;
+          return gu(bb, aa) * w00 + gu(bb, aa - 1) * w01 + gu(bb - 1, aa) * w10 +
+                 gu(bb - 1, aa - 1) * w11;
+        };
+        if (inside) {
+          // the window lies inside the accumulator: batches of KB pixels per
+          // lane, all accumulator loads issued before the stores
+          constexpr int KB = 3;
+          for (int i0 = t; i0 < P1 * P1; i0 += kDoeThreads * KB) {
+            C2<Tf> v[KB];
+            int li[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+              const int i = i0 + k * kDoeThreads;
+              li[k] = -1;
+              if (i < P1 * P1) {
+                int x, y;
+                v[k] = pix(i, x, y);
+                if (x >= 0 && x < W && y >= 0 && y < H) li[k] = (ly0 + i / P1) * AS + lx0 + i % P1;
+              }
+            }
+            C2<Tg> old[KB];
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+              if (li[k] >= 0) old[k] = accm[li[k]];
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+              if (li[k] >= 0) accm[li[k]] = {old[k].re + (Tg)v[k].re, old[k].im + (Tg)v[k].im};
+          }
+        } else {
+          for (int i = t; i < P1 * P1; i += kDoeThreads) {
+            int x, y;
+            const C2<Tf> v = pix(i, x, y);
+            if (x < 0 || x >= W || y < 0 || y >= H) continue;
+            if (v.re == Tf(0) && v.im == Tf(0)) continue;
             atomicAdd(&gt[(size_t)y * W + x].re, (Tg)v.re);
             atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
           }

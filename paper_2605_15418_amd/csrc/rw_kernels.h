@@ -193,6 +193,8 @@ __global__ __launch_bounds__(256) void k_trace(const DevCfg* cfg, const DevPair*
 }
 
 // ------------------------------------------------------------- DOE stage ---
+struct RayCtx;
+
 struct DoeArgs {
   const DevCfg* cfg;
   const DevPair* pairs;
@@ -217,16 +219,19 @@ struct DoeArgs {
   int want_lens;
   void* acc;                 // C2<Tg> [blocks][acc_side][acc_side] block-private dL/dt
   int acc_side;
+  RayCtx* ctx;               // [n_total] frame and wavevectors at the DOE hit (alive rays)
+  void* dlist;               // per block [N]: (bin, spectrum cogradient) of each draw
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
 struct RayCtx {
   double p[3], d[3], opl;
   double u[3], v[3], n[3];
-  double kin_u, kin_v, k0, k_out, n_in, n_out, dk;
+  double kin_u, kin_v, k0, k_out, n_in, n_out, dk, k2out;
   int pair, r;
   size_t gid;
 };
+constexpr int kCtxWords = (int)(sizeof(RayCtx) / 4);
 
 __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c) {
   const DevCfg& cfg = *a.cfg;
@@ -254,6 +259,26 @@ __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c
   c.kin_u = c.k0 * c.n_in * (c.d[0] * c.u[0] + c.d[1] * c.u[1] + c.d[2] * c.u[2]);
   c.kin_v = c.k0 * c.n_in * (c.d[0] * c.v[0] + c.d[1] * c.v[1] + c.d[2] * c.v[2]);
   c.dk = 2.0 * RW_PI / (cfg.M * cfg.pitch);
+  c.k2out = __dmul_rn(c.k_out, c.k_out);
+}
+
+// Context of every alive ray of [ray0, ray0 + nray), one thread per ray.
+static __global__ __launch_bounds__(256) void k_ray_ctx(DoeArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.nray) return;
+  const size_t gid = a.ray0 + i;
+  if (a.st[7 * a.n_total + gid] == 0.0) return;
+  RayCtx c;
+  make_ctx(a, gid, c);
+  a.ctx[gid] = c;
+}
+
+// Copy of a ray's context into shared memory by the first kCtxWords threads
+// (the caller synchronises).
+__device__ __forceinline__ void load_ctx(const DoeArgs& a, size_t gid, RayCtx& dst) {
+  if (threadIdx.x < kCtxWords)
+    reinterpret_cast<uint32_t*>(&dst)[threadIdx.x] =
+        reinterpret_cast<const uint32_t*>(a.ctx + gid)[threadIdx.x];
 }
 
 // Bilinear sample of the complex transmission at the xy projection of
