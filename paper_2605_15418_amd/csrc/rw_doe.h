@@ -197,7 +197,8 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
       const int m = gl + L * n2;
       x[n2] = m < P ? buf[row * SM + m] : C2<Tf>{Tf(0), Tf(0)};
     }
-    group_fft<Tf, L, E, -1>(x, gl, tw);
+    if (2 * P == M) group_fft<Tf, L, E, -1, true>(x, gl, tw);
+    else group_fft<Tf, L, E, -1>(x, gl, tw);
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
   }
@@ -211,7 +212,8 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
       const int n = gl + L * n2;
       x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
     }
-    group_fft<Tf, L, E, -1>(x, gl, tw);
+    if (2 * P == M) group_fft<Tf, L, E, -1, true>(x, gl, tw);
+    else group_fft<Tf, L, E, -1>(x, gl, tw);
     // this lane now holds rows ky = E*br .. E*br + E - 1 of column col
     const int jx = col < M / 2 ? col : col - M;
     const int ky0 = E * br;

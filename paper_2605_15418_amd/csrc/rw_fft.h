@@ -89,7 +89,10 @@ __host__ __device__ constexpr int bitrev(int x, int bits) {
   return r;
 }
 
-template <class T, int E, int DIR>
+// In-lane E-point DIT FFT.  HZ: elements E/2 .. E-1 are zero on entry (the
+// zero-padded half of the patch), which makes the first stage a copy.
+// Twiddles 1 and +-i are applied without multiplications.
+template <class T, int E, int DIR, bool HZ = false>
 __device__ __forceinline__ void reg_fft(C2<T> (&x)[E]) {
   constexpr int LB = Log2<E>::v;
 #pragma unroll
@@ -104,9 +107,21 @@ __device__ __forceinline__ void reg_fft(C2<T> (&x)[E]) {
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
         const int ti = j * (64 / len);
-        const C2<T> w = {T(kUnit64[ti][0]), T(DIR * kUnit64[ti][1])};
         const C2<T> u = x[i + j];
-        const C2<T> v = x[i + j + len / 2] * w;
+        if (HZ && len == 2) {          // the odd (bit-reversed upper) input is zero
+          x[i + j + len / 2] = u;
+          continue;
+        }
+        const C2<T> b = x[i + j + len / 2];
+        C2<T> v;
+        if (ti == 0) {
+          v = b;
+        } else if (ti == 16) {         // w = DIR * i
+          v = DIR > 0 ? C2<T>{-b.im, b.re} : C2<T>{b.im, -b.re};
+        } else {
+          const C2<T> w = {T(kUnit64[ti][0]), T(DIR * kUnit64[ti][1])};
+          v = b * w;
+        }
         x[i + j] = u + v;
         x[i + j + len / 2] = u - v;
       }
@@ -114,14 +129,59 @@ __device__ __forceinline__ void reg_fft(C2<T> (&x)[E]) {
   }
 }
 
+// x ^ MASK lane exchange: DPP quad permutations for masks 1 and 2,
+// ds_swizzle (bit mode, within 32 lanes) for 4 .. 16, ds_bpermute for 32.
+template <int MASK> __device__ __forceinline__ float xor_lane(float v) {
+  const int iv = __float_as_int(v);
+  int r;
+  if constexpr (MASK == 1)
+    r = __builtin_amdgcn_update_dpp(0, iv, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  else if constexpr (MASK == 2)
+    r = __builtin_amdgcn_update_dpp(0, iv, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  else if constexpr (MASK < 32)
+    r = __builtin_amdgcn_ds_swizzle(iv, 0x1F | (MASK << 10));
+  else
+    r = __shfl_xor(iv, MASK, 64);
+  return __int_as_float(r);
+}
+template <int MASK> __device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const float lo = xor_lane<MASK>(__int_as_float((int)(b & 0xffffffffll)));
+  const float hi = xor_lane<MASK>(__int_as_float((int)(b >> 32)));
+  return __longlong_as_double(((long long)__float_as_int(hi) << 32) |
+                              (unsigned int)__float_as_int(lo));
+}
+
 template <class T> __device__ __forceinline__ C2<T> shfl_xor_c(C2<T> v, int mask, int width) {
   return {__shfl_xor(v.re, mask, width), __shfl_xor(v.im, mask, width)};
 }
 
-template <class T, int L, int E, int DIR, class TW>
+// Cross-lane DIF stages h = H, H/2, ..., 1 (compile-time recursion).
+template <class T, int L, int E, int DIR, int H, class TW>
+__device__ __forceinline__ void xlane_stages(C2<T> (&x)[E], int g, const TW* tw) {
+  if constexpr (H >= 1) {
+    constexpr int N = L * E;
+    const bool upper = (g & H) != 0;
+    const int a = g & (H - 1);
+    C2<T> w = {T(tw[a * (N / (2 * H))].re), T(tw[a * (N / (2 * H))].im)};
+    if (DIR > 0) w.im = -w.im;
+    // lower lane: x + o; upper lane: (o - x) w
+    const T sg = upper ? T(-1) : T(1);
+    if (!upper) w = {T(1), T(0)};
+#pragma unroll
+    for (int k2 = 0; k2 < E; ++k2) {
+      const C2<T> o = {xor_lane<H>(x[k2].re), xor_lane<H>(x[k2].im)};
+      const C2<T> y = {o.re + sg * x[k2].re, o.im + sg * x[k2].im};
+      x[k2] = y * w;
+    }
+    xlane_stages<T, L, E, DIR, H / 2>(x, g, tw);
+  }
+}
+
+template <class T, int L, int E, int DIR, bool HZ = false, class TW>
 __device__ __forceinline__ void group_fft(C2<T> (&x)[E], int g, const TW* tw) {
   constexpr int N = L * E;
-  reg_fft<T, E, DIR>(x);
+  reg_fft<T, E, DIR, HZ>(x);
   if constexpr (L > 1) {
     // an opaque zero keeps the twiddle reads inside the call: hoisted out of
     // the callers' loops they would pin E + log2 L complex registers for the
@@ -136,18 +196,7 @@ __device__ __forceinline__ void group_fft(C2<T> (&x)[E], int g, const TW* tw) {
       if (DIR > 0) w.im = -w.im;
       x[k2] = x[k2] * w;
     }
-#pragma unroll
-    for (int h = L / 2; h >= 1; h >>= 1) {
-      const bool upper = (g & h) != 0;
-      const int a = g & (h - 1);
-      C2<T> w = {T(tw[a * (N / (2 * h))].re), T(tw[a * (N / (2 * h))].im)};
-      if (DIR > 0) w.im = -w.im;
-#pragma unroll
-      for (int k2 = 0; k2 < E; ++k2) {
-        const C2<T> o = shfl_xor_c(x[k2], h, L);
-        x[k2] = upper ? (o - x[k2]) * w : x[k2] + o;
-      }
-    }
+    xlane_stages<T, L, E, DIR, L / 2>(x, g, tw);
   }
 }
 
