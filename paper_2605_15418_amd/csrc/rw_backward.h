@@ -132,9 +132,14 @@ __device__ __forceinline__ void incident_from_wavelet(const DoeArgs& a, const Ra
   acc.gkin[1] += (gv - gn * sec.Kv / sec.kz) / c.k_out;
 }
 
+// Sum over the 64 lanes of a wave (butterfly: every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += xor_lane<32>(v);
+  v += xor_lane<16>(v);
+  v += xor_lane<8>(v);
+  v += xor_lane<4>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<1>(v);
   return v;
 }
 

@@ -46,6 +46,19 @@ template <int M> struct DoeGeom {
   static constexpr int LB = Log2<L>::v;
 };
 
+// Division of small non-negative integers (< 2^20) by a runtime divisor through
+// a float reciprocal: (i + 1/2) / d stays at least 1/(2d) away from an integer,
+// far beyond the float rounding error, so the truncation is exact.
+struct FDiv {
+  int d;
+  float inv;
+  __device__ __forceinline__ explicit FDiv(int dd) : d(dd), inv(1.0f / (float)dd) {}
+  __device__ __forceinline__ int div(int i) const { return (int)(((float)i + 0.5f) * inv); }
+};
+
+__device__ __forceinline__ float inv_sqrt(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
 // Propagating test of shifted bin (jx, jy): |k_in,t + kappa_j| < k_out, in FP64
 // with every rounding explicit, so that all call sites take the same decision.
 // For fixed jx the result is monotone in |K_v|, hence an interval of jy.
@@ -88,13 +101,27 @@ __device__ __forceinline__ TileRef tile_of(const DevCfg& cfg, const RayCtx& c) {
   return {(int)floor(fx) - cfg.P / 2 - 1, (int)floor(fy) - cfg.P / 2 - 1, tw};
 }
 
+// Batches of KB pixels per lane: all loads of a batch are issued before its
+// LDS stores, so the map latency is paid once per batch.
 template <class Tf>
 __device__ __forceinline__ void stage_tile(const DevCfg& cfg, const TileRef& tr, const C2<Tf>* tm,
                                            C2<Tf>* tile) {
-  for (int i = opaque_tid(); i < tr.tw * tr.tw; i += kDoeThreads) {
-    const int y = tr.ty0 + i / tr.tw, x = tr.tx0 + i % tr.tw;
-    tile[i] = (x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) ? tm[(size_t)y * cfg.W + x]
-                                                           : C2<Tf>{Tf(0), Tf(0)};
+  constexpr int KB = 80 / (int)sizeof(C2<Tf>);
+  const int n = tr.tw * tr.tw;
+  const FDiv dv(tr.tw);
+  for (int i0 = opaque_tid(); i0 < n; i0 += kDoeThreads * KB) {
+    C2<Tf> v[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = i0 + k * kDoeThreads;
+      const int q = dv.div(i);
+      const int y = tr.ty0 + q, x = tr.tx0 + (i - q * tr.tw);
+      v[k] = (i < n && x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) ? tm[(size_t)y * cfg.W + x]
+                                                                  : C2<Tf>{Tf(0), Tf(0)};
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (i0 + k * kDoeThreads < n) tile[i0 + k * kDoeThreads] = v[k];
   }
 }
 
@@ -178,14 +205,16 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
     const Tf w00 = (Tf(1) - pp.wx) * (Tf(1) - pp.wy), w01 = pp.wx * (Tf(1) - pp.wy);
     const Tf w10 = (Tf(1) - pp.wx) * pp.wy, w11 = pp.wx * pp.wy;
+    const int lgP = __builtin_ctz(P);                // P is a power of two
     for (int i = tid; i < P * P; i += kDoeThreads) {
-      const int m = i % P, n = i / P;
+      const int m = i & (P - 1), n = i >> lgP;
       const C2<Tf>* r0 = tile + (oy + n) * tr.tw + ox + m;
       buf[n * SM + m] = r0[0] * w00 + r0[1] * w01 + r0[tr.tw] * w10 + r0[tr.tw + 1] * w11;
     }
   } else {
+    const int lgP = __builtin_ctz(P);
     for (int i = tid; i < P * P; i += kDoeThreads) {
-      const int m = i % P, n = i / P;
+      const int m = i & (P - 1), n = i >> lgP;
       buf[n * SM + m] = patch_sample_t<Tf>(cfg, c, tm, tile, tr, m, n);
     }
   }
@@ -290,8 +319,7 @@ __device__ __forceinline__ int block_max_i(int v, int* red) {
 }
 
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double m = 0.0;
@@ -517,9 +545,9 @@ __device__ __forceinline__ void interp_adj_pair(const DevCfg& cfg,
     // keep the next group's loads from being scheduled above this point
     __builtin_amdgcn_sched_barrier(0);
   }
-  g0.re += __shfl_xor(g0.re, 1, 64); g0.im += __shfl_xor(g0.im, 1, 64);
-  dx.re += __shfl_xor(dx.re, 1, 64); dx.im += __shfl_xor(dx.im, 1, 64);
-  dy.re += __shfl_xor(dy.re, 1, 64); dy.im += __shfl_xor(dy.im, 1, 64);
+  g0.re += xor_lane<1>(g0.re); g0.im += xor_lane<1>(g0.im);
+  dx.re += xor_lane<1>(dx.re); dx.im += xor_lane<1>(dx.im);
+  dy.re += xor_lane<1>(dy.re); dy.im += xor_lane<1>(dy.im);
 }
 
 // Cogradients of one wavelet's inputs (its weight w, phase, grid frequencies and
@@ -581,6 +609,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
   const int N = cfg.N, P = cfg.P, t = threadIdx.x;
+  static_assert(kDoeThreads % M == 0, "the S-term pass keeps one column per lane");
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
   const int T = P + 4;                                  // bilinear tile side
@@ -673,21 +702,27 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           }
         }
         dLdS = block_sum_d(dLdS, s.red);     // orders every read of buf before the rewrite
-        // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins
-        for (int idx = t; idx < M * M; idx += kDoeThreads) {
-          const int ky = idx / M, kx = idx % M;
-          const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+        // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins;
+        // each lane keeps one column (M divides the block size)
+        {
+          const int kx = t % M;
+          const int jx = kx < M / 2 ? kx : kx - M;
           const Span sp = s.span[jx + M / 2];
-          C2<Tf>& X = buf[ky * SM + kx];
-          C2<Tf> v = {Tf(0), Tf(0)};
-          if (cfg.sampling == 0 && jy >= sp.lo && jy <= sp.hi) {
-            const Tf m = cabs_rn(X);
-            if (m > Tf(0)) {
-              const Tf f = (Tf)dLdS / m;
-              v = {X.re * f, X.im * f};
+          const bool mag = cfg.sampling == 0;
+          const Tf fS = (Tf)dLdS;
+          for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
+            const int jy = ky < M / 2 ? ky : ky - M;
+            C2<Tf>& X = buf[ky * SM + kx];
+            C2<Tf> v = {Tf(0), Tf(0)};
+            if (mag && jy >= sp.lo && jy <= sp.hi) {
+              const Tf m2 = X.re * X.re + X.im * X.im;
+              if (m2 > Tf(0)) {
+                const Tf f = fS * inv_sqrt(m2);
+                v = {X.re * f, X.im * f};
+              }
             }
+            X = v;
           }
-          X = v;
         }
         __syncthreads();
         // draw terms: each entry is re-read by the lane that wrote it
@@ -746,12 +781,19 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
 #pragma unroll
         for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[row * SM + gl + L * n2];
         group_fft<Tf, L, E, +1>(x, gl, s.tw);
+        // columns P and M - 1 become a zero border of the patch gradient
 #pragma unroll
         for (int k2 = 0; k2 < E; ++k2) {
           const int m = E * br + k2;
           if (m < P) buf[row * SM + m] = x[k2];
+          else if (m == P || m == M - 1) buf[row * SM + m] = C2<Tf>{Tf(0), Tf(0)};
         }
       }
+      // rows P and M - 1 too (the row pass touches rows < P only): the
+      // bilinear adjoint below reads samples -1 and P through the wrap M - 1
+      if (P < M - 1)
+        for (int i = t; i < 2 * M; i += kDoeThreads)
+          buf[(i < M ? P : M - 1) * SM + (i & (M - 1))] = C2<Tf>{Tf(0), Tf(0)};
       __syncthreads();
       // bilinear adjoint of the patch gather -> dL/dt, added to the block accumulator
       double gpx = 0.0, gpy = 0.0;
@@ -768,11 +810,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           atomicMin(&s_box[0], lx0); atomicMin(&s_box[1], ly0);
           atomicMax(&s_box[2], lx0 + P1); atomicMax(&s_box[3], ly0 + P1);
         }
-        auto gu = [&](int n, int m) {
-          return (m >= 0 && m < P && n >= 0 && n < P) ? buf[n * SM + m] : C2<Tf>{Tf(0), Tf(0)};
-        };
+        // samples -1 and P read the zero border (index -1 wraps to M - 1)
+        auto gu = [&](int n, int m) { return buf[(n & (M - 1)) * SM + (m & (M - 1))]; };
+        const FDiv dP1(P1);
         auto pix = [&](int i, int& x, int& y) -> C2<Tf> {
-          const int aa = i % P1, bb = i / P1;
+          const int bb = dP1.div(i), aa = i - bb * P1;
           x = pp.ix0 + aa; y = pp.iy0 + bb;
           return gu(bb, aa) * w00 + gu(bb, aa - 1) * w01 + gu(bb - 1, aa) * w10 +
                  gu(bb - 1, aa - 1) * w11;
@@ -780,7 +822,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         if (inside) {
           // the window lies inside the accumulator: batches of KB pixels per
           // lane, all accumulator loads issued before the stores
-          constexpr int KB = 3;
+          constexpr int KB = 9;
           for (int i0 = t; i0 < P1 * P1; i0 += kDoeThreads * KB) {
             C2<Tf> v[KB];
             int li[KB];
@@ -791,7 +833,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               if (i < P1 * P1) {
                 int x, y;
                 v[k] = pix(i, x, y);
-                if (x >= 0 && x < W && y >= 0 && y < H) li[k] = (ly0 + i / P1) * AS + lx0 + i % P1;
+                if (x >= 0 && x < W && y >= 0 && y < H)
+                  li[k] = (ly0 + y - pp.iy0) * AS + lx0 + x - pp.ix0;
               }
             }
             C2<Tg> old[KB];
@@ -813,14 +856,17 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           }
         }
         if (a.want_lens) {
-          // map tile under the patch (rows P.. of buf are free again)
+          // map tile under the patch (rows P.. of buf are free again once every
+          // lane has read the zero border)
+          __syncthreads();
           const TileRef tr = tile_of(cfg, c);
           C2<Tf>* mt = buf + P * SM;
           stage_tile<Tf>(cfg, tr, tm, mt);
           __syncthreads();
           const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
+          const int lgP = __builtin_ctz(P);
           for (int smp = t; smp < P * P; smp += kDoeThreads) {
-            const int m = smp % P, n = smp / P;
+            const int m = smp & (P - 1), n = smp >> lgP;
             const C2<Tf> g = buf[n * SM + m];
             const C2<Tf>* r0 = mt + (oy + n) * tr.tw + ox + m;
             const C2<Tf> t00 = r0[0], t01 = r0[1], t10 = r0[tr.tw], t11 = r0[tr.tw + 1];
@@ -903,22 +949,25 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         if ((t & 63) == 0)
           for (int q = 0; q < 7; ++q) s.acc[t >> 6][q] = v[q];
         __syncthreads();
-        if (t == 0) {
-          double r[7];
-          for (int q = 0; q < 7; ++q) {
-            r[q] = 0.0;
-            for (int wv = 0; wv < kDoeThreads / 64; ++wv) r[q] += s.acc[wv][q];
-          }
-          const DevPair& pr = a.pairs[c.pair];
-          const double f = c.k0 * pr.n_med[cfg.s_doe];
+        // output component t < 8 of the incident-state cogradient, one lane each
+        if (t < 8) {
+          auto tot = [&](int q) {
+            double r = 0.0;
+            for (int wv = 0; wv < kDoeThreads / 64; ++wv) r += s.acc[wv][q];
+            return r;
+          };
           const size_t n = a.n_total;
-          a.raygrad[0 * n + gid] = r[0];
-          a.raygrad[1 * n + gid] = r[1];
-          a.raygrad[2 * n + gid] = r[2];
-          for (int i = 0; i < 3; ++i)
-            a.raygrad[(3 + i) * n + gid] = f * (r[3] * c.u[i] + r[4] * c.v[i]);
-          a.raygrad[6 * n + gid] = r[5];
-          a.raygrad[7 * n + gid] = r[6];
+          double out;
+          if (t < 3) {
+            out = tot(t);
+          } else if (t < 6) {
+            const DevPair& pr = a.pairs[c.pair];
+            const double f = c.k0 * pr.n_med[cfg.s_doe];
+            out = f * (tot(3) * c.u[t - 3] + tot(4) * c.v[t - 3]);
+          } else {
+            out = tot(t - 1);
+          }
+          a.raygrad[(size_t)t * n + gid] = out;
         }
       }
       __syncthreads();   // buf, tile and pref are reused by the next ray
