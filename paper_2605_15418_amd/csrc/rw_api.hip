@@ -442,7 +442,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     while ((1 << shift) < pl->nf / nb) ++shift;
     pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb};
     const size_t tile = 4 * (size_t)pl->bg.bin;
-    if (tile * (tile + 1) * pl->sz_cg > 128 * 1024 || pl->w > 2 * pl->bg.bin) {
+    if (tile * (tile + 1) * pl->sz_cg + spread_static_lds(pl->sz_cg / 2, pl->w) > 160 * 1024 ||
+        pl->w > 2 * pl->bg.bin) {
       delete pl;
       return fail(RW_ERR_UNSUPPORTED, "PSF size too large for this precision");
     }
@@ -532,15 +533,16 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
 
   {
     // the spreading tile of the largest grids needs more than the default 64 KiB of LDS
-    const int lim = 128 * 1024;
     hipError_t ea = hipSuccess, eb = hipSuccess;
 #define RW_ATTR(W)                                                                              \
     if (ea == hipSuccess)                                                                       \
       ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<float, W>),        \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);                \
+                               hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                               (int)(160 * 1024 - spread_static_lds(sizeof(float), W)));        \
     if (eb == hipSuccess)                                                                       \
       eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<double, W>),       \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+                               hipFuncAttributeMaxDynamicSharedMemorySize,                     \
+                               (int)(160 * 1024 - spread_static_lds(sizeof(double), W)));
     RW_ATTR(4) RW_ATTR(5) RW_ATTR(6) RW_ATTR(7) RW_ATTR(8) RW_ATTR(9) RW_ATTR(10) RW_ATTR(11)
     RW_ATTR(12) RW_ATTR(13) RW_ATTR(14) RW_ATTR(15) RW_ATTR(16)
 #undef RW_ATTR

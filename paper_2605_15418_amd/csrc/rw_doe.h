@@ -219,15 +219,22 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     }
   }
   __syncthreads();
+  const bool half = 2 * P == M;     // pad factor 2: the upper half of every input is zero
   for (int row = g; row < P; row += G) {
     C2<Tf> x[E];
+    if (half) {
 #pragma unroll
-    for (int n2 = 0; n2 < E; ++n2) {
-      const int m = gl + L * n2;
-      x[n2] = m < P ? buf[row * SM + m] : C2<Tf>{Tf(0), Tf(0)};
+      for (int n2 = 0; n2 < E; ++n2)
+        x[n2] = n2 < E / 2 ? buf[row * SM + gl + L * n2] : C2<Tf>{Tf(0), Tf(0)};
+      group_fft<Tf, L, E, -1, true>(x, gl, tw);
+    } else {
+#pragma unroll
+      for (int n2 = 0; n2 < E; ++n2) {
+        const int m = gl + L * n2;
+        x[n2] = m < P ? buf[row * SM + m] : C2<Tf>{Tf(0), Tf(0)};
+      }
+      group_fft<Tf, L, E, -1>(x, gl, tw);
     }
-    if (2 * P == M) group_fft<Tf, L, E, -1, true>(x, gl, tw);
-    else group_fft<Tf, L, E, -1>(x, gl, tw);
 #pragma unroll
     for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
   }
@@ -236,13 +243,19 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   int lp = -1;
   for (int col = g; col < M; col += G) {
     C2<Tf> x[E];
+    if (half) {
 #pragma unroll
-    for (int n2 = 0; n2 < E; ++n2) {
-      const int n = gl + L * n2;
-      x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+      for (int n2 = 0; n2 < E; ++n2)
+        x[n2] = n2 < E / 2 ? buf[(gl + L * n2) * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+      group_fft<Tf, L, E, -1, true>(x, gl, tw);
+    } else {
+#pragma unroll
+      for (int n2 = 0; n2 < E; ++n2) {
+        const int n = gl + L * n2;
+        x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+      }
+      group_fft<Tf, L, E, -1>(x, gl, tw);
     }
-    if (2 * P == M) group_fft<Tf, L, E, -1, true>(x, gl, tw);
-    else group_fft<Tf, L, E, -1>(x, gl, tw);
     // this lane now holds rows ky = E*br .. E*br + E - 1 of column col
     const int jx = col < M / 2 ? col : col - M;
     const int ky0 = E * br;

@@ -560,12 +560,6 @@ __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const 
   }
 }
 
-// Spreading of one tile.  Each of the 4 waves owns a horizontal strip of the
-// tile (tile / 4 rows) that no other wave writes.  Every wave loads 64 records
-// at once (one per lane), keeps those whose footprint meets its strip, then
-// walks them: each record is broadcast with readlane and its taps are added by
-// one lane each with a plain LDS read-modify-write (the taps of one record are
-// distinct cells), so no atomics are needed.
 __device__ __forceinline__ int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 __device__ __forceinline__ float bcast_f(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -579,91 +573,142 @@ __device__ __forceinline__ double bcast_d(double v, int lane) {
 __device__ __forceinline__ float bcast_v(float v, int lane) { return bcast_f(v, lane); }
 __device__ __forceinline__ double bcast_v(double v, int lane) { return bcast_d(v, lane); }
 
+// LDS ordering between lanes of one wave (no other wave touches these arrays).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kSpreadWaves = 4;      // waves per spreading block (256 threads)
+constexpr int kSpreadQueue = 128;    // queued records per wave
+
+// Static LDS of k_spread_tiles<Tg, w> besides the dynamic accumulator tile.
+__host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
+  return (size_t)kSpreadWaves * (64 * (2 * (size_t)w * sz_g + 2 * sz_g + 8) + kSpreadQueue * 8 +
+                                 (18 + 19) * 8);
+}
+
+// Spreading of one tile (TILE x TILE cells, TILE = 4 BIN).  Wave q owns bin row
+// q of the tile (a strip no other wave writes) and scans the records of the
+// 3 x 6 bins whose kernel footprints can reach it (w / 2 <= BIN).  Records that
+// meet the strip are queued; per 64 queued records every lane evaluates the
+// separable ES-kernel factors of one record into LDS, then the wave walks the
+// batch: for each record every lane adds one tap with a plain LDS
+// read-modify-write (the taps of one record are distinct cells): no atomics.
 template <class Tg, int w>
 __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
                                                       const unsigned long long* offsets,
                                                       BinGeom g, double beta, int pair0,
                                                       C2<Tg>* grid) {
   using U = typename RecPos<Tg>::T;
+  constexpr int NW = kSpreadWaves, QN = kSpreadQueue;
   extern __shared__ unsigned char s_raw[];
+  __shared__ Tg s_kx[NW][64][w], s_ky[NW][64][w];
+  __shared__ C2<Tg> s_v[NW][64];
+  __shared__ int s_lx[NW][64], s_ly[NW][64];
+  __shared__ unsigned long long s_q[NW][QN];
+  __shared__ unsigned long long s_beg[NW][18], s_pre[NW][19];
   const int tile = 4 * g.bin;                 // cells per tile side
   const int ts = tile + 1;                    // padded row stride
   C2<Tg>* acc = (C2<Tg>*)s_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nwaves = blockDim.x >> 6;
   const int ntx = g.nf / tile;
   const int pair = pair0 + blockIdx.y;
   const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
   const int x0 = tx * tile, y0 = ty * tile;
+  const int strip = g.bin, sy0 = wave * strip;  // tile rows owned by this wave
   for (int i = threadIdx.x; i < tile * ts; i += blockDim.x) acc[i] = {Tg(0), Tg(0)};
   const U* pos = (const U*)srt_pos;
   const C2<Tg>* val = (const C2<Tg>*)srt_val;
   const unsigned long long* off = offsets + (size_t)pair * g.keys;
-  __shared__ unsigned long long s_beg[36], s_pre[37];
-  if (threadIdx.x < 36) {
-    const int by = (int)threadIdx.x / 6 - 1, bx = (int)threadIdx.x % 6 - 1;
-    const int bny = (ty * 4 + by + g.nb) % g.nb, bnx = (tx * 4 + bx + g.nb) % g.nb;
+  if (lane < 18) {
+    const int by = lane / 6 - 1, bx = lane % 6 - 1;
+    const int bny = (ty * 4 + wave + by + g.nb) % g.nb, bnx = (tx * 4 + bx + g.nb) % g.nb;
     const int k = bny * g.nb + bnx;
-    s_beg[threadIdx.x] = off[k];
-    s_pre[threadIdx.x + 1] = off[k + 1] - off[k];
+    s_beg[wave][lane] = off[k];
+    s_pre[wave][lane + 1] = off[k + 1] - off[k];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    s_pre[0] = 0;
-    for (int i = 1; i <= 36; ++i) s_pre[i] += s_pre[i - 1];
+  if (lane == 0) {
+    s_pre[wave][0] = 0;
+    for (int i = 1; i <= 18; ++i) s_pre[wave][i] += s_pre[wave][i - 1];
   }
   __syncthreads();
   const Tg two_w = Tg(2.0 / w), bet = (Tg)beta;
-  const unsigned long long ntot = s_pre[36];
-  const int strip = tile / nwaves;                // rows owned by this wave
-  const int sy0 = wave * strip;
-  const int ti = lane % w, tj = lane / w;          // this lane's tap (w * w <= 64 for w <= 8)
-  int bin = 0;                                     // monotonic per lane across batches
-  for (unsigned long long base = 0; base < ntot; base += 64) {
-    const unsigned long long j = base + lane;
-    int lx0 = 0, ly0 = 0;
-    double fx = 0.0, fy = 0.0;
-    C2<Tg> v = {Tg(0), Tg(0)};
-    bool hit = false;
-    if (j < ntot) {
-      while (j >= s_pre[bin + 1]) ++bin;
-      const unsigned long long r = s_beg[bin] + (j - s_pre[bin]);
+  const unsigned long long ntot = s_pre[wave][18];
+
+  // stage queue entries [0, n) and add their taps to the strip
+  auto process = [&](int n) {
+    wave_lds_sync();
+    if (lane < n) {
+      const unsigned long long r = s_q[wave][lane];
       const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
-      lx0 = (int)ceil(gx - 0.5 * w);
-      ly0 = (int)ceil(gy - 0.5 * w);
-      fx = gx - lx0;
-      fy = gy - ly0;
-      // footprint vs tile columns and vs this wave's strip rows (periodic)
-      const int cx0 = ((lx0 - x0) % g.nf + g.nf) % g.nf;
-      const int cy0 = ((ly0 - y0 - sy0) % g.nf + g.nf) % g.nf;
-      hit = (cx0 < tile || cx0 + w > g.nf) && (cy0 < strip || cy0 + w > g.nf);
-      if (hit) v = val[r];
+      const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
+      const double fx = gx - lx0, fy = gy - ly0;
+#pragma unroll
+      for (int i = 0; i < w; ++i) {
+        s_kx[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fx), two_w, bet);
+        s_ky[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fy), two_w, bet);
+      }
+      s_v[wave][lane] = val[r];
+      s_lx[wave][lane] = lx0;
+      s_ly[wave][lane] = ly0;
     }
-    unsigned long long mask = __ballot(hit);
-    while (mask) {
-      const int k = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const int blx = bcast_i(lx0, k), bly = bcast_i(ly0, k);
-      const double bfx = bcast_d(fx, k), bfy = bcast_d(fy, k);
-      const Tg vr = bcast_v(v.re, k), vi = bcast_v(v.im, k);
+    wave_lds_sync();
+    for (int k = 0; k < n; ++k) {
+      const int blx = s_lx[wave][k], bly = s_ly[wave][k];
+      const C2<Tg> v = s_v[wave][k];
 #pragma unroll
       for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
         const int tap = tap0 + lane;
-        const int i = tap0 == 0 ? ti : tap % w, jj = tap0 == 0 ? tj : tap / w;
         if (tap < w * w) {
+          const int i = tap % w, jj = tap / w;
           const int cx = ((blx + i) & (g.nf - 1)) - x0;
           const int cy = ((bly + jj) & (g.nf - 1)) - y0;
           if (cx >= 0 && cx < tile && cy >= sy0 && cy < sy0 + strip) {
-            const Tg kk = es_kernel<Tg>((Tg)((double)i - bfx), two_w, bet) *
-                          es_kernel<Tg>((Tg)((double)jj - bfy), two_w, bet);
+            const Tg kk = s_kx[wave][k][i] * s_ky[wave][k][jj];
             C2<Tg>& d = acc[cy * ts + cx];
-            d.re += vr * kk;
-            d.im += vi * kk;
+            d.re += v.re * kk;
+            d.im += v.im * kk;
           }
         }
       }
     }
+    wave_lds_sync();
+  };
+
+  int qn = 0;                                      // queued records (wave-uniform)
+  int bin = 0;                                     // monotonic per lane across batches
+  for (unsigned long long base = 0; base < ntot; base += 64) {
+    const unsigned long long j = base + lane;
+    unsigned long long r = 0;
+    bool hit = false;
+    if (j < ntot) {
+      while (j >= s_pre[wave][bin + 1]) ++bin;
+      r = s_beg[wave][bin] + (j - s_pre[wave][bin]);
+      const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+      const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
+      // footprint vs tile columns and vs this wave's strip rows (periodic)
+      const int cx0 = ((lx0 - x0) % g.nf + g.nf) % g.nf;
+      const int cy0 = ((ly0 - y0 - sy0) % g.nf + g.nf) % g.nf;
+      hit = (cx0 < tile || cx0 + w > g.nf) && (cy0 < strip || cy0 + w > g.nf);
+    }
+    const unsigned long long m = __ballot(hit);
+    const int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (hit) s_q[wave][qn + pre] = r;
+    qn += __popcll(m);
+    if (qn >= 64) {
+      process(64);
+      // move the overflow to the front of the queue
+      const int rest = qn - 64;
+      const unsigned long long t = lane < rest ? s_q[wave][64 + lane] : 0ull;
+      wave_lds_sync();
+      if (lane < rest) s_q[wave][lane] = t;
+      qn = rest;
+    }
   }
+  if (qn > 0) process(qn);
   __syncthreads();
   C2<Tg>* gp = grid + (size_t)pair * g.nf * g.nf;
   for (int i = threadIdx.x; i < tile * tile; i += blockDim.x) {
