@@ -19,9 +19,11 @@ roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded
 sample of the same workload on the host cores.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,51 @@ sys.path.insert(0, ROOT)
 
 METRIC = "traced rays/s fwd+bwd to PSF, batched vs plain FP32, at ≤1e-4 PSF err vs FP64"
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+CSRC = os.path.join(ROOT, "paper_2605_15418_amd", "csrc")
+# sources compiled into the MIXED DOE kernels
+DOE_SOURCES = ("rw_common.h", "rw_fft.h", "rw_kernels.h", "rw_backward.h", "rw_doe.h",
+               "rw_doe_mixed.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "doe_bwd_traffic_asphere_hologram.md")
+
+
+def doe_source_hash():
+    h = hashlib.sha256()
+    for name in DOE_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (already scaled by the copy-kernel calibration), if they
+    were taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m_src = re.search(r"kernel sources sha256\[:16\]: `([0-9a-f]+)`", text)
+    m_k = re.search(r"kernel: `([a-z_]+)`", text)
+    m_b = re.search(r"HBM bytes per launch \(calibrated\): `([0-9.eE+]+)`", text)
+    if not (m_src and m_k and m_b) or m_k.group(1) != kernel or m_src.group(1) != doe_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters (run under rocprofv3 --pmc)."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}),
+          flush=True)
 
 
 def doe_fwd_flops_per_ray(P, M, N):
@@ -60,7 +107,12 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the single-GPU share is the measured unit); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -127,26 +179,30 @@ def main():
     per_launch_ms = {k: prof[k][0] / max(prof[k][1], 1) for k in prof}
     dom = max(flops, key=lambda k: per_launch_ms[k])
     achieved = flops[dom] / (per_launch_ms[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(dom)
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
+                "kernel_sources": doe_source_hash(),
                 "launch_ms": round(per_launch_ms[dom], 3),
                 "algorithmic_flop_per_launch": flops[dom]}
 
     # ------------------------------------------------------------ plain FP32
-    log("plain FP32 form (one launch per pair)")
-    plain = rw.Plan(system, cfg, precision="fp32", batched=False)
-    step(plain)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.plain_steps):
+    plain, plain_rec = None, None
+    if args.plain_steps > 0:
+        log("plain FP32 form (one launch per pair)")
+        plain = rw.Plan(system, cfg, precision="fp32", batched=False)
         step(plain)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plain_value = n_rays * args.plain_steps / (t1 - t0)
-    plain_rec = {"value": plain_value, "ms_per_step": (t1 - t0) * 1e3 / args.plain_steps,
-                 "speedup_batched_mixed": value / plain_value}
-    log(f"plain FP32: {plain_rec['ms_per_step']:.1f} ms/step")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(plain)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain_value = n_rays * args.plain_steps / (t1 - t0)
+        plain_rec = {"value": plain_value, "ms_per_step": (t1 - t0) * 1e3 / args.plain_steps,
+                     "speedup_batched_mixed": value / plain_value}
+        log(f"plain FP32: {plain_rec['ms_per_step']:.1f} ms/step")
 
     # ---------------------------------------------- error against FP64 form
     check = None
@@ -166,7 +222,7 @@ def main():
             return {"psf_rel_l2_worst_pair": float(d.max()), "grad_rel_l2":
                     {"phase": ge[0], "amp": ge[1], "lens": ge[2]}}
 
-        check = {"mixed": errs(plan), "plain_fp32": errs(plain),
+        check = {"mixed": errs(plan), "plain_fp32": errs(plain) if plain else None,
                  "note": "same sample indices (FP64 draws replayed); relative L2 per pair / per group"}
         del p64
         log(f"errors vs FP64: {json.dumps(check)}")
