@@ -179,7 +179,7 @@ rw_status rw_get_stats(rw_plan* plan, rw_stats* out_host);
  * elapsed times (it synchronises those events).  Stages: */
 enum { RW_STAGE_TRACE = 0, RW_STAGE_DOE_FWD = 1, RW_STAGE_BIN = 2, RW_STAGE_SPREAD = 3,
        RW_STAGE_GRID_FWD = 4, RW_STAGE_GRID_BWD = 5, RW_STAGE_DOE_BWD = 6,
-       RW_STAGE_TRACE_BWD = 7, RW_N_STAGES = 8 };
+       RW_STAGE_TRACE_BWD = 7, RW_STAGE_INTERP = 8, RW_N_STAGES = 9 };
 typedef struct {
   double ms[RW_N_STAGES];          /* summed kernel time per stage            */
   uint64_t launches[RW_N_STAGES];  /* number of timed launches per stage      */

@@ -76,6 +76,8 @@ struct rw_plan {
   int acc_side;             // side of the block-private dL/dt accumulator
   int emit;                 // record slots per ray
   int group_pairs;          // pairs per launch group (memory-bounded)
+  bool tiled_interp;        // one launch group: the backward interpolates the records
+                            // of the forward tile by tile
   BinGeom bg;
   int rec_chunk;
   double beta;
@@ -91,7 +93,8 @@ struct rw_plan {
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
-      off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, total;
+      off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
+      off_interp, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -290,7 +293,8 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   hipLaunchKernelGGL(k_rec_scatter<Tg>, grid, dim3(256), lds_sc, st,
                      (const void*)(b + pl->off_rpos), (const void*)(b + pl->off_rval), per_pair,
                      chunk, g, pair0, (unsigned long long*)(b + pl->off_cur),
-                     (void*)(b + pl->off_spos), (void*)(b + pl->off_sval));
+                     (void*)(b + pl->off_spos), (void*)(b + pl->off_sval),
+                     pl->tiled_interp ? (unsigned long long*)(b + pl->off_sidx) : nullptr);
   delete tb_;
   const int tile = 4 * g.bin;
   const int ntiles = (g.nf / tile) * (g.nf / tile);
@@ -315,6 +319,42 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   }
   HIPCHK(hipGetLastError());
   return RW_OK;
+}
+
+// Type-2 interpolation of the sensor-grid cogradient at every record of the
+// forward, tile by tile (backward, one launch group only).
+template <class Tg>
+rw_status interp_tiles_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  char* b = (char*)ws;
+  const BinGeom g = pl->bg;
+  const int nsb = g.nb / 2;
+  const dim3 grid((unsigned)(nsb * nsb), (unsigned)npairs);
+  const size_t lds = (size_t)interp_side(g.bin, pl->w) * interp_side(g.bin, pl->w) * sizeof(C2<Tg>);
+  StageTimer ti_(pl, RW_STAGE_INTERP, st);
+  const void* sp = (const void*)(b + pl->off_spos);
+  const unsigned long long* si = (const unsigned long long*)(b + pl->off_sidx);
+  const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
+  const C2<Tg>* adj = (const C2<Tg>*)(b + pl->off_grid);
+  C2<Tg>* out = (C2<Tg>*)(b + pl->off_interp);
+  switch (pl->w) {
+#define RW_INTERP_CASE(W)                                                                     \
+    case W:                                                                                   \
+      hipLaunchKernelGGL((k_interp_tiles<Tg, W>), grid, dim3(256), lds, st, sp, si, so, g,   \
+                         pl->beta, pair0, adj, out);                                          \
+      break;
+    RW_INTERP_CASE(4) RW_INTERP_CASE(5) RW_INTERP_CASE(6) RW_INTERP_CASE(7) RW_INTERP_CASE(8)
+    RW_INTERP_CASE(9) RW_INTERP_CASE(10) RW_INTERP_CASE(11) RW_INTERP_CASE(12)
+    RW_INTERP_CASE(13) RW_INTERP_CASE(14) RW_INTERP_CASE(15) RW_INTERP_CASE(16)
+#undef RW_INTERP_CASE
+    default: return fail(RW_ERR_SHAPE, "spread_width must be in [4, 16]");
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status interp_tiles(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  if (pl->cfg.precision == RW_PREC_FP64) return interp_tiles_t<double>(pl, ws, st, pair0, npairs);
+  return interp_tiles_t<float>(pl, ws, st, pair0, npairs);
 }
 
 rw_status bin_and_spread(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
@@ -450,12 +490,17 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   }
   pl->rec_chunk = 16384;
   {
-    // launch groups of whole pairs whose secondary-ray records fit in 96 GiB
+    // launch groups of whole pairs whose secondary-ray records fit in 96 GiB; when
+    // all pairs fit in one group with the tiled interpolation's per-record
+    // index and results as well, the backward uses that path
     const size_t rec_bytes = (size_t)pl->R2 * pl->emit * 2 * (pl->sz_cg + (dbl_g ? 16 : 8));
+    const size_t tiled_bytes = rec_bytes + (size_t)pl->R2 * pl->emit * (8 + 3 * pl->sz_cg);
     const size_t budget = (size_t)96 << 30;
+    pl->tiled_interp = cfg->batched && tiled_bytes * pl->n_pairs <= budget;
     size_t gp = std::max<size_t>(1, budget / std::max<size_t>(rec_bytes, 1));
     pl->group_pairs = (int)std::min<size_t>(gp, (size_t)pl->n_pairs);
     if (!cfg->batched) pl->group_pairs = 1;
+    if (pl->tiled_interp) pl->group_pairs = pl->n_pairs;
   }
 
   // host copies of the constant tables
@@ -542,7 +587,13 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     if (eb == hipSuccess)                                                                       \
       eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread_tiles<double, W>),       \
                                hipFuncAttributeMaxDynamicSharedMemorySize,                     \
-                               (int)(160 * 1024 - spread_static_lds(sizeof(double), W)));
+                               (int)(160 * 1024 - spread_static_lds(sizeof(double), W)));       \
+    if (ea == hipSuccess)                                                                       \
+      ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_tiles<float, W>),        \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);         \
+    if (eb == hipSuccess)                                                                       \
+      eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_tiles<double, W>),       \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
     RW_ATTR(4) RW_ATTR(5) RW_ATTR(6) RW_ATTR(7) RW_ATTR(8) RW_ATTR(9) RW_ATTR(10) RW_ATTR(11)
     RW_ATTR(12) RW_ATTR(13) RW_ATTR(14) RW_ATTR(15) RW_ATTR(16)
 #undef RW_ATTR
@@ -602,6 +653,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     pl->off_spos = take(nrec * psz);
     pl->off_sval = take(nrec * pl->sz_cg);
     const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
+    pl->off_sidx = take(pl->tiled_interp ? nrec * 8 : 0);
+    pl->off_interp = take(pl->tiled_interp ? nrec * 3 * pl->sz_cg : 0);
     pl->off_cnt = take(nk * sizeof(unsigned int));
     pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
     pl->off_cur = take(nk * sizeof(unsigned long long));
@@ -788,6 +841,7 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   }
   DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
   a.adj = b + pl->off_grid;
+  a.interp = pl->tiled_interp ? (const void*)(b + pl->off_interp) : nullptr;
   a.want_lens = want_lens ? 1 : 0;
   a.stats = nullptr;
   for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
@@ -798,6 +852,10 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
       s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
     }
     if (s != RW_OK) return s;
+    if (pl->tiled_interp) {
+      s = interp_tiles(pl, ws, st, pair0, ppg);
+      if (s != RW_OK) return s;
+    }
     const size_t nr = (size_t)ppg * pl->R2;
     a.ray0 = (size_t)pair0 * pl->R2;
     a.nray = nr;

@@ -143,6 +143,98 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// ------------------------------------------ type-2 interpolation, tiled ---
+// Cogradient of every secondary-ray record of the forward (sorted by bin):
+// the sensor-grid cogradient B interpolated with the ES kernel at the record's
+// grid coordinate, and with the kernel's derivative along x and along y.  One
+// block per 2 x 2 bins stages every grid cell its records' footprints reach
+// in LDS; one lane per record; results go to the record's slot.
+__host__ __device__ constexpr int interp_side(int bin, int w) { return 2 * bin + 2 * ((w + 1) / 2); }
+
+template <class Tg, int w>
+__global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
+                                                      const unsigned long long* srt_idx,
+                                                      const unsigned long long* offsets,
+                                                      BinGeom g, double beta, int pair0,
+                                                      const C2<Tg>* adj, C2<Tg>* out) {
+  using U = typename RecPos<Tg>::T;
+  extern __shared__ unsigned char s_raw[];
+  C2<Tg>* cells = (C2<Tg>*)s_raw;
+  __shared__ unsigned long long s_beg[4], s_pre[5];
+  constexpr int half = (w + 1) / 2;
+  const int side = interp_side(g.bin, w);
+  const int nsb = g.nb / 2;
+  const int pair = pair0 + blockIdx.y;
+  const int sby = blockIdx.x / nsb, sbx = blockIdx.x % nsb;
+  const int X0 = sbx * 2 * g.bin - half, Y0 = sby * 2 * g.bin - half;
+  const C2<Tg>* gp = adj + (size_t)pair * g.nf * g.nf;
+  for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
+    const int cy = i / side, cx = i - cy * side;
+    cells[i] = gp[(size_t)((Y0 + cy) & (g.nf - 1)) * g.nf + ((X0 + cx) & (g.nf - 1))];
+  }
+  if (threadIdx.x < 4) {
+    const int by = sby * 2 + (int)threadIdx.x / 2, bx = sbx * 2 + (int)threadIdx.x % 2;
+    const int k = by * g.nb + bx;
+    const unsigned long long* off = offsets + (size_t)pair * g.keys;
+    s_beg[threadIdx.x] = off[k];
+    s_pre[threadIdx.x + 1] = off[k + 1] - off[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pre[0] = 0;
+    for (int i = 1; i <= 4; ++i) s_pre[i] += s_pre[i - 1];
+  }
+  __syncthreads();
+  const U* pos = (const U*)srt_pos;
+  const Tg tw = (Tg)(2.0 / w), bet = (Tg)beta;
+  const unsigned long long ntot = s_pre[4];
+  for (unsigned long long j = threadIdx.x; j < ntot; j += blockDim.x) {
+    int b = 0;
+    while (j >= s_pre[b + 1]) ++b;
+    const unsigned long long r = s_beg[b] + (j - s_pre[b]);
+    const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+    const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
+    Tg kx[w], dkx[w];
+#pragma unroll
+    for (int i = 0; i < w; ++i) {
+      kx[i] = Tg(0); dkx[i] = Tg(0);
+      const Tg tx = (Tg)((double)(lx0 + i) - gx) * tw;
+      const Tg ax = Tg(1) - tx * tx;
+      if (ax > Tg(0)) {
+        const Tg sx = sqrt(ax);
+        kx[i] = (Tg)exp(bet * (sx - Tg(1)));
+        dkx[i] = -kx[i] * bet * tx / sx * tw;
+      }
+    }
+    double g0r = 0, g0i = 0, dxr = 0, dxi = 0, dyr = 0, dyi = 0;
+    const C2<Tg>* base = cells + (ly0 - Y0) * side + (lx0 - X0);
+#pragma unroll
+    for (int jj = 0; jj < w; ++jj) {
+      const Tg ty = (Tg)((double)(ly0 + jj) - gy) * tw;
+      const Tg ay = Tg(1) - ty * ty;
+      if (!(ay > Tg(0))) continue;
+      const Tg sy = sqrt(ay);
+      const Tg ky = (Tg)exp(bet * (sy - Tg(1)));
+      const Tg dky = -ky * bet * ty / sy * tw;
+      const C2<Tg>* row = base + jj * side;
+      Tg s0r = 0, s0i = 0, s1r = 0, s1i = 0;
+#pragma unroll
+      for (int i = 0; i < w; ++i) {
+        const C2<Tg> v = row[i];
+        s0r += kx[i] * v.re; s0i += kx[i] * v.im;
+        s1r += dkx[i] * v.re; s1i += dkx[i] * v.im;
+      }
+      g0r += (double)(ky * s0r); g0i += (double)(ky * s0i);
+      dxr += (double)(ky * s1r); dxi += (double)(ky * s1i);
+      dyr += (double)(dky * s0r); dyi += (double)(dky * s0i);
+    }
+    C2<Tg>* o = out + 3 * srt_idx[r];
+    o[0] = {(Tg)g0r, (Tg)g0i};
+    o[1] = {(Tg)dxr, (Tg)dxi};
+    o[2] = {(Tg)dyr, (Tg)dyi};
+  }
+}
+
 // ---------------------------------------------------- dL/dt -> dphi, dA ---
 template <class Tg>
 __global__ void k_dmaps(const float* phase, const float* amp, const C2<Tg>* gt, float* dphi,

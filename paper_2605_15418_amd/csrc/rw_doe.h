@@ -565,11 +565,13 @@ __device__ __forceinline__ void interp_adj_pair(const DevCfg& cfg,
 
 // Cogradients of one wavelet's inputs (its weight w, phase, grid frequencies and
 // obliquity) from the interpolated sensor-grid cogradient; called by both lanes
-// of a pair with identical arguments.
+// of a pair with identical arguments.  The interpolation comes from the tiled
+// pass when it covered this record (record slot `slot`, non-zero forward value),
+// else it is done here.
 template <class Prec>
 __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const RayCtx& c, int jx,
                                                      int jy, C2<typename Prec::Tp> w, int h,
-                                                     WaveletAdj& wa, Secondary& sec) {
+                                                     size_t slot, WaveletAdj& wa, Secondary& sec) {
   using Tp = typename Prec::Tp;
   using Tg = typename Prec::Tg;
   const DevCfg& cfg = *a.cfg;
@@ -579,11 +581,24 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
   const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
   const C2<Tp> cv = (w * e) * (Tp)dza;
   C2<double> g0, dx, dy;
-  const Tp gx = grid_coord(wx, cfg.nf), gy = grid_coord(wy, cfg.nf);
-  if (cfg.w <= 8)
-    interp_adj_pair<Prec, 8>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
-  else
-    interp_adj_pair<Prec, 16>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
+  bool tiled = false;
+  if (a.interp) {
+    const C2<Tg> rv = ((const C2<Tg>*)a.rec_val)[slot];
+    tiled = rv.re != Tg(0) || rv.im != Tg(0);
+  }
+  if (tiled) {
+    const C2<Tg>* q = (const C2<Tg>*)a.interp + 3 * slot;
+    const C2<Tg> q0 = q[0], q1 = q[1], q2 = q[2];
+    g0 = {(double)q0.re, (double)q0.im};
+    dx = {(double)q1.re, (double)q1.im};
+    dy = {(double)q2.re, (double)q2.im};
+  } else {
+    const Tp gx = grid_coord(wx, cfg.nf), gy = grid_coord(wy, cfg.nf);
+    if (cfg.w <= 8)
+      interp_adj_pair<Prec, 8>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
+    else
+      interp_adj_pair<Prec, 16>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
+  }
   const C2<double> cd = {(double)cv.re, (double)cv.im};
   const double cell = cfg.nf / (2.0 * RW_PI);
   wa.g_wx = -(cd.re * dx.re + cd.im * dx.im) * cell;
@@ -651,6 +666,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
       const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
+      const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
@@ -693,7 +709,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               }
               WaveletAdj wa;
               Secondary sec;
-              if (ok) ok = wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, wa, sec);
+              if (ok)
+                ok = wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
               if (ok) {
                 C2<double> gU;
                 if (cfg.sampling == 0) {
@@ -765,7 +782,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
             WaveletAdj wa;
             Secondary sec;
-            if (wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, wa, sec)) {
+            const size_t slot = slot0 + (size_t)((jx + M / 2) * M + (jy + M / 2));
+            if (wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, slot, wa, sec)) {
               const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
               const double rr = (double)ref.re, ri = (double)ref.im;
               out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};

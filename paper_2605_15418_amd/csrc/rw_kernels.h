@@ -221,6 +221,8 @@ struct DoeArgs {
   int acc_side;
   RayCtx* ctx;               // [n_total] frame and wavevectors at the DOE hit (alive rays)
   void* dlist;               // per block [N]: (bin, spectrum cogradient) of each draw
+  const void* interp;        // C2<Tg> [n_slots][3] sensor-grid cogradient at each record
+                             // (value, d/dx, d/dy), or null: interpolate in the kernel
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
@@ -521,7 +523,8 @@ template <class Tg>
 __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const void* rec_val,
                                                      size_t per_pair, int chunk, BinGeom g,
                                                      int pair0, unsigned long long* cursor,
-                                                     void* srt_pos, void* srt_val) {
+                                                     void* srt_pos, void* srt_val,
+                                                     unsigned long long* srt_idx) {
   using U = typename RecPos<Tg>::T;
   extern __shared__ unsigned int s_h[];                 // [keys] counts, then [keys] bases
   unsigned long long* s_base = (unsigned long long*)(s_h + ((g.keys + 1) & ~1));
@@ -557,6 +560,7 @@ __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const 
     op[2 * o] = px;
     op[2 * o + 1] = py;
     ov[o] = v;
+    if (srt_idx) srt_idx[o] = r;
   }
 }
 

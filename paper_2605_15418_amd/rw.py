@@ -24,7 +24,8 @@ STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STA
 EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
             "rw_last_error", "rw_set_profiling", "rw_get_profile")
-STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd")
+STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd",
+          "interp")
 
 
 class rw_surface(ctypes.Structure):
@@ -58,7 +59,7 @@ class rw_config(ctypes.Structure):
 
 
 class rw_profile(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_uint64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("launches", ctypes.c_uint64 * len(STAGES))]
 
 
 class rw_stats(ctypes.Structure):
