@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
           const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
           const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
-          const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+          const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
           put_record<Prec>(a, slot0 + Lb, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
           ++n_sec;
         }
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           put_zero<Tg>(a, slot0 + i);
           continue;
         }
-        const C2<Tp> cv = (w * cis<Tp>(wrap_2pi(phi0))) * (Tp)dza;
+        const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
         put_record<Prec>(a, slot0 + i, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
         ++n_sec;
       }
@@ -578,7 +578,7 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
   Tp phi0, wx, wy;
   double dza;
   if (!secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) return false;
-  const C2<Tp> e = cis<Tp>(wrap_2pi(phi0));
+  const C2<Tp> e = wavelet_cis<Prec>(phi0);
   const C2<Tp> cv = (w * e) * (Tp)dza;
   C2<double> g0, dx, dy;
   bool tiled = false;

@@ -17,9 +17,28 @@ namespace rw {
 
 constexpr int kThreads = 256;
 
-struct PrecFP64 { using Tt = double; using Tf = double; using Tp = double; using Tg = double; };
-struct PrecMIXED { using Tt = double; using Tf = float; using Tp = double; using Tg = float; };
-struct PrecFP32 { using Tt = float; using Tf = float; using Tp = float; using Tg = float; };
+// Tt: trace; Tf: patch spectrum; Tp: optical path and wavelet phase; Tg: sensor
+// grid; Te: sine / cosine of the wavelet phase after its reduction to [0, 2 pi)
+// in Tp (an FP32 evaluation of a reduced angle is accurate to ~1e-7 rad).
+struct PrecFP64 {
+  using Tt = double; using Tf = double; using Tp = double; using Tg = double; using Te = double;
+};
+struct PrecMIXED {
+  using Tt = double; using Tf = float; using Tp = double; using Tg = float; using Te = float;
+};
+struct PrecFP32 {
+  using Tt = float; using Tf = float; using Tp = float; using Tg = float; using Te = float;
+};
+
+// e^{i phi} of a wavelet phase: reduced in Tp, evaluated in Te.
+template <class Prec>
+__device__ __forceinline__ C2<typename Prec::Tp> wavelet_cis(typename Prec::Tp phi) {
+  using Te = typename Prec::Te;
+  using Tp = typename Prec::Tp;
+  Te s, c;
+  sincos_any((Te)wrap_2pi(phi), &s, &c);
+  return {(Tp)c, (Tp)s};
+}
 
 struct DevCfg {
   int n_surf, s_doe, n_pairs, n_field, R, R2, P, M, N, Q, nf, w, sampling, H, W, n_params;
