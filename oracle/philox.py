@@ -65,3 +65,32 @@ def draw_uniforms(seed, pair, ray_ids, n_draws, stream=0):
     ctr[..., 3] = np.uint32(stream)
     out = philox4x32_10(ctr, key).reshape(r.shape[0], nblk * 4)[:, :n_draws]
     return word_to_uniform(out)
+
+
+# Streams of the Gumbel-softmax straight-through estimator (G2).  Per draw i of
+# a ray, the largest perturbed log-probability G*_i takes its uniform from
+# counter (i >> 2, ray, pair, 2), word i & 3; the unconditioned Gumbel of bin k
+# from counter (k, ray, pair, 0x10000 | (i >> 2)), word i & 3.
+STREAM_G2_TOP = 2
+STREAM_G2_BIN = 0x10000
+
+
+def g2_top_uniforms(seed, pair, ray_ids, n_draws):
+    """Uniforms u*[r, i] of the top Gumbel of every draw."""
+    return draw_uniforms(seed, pair, ray_ids, n_draws, stream=STREAM_G2_TOP)
+
+
+def g2_bin_uniforms(seed, pair, ray_ids, n_draws, n_bins):
+    """Uniforms u[r, i, k] of the per-bin Gumbels of every draw."""
+    key = seed_key(seed)
+    nblk = (n_draws + 3) // 4
+    r = np.asarray(ray_ids, dtype=np.uint32)
+    k = np.arange(n_bins, dtype=np.uint32)
+    b = np.arange(nblk, dtype=np.uint32)
+    ctr = np.zeros((r.shape[0], n_bins, nblk, 4), dtype=np.uint32)
+    ctr[..., 0] = k[None, :, None]
+    ctr[..., 1] = r[:, None, None]
+    ctr[..., 2] = np.uint32(pair)
+    ctr[..., 3] = np.uint32(STREAM_G2_BIN) | b[None, None, :]
+    out = philox4x32_10(ctr, key).reshape(r.shape[0], n_bins, nblk * 4)[:, :, :n_draws]
+    return word_to_uniform(out).transpose(0, 2, 1)

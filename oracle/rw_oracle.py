@@ -28,7 +28,7 @@ import math
 import numpy as np
 import torch
 
-from .philox import draw_uniforms
+from .philox import draw_uniforms, g2_bin_uniforms, g2_top_uniforms
 
 DT = torch.float64
 CT = torch.complex128
@@ -503,6 +503,9 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     jy = jj % M
     Kus = Ku[rr, jy, jx]
     Kvs = Kv[rr, jy, jx]
+    if sampling != "full" and cfg.get("grad", "G1") == "G2":
+        w, Kus, Kvs = _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w, Kus, Kvs,
+                                        rr, valid, sampling, M, Nd)
     kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs
     kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
     ds = (Kus[:, None] * u[rr] + Kvs[:, None] * v[rr] + kz[:, None] * nrm[rr]) / k_out
@@ -523,6 +526,82 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
                    J=J, amp=amp.detach(), phi0=phi0.detach(), wx=wx.detach(),
                    wy=wy.detach(), w=w.detach(), frame=(u.detach(), v.detach(), nrm.detach()))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Gumbel-softmax straight-through relaxation of the draws (reparameterised
+# sampling, Fig. 1c; G2).  Per draw i the hard one-hot y_hard(J_i) is kept in
+# value while the gradient flows through
+#     y_soft = softmax((log p + z_i) / tau),
+# z_i the Gumbel perturbations of the replica of p that draw i came from,
+# generated conditioned on argmax = J_i: the maximum G*_i = log sum p + Gumbel
+# (from its own uniform) sits at J_i, every other bin takes an unconditioned
+# Gumbel g_k = log p_k + Gumbel truncated below G*_i,
+#     g_k = -log(exp(-G*_i) + exp(-(log p_k + Gumbel))),
+# (the top-down construction of Maddison, Tarlow & Minka, "A* sampling", 2014),
+# and z = g - log p is held fixed (noise).  The relaxed weight and wavevector
+# of the draw are sum_k y_k w_k and sum_k y_k K_k with
+#     y = y_hard - stopgrad(y_soft) + y_soft.
+# READING: tau = 1 unless cfg["tau"] says otherwise; both the amplitude and the
+# wavevector are relaxed (the paper's softmax carries "the full scattering
+# wavevector distribution").  Parity unpinned beyond this construction (a
+# surrogate gradient has no finite-difference truth); pinned limits: G2 == G1
+# for uniform sampling, and G2 -> G1 as tau -> 0.
+# ----------------------------------------------------------------------------
+def conditional_gumbels(logp, J, u_top, u_bin):
+    """Perturbed log-probabilities phi[r, i, k] whose maximum over k is at J[r, i]:
+    logp [R, K] (-inf where p = 0), J [R, N], uniforms u_top [R, N], u_bin [R, N, K]."""
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        lse = np.log(np.sum(np.exp(logp), axis=1))                       # log sum p
+        gstar = lse[:, None] - np.log(-np.log(u_top))                    # [R, N]
+        ghat = logp[:, None, :] - np.log(-np.log(u_bin))                 # [R, N, K]
+        phi = -np.logaddexp(-gstar[:, :, None], -ghat)
+    np.put_along_axis(phi, J[:, :, None], gstar[:, :, None], axis=2)
+    return phi
+
+
+def _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w_hard, Kus, Kvs, rr, valid,
+                      sampling, M, Nd):
+    R = Utf.shape[0]
+    tau = float(cfg.get("tau", 1.0))
+    Kuf = Ku.transpose(1, 2).reshape(R, M * M)
+    Kvf = Kv.transpose(1, 2).reshape(R, M * M)
+    absU = Utf.abs()
+    live = propf & (absU > 0) if sampling == "mag" else propf
+    if sampling == "mag":
+        S = torch.where(propf, absU, torch.zeros((), dtype=DT)).sum(1)
+        logp = torch.log(torch.where(live, absU, torch.ones_like(absU))) - torch.log(
+            torch.where(S > 0, S, torch.ones_like(S)))[:, None]
+        w_all = Utf * (S[:, None] / (M * M * Nd * torch.where(live, absU, torch.ones_like(absU))))
+    else:
+        nprop = propf.sum(1).to(DT)
+        logp = -torch.log(torch.where(nprop > 0, nprop, torch.ones_like(nprop)))[:, None] * \
+            torch.ones_like(absU)
+        w_all = Utf * (nprop[:, None] / (M * M * Nd))
+    w_all = torch.where(live, w_all, torch.zeros_like(w_all))
+    neg_inf = torch.full((), -math.inf, dtype=DT)
+    logp = torch.where(live, logp, neg_inf)                          # [R, K]
+    # Gumbel perturbations conditioned on argmax = J (numbers: no gradient)
+    ut = g2_top_uniforms(cfg["seed"], pair, ray_ids, Nd)                 # [R, N]
+    ub = g2_bin_uniforms(cfg["seed"], pair, ray_ids, Nd, M * M)          # [R, N, K]
+    lp = logp.detach().numpy()
+    Jc = np.maximum(J, 0)
+    phi = conditional_gumbels(lp, Jc, ut, ub)
+    with np.errstate(invalid="ignore"):
+        z = np.where(np.isfinite(lp)[:, None, :], phi - lp[:, None, :], 0.0)
+    zt = torch.as_tensor(z)
+    y_soft = torch.softmax((logp[:, None, :] + zt) / tau, dim=2)         # [R, N, K]
+    y_hard = torch.zeros_like(y_soft)
+    y_hard.scatter_(2, torch.as_tensor(Jc)[:, :, None], 1.0)
+    y = y_hard - y_soft.detach() + y_soft
+    a = (y * w_all[:, None, :]).sum(2).reshape(-1)
+    Kr = (y * Kuf[:, None, :]).sum(2).reshape(-1)
+    Kv_r = (y * Kvf[:, None, :]).sum(2).reshape(-1)
+    ok = valid & (w_hard != 0)
+    a = torch.where(ok, a, torch.zeros_like(a))
+    Kr = torch.where(ok, Kr, Kus)
+    Kv_r = torch.where(ok, Kv_r, Kvs)
+    return a, Kr, Kv_r
 
 
 # ----------------------------------------------------------------------------

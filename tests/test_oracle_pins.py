@@ -460,3 +460,74 @@ def test_autograd_gradient_matches_central_differences(sampling):
             ref = g[name][y, x]
             assert abs(fd - ref) <= 1e-6 * np.abs(g[name]).max() + 1e-4 * abs(fd), \
                 (name, y, x, fd, ref)
+
+
+# ----------------------------------------------- G2 (straight-through) ------
+def test_conditional_gumbels_have_argmax_j_and_iid_gumbel_marginals():
+    """Top-down conditional Gumbels (Maddison, Tarlow & Minka 2014): with J drawn
+    from p, (J, phi) has the law of (argmax, values) of log p plus iid Gumbel(0)
+    noise, so every phi_k - log p_k is Gumbel(0) and the argmax is J."""
+    from scipy import stats
+    rng = np.random.default_rng(21)
+    K, N = 10, 20000
+    p = rng.uniform(0.05, 1.0, K)
+    p /= p.sum()
+    logp = np.log(p)[None, :]
+    u = philox.draw_uniforms(5, 3, [7], N)[0]
+    J, _ = O.draw_bins(p[None, :], np.ones((1, K), bool), u[None, :], "mag")
+    ut = philox.g2_top_uniforms(5, 3, [7], N)
+    ub = philox.g2_bin_uniforms(5, 3, [7], N, K)
+    phi = O.conditional_gumbels(logp, J, ut, ub)
+    assert np.array_equal(np.argmax(phi, axis=2), J)
+    noise = (phi - logp[:, None, :])[0]
+    for k in range(K):
+        ks = stats.kstest(noise[:, k], stats.gumbel_r.cdf)
+        assert ks.pvalue > 1e-3, (k, ks)
+    assert abs(noise.mean() - np.euler_gamma) < 0.02
+    assert abs(noise.var() - math.pi ** 2 / 6) < 0.05
+
+
+def test_straight_through_gradient_is_the_softmax_jacobian_of_the_scores():
+    """y = y_hard - stopgrad(y_soft) + y_soft keeps y_hard in value and passes
+    dL/dlog p_k = (1/tau) y_k (g_k - <y, g>) with g = dL/dy."""
+    rng = np.random.default_rng(4)
+    K, tau = 9, 0.7
+    logp = torch.tensor(np.log(rng.dirichlet(np.ones(K))), requires_grad=True)
+    z = torch.tensor(-np.log(-np.log(rng.uniform(size=K))))
+    c = torch.tensor(rng.normal(size=K))
+    ys = torch.softmax((logp + z) / tau, dim=0)
+    yh = torch.zeros(K, dtype=torch.float64)
+    yh[int(torch.argmax(logp + z))] = 1.0
+    y = yh - ys.detach() + ys
+    assert torch.equal(y.detach(), yh) or float((y.detach() - yh).abs().max()) < 1e-15
+    (c * y).sum().backward()
+    yv = ys.detach().numpy()
+    expect = (1.0 / tau) * yv * (c.numpy() - (yv * c.numpy()).sum())
+    assert np.allclose(logp.grad.numpy(), expect, rtol=1e-12, atol=1e-15)
+
+
+def _g2_case(sampling, grad, tau=1.0):
+    from rwcases import oracle_param_values, small_hologram
+    system, cfg, maps = small_hologram(sampling=sampling, rays=6, N=16, n_lambda=1,
+                                       n_field_side=1)
+    cfg = dict(cfg, grad=grad, tau=tau)
+    return O.loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                           maps["amp"].astype(np.float64), oracle_param_values(system),
+                           maps["target"].astype(np.float64))
+
+
+def test_g2_equals_g1_for_uniform_sampling_and_tends_to_it_as_tau_vanishes():
+    """p_uni does not depend on the DOE, so the softmax path carries nothing;
+    as tau -> 0 the soft sample tends to the hard one-hot and its Jacobian
+    vanishes.  Both limits of the relaxed estimator reduce to frozen draws."""
+    L1, g1, _, _ = _g2_case("uni", "G1")
+    L2, g2, _, _ = _g2_case("uni", "G2")
+    assert L1 == L2
+    for k in g1:
+        assert np.array_equal(g1[k], g2[k]), k
+    L1, g1, _, _ = _g2_case("mag", "G1")
+    L3, g3, _, _ = _g2_case("mag", "G2", tau=1e-6)
+    for k in g1:
+        assert np.linalg.norm(g3[k] - g1[k]) <= 1e-9 * np.linalg.norm(g1[k]), k
+    _, g4, _, _ = _g2_case("mag", "G2")
+    assert np.linalg.norm(g4["phase"] - g1["phase"]) > 1e-3 * np.linalg.norm(g1["phase"])
