@@ -98,6 +98,14 @@ typedef struct {
 
 enum { RW_SAMPLE_MAG = 0, RW_SAMPLE_UNI = 1, RW_SAMPLE_FULL = 2 };
 enum { RW_PREC_FP64 = 0, RW_PREC_MIXED = 1, RW_PREC_FP32 = 2 };
+/* Gradient of the Monte Carlo draws (reparameterised sampling, Fig. 1c):
+ * G1: the a.e. derivative with the drawn bins held fixed;
+ * G2: Gumbel-softmax straight-through -- per draw the hard one-hot sample keeps its
+ *     value while the gradient flows through softmax((log p + z) / tau), z the
+ *     replica's Gumbel perturbations regenerated conditioned on the drawn bin; both
+ *     the weight and the wavevector are relaxed.  Differs from G1 only for p ~ |U~|
+ *     (MAG); needs the sensor directly after the DOE. */
+enum { RW_GRAD_G1 = 0, RW_GRAD_G2 = 1 };
 
 typedef struct {
   int n_lambda;
@@ -121,6 +129,8 @@ typedef struct {
                                        0: one launch per pair (plain comparator form)  */
   int spread_width;                 /* NUFFT kernel width w, 0 = precision default      */
   uint64_t seed;                    /* Philox key of the secondary-ray draws            */
+  int grad;                         /* RW_GRAD_*                                        */
+  double tau;                       /* G2 softmax temperature (> 0)                     */
 } rw_config;
 
 typedef struct rw_plan rw_plan;

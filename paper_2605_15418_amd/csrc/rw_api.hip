@@ -76,6 +76,7 @@ struct rw_plan {
   int acc_side;             // side of the block-private dL/dt accumulator
   int emit;                 // record slots per ray
   int group_pairs;          // pairs per launch group (memory-bounded)
+  bool g2;                  // straight-through gradient of p_mag draws in the backward
   bool tiled_interp;        // one launch group: the backward interpolates the records
                             // of the forward tile by tile
   BinGeom bg;
@@ -94,7 +95,7 @@ struct rw_plan {
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
-      off_interp, total;
+      off_interp, off_g2, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -422,6 +423,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     return fail(RW_ERR_SHAPE, "empty ray grid, wavelength or field list");
   if (cfg->sampling < 0 || cfg->sampling > 2 || cfg->precision < 0 || cfg->precision > 2)
     return fail(RW_ERR_INVALID_ARG, "bad sampling or precision");
+  if (cfg->grad != RW_GRAD_G1 && cfg->grad != RW_GRAD_G2)
+    return fail(RW_ERR_INVALID_ARG, "bad gradient mode");
+  if (cfg->grad == RW_GRAD_G2 && !(cfg->tau > 0.0))
+    return fail(RW_ERR_INVALID_ARG, "the G2 temperature must be positive");
   if (cfg->sampling != RW_SAMPLE_FULL && (cfg->n_ssr < 1 || cfg->n_ssr > 2048))
     return fail(RW_ERR_SHAPE, "n_ssr must be in [1, 2048]");
   if (doe->H < 1 || doe->W < 1 || !(doe->pitch > 0))
@@ -465,6 +470,12 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   for (int i = 0; i < n_params; ++i)
     if (params[i].surface == s_doe && params[i].field != RW_PARAM_GAP) pl->planar_doe = false;
   pl->has_post = s_doe + 1 < n_surf;
+  // G2 differs from G1 only for p ~ |U~|
+  pl->g2 = cfg->grad == RW_GRAD_G2 && cfg->sampling == RW_SAMPLE_MAG;
+  if (pl->g2 && pl->has_post) {
+    delete pl;
+    return fail(RW_ERR_UNSUPPORTED, "the G2 gradient needs the sensor directly after the DOE");
+  }
   pl->base_sensor_z = cfg->sensor_z;
   const bool dbl_f = cfg->precision == RW_PREC_FP64;
   const bool dbl_g = cfg->precision == RW_PREC_FP64;
@@ -512,6 +523,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   dc.n_params = n_params;
   dc.pitch = doe->pitch; dc.x0 = doe->x0; dc.y0 = doe->y0;
   dc.inv_pitch = 1.0 / doe->pitch;
+  dc.grad = cfg->grad;
+  dc.tau = cfg->tau > 0.0 ? cfg->tau : 1.0;
   dc.planar = pl->planar_doe ? 1 : 0;
   dc.launch_z = cfg->launch_z; dc.launch_half = cfg->launch_half; dc.psf_pitch = cfg->psf_pitch;
   dc.beta = pl->beta;
@@ -639,6 +652,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
+  pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M / 2) *
+                                 sizeof(double)
+                           : 0);
   pl->off_dlist = take(cfg->sampling == RW_SAMPLE_FULL
                            ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf);
   pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
@@ -842,6 +858,7 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
   a.adj = b + pl->off_grid;
   a.interp = pl->tiled_interp ? (const void*)(b + pl->off_interp) : nullptr;
+  a.g2 = pl->g2 ? (void*)(b + pl->off_g2) : nullptr;
   a.want_lens = want_lens ? 1 : 0;
   a.stats = nullptr;
   for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {

@@ -104,6 +104,34 @@ struct IncAcc {
   double gp[3], gkin[2], gopl, gzs;
 };
 
+// Cogradient of the emitted secondary direction (planar DOE, sensor next).
+__device__ __forceinline__ void direction_cograd(const DoeArgs& a, const RayCtx& c,
+                                                 const Secondary& sec, const WaveletAdj& wa,
+                                                 double gds[3]) {
+  const DevCfg& cfg = *a.cfg;
+  const DevPair& pr = a.pairs[c.pair];
+  const double ns = pr.n_med[cfg.n_surf];
+  const double k0 = c.k0;
+  const double Xc[3] = {pr.pc[0], pr.pc[1], a.live->sensor_z};
+  // phi0 = k0 (OPL + ns ds . (Xc - p)),  w = k0 ns psf_pitch (ds_x, ds_y)
+  for (int i = 0; i < 3; ++i) gds[i] = k0 * ns * wa.g_phi0 * (Xc[i] - c.p[i]);
+  gds[0] += k0 * ns * cfg.psf_pitch * wa.g_wx;
+  gds[1] += k0 * ns * cfg.psf_pitch * wa.g_wy;
+  gds[2] += wa.g_dz * (sec.dsz >= 0 ? 1.0 : -1.0);
+}
+
+// dL/dK of the secondary's tangential wavevector from its direction cogradient:
+// ds = (Ku u + Kv v + kz n) / k_out, kz = sqrt(k_out^2 - Ku^2 - Kv^2).
+__device__ __forceinline__ void wavevector_cograd(const RayCtx& c, const Secondary& sec,
+                                                  const double gds[3], double& gKu,
+                                                  double& gKv) {
+  const double gu = gds[0] * c.u[0] + gds[1] * c.u[1] + gds[2] * c.u[2];
+  const double gv = gds[0] * c.v[0] + gds[1] * c.v[1] + gds[2] * c.v[2];
+  const double gn = gds[0] * c.n[0] + gds[1] * c.n[1] + gds[2] * c.n[2];
+  gKu = (gu - gn * sec.Ku / sec.kz) / c.k_out;
+  gKv = (gv - gn * sec.Kv / sec.kz) / c.k_out;
+}
+
 __device__ __forceinline__ void incident_from_wavelet(const DoeArgs& a, const RayCtx& c,
                                                       const Secondary& sec,
                                                       const WaveletAdj& wa, IncAcc& acc) {
@@ -112,24 +140,14 @@ __device__ __forceinline__ void incident_from_wavelet(const DoeArgs& a, const Ra
   const double ns = pr.n_med[cfg.n_surf];
   const double k0 = c.k0;
   const double ds[3] = {sec.dsx, sec.dsy, sec.dsz};
-  const double Xc[3] = {pr.pc[0], pr.pc[1], a.live->sensor_z};
-  // phi0 = k0 (OPL + ns ds . (Xc - p)),  w = k0 ns psf_pitch (ds_x, ds_y)
   acc.gopl += k0 * wa.g_phi0;
-  double gds[3];
-  for (int i = 0; i < 3; ++i) {
-    acc.gp[i] -= k0 * ns * wa.g_phi0 * ds[i];
-    gds[i] = k0 * ns * wa.g_phi0 * (Xc[i] - c.p[i]);
-  }
+  for (int i = 0; i < 3; ++i) acc.gp[i] -= k0 * ns * wa.g_phi0 * ds[i];
   acc.gzs += k0 * ns * wa.g_phi0 * ds[2];
-  gds[0] += k0 * ns * cfg.psf_pitch * wa.g_wx;
-  gds[1] += k0 * ns * cfg.psf_pitch * wa.g_wy;
-  gds[2] += wa.g_dz * (ds[2] >= 0 ? 1.0 : -1.0);
-  // ds = (Ku u + Kv v + kz n) / k_out, kz = sqrt(k_out^2 - Ku^2 - Kv^2)
-  const double gu = gds[0] * c.u[0] + gds[1] * c.u[1] + gds[2] * c.u[2];
-  const double gv = gds[0] * c.v[0] + gds[1] * c.v[1] + gds[2] * c.v[2];
-  const double gn = gds[0] * c.n[0] + gds[1] * c.n[1] + gds[2] * c.n[2];
-  acc.gkin[0] += (gu - gn * sec.Ku / sec.kz) / c.k_out;
-  acc.gkin[1] += (gv - gn * sec.Kv / sec.kz) / c.k_out;
+  double gds[3], gKu, gKv;
+  direction_cograd(a, c, sec, wa, gds);
+  wavevector_cograd(c, sec, gds, gKu, gKv);
+  acc.gkin[0] += gKu;
+  acc.gkin[1] += gKv;
 }
 
 // Sum over the 64 lanes of a wave (butterfly: every lane gets the total).

@@ -617,7 +617,168 @@ template <class Tf> struct DrawEnt {
   int k;
 };
 
-template <class Prec, int M, bool kLDS>
+// ------------------------------------------------ G2: straight-through ---
+// Gumbel-softmax straight-through gradient of the p_mag draws (reparameterised
+// sampling, Fig. 1c).  Draw i (bin J_i) keeps its hard value; its gradient flows
+// through y_i = softmax((log p + z_i) / tau), z_i the Gumbel perturbations of
+// its replica, regenerated conditioned on argmax = J_i (top-down construction
+// of Maddison, Tarlow & Minka 2014): the maximum G*_i = Gumbel(u*_i) (log of
+// the total mass is 0) sits at J_i, every other bin k takes the Gumbel
+// log p_k - log(-log u_ik) truncated below G*_i.  With the draw's weight and
+// wavevector relaxed to sum_k y_k w_k and sum_k y_k K_k,
+//     g_ik = dL/dy_ik = <A_i, w_k> + <B_i, K_k>,  A = dL/dw, B = dL/dK,
+//     dL/dlog p_k = (1/tau) sum_i y_ik (g_ik - <y_i, g_i>),
+// and log p_k = log|U~_k| - log S sends X_k/|X_k| (dL/dlog p_k / |X_k| - D / S),
+// D = sum_k dL/dlog p_k, into the spectrum cogradient.
+// Uniforms: u*_i from counter (i >> 2, ray, pair, 2), u_ik from counter
+// (k, ray, pair, 0x10000 | (i >> 2)), word i & 3, k the inverse-CDF bin index.
+struct G2Bin {              // per-bin quantities of one ray
+  bool live;
+  float lp, wr, wi, Ku, Kv;
+};
+
+template <class Tf, int M>
+__device__ __forceinline__ G2Bin g2_bin(const RayCtx& c, const C2<Tf>* buf, const Span* span,
+                                        int k, int P, float logS, float wmag) {
+  constexpr int SM = DoeGeom<M>::SM;
+  const int jx = k / M - M / 2, jy = k % M - M / 2;
+  const Span sp = span[jx + M / 2];
+  G2Bin b;
+  b.live = false;
+  if (jy < sp.lo || jy > sp.hi) return b;
+  const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+  const float m2 = (float)X.re * (float)X.re + (float)X.im * (float)X.im;
+  if (!(m2 > 0.0f)) return b;
+  const float im = rsqrtf(m2);
+  const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+  b.live = true;
+  b.lp = 0.5f * __logf(m2) - logS;                   // log |X| - log S
+  b.wr = (float)U.re * im * wmag;
+  b.wi = (float)U.im * im * wmag;
+  b.Ku = (float)(c.kin_u + c.dk * jx);
+  b.Kv = (float)(c.kin_v + c.dk * jy);
+  return b;
+}
+
+// The four uniforms u_ik of draws 4 gi .. 4 gi + 3 at bin k.
+__device__ __forceinline__ void g2_uniforms(const DevCfg& cfg, const RayCtx& c, int k, int gi,
+                                            float u[4]) {
+  uint32_t w[4] = {(uint32_t)k, (uint32_t)c.r, (uint32_t)c.pair, 0x10000u | (uint32_t)gi};
+  philox4x32_10(w, cfg.key0, cfg.key1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) u[q] = ((float)(w[q] >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+// Perturbed score of bin k in the replica of a draw (max G at bin J).
+__device__ __forceinline__ float g2_phi(float lp, float u, float G, bool at_j) {
+  if (at_j) return G;
+  const float gh = lp - __logf(-__logf(u));
+  // -log(exp(-G) + exp(-gh)) = min(G, gh) - log1p(exp(-|G - gh|))
+  return fminf(G, gh) - log1pf(__expf(-fabsf(G - gh)));
+}
+
+// Per-block draw record of the G2 pass: [0..1] A = dL/dw, [2..3] B = dL/dK,
+// [4] J (-1: no gradient), [5] G*, [6] Z, [7] <y, g>.
+constexpr int kG2Rec = 8;
+
+// Pass 1 (a wave per group of four draws): the softmax normaliser Z_i and
+// <y_i, g_i> of every draw.  Pass 2 (a lane per bin, the S-term layout):
+// dL/dlog p_k into dlg; returns D = sum_k dL/dlog p_k.
+template <class Prec, int M>
+__device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
+                            const C2<typename Prec::Tf>* buf, const Span* span, double S,
+                            double* gd, float* dlg, double* red) {
+  using Tf = typename Prec::Tf;
+  const DevCfg& cfg = *a.cfg;
+  const int N = cfg.N, P = cfg.P;
+  const int t = opaque_tid(), lane = t & 63, wv = t >> 6;
+  constexpr int NW = kDoeThreads / 64;
+  const float logS = (float)log(S);
+  const float wmag = (float)(S / ((double)M * M * N));
+  const float itau = (float)(1.0 / cfg.tau);
+  const int ng = (N + 3) / 4;
+  for (int gi = wv; gi < ng; gi += NW) {
+    float Ar[4], Ai[4], Bu[4], Bv[4], G[4];
+    int J[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * gi + q;
+      J[q] = -1;
+      Ar[q] = Ai[q] = Bu[q] = Bv[q] = 0.0f;
+      G[q] = 0.0f;
+      if (i < N) {
+        const double* e = gd + (size_t)i * kG2Rec;
+        J[q] = (int)e[4];
+        Ar[q] = (float)e[0]; Ai[q] = (float)e[1]; Bu[q] = (float)e[2]; Bv[q] = (float)e[3];
+        const double us = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
+                                       (uint32_t)c.pair, 2u);
+        G[q] = (float)(-log(-log(us)));
+      }
+    }
+    float Z[4] = {0, 0, 0, 0}, Sg[4] = {0, 0, 0, 0};
+    for (int k = lane; k < M * M; k += 64) {
+      const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, logS, wmag);
+      if (!b.live) continue;
+      float u[4];
+      g2_uniforms(cfg, c, k, gi, u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (J[q] < 0) continue;
+        const float phi = g2_phi(b.lp, u[q], G[q], k == J[q]);
+        const float e = __expf((phi - G[q]) * itau);
+        const float g = Ar[q] * b.wr + Ai[q] * b.wi + Bu[q] * b.Ku + Bv[q] * b.Kv;
+        Z[q] += e;
+        Sg[q] += e * g;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double z = wave_sum((double)Z[q]), sg = wave_sum((double)Sg[q]);
+      const int i = 4 * gi + q;
+      if (lane == 0 && i < N) {
+        double* e = gd + (size_t)i * kG2Rec;
+        e[5] = G[q];
+        e[6] = z;
+        e[7] = z > 0.0 ? sg / z : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  double Dsum = 0.0;
+  const int kx = t % M;
+  for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
+    const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+    const int k = (jx + M / 2) * M + (jy + M / 2);
+    const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, logS, wmag);
+    float acc = 0.0f;
+    if (b.live) {
+      for (int gi = 0; gi < ng; ++gi) {
+        float u[4];
+        g2_uniforms(cfg, c, k, gi, u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 4 * gi + q;
+          if (i >= N) break;
+          const double* e = gd + (size_t)i * kG2Rec;
+          const int J = (int)e[4];
+          if (J < 0) continue;
+          const float G = (float)e[5], Z = (float)e[6], yg = (float)e[7];
+          const float phi = g2_phi(b.lp, u[q], G, k == J);
+          const float y = __expf((phi - G) * itau) / Z;
+          const float g = (float)e[0] * b.wr + (float)e[1] * b.wi + (float)e[2] * b.Ku +
+                          (float)e[3] * b.Kv;
+          acc += y * (g - yg);
+        }
+      }
+    }
+    const float dl = acc * itau;
+    dlg[ky * M + kx] = dl;
+    Dsum += dl;
+  }
+  return block_sum_d(Dsum, red);
+}
+
+template <class Prec, int M, bool kLDS, bool kG2>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
   using Tf = typename Prec::Tf;
@@ -689,6 +850,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               J = draw_bin<Tf, M>(buf, s.pref, s.span, Tv, cfg.sampling, lastpos_all);
             }
             DrawEnt<Tf> ent = {{Tf(0), Tf(0)}, -1};
+            double g2r[5] = {0.0, 0.0, 0.0, 0.0, -1.0};      // A, B, J of the G2 record
             if (J >= 0) {
               const int jx = J / M - M / 2, jy = J % M - M / 2;
               const int kidx = (jy & (M - 1)) * SM + (jx & (M - 1));
@@ -726,12 +888,40 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 ent.k = kidx;
                 ent.g = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
                 if (a.want_lens && h == 1) incident_from_wavelet(a, c, sec, wa, acc);
+                if constexpr (kG2) {
+                  if (h == 0) {
+                    double gds[3];
+                    direction_cograd(a, c, sec, wa, gds);
+                    wavevector_cograd(c, sec, gds, g2r[2], g2r[3]);
+                    g2r[0] = wa.g_w.re;
+                    g2r[1] = wa.g_w.im;
+                    g2r[4] = (double)J;
+                  }
+                }
               }
             }
             if (h == 0) dl[i] = ent;
+            if constexpr (kG2) {
+              if (h == 0 && cfg.sampling == 0) {
+                double* e = (double*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M / 2) +
+                            (size_t)i * kG2Rec;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) e[q] = g2r[q];
+              }
+            }
           }
         }
         dLdS = block_sum_d(dLdS, s.red);     // orders every read of buf before the rewrite
+        double D2 = 0.0;                      // G2: sum of dL/dlog p
+        const float* dlg = nullptr;           // G2: dL/dlog p per bin, [ky][kx]
+        if constexpr (kG2) {
+          if (cfg.sampling == 0 && S > 0.0) {
+            double* gd = (double*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M / 2);
+            float* dg = (float*)(gd + (size_t)N * kG2Rec);
+            D2 = g2_passes<Prec, M>(a, c, buf, s.span, S, gd, dg, s.red);
+            dlg = dg;
+          }
+        }
         // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins;
         // each lane keeps one column (M divides the block size)
         {
@@ -747,7 +937,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             if (mag && jy >= sp.lo && jy <= sp.hi) {
               const Tf m2 = X.re * X.re + X.im * X.im;
               if (m2 > Tf(0)) {
-                const Tf f = fS * inv_sqrt(m2);
+                const Tf im = inv_sqrt(m2);
+                Tf f = fS * im;
+                if (kG2 && dlg) f += ((Tf)dlg[ky * M + kx] * im - (Tf)(D2 / S)) * im;
                 v = {X.re * f, X.im * f};
               }
             }

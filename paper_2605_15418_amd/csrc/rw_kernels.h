@@ -46,6 +46,8 @@ struct DevCfg {
   double pitch, x0, y0, launch_z, launch_half, psf_pitch, beta;
   double inv_pitch;
   uint32_t key0, key1;
+  int grad;                // 0: frozen draws (G1), 1: Gumbel-softmax straight-through (G2)
+  double tau;              // G2 temperature
 };
 
 struct DevPair {
@@ -242,6 +244,7 @@ struct DoeArgs {
   void* dlist;               // per block [N]: (bin, spectrum cogradient) of each draw
   const void* interp;        // C2<Tg> [n_slots][3] sensor-grid cogradient at each record
                              // (value, d/dx, d/dy), or null: interpolate in the kernel
+  void* g2;                  // G2 per block: double [N][8] draw data, then [M*M] dL/dlog p
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).

@@ -18,6 +18,7 @@ RW_SURF_ASPHERE, RW_SURF_PLANE = 0, 1
 PARAM_FIELDS = {"curv": 0, "conic": 1, "A4": 2, "A6": 3, "A8": 4, "A10": 5, "gap": 6}
 SAMPLING = {"mag": 0, "uni": 1, "full": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
+GRAD = {"G1": 0, "G2": 1}
 STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",
           4: "RW_ERR_NONFINITE", 5: "RW_ERR_OOM", 6: "RW_ERR_HIP", 7: "RW_ERR_UNSUPPORTED"}
 
@@ -55,7 +56,8 @@ class rw_config(ctypes.Structure):
                 ("psf_center_host", ctypes.POINTER(ctypes.c_double)),
                 ("patch_p", ctypes.c_int), ("pad_factor", ctypes.c_int), ("n_ssr", ctypes.c_int),
                 ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("batched", ctypes.c_int),
-                ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64)]
+                ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("grad", ctypes.c_int), ("tau", ctypes.c_double)]
 
 
 class rw_profile(ctypes.Structure):
@@ -185,6 +187,8 @@ class Plan:
         c.batched = int(bool(batched))
         c.spread_width = int(spread_width)
         c.seed = int(cfg["seed"])
+        c.grad = GRAD[cfg.get("grad", "G1")]
+        c.tau = float(cfg.get("tau", 1.0))
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
                                                  len(prm), ctypes.byref(c), ctypes.byref(h)))

@@ -114,3 +114,39 @@ def test_backward_state_errors(rw):
     plan.forward(vals, ph, am)
     with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
         plan.backward()          # no target in the forward and no dL_dpsf
+
+
+# ------------------------------------------------ G2 (straight-through) -----
+def _g2_case(**kw):
+    system, cfg, maps = small_hologram(sampling="mag", N=16, rays=6, n_lambda=1, n_field_side=3,
+                                       **kw)
+    return system, dict(cfg, grad="G2", tau=1.0), maps
+
+
+def test_g2_mixed_gradients_with_oracle_indices(rw):
+    """Gumbel-softmax straight-through gradient: the GPU's conditional Gumbels,
+    softmax passes and spectrum cogradient against the oracle's autograd of the
+    straight-through construction, on the oracle's draws.  Parity unpinned
+    beyond that construction (no finite-difference truth for a surrogate)."""
+    system, cfg, maps = _g2_case()
+    ref = _oracle_grad(system, cfg, maps)
+    idx = ref[3]
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed", replay=rep), ref, 1e-3)
+
+
+def test_g2_fp64_gradients_own_draws(rw):
+    system, cfg, maps = _g2_case()
+    _check(_gpu_grad(rw, system, cfg, maps, "fp64"), _oracle_grad(system, cfg, maps), 1e-4)
+
+
+def test_g2_differs_from_g1_and_uniform_g2_is_g1(rw):
+    system, cfg, maps = _g2_case()
+    g2 = _gpu_grad(rw, system, cfg, maps, "mixed")
+    g1 = _gpu_grad(rw, system, dict(cfg, grad="G1"), maps, "mixed")
+    assert rel_l2(g2[1], g1[1]) > 1e-2
+    system, cfg, maps = small_hologram(sampling="uni", N=16, rays=6, n_lambda=1, n_field_side=1)
+    a = _gpu_grad(rw, system, dict(cfg, grad="G2"), maps, "mixed")
+    b = _gpu_grad(rw, system, cfg, maps, "mixed")
+    for x, y in zip(a[1:], b[1:]):           # same kernels; atomics order only
+        assert rel_l2(x, y) < 1e-5
