@@ -652,8 +652,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
-  pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M / 2) *
-                                 sizeof(double)
+  pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
+                                 sizeof(float)
                            : 0);
   pl->off_dlist = take(cfg->sampling == RW_SAMPLE_FULL
                            ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf);

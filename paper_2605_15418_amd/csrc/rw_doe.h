@@ -632,14 +632,17 @@ template <class Tf> struct DrawEnt {
 // D = sum_k dL/dlog p_k, into the spectrum cogradient.
 // Uniforms: u*_i from counter (i >> 2, ray, pair, 2), u_ik from counter
 // (k, ray, pair, 0x10000 | (i >> 2)), word i & 3, k the inverse-CDF bin index.
+// With L = -log u, L* = -log u* (so G* = -log L*) and P_k = 1/p_k, the
+// truncated score gives exp((phi_k - G*) / tau) = (1 + P_k L / L*)^(-1/tau)
+// for k != J and 1 at J.
 struct G2Bin {              // per-bin quantities of one ray
   bool live;
-  float lp, wr, wi, Ku, Kv;
+  float P, wr, wi, Ku, Kv;  // 1/p, weight w_k, wavevector K_k
 };
 
 template <class Tf, int M>
 __device__ __forceinline__ G2Bin g2_bin(const RayCtx& c, const C2<Tf>* buf, const Span* span,
-                                        int k, int P, float logS, float wmag) {
+                                        int k, int P, float S, float wmag) {
   constexpr int SM = DoeGeom<M>::SM;
   const int jx = k / M - M / 2, jy = k % M - M / 2;
   const Span sp = span[jx + M / 2];
@@ -652,7 +655,7 @@ __device__ __forceinline__ G2Bin g2_bin(const RayCtx& c, const C2<Tf>* buf, cons
   const float im = rsqrtf(m2);
   const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
   b.live = true;
-  b.lp = 0.5f * __logf(m2) - logS;                   // log |X| - log S
+  b.P = S * im;
   b.wr = (float)U.re * im * wmag;
   b.wi = (float)U.im * im * wmag;
   b.Ku = (float)(c.kin_u + c.dk * jx);
@@ -669,16 +672,15 @@ __device__ __forceinline__ void g2_uniforms(const DevCfg& cfg, const RayCtx& c, 
   for (int q = 0; q < 4; ++q) u[q] = ((float)(w[q] >> 9) + 0.5f) * (1.0f / 8388608.0f);
 }
 
-// Perturbed score of bin k in the replica of a draw (max G at bin J).
-__device__ __forceinline__ float g2_phi(float lp, float u, float G, bool at_j) {
-  if (at_j) return G;
-  const float gh = lp - __logf(-__logf(u));
-  // -log(exp(-G) + exp(-gh)) = min(G, gh) - log1p(exp(-|G - gh|))
-  return fminf(G, gh) - log1pf(__expf(-fabsf(G - gh)));
+// exp((phi - G*) / tau) of a bin that is not the drawn one.
+__device__ __forceinline__ float g2_weight(float P, float u, float inv_ls, float itau, bool unit) {
+  const float x = fmaf(P * -__logf(u), inv_ls, 1.0f);
+  return unit ? __frcp_rn(x) : __expf(-itau * __logf(x));
 }
 
-// Per-block draw record of the G2 pass: [0..1] A = dL/dw, [2..3] B = dL/dK,
-// [4] J (-1: no gradient), [5] G*, [6] Z, [7] <y, g>.
+// Per-block draw record of the G2 pass (floats): [0..1] A = dL/dw, [2..3]
+// B = dL/dK, [4] J (bit pattern of an int, -1: no gradient), [5] 1/L*,
+// [6] 1/Z, [7] <y, g>.
 constexpr int kG2Rec = 8;
 
 // Pass 1 (a wave per group of four draws): the softmax normaliser Z_i and
@@ -687,45 +689,44 @@ constexpr int kG2Rec = 8;
 template <class Prec, int M>
 __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
                             const C2<typename Prec::Tf>* buf, const Span* span, double S,
-                            double* gd, float* dlg, double* red) {
+                            float* gd, float* dlg, double* red) {
   using Tf = typename Prec::Tf;
   const DevCfg& cfg = *a.cfg;
   const int N = cfg.N, P = cfg.P;
   const int t = opaque_tid(), lane = t & 63, wv = t >> 6;
   constexpr int NW = kDoeThreads / 64;
-  const float logS = (float)log(S);
+  const float Sf = (float)S;
   const float wmag = (float)(S / ((double)M * M * N));
   const float itau = (float)(1.0 / cfg.tau);
+  const bool unit = cfg.tau == 1.0;
   const int ng = (N + 3) / 4;
   for (int gi = wv; gi < ng; gi += NW) {
-    float Ar[4], Ai[4], Bu[4], Bv[4], G[4];
+    float Ar[4], Ai[4], Bu[4], Bv[4], IL[4];
     int J[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = 4 * gi + q;
       J[q] = -1;
-      Ar[q] = Ai[q] = Bu[q] = Bv[q] = 0.0f;
-      G[q] = 0.0f;
+      Ar[q] = Ai[q] = Bu[q] = Bv[q] = IL[q] = 0.0f;
       if (i < N) {
-        const double* e = gd + (size_t)i * kG2Rec;
-        J[q] = (int)e[4];
-        Ar[q] = (float)e[0]; Ai[q] = (float)e[1]; Bu[q] = (float)e[2]; Bv[q] = (float)e[3];
+        const float* e = gd + (size_t)i * kG2Rec;
+        J[q] = __float_as_int(e[4]);
+        Ar[q] = e[0]; Ai[q] = e[1]; Bu[q] = e[2]; Bv[q] = e[3];
         const double us = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
                                        (uint32_t)c.pair, 2u);
-        G[q] = (float)(-log(-log(us)));
+        IL[q] = (float)(1.0 / -log(us));
       }
     }
     float Z[4] = {0, 0, 0, 0}, Sg[4] = {0, 0, 0, 0};
     for (int k = lane; k < M * M; k += 64) {
-      const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, logS, wmag);
+      const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, Sf, wmag);
       if (!b.live) continue;
       float u[4];
       g2_uniforms(cfg, c, k, gi, u);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (J[q] < 0) continue;
-        const float phi = g2_phi(b.lp, u[q], G[q], k == J[q]);
-        const float e = __expf((phi - G[q]) * itau);
+        const float e = k == J[q] ? 1.0f : g2_weight(b.P, u[q], IL[q], itau, unit);
         const float g = Ar[q] * b.wr + Ai[q] * b.wi + Bu[q] * b.Ku + Bv[q] * b.Kv;
         Z[q] += e;
         Sg[q] += e * g;
@@ -736,10 +737,10 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
       const double z = wave_sum((double)Z[q]), sg = wave_sum((double)Sg[q]);
       const int i = 4 * gi + q;
       if (lane == 0 && i < N) {
-        double* e = gd + (size_t)i * kG2Rec;
-        e[5] = G[q];
-        e[6] = z;
-        e[7] = z > 0.0 ? sg / z : 0.0;
+        float* e = gd + (size_t)i * kG2Rec;
+        e[5] = IL[q];
+        e[6] = z > 0.0 ? (float)(1.0 / z) : 0.0f;
+        e[7] = z > 0.0 ? (float)(sg / z) : 0.0f;
       }
     }
   }
@@ -749,7 +750,7 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
   for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
     const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
     const int k = (jx + M / 2) * M + (jy + M / 2);
-    const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, logS, wmag);
+    const G2Bin b = g2_bin<Tf, M>(c, buf, span, k, P, Sf, wmag);
     float acc = 0.0f;
     if (b.live) {
       for (int gi = 0; gi < ng; ++gi) {
@@ -759,15 +760,12 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
         for (int q = 0; q < 4; ++q) {
           const int i = 4 * gi + q;
           if (i >= N) break;
-          const double* e = gd + (size_t)i * kG2Rec;
-          const int J = (int)e[4];
+          const float* e = gd + (size_t)i * kG2Rec;
+          const int J = __float_as_int(e[4]);
           if (J < 0) continue;
-          const float G = (float)e[5], Z = (float)e[6], yg = (float)e[7];
-          const float phi = g2_phi(b.lp, u[q], G, k == J);
-          const float y = __expf((phi - G) * itau) / Z;
-          const float g = (float)e[0] * b.wr + (float)e[1] * b.wi + (float)e[2] * b.Ku +
-                          (float)e[3] * b.Kv;
-          acc += y * (g - yg);
+          const float y = (k == J ? 1.0f : g2_weight(b.P, u[q], e[5], itau, unit)) * e[6];
+          const float g = e[0] * b.wr + e[1] * b.wi + e[2] * b.Ku + e[3] * b.Kv;
+          acc += y * (g - e[7]);
         }
       }
     }
@@ -903,10 +901,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             if (h == 0) dl[i] = ent;
             if constexpr (kG2) {
               if (h == 0 && cfg.sampling == 0) {
-                double* e = (double*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M / 2) +
-                            (size_t)i * kG2Rec;
+                float* e = (float*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M) +
+                           (size_t)i * kG2Rec;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) e[q] = g2r[q];
+                for (int q = 0; q < 4; ++q) e[q] = (float)g2r[q];
+                e[4] = __int_as_float((int)g2r[4]);
               }
             }
           }
@@ -916,8 +915,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         const float* dlg = nullptr;           // G2: dL/dlog p per bin, [ky][kx]
         if constexpr (kG2) {
           if (cfg.sampling == 0 && S > 0.0) {
-            double* gd = (double*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M / 2);
-            float* dg = (float*)(gd + (size_t)N * kG2Rec);
+            float* gd = (float*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M);
+            float* dg = gd + (size_t)N * kG2Rec;
             D2 = g2_passes<Prec, M>(a, c, buf, s.span, S, gd, dg, s.red);
             dlg = dg;
           }
