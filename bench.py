@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--g2-steps", type=int, default=1,
+                    help="fwd+bwd steps timed with the Gumbel-softmax straight-through gradient")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -204,6 +206,26 @@ def main():
                      "speedup_batched_mixed": value / plain_value}
         log(f"plain FP32: {plain_rec['ms_per_step']:.1f} ms/step")
 
+    # ------------------------------------------------ G2 (straight-through)
+    g2_rec = None
+    if args.g2_steps > 0:
+        log("G2 (Gumbel-softmax straight-through) backward, batched MIXED")
+        p2 = rw.Plan(system, dict(cfg, grad="G2", tau=1.0), precision="mixed", batched=True)
+        p2.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.g2_steps):
+            step(p2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pr2 = p2.profile()
+        g2_rec = {"value": n_rays * args.g2_steps / (t1 - t0), "unit": "rays/s",
+                  "ms_per_step": (t1 - t0) * 1e3 / args.g2_steps, "steps": args.g2_steps,
+                  "tau": 1.0,
+                  "doe_bwd_ms_per_step": round(pr2["doe_bwd"][0] / args.g2_steps, 1)}
+        del p2
+        log(f"G2: {g2_rec['ms_per_step']:.0f} ms/step")
+
     # ---------------------------------------------- error against FP64 form
     check = None
     if not args.no_check:
@@ -274,6 +296,7 @@ def main():
                    "secondary_rays_per_step": records,
                    "secondary_rays_per_s": records * args.steps / (ms_per_step * args.steps / 1e3)},
         "plain_fp32": plain_rec,
+        "g2_straight_through": g2_rec,
         "error_vs_fp64": check,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
         "roofline": roofline,

@@ -198,6 +198,14 @@ typedef struct {
 rw_status rw_set_profiling(rw_plan* plan, int enable);
 rw_status rw_get_profile(rw_plan* plan, rw_profile* out_host);
 
+/* Captured launch sequences.  enable = 1: rw_forward and rw_backward record their
+ * whole launch sequence into a HIP graph the first time they are called with a given
+ * set of pointer arguments (on a capture stream the plan owns) and from then on replay
+ * that graph on the caller's stream; a call with other pointers records anew.  Stage
+ * profiling covers eager calls only.  enable = 0 drops the recorded graphs.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_HIP (from the call that records). */
+rw_status rw_set_graph(rw_plan* plan, int enable);
+
 /* Diagnostic export of the incident ray state at the DOE of the last forward:
  * out [n_rays_total][8] double = (px, py, pz, dx, dy, dz, opl, alive). */
 rw_status rw_export_doe_hits(const rw_plan* plan, const void* workspace, double* out,

@@ -59,6 +59,29 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
+// Arguments a captured launch sequence was recorded with.
+struct GraphKey {
+  const void* p[9];
+  bool operator==(const GraphKey& o) const {
+    for (int i = 0; i < 9; ++i)
+      if (p[i] != o.p[i]) return false;
+    return true;
+  }
+};
+struct GraphState {
+  bool valid = false;
+  GraphKey key{};
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  void reset() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    x = nullptr;
+    g = nullptr;
+    valid = false;
+  }
+};
+
 }  // namespace
 
 struct rw_plan {
@@ -106,6 +129,11 @@ struct rw_plan {
   const float* fwd_amp = nullptr;
   void* fwd_ws = nullptr;
   hipStream_t fwd_stream = nullptr;
+  // captured launch sequences (rw_set_graph)
+  bool graph = false;
+  bool capturing = false;
+  GraphState gfwd, gbwd;
+  hipStream_t cap_st = nullptr;
   // stage timing
   bool prof = false;
   struct Ev { int stage; hipEvent_t a, b; };
@@ -127,12 +155,48 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   StageTimer(rw_plan* p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
-    if (pl->prof) { a = pl->ev_get(); b = pl->ev_get(); (void)hipEventRecord(a, st); }
+    if (pl->prof && !pl->capturing) {
+      a = pl->ev_get(); b = pl->ev_get(); (void)hipEventRecord(a, st);
+    }
   }
   ~StageTimer() {
-    if (pl->prof) { (void)hipEventRecord(b, st); pl->ev_used.push_back({stage, a, b}); }
+    if (a) { (void)hipEventRecord(b, st); pl->ev_used.push_back({stage, a, b}); }
   }
 };
+
+// Replays the launch sequence recorded for `key`, recording it first (on the
+// plan's own capture stream) when the arguments changed.  The launch goes on
+// the caller's stream.
+template <class F>
+rw_status graph_run(rw_plan* pl, GraphState& gs, const GraphKey& key, hipStream_t st,
+                    F enqueue) {
+  if (!gs.valid || !(gs.key == key)) {
+    gs.reset();
+    if (!pl->cap_st) HIPCHK(hipStreamCreateWithFlags(&pl->cap_st, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(pl->cap_st, hipStreamCaptureModeThreadLocal));
+    pl->capturing = true;
+    const rw_status r = enqueue(pl->cap_st);
+    pl->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap_st, &g);
+    if (r != RW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess)
+      return fail(RW_ERR_HIP, std::string("stream capture: ") + hipGetErrorString(e));
+    gs.g = g;
+    const hipError_t ei = hipGraphInstantiate(&gs.x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      gs.reset();
+      return fail(RW_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    gs.key = key;
+    gs.valid = true;
+  }
+  HIPCHK(hipGraphLaunch(gs.x, st));
+  return RW_OK;
+}
 }  // namespace
 
 // ------------------------------------------------------------ dispatch -----
@@ -697,26 +761,29 @@ rw_status rw_plan_destroy(rw_plan* pl) {
   (void)hipFree(pl->d_psi);
   for (auto& e : pl->ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto& e : pl->ev_pool) (void)hipEventDestroy(e);
+  pl->gfwd.reset();
+  pl->gbwd.reset();
+  if (pl->cap_st) (void)hipStreamDestroy(pl->cap_st);
   delete pl;
   return RW_OK;
 }
 
-rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_phase,
-                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
-                     void* ws, size_t ws_bytes, const int32_t* replay_idx, int32_t* idx_out,
-                     void* stream) {
-  if (!pl || !doe_phase || !doe_amp || !psf_out || !ws)
-    return fail(RW_ERR_INVALID_ARG, "null required argument");
-  if (pl->prm.size() > 0 && !lens_params)
-    return fail(RW_ERR_INVALID_ARG, "lens_params required when the plan has lens parameters");
-  if (target && !loss_out) return fail(RW_ERR_INVALID_ARG, "target given without loss_out");
-  if (ws_bytes < pl->total) return fail(RW_ERR_STATE, "workspace smaller than rw_plan_workspace_bytes");
-  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (replay_idx && pl->cfg.sampling == RW_SAMPLE_FULL)
-    return fail(RW_ERR_INVALID_ARG, "replay is meaningless in FULL sampling");
-  hipStream_t st = (hipStream_t)stream;
+rw_status rw_set_graph(rw_plan* pl, int enable) {
+  if (!pl) return fail(RW_ERR_INVALID_ARG, "null plan");
+  pl->graph = enable != 0;
+  if (!pl->graph) {
+    pl->gfwd.reset();
+    pl->gbwd.reset();
+  }
+  return RW_OK;
+}
+
+// Every launch of one forward pass, in stream order.
+static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                             const float* doe_amp, const float* target, float* psf_out,
+                             float* loss_out, void* ws, const int32_t* replay_idx,
+                             int32_t* idx_out, hipStream_t st) {
   char* b = (char*)ws;
-  pl->fwd_done = false;
   const bool dbl_f = pl->cfg.precision == RW_PREC_FP64;
   const bool dbl_g = pl->cfg.precision == RW_PREC_FP64;
   hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, pl->d_cfg, pl->d_base, pl->base_sensor_z,
@@ -776,6 +843,37 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
                        pl->n_pairs, loss_out);
     HIPCHK(hipGetLastError());
   }
+  return RW_OK;
+}
+
+rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
+                     void* ws, size_t ws_bytes, const int32_t* replay_idx, int32_t* idx_out,
+                     void* stream) {
+  if (!pl || !doe_phase || !doe_amp || !psf_out || !ws)
+    return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (pl->prm.size() > 0 && !lens_params)
+    return fail(RW_ERR_INVALID_ARG, "lens_params required when the plan has lens parameters");
+  if (target && !loss_out) return fail(RW_ERR_INVALID_ARG, "target given without loss_out");
+  if (ws_bytes < pl->total) return fail(RW_ERR_STATE, "workspace smaller than rw_plan_workspace_bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (replay_idx && pl->cfg.sampling == RW_SAMPLE_FULL)
+    return fail(RW_ERR_INVALID_ARG, "replay is meaningless in FULL sampling");
+  hipStream_t st = (hipStream_t)stream;
+  pl->fwd_done = false;
+  rw_status r;
+  if (pl->graph) {
+    const GraphKey key = {{(const void*)lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                           ws, replay_idx, idx_out}};
+    r = graph_run(pl, pl->gfwd, key, st, [&](hipStream_t cs) {
+      return fwd_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
+                         replay_idx, idx_out, cs);
+    });
+  } else {
+    r = fwd_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
+                    replay_idx, idx_out, st);
+  }
+  if (r != RW_OK) return r;
   pl->fwd_done = true;
   pl->fwd_target = target;
   pl->fwd_replay = replay_idx;
@@ -830,19 +928,9 @@ rw_status rw_export_doe_hits(const rw_plan* pl, const void* ws, double* out, voi
   return RW_OK;
 }
 
-rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
-                      float* d_lens, void* ws, size_t ws_bytes, void* stream) {
-  if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
-  if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
-  if (ws != pl->fwd_ws || ws_bytes < pl->total)
-    return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");
-  if (!dL_dpsf && !pl->fwd_target)
-    return fail(RW_ERR_STATE, "dL_dpsf is NULL and the forward had no target");
-  const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;
-  if (want_lens && (!pl->planar_doe || pl->has_post))
-    return fail(RW_ERR_UNSUPPORTED,
-                "lens-parameter gradients need a planar DOE followed directly by the sensor");
-  hipStream_t st = (hipStream_t)stream;
+// Every launch of one backward pass, in stream order.
+static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
+                             float* d_lens, void* ws, bool want_lens, hipStream_t st) {
   char* b = (char*)ws;
   const bool dbl = pl->cfg.precision == RW_PREC_FP64;
   const size_t nmap = (size_t)pl->H * pl->W;
@@ -905,6 +993,29 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
                        (const double*)(b + pl->off_lensg), d_lens);
   HIPCHK(hipGetLastError());
   return RW_OK;
+}
+
+rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
+                      float* d_lens, void* ws, size_t ws_bytes, void* stream) {
+  if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
+  if (ws != pl->fwd_ws || ws_bytes < pl->total)
+    return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");
+  if (!dL_dpsf && !pl->fwd_target)
+    return fail(RW_ERR_STATE, "dL_dpsf is NULL and the forward had no target");
+  const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;
+  if (want_lens && (!pl->planar_doe || pl->has_post))
+    return fail(RW_ERR_UNSUPPORTED,
+                "lens-parameter gradients need a planar DOE followed directly by the sensor");
+  hipStream_t st = (hipStream_t)stream;
+  if (pl->graph) {
+    const GraphKey key = {{(const void*)dL_dpsf, d_phase, d_amp, d_lens, ws, pl->fwd_replay,
+                           pl->fwd_target, pl->fwd_phase, pl->fwd_amp}};
+    return graph_run(pl, pl->gbwd, key, st, [&](hipStream_t cs) {
+      return bwd_enqueue(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, want_lens, cs);
+    });
+  }
+  return bwd_enqueue(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, want_lens, st);
 }
 
 }  // extern "C"

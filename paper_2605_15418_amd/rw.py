@@ -24,7 +24,7 @@ STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STA
 
 EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
-            "rw_last_error", "rw_set_profiling", "rw_get_profile")
+            "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph")
 STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd",
           "interp")
 
@@ -92,12 +92,13 @@ def load_library(path=LIB_PATH):
     lib.rw_plan_destroy.argtypes = [vp]
     lib.rw_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.rw_get_profile.argtypes = [vp, ctypes.POINTER(rw_profile)]
+    lib.rw_set_graph.argtypes = [vp, ctypes.c_int]
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
     for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
-                 "rw_get_profile"):
+                 "rw_get_profile", "rw_set_graph"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -256,6 +257,10 @@ class Plan:
         _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
         return {"rays_total": s.rays_total, "rays_alive": s.rays_alive,
                 "secondaries": s.secondaries}
+
+    def set_graph(self, enable=True):
+        """Record the forward / backward launch sequences as HIP graphs and replay them."""
+        _check(self.lib, self.lib.rw_set_graph(self.handle, int(bool(enable))))
 
     def set_profiling(self, enable=True):
         _check(self.lib, self.lib.rw_set_profiling(self.handle, int(bool(enable))))

@@ -168,3 +168,39 @@ def test_invalid_shapes_are_rejected(rw):
     bad = dict(cfg, patch_p=12)
     with pytest.raises(rw.RWError, match="RW_ERR_SHAPE"):
         rw.Plan(system, bad, precision="fp64")
+
+
+def test_graph_replays_match_eager(rw):
+    """Recorded launch sequences (HIP graphs): several forward + backward replays,
+    with eager work and synchronisations between them, against the eager run;
+    changing an argument pointer records anew."""
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    eager = rw.Plan(system, cfg, precision="mixed")
+    psf0, loss0, idx0 = eager.forward(vals, ph, am, target=tg, want_idx=True)
+    g0 = eager.backward()
+    torch.cuda.synchronize()
+    plan = rw.Plan(system, cfg, precision="mixed")
+    plan.set_graph(True)
+    psf = torch.empty_like(psf0)
+    loss = torch.empty_like(loss0)
+    idx = torch.empty_like(idx0)
+    dp, da, dl = (torch.empty_like(x) for x in g0)
+    for rep in range(3):                                     # same pointers: replays
+        plan.forward(vals, ph, am, target=tg, psf_out=psf, loss_out=loss, idx_out=idx)
+        plan.backward(d_phase=dp, d_amp=da, d_lens=dl)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(idx, idx0), rep
+        assert rel_l2(psf.cpu().numpy(), psf0.cpu().numpy()) < 1e-5, rep
+        assert abs(float(loss) - float(loss0)) <= 1e-5 * abs(float(loss0)), rep
+        for a, b in zip((dp, da, dl), g0):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5, rep
+        psf.zero_()
+        dp.zero_()
+    ph2 = ph.clone()                                         # new pointer: records again
+    psf2, _, _ = plan.forward(vals, ph2, am, target=tg)
+    torch.cuda.synchronize()
+    assert rel_l2(psf2.cpu().numpy(), psf0.cpu().numpy()) < 1e-5
