@@ -131,6 +131,14 @@ typedef struct {
   uint64_t seed;                    /* Philox key of the secondary-ray draws            */
   int grad;                         /* RW_GRAD_*                                        */
   double tau;                       /* G2 softmax temperature (> 0)                     */
+  /* Patch classes (curvature bound, Eq. 4): besides patch_p, up to three smaller
+   * patch sides; each ray takes the largest side D = P pitch with
+   * arcsin(D / 2 R_loc) <= curv_eps, R_loc the smallest principal radius of the DOE
+   * surface at the hit (the smallest side when none qualifies).  n_patch_class = 0:
+   * every ray uses patch_p.  Every class satisfies the M rules of patch_p. */
+  int n_patch_class;
+  int patch_class_p[3];
+  double curv_eps;
 } rw_config;
 
 typedef struct rw_plan rw_plan;

@@ -422,6 +422,54 @@ def sensor_field(amp, phi0, wx, wy, Q, chunk=1 << 15):
 # ----------------------------------------------------------------------------
 # One (wavelength, field) pair, end to end.
 # ----------------------------------------------------------------------------
+def local_radius(surf, x, y):
+    """Smallest principal radius of curvature of a rotationally symmetric surface
+    z(r) at (x, y): meridional z'' / (1 + z'^2)^(3/2), sagittal z' / (r (1 + z'^2)^(1/2))
+    (-> z''(0) on axis); infinite for a plane."""
+    rho = x * x + y * y
+    r = torch.sqrt(rho)
+    c, k = surf["c"], surf["k"]
+    A4, A6, A8, A10 = surf["A"]
+    arg = 1.0 - (1.0 + k) * c * c * rho
+    sq = torch.sqrt(torch.where(arg > 0, arg, torch.ones_like(arg)))
+    d1 = c / (2.0 * sq) + 2.0 * A4 * rho + 3.0 * A6 * rho ** 2 + 4.0 * A8 * rho ** 3 \
+        + 5.0 * A10 * rho ** 4                                     # dz/d(rho)
+    d2 = c * (1.0 + k) * c * c / (4.0 * sq ** 3) + 2.0 * A4 + 6.0 * A6 * rho \
+        + 12.0 * A8 * rho ** 2 + 20.0 * A10 * rho ** 3             # d2z/d(rho)2
+    zp = 2.0 * r * d1
+    zpp = 2.0 * d1 + 4.0 * rho * d2
+    km = zpp / (1.0 + zp * zp) ** 1.5
+    ks = torch.where(r > 0, 2.0 * d1 / torch.sqrt(1.0 + zp * zp), zpp)
+    kmax = torch.maximum(km.abs(), ks.abs())
+    return torch.where(kmax > 0, 1.0 / torch.where(kmax > 0, kmax, torch.ones_like(kmax)),
+                       torch.full_like(kmax, math.inf))
+
+
+def patch_classes(cfg):
+    """Candidate patch sides, largest first: patch_p and cfg["patch_classes"]."""
+    return sorted({int(cfg["patch_p"])} | {int(q) for q in cfg.get("patch_classes", [])},
+                  reverse=True)
+
+
+def ray_patch_sides(surf, p, pitch, cfg):
+    """Per-ray patch side by the curvature bound of Eq. 4: the largest candidate
+    P with arcsin(P pitch / 2 R_loc) <= eps (READING: R_loc the smallest principal
+    radius at the hit); the smallest candidate when none qualifies."""
+    cands = patch_classes(cfg)
+    if len(cands) == 1:
+        return np.full(p.shape[0], cands[0], dtype=np.int64)
+    eps = float(cfg.get("curv_eps", 0.1))
+    R = local_radius(surf, p[:, 0].detach(), p[:, 1].detach()).numpy()
+    out = np.full(p.shape[0], cands[-1], dtype=np.int64)
+    for i, Rl in enumerate(R):
+        for P in cands:
+            D = P * pitch
+            if math.isinf(Rl) or (D <= 2.0 * Rl and math.asin(D / (2.0 * Rl)) <= eps):
+                out[i] = P
+                break
+    return out
+
+
 def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
                  keep=False, ray_subset=None):
     """Returns dict with field U [Q, Q] (complex, differentiable), PSF, and
@@ -430,8 +478,6 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     doe = system["doe"]
     lam = cfg["lambdas"][lam_idx]
     k0 = TWO_PI / lam
-    P = cfg["patch_p"]
-    M = cfg["pad"] * P
     Nd = cfg["n_ssr"]
     Q = cfg["psf_q"]
     F = len(cfg["fields"])
@@ -461,6 +507,57 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     u, v, nrm = tangent_frame(surf_doe, p)
     k_in_t = k0 * n_in * torch.stack([(d * u).sum(-1), (d * v).sum(-1)], dim=-1)
 
+    # patch classes (Eq. 4); one class unless cfg lists several candidate sides
+    sides = ray_patch_sides(surf_doe, p, doe["pitch"], cfg)
+    R = p.shape[0]
+    J_all = np.full((R, Nd), -1, dtype=np.int64) if sampling != "full" else None
+    parts = []
+    for P in sorted(set(sides.tolist()), reverse=True):
+        sel = np.nonzero(sides == P)[0]
+        rsel = torch.as_tensor(sel)
+        rep = None
+        if replay is not None:
+            rep = np.asarray(replay, dtype=np.int64).reshape(R, Nd)[sel]
+        part = _class_secondaries(cfg, tmap, doe, pair, ray_ids[sel], P, p[rsel], opl[rsel],
+                                  amp_in[rsel], u[rsel], v[rsel], nrm[rsel], k_in_t[rsel],
+                                  alive[rsel], k_out, rep, sampling, Nd)
+        if J_all is not None:
+            J_all[sel] = part["J"]
+        parts.append((sel, part))
+        if keep and len(parts) == 1 and len(set(sides.tolist())) == 1:
+            out.update(spectrum=part["Ut"].detach(), prop=part["prop"])
+    rr = torch.cat([torch.as_tensor(sel)[part["rr"]] for sel, part in parts])
+    w = torch.cat([part["w"] for _, part in parts])
+    Kus = torch.cat([part["Kus"] for _, part in parts])
+    Kvs = torch.cat([part["Kvs"] for _, part in parts])
+    kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs
+    kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
+    ds = (Kus[:, None] * u[rr] + Kvs[:, None] * v[rr] + kz[:, None] * nrm[rr]) / k_out
+    a_s = amp_in[rr] * w
+    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z)
+    a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
+    lc = cfg["psf_center"][lam_idx][f_idx]
+    Xc = torch.stack([_t(lc[0]), _t(lc[1]), sensor_z * torch.ones((), dtype=DT)])
+    phi0 = k0 * (opls + n_s * (dsn * (Xc[None, :] - ps)).sum(-1))
+    wx = k0 * n_s * cfg["psf_pitch"] * dsn[:, 0]
+    wy = k0 * n_s * cfg["psf_pitch"] * dsn[:, 1]
+    amp = a_s * dsn[:, 2].abs()
+    U = sensor_field(amp, phi0, wx, wy, Q)
+    out["U"] = U
+    out["psf"] = (U.real ** 2 + U.imag ** 2)
+    if keep:
+        out.update(k_in_t=k_in_t.detach(), J=J_all, sides=sides, amp=amp.detach(),
+                   phi0=phi0.detach(), wx=wx.detach(), wy=wy.detach(), w=w.detach(),
+                   frame=(u.detach(), v.detach(), nrm.detach()))
+    return out
+
+
+def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, nrm, k_in_t,
+                       alive, k_out, replay, sampling, Nd):
+    """Patch spectra, evanescent cut, draws (or FULL) and Eq. 1 weights of the
+    rays of one patch class (side P, M = pad P).  Returns the secondary rays as
+    (parent index rr into the class's rays, weight w, tangential wavevector)."""
+    M = cfg["pad"] * P
     Upatch = patch_field(tmap, doe, p, u, v, P)
     Ut = angular_spectrum(Upatch, M)                        # [R, M, M]
     Ku, Kv = wavevectors(k_in_t, M, doe["pitch"])
@@ -470,10 +567,10 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     # flatten j_x-major: linear bin index J = (j_x + M/2) M + (j_y + M/2)
     Utf = Ut.transpose(1, 2).reshape(R, M * M)
     propf = prop.transpose(1, 2).reshape(R, M * M)
+    J = None
     if sampling == "full":
         rr, jj = torch.nonzero(propf, as_tuple=True)
         w = Utf[rr, jj] / (M * M)
-        J = None
     else:
         mag = Utf.detach().abs().numpy()
         pn = propf.numpy()
@@ -506,26 +603,7 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     if sampling != "full" and cfg.get("grad", "G1") == "G2":
         w, Kus, Kvs = _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w, Kus, Kvs,
                                         rr, valid, sampling, M, Nd)
-    kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs
-    kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
-    ds = (Kus[:, None] * u[rr] + Kvs[:, None] * v[rr] + kz[:, None] * nrm[rr]) / k_out
-    a_s = amp_in[rr] * w
-    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z)
-    a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
-    lc = cfg["psf_center"][lam_idx][f_idx]
-    Xc = torch.stack([_t(lc[0]), _t(lc[1]), sensor_z * torch.ones((), dtype=DT)])
-    phi0 = k0 * (opls + n_s * (dsn * (Xc[None, :] - ps)).sum(-1))
-    wx = k0 * n_s * cfg["psf_pitch"] * dsn[:, 0]
-    wy = k0 * n_s * cfg["psf_pitch"] * dsn[:, 1]
-    amp = a_s * dsn[:, 2].abs()
-    U = sensor_field(amp, phi0, wx, wy, Q)
-    out["U"] = U
-    out["psf"] = (U.real ** 2 + U.imag ** 2)
-    if keep:
-        out.update(spectrum=Ut.detach(), prop=prop, k_in_t=k_in_t.detach(),
-                   J=J, amp=amp.detach(), phi0=phi0.detach(), wx=wx.detach(),
-                   wy=wy.detach(), w=w.detach(), frame=(u.detach(), v.detach(), nrm.detach()))
-    return out
+    return dict(rr=rr, w=w, Kus=Kus, Kvs=Kvs, J=J, Ut=Ut, prop=prop)
 
 
 # ----------------------------------------------------------------------------
@@ -665,7 +743,8 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
     g = None
     if want_grad:
         g = dict(phase=ph.grad.numpy().copy(), amp=am.grad.numpy().copy(),
-                 lens=vals.grad.numpy().copy())
+                 lens=(vals.grad.numpy().copy() if vals.grad is not None
+                       else np.zeros(vals.shape)))
     return total, g, psfs, idx
 
 

@@ -94,6 +94,10 @@ struct rw_plan {
   size_t n_total;
   bool planar_doe, has_post;
   bool lds_patch;
+  int n_class;              // patch classes, largest side first
+  int class_p[4], class_m[4];
+  bool class_lds[4];
+  void* d_tw_cls[4] = {nullptr, nullptr, nullptr, nullptr};   // FFT twiddles per class M
   int doe_blocks;           // persistent workgroups of the ray-wave kernels
   int ray_block;            // side of the spatial ray blocks (work items)
   int acc_side;             // side of the block-private dL/dt accumulator
@@ -110,7 +114,6 @@ struct rw_plan {
   DevPair* d_pairs = nullptr;
   DevSurf* d_base = nullptr;
   DevParam* d_prm = nullptr;
-  void* d_tw_m = nullptr;
   void* d_tw_nf = nullptr;
   double* d_psi = nullptr;
   double base_sensor_z;
@@ -118,7 +121,7 @@ struct rw_plan {
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
-      off_interp, off_g2, total;
+      off_interp, off_g2, off_rcls, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
@@ -246,7 +249,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.st = (const double*)(b + pl->off_st);
   a.n_total = pl->n_total;
   a.tmap = b + pl->off_tmap;
-  a.tw = pl->d_tw_m;
+  a.tw = pl->d_tw_cls[0];
   a.grid = b + pl->off_grid;
   a.rec_pos = b + pl->off_rpos;
   a.rec_val = b + pl->off_rval;
@@ -261,6 +264,8 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.acc_side = pl->acc_side;
   a.ctx = (RayCtx*)(b + pl->off_ctx);
   a.dlist = b + pl->off_dlist;
+  a.ray_class = (unsigned char*)(b + pl->off_rcls);
+  a.cls = 0;
   return a;
 }
 
@@ -274,21 +279,30 @@ rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npa
   it.R = pl->R;
   const long long n_items = (long long)npairs * it.per_pair;
   const int blocks = (int)std::min<long long>(n_items, pl->doe_blocks);
-  bool ok = true;
-  hipError_t e;
-  switch (pl->cfg.precision) {
-    case RW_PREC_FP64:
-      e = launch_doe_fp64(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
-      break;
-    case RW_PREC_MIXED:
-      e = launch_doe_mixed(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
-      break;
-    default:
-      e = launch_doe_fp32(fwd, pl->M, pl->lds_patch, a, it, n_items, pair0, blocks, st, &ok);
+  // one launch per patch class, each over the whole work list (rays of other
+  // classes are skipped; dead rays belong to class 0)
+  for (int c = 0; c < pl->n_class; ++c) {
+    DoeArgs ac = a;
+    ac.cls = c;
+    ac.tw = pl->d_tw_cls[c];
+    const int M = pl->class_m[c];
+    const bool lds = pl->class_lds[c];
+    bool ok = true;
+    hipError_t e;
+    switch (pl->cfg.precision) {
+      case RW_PREC_FP64:
+        e = launch_doe_fp64(fwd, M, lds, ac, it, n_items, pair0, blocks, st, &ok);
+        break;
+      case RW_PREC_MIXED:
+        e = launch_doe_mixed(fwd, M, lds, ac, it, n_items, pair0, blocks, st, &ok);
+        break;
+      default:
+        e = launch_doe_fp32(fwd, M, lds, ac, it, n_items, pair0, blocks, st, &ok);
+    }
+    if (!ok) return fail(RW_ERR_SHAPE, "unsupported FFT size M for this precision");
+    if (e != hipSuccess)
+      return fail(RW_ERR_HIP, std::string("DOE kernel launch: ") + hipGetErrorString(e));
   }
-  if (!ok) return fail(RW_ERR_SHAPE, "unsupported FFT size M for this precision");
-  if (e != hipSuccess)
-    return fail(RW_ERR_HIP, std::string("DOE kernel launch: ") + hipGetErrorString(e));
   return RW_OK;
 }
 
@@ -497,6 +511,16 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     return fail(RW_ERR_SHAPE, "bad DOE map description");
   if (cfg->precision == RW_PREC_FP64 && M > 128)
     return fail(RW_ERR_UNSUPPORTED, "FP64 supports M <= 128");
+  if (cfg->n_patch_class < 0 || cfg->n_patch_class > 3)
+    return fail(RW_ERR_INVALID_ARG, "at most three patch classes besides patch_p");
+  for (int i = 0; i < cfg->n_patch_class; ++i) {
+    const int q = cfg->patch_class_p[i], mq = q * pad;
+    if (q < 1 || q >= (i ? cfg->patch_class_p[i - 1] : P) || !is_pow2(mq) || mq < 16)
+      return fail(RW_ERR_SHAPE, "patch classes must be decreasing sides below patch_p whose "
+                                "M = pad_factor * side is a power of two >= 16");
+  }
+  if (cfg->n_patch_class > 0 && !(cfg->curv_eps > 0.0))
+    return fail(RW_ERR_INVALID_ARG, "curv_eps must be positive");
   for (int l = 0; l < cfg->n_lambda; ++l)
     if (!(cfg->lambda_host[l] > 0)) return fail(RW_ERR_INVALID_ARG, "wavelength must be > 0");
 
@@ -515,6 +539,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->n_total = (size_t)pl->n_pairs * pl->R2;
   pl->P = P;
   pl->M = M;
+  pl->n_class = 1 + cfg->n_patch_class;
+  pl->class_p[0] = P;
+  for (int i = 0; i < cfg->n_patch_class; ++i) pl->class_p[1 + i] = cfg->patch_class_p[i];
+  for (int i = 0; i < pl->n_class; ++i) pl->class_m[i] = pl->class_p[i] * pad;
   pl->N = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
   pl->Q = cfg->psf_q;
   pl->nf = std::max(2 * cfg->psf_q, 64);
@@ -550,6 +578,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->ray_block = 8;
   pl->acc_side = 256;
   pl->doe_blocks = pl->lds_patch ? 1024 : 512;
+  for (int i = 0; i < pl->n_class; ++i) {
+    const size_t m = pl->class_m[i];
+    pl->class_lds[i] = m * (m + 1) * pl->sz_cf + m * pl->sz_cf + m * 64 * 8 + 4096 <= 160 * 1024;
+  }
   pl->emit = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
   {
     const int nb = std::min(64, pl->nf / 8);
@@ -588,6 +620,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   dc.pitch = doe->pitch; dc.x0 = doe->x0; dc.y0 = doe->y0;
   dc.inv_pitch = 1.0 / doe->pitch;
   dc.grad = cfg->grad;
+  dc.pad = pad;
+  dc.n_class = pl->n_class;
+  for (int i = 0; i < pl->n_class; ++i) dc.class_p[i] = pl->class_p[i];
+  dc.curv_eps = cfg->curv_eps;
   dc.tau = cfg->tau > 0.0 ? cfg->tau : 1.0;
   dc.planar = pl->planar_doe ? 1 : 0;
   dc.launch_z = cfg->launch_z; dc.launch_half = cfg->launch_half; dc.psf_pitch = cfg->psf_pitch;
@@ -638,7 +674,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     }
     return out;
   };
-  std::vector<char> twm = twiddles(M, dbl_f), twn = twiddles(pl->nf, dbl_g);
+  std::vector<char> twn = twiddles(pl->nf, dbl_g);
   // Fourier transform of the spreading kernel at the kept modes (deconvolution)
   std::vector<double> gx, gw, psi(pl->Q);
   gauss_legendre(200, gx, gw);
@@ -689,7 +725,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   if (e == hipSuccess) e = up((void**)&pl->d_pairs, pairs.data(), pairs.size() * sizeof(DevPair));
   if (e == hipSuccess) e = up((void**)&pl->d_base, base.data(), base.size() * sizeof(DevSurf));
   if (e == hipSuccess) e = up((void**)&pl->d_prm, prm.data(), prm.size() * sizeof(DevParam));
-  if (e == hipSuccess) e = up(&pl->d_tw_m, twm.data(), twm.size());
+  for (int i = 0; i < pl->n_class && e == hipSuccess; ++i) {
+    const std::vector<char> twc = twiddles(pl->class_m[i], dbl_f);
+    e = up(&pl->d_tw_cls[i], twc.data(), twc.size());
+  }
   if (e == hipSuccess) e = up(&pl->d_tw_nf, twn.data(), twn.size());
   if (e == hipSuccess) e = up((void**)&pl->d_psi, psi.data(), psi.size() * sizeof(double));
   if (e != hipSuccess) {
@@ -716,6 +755,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
+  pl->off_rcls = take((size_t)nt);
   pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
                                  sizeof(float)
                            : 0);
@@ -756,7 +796,7 @@ rw_status rw_plan_destroy(rw_plan* pl) {
   (void)hipFree(pl->d_pairs);
   (void)hipFree(pl->d_base);
   (void)hipFree(pl->d_prm);
-  (void)hipFree(pl->d_tw_m);
+  for (int i = 0; i < 4; ++i) (void)hipFree(pl->d_tw_cls[i]);
   (void)hipFree(pl->d_tw_nf);
   (void)hipFree(pl->d_psi);
   for (auto& e : pl->ev_used) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }

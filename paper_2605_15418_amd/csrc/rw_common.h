@@ -207,6 +207,24 @@ __device__ __forceinline__ void surface_normal(const Surf<S>& s, const S& x, con
   n[0] = -sx * inv; n[1] = -sy * inv; n[2] = inv;
 }
 
+// Smallest principal radius of curvature of the rotationally symmetric surface at
+// (x, y): meridional z''/(1 + z'^2)^(3/2), sagittal z'/(r (1 + z'^2)^(1/2));
+// infinite for a plane.
+__device__ __forceinline__ double local_radius(const Surf<double>& s, double x, double y) {
+  const double rho = x * x + y * y, r = sqrt(rho);
+  const double arg = 1.0 - (1.0 + s.k) * s.c * s.c * rho;
+  const double sq = sqrt(arg > 0.0 ? arg : 1.0);
+  const double d1 = s.c / (2.0 * sq) + 2.0 * s.A4 * rho + 3.0 * s.A6 * rho * rho +
+                    4.0 * s.A8 * rho * rho * rho + 5.0 * s.A10 * rho * rho * rho * rho;
+  const double d2 = s.c * (1.0 + s.k) * s.c * s.c / (4.0 * sq * sq * sq) + 2.0 * s.A4 +
+                    6.0 * s.A6 * rho + 12.0 * s.A8 * rho * rho + 20.0 * s.A10 * rho * rho * rho;
+  const double zp = 2.0 * r * d1, zpp = 2.0 * d1 + 4.0 * rho * d2;
+  const double km = fabs(zpp) / pow(1.0 + zp * zp, 1.5);
+  const double ks = r > 0.0 ? fabs(2.0 * d1) / sqrt(1.0 + zp * zp) : fabs(zpp);
+  const double kmax = km > ks ? km : ks;
+  return kmax > 0.0 ? 1.0 / kmax : INFINITY;
+}
+
 // Vector Snell law with the normal oriented along the ray; false on TIR.
 template <class S>
 __device__ __forceinline__ bool refract(S d[3], const S n[3], const S& mu) {

@@ -97,8 +97,8 @@ struct TileRef { int tx0, ty0, tw; };
 
 __device__ __forceinline__ TileRef tile_of(const DevCfg& cfg, const RayCtx& c) {
   const double fx = (c.p[0] - cfg.x0) * cfg.inv_pitch, fy = (c.p[1] - cfg.y0) * cfg.inv_pitch;
-  const int tw = cfg.P + 4;
-  return {(int)floor(fx) - cfg.P / 2 - 1, (int)floor(fy) - cfg.P / 2 - 1, tw};
+  const int tw = c.P + 4;
+  return {(int)floor(fx) - c.P / 2 - 1, (int)floor(fy) - c.P / 2 - 1, tw};
 }
 
 // Batches of KB pixels per lane: all loads of a batch are issued before its
@@ -131,8 +131,8 @@ template <class Tf>
 __device__ __forceinline__ C2<Tf> patch_sample_t(const DevCfg& cfg, const RayCtx& c,
                                                  const C2<Tf>* tm, const C2<Tf>* tile,
                                                  const TileRef& tr, int m, int n) {
-  const double sm = (m - (cfg.P - 1) * 0.5) * cfg.pitch;
-  const double sn = (n - (cfg.P - 1) * 0.5) * cfg.pitch;
+  const double sm = (m - (c.P - 1) * 0.5) * cfg.pitch;
+  const double sn = (n - (c.P - 1) * 0.5) * cfg.pitch;
   const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
   const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
   const double fx = (qx - cfg.x0) * cfg.inv_pitch, fy = (qy - cfg.y0) * cfg.inv_pitch;
@@ -162,8 +162,8 @@ template <class Tf> struct PlanarPatch {
 };
 template <class Tf>
 __device__ __forceinline__ PlanarPatch<Tf> planar_patch(const DevCfg& cfg, const RayCtx& c) {
-  const double fx0 = (c.p[0] - cfg.x0) * cfg.inv_pitch - 0.5 * (cfg.P - 1);
-  const double fy0 = (c.p[1] - cfg.y0) * cfg.inv_pitch - 0.5 * (cfg.P - 1);
+  const double fx0 = (c.p[0] - cfg.x0) * cfg.inv_pitch - 0.5 * (c.P - 1);
+  const double fy0 = (c.p[1] - cfg.y0) * cfg.inv_pitch - 0.5 * (c.P - 1);
   const double flx = floor(fx0), fly = floor(fy0);
   return {(int)flx, (int)fly, (Tf)(fx0 - flx), (Tf)(fy0 - fly)};
 }
@@ -193,7 +193,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   const int tid = opaque_tid();
   const int g = tid / L, gl = tid % L;
   const int br = bitrev(gl, Gm::LB);
-  const int P = cfg.P;
+  const int P = c.P;
   // the map tile goes into rows P.. of buf, which the row pass leaves untouched
   const TileRef tr = tile_of(cfg, c);
   C2<Tf>* tile = (M - P) * SM >= tr.tw * tr.tw ? buf + P * SM : nullptr;
@@ -400,13 +400,13 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
-  const int N = cfg.N, P = cfg.P, t = threadIdx.x, emit = a.emit;
+  const int N = cfg.N, t = threadIdx.x, emit = a.emit;
   const double inv_m2 = 1.0 / ((double)M * M);
   unsigned long long n_sec = 0, n_alive = 0;
   for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
     for (int k = 0; k < itr.count(); ++k) {
       const long long gid = itr.ray(it, k, pair0);
-      if (gid < 0) continue;
+      if (gid < 0 || a.ray_class[gid] != a.cls) continue;     // other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
       if (a.st[7 * a.n_total + gid] == 0.0) {
         for (int i = t; i < emit; i += kDoeThreads) put_zero<Tg>(a, slot0 + i);
@@ -419,9 +419,12 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       __syncthreads();
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
+      const int P = c.P;
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       if (cfg.sampling == 2) {
+        // slots beyond this class's M^2 bins (classes smaller than the largest)
+        for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_zero<Tg>(a, slot0 + Lb);
         for (int Lb = t; Lb < M * M; Lb += kDoeThreads) {
           const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
           Tp phi0, wx, wy; double dza; Secondary sec;
@@ -692,7 +695,7 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
                             float* gd, float* dlg, double* red) {
   using Tf = typename Prec::Tf;
   const DevCfg& cfg = *a.cfg;
-  const int N = cfg.N, P = cfg.P;
+  const int N = cfg.N, P = c.P;
   const int t = opaque_tid(), lane = t & 63, wv = t >> 6;
   constexpr int NW = kDoeThreads / 64;
   const float Sf = (float)S;
@@ -795,12 +798,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   C2<Tg>* accm = (C2<Tg>*)a.acc + (size_t)blockIdx.x * AS * AS;
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
-  const int N = cfg.N, P = cfg.P, t = threadIdx.x;
+  const int N = cfg.N, t = threadIdx.x;
   static_assert(kDoeThreads % M == 0, "the S-term pass keeps one column per lane");
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
-  const int T = P + 4;                                  // bilinear tile side
-  const bool use_tile = (M - P) * SM >= T * T;
   for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
     // anchor of the accumulator: the first live ray of the block
     if (t == 0) { s_box[0] = INT_MAX; s_box[1] = INT_MAX; s_box[2] = INT_MIN; s_box[3] = INT_MIN; }
@@ -808,7 +809,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
     bool have_anchor = false;
     for (int k = 0; k < itr.count() && !have_anchor; ++k) {
       const long long gid = itr.ray(it, k, pair0);
-      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0) continue;
+      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0 || a.ray_class[gid] != a.cls) continue;
       const double fx = (a.st[0 * a.n_total + gid] - cfg.x0) * cfg.inv_pitch;
       const double fy = (a.st[1 * a.n_total + gid] - cfg.y0) * cfg.inv_pitch;
       ax0 = (int)floor(fx) - AS / 2;
@@ -819,12 +820,15 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
     if (!have_anchor) continue;
     for (int k = 0; k < itr.count(); ++k) {
       const long long gid = itr.ray(it, k, pair0);
-      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0) continue;
+      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0 || a.ray_class[gid] != a.cls) continue;
       load_ctx(a, (size_t)gid, s.ctx);
       __syncthreads();
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
       const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
+      const int P = c.P;
+      const int T = P + 4;                                // bilinear tile side
+      const bool use_tile = (M - P) * SM >= T * T;
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);

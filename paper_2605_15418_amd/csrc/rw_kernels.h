@@ -48,6 +48,10 @@ struct DevCfg {
   uint32_t key0, key1;
   int grad;                // 0: frozen draws (G1), 1: Gumbel-softmax straight-through (G2)
   double tau;              // G2 temperature
+  int pad;                 // M / P
+  int n_class;             // patch classes (1: every ray uses P)
+  int class_p[4];          // candidate patch sides, largest first (class_p[0] = P)
+  double curv_eps;         // curvature bound of the class rule
 };
 
 struct DevPair {
@@ -245,6 +249,8 @@ struct DoeArgs {
   const void* interp;        // C2<Tg> [n_slots][3] sensor-grid cogradient at each record
                              // (value, d/dx, d/dy), or null: interpolate in the kernel
   void* g2;                  // G2 per block: double [N][8] draw data, then [M*M] dL/dlog p
+  unsigned char* ray_class;  // [n_total] patch class of every ray (0 for dead rays)
+  int cls;                   // class processed by this launch
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
@@ -253,6 +259,7 @@ struct RayCtx {
   double u[3], v[3], n[3];
   double kin_u, kin_v, k0, k_out, n_in, n_out, dk, k2out;
   int pair, r;
+  int P, cls;               // patch side and class of this ray
   size_t gid;
 };
 constexpr int kCtxWords = (int)(sizeof(RayCtx) / 4);
@@ -282,7 +289,22 @@ __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c
   c.k_out = c.k0 * c.n_out;
   c.kin_u = c.k0 * c.n_in * (c.d[0] * c.u[0] + c.d[1] * c.u[1] + c.d[2] * c.u[2]);
   c.kin_v = c.k0 * c.n_in * (c.d[0] * c.v[0] + c.d[1] * c.v[1] + c.d[2] * c.v[2]);
-  c.dk = 2.0 * RW_PI / (cfg.M * cfg.pitch);
+  // patch class (Eq. 4): the largest candidate side D = P pitch with
+  // arcsin(D / 2 R_loc) <= eps at the hit, else the smallest
+  c.cls = 0;
+  if (cfg.n_class > 1) {
+    const double Rl = local_radius(sf, c.p[0], c.p[1]);
+    c.cls = cfg.n_class - 1;
+    for (int k = 0; k < cfg.n_class; ++k) {
+      const double D = cfg.class_p[k] * cfg.pitch;
+      if (isinf(Rl) || (D <= 2.0 * Rl && asin(D / (2.0 * Rl)) <= cfg.curv_eps)) {
+        c.cls = k;
+        break;
+      }
+    }
+  }
+  c.P = cfg.class_p[c.cls];
+  c.dk = 2.0 * RW_PI / ((double)cfg.pad * c.P * cfg.pitch);
   c.k2out = __dmul_rn(c.k_out, c.k_out);
 }
 
@@ -291,10 +313,14 @@ static __global__ __launch_bounds__(256) void k_ray_ctx(DoeArgs a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.nray) return;
   const size_t gid = a.ray0 + i;
-  if (a.st[7 * a.n_total + gid] == 0.0) return;
+  if (a.st[7 * a.n_total + gid] == 0.0) {
+    a.ray_class[gid] = 0;
+    return;
+  }
   RayCtx c;
   make_ctx(a, gid, c);
   a.ctx[gid] = c;
+  a.ray_class[gid] = (unsigned char)c.cls;
 }
 
 // Copy of a ray's context into shared memory by the first kCtxWords threads
@@ -305,36 +331,6 @@ __device__ __forceinline__ void load_ctx(const DoeArgs& a, size_t gid, RayCtx& d
         reinterpret_cast<const uint32_t*>(a.ctx + gid)[threadIdx.x];
 }
 
-// Bilinear sample of the complex transmission at the xy projection of
-// p + s_m u + s_n v (zero outside the map).
-template <class Tf>
-__device__ __forceinline__ C2<Tf> patch_sample(const DevCfg& cfg, const RayCtx& c,
-                                               const C2<Tf>* tm, int m, int n) {
-  const double sm = (m - (cfg.P - 1) * 0.5) * cfg.pitch;
-  const double sn = (n - (cfg.P - 1) * 0.5) * cfg.pitch;
-  const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
-  const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
-  const double fx = (qx - cfg.x0) / cfg.pitch, fy = (qy - cfg.y0) / cfg.pitch;
-  const double flx = floor(fx), fly = floor(fy);
-  const int ix = (int)flx, iy = (int)fly;
-  const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
-  C2<Tf> acc = {Tf(0), Tf(0)};
-  const int W = cfg.W, H = cfg.H;
-#pragma unroll
-  for (int dy = 0; dy < 2; ++dy) {
-    const int y = iy + dy;
-    if (y < 0 || y >= H) continue;
-    const Tf wyv = dy ? wy : Tf(1) - wy;
-#pragma unroll
-    for (int dx = 0; dx < 2; ++dx) {
-      const int x = ix + dx;
-      if (x < 0 || x >= W) continue;
-      const Tf wxv = dx ? wx : Tf(1) - wx;
-      acc = acc + tm[(size_t)y * W + x] * (wxv * wyv);
-    }
-  }
-  return acc;
-}
 
 // Exponential-of-semicircle spreading kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)).
 template <class Tg>

@@ -57,7 +57,9 @@ class rw_config(ctypes.Structure):
                 ("patch_p", ctypes.c_int), ("pad_factor", ctypes.c_int), ("n_ssr", ctypes.c_int),
                 ("sampling", ctypes.c_int), ("precision", ctypes.c_int), ("batched", ctypes.c_int),
                 ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("grad", ctypes.c_int), ("tau", ctypes.c_double)]
+                ("grad", ctypes.c_int), ("tau", ctypes.c_double),
+                ("n_patch_class", ctypes.c_int), ("patch_class_p", ctypes.c_int * 3),
+                ("curv_eps", ctypes.c_double)]
 
 
 class rw_profile(ctypes.Structure):
@@ -190,6 +192,14 @@ class Plan:
         c.seed = int(cfg["seed"])
         c.grad = GRAD[cfg.get("grad", "G1")]
         c.tau = float(cfg.get("tau", 1.0))
+        extra = sorted({int(q) for q in cfg.get("patch_classes", [])} - {int(cfg["patch_p"])},
+                       reverse=True)
+        if len(extra) > 3:
+            raise ValueError("at most three patch classes besides patch_p")
+        c.n_patch_class = len(extra)
+        for i, q in enumerate(extra):
+            c.patch_class_p[i] = q
+        c.curv_eps = float(cfg.get("curv_eps", 0.1))
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
                                                  len(prm), ctypes.byref(c), ctypes.byref(h)))

@@ -531,3 +531,43 @@ def test_g2_equals_g1_for_uniform_sampling_and_tends_to_it_as_tau_vanishes():
         assert np.linalg.norm(g3[k] - g1[k]) <= 1e-9 * np.linalg.norm(g1[k]), k
     _, g4, _, _ = _g2_case("mag", "G2")
     assert np.linalg.norm(g4["phase"] - g1["phase"]) > 1e-3 * np.linalg.norm(g1["phase"])
+
+
+# ---------------------------------------------------- patch classes (Eq. 4) --
+def test_local_radius_sphere_and_asphere_against_sag_derivatives():
+    """Sphere: R_loc = R everywhere.  Even asphere: the closed-form principal
+    curvatures against autograd derivatives of the sag itself."""
+    sph = {"c": 1 / 30.0, "k": 0.0, "A": [0.0, 0.0, 0.0, 0.0]}
+    x = torch.tensor([0.0, 1.0, 3.0, -4.0], dtype=torch.float64)
+    y = torch.tensor([0.0, 2.0, -1.0, 5.0], dtype=torch.float64)
+    assert torch.allclose(O.local_radius(sph, x, y), torch.full_like(x, 30.0), rtol=1e-12)
+    asp = {"c": 1 / 40.0, "k": -0.7, "A": [2e-5, -3e-7, 1e-9, 0.0]}
+    for r0 in (0.0, 0.8, 2.5, 6.0):
+        r = torch.tensor(r0, dtype=torch.float64, requires_grad=True)
+        z = O.sag_and_grad(asp, r, torch.zeros((), dtype=torch.float64))[0]
+        (zp,) = torch.autograd.grad(z, r, create_graph=True)
+        (zpp,) = torch.autograd.grad(zp, r)
+        km = abs(float(zpp)) / (1 + float(zp) ** 2) ** 1.5
+        ks = abs(float(zp)) / (r0 * math.sqrt(1 + float(zp) ** 2)) if r0 > 0 else abs(float(zpp))
+        R = float(O.local_radius(asp, torch.tensor([r0], dtype=torch.float64),
+                                 torch.zeros(1, dtype=torch.float64))[0])
+        assert abs(R - 1.0 / max(km, ks)) <= 1e-10 * R, (r0, R)
+    plane = {"c": 0.0, "k": 0.0, "A": [0.0, 0.0, 0.0, 0.0]}
+    assert torch.isinf(O.local_radius(plane, x, y)).all()
+
+
+def test_patch_class_rule_follows_the_curvature_bound():
+    """Largest candidate P with arcsin(P pitch / 2R) <= eps (Eq. 4)."""
+    pitch, eps = 0.5e-3, 0.1
+    cfg = {"patch_p": 128, "patch_classes": [64, 32], "curv_eps": eps}
+    p = torch.zeros((3, 3), dtype=torch.float64)
+    for R, expect in ((1e9, 128), (0.5, 128), (0.2, 64), (0.1, 32), (0.05, 32)):
+        surf = {"c": 1.0 / R, "k": 0.0, "A": [0.0, 0.0, 0.0, 0.0]}
+        sides = O.ray_patch_sides(surf, p, pitch, cfg)
+        assert (sides == expect).all(), (R, sides)
+        P = int(sides[0])
+        fits = P * pitch <= 2 * R and math.asin(P * pitch / (2 * R)) <= eps
+        assert fits or P == 32                     # the smallest side when none fits
+        if P < 128:                                # the next larger side violates the bound
+            D = 2 * P * pitch
+            assert D > 2 * R or math.asin(D / (2 * R)) > eps

@@ -222,6 +222,37 @@ def free_space_doe(phase, amp, pitch, dz, lam, rays_side, P, Q, psf_pitch, N=256
     return system, cfg, maps
 
 
+# ----------------------------------------------------------------------------
+# Conformal DOE: a random complex hologram on an even-asphere surface in air
+# (R = 10 mm at the vertex, A4 = 0.42 mm^-3, so the smallest principal radius
+# falls to ~2.4 mm at the map edge) under collimated light; the patch-class
+# rule (Eq. 4) gives patch side P near the axis and the smaller class further
+# out.  Sensor 5 mm behind the vertex.
+# ----------------------------------------------------------------------------
+def conformal_hologram(rays_side=8, H=256, pitch=0.002, P=32, classes=(16,), N=32, Q=32,
+                       psf_pitch=0.004, sampling="mag", curv_eps=0.006, n_field_side=1,
+                       max_deg=2.0, seed=0, cfg_id=7):
+    surfs = [surface(0.0, c=0.1, A=(0.42, 0.0, 0.0, 0.0), medium=AIR, doe=True)]
+    dz = 5.0
+    system = {"surfaces": surfs, "sensor_z": dz, "doe": doe_desc(H, H, pitch), "params": []}
+    fields = field_grid(max_deg, n_field_side)
+    half = 0.45 * H * pitch
+    cfg = _cfg([LAM_D], fields, 0.0, -1.0, half, rays_side, Q, psf_pitch, dz, P, N, sampling,
+               seed=seed)
+    cfg["patch_classes"] = [int(q) for q in classes]
+    cfg["curv_eps"] = float(curv_eps)
+    rng = np.random.default_rng(20260000 + cfg_id)
+    phase = 2 * math.pi * bandlimited_uniform(H, H, 0.25, rng)
+    amp = 0.5 + 0.5 * bandlimited_uniform(H, H, 0.25, rng)
+    rng_t = np.random.default_rng(20260200 + cfg_id)
+    NA = (H * pitch / 2) / dz
+    target = np.zeros((1, len(fields), Q, Q), dtype=np.float32)
+    for f in range(len(fields)):
+        target[0, f] = airy_target(Q, psf_pitch, LAM_D, NA, (0.0, 0.0), rng_t.uniform(-2, 2, 2))
+    maps = {"phase": phase.astype(np.float32), "amp": amp.astype(np.float32), "target": target}
+    return system, cfg, maps
+
+
 def workload(name):
     """Named full-size workloads."""
     if name == "singlet_zoneplate":
