@@ -206,6 +206,18 @@ typedef struct {
 rw_status rw_set_profiling(rw_plan* plan, int enable);
 rw_status rw_get_profile(rw_plan* plan, rw_profile* out_host);
 
+/* Launch-shape autotuning of the ray-wave kernels.  Times the forward and the
+ * backward DOE kernels on the inputs of the preceding rw_forward (same plan and
+ * workspace) for persistent workgroups in {256, 512, 1024, 2048} x spatial ray
+ * blocks of {4, 8, 16}^2 rays, keeps the fastest shape of each direction in the
+ * plan, and writes it to shape_out[4] (forward workgroups, forward block side,
+ * backward workgroups, backward block side) if not NULL.  Synchronises the stream.
+ * The trial launches overwrite forward state: call rw_forward again before
+ * rw_backward.  Recorded graphs are dropped.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_STATE (no forward on this workspace), RW_ERR_HIP. */
+rw_status rw_autotune(rw_plan* plan, void* workspace, size_t workspace_bytes, int* shape_out,
+                      void* stream);
+
 /* Captured launch sequences.  enable = 1: rw_forward and rw_backward record their
  * whole launch sequence into a HIP graph the first time they are called with a given
  * set of pointer arguments (on a capture stream the plan owns) and from then on replay

@@ -98,8 +98,11 @@ struct rw_plan {
   int class_p[4], class_m[4];
   bool class_lds[4];
   void* d_tw_cls[4] = {nullptr, nullptr, nullptr, nullptr};   // FFT twiddles per class M
-  int doe_blocks;           // persistent workgroups of the ray-wave kernels
-  int ray_block;            // side of the spatial ray blocks (work items)
+  int doe_blocks;           // workgroups the workspace is sized for (upper bound)
+  int ray_block;            // side of the spatial ray blocks (default)
+  // launch shape of the ray-wave kernels per direction (rw_autotune may change it)
+  int blocks_dir[2];        // [0] forward, [1] backward: persistent workgroups
+  int rb_dir[2];            // side of the spatial ray blocks
   int acc_side;             // side of the block-private dL/dt accumulator
   int emit;                 // record slots per ray
   int group_pairs;          // pairs per launch group (memory-bounded)
@@ -273,12 +276,12 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
 rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npairs,
                      hipStream_t st) {
   RayBlockIter it;
-  it.rb = pl->ray_block;
+  it.rb = pl->rb_dir[fwd ? 0 : 1];
   it.nbx = (pl->R + it.rb - 1) / it.rb;
   it.per_pair = it.nbx * it.nbx;
   it.R = pl->R;
   const long long n_items = (long long)npairs * it.per_pair;
-  const int blocks = (int)std::min<long long>(n_items, pl->doe_blocks);
+  const int blocks = (int)std::min<long long>(n_items, pl->blocks_dir[fwd ? 0 : 1]);
   // one launch per patch class, each over the whole work list (rays of other
   // classes are skipped; dead rays belong to class 0)
   for (int c = 0; c < pl->n_class; ++c) {
@@ -577,7 +580,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
                   160 * 1024;
   pl->ray_block = 8;
   pl->acc_side = 256;
-  pl->doe_blocks = pl->lds_patch ? 1024 : 512;
+  pl->doe_blocks = pl->lds_patch ? 2048 : 1024;
+  pl->blocks_dir[0] = pl->blocks_dir[1] = pl->lds_patch ? 1024 : 512;
+  pl->rb_dir[0] = pl->rb_dir[1] = pl->ray_block;
   for (int i = 0; i < pl->n_class; ++i) {
     const size_t m = pl->class_m[i];
     pl->class_lds[i] = m * (m + 1) * pl->sz_cf + m * pl->sz_cf + m * 64 * 8 + 4096 <= 160 * 1024;
@@ -808,6 +813,68 @@ rw_status rw_plan_destroy(rw_plan* pl) {
   return RW_OK;
 }
 
+rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, void* stream) {
+  if (!pl || !ws) return fail(RW_ERR_INVALID_ARG, "null argument");
+  if (!pl->fwd_done || ws != pl->fwd_ws || ws_bytes < pl->total)
+    return fail(RW_ERR_STATE, "rw_autotune needs a preceding rw_forward on this workspace");
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)ws;
+  pl->gfwd.reset();
+  pl->gbwd.reset();
+  const bool prof = pl->prof;
+  pl->prof = false;
+  DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
+  a.adj = b + pl->off_grid;
+  a.interp = pl->tiled_interp ? (const void*)(b + pl->off_interp) : nullptr;
+  a.g2 = pl->g2 ? (void*)(b + pl->off_g2) : nullptr;
+  a.want_lens = 0;
+  a.ray0 = 0;
+  const int ppg = pl->group_pairs;
+  a.nray = (size_t)ppg * pl->R2;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int blocks_c[4] = {256, 512, 1024, 2048};
+  const int rb_c[3] = {4, 8, 16};
+  rw_status res = RW_OK;
+  for (int dir = 0; dir < 2 && res == RW_OK; ++dir) {
+    const bool fwd = dir == 0;
+    float best = 1e30f;
+    int bb = pl->blocks_dir[dir], br = pl->rb_dir[dir];
+    for (int i = 0; i < 4 && res == RW_OK; ++i) {
+      if (blocks_c[i] > pl->doe_blocks) continue;
+      for (int j = 0; j < 3 && res == RW_OK; ++j) {
+        pl->blocks_dir[dir] = blocks_c[i];
+        pl->rb_dir[dir] = rb_c[j];
+        // one untimed launch, then one timed
+        res = doe_launch(pl, fwd, a, 0, ppg, st);
+        if (res != RW_OK) break;
+        (void)hipEventRecord(e0, st);
+        res = doe_launch(pl, fwd, a, 0, ppg, st);
+        (void)hipEventRecord(e1, st);
+        if (res != RW_OK) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          res = fail(RW_ERR_HIP, "rw_autotune: event timing failed");
+          break;
+        }
+        if (ms < best) { best = ms; bb = blocks_c[i]; br = rb_c[j]; }
+      }
+    }
+    pl->blocks_dir[dir] = bb;
+    pl->rb_dir[dir] = br;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  pl->prof = prof;
+  pl->fwd_done = false;             // the trial launches overwrote forward state
+  if (shape_out) {
+    shape_out[0] = pl->blocks_dir[0]; shape_out[1] = pl->rb_dir[0];
+    shape_out[2] = pl->blocks_dir[1]; shape_out[3] = pl->rb_dir[1];
+  }
+  return res;
+}
+
 rw_status rw_set_graph(rw_plan* pl, int enable) {
   if (!pl) return fail(RW_ERR_INVALID_ARG, "null plan");
   pl->graph = enable != 0;
@@ -979,7 +1046,7 @@ static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, 
   zero<double>(b + pl->off_lensg, RW_LENSG_SLOTS, st);
   if (want_lens) zero<double>(b + pl->off_raygrad, 8 * pl->n_total, st);
   {
-    const size_t nacc = (size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * 2;
+    const size_t nacc = (size_t)pl->blocks_dir[1] * pl->acc_side * pl->acc_side * 2;
     if (dbl) zero<double>(b + pl->off_acc, nacc, st);
     else zero<float>(b + pl->off_acc, nacc, st);
   }

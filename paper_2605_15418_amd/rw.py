@@ -24,7 +24,8 @@ STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STA
 
 EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
-            "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph")
+            "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph",
+            "rw_autotune")
 STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd",
           "interp")
 
@@ -95,12 +96,13 @@ def load_library(path=LIB_PATH):
     lib.rw_set_profiling.argtypes = [vp, ctypes.c_int]
     lib.rw_get_profile.argtypes = [vp, ctypes.POINTER(rw_profile)]
     lib.rw_set_graph.argtypes = [vp, ctypes.c_int]
+    lib.rw_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_int), vp]
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
     for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
-                 "rw_get_profile", "rw_set_graph"):
+                 "rw_get_profile", "rw_set_graph", "rw_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -267,6 +269,15 @@ class Plan:
         _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
         return {"rays_total": s.rays_total, "rays_alive": s.rays_alive,
                 "secondaries": s.secondaries}
+
+    def autotune(self):
+        """Pick the fastest launch shape of the DOE kernels on the inputs of the last
+        forward; returns (fwd workgroups, fwd ray block, bwd workgroups, bwd ray block).
+        Run forward again before backward."""
+        shape = (ctypes.c_int * 4)()
+        _check(self.lib, self.lib.rw_autotune(self.handle, _dptr(self.ws), self.ws_bytes, shape,
+                                              self._stream()))
+        return tuple(shape)
 
     def set_graph(self, enable=True):
         """Record the forward / backward launch sequences as HIP graphs and replay them."""

@@ -204,3 +204,27 @@ def test_graph_replays_match_eager(rw):
     psf2, _, _ = plan.forward(vals, ph2, am, target=tg)
     torch.cuda.synchronize()
     assert rel_l2(psf2.cpu().numpy(), psf0.cpu().numpy()) < 1e-5
+
+
+def test_autotune_keeps_results(rw):
+    """The launch shape chosen by rw_autotune changes nothing but speed."""
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    ref = rw.Plan(system, cfg, precision="mixed")
+    p0, l0, i0 = ref.forward(vals, ph, am, target=tg, want_idx=True)
+    g0 = ref.backward()
+    plan = rw.Plan(system, cfg, precision="mixed")
+    plan.forward(vals, ph, am, target=tg)
+    shape = plan.autotune()
+    assert shape[0] in (256, 512, 1024, 2048) and shape[1] in (4, 8, 16)
+    assert shape[2] in (256, 512, 1024, 2048) and shape[3] in (4, 8, 16)
+    with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
+        plan.backward()                          # autotune invalidated the forward state
+    p1, l1, i1 = plan.forward(vals, ph, am, target=tg, want_idx=True)
+    g1 = plan.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(i0, i1)
+    assert rel_l2(p1.cpu().numpy(), p0.cpu().numpy()) < 1e-6
+    for a, b in zip(g1, g0):
+        assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
