@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       if (gid < 0 || a.ray_class[gid] != a.cls) continue;     // other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
       if (a.st[7 * a.n_total + gid] == 0.0) {
-        for (int i = t; i < emit; i += kDoeThreads) put_zero<Tg>(a, slot0 + i);
+        for (int i = t; i < emit; i += kDoeThreads) put_none<Tg>(a, slot0 + i);
         if (a.idx_out && cfg.sampling != 2)
           for (int i = t; i < N; i += kDoeThreads) a.idx_out[gid * N + i] = -1;
         continue;
@@ -424,14 +424,14 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       if (cfg.sampling == 2) {
         // slots beyond this class's M^2 bins (classes smaller than the largest)
-        for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_zero<Tg>(a, slot0 + Lb);
+        for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_none<Tg>(a, slot0 + Lb);
         for (int Lb = t; Lb < M * M; Lb += kDoeThreads) {
           const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
           Tp phi0, wx, wy; double dza; Secondary sec;
           const Span sp = s.span[jx + M / 2];
           if (jy < sp.lo || jy > sp.hi ||
               !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
-            put_zero<Tg>(a, slot0 + Lb);
+            put_none<Tg>(a, slot0 + Lb);
             continue;
           }
           const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
         Tp phi0, wx, wy; double dza; Secondary sec;
         if (ok) ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
         if (!ok) {
-          put_zero<Tg>(a, slot0 + i);
+          put_none<Tg>(a, slot0 + i);
           continue;
         }
         const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
@@ -571,7 +571,7 @@ __device__ __forceinline__ void interp_adj_pair(const DevCfg& cfg,
 // of a pair with identical arguments.  The interpolation comes from the tiled
 // pass when it covered this record (record slot `slot`, non-zero forward value),
 // else it is done here.
-template <class Prec>
+template <class Prec, bool kTiled>
 __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const RayCtx& c, int jx,
                                                      int jy, C2<typename Prec::Tp> w, int h,
                                                      size_t slot, WaveletAdj& wa, Secondary& sec) {
@@ -584,18 +584,15 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
   const C2<Tp> e = wavelet_cis<Prec>(phi0);
   const C2<Tp> cv = (w * e) * (Tp)dza;
   C2<double> g0, dx, dy;
-  bool tiled = false;
-  if (a.interp) {
-    const C2<Tg> rv = ((const C2<Tg>*)a.rec_val)[slot];
-    tiled = rv.re != Tg(0) || rv.im != Tg(0);
-  }
+  bool tiled = kTiled;
+  if (!kTiled && a.interp) tiled = !is_none(((const C2<Tg>*)a.rec_val)[slot]);
   if (tiled) {
     const C2<Tg>* q = (const C2<Tg>*)a.interp + 3 * slot;
     const C2<Tg> q0 = q[0], q1 = q[1], q2 = q[2];
     g0 = {(double)q0.re, (double)q0.im};
     dx = {(double)q1.re, (double)q1.im};
     dy = {(double)q2.re, (double)q2.im};
-  } else {
+  } else if constexpr (!kTiled) {
     const Tp gx = grid_coord(wx, cfg.nf), gy = grid_coord(wy, cfg.nf);
     if (cfg.w <= 8)
       interp_adj_pair<Prec, 8>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
@@ -779,7 +776,10 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
   return block_sum_d(Dsum, red);
 }
 
-template <class Prec, int M, bool kLDS, bool kG2>
+// kTiled: the sensor-grid cogradient of every record comes from the tiled
+// interpolation pass (one lane per secondary ray); otherwise the kernel
+// interpolates it itself (two lanes per secondary ray share the kernel rows).
+template <class Prec, int M, bool kLDS, bool kG2, bool kTiled>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
   using Tf = typename Prec::Tf;
@@ -834,7 +834,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
       double dLdS = 0.0;
-      const int h = t & 1;                  // lane pairs share one secondary ray
+      constexpr int LPD = kTiled ? 1 : 2;   // lanes per secondary ray
+      const int h = kTiled ? 0 : (t & 1);
+      const bool lead = kTiled || h == 0;   // writes the draw's entries
+      const bool side = kTiled || h == 1;   // accumulates the incident-state cogradient
       if (cfg.sampling != 2) {
         const double S = chunk_scan<M>(s.pref, s.red);
         const int lastpos_all = block_max_i(lp, s.redi);
@@ -842,7 +845,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         if (S > 0.0) {
           const double scale = S * inv_m2 / N;
 #pragma unroll 1
-          for (int i = t >> 1; i < N; i += kDoeThreads / 2) {
+          for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
             int J;
             if (a.replay) {
               J = a.replay[gid * N + i];
@@ -874,12 +877,12 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               WaveletAdj wa;
               Secondary sec;
               if (ok)
-                ok = wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
+                ok = wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
               if (ok) {
                 C2<double> gU;
                 if (cfg.sampling == 0) {
                   const double hr = (double)U.re / mag, hi_ = (double)U.im / mag;
-                  if (h == 0) dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
+                  if (lead) dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
                   const double gr = wa.g_w.re * scale, gi = wa.g_w.im * scale;
                   const double im = -(gr * hi_ - gi * hr) / mag;
                   gU = {-im * hi_, im * hr};
@@ -889,9 +892,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 const double rr = (double)ref.re, ri = (double)ref.im;
                 ent.k = kidx;
                 ent.g = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
-                if (a.want_lens && h == 1) incident_from_wavelet(a, c, sec, wa, acc);
+                if (a.want_lens && side) incident_from_wavelet(a, c, sec, wa, acc);
                 if constexpr (kG2) {
-                  if (h == 0) {
+                  if (lead) {
                     double gds[3];
                     direction_cograd(a, c, sec, wa, gds);
                     wavevector_cograd(c, sec, gds, g2r[2], g2r[3]);
@@ -902,9 +905,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 }
               }
             }
-            if (h == 0) dl[i] = ent;
+            if (lead) dl[i] = ent;
             if constexpr (kG2) {
-              if (h == 0 && cfg.sampling == 0) {
+              if (lead && cfg.sampling == 0) {
                 float* e = (float*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M) +
                            (size_t)i * kG2Rec;
 #pragma unroll
@@ -951,9 +954,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         }
         __syncthreads();
         // draw terms: each entry is re-read by the lane that wrote it
-        if (S > 0.0 && h == 0) {
+        if (S > 0.0 && lead) {
 #pragma unroll 1
-          for (int i = t >> 1; i < N; i += kDoeThreads / 2) {
+          for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
             const DrawEnt<Tf> e = dl[i];
             if (e.k >= 0) {
               atomicAdd(&buf[e.k].re, e.g.re);
@@ -962,10 +965,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           }
         }
       } else {
-        // FULL: every bin once; a lane pair per bin (both lanes read the bin
-        // before the first of them writes it)
+        // FULL: every bin once, LPD lanes per bin (with two, both lanes read the
+        // bin before the first of them writes it)
 #pragma unroll 1
-        for (int idx = t >> 1; idx < M * M; idx += kDoeThreads / 2) {
+        for (int idx = t / LPD; idx < M * M; idx += kDoeThreads / LPD) {
           const int ky = idx / M, kx = idx % M;
           const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
           const Span sp = s.span[jx + M / 2];
@@ -978,14 +981,14 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             WaveletAdj wa;
             Secondary sec;
             const size_t slot = slot0 + (size_t)((jx + M / 2) * M + (jy + M / 2));
-            if (wavelet_adjoint_pair<Prec>(a, c, jx, jy, w, h, slot, wa, sec)) {
+            if (wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot, wa, sec)) {
               const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
               const double rr = (double)ref.re, ri = (double)ref.im;
               out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};
-              if (a.want_lens && h == 1) incident_from_wavelet(a, c, sec, wa, acc);
+              if (a.want_lens && side) incident_from_wavelet(a, c, sec, wa, acc);
             }
           }
-          if (h == 0) buf[ky * SM + kx] = out;
+          if (lead) buf[ky * SM + kx] = out;
         }
       }
       __syncthreads();

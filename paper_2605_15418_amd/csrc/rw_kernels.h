@@ -448,10 +448,14 @@ __device__ __forceinline__ void put_record(const DoeArgs& a, size_t slot,
   ((C2<Tg>*)a.rec_val)[slot] = v;
 }
 
+// A slot that carries no secondary ray (dead incident ray, failed emission,
+// evanescent FULL bin) holds a NaN value; binning skips it.  A valid ray keeps
+// its record even when its value is exactly zero, so that the adjoint finds it.
 template <class Tg>
-__device__ __forceinline__ void put_zero(const DoeArgs& a, size_t slot) {
-  ((C2<Tg>*)a.rec_val)[slot] = {Tg(0), Tg(0)};
+__device__ __forceinline__ void put_none(const DoeArgs& a, size_t slot) {
+  ((C2<Tg>*)a.rec_val)[slot] = {(Tg)NAN, (Tg)NAN};
 }
+template <class Tg> __device__ __forceinline__ bool is_none(const C2<Tg>& v) { return v.re != v.re; }
 
 // Angle reference of the patch centre: U~_j = X_k exp(i pi (jx + jy)(P - 1) / M).
 template <class Tf>
@@ -494,7 +498,7 @@ __global__ __launch_bounds__(256) void k_rec_hist(const void* rec_pos, const voi
   const C2<Tg>* val = (const C2<Tg>*)rec_val;
   for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
     const C2<Tg> v = val[r];
-    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    if (is_none(v)) continue;
     const int k = rec_key(turns_to_cells(pos[2 * r], g.nf), turns_to_cells(pos[2 * r + 1], g.nf), g);
     atomicAdd(&s_h[k], 1u);
   }
@@ -555,7 +559,7 @@ __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const 
   const C2<Tg>* val = (const C2<Tg>*)rec_val;
   for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
     const C2<Tg> v = val[r];
-    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    if (is_none(v)) continue;
     const int k = rec_key(turns_to_cells(pos[2 * r], g.nf), turns_to_cells(pos[2 * r + 1], g.nf), g);
     atomicAdd(&s_h[k], 1u);
   }
@@ -571,7 +575,7 @@ __global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const 
   C2<Tg>* ov = (C2<Tg>*)srt_val;
   for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
     const C2<Tg> v = val[r];
-    if (v.re == Tg(0) && v.im == Tg(0)) continue;
+    if (is_none(v)) continue;
     const U px = pos[2 * r], py = pos[2 * r + 1];
     const int k = rec_key(turns_to_cells(px, g.nf), turns_to_cells(py, g.nf), g);
     const unsigned long long o = s_base[k] + atomicAdd(&s_h[k], 1u);
