@@ -1048,65 +1048,67 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           return gu(bb, aa) * w00 + gu(bb, aa - 1) * w01 + gu(bb - 1, aa) * w10 +
                  gu(bb - 1, aa - 1) * w11;
         };
+        // Lens position gradient: sum over samples of <g_s, dU_s/dx> equals the
+        // sum over pixels of <G'_p, t_p>, G' the bilinear adjoint with the
+        // weights differentiated in the sub-pixel offset (x: wx, y: wy).
+        const bool lens = a.want_lens != 0;
+        auto lens_term = [&](int i, const C2<Tf>& tp) {
+          const int bb = dP1.div(i), aa = i - bb * P1;
+          const C2<Tf> g00 = gu(bb, aa), g01 = gu(bb, aa - 1), g10 = gu(bb - 1, aa),
+                       g11 = gu(bb - 1, aa - 1);
+          const C2<Tf> gx = (g01 - g00) * (Tf(1) - pp.wy) + (g11 - g10) * pp.wy;
+          const C2<Tf> gy = (g10 - g00) * (Tf(1) - pp.wx) + (g11 - g01) * pp.wx;
+          gpx += (double)(gx.re * tp.re + gx.im * tp.im);
+          gpy += (double)(gy.re * tp.re + gy.im * tp.im);
+        };
         if (inside) {
           // the window lies inside the accumulator: batches of KB pixels per
-          // lane, all accumulator loads issued before the stores
+          // lane, all accumulator (and map) loads issued before the stores
           constexpr int KB = 9;
           for (int i0 = t; i0 < P1 * P1; i0 += kDoeThreads * KB) {
             C2<Tf> v[KB];
-            int li[KB];
+            int li[KB], mi[KB];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
               const int i = i0 + k * kDoeThreads;
               li[k] = -1;
+              mi[k] = -1;
               if (i < P1 * P1) {
                 int x, y;
                 v[k] = pix(i, x, y);
-                if (x >= 0 && x < W && y >= 0 && y < H)
+                if (x >= 0 && x < W && y >= 0 && y < H) {
                   li[k] = (ly0 + y - pp.iy0) * AS + lx0 + x - pp.ix0;
+                  mi[k] = y * W + x;
+                }
               }
             }
             C2<Tg> old[KB];
+            C2<Tf> tp[KB];
 #pragma unroll
-            for (int k = 0; k < KB; ++k)
+            for (int k = 0; k < KB; ++k) {
               if (li[k] >= 0) old[k] = accm[li[k]];
+              tp[k] = (lens && mi[k] >= 0) ? tm[mi[k]] : C2<Tf>{Tf(0), Tf(0)};
+            }
 #pragma unroll
-            for (int k = 0; k < KB; ++k)
-              if (li[k] >= 0) accm[li[k]] = {old[k].re + (Tg)v[k].re, old[k].im + (Tg)v[k].im};
+            for (int k = 0; k < KB; ++k) {
+              if (li[k] < 0) continue;
+              accm[li[k]] = {old[k].re + (Tg)v[k].re, old[k].im + (Tg)v[k].im};
+              if (lens) lens_term(i0 + k * kDoeThreads, tp[k]);
+            }
           }
         } else {
           for (int i = t; i < P1 * P1; i += kDoeThreads) {
             int x, y;
             const C2<Tf> v = pix(i, x, y);
             if (x < 0 || x >= W || y < 0 || y >= H) continue;
+            if (lens) lens_term(i, tm[(size_t)y * W + x]);
             if (v.re == Tf(0) && v.im == Tf(0)) continue;
             atomicAdd(&gt[(size_t)y * W + x].re, (Tg)v.re);
             atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
           }
         }
-        if (a.want_lens) {
-          // map tile under the patch (rows P.. of buf are free again once every
-          // lane has read the zero border)
-          __syncthreads();
-          const TileRef tr = tile_of(cfg, c);
-          C2<Tf>* mt = buf + P * SM;
-          stage_tile<Tf>(cfg, tr, tm, mt);
-          __syncthreads();
-          const int ox = pp.ix0 - tr.tx0, oy = pp.iy0 - tr.ty0;
-          const int lgP = __builtin_ctz(P);
-          for (int smp = t; smp < P * P; smp += kDoeThreads) {
-            const int m = smp & (P - 1), n = smp >> lgP;
-            const C2<Tf> g = buf[n * SM + m];
-            const C2<Tf>* r0 = mt + (oy + n) * tr.tw + ox + m;
-            const C2<Tf> t00 = r0[0], t01 = r0[1], t10 = r0[tr.tw], t11 = r0[tr.tw + 1];
-            const C2<Tf> dUx = (t01 - t00) * (Tf(1) - pp.wy) + (t11 - t10) * pp.wy;
-            const C2<Tf> dUy = (t10 - t00) * (Tf(1) - pp.wx) + (t11 - t01) * pp.wx;
-            gpx += (double)(g.re * dUx.re + g.im * dUx.im);
-            gpy += (double)(g.re * dUy.re + g.im * dUy.im);
-          }
-          gpx *= cfg.inv_pitch;
-          gpy *= cfg.inv_pitch;
-        }
+        gpx *= cfg.inv_pitch;
+        gpy *= cfg.inv_pitch;
       } else {
       // general surface: LDS-tiled scatter of every sample's 2 x 2 stencil
       C2<Tf>* tile = buf + P * SM;
