@@ -576,17 +576,17 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   const bool dbl_g = cfg->precision == RW_PREC_FP64;
   pl->sz_cf = dbl_f ? 16 : 8;
   pl->sz_cg = dbl_g ? 16 : 8;
-  pl->lds_patch = (size_t)M * (M + 1) * pl->sz_cf + M * pl->sz_cf + (size_t)M * 64 * 8 + 4096 <=
-                  160 * 1024;
+  // the patch buffer sits in LDS up to M = 128 (float spectra) or M = 64
+  // (double spectra), as the precision units instantiate the DOE kernels
+  auto in_lds = [&](int m) { return m <= (dbl_f ? 64 : 128); };
+  pl->lds_patch = in_lds(M);
   pl->ray_block = 8;
   pl->acc_side = 256;
-  pl->doe_blocks = pl->lds_patch ? 2048 : 1024;
-  pl->blocks_dir[0] = pl->blocks_dir[1] = pl->lds_patch ? 1024 : 512;
+  // several workgroups per CU fit from M = 64 down
+  pl->doe_blocks = M <= 64 ? 2048 : 1024;
+  pl->blocks_dir[0] = pl->blocks_dir[1] = M <= 64 ? 1024 : 512;
   pl->rb_dir[0] = pl->rb_dir[1] = pl->ray_block;
-  for (int i = 0; i < pl->n_class; ++i) {
-    const size_t m = pl->class_m[i];
-    pl->class_lds[i] = m * (m + 1) * pl->sz_cf + m * pl->sz_cf + m * 64 * 8 + 4096 <= 160 * 1024;
-  }
+  for (int i = 0; i < pl->n_class; ++i) pl->class_lds[i] = in_lds(pl->class_m[i]);
   pl->emit = cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr;
   {
     const int nb = std::min(64, pl->nf / 8);
@@ -757,7 +757,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_lossp = take(pl->n_pairs * sizeof(double));
   pl->off_stats = take(4 * sizeof(unsigned long long));
   pl->off_scratch =
-      take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * M * (M + 1) * pl->sz_cf);
+      take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * doe_buf_elems(M) * pl->sz_cf);
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
   pl->off_rcls = take((size_t)nt);

@@ -35,15 +35,46 @@ __device__ __forceinline__ int opaque_tid() {
   return t;
 }
 
+// Lanes per M-point transform of a DOE workgroup.
+__host__ __device__ constexpr int doe_lanes(int M) {
+  return 2 * kDoeThreads / M < 2 ? 2 : (2 * kDoeThreads / M > M / 2 ? M / 2 : 2 * kDoeThreads / M);
+}
+// Patch buffer layout.  A 64-bit LDS store serves 16 lanes per cycle through
+// 16 eight-byte bank slots, and the transforms' stores are runs of E outputs
+// per lane, lanes E elements apart.  For M = 128 (E = 16) element (r, c) sits
+// at r SM + 2 (r >> 4) + c + (c >> 4), SM = M + 8: one element of skew per 16
+// columns and two per 16 rows put the 16 lanes of every row-pass and
+// column-pass store (and load) into distinct slots.  Other M: rows of M + 1.
+__host__ __device__ constexpr bool doe_skew(int M) { return M == 128; }
+__host__ __device__ constexpr int doe_stride(int M) { return doe_skew(M) ? M + 8 : M + 1; }
+__host__ __device__ constexpr int doe_buf_elems(int M) {
+  return M * doe_stride(M) + (doe_skew(M) ? 16 : 0);
+}
+
 template <int M> struct DoeGeom {
   static constexpr int NT = kDoeThreads;
-  static constexpr int Lraw = 2 * NT / M;
-  static constexpr int L = Lraw < 2 ? 2 : (Lraw > M / 2 ? M / 2 : Lraw);  // lanes per transform
+  static constexpr int L = doe_lanes(M);                                   // lanes per transform
   static constexpr int E = M / L;                                          // elements per lane
   static constexpr int G = NT / L;                                         // transform groups
-  static constexpr int SM = M + 1;                                         // LDS row stride
+  static constexpr bool kSkew = doe_skew(M);
+  static constexpr int SM = doe_stride(M);                                 // buffer row stride
+  static constexpr int SIZE = doe_buf_elems(M);                            // buffer elements
   static constexpr int NCH = M * L;                                        // CDF chunks of E bins
   static constexpr int LB = Log2<L>::v;
+  static_assert(!kSkew || (E == 16 && L <= 16), "the skewed layout assumes runs of 16");
+  // element offsets of row r and of column c
+  __device__ static __forceinline__ int row(int r) { return r * SM + (kSkew ? 2 * (r >> 4) : 0); }
+  __device__ static __forceinline__ int col(int c) { return kSkew ? c + (c >> 4) : c; }
+  __device__ static __forceinline__ int at(int r, int c) { return row(r) + col(c); }
+  // row / column a + o of a transform's input: runtime lane part a < L,
+  // compile-time part o a multiple of L, so that the skew is o's alone.  (An
+  // output run E b + k, k < E, is row(E b) + k SM, column col(E b) + k.)
+  __device__ static __forceinline__ int row_split(int a, int o) {
+    return (a + o) * SM + (kSkew ? 2 * (o >> 4) : 0);
+  }
+  __device__ static __forceinline__ int col_split(int a, int o) {
+    return a + o + (kSkew ? (o >> 4) : 0);
+  }
 };
 
 // Division of small non-negative integers (< 2^20) by a runtime divisor through
@@ -170,7 +201,7 @@ __device__ __forceinline__ PlanarPatch<Tf> planar_patch(const DevCfg& cfg, const
 
 // Shared scratch of one workgroup.
 template <class Tf, int M, bool kLDS> struct DoeLds {
-  C2<Tf> buf[kLDS ? M * DoeGeom<M>::SM : 1];
+  C2<Tf> buf[kLDS ? DoeGeom<M>::SIZE : 1];
   C2<Tf> tw[M];
   double pref[DoeGeom<M>::NCH + 1];
   double red[16];
@@ -196,7 +227,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   const int P = c.P;
   // the map tile goes into rows P.. of buf, which the row pass leaves untouched
   const TileRef tr = tile_of(cfg, c);
-  C2<Tf>* tile = (M - P) * SM >= tr.tw * tr.tw ? buf + P * SM : nullptr;
+  C2<Tf>* tile = Gm::SIZE - Gm::row(P) >= tr.tw * tr.tw ? buf + Gm::row(P) : nullptr;
   if (tile) stage_tile<Tf>(cfg, tr, tm, tile);
   __syncthreads();
   // bilinear samples of the patch into rows 0..P-1, columns 0..P-1 of buf
@@ -209,13 +240,13 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     for (int i = tid; i < P * P; i += kDoeThreads) {
       const int m = i & (P - 1), n = i >> lgP;
       const C2<Tf>* r0 = tile + (oy + n) * tr.tw + ox + m;
-      buf[n * SM + m] = r0[0] * w00 + r0[1] * w01 + r0[tr.tw] * w10 + r0[tr.tw + 1] * w11;
+      buf[Gm::at(n, m)] = r0[0] * w00 + r0[1] * w01 + r0[tr.tw] * w10 + r0[tr.tw + 1] * w11;
     }
   } else {
     const int lgP = __builtin_ctz(P);
     for (int i = tid; i < P * P; i += kDoeThreads) {
       const int m = i & (P - 1), n = i >> lgP;
-      buf[n * SM + m] = patch_sample_t<Tf>(cfg, c, tm, tile, tr, m, n);
+      buf[Gm::at(n, m)] = patch_sample_t<Tf>(cfg, c, tm, tile, tr, m, n);
     }
   }
   __syncthreads();
@@ -225,18 +256,18 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     if (half) {
 #pragma unroll
       for (int n2 = 0; n2 < E; ++n2)
-        x[n2] = n2 < E / 2 ? buf[row * SM + gl + L * n2] : C2<Tf>{Tf(0), Tf(0)};
+        x[n2] = n2 < E / 2 ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
       group_fft<Tf, L, E, -1, true>(x, gl, tw);
     } else {
 #pragma unroll
       for (int n2 = 0; n2 < E; ++n2) {
         const int m = gl + L * n2;
-        x[n2] = m < P ? buf[row * SM + m] : C2<Tf>{Tf(0), Tf(0)};
+        x[n2] = m < P ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
       }
       group_fft<Tf, L, E, -1>(x, gl, tw);
     }
 #pragma unroll
-    for (int k2 = 0; k2 < E; ++k2) buf[row * SM + E * br + k2] = x[k2];
+    for (int k2 = 0; k2 < E; ++k2) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
   }
   for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
   __syncthreads();
@@ -246,13 +277,13 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     if (half) {
 #pragma unroll
       for (int n2 = 0; n2 < E; ++n2)
-        x[n2] = n2 < E / 2 ? buf[(gl + L * n2) * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+        x[n2] = n2 < E / 2 ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
       group_fft<Tf, L, E, -1, true>(x, gl, tw);
     } else {
 #pragma unroll
       for (int n2 = 0; n2 < E; ++n2) {
         const int n = gl + L * n2;
-        x[n2] = n < P ? buf[n * SM + col] : C2<Tf>{Tf(0), Tf(0)};
+        x[n2] = n < P ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
       }
       group_fft<Tf, L, E, -1>(x, gl, tw);
     }
@@ -267,7 +298,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     for (int k2 = 0; k2 < E; ++k2) {
       const int ky = ky0 + k2;
       const int jy = ky < M / 2 ? ky : ky - M;
-      buf[ky * SM + col] = x[k2];
+      buf[Gm::row(ky0) + k2 * SM + Gm::col(col)] = x[k2];
       double wgt = 0.0;
       if (jy >= sp.lo && jy <= sp.hi) wgt = sampling == 0 ? (double)cabs_rn(x[k2]) : 1.0;
       s += wgt;
@@ -362,7 +393,7 @@ __device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, c
     const int jy = (base % M) + q - M / 2;
     double wgt = 0.0;
     if (jy >= sp.lo && jy <= sp.hi)
-      wgt = sampling == 0 ? (double)cabs_rn(buf[(jy & (M - 1)) * SM + kx]) : 1.0;
+      wgt = sampling == 0 ? (double)cabs_rn(buf[Gm::at(jy & (M - 1), kx)]) : 1.0;
     run += wgt;
     if (wgt > 0.0) lp = base + q;
     if (run > T) return base + q;
@@ -396,7 +427,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   constexpr int SM = Gm::SM;
   __shared__ DoeLds<Tf, M, kLDS> s;
   const DevCfg& cfg = *a.cfg;
-  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
+  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * Gm::SIZE;
   const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
@@ -434,7 +465,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
             put_none<Tg>(a, slot0 + Lb);
             continue;
           }
-          const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+          const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
           const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
           const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
           const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
@@ -464,7 +495,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
         int jx = 0, jy = 0;
         if (ok) {
           jx = J / M - M / 2; jy = J % M - M / 2;
-          const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+          const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
           const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
           if (cfg.sampling == 0) {
             const Tf mag = cabs_rn(X);
@@ -649,7 +680,7 @@ __device__ __forceinline__ G2Bin g2_bin(const RayCtx& c, const C2<Tf>* buf, cons
   G2Bin b;
   b.live = false;
   if (jy < sp.lo || jy > sp.hi) return b;
-  const C2<Tf> X = buf[(jy & (M - 1)) * SM + (jx & (M - 1))];
+  const C2<Tf> X = buf[DoeGeom<M>::at(jy & (M - 1), jx & (M - 1))];
   const float m2 = (float)X.re * (float)X.re + (float)X.im * (float)X.im;
   if (!(m2 > 0.0f)) return b;
   const float im = rsqrtf(m2);
@@ -790,7 +821,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   __shared__ DoeLds<Tf, M, kLDS> s;
   __shared__ int s_box[4];
   const DevCfg& cfg = *a.cfg;
-  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * M * SM;
+  C2<Tf>* buf = kLDS ? s.buf : (C2<Tf>*)a.scratch + (size_t)blockIdx.x * Gm::SIZE;
   const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
   C2<Tg>* gt = (C2<Tg>*)a.gt;
   // block-private accumulator of dL/dt over one ray block
@@ -828,7 +859,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int g = t / L, gl = t % L, br = bitrev(gl, Gm::LB);
       const int P = c.P;
       const int T = P + 4;                                // bilinear tile side
-      const bool use_tile = (M - P) * SM >= T * T;
+      const bool use_tile = Gm::SIZE - Gm::row(P) >= T * T;
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
@@ -858,7 +889,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             double g2r[5] = {0.0, 0.0, 0.0, 0.0, -1.0};      // A, B, J of the G2 record
             if (J >= 0) {
               const int jx = J / M - M / 2, jy = J % M - M / 2;
-              const int kidx = (jy & (M - 1)) * SM + (jx & (M - 1));
+              const int kidx = Gm::at(jy & (M - 1), jx & (M - 1));
               const C2<Tf> X = buf[kidx];
               const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
               const C2<Tf> U = X * ref;
@@ -938,7 +969,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           const Tf fS = (Tf)dLdS;
           for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
             const int jy = ky < M / 2 ? ky : ky - M;
-            C2<Tf>& X = buf[ky * SM + kx];
+            C2<Tf>& X = buf[Gm::at(ky, kx)];
             C2<Tf> v = {Tf(0), Tf(0)};
             if (mag && jy >= sp.lo && jy <= sp.hi) {
               const Tf m2 = X.re * X.re + X.im * X.im;
@@ -974,7 +1005,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           const Span sp = s.span[jx + M / 2];
           C2<Tf> out = {Tf(0), Tf(0)};
           if (jy >= sp.lo && jy <= sp.hi) {
-            const C2<Tf> X = buf[ky * SM + kx];
+            const C2<Tf> X = buf[Gm::at(ky, kx)];
             const C2<Tf> ref = centre_ref<Tf>(jx, jy, P, M);
             const C2<Tf> U = X * ref;
             const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
@@ -988,7 +1019,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               if (a.want_lens && side) incident_from_wavelet(a, c, sec, wa, acc);
             }
           }
-          if (lead) buf[ky * SM + kx] = out;
+          if (lead) buf[Gm::at(ky, kx)] = out;
         }
       }
       __syncthreads();
@@ -996,37 +1027,37 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       for (int col = g; col < M; col += G) {
         C2<Tf> x[E];
 #pragma unroll
-        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[(gl + L * n2) * SM + col];
+        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row_split(gl, L * n2) + Gm::col(col)];
         group_fft<Tf, L, E, +1>(x, gl, s.tw);
 #pragma unroll
         for (int k2 = 0; k2 < E; ++k2) {
           const int n = E * br + k2;
-          if (n < P) buf[n * SM + col] = x[k2];
+          if (n < P) buf[Gm::row(E * br) + k2 * SM + Gm::col(col)] = x[k2];
         }
       }
       __syncthreads();
       for (int row = g; row < P; row += G) {
         C2<Tf> x[E];
 #pragma unroll
-        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[row * SM + gl + L * n2];
+        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row(row) + Gm::col_split(gl, L * n2)];
         group_fft<Tf, L, E, +1>(x, gl, s.tw);
         // columns P and M - 1 become a zero border of the patch gradient
 #pragma unroll
         for (int k2 = 0; k2 < E; ++k2) {
           const int m = E * br + k2;
-          if (m < P) buf[row * SM + m] = x[k2];
-          else if (m == P || m == M - 1) buf[row * SM + m] = C2<Tf>{Tf(0), Tf(0)};
+          if (m < P) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
+          else if (m == P || m == M - 1) buf[Gm::row(row) + Gm::col(E * br) + k2] = C2<Tf>{Tf(0), Tf(0)};
         }
       }
       // rows P and M - 1 too (the row pass touches rows < P only): the
       // bilinear adjoint below reads samples -1 and P through the wrap M - 1
       if (P < M - 1)
         for (int i = t; i < 2 * M; i += kDoeThreads)
-          buf[(i < M ? P : M - 1) * SM + (i & (M - 1))] = C2<Tf>{Tf(0), Tf(0)};
+          buf[Gm::at(i < M ? P : M - 1, i & (M - 1))] = C2<Tf>{Tf(0), Tf(0)};
       __syncthreads();
       // bilinear adjoint of the patch gather -> dL/dt, added to the block accumulator
       double gpx = 0.0, gpy = 0.0;
-      if (cfg.planar && (M - P) * SM >= T * T) {
+      if (cfg.planar && Gm::SIZE - Gm::row(P) >= T * T) {
         // gather form: pixel (ix0 + a, iy0 + b) collects the (up to) four samples
         // whose 2 x 2 stencils contain it; no atomics
         const PlanarPatch<Tf> pp = planar_patch<Tf>(cfg, c);
@@ -1040,7 +1071,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           atomicMax(&s_box[2], lx0 + P1); atomicMax(&s_box[3], ly0 + P1);
         }
         // samples -1 and P read the zero border (index -1 wraps to M - 1)
-        auto gu = [&](int n, int m) { return buf[(n & (M - 1)) * SM + (m & (M - 1))]; };
+        auto gu = [&](int n, int m) { return buf[Gm::at(n & (M - 1), m & (M - 1))]; };
         const FDiv dP1(P1);
         auto pix = [&](int i, int& x, int& y) -> C2<Tf> {
           const int bb = dP1.div(i), aa = i - bb * P1;
@@ -1052,6 +1083,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         // sum over pixels of <G'_p, t_p>, G' the bilinear adjoint with the
         // weights differentiated in the sub-pixel offset (x: wx, y: wy).
         const bool lens = a.want_lens != 0;
+        // read before the accumulator stores: a global load after them would
+        // wait for the stores to complete
+        const double inv_pitch = cfg.inv_pitch;
         auto lens_term = [&](int i, const C2<Tf>& tp) {
           const int bb = dP1.div(i), aa = i - bb * P1;
           const C2<Tf> g00 = gu(bb, aa), g01 = gu(bb, aa - 1), g10 = gu(bb - 1, aa),
@@ -1107,11 +1141,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
           }
         }
-        gpx *= cfg.inv_pitch;
-        gpy *= cfg.inv_pitch;
+        gpx *= inv_pitch;
+        gpy *= inv_pitch;
       } else {
       // general surface: LDS-tiled scatter of every sample's 2 x 2 stencil
-      C2<Tf>* tile = buf + P * SM;
+      C2<Tf>* tile = buf + Gm::row(P);
       const double cfx = (c.p[0] - cfg.x0) * cfg.inv_pitch, cfy = (c.p[1] - cfg.y0) * cfg.inv_pitch;
       const int tx0 = (int)floor(cfx) - T / 2, ty0 = (int)floor(cfy) - T / 2;
       if (use_tile) {
@@ -1120,7 +1154,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       }
       for (int smp = t; smp < P * P; smp += kDoeThreads) {
         const int m = smp % P, n = smp / P;
-        const C2<Tf> gu = buf[n * SM + m];
+        const C2<Tf> gu = buf[Gm::at(n, m)];
         const double sm = (m - (P - 1) * 0.5) * cfg.pitch;
         const double sn = (n - (P - 1) * 0.5) * cfg.pitch;
         const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
@@ -1192,8 +1226,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           if (t < 3) {
             out = tot(t);
           } else if (t < 6) {
-            const DevPair& pr = a.pairs[c.pair];
-            const double f = c.k0 * pr.n_med[cfg.s_doe];
+            const double f = c.k0 * c.n_in;
             out = f * (tot(3) * c.u[t - 3] + tot(4) * c.v[t - 3]);
           } else {
             out = tot(t - 1);

@@ -150,3 +150,21 @@ def test_g2_differs_from_g1_and_uniform_g2_is_g1(rw):
     b = _gpu_grad(rw, system, cfg, maps, "mixed")
     for x, y in zip(a[1:], b[1:]):           # same kernels; atomics order only
         assert rel_l2(x, y) < 1e-5
+
+
+# ------------------------------------------- the headline FFT size, M = 128 --
+def _p64_case(sampling, N=64):
+    return small_hologram(sampling=sampling, P=64, N=N, rays=4, n_lambda=1, n_field_side=1)
+
+
+def test_mixed_p64_full_mode_gradients(rw):
+    system, cfg, maps = _p64_case("full")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed"), _oracle_grad(system, cfg, maps), 1e-3)
+
+
+def test_mixed_p64_mc_gradients_with_oracle_indices(rw):
+    system, cfg, maps = _p64_case("mag")
+    ref = _oracle_grad(system, cfg, maps)
+    idx = ref[3]
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    _check(_gpu_grad(rw, system, cfg, maps, "mixed", replay=rep), ref, 1e-3)

@@ -228,3 +228,35 @@ def test_autotune_keeps_results(rw):
     assert rel_l2(p1.cpu().numpy(), p0.cpu().numpy()) < 1e-6
     for a, b in zip(g1, g0):
         assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+
+
+# ------------------------------------------- the headline FFT size, M = 128 --
+def _p64_case(sampling, N=64):
+    """Patch side 64 (M = 128, the transform size of the throughput workload),
+    one wavelength and field, 4 x 4 rays."""
+    return small_hologram(sampling=sampling, P=64, N=N, rays=4, n_lambda=1, n_field_side=1)
+
+
+def test_mixed_p64_full_mode_psf_within_1e4(rw):
+    system, cfg, maps = _p64_case("full")
+    plan, psf, _ = _run(rw, system, cfg, maps, "mixed")
+    ref, _ = oracle_psf(system, cfg, maps, values=oracle_param_values(system))
+    assert worst_pair_rel(psf, ref) < 1e-4
+
+
+def test_mixed_p64_mc_replayed_oracle_indices_within_1e4(rw):
+    system, cfg, maps = _p64_case("mag")
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    rep = torch.tensor(np.stack([aux[p]["J"] for p in sorted(aux)]), dtype=torch.int32,
+                       device="cuda")
+    plan, psf, _ = _run(rw, system, cfg, maps, "mixed", replay=rep)
+    assert worst_pair_rel(psf, ref) < 1e-4
+
+
+def test_mixed_p64_own_draws_agree(rw):
+    system, cfg, maps = _p64_case("mag")
+    plan, psf, idx = _run(rw, system, cfg, maps, "mixed", want_idx=True)
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    gi = idx.cpu().numpy()
+    J = np.stack([aux[p]["J"] for p in sorted(aux)])
+    assert (gi == J).mean() >= 0.97
