@@ -211,6 +211,100 @@ template <class Tf, int M, bool kLDS> struct DoeLds {
   RayCtx ctx;
 };
 
+// Sampling weight of a propagating bin: |X| (p_mag) or 1 (p_uni).  Float
+// spectra take the hardware square root; the chunk sums and the draws'
+// rescan of a chunk use this same function, which is all the inverse CDF
+// needs from it.
+__device__ __forceinline__ float samp_w(const C2<float>& x, int sampling) {
+  return sampling == 0 ? __builtin_amdgcn_sqrtf(fmaf(x.re, x.re, x.im * x.im)) : 1.0f;
+}
+__device__ __forceinline__ double samp_w(const C2<double>& x, int sampling) {
+  return sampling == 0 ? cabs_rn(x) : 1.0;
+}
+
+// 128-point transforms of the lines (rows or columns) of the patch buffer in
+// two register passes, n = a + 16 b, k = k1 + 8 k2:
+//   pass A, per (line, a): the 8-point DFT over b, times W_128^(a k1), back
+//   into slots a + 16 k1;
+//   pass B, per (line, k1): the 16-point DFT over the slots a + 16 k1, stored
+//   to slot k1 + 8 k2 once every pass-B read is done.
+// Inputs at or beyond nin are zero (nin = M / 2: the upper half of every
+// 8-point input); outputs below nout are stored, and with zb the outputs nout
+// and M - 1 are stored as zeros.  Row transforms run the lanes along the
+// row, column transforms across 16 consecutive columns, so that the 64-bit
+// stores of every quarter-wavefront land on distinct bank slots of the skewed
+// layout.  Starts and ends with every lane's LDS traffic ordered.
+template <class Tf, int M, int DIR, bool COLS>
+__device__ __forceinline__ void line_fft2(C2<Tf>* buf, const C2<Tf>* tw, int nl, int nin,
+                                          int nout, bool zb) {
+  using Gm = DoeGeom<M>;
+  static_assert(M == 128 && Gm::kSkew, "two-pass lines are 8 x 16 points in the skewed layout");
+  constexpr int SM = Gm::SM;
+  constexpr int RB = 16 * SM + 2;          // 16 rows further in the skewed layout
+  const int tid = opaque_tid();
+  const bool hz = 2 * nin == M;
+  // pass A
+  for (int t = tid; t < nl * 16; t += kDoeThreads) {
+    const int line = COLS ? (t & (M - 1)) : (t >> 4), a = COLS ? (t >> 7) : (t & 15);
+    // slot a + 16 b sits at base + b * step
+    const int base = COLS ? a * SM + Gm::col(line) : Gm::row(line) + a;
+    constexpr int step = COLS ? RB : 17;
+    C2<Tf> x[8];
+    if (hz) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) x[b] = b < 4 ? buf[base + b * step] : C2<Tf>{Tf(0), Tf(0)};
+      reg_fft<Tf, 8, DIR, true>(x);
+    } else {
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        x[b] = a + 16 * b < nin ? buf[base + b * step] : C2<Tf>{Tf(0), Tf(0)};
+      reg_fft<Tf, 8, DIR>(x);
+    }
+#pragma unroll
+    for (int k1 = 1; k1 < 8; ++k1) {
+      const C2<Tf> w0 = tw[(a * k1) & (M - 1)];
+      const C2<Tf> w = {w0.re, DIR > 0 ? -w0.im : w0.im};
+      x[k1] = x[k1] * w;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) buf[base + k1 * step] = x[k1];
+  }
+  __syncthreads();
+  // pass B: at most two tasks per lane (nl * 8 <= 1024)
+  constexpr int NT = 2;
+  C2<Tf> z[NT][16];
+  int ob[NT], k1s[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int t = tid + j * kDoeThreads;
+    k1s[j] = -1;
+    if (t < nl * 8) {
+      const int line = COLS ? (t & (M - 1)) : (t >> 3), k1 = COLS ? (t >> 7) : (t & 7);
+      // slots a + 16 k1 (a < 16) and outputs k1 + 8 k2
+      const int ib = COLS ? 16 * k1 * SM + 2 * k1 + Gm::col(line) : Gm::row(line) + 17 * k1;
+      constexpr int istep = COLS ? SM : 1;
+#pragma unroll
+      for (int a = 0; a < 16; ++a) z[j][a] = buf[ib + a * istep];
+      reg_fft<Tf, 16, DIR>(z[j]);
+      ob[j] = COLS ? k1 * SM + Gm::col(line) : Gm::row(line) + k1;
+      k1s[j] = k1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    if (k1s[j] < 0) continue;
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      const int e = k1s[j] + 8 * k2;
+      const int o = ob[j] + (COLS ? 8 * k2 * SM + 2 * (k2 >> 1) : 8 * k2 + (k2 >> 1));
+      if (e < nout) buf[o] = z[j][k2];
+      else if (zb && (e == nout || e == M - 1)) buf[o] = C2<Tf>{Tf(0), Tf(0)};
+    }
+  }
+  __syncthreads();
+}
+
 // Spectrum of the ray's patch into buf (natural order) and the per-chunk sums of
 // the sampling density into s.pref[chunk] (before the scan).  Returns lastpos
 // candidates through *lastpos (block maximum taken by the caller).
@@ -250,61 +344,91 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     }
   }
   __syncthreads();
-  const bool half = 2 * P == M;     // pad factor 2: the upper half of every input is zero
-  for (int row = g; row < P; row += G) {
-    C2<Tf> x[E];
-    if (half) {
-#pragma unroll
-      for (int n2 = 0; n2 < E; ++n2)
-        x[n2] = n2 < E / 2 ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
-      group_fft<Tf, L, E, -1, true>(x, gl, tw);
-    } else {
-#pragma unroll
-      for (int n2 = 0; n2 < E; ++n2) {
-        const int m = gl + L * n2;
-        x[n2] = m < P ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
-      }
-      group_fft<Tf, L, E, -1>(x, gl, tw);
-    }
-#pragma unroll
-    for (int k2 = 0; k2 < E; ++k2) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
-  }
-  for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
-  __syncthreads();
   int lp = -1;
-  for (int col = g; col < M; col += G) {
-    C2<Tf> x[E];
-    if (half) {
+  if constexpr (Gm::kSkew) {
+    line_fft2<Tf, M, -1, false>(buf, tw, P, P, M, false);      // rows n < P, inputs m < P
+    for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
+    line_fft2<Tf, M, -1, true>(buf, tw, M, P, M, false);       // columns, inputs n < P
+    // sampling weights of the chunks of E consecutive rows of a column
+    for (int t = tid; t < M * (M / E); t += kDoeThreads) {
+      const int col = t & (M - 1), ky0 = E * (t / M);
+      const int jx = col < M / 2 ? col : col - M;
+      const int jys0 = (ky0 + M / 2) & (M - 1);
+      const int ch = ((jx + M / 2) * M + jys0) / E;
+      const Span sp = span[jx + M / 2];
+      const int base = Gm::row(ky0) + Gm::col(col);
+      Tf sum = Tf(0);
+      int last = -1;                                  // last bin of positive weight
 #pragma unroll
-      for (int n2 = 0; n2 < E; ++n2)
-        x[n2] = n2 < E / 2 ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
-      group_fft<Tf, L, E, -1, true>(x, gl, tw);
-    } else {
-#pragma unroll
-      for (int n2 = 0; n2 < E; ++n2) {
-        const int n = gl + L * n2;
-        x[n2] = n < P ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
+      for (int k2 = 0; k2 < E; ++k2) {
+        const int ky = ky0 + k2;
+        const int jy = ky < M / 2 ? ky : ky - M;
+        Tf wgt = Tf(0);
+        if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(buf[base + k2 * SM], sampling);
+        sum += wgt;
+        if (wgt > Tf(0)) last = k2;
       }
-      group_fft<Tf, L, E, -1>(x, gl, tw);
+      chunk[ch] = (double)sum;
+      if (last >= 0) lp = max(lp, ch * E + last);
     }
-    // this lane now holds rows ky = E*br .. E*br + E - 1 of column col
-    const int jx = col < M / 2 ? col : col - M;
-    const int ky0 = E * br;
-    const int jys0 = (ky0 + M / 2) & (M - 1);                  // shifted row of the first bin
-    const int ch = ((jx + M / 2) * M + jys0) / E;              // chunk id (j_x-major)
-    const Span sp = span[jx + M / 2];
-    double s = 0.0;
+  } else {
+    const bool half = 2 * P == M;     // pad factor 2: the upper half of every input is zero
+    for (int row = g; row < P; row += G) {
+      C2<Tf> x[E];
+      if (half) {
 #pragma unroll
-    for (int k2 = 0; k2 < E; ++k2) {
-      const int ky = ky0 + k2;
-      const int jy = ky < M / 2 ? ky : ky - M;
-      buf[Gm::row(ky0) + k2 * SM + Gm::col(col)] = x[k2];
-      double wgt = 0.0;
-      if (jy >= sp.lo && jy <= sp.hi) wgt = sampling == 0 ? (double)cabs_rn(x[k2]) : 1.0;
-      s += wgt;
-      if (wgt > 0.0) lp = max(lp, (jx + M / 2) * M + (jy + M / 2));
+        for (int n2 = 0; n2 < E; ++n2)
+          x[n2] = n2 < E / 2 ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
+        group_fft<Tf, L, E, -1, true>(x, gl, tw);
+      } else {
+#pragma unroll
+        for (int n2 = 0; n2 < E; ++n2) {
+          const int m = gl + L * n2;
+          x[n2] = m < P ? buf[Gm::row(row) + Gm::col_split(gl, L * n2)] : C2<Tf>{Tf(0), Tf(0)};
+        }
+        group_fft<Tf, L, E, -1>(x, gl, tw);
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
     }
-    chunk[ch] = s;
+    for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
+    __syncthreads();
+    for (int col = g; col < M; col += G) {
+      C2<Tf> x[E];
+      if (half) {
+#pragma unroll
+        for (int n2 = 0; n2 < E; ++n2)
+          x[n2] = n2 < E / 2 ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
+        group_fft<Tf, L, E, -1, true>(x, gl, tw);
+      } else {
+#pragma unroll
+        for (int n2 = 0; n2 < E; ++n2) {
+          const int n = gl + L * n2;
+          x[n2] = n < P ? buf[Gm::row_split(gl, L * n2) + Gm::col(col)] : C2<Tf>{Tf(0), Tf(0)};
+        }
+        group_fft<Tf, L, E, -1>(x, gl, tw);
+      }
+      // this lane now holds rows ky = E*br .. E*br + E - 1 of column col
+      const int jx = col < M / 2 ? col : col - M;
+      const int ky0 = E * br;
+      const int jys0 = (ky0 + M / 2) & (M - 1);                  // shifted row of the first bin
+      const int ch = ((jx + M / 2) * M + jys0) / E;              // chunk id (j_x-major)
+      const Span sp = span[jx + M / 2];
+      Tf s = Tf(0);
+      int last = -1;
+#pragma unroll
+      for (int k2 = 0; k2 < E; ++k2) {
+        const int ky = ky0 + k2;
+        const int jy = ky < M / 2 ? ky : ky - M;
+        buf[Gm::row(ky0) + k2 * SM + Gm::col(col)] = x[k2];
+        Tf wgt = Tf(0);
+        if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(x[k2], sampling);
+        s += wgt;
+        if (wgt > Tf(0)) last = k2;
+      }
+      chunk[ch] = (double)s;
+      if (last >= 0) lp = max(lp, ch * E + last);
+    }
   }
   *lastpos = lp;
   __syncthreads();
@@ -383,20 +507,23 @@ __device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, c
     const int mid = (lo + hi + 1) >> 1;
     if (pref[mid] <= T) lo = mid; else hi = mid - 1;
   }
-  double run = pref[lo];
   const int base = lo * E;                       // linear bin of the chunk's first bin
   const int jx = base / M - M / 2;
   const int kx = jx & (M - 1);
   const Span sp = span[jx + M / 2];
+  // double spectra continue the prefix; float spectra rescan the chunk in the
+  // type and order of its chunk sum
+  constexpr bool kDbl = sizeof(Tf) == sizeof(double);
+  const double Tc = kDbl ? T : T - pref[lo];
+  Tf run = kDbl ? (Tf)pref[lo] : Tf(0);
   int lp = -1;
   for (int q = 0; q < E; ++q) {
     const int jy = (base % M) + q - M / 2;
-    double wgt = 0.0;
-    if (jy >= sp.lo && jy <= sp.hi)
-      wgt = sampling == 0 ? (double)cabs_rn(buf[Gm::at(jy & (M - 1), kx)]) : 1.0;
+    Tf wgt = Tf(0);
+    if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(buf[Gm::at(jy & (M - 1), kx)], sampling);
     run += wgt;
-    if (wgt > 0.0) lp = base + q;
-    if (run > T) return base + q;
+    if (wgt > Tf(0)) lp = base + q;
+    if ((double)run > Tc) return base + q;
   }
   return lp >= 0 ? lp : lastpos_all;
 }
@@ -1023,30 +1150,36 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         }
       }
       __syncthreads();
-      // inverse transform: columns (keep rows n < P), then rows n < P (keep m < P)
-      for (int col = g; col < M; col += G) {
-        C2<Tf> x[E];
+      // inverse transform: columns (keep rows n < P), then rows n < P (keep m < P;
+      // columns P and M - 1 become a zero border of the patch gradient)
+      if constexpr (Gm::kSkew) {
+        line_fft2<Tf, M, +1, true>(buf, s.tw, M, M, P, false);
+        line_fft2<Tf, M, +1, false>(buf, s.tw, P, M, P, true);
+      } else {
+        for (int col = g; col < M; col += G) {
+          C2<Tf> x[E];
 #pragma unroll
-        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row_split(gl, L * n2) + Gm::col(col)];
-        group_fft<Tf, L, E, +1>(x, gl, s.tw);
+          for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row_split(gl, L * n2) + Gm::col(col)];
+          group_fft<Tf, L, E, +1>(x, gl, s.tw);
 #pragma unroll
-        for (int k2 = 0; k2 < E; ++k2) {
-          const int n = E * br + k2;
-          if (n < P) buf[Gm::row(E * br) + k2 * SM + Gm::col(col)] = x[k2];
+          for (int k2 = 0; k2 < E; ++k2) {
+            const int n = E * br + k2;
+            if (n < P) buf[Gm::row(E * br) + k2 * SM + Gm::col(col)] = x[k2];
+          }
         }
-      }
-      __syncthreads();
-      for (int row = g; row < P; row += G) {
-        C2<Tf> x[E];
+        __syncthreads();
+        for (int row = g; row < P; row += G) {
+          C2<Tf> x[E];
 #pragma unroll
-        for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row(row) + Gm::col_split(gl, L * n2)];
-        group_fft<Tf, L, E, +1>(x, gl, s.tw);
-        // columns P and M - 1 become a zero border of the patch gradient
+          for (int n2 = 0; n2 < E; ++n2) x[n2] = buf[Gm::row(row) + Gm::col_split(gl, L * n2)];
+          group_fft<Tf, L, E, +1>(x, gl, s.tw);
+          // columns P and M - 1 become a zero border of the patch gradient
 #pragma unroll
-        for (int k2 = 0; k2 < E; ++k2) {
-          const int m = E * br + k2;
-          if (m < P) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
-          else if (m == P || m == M - 1) buf[Gm::row(row) + Gm::col(E * br) + k2] = C2<Tf>{Tf(0), Tf(0)};
+          for (int k2 = 0; k2 < E; ++k2) {
+            const int m = E * br + k2;
+            if (m < P) buf[Gm::row(row) + Gm::col(E * br) + k2] = x[k2];
+            else if (m == P || m == M - 1) buf[Gm::row(row) + Gm::col(E * br) + k2] = C2<Tf>{Tf(0), Tf(0)};
+          }
         }
       }
       // rows P and M - 1 too (the row pass touches rows < P only): the
