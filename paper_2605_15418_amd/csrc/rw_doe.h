@@ -200,6 +200,13 @@ __device__ __forceinline__ PlanarPatch<Tf> planar_patch(const DevCfg& cfg, const
 }
 
 // Shared scratch of one workgroup.
+// One draw's spectrum cogradient term (bin index k, -1: none).
+template <class Tf> struct DrawEnt {
+  C2<Tf> g;
+  int k;
+};
+constexpr int kDrawLds = 256;   // draws per ray whose terms stay in LDS
+
 template <class Tf, int M, bool kLDS> struct DoeLds {
   C2<Tf> buf[kLDS ? DoeGeom<M>::SIZE : 1];
   C2<Tf> tw[M];
@@ -209,6 +216,7 @@ template <class Tf, int M, bool kLDS> struct DoeLds {
   double acc[8][16];
   Span span[M];             // propagating rows of each shifted column
   RayCtx ctx;
+  DrawEnt<Tf> dl[kLDS ? kDrawLds : 1];   // adjoint: the draws' terms when N <= kDrawLds
 };
 
 // Sampling weight of a propagating bin: |X| (p_mag) or 1 (p_uni).  Float
@@ -243,31 +251,53 @@ __device__ __forceinline__ void line_fft2(C2<Tf>* buf, const C2<Tf>* tw, int nl,
   constexpr int RB = 16 * SM + 2;          // 16 rows further in the skewed layout
   const int tid = opaque_tid();
   const bool hz = 2 * nin == M;
-  // pass A
-  for (int t = tid; t < nl * 16; t += kDoeThreads) {
-    const int line = COLS ? (t & (M - 1)) : (t >> 4), a = COLS ? (t >> 7) : (t & 15);
-    // slot a + 16 b sits at base + b * step
-    const int base = COLS ? a * SM + Gm::col(line) : Gm::row(line) + a;
-    constexpr int step = COLS ? RB : 17;
-    C2<Tf> x[8];
+  // pass A, two tasks per round: a lane's tasks touch disjoint slots, so the
+  // loads of both are issued before either transform
+  constexpr int step = COLS ? RB : 17;     // slot a + 16 b sits at base + b * step
+  for (int t0 = tid; t0 < nl * 16; t0 += 2 * kDoeThreads) {
+    C2<Tf> x[2][8];
+    int base[2], av[2];
+    bool on[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = t0 + j * kDoeThreads;
+      on[j] = t < nl * 16;
+      const int line = COLS ? (t & (M - 1)) : (t >> 4);
+      av[j] = COLS ? (t >> 7) : (t & 15);
+      base[j] = COLS ? av[j] * SM + Gm::col(line) : Gm::row(line) + av[j];
+    }
     if (hz) {
 #pragma unroll
-      for (int b = 0; b < 8; ++b) x[b] = b < 4 ? buf[base + b * step] : C2<Tf>{Tf(0), Tf(0)};
-      reg_fft<Tf, 8, DIR, true>(x);
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          x[j][b] = on[j] && b < 4 ? buf[base[j] + b * step] : C2<Tf>{Tf(0), Tf(0)};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) reg_fft<Tf, 8, DIR, true>(x[j]);
     } else {
 #pragma unroll
-      for (int b = 0; b < 8; ++b)
-        x[b] = a + 16 * b < nin ? buf[base + b * step] : C2<Tf>{Tf(0), Tf(0)};
-      reg_fft<Tf, 8, DIR>(x);
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+          x[j][b] = on[j] && av[j] + 16 * b < nin ? buf[base[j] + b * step]
+                                                  : C2<Tf>{Tf(0), Tf(0)};
+#pragma unroll
+      for (int j = 0; j < 2; ++j) reg_fft<Tf, 8, DIR>(x[j]);
     }
 #pragma unroll
-    for (int k1 = 1; k1 < 8; ++k1) {
-      const C2<Tf> w0 = tw[(a * k1) & (M - 1)];
-      const C2<Tf> w = {w0.re, DIR > 0 ? -w0.im : w0.im};
-      x[k1] = x[k1] * w;
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int k1 = 1; k1 < 8; ++k1) {
+        const C2<Tf> w0 = tw[(av[j] * k1) & (M - 1)];
+        const C2<Tf> w = {w0.re, DIR > 0 ? -w0.im : w0.im};
+        x[j][k1] = x[j][k1] * w;
+      }
     }
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1) buf[base + k1 * step] = x[k1];
+    for (int j = 0; j < 2; ++j)
+      if (on[j])
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) buf[base[j] + k1 * step] = x[j][k1];
   }
   __syncthreads();
   // pass B: at most two tasks per lane (nl * 8 <= 1024)
@@ -770,11 +800,6 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
 
 // Spectrum cogradient of one draw, kept in global memory between the draw pass
 // and the S-term pass (bin index k into the LDS spectrum, -1 for none).
-template <class Tf> struct DrawEnt {
-  C2<Tf> g;
-  int k;
-};
-
 // ------------------------------------------------ G2: straight-through ---
 // Gumbel-softmax straight-through gradient of the p_mag draws (reparameterised
 // sampling, Fig. 1c).  Draw i (bin J_i) keeps its hard value; its gradient flows
@@ -999,7 +1024,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       if (cfg.sampling != 2) {
         const double S = chunk_scan<M>(s.pref, s.red);
         const int lastpos_all = block_max_i(lp, s.redi);
-        DrawEnt<Tf>* dl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
+        DrawEnt<Tf>* gdl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
+        const bool dl_lds = kLDS && N <= kDrawLds;
         if (S > 0.0) {
           const double scale = S * inv_m2 / N;
 #pragma unroll 1
@@ -1063,7 +1089,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 }
               }
             }
-            if (lead) dl[i] = ent;
+            if (lead) {
+              if (dl_lds) s.dl[i] = ent;
+              else gdl[i] = ent;
+            }
             if constexpr (kG2) {
               if (lead && cfg.sampling == 0) {
                 float* e = (float*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M) +
@@ -1094,20 +1123,33 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           const Span sp = s.span[jx + M / 2];
           const bool mag = cfg.sampling == 0;
           const Tf fS = (Tf)dLdS;
-          for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
-            const int jy = ky < M / 2 ? ky : ky - M;
-            C2<Tf>& X = buf[Gm::at(ky, kx)];
-            C2<Tf> v = {Tf(0), Tf(0)};
-            if (mag && jy >= sp.lo && jy <= sp.hi) {
-              const Tf m2 = X.re * X.re + X.im * X.im;
-              if (m2 > Tf(0)) {
-                const Tf im = inv_sqrt(m2);
-                Tf f = fS * im;
-                if (kG2 && dlg) f += ((Tf)dlg[ky * M + kx] * im - (Tf)(D2 / S)) * im;
-                v = {X.re * f, X.im * f};
-              }
+          // batches of SB rows: a lane's bins are distinct, so every load of a
+          // batch is issued before its stores
+          constexpr int RS = kDoeThreads / M, SB = M / RS >= 8 ? 8 : (M / RS >= 1 ? M / RS : 1);
+          for (int ky0 = t / M; ky0 < M; ky0 += SB * RS) {
+            C2<Tf> xv[SB];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+              const int ky = ky0 + q * RS;
+              xv[q] = ky < M ? buf[Gm::at(ky, kx)] : C2<Tf>{Tf(0), Tf(0)};
             }
-            X = v;
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+              const int ky = ky0 + q * RS;
+              const int jy = ky < M / 2 ? ky : ky - M;
+              const C2<Tf> X = xv[q];
+              C2<Tf> v = {Tf(0), Tf(0)};
+              if (mag && jy >= sp.lo && jy <= sp.hi) {
+                const Tf m2 = X.re * X.re + X.im * X.im;
+                if (m2 > Tf(0)) {
+                  const Tf im = inv_sqrt(m2);
+                  Tf f = fS * im;
+                  if (kG2 && dlg) f += ((Tf)dlg[ky * M + kx] * im - (Tf)(D2 / S)) * im;
+                  v = {X.re * f, X.im * f};
+                }
+              }
+              if (ky < M) buf[Gm::at(ky, kx)] = v;
+            }
           }
         }
         __syncthreads();
@@ -1115,7 +1157,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         if (S > 0.0 && lead) {
 #pragma unroll 1
           for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
-            const DrawEnt<Tf> e = dl[i];
+            const DrawEnt<Tf> e = dl_lds ? s.dl[i] : gdl[i];
             if (e.k >= 0) {
               atomicAdd(&buf[e.k].re, e.g.re);
               atomicAdd(&buf[e.k].im, e.g.im);
