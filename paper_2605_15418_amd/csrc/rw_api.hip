@@ -382,7 +382,7 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   const int ntiles = (g.nf / tile) * (g.nf / tile);
   StageTimer ts_(pl, RW_STAGE_SPREAD, st);
   const dim3 sg(ntiles, npairs);
-  const size_t lds = (size_t)tile * (tile + 1) * sizeof(C2<Tg>);
+  const size_t lds = (size_t)tile * (tile + pl->w) * sizeof(C2<Tg>);
   const void* sp = (const void*)(b + pl->off_spos);
   const void* sv = (const void*)(b + pl->off_sval);
   const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
@@ -594,7 +594,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     while ((1 << shift) < pl->nf / nb) ++shift;
     pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb};
     const size_t tile = 4 * (size_t)pl->bg.bin;
-    if (tile * (tile + 1) * pl->sz_cg + spread_static_lds(pl->sz_cg / 2, pl->w) > 160 * 1024 ||
+    if (tile * (tile + pl->w) * pl->sz_cg + spread_static_lds(pl->sz_cg / 2, pl->w) > 160 * 1024 ||
         pl->w > 2 * pl->bg.bin) {
       delete pl;
       return fail(RW_ERR_UNSUPPORTED, "PSF size too large for this precision");

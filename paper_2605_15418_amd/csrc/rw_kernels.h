@@ -636,7 +636,9 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   __shared__ unsigned long long s_q[NW][QN];
   __shared__ unsigned long long s_beg[NW][18], s_pre[NW][19];
   const int tile = 4 * g.bin;                 // cells per tile side
-  const int ts = tile + 1;                    // padded row stride
+  // row stride = w (mod 16): the w x w taps of one record (lane = i + w j)
+  // fall on consecutive 8-byte bank slots, conflict-free for the stores
+  const int ts = tile + w;
   C2<Tg>* acc = (C2<Tg>*)s_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ntx = g.nf / tile;
@@ -678,21 +680,22 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
         s_ky[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fy), two_w, bet);
       }
       s_v[wave][lane] = val[r];
-      s_lx[wave][lane] = lx0;
-      s_ly[wave][lane] = ly0;
+      // first tap relative to the tile origin, in [-w, nf - w): a tap lands in
+      // the tile iff its offset is in [0, tile) (nf >= tile + w)
+      s_lx[wave][lane] = ((lx0 - x0 + w) & (g.nf - 1)) - w;
+      s_ly[wave][lane] = ((ly0 - y0 + w) & (g.nf - 1)) - w;
     }
     wave_lds_sync();
     for (int k = 0; k < n; ++k) {
-      const int blx = s_lx[wave][k], bly = s_ly[wave][k];
+      const int dx = s_lx[wave][k], dy = s_ly[wave][k] - sy0;
       const C2<Tg> v = s_v[wave][k];
 #pragma unroll
       for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
         const int tap = tap0 + lane;
         if (tap < w * w) {
           const int i = tap % w, jj = tap / w;
-          const int cx = ((blx + i) & (g.nf - 1)) - x0;
-          const int cy = ((bly + jj) & (g.nf - 1)) - y0;
-          if (cx >= 0 && cx < tile && cy >= sy0 && cy < sy0 + strip) {
+          const int cx = dx + i, cy = dy + jj + sy0;
+          if ((unsigned)cx < (unsigned)tile && (unsigned)(dy + jj) < (unsigned)strip) {
             const Tg kk = s_kx[wave][k][i] * s_ky[wave][k][jj];
             C2<Tg>& d = acc[cy * ts + cx];
             d.re += v.re * kk;
@@ -716,8 +719,8 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
       const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
       const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
       // footprint vs tile columns and vs this wave's strip rows (periodic)
-      const int cx0 = ((lx0 - x0) % g.nf + g.nf) % g.nf;
-      const int cy0 = ((ly0 - y0 - sy0) % g.nf + g.nf) % g.nf;
+      const int cx0 = (lx0 - x0) & (g.nf - 1);
+      const int cy0 = (ly0 - y0 - sy0) & (g.nf - 1);
       hit = (cx0 < tile || cx0 + w > g.nf) && (cy0 < strip || cy0 + w > g.nf);
     }
     const unsigned long long m = __ballot(hit);
