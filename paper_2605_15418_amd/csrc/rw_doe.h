@@ -1298,11 +1298,21 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               if (li[k] >= 0) old[k] = accm[li[k]];
               tp[k] = (lens && mi[k] >= 0) ? tm[mi[k]] : C2<Tf>{Tf(0), Tf(0)};
             }
+            // every map value is consumed, on every path, before the stores:
+            // a load still pending behind them would make later code wait for
+            // the stores.  Slots without a pixel carry tp = 0 (their samples
+            // are finite LDS values).
+            if (lens) {
+#pragma unroll
+              for (int k = 0; k < KB; ++k) lens_term(i0 + k * kDoeThreads, tp[k]);
+            }
+            // and none is left in flight (vmcnt(0) alone: 0x0F70 keeps the
+            // export and LDS counters unconstrained)
+            __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
               if (li[k] < 0) continue;
               accm[li[k]] = {old[k].re + (Tg)v[k].re, old[k].im + (Tg)v[k].im};
-              if (lens) lens_term(i0 + k * kDoeThreads, tp[k]);
             }
           }
         } else {
@@ -1381,6 +1391,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         }
       }
       }
+      // lens: per-wave sums of the incident-state cogradient into s.acc; lanes
+      // 3..5 keep the frame they need, so that the combination can run after
+      // the end-of-ray barrier while the other waves start the next ray
+      double lf = 0.0, lu = 0.0, lv = 0.0;
       if (a.want_lens) {
         double v[7] = {acc.gp[0] + gpx, acc.gp[1] + gpy, acc.gp[2], acc.gkin[0], acc.gkin[1],
                        acc.gopl, acc.gzs};
@@ -1388,28 +1402,27 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
         if ((t & 63) == 0)
           for (int q = 0; q < 7; ++q) s.acc[t >> 6][q] = v[q];
-        __syncthreads();
-        // output component t < 8 of the incident-state cogradient, one lane each
-        if (t < 8) {
-          auto tot = [&](int q) {
-            double r = 0.0;
-            for (int wv = 0; wv < kDoeThreads / 64; ++wv) r += s.acc[wv][q];
-            return r;
-          };
-          const size_t n = a.n_total;
-          double out;
-          if (t < 3) {
-            out = tot(t);
-          } else if (t < 6) {
-            const double f = c.k0 * c.n_in;
-            out = f * (tot(3) * c.u[t - 3] + tot(4) * c.v[t - 3]);
-          } else {
-            out = tot(t - 1);
-          }
-          a.raygrad[(size_t)t * n + gid] = out;
+        if (t >= 3 && t < 6) {
+          lf = c.k0 * c.n_in;
+          lu = c.u[t - 3];
+          lv = c.v[t - 3];
         }
       }
-      __syncthreads();   // buf, tile and pref are reused by the next ray
+      __syncthreads();   // buf, tile and pref are reused by the next ray; s.acc is complete
+      // component t < 8 of the incident-state cogradient, one lane each (s.acc
+      // is next written after several barriers of the next ray)
+      if (a.want_lens && t < 8) {
+        auto tot = [&](int q) {
+          double r = 0.0;
+          for (int wv = 0; wv < kDoeThreads / 64; ++wv) r += s.acc[wv][q];
+          return r;
+        };
+        double out;
+        if (t < 3) out = tot(t);
+        else if (t < 6) out = lf * (tot(3) * lu + tot(4) * lv);
+        else out = tot(t - 1);
+        a.raygrad[(size_t)t * a.n_total + gid] = out;
+      }
     }
     // flush the accumulator over the touched box, clearing it for the next block
     const int bx0 = s_box[0], by0 = s_box[1], bx1 = s_box[2], by1 = s_box[3];
