@@ -124,6 +124,7 @@ struct rw_plan {
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
+      off_jdraw,
       off_interp, off_g2, off_rcls, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
@@ -268,6 +269,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.ctx = (RayCtx*)(b + pl->off_ctx);
   a.dlist = b + pl->off_dlist;
   a.ray_class = (unsigned char*)(b + pl->off_rcls);
+  a.jdraw = pl->cfg.sampling == RW_SAMPLE_FULL ? nullptr : (int32_t*)(b + pl->off_jdraw);
   a.cls = 0;
   return a;
 }
@@ -761,6 +763,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
   pl->off_rcls = take((size_t)nt);
+  pl->off_jdraw = take(cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t));
   pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
                                  sizeof(float)
                            : 0);

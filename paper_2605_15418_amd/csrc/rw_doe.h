@@ -342,7 +342,7 @@ template <class Tf, int M>
 __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
                                              const C2<Tf>* tm, C2<Tf>* buf, const C2<Tf>* tw,
                                              double* chunk, Span* span, int sampling,
-                                             int* lastpos) {
+                                             int* lastpos, bool cdf = true) {
   using Gm = DoeGeom<M>;
   constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
   const int tid = opaque_tid();
@@ -380,7 +380,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
     line_fft2<Tf, M, -1, true>(buf, tw, M, P, M, false);       // columns, inputs n < P
     // sampling weights of the chunks of E consecutive rows of a column
-    for (int t = tid; t < M * (M / E); t += kDoeThreads) {
+    for (int t = tid; cdf && t < M * (M / E); t += kDoeThreads) {
       const int col = t & (M - 1), ky0 = E * (t / M);
       const int jx = col < M / 2 ? col : col - M;
       const int jys0 = (ky0 + M / 2) & (M - 1);
@@ -635,6 +635,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const double S = chunk_scan<M>(s.pref, s.red);
       const int lastpos_all = block_max_i(lp, s.redi);
       const double scale = S * inv_m2 / N;               // S or |Pi| over M^2 N
+      if (t == 0) a.ctx[gid].S = S;                      // for the backward
       for (int i = t; i < N; i += kDoeThreads) {
         int J = -1;
         if (S > 0.0) {
@@ -647,6 +648,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           }
         }
         if (a.idx_out) a.idx_out[gid * N + i] = J;
+        if (a.jdraw) a.jdraw[gid * N + i] = J;
         bool ok = J >= 0;
         C2<Tp> w = {Tp(0), Tp(0)};
         int jx = 0, jy = 0;
@@ -1013,8 +1015,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int T = P + 4;                                // bilinear tile side
       const bool use_tile = Gm::SIZE - Gm::row(P) >= T * T;
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
-      int lp;
-      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
+      // the forward's draws and normaliser, when it recorded them: no CDF here
+      const bool stored = a.jdraw != nullptr && cfg.sampling != 2;
+      const int jpre = stored && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
+      int lp = -1;
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp, !stored);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
       double dLdS = 0.0;
       constexpr int LPD = kTiled ? 1 : 2;   // lanes per secondary ray
@@ -1022,8 +1027,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const bool lead = kTiled || h == 0;   // writes the draw's entries
       const bool side = kTiled || h == 1;   // accumulates the incident-state cogradient
       if (cfg.sampling != 2) {
-        const double S = chunk_scan<M>(s.pref, s.red);
-        const int lastpos_all = block_max_i(lp, s.redi);
+        const double S = stored ? c.S : chunk_scan<M>(s.pref, s.red);
+        const int lastpos_all = stored ? -1 : block_max_i(lp, s.redi);
         DrawEnt<Tf>* gdl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
         const bool dl_lds = kLDS && N <= kDrawLds;
         if (S > 0.0) {
@@ -1031,7 +1036,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
 #pragma unroll 1
           for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
             int J;
-            if (a.replay) {
+            if (stored) {
+              J = i == t ? jpre : a.jdraw[gid * N + i];
+            } else if (a.replay) {
               J = a.replay[gid * N + i];
             } else {
               const double Tv = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,

@@ -250,6 +250,7 @@ struct DoeArgs {
                              // (value, d/dx, d/dy), or null: interpolate in the kernel
   void* g2;                  // G2 per block: double [N][8] draw data, then [M*M] dL/dlog p
   unsigned char* ray_class;  // [n_total] patch class of every ray (0 for dead rays)
+  int32_t* jdraw;            // [n_total][N] bins drawn by the forward (read by the backward)
   int cls;                   // class processed by this launch
 };
 
@@ -258,6 +259,7 @@ struct RayCtx {
   double p[3], d[3], opl;
   double u[3], v[3], n[3];
   double kin_u, kin_v, k0, k_out, n_in, n_out, dk, k2out;
+  double S;                 // sampling normaliser (sum of weights), set by the forward
   int pair, r;
   int P, cls;               // patch side and class of this ray
   size_t gid;
@@ -306,6 +308,7 @@ __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c
   c.P = cfg.class_p[c.cls];
   c.dk = 2.0 * RW_PI / ((double)cfg.pad * c.P * cfg.pitch);
   c.k2out = __dmul_rn(c.k_out, c.k_out);
+  c.S = 0.0;
 }
 
 // Context of every alive ray of [ray0, ray0 + nray), one thread per ray.
