@@ -88,11 +88,12 @@ def doe_fwd_flops_per_ray(P, M, N):
 
 
 def doe_bwd_flops_per_ray(P, M, N, w):
-    """Recomputed forward FFT and draws, the inverse FFT of the spectrum
-    cogradient, bilinear adjoint, and per draw the type-2 interpolation of
-    the value and its two frequency derivatives."""
-    return (2 * 5 * M * M * math.log2(M * M) + 2 * 14 * P * P + 8 * M * M
-            + N * (40 + math.log2(M * M)) + 240 * N + N * 3 * 8 * w * w)
+    """Recomputed forward FFT (the draws and their normaliser are the
+    forward's, not recomputed), the inverse FFT of the spectrum cogradient,
+    bilinear adjoint, and per draw the type-2 interpolation of the value and
+    its two frequency derivatives."""
+    return (2 * 5 * M * M * math.log2(M * M) + 2 * 14 * P * P
+            + 240 * N + N * 3 * 8 * w * w)
 
 
 def spread_flops_per_record(w):
