@@ -338,11 +338,11 @@ __device__ __forceinline__ void line_fft2(C2<Tf>* buf, const C2<Tf>* tw, int nl,
 // Spectrum of the ray's patch into buf (natural order) and the per-chunk sums of
 // the sampling density into s.pref[chunk] (before the scan).  Returns lastpos
 // candidates through *lastpos (block maximum taken by the caller).
-template <class Tf, int M>
+template <class Tf, int M, bool kCdf = true>
 __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
                                              const C2<Tf>* tm, C2<Tf>* buf, const C2<Tf>* tw,
                                              double* chunk, Span* span, int sampling,
-                                             int* lastpos, bool cdf = true) {
+                                             int* lastpos) {
   using Gm = DoeGeom<M>;
   constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
   const int tid = opaque_tid();
@@ -380,7 +380,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
     line_fft2<Tf, M, -1, true>(buf, tw, M, P, M, false);       // columns, inputs n < P
     // sampling weights of the chunks of E consecutive rows of a column
-    for (int t = tid; cdf && t < M * (M / E); t += kDoeThreads) {
+    for (int t = tid; kCdf && t < M * (M / E); t += kDoeThreads) {
       const int col = t & (M - 1), ky0 = E * (t / M);
       const int jx = col < M / 2 ? col : col - M;
       const int jys0 = (ky0 + M / 2) & (M - 1);
@@ -531,11 +531,20 @@ template <class Tf, int M>
 __device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, const Span* span,
                                         double T, int sampling, int lastpos_all) {
   using Gm = DoeGeom<M>;
-  constexpr int E = Gm::E, SM = Gm::SM;
-  int lo = 0, hi = Gm::NCH - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pref[mid] <= T) lo = mid; else hi = mid - 1;
+  constexpr int E = Gm::E, NCH = Gm::NCH;
+  // chunk lo: the last with pref[lo] <= T (prefix sums are non-decreasing),
+  // by a 4-way descent: three independent reads per level
+  static_assert((NCH & (NCH - 1)) == 0 && NCH >= 4, "chunk count must be a power of two");
+  constexpr bool kPow4 = (NCH & 0x55555555) != 0;
+  int lo = 0;
+  int width = NCH;                               // the chunk is in [lo, lo + width)
+  if constexpr (!kPow4) {
+    if (pref[NCH / 2] <= T) lo = NCH / 2;
+    width = NCH / 2;
+  }
+  for (int step = width / 4; step >= 1; step /= 4) {
+    const double p1 = pref[lo + step], p2 = pref[lo + 2 * step], p3 = pref[lo + 3 * step];
+    lo += (p1 <= T ? step : 0) + (p2 <= T ? step : 0) + (p3 <= T ? step : 0);
   }
   const int base = lo * E;                       // linear bin of the chunk's first bin
   const int jx = base / M - M / 2;
@@ -547,13 +556,23 @@ __device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, c
   const double Tc = kDbl ? T : T - pref[lo];
   Tf run = kDbl ? (Tf)pref[lo] : Tf(0);
   int lp = -1;
-  for (int q = 0; q < E; ++q) {
-    const int jy = (base % M) + q - M / 2;
-    Tf wgt = Tf(0);
-    if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(buf[Gm::at(jy & (M - 1), kx)], sampling);
-    run += wgt;
-    if (wgt > Tf(0)) lp = base + q;
-    if ((double)run > Tc) return base + q;
+  // the chunk's bins are read in groups before the scan (all in range)
+  constexpr int EB = E < 16 ? E : 16;
+  for (int q0 = 0; q0 < E; q0 += EB) {
+    C2<Tf> xs[EB];
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const int jy = (base % M) + q0 + q - M / 2;
+      xs[q] = buf[Gm::at(jy & (M - 1), kx)];
+    }
+    for (int q = 0; q < EB; ++q) {
+      const int jy = (base % M) + q0 + q - M / 2;
+      Tf wgt = Tf(0);
+      if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(xs[q], sampling);
+      run += wgt;
+      if (wgt > Tf(0)) lp = base + q0 + q;
+      if ((double)run > Tc) return base + q0 + q;
+    }
   }
   return lp >= 0 ? lp : lastpos_all;
 }
@@ -1015,11 +1034,12 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int T = P + 4;                                // bilinear tile side
       const bool use_tile = Gm::SIZE - Gm::row(P) >= T * T;
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
-      // the forward's draws and normaliser, when it recorded them: no CDF here
-      const bool stored = a.jdraw != nullptr && cfg.sampling != 2;
-      const int jpre = stored && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
+      // the forward's draws and normaliser (it records them for every sampled
+      // ray): no CDF here
+      const bool mc = cfg.sampling != 2;
+      const int jpre = mc && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
       int lp = -1;
-      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp, !stored);
+      doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
       double dLdS = 0.0;
       constexpr int LPD = kTiled ? 1 : 2;   // lanes per secondary ray
@@ -1027,24 +1047,14 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const bool lead = kTiled || h == 0;   // writes the draw's entries
       const bool side = kTiled || h == 1;   // accumulates the incident-state cogradient
       if (cfg.sampling != 2) {
-        const double S = stored ? c.S : chunk_scan<M>(s.pref, s.red);
-        const int lastpos_all = stored ? -1 : block_max_i(lp, s.redi);
+        const double S = c.S;
         DrawEnt<Tf>* gdl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
         const bool dl_lds = kLDS && N <= kDrawLds;
         if (S > 0.0) {
           const double scale = S * inv_m2 / N;
 #pragma unroll 1
           for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
-            int J;
-            if (stored) {
-              J = i == t ? jpre : a.jdraw[gid * N + i];
-            } else if (a.replay) {
-              J = a.replay[gid * N + i];
-            } else {
-              const double Tv = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
-                                             (uint32_t)c.pair, 0u) * S;
-              J = draw_bin<Tf, M>(buf, s.pref, s.span, Tv, cfg.sampling, lastpos_all);
-            }
+            const int J = i == t ? jpre : a.jdraw[gid * N + i];
             DrawEnt<Tf> ent = {{Tf(0), Tf(0)}, -1};
             double g2r[5] = {0.0, 0.0, 0.0, 0.0, -1.0};      // A, B, J of the G2 record
             if (J >= 0) {
