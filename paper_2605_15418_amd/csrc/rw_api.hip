@@ -270,6 +270,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.dlist = b + pl->off_dlist;
   a.ray_class = (unsigned char*)(b + pl->off_rcls);
   a.jdraw = pl->cfg.sampling == RW_SAMPLE_FULL ? nullptr : (int32_t*)(b + pl->off_jdraw);
+  a.full = pl->cfg.sampling == RW_SAMPLE_FULL;
   a.cls = 0;
   return a;
 }

@@ -983,7 +983,7 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
 // kTiled: the sensor-grid cogradient of every record comes from the tiled
 // interpolation pass (one lane per secondary ray); otherwise the kernel
 // interpolates it itself (two lanes per secondary ray share the kernel rows).
-template <class Prec, int M, bool kLDS, bool kG2, bool kTiled>
+template <class Prec, int M, bool kLDS, bool kG2, bool kTiled, bool kFull>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
   using Tf = typename Prec::Tf;
@@ -1036,8 +1036,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
       // the forward's draws and normaliser (it records them for every sampled
       // ray): no CDF here
-      const bool mc = cfg.sampling != 2;
-      const int jpre = mc && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
+      const int jpre = !kFull && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
       int lp = -1;
       doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
@@ -1046,7 +1045,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int h = kTiled ? 0 : (t & 1);
       const bool lead = kTiled || h == 0;   // writes the draw's entries
       const bool side = kTiled || h == 1;   // accumulates the incident-state cogradient
-      if (cfg.sampling != 2) {
+      if constexpr (!kFull) {
         const double S = c.S;
         DrawEnt<Tf>* gdl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
         const bool dl_lds = kLDS && N <= kDrawLds;

@@ -10,18 +10,24 @@ static void go(bool fwd, const DoeArgs& a, const RayBlockIter& it, long long n, 
   if (fwd)
     hipLaunchKernelGGL((k_doe_fwd2<PrecMIXED, M, LDS>), dim3(blocks), dim3(kDoeThreads), 0, st, a, it,
                        n, pair0);
+  else if (a.full && a.interp)
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, true, true>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
+  else if (a.full)
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, false, true>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
   else if (a.g2 && a.interp)
-    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, true, true>), dim3(blocks), dim3(kDoeThreads), 0,
-                       st, a, it, n, pair0);
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, true, true, false>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
   else if (a.g2)
-    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, true, false>), dim3(blocks), dim3(kDoeThreads), 0,
-                       st, a, it, n, pair0);
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, true, false, false>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
   else if (a.interp)
-    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, true>), dim3(blocks), dim3(kDoeThreads), 0,
-                       st, a, it, n, pair0);
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, true, false>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
   else
-    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, false>), dim3(blocks), dim3(kDoeThreads), 0,
-                       st, a, it, n, pair0);
+    hipLaunchKernelGGL((k_doe_bwd2<PrecMIXED, M, LDS, false, false, false>), dim3(blocks),
+                       dim3(kDoeThreads), 0, st, a, it, n, pair0);
 }
 
 hipError_t launch_doe_mixed(bool fwd, int M, bool lds, const DoeArgs& a, const RayBlockIter& it,

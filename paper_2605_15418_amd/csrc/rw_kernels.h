@@ -251,6 +251,7 @@ struct DoeArgs {
   void* g2;                  // G2 per block: double [N][8] draw data, then [M*M] dL/dlog p
   unsigned char* ray_class;  // [n_total] patch class of every ray (0 for dead rays)
   int32_t* jdraw;            // [n_total][N] bins drawn by the forward (read by the backward)
+  int full;                  // FULL sampling (every propagating bin, no draws)
   int cls;                   // class processed by this launch
 };
 
