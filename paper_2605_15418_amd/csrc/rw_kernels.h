@@ -615,8 +615,9 @@ constexpr int kSpreadQueue = 128;    // queued records per wave
 
 // Static LDS of k_spread_tiles<Tg, w> besides the dynamic accumulator tile.
 __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
-  return (size_t)kSpreadWaves * (64 * (2 * (size_t)w * sz_g + 2 * sz_g + 8) + kSpreadQueue * 8 +
-                                 (18 + 19) * 8);
+  return (size_t)kSpreadWaves * (64 * (2 * (size_t)w * sz_g + (2 * sz_g + 8 + 15) / 16 * 16) +
+                                 kSpreadQueue * 8 + (18 + 19) * 8) +
+         256;   // slack for the compiler's alignment of the arrays
 }
 
 // Spreading of one tile (TILE x TILE cells, TILE = 4 BIN).  Wave q owns bin row
@@ -635,8 +636,9 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   constexpr int NW = kSpreadWaves, QN = kSpreadQueue;
   extern __shared__ unsigned char s_raw[];
   __shared__ Tg s_kx[NW][64][w], s_ky[NW][64][w];
-  __shared__ C2<Tg> s_v[NW][64];
-  __shared__ int s_lx[NW][64], s_ly[NW][64];
+  // per queued record: value and first-tap offsets, read by the wave as one entry
+  struct alignas(16) RecEnt { C2<Tg> v; int dx, dy; };
+  __shared__ RecEnt s_r[NW][64];
   __shared__ unsigned long long s_q[NW][QN];
   __shared__ unsigned long long s_beg[NW][18], s_pre[NW][19];
   const int tile = 4 * g.bin;                 // cells per tile side
@@ -683,16 +685,19 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
         s_kx[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fx), two_w, bet);
         s_ky[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fy), two_w, bet);
       }
-      s_v[wave][lane] = val[r];
+      RecEnt e;
+      e.v = val[r];
       // first tap relative to the tile origin, in [-w, nf - w): a tap lands in
       // the tile iff its offset is in [0, tile) (nf >= tile + w)
-      s_lx[wave][lane] = ((lx0 - x0 + w) & (g.nf - 1)) - w;
-      s_ly[wave][lane] = ((ly0 - y0 + w) & (g.nf - 1)) - w;
+      e.dx = ((lx0 - x0 + w) & (g.nf - 1)) - w;
+      e.dy = ((ly0 - y0 + w) & (g.nf - 1)) - w;
+      s_r[wave][lane] = e;
     }
     wave_lds_sync();
     for (int k = 0; k < n; ++k) {
-      const int dx = s_lx[wave][k], dy = s_ly[wave][k] - sy0;
-      const C2<Tg> v = s_v[wave][k];
+      const RecEnt e = s_r[wave][k];
+      const int dx = e.dx, dy = e.dy - sy0;
+      const C2<Tg> v = e.v;
 #pragma unroll
       for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
         const int tap = tap0 + lane;
