@@ -124,6 +124,7 @@ struct rw_plan {
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
       off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
+      off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
       off_interp, off_g2, off_rcls, total;
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
@@ -372,14 +373,30 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   hipLaunchKernelGGL(k_rec_hist<Tg>, grid, dim3(256), g.keys * sizeof(unsigned int), st,
                      (const void*)(b + pl->off_rpos), (const void*)(b + pl->off_rval), per_pair,
                      chunk, g, pair0, (unsigned int*)(b + pl->off_cnt));
+  const int fpc = 1 << (2 * g.sshift);
+  const int nsup = g.keys / fpc;
+  constexpr int C = RecChunk<Tg>::C;
+  unsigned long long* scur = (unsigned long long*)(b + pl->off_scur) + (size_t)pair0 * nsup;
+  unsigned int* work = (unsigned int*)(b + pl->off_work);
   hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(1024), 0, st, (const unsigned int*)cnt,
-                     (size_t)npairs * g.keys, offs, cur);
-  const size_t lds_sc = (size_t)((g.keys + 1) & ~1) * 4 + (size_t)g.keys * 8;
-  hipLaunchKernelGGL(k_rec_scatter<Tg>, grid, dim3(256), lds_sc, st,
-                     (const void*)(b + pl->off_rpos), (const void*)(b + pl->off_rval), per_pair,
-                     chunk, g, pair0, (unsigned long long*)(b + pl->off_cur),
-                     (void*)(b + pl->off_spos), (void*)(b + pl->off_sval),
-                     pl->tiled_interp ? (unsigned long long*)(b + pl->off_sidx) : nullptr);
+                     (size_t)npairs * g.keys, fpc, C, offs, cur, scur, work);
+  unsigned int* tidx = pl->tiled_interp ? (unsigned int*)(b + pl->off_tidx) : nullptr;
+  const unsigned long long* offs_all = (const unsigned long long*)(b + pl->off_offs);
+  hipLaunchKernelGGL((k_rec_place<Tg, true>), dim3((unsigned)((per_pair + C - 1) / C), npairs),
+                     dim3(256), 0, st, (const void*)(b + pl->off_rpos),
+                     (const void*)(b + pl->off_rval), (const unsigned int*)nullptr, per_pair,
+                     offs_all, (const unsigned int*)work, g, pair0,
+                     (unsigned long long*)(b + pl->off_scur), (void*)(b + pl->off_tpos),
+                     (void*)(b + pl->off_tval), tidx);
+  // every super-bin takes ceil(count / C) workgroups: at most records / C + super-bins
+  const size_t nitems = (size_t)npairs * nsup;
+  hipLaunchKernelGGL((k_rec_place<Tg, false>),
+                     dim3((unsigned)((size_t)npairs * per_pair / C + nitems)), dim3(256), 0, st,
+                     (const void*)(b + pl->off_tpos), (const void*)(b + pl->off_tval),
+                     (const unsigned int*)tidx, nitems, offs_all, (const unsigned int*)work, g,
+                     pair0, (unsigned long long*)(b + pl->off_cur), (void*)(b + pl->off_spos),
+                     (void*)(b + pl->off_sval),
+                     pl->tiled_interp ? (unsigned int*)(b + pl->off_sidx) : nullptr);
   delete tb_;
   const int tile = 4 * g.bin;
   const int ntiles = (g.nf / tile) * (g.nf / tile);
@@ -417,7 +434,7 @@ rw_status interp_tiles_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int n
   const size_t lds = (size_t)interp_side(g.bin, pl->w) * interp_side(g.bin, pl->w) * sizeof(C2<Tg>);
   StageTimer ti_(pl, RW_STAGE_INTERP, st);
   const void* sp = (const void*)(b + pl->off_spos);
-  const unsigned long long* si = (const unsigned long long*)(b + pl->off_sidx);
+  const unsigned int* si = (const unsigned int*)(b + pl->off_sidx);
   const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
   const C2<Tg>* adj = (const C2<Tg>*)(b + pl->off_grid);
   C2<Tg>* out = (C2<Tg>*)(b + pl->off_interp);
@@ -595,7 +612,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     const int nb = std::min(64, pl->nf / 8);
     int shift = 0;
     while ((1 << shift) < pl->nf / nb) ++shift;
-    pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb};
+    int ss = 0;                                   // super-bins of up to 8 x 8 bins
+    while (ss < 3 && (2 << ss) <= nb) ++ss;
+    pl->bg = {pl->nf, 1 << shift, shift, nb, nb * nb, ss};
     const size_t tile = 4 * (size_t)pl->bg.bin;
     if (tile * (tile + pl->w) * pl->sz_cg + spread_static_lds(pl->sz_cg / 2, pl->w) > 160 * 1024 ||
         pl->w > 2 * pl->bg.bin) {
@@ -605,13 +624,16 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   }
   pl->rec_chunk = 16384;
   {
-    // launch groups of whole pairs whose secondary-ray records fit in 96 GiB; when
-    // all pairs fit in one group with the tiled interpolation's per-record
-    // index and results as well, the backward uses that path
-    const size_t rec_bytes = (size_t)pl->R2 * pl->emit * 2 * (pl->sz_cg + (dbl_g ? 16 : 8));
-    const size_t tiled_bytes = rec_bytes + (size_t)pl->R2 * pl->emit * (8 + 3 * pl->sz_cg);
+    // launch groups of whole pairs whose secondary-ray records (as produced, after
+    // the super-bin pass and sorted) fit in 96 GiB; when all pairs fit in one
+    // group with the tiled interpolation's per-record indices (32-bit) and
+    // results as well, the backward uses that path
+    const size_t nrec_pair = (size_t)pl->R2 * pl->emit;
+    const size_t rec_bytes = nrec_pair * 3 * (pl->sz_cg + (dbl_g ? 16 : 8));
+    const size_t tiled_bytes = rec_bytes + nrec_pair * (4 + 4 + 3 * pl->sz_cg);
     const size_t budget = (size_t)96 << 30;
-    pl->tiled_interp = cfg->batched && tiled_bytes * pl->n_pairs <= budget;
+    pl->tiled_interp = cfg->batched && tiled_bytes * pl->n_pairs <= budget &&
+                       nrec_pair * pl->n_pairs < ((size_t)1 << 32);
     size_t gp = std::max<size_t>(1, budget / std::max<size_t>(rec_bytes, 1));
     pl->group_pairs = (int)std::min<size_t>(gp, (size_t)pl->n_pairs);
     if (!cfg->batched) pl->group_pairs = 1;
@@ -779,10 +801,15 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     const size_t psz = dbl_g ? 16 : 8;
     pl->off_rpos = take(nrec * psz);
     pl->off_rval = take(nrec * pl->sz_cg);
+    pl->off_tpos = take(nrec * psz);
+    pl->off_tval = take(nrec * pl->sz_cg);
+    pl->off_tidx = take(pl->tiled_interp ? nrec * 4 : 0);
     pl->off_spos = take(nrec * psz);
     pl->off_sval = take(nrec * pl->sz_cg);
     const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
-    pl->off_sidx = take(pl->tiled_interp ? nrec * 8 : 0);
+    pl->off_sidx = take(pl->tiled_interp ? nrec * 4 : 0);
+    pl->off_scur = take((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) * 8);
+    pl->off_work = take(((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) + 1) * 4);
     pl->off_interp = take(pl->tiled_interp ? nrec * 3 * pl->sz_cg : 0);
     pl->off_cnt = take(nk * sizeof(unsigned int));
     pl->off_offs = take((nk + 1) * sizeof(unsigned long long));

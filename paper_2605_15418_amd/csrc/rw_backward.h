@@ -171,7 +171,7 @@ __host__ __device__ constexpr int interp_side(int bin, int w) { return 2 * bin +
 
 template <class Tg, int w>
 __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
-                                                      const unsigned long long* srt_idx,
+                                                      const unsigned int* srt_idx,
                                                       const unsigned long long* offsets,
                                                       BinGeom g, double beta, int pair0,
                                                       const C2<Tg>* adj, C2<Tg>* out) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   }
   if (threadIdx.x < 4) {
     const int by = sby * 2 + (int)threadIdx.x / 2, bx = sbx * 2 + (int)threadIdx.x % 2;
-    const int k = by * g.nb + bx;
+    const int k = bin_key(by, bx, g);
     const unsigned long long* off = offsets + (size_t)pair * g.keys;
     s_beg[threadIdx.x] = off[k];
     s_pre[threadIdx.x + 1] = off[k + 1] - off[k];
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
       dxr += (double)(ky * s1r); dxi += (double)(ky * s1i);
       dyr += (double)(dky * s0r); dyi += (double)(dky * s0i);
     }
-    C2<Tg>* o = out + 3 * srt_idx[r];
+    C2<Tg>* o = out + 3 * (size_t)srt_idx[r];
     o[0] = {(Tg)g0r, (Tg)g0i};
     o[1] = {(Tg)dxr, (Tg)dxi};
     o[2] = {(Tg)dyr, (Tg)dyi};

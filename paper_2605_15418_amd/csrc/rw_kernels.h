@@ -5,7 +5,7 @@
 //   k_trace      launch + conventional refractive trace to the DOE, with
 //                per-surface checkpoints of the ray state (one thread per ray)
 //   (the ray-wave interface kernels live in rw_doe.h)
-//   k_rec_hist / k_rec_scan / k_rec_scatter / k_spread_tiles   binned type-1
+//   k_rec_hist / k_rec_scan / k_rec_place / k_spread_tiles   binned type-1
 //                NUFFT spreading of the Eq. 2 wavelets onto the 2x grid
 //   k_grid_rows / k_grid_cols   grid FFT, deconvolution, crop, |U|^2
 //   k_loss_pairs / k_loss_total Eq. 5 with the closed-form alpha per PSF
@@ -476,15 +476,30 @@ __device__ __forceinline__ C2<Tf> centre_ref(int jx, int jy, int P, int M) {
 // workgroup per TILE x TILE cells (TILE = 4 BIN) gathers the records of its own
 // bins and of a one-bin margin (w / 2 <= BIN), accumulates the ES-kernel taps
 // that fall inside its tile in LDS, and stores the tile: no global atomics.
+//
+// Bin keys run over super-bins of SB x SB bins (SB = 1 << sshift), bins of one
+// super-bin contiguous, so the counting sort can go in two passes that both
+// write long runs: records to their super-bin, then each super-bin's records to
+// their bins (a one-pass scatter over all bins of a pair writes a few records
+// per bin and workgroup, each its own partial line).
 struct BinGeom {
   int nf, bin, shift;      // BIN = 1 << shift cells
   int nb;                  // bins per axis
   int keys;                // bins per pair
+  int sshift;              // super-bin side = 1 << sshift bins (<= nb)
 };
+
+constexpr int kMaxSuper = 64;  // super-bins per pair
+
+__host__ __device__ __forceinline__ int bin_key(int by, int bx, const BinGeom& g) {
+  const int sm = (1 << g.sshift) - 1, ns = g.nb >> g.sshift;
+  return ((((by >> g.sshift) * ns + (bx >> g.sshift)) << g.sshift | (by & sm)) << g.sshift) |
+         (bx & sm);
+}
 
 __device__ __forceinline__ int rec_key(double gx, double gy, const BinGeom& g) {
   const int cx = min((int)gx, g.nf - 1), cy = min((int)gy, g.nf - 1);
-  return (cy >> g.shift) * g.nb + (cx >> g.shift);
+  return bin_key(cy >> g.shift, cx >> g.shift, g);
 }
 
 template <class Tg>
@@ -512,18 +527,22 @@ __global__ __launch_bounds__(256) void k_rec_hist(const void* rec_pos, const voi
     if (s_h[i]) atomicAdd(&out[i], s_h[i]);
 }
 
-// Exclusive scan of the bin counts (one workgroup); cursors start at the offsets.
+// Exclusive scan of the bin counts (one workgroup); cursors start at the offsets,
+// and the cursor of each super-bin (fpc bins) at its first bin's offset.  Then
+// the work list of the second sort pass: work[i] = first workgroup of super-bin
+// i (pair-major), each super-bin taking ceil(count / chunk) workgroups.
 static __global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* counts, size_t n,
+                                                   int fpc, int chunk,
                                                    unsigned long long* offsets,
-                                                   unsigned long long* cursor) {
+                                                   unsigned long long* cursor,
+                                                   unsigned long long* scursor,
+                                                   unsigned int* work) {
   __shared__ unsigned long long s_w[16];
   __shared__ unsigned long long s_carry;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (size_t b0 = 0; b0 < n; b0 += 1024) {
-    const size_t i = b0 + threadIdx.x;
-    const unsigned long long v = i < n ? counts[i] : 0ull;
+  auto block_scan = [&](unsigned long long v, unsigned long long& pre_out) {
     unsigned long long inc = v;
     for (int o = 1; o < 64; o <<= 1) {
       const unsigned long long x = __shfl_up(inc, o, 64);
@@ -533,7 +552,7 @@ static __global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* co
     __syncthreads();
     unsigned long long pre = s_carry;
     for (int k = 0; k < wv; ++k) pre += s_w[k];
-    if (i < n) { offsets[i] = pre + inc - v; cursor[i] = pre + inc - v; }
+    pre_out = pre + inc - v;
     __syncthreads();
     if (threadIdx.x == 1023) {
       unsigned long long tot = s_carry;
@@ -541,52 +560,162 @@ static __global__ __launch_bounds__(1024) void k_rec_scan(const unsigned int* co
       s_carry = tot;
     }
     __syncthreads();
+  };
+  for (size_t b0 = 0; b0 < n; b0 += 1024) {
+    const size_t i = b0 + threadIdx.x;
+    unsigned long long ex;
+    block_scan(i < n ? counts[i] : 0ull, ex);
+    if (i < n) {
+      offsets[i] = ex;
+      cursor[i] = ex;
+      if (i % fpc == 0) scursor[i / fpc] = ex;
+    }
   }
-  if (threadIdx.x == 0) offsets[n] = s_carry;
+  if (threadIdx.x == 0) { offsets[n] = s_carry; s_carry = 0; }
+  __syncthreads();                       // offsets visible to the whole workgroup
+  const size_t ns = n / fpc;
+  for (size_t b0 = 0; b0 < ns; b0 += 1024) {
+    const size_t i = b0 + threadIdx.x;
+    unsigned long long nch = 0;
+    if (i < ns) nch = (offsets[(i + 1) * fpc] - offsets[i * fpc] + chunk - 1) / chunk;
+    unsigned long long ex;
+    block_scan(nch, ex);
+    if (i < ns) work[i] = (unsigned int)ex;
+  }
+  if (threadIdx.x == 0) work[ns] = (unsigned int)s_carry;
 }
 
-template <class Tg>
-__global__ __launch_bounds__(256) void k_rec_scatter(const void* rec_pos, const void* rec_val,
-                                                     size_t per_pair, int chunk, BinGeom g,
-                                                     int pair0, unsigned long long* cursor,
-                                                     void* srt_pos, void* srt_val,
-                                                     unsigned long long* srt_idx) {
+// Records per workgroup of either sort pass.
+template <class Tg> struct RecChunk { static constexpr int C = sizeof(Tg) == 4 ? 2048 : 1024; };
+
+// One counting-sort pass over a chunk of records.  kSuper: the records of a
+// chunk of slots of one pair go to their super-bin (skipping empty slots; the
+// slot goes along as the record's index when dst_idx is given).  Otherwise: a
+// chunk of one super-bin's records (work-list item) goes to its bins.  The
+// chunk is ranked by key in LDS (one atomic per record), every key reserves its
+// range with one global atomic, and the chunk is staged in LDS in key order, so
+// that each wave stores runs of consecutive records: whole lines, where the
+// direct scatter of a record at a time left a partial line per record.
+template <class Tg, bool kSuper>
+__global__ __launch_bounds__(256) void k_rec_place(const void* src_pos, const void* src_val,
+                                                   const unsigned int* src_idx, size_t per_pair,
+                                                   const unsigned long long* offsets,
+                                                   const unsigned int* work, BinGeom g,
+                                                   int pair0, unsigned long long* cursor,
+                                                   void* dst_pos, void* dst_val,
+                                                   unsigned int* dst_idx) {
   using U = typename RecPos<Tg>::T;
-  extern __shared__ unsigned int s_h[];                 // [keys] counts, then [keys] bases
-  unsigned long long* s_base = (unsigned long long*)(s_h + ((g.keys + 1) & ~1));
-  const int pair_l = blockIdx.y;
-  const size_t base = (size_t)pair_l * per_pair + (size_t)blockIdx.x * chunk;
-  const size_t end = min(base + (size_t)chunk, (size_t)(pair_l + 1) * per_pair);
-  for (int i = threadIdx.x; i < g.keys; i += blockDim.x) s_h[i] = 0;
-  __syncthreads();
-  const U* pos = (const U*)rec_pos;
-  const C2<Tg>* val = (const C2<Tg>*)rec_val;
-  for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
-    const C2<Tg> v = val[r];
-    if (is_none(v)) continue;
-    const int k = rec_key(turns_to_cells(pos[2 * r], g.nf), turns_to_cells(pos[2 * r + 1], g.nf), g);
-    atomicAdd(&s_h[k], 1u);
+  constexpr int C = RecChunk<Tg>::C, PER = C / 256;
+  struct UP { U x, y; };
+  __shared__ UP s_pos[C];
+  __shared__ C2<Tg> s_val[C];
+  __shared__ unsigned int s_idx[C];
+  __shared__ unsigned char s_key[C];
+  __shared__ unsigned int s_cnt[kMaxSuper], s_loc[kMaxSuper];
+  __shared__ unsigned long long s_gb[kMaxSuper];
+  __shared__ unsigned long long s_rng[2];
+  __shared__ int s_item;
+  const int fsh = 2 * g.sshift, fpc = 1 << fsh;
+  const int nsx = g.nb >> g.sshift, ns = nsx * nsx;
+  const int nk = kSuper ? ns : fpc;                     // keys of this pass (<= 64)
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < kMaxSuper) s_cnt[tid] = 0;
+  if (tid == 0) {
+    if constexpr (kSuper) {
+      const size_t b0 = (size_t)blockIdx.y * per_pair + (size_t)blockIdx.x * C;
+      s_rng[0] = b0;
+      s_rng[1] = min(b0 + (size_t)C, (size_t)(blockIdx.y + 1) * per_pair);
+      s_item = blockIdx.y * ns;
+    } else {
+      // work item: the super-bin i with work[i] <= blockIdx.x < work[i + 1]
+      const unsigned int w = blockIdx.x;
+      const int nitems = (int)per_pair;
+      int item = -1;
+      if (w < work[nitems]) {
+        int lo = 0, hi = nitems;                        // work[lo] <= w < work[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (work[mid] <= w) lo = mid; else hi = mid;
+        }
+        item = lo;
+        const int pl = item / ns, sb = item % ns;
+        const unsigned long long* off = offsets + (size_t)(pair0 + pl) * g.keys + (size_t)sb * fpc;
+        const unsigned long long b0 = off[0] + (unsigned long long)(w - work[item]) * C;
+        s_rng[0] = b0;
+        s_rng[1] = min(b0 + (unsigned long long)C, off[fpc]);
+      }
+      s_item = item;
+    }
   }
   __syncthreads();
-  unsigned long long* cur = cursor + (size_t)(pair0 + pair_l) * g.keys;
-  for (int i = threadIdx.x; i < g.keys; i += blockDim.x) {
-    const unsigned int n = s_h[i];
-    s_base[i] = n ? atomicAdd(&cur[i], (unsigned long long)n) : 0ull;
-    s_h[i] = 0;
+  const int item = s_item;
+  if (item < 0) return;                                 // uniform over the workgroup
+  const unsigned long long base = s_rng[0], end = s_rng[1];
+  const U* pos = (const U*)src_pos;
+  const C2<Tg>* val = (const C2<Tg>*)src_val;
+  U px[PER], py[PER];
+  C2<Tg> v[PER];
+  unsigned int id[PER];
+  int key[PER], rank[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const unsigned long long r = base + (unsigned long long)(j * 256 + tid);
+    key[j] = -1;
+    if (r < end) {
+      v[j] = val[r];
+      px[j] = pos[2 * r];
+      py[j] = pos[2 * r + 1];
+      id[j] = kSuper ? (unsigned int)r : (src_idx ? src_idx[r] : 0u);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const unsigned long long r = base + (unsigned long long)(j * 256 + tid);
+    if (r < end && (!kSuper || !is_none(v[j]))) {
+      const int k = rec_key(turns_to_cells(px[j], g.nf), turns_to_cells(py[j], g.nf), g);
+      key[j] = kSuper ? k >> fsh : k & (fpc - 1);
+      rank[j] = (int)atomicAdd(&s_cnt[key[j]], 1u);
+    }
   }
   __syncthreads();
-  U* op = (U*)srt_pos;
-  C2<Tg>* ov = (C2<Tg>*)srt_val;
-  for (size_t r = base + threadIdx.x; r < end; r += blockDim.x) {
-    const C2<Tg> v = val[r];
-    if (is_none(v)) continue;
-    const U px = pos[2 * r], py = pos[2 * r + 1];
-    const int k = rec_key(turns_to_cells(px, g.nf), turns_to_cells(py, g.nf), g);
-    const unsigned long long o = s_base[k] + atomicAdd(&s_h[k], 1u);
-    op[2 * o] = px;
-    op[2 * o + 1] = py;
-    ov[o] = v;
-    if (srt_idx) srt_idx[o] = r;
+  if (tid < 64) {
+    const unsigned int c = tid < nk ? s_cnt[tid] : 0u;
+    unsigned int inc = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned int x = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += x;
+    }
+    if (tid < nk) {
+      s_loc[tid] = inc - c;
+      unsigned long long* cur =
+          kSuper ? cursor + (size_t)(pair0 + item / ns) * ns + tid
+                 : cursor + (size_t)(pair0 + item / ns) * g.keys + (size_t)(item % ns) * fpc + tid;
+      s_gb[tid] = c ? atomicAdd(cur, (unsigned long long)c) : 0ull;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    if (key[j] >= 0) {
+      const int p = (int)s_loc[key[j]] + rank[j];
+      s_pos[p] = {px[j], py[j]};
+      s_val[p] = v[j];
+      s_idx[p] = id[j];
+      s_key[p] = (unsigned char)key[j];
+    }
+  }
+  __syncthreads();
+  const int tot = (int)(s_loc[nk - 1] + s_cnt[nk - 1]);
+  U* op = (U*)dst_pos;
+  C2<Tg>* ov = (C2<Tg>*)dst_val;
+  for (int t = tid; t < tot; t += 256) {
+    const int k = s_key[t];
+    const unsigned long long o = s_gb[k] + (unsigned long long)(t - (int)s_loc[k]);
+    const UP q = s_pos[t];
+    op[2 * o] = q.x;
+    op[2 * o + 1] = q.y;
+    ov[o] = s_val[t];
+    if (dst_idx) dst_idx[o] = s_idx[t];
   }
 }
 
@@ -659,7 +788,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   if (lane < 18) {
     const int by = lane / 6 - 1, bx = lane % 6 - 1;
     const int bny = (ty * 4 + wave + by + g.nb) % g.nb, bnx = (tx * 4 + bx + g.nb) % g.nb;
-    const int k = bny * g.nb + bnx;
+    const int k = bin_key(bny, bnx, g);
     s_beg[wave][lane] = off[k];
     s_pre[wave][lane + 1] = off[k + 1] - off[k];
   }
