@@ -823,21 +823,31 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
       s_r[wave][lane] = e;
     }
     wave_lds_sync();
-    for (int k = 0; k < n; ++k) {
-      const RecEnt e = s_r[wave][k];
-      const int dx = e.dx, dy = e.dy - sy0;
-      const C2<Tg> v = e.v;
+    // entries are read RB at a time ahead of the accumulator updates, so that
+    // each record costs one LDS round trip (the read-modify-write of its taps)
+    constexpr int RB = 4;
+    for (int k0 = 0; k0 < n; k0 += RB) {
+      RecEnt e[RB];
 #pragma unroll
-      for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
-        const int tap = tap0 + lane;
-        if (tap < w * w) {
-          const int i = tap % w, jj = tap / w;
-          const int cx = dx + i, cy = dy + jj + sy0;
-          if ((unsigned)cx < (unsigned)tile && (unsigned)(dy + jj) < (unsigned)strip) {
-            const Tg kk = s_kx[wave][k][i] * s_ky[wave][k][jj];
-            C2<Tg>& d = acc[cy * ts + cx];
-            d.re += v.re * kk;
-            d.im += v.im * kk;
+      for (int u = 0; u < RB; ++u) e[u] = s_r[wave][min(k0 + u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int k = k0 + u;
+        if (k >= n) break;                         // wave-uniform
+        const int dx = e[u].dx, dy = e[u].dy - sy0;
+        const C2<Tg> v = e[u].v;
+#pragma unroll
+        for (int tap0 = 0; tap0 < w * w; tap0 += 64) {
+          const int tap = tap0 + lane;
+          if (tap < w * w) {
+            const int i = tap % w, jj = tap / w;
+            const int cx = dx + i, cy = dy + jj + sy0;
+            if ((unsigned)cx < (unsigned)tile && (unsigned)(dy + jj) < (unsigned)strip) {
+              const Tg kk = s_kx[wave][k][i] * s_ky[wave][k][jj];
+              C2<Tg>& d = acc[cy * ts + cx];
+              d.re += v.re * kk;
+              d.im += v.im * kk;
+            }
           }
         }
       }
