@@ -740,11 +740,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kSpreadWaves = 4;      // waves per spreading block (256 threads)
-constexpr int kSpreadQueue = 128;    // queued records per wave
+constexpr int kSpreadBatch = 32;     // queued records staged and added per round
+constexpr int kSpreadQueue = 96;     // queue capacity: a batch plus one scan step
 
 // Static LDS of k_spread_tiles<Tg, w> besides the dynamic accumulator tile.
 __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
-  return (size_t)kSpreadWaves * (64 * (2 * (size_t)w * sz_g + (2 * sz_g + 8 + 15) / 16 * 16) +
+  return (size_t)kSpreadWaves * (kSpreadBatch * (2 * (size_t)w * sz_g + (2 * sz_g + 8 + 15) / 16 * 16) +
                                  kSpreadQueue * 8 + (18 + 19) * 8) +
          256;   // slack for the compiler's alignment of the arrays
 }
@@ -752,22 +753,24 @@ __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
 // Spreading of one tile (TILE x TILE cells, TILE = 4 BIN).  Wave q owns bin row
 // q of the tile (a strip no other wave writes) and scans the records of the
 // 3 x 6 bins whose kernel footprints can reach it (w / 2 <= BIN).  Records that
-// meet the strip are queued; per 64 queued records every lane evaluates the
-// separable ES-kernel factors of one record into LDS, then the wave walks the
-// batch: for each record every lane adds one tap with a plain LDS
-// read-modify-write (the taps of one record are distinct cells): no atomics.
+// meet the strip are queued; per 32 queued records the lanes evaluate the
+// separable ES-kernel factors (x in the low half-wave, y in the high one) into
+// LDS, then the wave walks the batch: for each record every lane adds one tap
+// with a plain LDS read-modify-write (the taps of one record are distinct
+// cells): no atomics.  Batches of 32 keep the block within a third of the LDS,
+// three blocks per CU.
 template <class Tg, int w>
 __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
                                                       const unsigned long long* offsets,
                                                       BinGeom g, double beta, int pair0,
                                                       C2<Tg>* grid) {
   using U = typename RecPos<Tg>::T;
-  constexpr int NW = kSpreadWaves, QN = kSpreadQueue;
+  constexpr int NW = kSpreadWaves, QN = kSpreadQueue, QB = kSpreadBatch;
   extern __shared__ unsigned char s_raw[];
-  __shared__ Tg s_kx[NW][64][w], s_ky[NW][64][w];
+  __shared__ Tg s_kx[NW][QB][w], s_ky[NW][QB][w];
   // per queued record: value and first-tap offsets, read by the wave as one entry
   struct alignas(16) RecEnt { C2<Tg> v; int dx, dy; };
-  __shared__ RecEnt s_r[NW][64];
+  __shared__ RecEnt s_r[NW][QB];
   __shared__ unsigned long long s_q[NW][QN];
   __shared__ unsigned long long s_beg[NW][18], s_pre[NW][19];
   const int tile = 4 * g.bin;                 // cells per tile side
@@ -804,23 +807,25 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   // stage queue entries [0, n) and add their taps to the strip
   auto process = [&](int n) {
     wave_lds_sync();
-    if (lane < n) {
-      const unsigned long long r = s_q[wave][lane];
+    const int q = lane & (QB - 1);                 // record of this lane
+    const bool hi = lane >= QB;                    // low half: x factors, high half: y
+    if (q < n) {
+      const unsigned long long r = s_q[wave][q];
       const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
       const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
-      const double fx = gx - lx0, fy = gy - ly0;
+      const double f = hi ? gy - ly0 : gx - lx0;
+      Tg* kf = hi ? &s_ky[wave][q][0] : &s_kx[wave][q][0];
 #pragma unroll
-      for (int i = 0; i < w; ++i) {
-        s_kx[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fx), two_w, bet);
-        s_ky[wave][lane][i] = es_kernel<Tg>((Tg)((double)i - fy), two_w, bet);
+      for (int i = 0; i < w; ++i) kf[i] = es_kernel<Tg>((Tg)((double)i - f), two_w, bet);
+      if (!hi) {
+        RecEnt e;
+        e.v = val[r];
+        // first tap relative to the tile origin, in [-w, nf - w): a tap lands in
+        // the tile iff its offset is in [0, tile) (nf >= tile + w)
+        e.dx = ((lx0 - x0 + w) & (g.nf - 1)) - w;
+        e.dy = ((ly0 - y0 + w) & (g.nf - 1)) - w;
+        s_r[wave][q] = e;
       }
-      RecEnt e;
-      e.v = val[r];
-      // first tap relative to the tile origin, in [-w, nf - w): a tap lands in
-      // the tile iff its offset is in [0, tile) (nf >= tile + w)
-      e.dx = ((lx0 - x0 + w) & (g.nf - 1)) - w;
-      e.dy = ((ly0 - y0 + w) & (g.nf - 1)) - w;
-      s_r[wave][lane] = e;
     }
     wave_lds_sync();
     // entries are read RB at a time ahead of the accumulator updates, so that
@@ -873,13 +878,13 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
     }
     const unsigned long long m = __ballot(hit);
     const int pre = __popcll(m & ((1ull << lane) - 1ull));
-    if (hit) s_q[wave][qn + pre] = r;
+    if (hit) s_q[wave][qn + pre] = r;          // qn < QB: at most QB + 63 < QN entries
     qn += __popcll(m);
-    if (qn >= 64) {
-      process(64);
-      // move the overflow to the front of the queue
-      const int rest = qn - 64;
-      const unsigned long long t = lane < rest ? s_q[wave][64 + lane] : 0ull;
+    while (qn >= QB) {                         // wave-uniform
+      process(QB);
+      // move the overflow (< 64 entries) to the front of the queue
+      const int rest = qn - QB;
+      const unsigned long long t = lane < rest ? s_q[wave][QB + lane] : 0ull;
       wave_lds_sync();
       if (lane < rest) s_q[wave][lane] = t;
       qn = rest;
