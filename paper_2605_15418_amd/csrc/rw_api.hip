@@ -630,7 +630,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     // results as well, the backward uses that path
     const size_t nrec_pair = (size_t)pl->R2 * pl->emit;
     const size_t rec_bytes = nrec_pair * 3 * (pl->sz_cg + (dbl_g ? 16 : 8));
-    const size_t tiled_bytes = rec_bytes + nrec_pair * (4 + 4 + 3 * pl->sz_cg);
+    const size_t tiled_bytes = rec_bytes + nrec_pair * (4 + 4 + kInterpStride * pl->sz_cg);
     const size_t budget = (size_t)96 << 30;
     pl->tiled_interp = cfg->batched && tiled_bytes * pl->n_pairs <= budget &&
                        nrec_pair * pl->n_pairs < ((size_t)1 << 32);
@@ -810,7 +810,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     pl->off_sidx = take(pl->tiled_interp ? nrec * 4 : 0);
     pl->off_scur = take((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) * 8);
     pl->off_work = take(((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) + 1) * 4);
-    pl->off_interp = take(pl->tiled_interp ? nrec * 3 * pl->sz_cg : 0);
+    pl->off_interp = take(pl->tiled_interp ? nrec * kInterpStride * pl->sz_cg : 0);
     pl->off_cnt = take(nk * sizeof(unsigned int));
     pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
     pl->off_cur = take(nk * sizeof(unsigned long long));

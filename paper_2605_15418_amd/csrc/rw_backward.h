@@ -162,6 +162,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------ type-2 interpolation, tiled ---
+// Results per record: B, dB/dx, dB/dy and a pad, so that a record fills one
+// aligned 32-byte sector (FP32) of the scattered stores.
+constexpr int kInterpStride = 4;
+
 // Cogradient of every secondary-ray record of the forward (sorted by bin):
 // the sensor-grid cogradient B interpolated with the ES kernel at the record's
 // grid coordinate, and with the kernel's derivative along x and along y.  One
@@ -186,9 +190,21 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   const int sby = blockIdx.x / nsb, sbx = blockIdx.x % nsb;
   const int X0 = sbx * 2 * g.bin - half, Y0 = sby * 2 * g.bin - half;
   const C2<Tg>* gp = adj + (size_t)pair * g.nf * g.nf;
-  for (int i = threadIdx.x; i < side * side; i += blockDim.x) {
-    const int cy = i / side, cx = i - cy * side;
-    cells[i] = gp[(size_t)((Y0 + cy) & (g.nf - 1)) * g.nf + ((X0 + cx) & (g.nf - 1))];
+  // cells staged 8 per lane at a time: the loads are issued before the stores
+  for (int i0 = threadIdx.x; i0 < side * side; i0 += 8 * blockDim.x) {
+    C2<Tg> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      const int cy = i / side, cx = i - cy * side;
+      if (i < side * side)
+        v[u] = gp[(size_t)((Y0 + cy) & (g.nf - 1)) * g.nf + ((X0 + cx) & (g.nf - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * (int)blockDim.x;
+      if (i < side * side) cells[i] = v[u];
+    }
   }
   if (threadIdx.x < 4) {
     const int by = sby * 2 + (int)threadIdx.x / 2, bx = sbx * 2 + (int)threadIdx.x % 2;
@@ -206,11 +222,27 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   const U* pos = (const U*)srt_pos;
   const Tg tw = (Tg)(2.0 / w), bet = (Tg)beta;
   const unsigned long long ntot = s_pre[4];
-  for (unsigned long long j = threadIdx.x; j < ntot; j += blockDim.x) {
-    int b = 0;
+  // the position and slot of the next record are loaded before the current one
+  // is interpolated
+  int b = 0;                                        // monotonic over the lane's records
+  auto rec_of = [&](unsigned long long j) {
     while (j >= s_pre[b + 1]) ++b;
-    const unsigned long long r = s_beg[b] + (j - s_pre[b]);
-    const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+    return s_beg[b] + (j - s_pre[b]);
+  };
+  U nx = 0, ny = 0;
+  unsigned int nid = 0;
+  if (threadIdx.x < ntot) {
+    const unsigned long long r = rec_of(threadIdx.x);
+    nx = pos[2 * r]; ny = pos[2 * r + 1]; nid = srt_idx[r];
+  }
+  for (unsigned long long j = threadIdx.x; j < ntot; j += blockDim.x) {
+    const U px = nx, py = ny;
+    const unsigned int slot = nid;
+    if (j + blockDim.x < ntot) {
+      const unsigned long long r = rec_of(j + blockDim.x);
+      nx = pos[2 * r]; ny = pos[2 * r + 1]; nid = srt_idx[r];
+    }
+    const double gx = turns_to_cells(px, g.nf), gy = turns_to_cells(py, g.nf);
     const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
     Tg kx[w], dkx[w];
 #pragma unroll
@@ -246,10 +278,11 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
       dxr += (double)(ky * s1r); dxi += (double)(ky * s1i);
       dyr += (double)(dky * s0r); dyi += (double)(dky * s0i);
     }
-    C2<Tg>* o = out + 3 * (size_t)srt_idx[r];
+    C2<Tg>* o = out + kInterpStride * (size_t)slot;
     o[0] = {(Tg)g0r, (Tg)g0i};
     o[1] = {(Tg)dxr, (Tg)dxi};
     o[2] = {(Tg)dyr, (Tg)dyi};
+    o[3] = {Tg(0), Tg(0)};
   }
 }
 

@@ -796,7 +796,7 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
   bool tiled = kTiled;
   if (!kTiled && a.interp) tiled = !is_none(((const C2<Tg>*)a.rec_val)[slot]);
   if (tiled) {
-    const C2<Tg>* q = (const C2<Tg>*)a.interp + 3 * slot;
+    const C2<Tg>* q = (const C2<Tg>*)a.interp + kInterpStride * slot;
     const C2<Tg> q0 = q[0], q1 = q[1], q2 = q[2];
     g0 = {(double)q0.re, (double)q0.im};
     dx = {(double)q1.re, (double)q1.im};

@@ -246,7 +246,7 @@ struct DoeArgs {
   int acc_side;
   RayCtx* ctx;               // [n_total] frame and wavevectors at the DOE hit (alive rays)
   void* dlist;               // per block [N]: (bin, spectrum cogradient) of each draw
-  const void* interp;        // C2<Tg> [n_slots][3] sensor-grid cogradient at each record
+  const void* interp;        // C2<Tg> [n_slots][4] sensor-grid cogradient at each record (+ pad)
                              // (value, d/dx, d/dy), or null: interpolate in the kernel
   void* g2;                  // G2 per block: double [N][8] draw data, then [M*M] dL/dlog p
   unsigned char* ray_class;  // [n_total] patch class of every ray (0 for dead rays)
