@@ -862,14 +862,27 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
 
   int qn = 0;                                      // queued records (wave-uniform)
   int bin = 0;                                     // monotonic per lane across batches
-  for (unsigned long long base = 0; base < ntot; base += 64) {
-    const unsigned long long j = base + lane;
-    unsigned long long r = 0;
-    bool hit = false;
+  // the positions of the next 64 records are loaded before the current ones
+  // are tested and queued
+  unsigned long long rn = 0;
+  U pxn = 0, pyn = 0;
+  auto fetch = [&](unsigned long long j) {
     if (j < ntot) {
       while (j >= s_pre[wave][bin + 1]) ++bin;
-      r = s_beg[wave][bin] + (j - s_pre[wave][bin]);
-      const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+      rn = s_beg[wave][bin] + (j - s_pre[wave][bin]);
+      pxn = pos[2 * rn];
+      pyn = pos[2 * rn + 1];
+    }
+  };
+  fetch(lane);
+  for (unsigned long long base = 0; base < ntot; base += 64) {
+    const unsigned long long j = base + lane;
+    const unsigned long long r = rn;
+    const U px = pxn, py = pyn;
+    fetch(j + 64);
+    bool hit = false;
+    if (j < ntot) {
+      const double gx = turns_to_cells(px, g.nf), gy = turns_to_cells(py, g.nf);
       const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
       // footprint vs tile columns and vs this wave's strip rows (periodic)
       const int cx0 = (lx0 - x0) & (g.nf - 1);
