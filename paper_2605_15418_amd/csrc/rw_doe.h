@@ -1288,10 +1288,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         };
         if (inside) {
           // the window lies inside the accumulator: batches of KB pixels per
-          // lane, all accumulator (and map) loads issued before the stores
+          // lane; the accumulator and map loads of a batch are issued first,
+          // then its samples are read from LDS once for both the pixel value
+          // and the lens terms while those loads are in flight
           constexpr int KB = 9;
           for (int i0 = t; i0 < P1 * P1; i0 += kDoeThreads * KB) {
-            C2<Tf> v[KB];
             int li[KB], mi[KB];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
@@ -1299,10 +1300,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               li[k] = -1;
               mi[k] = -1;
               if (i < P1 * P1) {
-                int x, y;
-                v[k] = pix(i, x, y);
+                const int bb = dP1.div(i), aa = i - bb * P1;
+                const int x = pp.ix0 + aa, y = pp.iy0 + bb;
                 if (x >= 0 && x < W && y >= 0 && y < H) {
-                  li[k] = (ly0 + y - pp.iy0) * AS + lx0 + x - pp.ix0;
+                  li[k] = (ly0 + bb) * AS + lx0 + aa;
                   mi[k] = y * W + x;
                 }
               }
@@ -1314,16 +1315,27 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               if (li[k] >= 0) old[k] = accm[li[k]];
               tp[k] = (lens && mi[k] >= 0) ? tm[mi[k]] : C2<Tf>{Tf(0), Tf(0)};
             }
-            // every map value is consumed, on every path, before the stores:
-            // a load still pending behind them would make later code wait for
-            // the stores.  Slots without a pixel carry tp = 0 (their samples
-            // are finite LDS values).
-            if (lens) {
+            C2<Tf> v[KB];
 #pragma unroll
-              for (int k = 0; k < KB; ++k) lens_term(i0 + k * kDoeThreads, tp[k]);
+            for (int k = 0; k < KB; ++k) {
+              v[k] = {Tf(0), Tf(0)};
+              if (li[k] < 0) continue;
+              const int i = i0 + k * kDoeThreads;
+              const int bb = dP1.div(i), aa = i - bb * P1;
+              const C2<Tf> g00 = gu(bb, aa), g01 = gu(bb, aa - 1), g10 = gu(bb - 1, aa),
+                           g11 = gu(bb - 1, aa - 1);
+              v[k] = g00 * w00 + g01 * w01 + g10 * w10 + g11 * w11;
+              if (lens) {
+                const C2<Tf> gx = (g01 - g00) * (Tf(1) - pp.wy) + (g11 - g10) * pp.wy;
+                const C2<Tf> gy = (g10 - g00) * (Tf(1) - pp.wx) + (g11 - g01) * pp.wx;
+                gpx += (double)(gx.re * tp[k].re + gx.im * tp[k].im);
+                gpy += (double)(gy.re * tp[k].re + gy.im * tp[k].im);
+              }
             }
-            // and none is left in flight (vmcnt(0) alone: 0x0F70 keeps the
-            // export and LDS counters unconstrained)
+            // every load of the batch is consumed before the stores, and none
+            // is left in flight (vmcnt(0) alone: 0x0F70 keeps the export and
+            // LDS counters unconstrained): a load pending behind the stores
+            // would make later code wait for them
             __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
