@@ -379,27 +379,41 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
     line_fft2<Tf, M, -1, false>(buf, tw, P, P, M, false);      // rows n < P, inputs m < P
     for (int i = opaque_tid(); i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
     line_fft2<Tf, M, -1, true>(buf, tw, M, P, M, false);       // columns, inputs n < P
-    // sampling weights of the chunks of E consecutive rows of a column
-    for (int t = tid; kCdf && t < M * (M / E); t += kDoeThreads) {
-      const int col = t & (M - 1), ky0 = E * (t / M);
-      const int jx = col < M / 2 ? col : col - M;
-      const int jys0 = (ky0 + M / 2) & (M - 1);
-      const int ch = ((jx + M / 2) * M + jys0) / E;
-      const Span sp = span[jx + M / 2];
-      const int base = Gm::row(ky0) + Gm::col(col);
-      Tf sum = Tf(0);
-      int last = -1;                                  // last bin of positive weight
+    // sampling weights of the chunks of E consecutive rows of a column; a
+    // lane's two chunks are loaded together (M * M / E = 2 * kDoeThreads)
+    static_assert(M * (M / E) == 2 * kDoeThreads, "two chunks per lane");
+    if constexpr (kCdf) {
+      C2<Tf> xv[2][E];
 #pragma unroll
-      for (int k2 = 0; k2 < E; ++k2) {
-        const int ky = ky0 + k2;
-        const int jy = ky < M / 2 ? ky : ky - M;
-        Tf wgt = Tf(0);
-        if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(buf[base + k2 * SM], sampling);
-        sum += wgt;
-        if (wgt > Tf(0)) last = k2;
+      for (int j = 0; j < 2; ++j) {
+        const int t = tid + j * kDoeThreads;
+        const int col = t & (M - 1), ky0 = E * (t / M);
+        const int base = Gm::row(ky0) + Gm::col(col);
+#pragma unroll
+        for (int k2 = 0; k2 < E; ++k2) xv[j][k2] = buf[base + k2 * SM];
       }
-      chunk[ch] = (double)sum;
-      if (last >= 0) lp = max(lp, ch * E + last);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int t = tid + j * kDoeThreads;
+        const int col = t & (M - 1), ky0 = E * (t / M);
+        const int jx = col < M / 2 ? col : col - M;
+        const int jys0 = (ky0 + M / 2) & (M - 1);
+        const int ch = ((jx + M / 2) * M + jys0) / E;
+        const Span sp = span[jx + M / 2];
+        Tf sum = Tf(0);
+        int last = -1;                                  // last bin of positive weight
+#pragma unroll
+        for (int k2 = 0; k2 < E; ++k2) {
+          const int ky = ky0 + k2;
+          const int jy = ky < M / 2 ? ky : ky - M;
+          Tf wgt = Tf(0);
+          if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(xv[j][k2], sampling);
+          sum += wgt;
+          if (wgt > Tf(0)) last = k2;
+        }
+        chunk[ch] = (double)sum;
+        if (last >= 0) lp = max(lp, ch * E + last);
+      }
     }
   } else {
     const bool half = 2 * P == M;     // pad factor 2: the upper half of every input is zero
