@@ -746,7 +746,7 @@ constexpr int kSpreadQueue = 96;     // queue capacity: a batch plus one scan st
 // Static LDS of k_spread_tiles<Tg, w> besides the dynamic accumulator tile.
 __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
   return (size_t)kSpreadWaves * (kSpreadBatch * (2 * (size_t)w * sz_g + (2 * sz_g + 8 + 15) / 16 * 16) +
-                                 kSpreadQueue * 8 + (18 + 19) * 8) +
+                                 kSpreadQueue * 4 * sz_g + (18 + 19) * 8) +
          256;   // slack for the compiler's alignment of the arrays
 }
 
@@ -771,7 +771,9 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   // per queued record: value and first-tap offsets, read by the wave as one entry
   struct alignas(16) RecEnt { C2<Tg> v; int dx, dy; };
   __shared__ RecEnt s_r[NW][QB];
-  __shared__ unsigned long long s_q[NW][QN];
+  // queued record: its grid position and value (no global load when staged)
+  struct QEnt { U px, py; C2<Tg> v; };
+  __shared__ QEnt s_q[NW][QN];
   __shared__ unsigned long long s_beg[NW][18], s_pre[NW][19];
   const int tile = 4 * g.bin;                 // cells per tile side
   // row stride = w (mod 16): the w x w taps of one record (lane = i + w j)
@@ -810,8 +812,8 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
     const int q = lane & (QB - 1);                 // record of this lane
     const bool hi = lane >= QB;                    // low half: x factors, high half: y
     if (q < n) {
-      const unsigned long long r = s_q[wave][q];
-      const double gx = turns_to_cells(pos[2 * r], g.nf), gy = turns_to_cells(pos[2 * r + 1], g.nf);
+      const QEnt qe = s_q[wave][q];
+      const double gx = turns_to_cells(qe.px, g.nf), gy = turns_to_cells(qe.py, g.nf);
       const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
       const double f = hi ? gy - ly0 : gx - lx0;
       Tg* kf = hi ? &s_ky[wave][q][0] : &s_kx[wave][q][0];
@@ -819,7 +821,7 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
       for (int i = 0; i < w; ++i) kf[i] = es_kernel<Tg>((Tg)((double)i - f), two_w, bet);
       if (!hi) {
         RecEnt e;
-        e.v = val[r];
+        e.v = qe.v;
         // first tap relative to the tile origin, in [-w, nf - w): a tap lands in
         // the tile iff its offset is in [0, tile) (nf >= tile + w)
         e.dx = ((lx0 - x0 + w) & (g.nf - 1)) - w;
@@ -862,23 +864,24 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
 
   int qn = 0;                                      // queued records (wave-uniform)
   int bin = 0;                                     // monotonic per lane across batches
-  // the positions of the next 64 records are loaded before the current ones
-  // are tested and queued
-  unsigned long long rn = 0;
+  // the positions and values of the next 64 records are loaded before the
+  // current ones are tested and queued
   U pxn = 0, pyn = 0;
+  C2<Tg> vn{};
   auto fetch = [&](unsigned long long j) {
     if (j < ntot) {
       while (j >= s_pre[wave][bin + 1]) ++bin;
-      rn = s_beg[wave][bin] + (j - s_pre[wave][bin]);
-      pxn = pos[2 * rn];
-      pyn = pos[2 * rn + 1];
+      const unsigned long long r = s_beg[wave][bin] + (j - s_pre[wave][bin]);
+      pxn = pos[2 * r];
+      pyn = pos[2 * r + 1];
+      vn = val[r];
     }
   };
   fetch(lane);
   for (unsigned long long base = 0; base < ntot; base += 64) {
     const unsigned long long j = base + lane;
-    const unsigned long long r = rn;
     const U px = pxn, py = pyn;
+    const C2<Tg> v = vn;
     fetch(j + 64);
     bool hit = false;
     if (j < ntot) {
@@ -891,13 +894,14 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
     }
     const unsigned long long m = __ballot(hit);
     const int pre = __popcll(m & ((1ull << lane) - 1ull));
-    if (hit) s_q[wave][qn + pre] = r;          // qn < QB: at most QB + 63 < QN entries
+    if (hit) s_q[wave][qn + pre] = QEnt{px, py, v};   // qn < QB: at most QB + 63 < QN entries
     qn += __popcll(m);
     while (qn >= QB) {                         // wave-uniform
       process(QB);
       // move the overflow (< 64 entries) to the front of the queue
       const int rest = qn - QB;
-      const unsigned long long t = lane < rest ? s_q[wave][QB + lane] : 0ull;
+      QEnt t{};
+      if (lane < rest) t = s_q[wave][QB + lane];
       wave_lds_sync();
       if (lane < rest) s_q[wave][lane] = t;
       qn = rest;
