@@ -478,9 +478,48 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   __syncthreads();
 }
 
-// Exclusive scan of the chunk sums in place; returns the total S.
+// Wave-level prefix operations with DPP row shifts (lanes whose source lies
+// outside their 16-lane row keep `old`) and the three row totals by readlane.
+template <int CTRL> __device__ __forceinline__ int dpp_shr(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shr_d(double v) {   // 0 without source
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_shr<CTRL>(0, (int)(b & 0xffffffff));
+  const int hi = dpp_shr<CTRL>(0, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ double wave_incl_sum(double v, int lane) {
+  v += dpp_shr_d<0x111>(v);               // row_shr:1
+  v += dpp_shr_d<0x112>(v);               // row_shr:2
+  v += dpp_shr_d<0x114>(v);               // row_shr:4
+  v += dpp_shr_d<0x118>(v);               // row_shr:8
+  const double r0 = lane_d(v, 15), r1 = lane_d(v, 31), r2 = lane_d(v, 47);
+  const int row = lane >> 4;
+  return v + (row >= 1 ? r0 : 0.0) + (row >= 2 ? r1 : 0.0) + (row >= 3 ? r2 : 0.0);
+}
+// Maximum over the 64 lanes.
+__device__ __forceinline__ int wave_max_i(int v) {
+  v = max(v, dpp_shr<0x111>(v, v));
+  v = max(v, dpp_shr<0x112>(v, v));
+  v = max(v, dpp_shr<0x114>(v, v));
+  v = max(v, dpp_shr<0x118>(v, v));
+  return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+
+// Exclusive scan of the chunk sums in place, returning the total S, and the
+// block maximum of lp (last bin of positive weight) through the same barrier.
 template <int M>
-__device__ __forceinline__ double chunk_scan(double* pref, double* red) {
+__device__ __forceinline__ double chunk_scan(double* pref, double* red, int lp, int* redi,
+                                             int& lp_all) {
   using Gm = DoeGeom<M>;
   constexpr int K = (Gm::NCH + kDoeThreads - 1) / kDoeThreads;
   const int t = threadIdx.x;
@@ -493,19 +532,17 @@ __device__ __forceinline__ double chunk_scan(double* pref, double* red) {
   }
   // block exclusive scan of the per-thread totals (8 waves)
   const int lane = t & 63, wv = t >> 6;
-  double inc = tot;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double n = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += n;
-  }
-  if (lane == 63) red[wv] = inc;
+  const double inc = wave_incl_sum(tot, lane);
+  const int wmax = wave_max_i(lp);
+  if (lane == 63) { red[wv] = inc; redi[wv] = wmax; }
   __syncthreads();
   double base = 0.0, S = 0.0;
+  int m = redi[0];
 #pragma unroll
   for (int i = 0; i < kDoeThreads / 64; ++i) {
     if (i < wv) base += red[i];
     S += red[i];
+    m = max(m, redi[i]);
   }
   double run = base + inc - tot;
 #pragma unroll
@@ -515,19 +552,9 @@ __device__ __forceinline__ double chunk_scan(double* pref, double* red) {
     run += v[k];
   }
   if (t == 0) pref[Gm::NCH] = S;
+  lp_all = m;
   __syncthreads();
   return S;
-}
-
-__device__ __forceinline__ int block_max_i(int v, int* red) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  int m = red[0];
-  for (int i = 1; i < kDoeThreads / 64; ++i) m = max(m, red[i]);
-  __syncthreads();
-  return m;
 }
 
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
@@ -665,8 +692,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
         __syncthreads();
         continue;
       }
-      const double S = chunk_scan<M>(s.pref, s.red);
-      const int lastpos_all = block_max_i(lp, s.redi);
+      int lastpos_all;
+      const double S = chunk_scan<M>(s.pref, s.red, lp, s.redi, lastpos_all);
       const double scale = S * inv_m2 / N;               // S or |Pi| over M^2 N
       if (t == 0) a.ctx[gid].S = S;                      // for the backward
       for (int i = t; i < N; i += kDoeThreads) {
