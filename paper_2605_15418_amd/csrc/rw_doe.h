@@ -651,19 +651,42 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   const int N = cfg.N, t = threadIdx.x, emit = a.emit;
   const double inv_m2 = 1.0 / ((double)M * M);
   unsigned long long n_sec = 0, n_alive = 0;
-  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
-    for (int k = 0; k < itr.count(); ++k) {
-      const long long gid = itr.ray(it, k, pair0);
-      if (gid < 0 || a.ray_class[gid] != a.cls) continue;     // other patch class
+  // rays in work-list order; the class, alive flag and context word (thread
+  // t < kCtxWords) of the next ray are loaded while the current one runs
+  const int cnt = itr.count();
+  long long it_n = blockIdx.x;
+  int k_n = 0;
+  long long gid_n = -1;
+  int cls_n = -1;
+  double alive_n = 0.0;
+  uint32_t cw_n = 0;
+  auto fetch = [&]() {
+    gid_n = it_n < n_items ? itr.ray(it_n, k_n, pair0) : -1;
+    if (gid_n >= 0) {
+      cls_n = a.ray_class[gid_n];
+      alive_n = a.st[7 * a.n_total + gid_n];
+      if (t < kCtxWords) cw_n = reinterpret_cast<const uint32_t*>(a.ctx + gid_n)[t];
+    }
+  };
+  fetch();
+  while (it_n < n_items) {                     // uniform over the workgroup
+    {
+      const long long gid = gid_n;
+      const int cls = cls_n;
+      const double alive = alive_n;
+      const uint32_t cw = cw_n;
+      if (++k_n == cnt) { k_n = 0; it_n += gridDim.x; }
+      fetch();
+      if (gid < 0 || cls != a.cls) continue;   // past the grid edge or other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
-      if (a.st[7 * a.n_total + gid] == 0.0) {
+      if (alive == 0.0) {
         for (int i = t; i < emit; i += kDoeThreads) put_none<Tg>(a, slot0 + i);
         if (a.idx_out && cfg.sampling != 2)
           for (int i = t; i < N; i += kDoeThreads) a.idx_out[gid * N + i] = -1;
         continue;
       }
       n_alive += (t == 0);
-      load_ctx(a, (size_t)gid, s.ctx);
+      if (t < kCtxWords) reinterpret_cast<uint32_t*>(&s.ctx)[t] = cw;
       __syncthreads();
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
