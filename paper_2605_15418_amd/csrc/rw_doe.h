@@ -1086,10 +1086,30 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
     }
     __syncthreads();
     if (!have_anchor) continue;
-    for (int k = 0; k < itr.count(); ++k) {
-      const long long gid = itr.ray(it, k, pair0);
-      if (gid < 0 || a.st[7 * a.n_total + gid] == 0.0 || a.ray_class[gid] != a.cls) continue;
-      load_ctx(a, (size_t)gid, s.ctx);
+    // the alive flag, class and context word (thread t < kCtxWords) of the
+    // block's next ray are loaded while the current one runs
+    const int cnt = itr.count();
+    long long gid_n = itr.ray(it, 0, pair0);
+    double alive_n = 0.0;
+    int cls_n = -1;
+    uint32_t cw_n = 0;
+    auto fetch = [&]() {
+      if (gid_n >= 0) {
+        alive_n = a.st[7 * a.n_total + gid_n];
+        cls_n = a.ray_class[gid_n];
+        if (t < kCtxWords) cw_n = reinterpret_cast<const uint32_t*>(a.ctx + gid_n)[t];
+      }
+    };
+    fetch();
+    for (int k = 0; k < cnt; ++k) {
+      const long long gid = gid_n;
+      const double alive = alive_n;
+      const int cls = cls_n;
+      const uint32_t cw = cw_n;
+      gid_n = k + 1 < cnt ? itr.ray(it, k + 1, pair0) : -1;
+      fetch();
+      if (gid < 0 || alive == 0.0 || cls != a.cls) continue;
+      if (t < kCtxWords) reinterpret_cast<uint32_t*>(&s.ctx)[t] = cw;
       __syncthreads();
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
