@@ -2,11 +2,11 @@
 configuration bench.py times (batched MIXED, default launch shape): 27 pairs x
 256^2 rays, P = 64 (M = 128), N = 256 draws, Q = 512.
 
-The PSF and the gradients sum over every ray and are compared with the FP64
-form in bench.py; here the outputs the oracle can compute ray by ray are
-checked on a sample of rays of several pairs: the ray state at the DOE, and
-the drawn bins (own draws: the MIXED form's FP32 spectrum may move a CDF edge,
-so >= 97% equal; the FP64 form: equal).
+The outputs the oracle can compute ray by ray are checked on a sample of
+rays of several pairs: the ray state at the DOE, and the drawn bins (own
+draws: the MIXED form's FP32 spectrum may move a CDF edge, so >= 97% equal;
+the FP64 form: equal).  The PSF and the gradients, which sum over every ray,
+are compared with the FP64 form on its replayed draws.
 """
 import numpy as np
 import pytest
@@ -86,3 +86,28 @@ def test_full_size_sampled_rays(rw, full, precision):
         equal += int((gi == J).sum())
         total += J.size
     assert equal / total >= 0.97, equal / total
+
+
+def test_full_size_mixed_against_fp64_form(rw, full):
+    """The whole PSF and every gradient at full size: MIXED against the FP64
+    form on the FP64 form's own draws replayed (the form is checked against the
+    oracle on smaller cases).  Bars: PSF 1e-4 relative L2 per pair, gradients
+    1e-3 per group (dphi, dA, dlens)."""
+    system, cfg, maps = full
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    p64 = rw.Plan(system, cfg, precision="fp64", batched=True)
+    psf64, _, idx = p64.forward(vals, ph, am, target=tg, want_idx=True)
+    g64 = [g.double() for g in p64.backward()]
+    psf64 = psf64.double()
+    del p64
+    plan = rw.Plan(system, cfg, precision="mixed", batched=True)
+    psf, loss, _ = plan.forward(vals, ph, am, target=tg, replay=idx)
+    g = [x.double() for x in plan.backward()]
+    torch.cuda.synchronize()
+    assert np.isfinite(float(loss))
+    d = ((psf.double() - psf64).flatten(2).norm(dim=2) / psf64.flatten(2).norm(dim=2)).max()
+    assert float(d) < 1e-4, float(d)
+    for name, a, b in zip(("phase", "amp", "lens"), g, g64):
+        e = float((a - b).norm() / b.norm())
+        assert e < 1e-3, (name, e)
