@@ -957,7 +957,7 @@ constexpr int kG2Rec = 8;
 template <class Prec, int M>
 __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
                             const C2<typename Prec::Tf>* buf, const Span* span, double S,
-                            float* gd, float* dlg, double* red) {
+                            float* gd, float* dlg, double* red, float* lrec) {
   using Tf = typename Prec::Tf;
   const DevCfg& cfg = *a.cfg;
   const int N = cfg.N, P = c.P;
@@ -1013,6 +1013,14 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
     }
   }
   __syncthreads();
+  // pass 2 reads the draw records from LDS when a buffer is given (every lane
+  // reads the same record at a time: broadcasts)
+  const float* rec = gd;
+  if (lrec) {
+    for (int i = t; i < N * kG2Rec; i += kDoeThreads) lrec[i] = gd[i];
+    __syncthreads();
+    rec = lrec;
+  }
   double Dsum = 0.0;
   const int kx = t % M;
   for (int ky = t / M; ky < M; ky += kDoeThreads / M) {
@@ -1028,7 +1036,7 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
         for (int q = 0; q < 4; ++q) {
           const int i = 4 * gi + q;
           if (i >= N) break;
-          const float* e = gd + (size_t)i * kG2Rec;
+          const float* e = rec + (size_t)i * kG2Rec;
           const int J = __float_as_int(e[4]);
           if (J < 0) continue;
           const float y = (k == J ? 1.0f : g2_weight(b.P, u[q], e[5], itau, unit)) * e[6];
@@ -1211,7 +1219,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           if (cfg.sampling == 0 && S > 0.0) {
             float* gd = (float*)a.g2 + (size_t)blockIdx.x * (N * kG2Rec + M * M);
             float* dg = gd + (size_t)N * kG2Rec;
-            D2 = g2_passes<Prec, M>(a, c, buf, s.span, S, gd, dg, s.red);
+            // the CDF prefix buffer is free in the adjoint (it takes the recorded draws)
+            float* lrec = N * kG2Rec * sizeof(float) <= sizeof(s.pref) ? (float*)s.pref : nullptr;
+            D2 = g2_passes<Prec, M>(a, c, buf, s.span, S, gd, dg, s.red, lrec);
             dlg = dg;
           }
         }
