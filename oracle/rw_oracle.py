@@ -530,9 +530,7 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     w = torch.cat([part["w"] for _, part in parts])
     Kus = torch.cat([part["Kus"] for _, part in parts])
     Kvs = torch.cat([part["Kvs"] for _, part in parts])
-    kz2 = k_out * k_out - Kus * Kus - Kvs * Kvs
-    kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
-    ds = (Kus[:, None] * u[rr] + Kvs[:, None] * v[rr] + kz[:, None] * nrm[rr]) / k_out
+    ds = emit_direction(Kus, Kvs, u[rr], v[rr], nrm[rr], k_out)
     a_s = amp_in[rr] * w
     ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z)
     a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
@@ -550,6 +548,16 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
                    phi0=phi0.detach(), wx=wx.detach(), wy=wy.detach(), w=w.detach(),
                    frame=(u.detach(), v.detach(), nrm.detach()))
     return out
+
+
+def emit_direction(Ku, Kv, u, v, nrm, k_out):
+    """Unit direction of the plane wave with tangential wavevector (Ku, Kv) in
+    the frame (u, v, n) leaving the DOE into the medium of wavenumber k_out
+    (Formalism, second paragraph): (Ku u + Kv v + sqrt(k_out^2 - |K|^2) n) / k_out,
+    the forward-going (+n) root."""
+    kz2 = k_out * k_out - Ku * Ku - Kv * Kv
+    kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
+    return (Ku[:, None] * u + Kv[:, None] * v + kz[:, None] * nrm) / k_out
 
 
 def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, nrm, k_in_t,
@@ -638,12 +646,11 @@ def conditional_gumbels(logp, J, u_top, u_bin):
     return phi
 
 
-def _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w_hard, Kus, Kvs, rr, valid,
-                      sampling, M, Nd):
-    R = Utf.shape[0]
-    tau = float(cfg.get("tau", 1.0))
-    Kuf = Ku.transpose(1, 2).reshape(R, M * M)
-    Kvf = Kv.transpose(1, 2).reshape(R, M * M)
+def relaxed_weights(Utf, propf, sampling, M, Nd):
+    """Per bin k of every ray: log p_k, and the Eq. 1 weight w_k = U~_k / (M^2 N p_k)
+    that draw i would carry had it landed on k (the quantities the softmax
+    relaxation mixes); -inf / 0 on bins that cannot be drawn.  Returns
+    (logp, w_all, live), each [R, M*M]."""
     absU = Utf.abs()
     live = propf & (absU > 0) if sampling == "mag" else propf
     if sampling == "mag":
@@ -658,7 +665,17 @@ def _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w_hard, Kus, Kv
         w_all = Utf * (nprop[:, None] / (M * M * Nd))
     w_all = torch.where(live, w_all, torch.zeros_like(w_all))
     neg_inf = torch.full((), -math.inf, dtype=DT)
-    logp = torch.where(live, logp, neg_inf)                          # [R, K]
+    logp = torch.where(live, logp, neg_inf)
+    return logp, w_all, live
+
+
+def _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w_hard, Kus, Kvs, rr, valid,
+                      sampling, M, Nd):
+    R = Utf.shape[0]
+    tau = float(cfg.get("tau", 1.0))
+    Kuf = Ku.transpose(1, 2).reshape(R, M * M)
+    Kvf = Kv.transpose(1, 2).reshape(R, M * M)
+    logp, w_all, live = relaxed_weights(Utf, propf, sampling, M, Nd)
     # Gumbel perturbations conditioned on argmax = J (numbers: no gradient)
     ut = g2_top_uniforms(cfg["seed"], pair, ray_ids, Nd)                 # [R, N]
     ub = g2_bin_uniforms(cfg["seed"], pair, ray_ids, Nd, M * M)          # [R, N, K]
