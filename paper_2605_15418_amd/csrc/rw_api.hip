@@ -61,9 +61,9 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 
 // Arguments a captured launch sequence was recorded with.
 struct GraphKey {
-  const void* p[9];
+  const void* p[10];
   bool operator==(const GraphKey& o) const {
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 10; ++i)
       if (p[i] != o.p[i]) return false;
     return true;
   }
@@ -1002,7 +1002,7 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   rw_status r;
   if (pl->graph) {
     const GraphKey key = {{(const void*)lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
-                           ws, replay_idx, idx_out}};
+                           ws, replay_idx, idx_out, nullptr}};
     r = graph_run(pl, pl->gfwd, key, st, [&](hipStream_t cs) {
       return fwd_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
                          replay_idx, idx_out, cs);
@@ -1147,8 +1147,10 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
                 "lens-parameter gradients need a planar DOE followed directly by the sensor");
   hipStream_t st = (hipStream_t)stream;
   if (pl->graph) {
+    // every pointer the recorded kernels read: the forward's PSF feeds the Eq. 5
+    // cogradient when dL_dpsf is NULL
     const GraphKey key = {{(const void*)dL_dpsf, d_phase, d_amp, d_lens, ws, pl->fwd_replay,
-                           pl->fwd_target, pl->fwd_phase, pl->fwd_amp}};
+                           pl->fwd_target, pl->fwd_phase, pl->fwd_amp, pl->fwd_psf}};
     return graph_run(pl, pl->gbwd, key, st, [&](hipStream_t cs) {
       return bwd_enqueue(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, want_lens, cs);
     });

@@ -219,6 +219,7 @@ class Plan:
         self.n_rays = self.L * self.F * cfg["rays_side"] ** 2
         self.N = cfg["n_ssr"]
         self.M = cfg["patch_p"] * cfg["pad"]
+        self.generation = 0        # forwards run on this plan (HybridPSF checks it)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -244,6 +245,7 @@ class Plan:
             idx = torch.empty((self.L * self.F, self.cfg["rays_side"] ** 2, self.N),
                               dtype=torch.int32, device=dev)
         self._fwd_keep = (lens_params, phase, amp, target, replay)
+        self.generation += 1
         st = self.lib.rw_forward(self.handle, _dptr(lens_params), _dptr(phase), _dptr(amp),
                                  _dptr(target), _dptr(psf), _dptr(loss), _dptr(self.ws),
                                  self.ws_bytes, _dptr(replay), _dptr(idx), self._stream())
@@ -300,15 +302,23 @@ class Plan:
 
 
 class HybridPSF(torch.autograd.Function):
-    """torch.autograd.Function over rw_forward / rw_backward (adjoint G1)."""
+    """torch.autograd.Function over rw_forward / rw_backward (the plan's gradient mode).
+
+    The backward reads the state the forward left in the plan's workspace, so a
+    plan serves one pending backward at a time: if another forward ran on the
+    same plan in between, the backward raises (RW_ERR_STATE) instead of
+    returning the gradient of the later forward."""
 
     @staticmethod
     def forward(ctx, plan, lens_params, phase, amp):
         psf, _, _ = plan.forward(lens_params, phase, amp)
         ctx.plan = plan
+        ctx.generation = plan.generation
         return psf
 
     @staticmethod
     def backward(ctx, g):
+        if ctx.plan.generation != ctx.generation:
+            raise RWError(3, "the plan ran another forward after the one being differentiated")
         dp, da, dl = ctx.plan.backward(g.contiguous())
         return None, dl, dp, da

@@ -50,3 +50,31 @@ def gpu_inputs(system, maps, device="cuda"):
 def oracle_param_values(system):
     """The lens parameters as the GPU sees them (rounded to float32)."""
     return O.initial_param_values(system).astype(np.float32).astype(np.float64)
+
+
+def elementwise_rel(a, b):
+    """max |a - b| / max |b|: the worst element against the scale of the reference."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def check_draws_valid(gi, J, spectrum, prop, u, sampling="mag", tol=1e-5):
+    """Own draws of a form whose spectrum carries rounding: every index that
+    differs from the oracle's must be a CDF edge flip, i.e. the oracle's
+    threshold u S lies within tol S of the edge between the two bins (the
+    oracle's inclusive CDF at the lower bin), and every bin strictly between
+    them has zero weight.  gi, J, u: [rays, N]; spectrum, prop: [rays, M, M]
+    in the oracle's (j_y, j_x) shifted layout.  Returns the agreeing fraction."""
+    R = J.shape[0]
+    mag = spectrum.abs().transpose(1, 2).reshape(R, -1).numpy()
+    pr = prop.transpose(1, 2).reshape(R, -1).numpy()
+    w = np.where(pr, mag if sampling == "mag" else 1.0, 0.0)
+    cdf = np.cumsum(w, axis=1)
+    for r, i in zip(*np.nonzero(gi != J)):
+        lo, hi = sorted((int(gi[r, i]), int(J[r, i])))
+        assert lo >= 0, (r, i, lo, hi)
+        assert np.all(w[r, lo + 1:hi] == 0), (r, i, lo, hi)
+        S = cdf[r, -1]
+        assert abs(u[r, i] * S - cdf[r, lo]) <= tol * S, (r, i, u[r, i] * S, cdf[r, lo], S)
+    return float((gi == J).mean())

@@ -12,9 +12,10 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import philox
 from oracle import rw_oracle as O
-from rwcases import (gpu_inputs, oracle_param_values, oracle_psf, rel_l2, small_hologram,
-                     small_singlet, worst_pair_rel)
+from rwcases import (check_draws_valid, gpu_inputs, oracle_param_values, oracle_psf, rel_l2,
+                     small_hologram, small_singlet, worst_pair_rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -106,25 +107,11 @@ def test_mixed_mc_own_draws_agree_and_are_valid(rw):
     plan, psf, idx = _run(rw, system, cfg, maps, "mixed", want_idx=True)
     ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
     gi = idx.cpu().numpy()
-    agree, total = 0, 0
+    agree = []
     for pr, a in aux.items():
-        J = a["J"]
-        agree += int((gi[pr] == J).sum())
-        total += J.size
-        # every disagreement must be a CDF edge flip: both bins adjacent in the
-        # oracle's CDF order once zero-weight bins are skipped
-        mag = a["spectrum"].abs().transpose(1, 2).reshape(J.shape[0], -1).numpy()
-        prop = a["prop"].transpose(1, 2).reshape(J.shape[0], -1).numpy()
-        w = np.where(prop, mag, 0.0)
-        cdf = np.cumsum(w, axis=1)
-        for r, i in zip(*np.nonzero(gi[pr] != J)):
-            lo, hi = sorted((int(gi[pr][r, i]), int(J[r, i])))
-            assert lo >= 0
-            between = w[r, lo + 1:hi]
-            assert np.all(between == 0) or hi - lo == 1, (pr, r, i, lo, hi)
-            # the edge sits within the FP32 spectrum error of the draw
-            assert abs(cdf[r, lo] / cdf[r, -1]) > 0
-    assert agree / total >= 0.97, agree / total
+        u = philox.draw_uniforms(cfg["seed"], pr, np.arange(a["J"].shape[0]), cfg["n_ssr"])
+        agree.append(check_draws_valid(gi[pr], a["J"], a["spectrum"], a["prop"], u))
+    assert np.mean(agree) >= 0.97, agree
 
 
 def test_batched_equals_per_pair_launches(rw):
@@ -204,6 +191,67 @@ def test_graph_replays_match_eager(rw):
     psf2, _, _ = plan.forward(vals, ph2, am, target=tg)
     torch.cuda.synchronize()
     assert rel_l2(psf2.cpu().numpy(), psf0.cpu().numpy()) < 1e-5
+
+
+def test_graph_backward_follows_the_psf_buffer_of_each_forward(rw):
+    """A training loop with graphs on, fixed gradient buffers and a fresh PSF
+    tensor per step (two buffers in turn): the backward of the Eq. 5 loss reads
+    the PSF of the forward it follows, so its replay must match eager every step."""
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    eager = rw.Plan(system, cfg, precision="mixed")
+    plan = rw.Plan(system, cfg, precision="mixed")
+    plan.set_graph(True)
+    psf_bufs = [torch.empty((plan.L, plan.F, plan.Q, plan.Q), device="cuda") for _ in range(2)]
+    loss = torch.empty(1, device="cuda")
+    dp = torch.empty_like(ph)
+    da = torch.empty_like(am)
+    dl = torch.empty_like(vals)
+    for step in range(4):
+        v = vals * (1.0 + 1e-3 * step)                   # the parameters move every step
+        vk = torch.empty_like(vals)
+        vk.copy_(v)
+        eager.forward(vk, ph, am, target=tg)
+        g0 = eager.backward()
+        psf_bufs[step % 2].fill_(float("nan"))           # stale contents must never be read
+        plan.forward(vk, ph, am, target=tg, psf_out=psf_bufs[step % 2], loss_out=loss)
+        plan.backward(d_phase=dp, d_amp=da, d_lens=dl)
+        torch.cuda.synchronize()
+        for a, b in zip((dp, da, dl), g0):
+            assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) < 1e-5, step
+
+
+def test_hybrid_psf_autograd_matches_oracle_and_guards_the_workspace(rw):
+    """torch.autograd through HybridPSF: the gradient of a scalar loss of the PSF
+    against the oracle's; a backward whose forward was followed by another
+    forward on the same plan raises instead of differentiating the later one."""
+    system, cfg, maps = small_hologram(sampling="full", rays=6, n_lambda=1, n_field_side=1)
+    Q = cfg["psf_q"]
+    Wt = np.random.default_rng(4).uniform(size=(1, 1, Q, Q))
+    vals = oracle_param_values(system)
+    ph64 = torch.tensor(maps["phase"].astype(np.float64), requires_grad=True)
+    am64 = torch.tensor(maps["amp"].astype(np.float64), requires_grad=True)
+    v64 = torch.tensor(vals, requires_grad=True)
+    r = O.pair_forward(system, cfg, O.transmission(ph64, am64), 0, 0, v64)
+    (r["psf"] * torch.tensor(Wt[0, 0])).sum().backward()
+    plan = rw.Plan(system, cfg, precision="mixed")
+    gv, gph, gam = gpu_inputs(system, maps)
+    gv.requires_grad_(True)
+    gph.requires_grad_(True)
+    gam.requires_grad_(True)
+    psf = rw.HybridPSF.apply(plan, gv, gph, gam)
+    (psf * torch.tensor(Wt, dtype=torch.float32, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    assert rel_l2(gph.grad.cpu().numpy(), ph64.grad.numpy()) < 1e-3
+    assert rel_l2(gam.grad.cpu().numpy(), am64.grad.numpy()) < 1e-3
+    assert rel_l2(gv.grad.cpu().numpy(), v64.grad.numpy()) < 1e-3
+    psf1 = rw.HybridPSF.apply(plan, gv, gph, gam)
+    psf2 = rw.HybridPSF.apply(plan, gv, gph, gam)          # overwrites the workspace
+    with pytest.raises(RuntimeError, match="RW_ERR_STATE"):
+        psf1.sum().backward()
+    psf2.sum().backward()                                   # the latest forward is fine
+    torch.cuda.synchronize()
 
 
 def test_autotune_keeps_results(rw):
