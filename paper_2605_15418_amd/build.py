@@ -18,15 +18,30 @@ def _run(cmd):
     return r.returncode, r.stdout + r.stderr
 
 
-def build(verbose=False, jobs=None):
+def _stale(obj, unit):
+    """An object is stale if it is missing or older than its unit or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    srcs = [os.path.join(CSRC, unit)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC)
+                                         if h.endswith(".h")]
+    srcs.append(os.path.join(os.path.dirname(HERE), "include", "rw.h"))
+    return any(os.path.getmtime(x) > t for x in srcs)
+
+
+def build(verbose=False, jobs=None, incremental=False):
+    """Compile every unit (incremental=True: only units older than their sources)
+    and link librw.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs, cmds = [], []
     for u in UNITS:
         o = os.path.join(BUILD_DIR, u.replace(".hip", ".o"))
         objs.append(o)
+        if incremental and not _stale(o, u):
+            continue
         cmds.append([hipcc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, u)])
-    jobs = jobs or min(len(cmds), max(1, (os.cpu_count() or 1)))
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_run, cmds))
     for (rc, out), cmd in zip(results, cmds):
@@ -45,4 +60,4 @@ def build(verbose=False, jobs=None):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -253,10 +253,144 @@ def conformal_hologram(rays_side=8, H=256, pitch=0.002, P=32, classes=(16,), N=3
     return system, cfg, maps
 
 
+def paraxial_pupil(surfs, z_stop, lam):
+    """Paraxial entrance pupil of a stop at z_stop behind the given surfaces
+    (first-order ray transfer, nu' = nu - y c (n' - n)): returns (z_ep, m), the
+    pupil position and the ratio of stop height to pupil height.  Used only to
+    aim the launch grids."""
+    def trace(y, u, z):
+        n = 1.0
+        for sf in surfs:
+            if sf["z"] >= z_stop:
+                break
+            y += u * (sf["z"] - z)
+            z = sf["z"]
+            na = sf["nA"] + sf["nB"] / (lam * 1e3) ** 2
+            u = (n * u - y * sf["c"] * (na - n)) / na
+            n = na
+        return y + u * (z_stop - z)
+    z0 = surfs[0]["z"] - 1.0
+    m = trace(1.0, 0.0, z0)                     # a collimated ray's height at the stop
+    y_a = trace(0.0, 1e-3, z0)                  # a ray crossing the axis at z0 ...
+    y_b = trace(-1e-3, 1e-3, z0)                # ... and one crossing it at z0 + 1
+    z_ep = z0 + y_a / (y_a - y_b)               # the axis point whose ray meets the stop centre
+    return z_ep, m
+
+
+# ----------------------------------------------------------------------------
+# Workload 4: conformal DOE on the convex R = 30 front of a BK7 plano-convex
+# (CT 4, planar rear face after the DOE), 2048 x 2048 random phase at 0.5 um
+# on the xy projection (band-limited to 0.4 cycles/pixel, A = 1), 31
+# wavelengths 400-700 nm x 25 fields (5 x 5 up to +-20 deg), 128 x 128 rays per
+# field, N = 256, 256 x 256 PSF at 1 um at the 587.6 nm back focus.  Patch
+# classes 128 / 64 / 32 by the curvature bound (Eq. 4): the front is the
+# R = 30 sphere plus an A4 term that lowers the local radius across the DOE,
+# so that the bound splits the rays into three concentric zones.
+# ----------------------------------------------------------------------------
+def conformal_sphere(rays_side=128, H=2048, pitch=0.0005, P=128, classes=(64, 32), N=256,
+                     Q=256, psf_pitch=0.001, n_lambda=31, n_field_side=5, max_deg=20.0,
+                     sampling="mag", curv_eps=0.0082, A4=0.2, seed=0, cfg_id=4):
+    R, ct = 30.0, 4.0
+    surfs = [surface(0.0, c=1 / R, A=(A4, 0.0, 0.0, 0.0), semi_ap=6.0, medium=BK7, doe=True),
+             surface(ct, medium=AIR)]
+    surfs[0]["kind"] = "asphere"
+    n_d = BK7[0] + BK7[1] / (LAM_D * 1e3) ** 2
+    bfl = R / (n_d - 1) - ct / n_d
+    system = {"surfaces": surfs, "sensor_z": ct + bfl, "doe": doe_desc(H, H, pitch),
+              "params": []}
+    lambdas = list(np.linspace(400e-6, 700e-6, n_lambda)) if n_lambda > 1 else [LAM_D]
+    fields = field_grid(max_deg, n_field_side)
+    half = 0.5 * H * pitch * (1 - 1.0 / rays_side)
+    cfg = _cfg(lambdas, fields, 0.0, -1.0, half, rays_side, Q, psf_pitch, 0.0, P, N, sampling,
+               seed=seed)
+    # sensor window on each chief ray (paraxial: through the DOE centre, n_d inside the lens)
+    cfg["psf_center"] = [[[tx * (ct / n_d + bfl), ty * (ct / n_d + bfl)] for tx, ty in fields]
+                         for _ in lambdas]
+    cfg["patch_classes"] = [int(q) for q in classes]
+    cfg["curv_eps"] = float(curv_eps)
+    rng = np.random.default_rng(20260000 + cfg_id)
+    phase = 2 * math.pi * bandlimited_uniform(H, H, 0.4, rng)
+    maps = {"phase": phase.astype(np.float32), "amp": np.ones((H, H), dtype=np.float32),
+            "target": None}
+    return system, cfg, maps
+
+
+# ----------------------------------------------------------------------------
+# Workload 5: end-to-end hybrid design.  L1 (BK7, R +40 / -60, CT 5) and L2
+# (F2, R +30 / -200, CT 3), semi-apertures 7.5, even-asphere terms A4, A6 on
+# every surface (seeded, small, plus a fixed A4 on the DOE surface so that its
+# local radius varies), a 4096 x 4096 complex DOE at 0.5 um on L2's rear
+# surface (F2 -> air), the stop.  8 wavelengths 400-700 nm x 16 fields (4 x 4
+# up to +-25 deg), 512 x 512 rays per field, patch classes 128 / 64 by Eq. 4,
+# N = 256, 1024 x 1024 PSF at 1 um at the paraxial focus, Airy targets;
+# 14 lens parameters: 4 curvatures, 4 A4, 4 A6, 2 centre thicknesses.
+# ----------------------------------------------------------------------------
+def two_lens_hybrid(rays_side=512, H=4096, pitch=0.0005, P=128, classes=(64,), N=256, Q=1024,
+                    psf_pitch=0.001, n_lambda=8, n_field_side=4, max_deg=25.0, sampling="mag",
+                    curv_eps=2.5e-4, A4_doe=2e-3, seed=0, with_target=True, cfg_id=5):
+    rng_a = np.random.default_rng(20260100 + cfg_id)
+    Rs = (40.0, -60.0, 30.0, -200.0)
+    zs = (0.0, 5.0, 7.0, 10.0)
+    meds = (BK7, AIR, F2, AIR)
+    A = rng_a.normal(0.0, 1e-6, (4, 2))
+    A[3, 0] += A4_doe
+    surfs = [surface(zs[i], c=1 / Rs[i], A=(A[i, 0], A[i, 1], 0.0, 0.0), semi_ap=7.5,
+                     medium=meds[i], doe=(i == 3)) for i in range(4)]
+    for sf in surfs:
+        sf["kind"] = "asphere"
+    # paraxial focus of the d line behind the DOE surface
+    y, u, n, z = 1.0, 0.0, 1.0, zs[0]
+    for sf in surfs:
+        y += u * (sf["z"] - z)
+        z = sf["z"]
+        na = sf["nA"] + sf["nB"] / (LAM_D * 1e3) ** 2
+        u = (n * u - y * sf["c"] * (na - n)) / na
+        n = na
+    dz = -y / u
+    r_fp = 0.5 * H * pitch
+    system = {"surfaces": surfs, "sensor_z": zs[3] + dz, "doe": doe_desc(H, H, pitch),
+              "params": []}
+    for s_i in range(4):
+        system["params"].append({"surface": s_i, "field": "curv", "scale": 1 / abs(Rs[s_i])})
+    for s_i in range(4):
+        system["params"].append({"surface": s_i, "field": "A4", "scale": LAM_D / r_fp ** 4})
+    for s_i in range(4):
+        system["params"].append({"surface": s_i, "field": "A6", "scale": LAM_D / r_fp ** 6})
+    system["params"].append({"surface": 0, "field": "gap", "scale": 1.0})
+    system["params"].append({"surface": 2, "field": "gap", "scale": 1.0})
+    lambdas = list(np.linspace(400e-6, 700e-6, n_lambda)) if n_lambda > 1 else [LAM_D]
+    fields = field_grid(max_deg, n_field_side)
+    z_ep, m = paraxial_pupil(surfs, zs[3], LAM_D)
+    half = 0.5 * H * pitch * (1 - 1.0 / rays_side) / abs(m)
+    cfg = _cfg(lambdas, fields, z_ep, -1.0, half, rays_side, Q, psf_pitch, dz, P, N, sampling,
+               seed=seed)
+    cfg["patch_classes"] = [int(q) for q in classes]
+    cfg["curv_eps"] = float(curv_eps)
+    rng = np.random.default_rng(20260000 + cfg_id)
+    phase = 2 * math.pi * bandlimited_uniform(H, H, 0.25, rng)
+    amp = 0.5 + 0.5 * bandlimited_uniform(H, H, 0.25, rng)
+    target = None
+    if with_target:
+        rng_t = np.random.default_rng(20260200 + cfg_id)
+        NA = r_fp / dz
+        L, F = len(lambdas), len(fields)
+        target = np.zeros((L, F, Q, Q), dtype=np.float32)
+        for l in range(L):
+            for f in range(F):
+                target[l, f] = airy_target(Q, psf_pitch, lambdas[l], NA, (0.0, 0.0),
+                                           rng_t.uniform(-8, 8, 2))
+    maps = {"phase": phase.astype(np.float32), "amp": amp.astype(np.float32), "target": target}
+    return system, cfg, maps
+
+
 def workload(name):
     """Named full-size workloads."""
     if name == "singlet_zoneplate":
         return singlet_zoneplate()
     if name == "asphere_hologram":
         return asphere_hologram()
+    if name == "conformal_sphere":
+        return conformal_sphere()
+    if name == "two_lens_hybrid":
+        return two_lens_hybrid()
     raise KeyError(name)
