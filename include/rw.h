@@ -157,9 +157,15 @@ rw_status rw_plan_create(const rw_surface* surfaces_host, int n_surf, const rw_d
                          const rw_param_ref* params_host, int n_params, const rw_config* cfg_host,
                          rw_plan** out_plan);
 
-/* Bytes of device workspace the caller must provide to rw_forward / rw_backward
- * (256-byte aligned).  The same workspace must be passed to the backward. */
-rw_status rw_plan_workspace_bytes(const rw_plan* plan, size_t* bytes);
+/* Device workspace sizes (256-byte aligned buffers):
+ *  *fwd_bytes        the workspace of a forward pass that is not followed by a backward;
+ *  *bwd_extra_bytes  (may be NULL) what a forward must have on top of fwd_bytes to leave
+ *                    the state of rw_backward (the drawn bins, the records' slots) and
+ *                    what the backward itself uses.
+ * rw_forward with fwd_bytes <= workspace_bytes < fwd_bytes + bwd_extra_bytes runs
+ * forward-only: rw_backward then returns RW_ERR_STATE.  The same workspace must be
+ * passed to the backward. */
+rw_status rw_plan_workspace_bytes(const rw_plan* plan, size_t* fwd_bytes, size_t* bwd_extra_bytes);
 
 /* Forward pass.
  *  lens_params [n_params] float  normalised lens parameters (may be NULL if n_params = 0)
@@ -170,12 +176,13 @@ rw_status rw_plan_workspace_bytes(const rw_plan* plan, size_t* bytes);
  *  psf_out [L][F][Q][Q] float (written)
  *  replay_idx: NULL, or sample indices (layout above) used instead of the Philox draws
  *  idx_out: NULL, or receives the sample indices that were used
- * Errors: RW_ERR_INVALID_ARG (null required pointer), RW_ERR_STATE (workspace too small),
- *         RW_ERR_HIP. */
+ * Errors: RW_ERR_INVALID_ARG (null required pointer), RW_ERR_STATE (workspace smaller than
+ *         fwd_bytes), RW_ERR_HIP. */
 rw_status rw_forward(rw_plan* plan, const float* lens_params, const float* doe_phase,
                      const float* doe_amp, const float* target, float* psf_out, float* loss_out,
                      void* workspace, size_t workspace_bytes, const int32_t* replay_idx,
                      int32_t* idx_out, void* stream);
+
 
 /* Backward pass (adjoint G1: the a.e. derivative with the sample indices of the
  * preceding forward held fixed).

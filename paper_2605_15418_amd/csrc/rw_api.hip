@@ -127,9 +127,12 @@ struct rw_plan {
       off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
       off_interp, off_g2, off_rcls, total;
+  size_t fwd_bytes;        // workspace of a forward-only pass (a prefix of the layout)
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
   bool fwd_done = false;
+  bool fwd_full = false;    // the last forward left the backward's state (draws, slots)
+  bool fwd_only = false;    // the forward being enqueued writes no backward state
   const float* fwd_target = nullptr;
   const int32_t* fwd_replay = nullptr;
   const float* fwd_phase = nullptr;
@@ -270,7 +273,8 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.ctx = (RayCtx*)(b + pl->off_ctx);
   a.dlist = b + pl->off_dlist;
   a.ray_class = (unsigned char*)(b + pl->off_rcls);
-  a.jdraw = pl->cfg.sampling == RW_SAMPLE_FULL ? nullptr : (int32_t*)(b + pl->off_jdraw);
+  a.jdraw = pl->cfg.sampling == RW_SAMPLE_FULL || pl->fwd_only ? nullptr
+                                                                 : (int32_t*)(b + pl->off_jdraw);
   a.full = pl->cfg.sampling == RW_SAMPLE_FULL;
   a.cls = 0;
   return a;
@@ -380,7 +384,8 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   unsigned int* work = (unsigned int*)(b + pl->off_work);
   hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(1024), 0, st, (const unsigned int*)cnt,
                      (size_t)npairs * g.keys, fpc, C, offs, cur, scur, work);
-  unsigned int* tidx = pl->tiled_interp ? (unsigned int*)(b + pl->off_tidx) : nullptr;
+  const bool slots = pl->tiled_interp && !pl->fwd_only;   // record slots for the backward
+  unsigned int* tidx = slots ? (unsigned int*)(b + pl->off_tidx) : nullptr;
   const unsigned long long* offs_all = (const unsigned long long*)(b + pl->off_offs);
   hipLaunchKernelGGL((k_rec_place<Tg, true>), dim3((unsigned)((per_pair + C - 1) / C), npairs),
                      dim3(256), 0, st, (const void*)(b + pl->off_rpos),
@@ -396,7 +401,7 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
                      (const unsigned int*)tidx, nitems, offs_all, (const unsigned int*)work, g,
                      pair0, (unsigned long long*)(b + pl->off_cur), (void*)(b + pl->off_spos),
                      (void*)(b + pl->off_sval),
-                     pl->tiled_interp ? (unsigned int*)(b + pl->off_sidx) : nullptr);
+                     slots ? (unsigned int*)(b + pl->off_sidx) : nullptr);
   delete tb_;
   const int tile = 4 * g.bin;
   const int ntiles = (g.nf / tile) * (g.nf / tile);
@@ -767,10 +772,15 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
                 std::string("plan tables: ") + hipGetErrorString(e));
   }
 
-  // workspace layout
+  // workspace layout: what a forward needs first, then the state a forward
+  // leaves for the backward (the draws, the records' slots), then the
+  // backward's own buffers; a workspace of fwd_bytes runs forward-only passes
   size_t o = 0;
   auto take = [&](size_t bytes) { const size_t r = o; o = align256(o + bytes); return r; };
   const size_t nt = pl->n_total;
+  const size_t nrec = (size_t)pl->group_pairs * pl->R2 * pl->emit;
+  const size_t psz = dbl_g ? 16 : 8;
+  const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
   pl->off_live = take(sizeof(DevLive));
   pl->off_tmap = take((size_t)doe->H * doe->W * pl->sz_cf);
   pl->off_st = take(8 * nt * sizeof(double));
@@ -780,49 +790,48 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_U = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
   pl->off_alpha = take(pl->n_pairs * sizeof(double));
   pl->off_lossp = take(pl->n_pairs * sizeof(double));
-  pl->off_stats = take(4 * sizeof(unsigned long long));
+  pl->off_stats = take(RW_N_STATS * sizeof(unsigned long long));
   pl->off_scratch =
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * doe_buf_elems(M) * pl->sz_cf);
-  pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));
   pl->off_rcls = take((size_t)nt);
+  pl->off_rpos = take(nrec * psz);
+  pl->off_rval = take(nrec * pl->sz_cg);
+  pl->off_tpos = take(nrec * psz);
+  pl->off_tval = take(nrec * pl->sz_cg);
+  pl->off_spos = take(nrec * psz);
+  pl->off_sval = take(nrec * pl->sz_cg);
+  pl->off_scur = take((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) * 8);
+  pl->off_work = take(((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) + 1) * 4);
+  pl->off_cnt = take(nk * sizeof(unsigned int));
+  pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
+  pl->off_cur = take(nk * sizeof(unsigned long long));
+  pl->fwd_bytes = o;
+  // state of the forward that only the backward reads
   pl->off_jdraw = take(cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t));
+  pl->off_tidx = take(pl->tiled_interp ? nrec * 4 : 0);
+  pl->off_sidx = take(pl->tiled_interp ? nrec * 4 : 0);
+  // the backward's own buffers
+  pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
                                  sizeof(float)
                            : 0);
   pl->off_dlist = take(cfg->sampling == RW_SAMPLE_FULL
                            ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf);
   pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
-  pl->off_raygrad = take(8 * nt * sizeof(double));
+  pl->off_raygrad = take((size_t)RW_RAYGRAD * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
   pl->off_G = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
-  {
-    const size_t nrec = (size_t)pl->group_pairs * pl->R2 * pl->emit;
-    const size_t psz = dbl_g ? 16 : 8;
-    pl->off_rpos = take(nrec * psz);
-    pl->off_rval = take(nrec * pl->sz_cg);
-    pl->off_tpos = take(nrec * psz);
-    pl->off_tval = take(nrec * pl->sz_cg);
-    pl->off_tidx = take(pl->tiled_interp ? nrec * 4 : 0);
-    pl->off_spos = take(nrec * psz);
-    pl->off_sval = take(nrec * pl->sz_cg);
-    const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
-    pl->off_sidx = take(pl->tiled_interp ? nrec * 4 : 0);
-    pl->off_scur = take((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) * 8);
-    pl->off_work = take(((size_t)pl->n_pairs * (pl->bg.keys >> (2 * pl->bg.sshift)) + 1) * 4);
-    pl->off_interp = take(pl->tiled_interp ? nrec * kInterpStride * pl->sz_cg : 0);
-    pl->off_cnt = take(nk * sizeof(unsigned int));
-    pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
-    pl->off_cur = take(nk * sizeof(unsigned long long));
-  }
+  pl->off_interp = take(pl->tiled_interp ? nrec * kInterpStride * pl->sz_cg : 0);
   pl->total = o;
   *out = pl;
   return RW_OK;
 }
 
-rw_status rw_plan_workspace_bytes(const rw_plan* pl, size_t* bytes) {
-  if (!pl || !bytes) return fail(RW_ERR_INVALID_ARG, "null argument");
-  *bytes = pl->total;
+rw_status rw_plan_workspace_bytes(const rw_plan* pl, size_t* fwd_bytes, size_t* bwd_extra_bytes) {
+  if (!pl || !fwd_bytes) return fail(RW_ERR_INVALID_ARG, "null argument");
+  *fwd_bytes = pl->fwd_bytes;
+  if (bwd_extra_bytes) *bwd_extra_bytes = pl->total - pl->fwd_bytes;
   return RW_OK;
 }
 
@@ -846,8 +855,9 @@ rw_status rw_plan_destroy(rw_plan* pl) {
 
 rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, void* stream) {
   if (!pl || !ws) return fail(RW_ERR_INVALID_ARG, "null argument");
-  if (!pl->fwd_done || ws != pl->fwd_ws || ws_bytes < pl->total)
-    return fail(RW_ERR_STATE, "rw_autotune needs a preceding rw_forward on this workspace");
+  if (!pl->fwd_done || !pl->fwd_full || ws != pl->fwd_ws || ws_bytes < pl->total)
+    return fail(RW_ERR_STATE, "rw_autotune needs a preceding rw_forward on this workspace "
+                              "(of fwd + bwd bytes)");
   hipStream_t st = (hipStream_t)stream;
   char* b = (char*)ws;
   pl->gfwd.reset();
@@ -934,7 +944,7 @@ static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float*
     hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
                        doe_amp, (C2<float>*)(b + pl->off_tmap), nmap);
   HIPCHK(hipGetLastError());
-  zero<unsigned long long>(b + pl->off_stats, 4, st);
+  zero<unsigned long long>(b + pl->off_stats, RW_N_STATS, st);
   DoeArgs a = doe_args(pl, ws, replay_idx, idx_out);
   for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
     const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
@@ -984,25 +994,16 @@ static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float*
   return RW_OK;
 }
 
-rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_phase,
-                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
-                     void* ws, size_t ws_bytes, const int32_t* replay_idx, int32_t* idx_out,
-                     void* stream) {
-  if (!pl || !doe_phase || !doe_amp || !psf_out || !ws)
-    return fail(RW_ERR_INVALID_ARG, "null required argument");
-  if (pl->prm.size() > 0 && !lens_params)
-    return fail(RW_ERR_INVALID_ARG, "lens_params required when the plan has lens parameters");
-  if (target && !loss_out) return fail(RW_ERR_INVALID_ARG, "target given without loss_out");
-  if (ws_bytes < pl->total) return fail(RW_ERR_STATE, "workspace smaller than rw_plan_workspace_bytes");
-  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  if (replay_idx && pl->cfg.sampling == RW_SAMPLE_FULL)
-    return fail(RW_ERR_INVALID_ARG, "replay is meaningless in FULL sampling");
-  hipStream_t st = (hipStream_t)stream;
+static rw_status forward_impl(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, const float* target, float* psf_out,
+                              float* loss_out, void* ws, bool fwd_only, bool use_graph,
+                              const int32_t* replay_idx, int32_t* idx_out, hipStream_t st) {
   pl->fwd_done = false;
+  pl->fwd_only = fwd_only;
   rw_status r;
-  if (pl->graph) {
+  if (use_graph) {
     const GraphKey key = {{(const void*)lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
-                           ws, replay_idx, idx_out, nullptr}};
+                           ws, replay_idx, idx_out, fwd_only ? (const void*)1 : nullptr}};
     r = graph_run(pl, pl->gfwd, key, st, [&](hipStream_t cs) {
       return fwd_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
                          replay_idx, idx_out, cs);
@@ -1011,8 +1012,10 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
     r = fwd_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
                     replay_idx, idx_out, st);
   }
+  pl->fwd_only = false;
   if (r != RW_OK) return r;
   pl->fwd_done = true;
+  pl->fwd_full = !fwd_only;
   pl->fwd_target = target;
   pl->fwd_replay = replay_idx;
   pl->fwd_phase = doe_phase;
@@ -1021,6 +1024,34 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   pl->fwd_ws = ws;
   pl->fwd_stream = st;
   return RW_OK;
+}
+
+static rw_status forward_args(const rw_plan* pl, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, const float* target, const float* psf_out,
+                              const float* loss_out, const int32_t* replay_idx) {
+  if (!pl || !doe_phase || !doe_amp || !psf_out)
+    return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (pl->prm.size() > 0 && !lens_params)
+    return fail(RW_ERR_INVALID_ARG, "lens_params required when the plan has lens parameters");
+  if (target && !loss_out) return fail(RW_ERR_INVALID_ARG, "target given without loss_out");
+  if (replay_idx && pl->cfg.sampling == RW_SAMPLE_FULL)
+    return fail(RW_ERR_INVALID_ARG, "replay is meaningless in FULL sampling");
+  return RW_OK;
+}
+
+rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                     const float* doe_amp, const float* target, float* psf_out, float* loss_out,
+                     void* ws, size_t ws_bytes, const int32_t* replay_idx, int32_t* idx_out,
+                     void* stream) {
+  const rw_status a = forward_args(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                                   replay_idx);
+  if (a != RW_OK) return a;
+  if (!ws) return fail(RW_ERR_INVALID_ARG, "null workspace");
+  if (ws_bytes < pl->fwd_bytes)
+    return fail(RW_ERR_STATE, "workspace smaller than the forward bytes of rw_plan_workspace_bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  return forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
+                      ws_bytes < pl->total, pl->graph, replay_idx, idx_out, (hipStream_t)stream);
 }
 
 rw_status rw_set_profiling(rw_plan* pl, int enable) {
@@ -1139,6 +1170,8 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
   if (ws != pl->fwd_ws || ws_bytes < pl->total)
     return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");
+  if (!pl->fwd_full)
+    return fail(RW_ERR_STATE, "the forward ran forward-only (its workspace held fwd bytes only)");
   if (!dL_dpsf && !pl->fwd_target)
     return fail(RW_ERR_STATE, "dL_dpsf is NULL and the forward had no target");
   const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;

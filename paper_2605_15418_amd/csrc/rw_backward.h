@@ -14,6 +14,7 @@
 #include "rw_kernels.h"
 
 #define RW_LENSG_SLOTS 128
+#define RW_RAYGRAD 8          // cogradient components per incident ray at the DOE
 #define RW_LENSG_SENSOR (RW_MAX_SURF * 8)
 
 namespace rw {

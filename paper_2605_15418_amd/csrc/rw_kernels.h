@@ -16,6 +16,7 @@
 namespace rw {
 
 constexpr int kThreads = 256;
+#define RW_N_STATS 4           // forward counters (alive rays, secondaries, ...)
 
 // Tt: trace; Tf: patch spectrum; Tp: optical path and wavelet phase; Tg: sensor
 // grid; Te: sine / cosine of the wavelet phase after its reduction to [0, 2 pi)

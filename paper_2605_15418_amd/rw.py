@@ -87,7 +87,7 @@ def load_library(path=LIB_PATH):
     lib.rw_plan_create.argtypes = [ctypes.POINTER(rw_surface), ctypes.c_int,
                                    ctypes.POINTER(rw_doe_desc), ctypes.POINTER(rw_param_ref),
                                    ctypes.c_int, ctypes.POINTER(rw_config), ctypes.POINTER(vp)]
-    lib.rw_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+    lib.rw_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.rw_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.rw_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.rw_get_stats.argtypes = [vp, ctypes.POINTER(rw_stats)]
@@ -206,9 +206,10 @@ class Plan:
         _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
                                                  len(prm), ctypes.byref(c), ctypes.byref(h)))
         self.handle = h
-        nb = ctypes.c_size_t()
-        _check(self.lib, self.lib.rw_plan_workspace_bytes(h, ctypes.byref(nb)))
-        self.ws_bytes = nb.value
+        nf, nx = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(self.lib, self.lib.rw_plan_workspace_bytes(h, ctypes.byref(nf), ctypes.byref(nx)))
+        self.fwd_bytes = nf.value
+        self.ws_bytes = nf.value + nx.value
         self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws_raw.data_ptr()) % 256
         self.ws = self._ws_raw[off:off + self.ws_bytes]

@@ -254,6 +254,33 @@ def test_hybrid_psf_autograd_matches_oracle_and_guards_the_workspace(rw):
     torch.cuda.synchronize()
 
 
+def test_forward_only_workspace(rw):
+    """A workspace of fwd_bytes runs a forward without the backward's state: the
+    same PSF and draws as with the whole workspace, and rw_backward refuses."""
+    import ctypes
+    system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
+    plan = rw.Plan(system, cfg, precision="mixed")
+    assert 0 < plan.fwd_bytes < plan.ws_bytes
+    vals, ph, am = gpu_inputs(system, maps)
+    psf0, _, idx0 = plan.forward(vals, ph, am, want_idx=True)
+    psf = torch.empty_like(psf0)
+    idx = torch.empty_like(idx0)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = plan.lib.rw_forward(plan.handle, p(vals), p(ph), p(am), None, p(psf), None, p(plan.ws),
+                             plan.fwd_bytes, None, p(idx),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert st == 0
+    assert torch.equal(idx, idx0)
+    assert rel_l2(psf.cpu().numpy(), psf0.cpu().numpy()) < 1e-5
+    with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
+        plan.backward(torch.ones_like(psf))
+    st = plan.lib.rw_forward(plan.handle, p(vals), p(ph), p(am), None, p(psf), None, p(plan.ws),
+                             plan.fwd_bytes - 256, None, None,
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rw.rw.STATUS[st] == "RW_ERR_STATE"
+
+
 def test_autotune_keeps_results(rw):
     """The launch shape chosen by rw_autotune changes nothing but speed."""
     system, cfg, maps = small_hologram(sampling="mag", N=32, rays=8)
