@@ -183,6 +183,22 @@ rw_status rw_forward(rw_plan* plan, const float* lens_params, const float* doe_p
                      void* workspace, size_t workspace_bytes, const int32_t* replay_idx,
                      int32_t* idx_out, void* stream);
 
+/* Forward pass that allocates nothing, for callers that cannot call hipMalloc (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments and results as a forward-only rw_forward, but the workspace is a
+ * device array of the library, 256 MiB per GPU (RW_STATIC_SCRATCH_BYTES), held by each
+ * GPU the library runs on until the process ends; the caller still passes every input
+ * and output.  The call records no events and no graph (profiling and rw_set_graph do
+ * not apply to it), and rw_backward cannot follow it (RW_ERR_STATE).  Every call on one
+ * GPU uses the same array and leaves its contents to the next call (each forward
+ * clears what it needs); calls that overlap on one GPU, from any plan or stream, race.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_UNSUPPORTED (fwd_bytes of the plan above 256 MiB),
+ *         RW_ERR_HIP. */
+#define RW_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+rw_status rw_forward_static(rw_plan* plan, const float* lens_params, const float* doe_phase,
+                            const float* doe_amp, const float* target, float* psf_out,
+                            float* loss_out, const int32_t* replay_idx, int32_t* idx_out,
+                            void* stream);
 
 /* Backward pass (adjoint G1: the a.e. derivative with the sample indices of the
  * preceding forward held fixed).

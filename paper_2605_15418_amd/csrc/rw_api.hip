@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -133,6 +134,7 @@ struct rw_plan {
   bool fwd_done = false;
   bool fwd_full = false;    // the last forward left the backward's state (draws, slots)
   bool fwd_only = false;    // the forward being enqueued writes no backward state
+  bool no_alloc = false;    // enqueue without events or graphs (rw_forward_static)
   const float* fwd_target = nullptr;
   const int32_t* fwd_replay = nullptr;
   const float* fwd_phase = nullptr;
@@ -166,7 +168,7 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   StageTimer(rw_plan* p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
-    if (pl->prof && !pl->capturing) {
+    if (pl->prof && !pl->capturing && !pl->no_alloc) {
       a = pl->ev_get(); b = pl->ev_get(); (void)hipEventRecord(a, st);
     }
   }
@@ -1052,6 +1054,62 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   return forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
                       ws_bytes < pl->total, pl->graph, replay_idx, idx_out, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- forward without allocation ---
+// The device workspace of rw_forward_static: one array per GPU the library runs
+// on, held until the process ends.  Host code never uses the array's name as an
+// address; it takes the device address from hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[RW_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (looked up once per device,
+// with the device current).
+rw_status static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RW_ERR_UNSUPPORTED, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RW_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rw_status rw_forward_static(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                            const float* doe_amp, const float* target, float* psf_out,
+                            float* loss_out, const int32_t* replay_idx, int32_t* idx_out,
+                            void* stream) {
+  const rw_status a = forward_args(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                                   replay_idx);
+  if (a != RW_OK) return a;
+  if (pl->fwd_bytes > RW_STATIC_SCRATCH_BYTES)
+    return fail(RW_ERR_UNSUPPORTED,
+                "the plan's forward workspace (" + std::to_string(pl->fwd_bytes) +
+                    " bytes) exceeds the static scratch of rw_forward_static (" +
+                    std::to_string(RW_STATIC_SCRATCH_BYTES) + " bytes)");
+  void* ws = nullptr;
+  const rw_status e = static_scratch(&ws);
+  if (e != RW_OK) return e;
+  pl->no_alloc = true;
+  const rw_status r = forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                                   ws, true, false, replay_idx, idx_out, (hipStream_t)stream);
+  pl->no_alloc = false;
+  return r;
 }
 
 rw_status rw_set_profiling(rw_plan* pl, int enable) {

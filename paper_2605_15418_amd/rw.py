@@ -19,10 +19,12 @@ PARAM_FIELDS = {"curv": 0, "conic": 1, "A4": 2, "A6": 3, "A8": 4, "A10": 5, "gap
 SAMPLING = {"mag": 0, "uni": 1, "full": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 GRAD = {"G1": 0, "G2": 1}
+RW_STATIC_SCRATCH_BYTES = 256 << 20   # workspace of rw_forward_static (include/rw.h)
 STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",
           4: "RW_ERR_NONFINITE", 5: "RW_ERR_OOM", 6: "RW_ERR_HIP", 7: "RW_ERR_UNSUPPORTED"}
 
-EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
+EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
+            "rw_backward",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
             "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph",
             "rw_autotune")
@@ -89,6 +91,7 @@ def load_library(path=LIB_PATH):
                                    ctypes.c_int, ctypes.POINTER(rw_config), ctypes.POINTER(vp)]
     lib.rw_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.rw_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    lib.rw_forward_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rw_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.rw_get_stats.argtypes = [vp, ctypes.POINTER(rw_stats)]
     lib.rw_export_doe_hits.argtypes = [vp, vp, vp, vp]
@@ -100,7 +103,8 @@ def load_library(path=LIB_PATH):
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
-    for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_backward",
+    for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
+                 "rw_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
                  "rw_get_profile", "rw_set_graph", "rw_autotune"):
         getattr(lib, name).restype = ctypes.c_int
