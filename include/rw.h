@@ -51,7 +51,7 @@ typedef enum {
   RW_ERR_INVALID_ARG = 1,   /* null pointer, out-of-range enum, bad value      */
   RW_ERR_SHAPE = 2,         /* sizes the kernels do not support               */
   RW_ERR_STATE = 3,         /* backward before forward, workspace too small   */
-  RW_ERR_NONFINITE = 4,     /* reserved                                       */
+  RW_ERR_NONFINITE = 4,     /* NaN / Inf input (rw_config.check_finite)       */
   RW_ERR_OOM = 5,           /* a plan table could not be allocated            */
   RW_ERR_HIP = 6,           /* a HIP runtime call failed                      */
   RW_ERR_UNSUPPORTED = 7    /* a valid request outside what the kernels cover */
@@ -139,14 +139,27 @@ typedef struct {
   int n_patch_class;
   int patch_class_p[3];
   double curv_eps;
+  /* 1: rw_forward checks lens_params, the DOE maps and the target for NaN / Inf
+   * first (one reduction kernel and a synchronisation of the stream) and returns
+   * RW_ERR_NONFINITE without running the pass; 0: no check. */
+  int check_finite;
 } rw_config;
 
 typedef struct rw_plan rw_plan;
 
+/* Counters of the last forward.  Rays that end early (Q14 of the design notes:
+ * terminated, kept in the ray order with zero amplitude) are counted by cause. */
 typedef struct {
-  uint64_t rays_total;      /* incident rays launched                    */
-  uint64_t rays_alive;      /* incident rays that reached the DOE inside the stop */
-  uint64_t secondaries;     /* secondary rays emitted with non-zero weight */
+  uint64_t rays_total;          /* incident rays launched                                */
+  uint64_t rays_alive;          /* incident rays that reached the DOE inside the stop    */
+  uint64_t secondaries;         /* secondary rays that reached the sensor with a weight  */
+  uint64_t killed_no_hit;       /* no ray-surface intersection (Newton failed)           */
+  uint64_t killed_aperture;     /* outside a surface's semi-aperture                     */
+  uint64_t killed_tir;          /* total internal reflection                             */
+  uint64_t killed_outside_doe;  /* hit the DOE surface outside the map (the stop)        */
+  uint64_t secondaries_lost;    /* drawn secondaries that failed between DOE and sensor  */
+  uint64_t evanescent_bins;     /* evanescent bins of the alive rays' spectra ...        */
+  uint64_t spectrum_bins;       /* ... out of this many (M^2 per alive ray)              */
 } rw_stats;
 
 /* Creates a plan: validates shapes, builds constant tables (wavelength-dependent

@@ -459,7 +459,7 @@ def ray_patch_sides(surf, p, pitch, cfg):
     if len(cands) == 1:
         return np.full(p.shape[0], cands[0], dtype=np.int64)
     eps = float(cfg.get("curv_eps", 0.1))
-    R = local_radius(surf, p[:, 0].detach(), p[:, 1].detach()).numpy()
+    R = local_radius(surf, p[:, 0].detach(), p[:, 1].detach()).detach().numpy()
     out = np.full(p.shape[0], cands[-1], dtype=np.int64)
     for i, Rl in enumerate(R):
         for P in cands:

@@ -270,6 +270,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.stats = (unsigned long long*)(b + pl->off_stats);
   a.gt = b + pl->off_gt;
   a.raygrad = (double*)(b + pl->off_raygrad);
+  a.lensg = (double*)(b + pl->off_lensg);
   a.acc = b + pl->off_acc;
   a.acc_side = pl->acc_side;
   a.ctx = (RayCtx*)(b + pl->off_ctx);
@@ -957,11 +958,13 @@ static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float*
     if (pl->cfg.precision == RW_PREC_FP32)
       hipLaunchKernelGGL(k_trace<float>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
                          (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
-                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg);
+                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg,
+                         (unsigned long long*)(b + pl->off_stats));
     else
       hipLaunchKernelGGL(k_trace<double>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
                          (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
-                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg);
+                         (double*)(b + pl->off_ck), pl->n_total, pair0, ppg,
+                         (unsigned long long*)(b + pl->off_stats));
     }
     HIPCHK(hipGetLastError());
     a.ray0 = (size_t)pair0 * pl->R2;
@@ -1052,6 +1055,24 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
   if (ws_bytes < pl->fwd_bytes)
     return fail(RW_ERR_STATE, "workspace smaller than the forward bytes of rw_plan_workspace_bytes");
   if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (pl->cfg.check_finite) {
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int* flag = (unsigned int*)((char*)ws + pl->off_stats);
+    zero<unsigned int>(flag, 1, st);
+    const size_t nmap = (size_t)pl->H * pl->W;
+    const size_t nt = target ? (size_t)pl->n_pairs * pl->Q * pl->Q : 0;
+    hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, st, lens_params,
+                       lens_params ? pl->prm.size() : (size_t)0, doe_phase, nmap, doe_amp, nmap,
+                       target, nt, flag);
+    HIPCHK(hipGetLastError());
+    unsigned int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h) {
+      pl->fwd_done = false;
+      return fail(RW_ERR_NONFINITE, "NaN or Inf in lens_params, doe_phase, doe_amp or target");
+    }
+  }
   return forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
                       ws_bytes < pl->total, pl->graph, replay_idx, idx_out, (hipStream_t)stream);
 }
@@ -1136,12 +1157,19 @@ rw_status rw_get_profile(rw_plan* pl, rw_profile* out) {
 rw_status rw_get_stats(rw_plan* pl, rw_stats* out) {
   if (!pl || !out) return fail(RW_ERR_INVALID_ARG, "null argument");
   if (!pl->fwd_done) return fail(RW_ERR_STATE, "no forward pass yet");
-  unsigned long long h[4];
+  unsigned long long h[RW_N_STATS];
   HIPCHK(hipStreamSynchronize(pl->fwd_stream));
   HIPCHK(hipMemcpy(h, (char*)pl->fwd_ws + pl->off_stats, sizeof(h), hipMemcpyDeviceToHost));
   out->rays_total = pl->n_total;
-  out->rays_alive = h[0];
-  out->secondaries = h[1];
+  out->rays_alive = h[RW_ST_ALIVE];
+  out->secondaries = h[RW_ST_SEC];
+  out->killed_no_hit = h[RW_ST_NOHIT];
+  out->killed_aperture = h[RW_ST_APER];
+  out->killed_tir = h[RW_ST_TIR];
+  out->killed_outside_doe = h[RW_ST_OUTSIDE];
+  out->secondaries_lost = h[RW_ST_LOST];
+  out->evanescent_bins = h[RW_ST_EVAN];
+  out->spectrum_bins = h[RW_ST_BINS];
   return RW_OK;
 }
 
@@ -1164,7 +1192,7 @@ static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, 
   if (dbl) zero<double>(b + pl->off_gt, 2 * nmap, st);
   else zero<float>(b + pl->off_gt, 2 * nmap, st);
   zero<double>(b + pl->off_lensg, RW_LENSG_SLOTS, st);
-  if (want_lens) zero<double>(b + pl->off_raygrad, 8 * pl->n_total, st);
+  if (want_lens) zero<double>(b + pl->off_raygrad, (size_t)RW_RAYGRAD * pl->n_total, st);
   {
     const size_t nacc = (size_t)pl->blocks_dir[1] * pl->acc_side * pl->acc_side * 2;
     if (dbl) zero<double>(b + pl->off_acc, nacc, st);
@@ -1196,6 +1224,15 @@ static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, 
       s = doe_launch(pl, false, a, pair0, ppg, st);
     }
     if (s != RW_OK) return s;
+    if (want_lens && pl->has_post) {
+      StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
+      const unsigned nb = (unsigned)((nr + 3) / 4);
+      if (pl->cfg.precision == RW_PREC_FP64)
+        hipLaunchKernelGGL(k_post_bwd<double>, dim3(nb), dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL(k_post_bwd<float>, dim3(nb), dim3(256), 0, st, a);
+      HIPCHK(hipGetLastError());
+    }
     if (want_lens) {
       StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
       hipLaunchKernelGGL(k_trace_bwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
@@ -1233,9 +1270,10 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
   if (!dL_dpsf && !pl->fwd_target)
     return fail(RW_ERR_STATE, "dL_dpsf is NULL and the forward had no target");
   const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;
-  if (want_lens && (!pl->planar_doe || pl->has_post))
+  if (want_lens && pl->has_post && (!pl->tiled_interp || pl->n_surf - pl->s_doe - 1 > kPostMax))
     return fail(RW_ERR_UNSUPPORTED,
-                "lens-parameter gradients need a planar DOE followed directly by the sensor");
+                "lens-parameter gradients through surfaces after the DOE need a batched plan "
+                "whose records fit one launch group, and at most 4 such surfaces");
   hipStream_t st = (hipStream_t)stream;
   if (pl->graph) {
     // every pointer the recorded kernels read: the forward's PSF feeds the Eq. 5

@@ -14,7 +14,10 @@
 #include "rw_kernels.h"
 
 #define RW_LENSG_SLOTS 128
-#define RW_RAYGRAD 8          // cogradient components per incident ray at the DOE
+// Cogradient components per incident ray at the DOE: position (3), direction (3),
+// optical path, sensor z, then the frame: u (3), v (3) as explicit vectors and
+// the torque (3) of an infinitesimal rotation of the whole frame (u, v, n).
+#define RW_RAYGRAD 17
 #define RW_LENSG_SENSOR (RW_MAX_SURF * 8)
 
 namespace rw {
@@ -100,9 +103,12 @@ struct WaveletAdj {    // cogradients of one wavelet's inputs
   double g_phi0, g_wx, g_wy, g_dz;
 };
 
-// Cogradient of the incident state from one wavelet (planar DOE, sensor next).
+// Cogradient of the incident state from the wavelets of one ray (sensor next):
+// hit point, incident tangential wavevector, optical path, sensor z, and the
+// torque sum_i d_i x dL/dd_i of the emitted directions, the cogradient of a
+// rotation of the frame (u, v, n) at fixed tangential wavevectors.
 struct IncAcc {
-  double gp[3], gkin[2], gopl, gzs;
+  double gp[3], gkin[2], gopl, gzs, tq[3];
 };
 
 // Cogradient of the emitted secondary direction (planar DOE, sensor next).
@@ -149,7 +155,17 @@ __device__ __forceinline__ void incident_from_wavelet(const DoeArgs& a, const Ra
   wavevector_cograd(c, sec, gds, gKu, gKv);
   acc.gkin[0] += gKu;
   acc.gkin[1] += gKv;
+  acc.tq[0] += ds[1] * gds[2] - ds[2] * gds[1];
+  acc.tq[1] += ds[2] * gds[0] - ds[0] * gds[2];
+  acc.tq[2] += ds[0] * gds[1] - ds[1] * gds[0];
 }
+
+// Inputs of one surface step of the trace adjoints: p_in, d_in and the surface's
+// (z, c, k, A4, A6, A8, A10).
+constexpr int kNT = 13;
+
+// Entries per record of the tiled interpolation's results (value, d/dx, d/dy, pad).
+constexpr int kInterpStride = 4;
 
 // Sum over the 64 lanes of a wave (butterfly: every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -162,10 +178,163 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// ------------------------------------- secondaries through post-DOE surfaces ---
+// Adjoint of the conventional trace of every secondary ray through the surfaces
+// between the DOE and the sensor, for the lens-parameter gradient (the DOE
+// adjoint covers the weights; with such surfaces it leaves the geometry here).
+// One wave per incident ray, its lanes over the ray's record slots: the
+// secondary is re-traced in FP64 with its entry state before every surface,
+// its wavelet cogradient formed from the forward's record value and the tiled
+// interpolation, then taken back through the sensor step (analytic) and each
+// surface (dual numbers of the 13 inputs of a step, as in the incident trace
+// adjoint).  Adds, per ray, the cogradients of the hit point, the incident
+// tangential wavevector, the optical path, the sensor z and the frame torque to
+// the DOE adjoint's; the surfaces' own parameters go to lensg.
+constexpr int kPostMax = 4;     // refracting surfaces after the DOE
+
+template <class Tg>
+__global__ __launch_bounds__(256) void k_post_bwd(DoeArgs a) {
+  const DevCfg& cfg = *a.cfg;
+  const int lane = threadIdx.x & 63;
+  const size_t w = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= a.nray) return;                                   // uniform over the wave
+  const size_t gid = a.ray0 + w;
+  if (a.st[7 * a.n_total + gid] == 0.0) return;
+  const RayCtx c = a.ctx[gid];
+  const DevPair& pr = a.pairs[c.pair];
+  const int sd = cfg.s_doe, S = cfg.n_surf, npost = S - sd - 1;
+  const int M = cfg.pad * c.P;
+  const double ns = pr.n_med[S], k0 = c.k0;
+  const double Xc[3] = {pr.pc[0], pr.pc[1], a.live->sensor_z};
+  const double cell = cfg.nf / (2.0 * RW_PI);
+  double gp[3] = {0, 0, 0}, gkin[2] = {0, 0}, gopl = 0.0, gzs = 0.0, tq[3] = {0, 0, 0};
+  double gsurf[kPostMax][7];
+  for (int j = 0; j < kPostMax; ++j)
+    for (int f = 0; f < 7; ++f) gsurf[j][f] = 0.0;
+  const int nslot = a.full ? M * M : cfg.N;
+  for (int i = lane; i < nslot; i += 64) {
+    int J = i;
+    if (!a.full) J = a.jdraw[gid * cfg.N + i];
+    if (J < 0) continue;
+    const size_t slot = (gid - a.ray0) * (size_t)a.emit + i;
+    const C2<Tg> rv = ((const C2<Tg>*)a.rec_val)[slot];
+    if (is_none(rv)) continue;
+    const int jx = J / M - M / 2, jy = J % M - M / 2;
+    const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+    const double kz = sqrt(c.k_out * c.k_out - Ku * Ku - Kv * Kv);
+    double ds[3], p[3], d[3], pe[kPostMax][3], de[kPostMax][3];
+    for (int q = 0; q < 3; ++q) {
+      ds[q] = (Ku * c.u[q] + Kv * c.v[q] + kz * c.n[q]) / c.k_out;
+      p[q] = c.p[q];
+      d[q] = ds[q];
+    }
+    bool ok = true;
+    for (int j = 0; j < npost && ok; ++j) {
+      const int s = sd + 1 + j;
+      for (int q = 0; q < 3; ++q) { pe[j][q] = p[q]; de[j][q] = d[q]; }
+      const Surf<double> sf = surf_of<double>(a.live->s[s]);
+      double t;
+      ok = intersect(sf, p, d, t);
+      if (!ok) break;
+      for (int q = 0; q < 3; ++q) p[q] += t * d[q];
+      double nrm[3];
+      surface_normal(sf, p[0], p[1], nrm);
+      ok = refract(d, nrm, pr.n_med[s] / pr.n_med[s + 1]);
+    }
+    if (!ok) continue;                 // the forward kept no record for it either
+    // wavelet cogradients from the record value cv = w |d_z| e^{i phi0}
+    const C2<Tg>* q3 = (const C2<Tg>*)a.interp + kInterpStride * slot;
+    const double g0r = q3[0].re, g0i = q3[0].im, dxr = q3[1].re, dxi = q3[1].im,
+                 dyr = q3[2].re, dyi = q3[2].im;
+    const double cr = rv.re, ci = rv.im;
+    const double dza = fabs(d[2]);
+    const double g_wx = -(cr * dxr + ci * dxi) * cell, g_wy = -(cr * dyr + ci * dyi) * cell;
+    const double g_phi0 = -(g0r * ci - g0i * cr), g_dz = (g0r * cr + g0i * ci) / dza;
+    // sensor step: phi0 = k0 (OPL + ns d.(Xc - p)), w = k0 ns pitch (d_x, d_y), |d_z|
+    double g_p[3], g_d[3];
+    for (int q = 0; q < 3; ++q) {
+      g_p[q] = -k0 * ns * g_phi0 * d[q];
+      g_d[q] = k0 * ns * g_phi0 * (Xc[q] - p[q]);
+    }
+    g_d[0] += k0 * ns * cfg.psf_pitch * g_wx;
+    g_d[1] += k0 * ns * cfg.psf_pitch * g_wy;
+    g_d[2] += g_dz * (d[2] >= 0 ? 1.0 : -1.0);
+    const double g_o = k0 * g_phi0;
+    gopl += g_o;
+    gzs += k0 * ns * g_phi0 * d[2];
+    // back through the surfaces, last first
+    for (int j = npost - 1; j >= 0; --j) {
+      const int s = sd + 1 + j;
+      typedef Dual<kNT> D;
+      D pd[3], dd[3];
+      for (int q = 0; q < 3; ++q) {
+        pd[q] = dvar<kNT>(pe[j][q], q);
+        dd[q] = dvar<kNT>(de[j][q], 3 + q);
+      }
+      const DevSurf& dsf = a.live->s[s];
+      Surf<D> sf;
+      sf.z = dvar<kNT>(dsf.z, 6);
+      sf.c = dvar<kNT>(dsf.c, 7);
+      sf.k = dvar<kNT>(dsf.k, 8);
+      sf.A4 = dvar<kNT>(dsf.A4, 9);
+      sf.A6 = dvar<kNT>(dsf.A6, 10);
+      sf.A8 = dvar<kNT>(dsf.A8, 11);
+      sf.A10 = dvar<kNT>(dsf.A10, 12);
+      D tt;
+      intersect(sf, pd, dd, tt);
+      D qq[3];
+      for (int q = 0; q < 3; ++q) qq[q] = pd[q] + tt * dd[q];
+      const D dopl = tt * pr.n_med[s];
+      D nrm[3];
+      surface_normal(sf, qq[0], qq[1], nrm);
+      refract(dd, nrm, dconst<kNT>(pr.n_med[s] / pr.n_med[s + 1]));
+      double gin[kNT];
+      for (int k = 0; k < kNT; ++k) {
+        double v = g_o * dopl.d[k];
+        for (int q = 0; q < 3; ++q) v += g_p[q] * qq[q].d[k] + g_d[q] * dd[q].d[k];
+        gin[k] = v;
+      }
+      for (int q = 0; q < 3; ++q) { g_p[q] = gin[q]; g_d[q] = gin[3 + q]; }
+      for (int f = 0; f < 7; ++f) gsurf[j][f] += gin[6 + f];
+    }
+    // at the DOE: origin p, direction ds = (Ku u + Kv v + kz n) / k_out
+    for (int q = 0; q < 3; ++q) gp[q] += g_p[q];
+    const double gu = g_d[0] * c.u[0] + g_d[1] * c.u[1] + g_d[2] * c.u[2];
+    const double gv = g_d[0] * c.v[0] + g_d[1] * c.v[1] + g_d[2] * c.v[2];
+    const double gn = g_d[0] * c.n[0] + g_d[1] * c.n[1] + g_d[2] * c.n[2];
+    gkin[0] += (gu - gn * Ku / kz) / c.k_out;
+    gkin[1] += (gv - gn * Kv / kz) / c.k_out;
+    tq[0] += ds[1] * g_d[2] - ds[2] * g_d[1];
+    tq[1] += ds[2] * g_d[0] - ds[0] * g_d[2];
+    tq[2] += ds[0] * g_d[1] - ds[1] * g_d[0];
+  }
+  double v[10] = {gp[0], gp[1], gp[2], gkin[0], gkin[1], gopl, gzs, tq[0], tq[1], tq[2]};
+  for (int q = 0; q < 10; ++q) v[q] = wave_sum(v[q]);
+  for (int j = 0; j < npost; ++j)
+    for (int f = 0; f < 7; ++f) {
+      const double sum = wave_sum(gsurf[j][f]);
+      if (lane == 0 && sum != 0.0) atomicAdd(&a.lensg[(sd + 1 + j) * 8 + f], sum);
+    }
+  if (lane == 0) {
+    // one writer per ray: add to what the DOE adjoint stored
+    const double lf = c.k0 * c.n_in;
+    double add[RW_RAYGRAD];
+    for (int q = 0; q < 3; ++q) {
+      add[q] = v[q];
+      add[3 + q] = lf * (v[3] * c.u[q] + v[4] * c.v[q]);
+      add[8 + q] = lf * v[3] * c.d[q];
+      add[11 + q] = lf * v[4] * c.d[q];
+      add[14 + q] = v[7 + q];
+    }
+    add[6] = v[5];
+    add[7] = v[6];
+    for (int q = 0; q < RW_RAYGRAD; ++q) a.raygrad[(size_t)q * a.n_total + gid] += add[q];
+  }
+}
+
 // ------------------------------------------ type-2 interpolation, tiled ---
-// Results per record: B, dB/dx, dB/dy and a pad, so that a record fills one
-// aligned 32-byte sector (FP32) of the scattered stores.
-constexpr int kInterpStride = 4;
+// Results per record: B, dB/dx, dB/dy and a pad (kInterpStride), so that a
+// record fills one aligned 32-byte sector (FP32) of the scattered stores.
 
 // Cogradient of every secondary-ray record of the forward (sorted by bin):
 // the sensor-grid cogradient B interpolated with the ES kernel at the record's
@@ -304,8 +473,7 @@ __global__ void k_dmaps(const float* phase, const float* amp, const C2<Tg>* gt, 
 
 // ------------------------------------------------------- trace adjoint ---
 // One surface step as a function of (p_in, d_in) and the surface's
-// (z, c, k, A4, A6, A8, A10); dual numbers give its Jacobian columns.
-constexpr int kNT = 13;
+// (z, c, k, A4, A6, A8, A10); dual numbers give its Jacobian columns (kNT).
 
 static __global__ __launch_bounds__(256) void k_trace_bwd(const DevCfg* cfg, const DevPair* pairs,
                                                    const DevLive* live, const double* st,
@@ -323,10 +491,13 @@ static __global__ __launch_bounds__(256) void k_trace_bwd(const DevCfg* cfg, con
   if (active && st[7 * n_total + gid] != 0.0) {
     const int pair = (int)(gid / cfg->R2);
     const DevPair& pr = pairs[pair];
-    double gp[3], gd[3];
+    double gp[3], gd[3], gu[3], gv[3], gtq[3];
     for (int i = 0; i < 3; ++i) {
       gp[i] = raygrad[i * n_total + gid];
       gd[i] = raygrad[(3 + i) * n_total + gid];
+      gu[i] = raygrad[(8 + i) * n_total + gid];
+      gv[i] = raygrad[(11 + i) * n_total + gid];
+      gtq[i] = raygrad[(14 + i) * n_total + gid];
     }
     const double gopl = raygrad[6 * n_total + gid];
     gzs = raygrad[7 * n_total + gid];
@@ -363,6 +534,32 @@ static __global__ __launch_bounds__(256) void k_trace_bwd(const DevCfg* cfg, con
         double v = gopl * dopl.d[k];
         for (int i = 0; i < 3; ++i) v += gp[i] * q[i].d[k] + gd[i] * d[i].d[k];
         gin[k] = v;
+      }
+      if (s == sd && !cfg->planar) {
+        // the tangent frame at the hit of a curved DOE: n from the sag gradient,
+        // u the normalised projection of x on the tangent plane, v = n x u
+        D n[3], u[3], v[3];
+        surface_normal(sf, q[0], q[1], n);
+        D ux = 1.0 - n[0] * n[0], uy = -(n[0] * n[1]), uz = -(n[0] * n[2]);
+        const D iu = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+        u[0] = ux * iu; u[1] = uy * iu; u[2] = uz * iu;
+        v[0] = n[1] * u[2] - n[2] * u[1];
+        v[1] = n[2] * u[0] - n[0] * u[2];
+        v[2] = n[0] * u[1] - n[1] * u[0];
+        for (int k = 0; k < kNT; ++k) {
+          // rotation of the frame induced by input k: w = (a x da) / 2 summed over u, v, n
+          double w[3] = {0.0, 0.0, 0.0}, g = 0.0;
+          const D* fr[3] = {u, v, n};
+          for (int f = 0; f < 3; ++f) {
+            const D* a3 = fr[f];
+            w[0] += a3[1].v * a3[2].d[k] - a3[2].v * a3[1].d[k];
+            w[1] += a3[2].v * a3[0].d[k] - a3[0].v * a3[2].d[k];
+            w[2] += a3[0].v * a3[1].d[k] - a3[1].v * a3[0].d[k];
+          }
+          for (int i = 0; i < 3; ++i)
+            g += gu[i] * u[i].d[k] + gv[i] * v[i].d[k] + 0.5 * gtq[i] * w[i];
+          gin[k] += g;
+        }
       }
       for (int i = 0; i < 3; ++i) { gp[i] = gin[i]; gd[i] = gin[3 + i]; }
       for (int f = 0; f < 7; ++f) gsurf[s][f] += gin[6 + f];

@@ -650,7 +650,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   __syncthreads();
   const int N = cfg.N, t = threadIdx.x, emit = a.emit;
   const double inv_m2 = 1.0 / ((double)M * M);
-  unsigned long long n_sec = 0, n_alive = 0;
+  unsigned long long n_sec = 0, n_alive = 0, n_lost = 0, n_evan = 0, n_bins = 0;
   // rays in work-list order; the class, alive flag and context word (thread
   // t < kCtxWords) of the next ray are loaded while the current one runs
   const int cnt = itr.count();
@@ -693,6 +693,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const int P = c.P;
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
+      if (t < M) {
+        const Span sp = s.span[t];
+        n_evan += (unsigned long long)(M - (sp.hi >= sp.lo ? sp.hi - sp.lo + 1 : 0));
+      }
+      n_bins += t == 0 ? (unsigned long long)M * M : 0ull;
       if (cfg.sampling == 2) {
         // slots beyond this class's M^2 bins (classes smaller than the largest)
         for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_none<Tg>(a, slot0 + Lb);
@@ -700,8 +705,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
           Tp phi0, wx, wy; double dza; Secondary sec;
           const Span sp = s.span[jx + M / 2];
-          if (jy < sp.lo || jy > sp.hi ||
-              !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
+          const bool prop = jy >= sp.lo && jy <= sp.hi;
+          if (!prop || !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
+            n_lost += prop;
             put_none<Tg>(a, slot0 + Lb);
             continue;
           }
@@ -749,7 +755,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           }
         }
         Tp phi0, wx, wy; double dza; Secondary sec;
-        if (ok) ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
+        if (ok) {
+          ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
+          n_lost += !ok;
+        }
         if (!ok) {
           put_none<Tg>(a, slot0 + i);
           continue;
@@ -762,8 +771,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
     }
   }
   if (a.stats) {
-    if (n_alive) atomicAdd(&a.stats[0], n_alive);
-    if (n_sec) atomicAdd(&a.stats[1], n_sec);
+    if (n_alive) atomicAdd(&a.stats[RW_ST_ALIVE], n_alive);
+    if (n_sec) atomicAdd(&a.stats[RW_ST_SEC], n_sec);
+    if (n_lost) atomicAdd(&a.stats[RW_ST_LOST], n_lost);
+    if (n_evan) atomicAdd(&a.stats[RW_ST_EVAN], n_evan);
+    if (n_bins) atomicAdd(&a.stats[RW_ST_BINS], n_bins);
   }
 }
 
@@ -1131,7 +1143,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int jpre = !kFull && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
       int lp = -1;
       doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
-      IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0};
+      IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0, {0, 0, 0}};
       double dLdS = 0.0;
       constexpr int LPD = kTiled ? 1 : 2;   // lanes per secondary ray
       const int h = kTiled ? 0 : (t & 1);
@@ -1184,7 +1196,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 const double rr = (double)ref.re, ri = (double)ref.im;
                 ent.k = kidx;
                 ent.g = {(Tf)(rr * gU.re + ri * gU.im), (Tf)(rr * gU.im - ri * gU.re)};
-                if (a.want_lens && side) incident_from_wavelet(a, c, sec, wa, acc);
+                // with surfaces after the DOE the secondaries' geometry goes to k_post_bwd
+                if (a.want_lens && side && cfg.s_doe + 1 == cfg.n_surf)
+                  incident_from_wavelet(a, c, sec, wa, acc);
                 if constexpr (kG2) {
                   if (lead) {
                     double gds[3];
@@ -1295,7 +1309,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
               const double rr = (double)ref.re, ri = (double)ref.im;
               out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};
-              if (a.want_lens && side) incident_from_wavelet(a, c, sec, wa, acc);
+              if (a.want_lens && side && cfg.s_doe + 1 == cfg.n_surf)
+                incident_from_wavelet(a, c, sec, wa, acc);
             }
           }
           if (lead) buf[Gm::at(ky, kx)] = out;
@@ -1342,6 +1357,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       __syncthreads();
       // bilinear adjoint of the patch gather -> dL/dt, added to the block accumulator
       double gpx = 0.0, gpy = 0.0;
+      // curved DOE: the samples sit at p + s_m u + s_n v, so the position
+      // cogradient of each sample also moves u and v (xy parts)
+      double gux = 0.0, guy = 0.0, gvx = 0.0, gvy = 0.0;
       if (cfg.planar && Gm::SIZE - Gm::row(P) >= T * T) {
         // gather form: pixel (ix0 + a, iy0 + b) collects the (up to) four samples
         // whose 2 x 2 stencils contain it; no atomics
@@ -1470,6 +1488,22 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         const double flx = floor(fx), fly = floor(fy);
         const int ix = (int)flx, iy = (int)fly;
         const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
+        if (a.want_lens) {
+          // <g, dU/dq> with the bilinear interpolant's xy derivative at q
+          auto at = [&](int y, int x) {
+            return (x >= 0 && x < W && y >= 0 && y < H) ? tm[(size_t)y * W + x]
+                                                        : C2<Tf>{Tf(0), Tf(0)};
+          };
+          const C2<Tf> t00 = at(iy, ix), t01 = at(iy, ix + 1), t10 = at(iy + 1, ix),
+                       t11 = at(iy + 1, ix + 1);
+          const C2<Tf> dtx = (t01 - t00) * (Tf(1) - wy) + (t11 - t10) * wy;
+          const C2<Tf> dty = (t10 - t00) * (Tf(1) - wx) + (t11 - t01) * wx;
+          const double qx_ = ((double)gu.re * dtx.re + (double)gu.im * dtx.im) * cfg.inv_pitch;
+          const double qy_ = ((double)gu.re * dty.re + (double)gu.im * dty.im) * cfg.inv_pitch;
+          gpx += qx_; gpy += qy_;
+          gux += sm * qx_; guy += sm * qy_;
+          gvx += sn * qx_; gvy += sn * qy_;
+        }
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
 #pragma unroll
@@ -1516,24 +1550,27 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       // lens: per-wave sums of the incident-state cogradient into s.acc; lanes
       // 3..5 keep the frame they need, so that the combination can run after
       // the end-of-ray barrier while the other waves start the next ray
-      double lf = 0.0, lu = 0.0, lv = 0.0;
+      double lf = 0.0, lu = 0.0, lv = 0.0, ld = 0.0;
       if (a.want_lens) {
-        double v[7] = {acc.gp[0] + gpx, acc.gp[1] + gpy, acc.gp[2], acc.gkin[0], acc.gkin[1],
-                       acc.gopl, acc.gzs};
+        constexpr int NQ = 14;
+        double v[NQ] = {acc.gp[0] + gpx, acc.gp[1] + gpy, acc.gp[2], acc.gkin[0], acc.gkin[1],
+                        acc.gopl, acc.gzs, acc.tq[0], acc.tq[1], acc.tq[2], gux, guy, gvx, gvy};
 #pragma unroll
-        for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+        for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
         if ((t & 63) == 0)
-          for (int q = 0; q < 7; ++q) s.acc[t >> 6][q] = v[q];
+          for (int q = 0; q < NQ; ++q) s.acc[t >> 6][q] = v[q];
+        lf = c.k0 * c.n_in;
         if (t >= 3 && t < 6) {
-          lf = c.k0 * c.n_in;
           lu = c.u[t - 3];
           lv = c.v[t - 3];
         }
+        if (t >= 8 && t < 14) ld = c.d[(t - 8) % 3];
       }
       __syncthreads();   // buf, tile and pref are reused by the next ray; s.acc is complete
-      // component t < 8 of the incident-state cogradient, one lane each (s.acc
-      // is next written after several barriers of the next ray)
-      if (a.want_lens && t < 8) {
+      // component t < RW_RAYGRAD of the incident-state cogradient, one lane each
+      // (s.acc is next written after several barriers of the next ray):
+      // k_in,t = k0 n_in (d.u, d.v) feeds the direction d and the vectors u, v
+      if (a.want_lens && t < RW_RAYGRAD) {
         auto tot = [&](int q) {
           double r = 0.0;
           for (int wv = 0; wv < kDoeThreads / 64; ++wv) r += s.acc[wv][q];
@@ -1542,7 +1579,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         double out;
         if (t < 3) out = tot(t);
         else if (t < 6) out = lf * (tot(3) * lu + tot(4) * lv);
-        else out = tot(t - 1);
+        else if (t < 8) out = tot(t - 1);
+        else if (t < 11) out = (t < 10 ? tot(10 + (t - 8)) : 0.0) + lf * tot(3) * ld;
+        else if (t < 14) out = (t < 13 ? tot(12 + (t - 11)) : 0.0) + lf * tot(4) * ld;
+        else out = tot(7 + (t - 14));
         a.raygrad[(size_t)t * a.n_total + gid] = out;
       }
     }

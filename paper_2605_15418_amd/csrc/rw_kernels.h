@@ -16,7 +16,11 @@
 namespace rw {
 
 constexpr int kThreads = 256;
-#define RW_N_STATS 4           // forward counters (alive rays, secondaries, ...)
+// Forward counters: alive rays, secondaries, rays ended by cause (no hit,
+// aperture, TIR, outside the DOE), secondaries lost after the DOE, evanescent
+// and total spectrum bins of the alive rays.
+enum { RW_ST_ALIVE = 0, RW_ST_SEC = 1, RW_ST_NOHIT = 2, RW_ST_APER = 3, RW_ST_TIR = 4,
+       RW_ST_OUTSIDE = 5, RW_ST_LOST = 6, RW_ST_EVAN = 7, RW_ST_BINS = 8, RW_N_STATS = 9 };
 
 // Tt: trace; Tf: patch spectrum; Tp: optical path and wavelet phase; Tg: sensor
 // grid; Te: sine / cosine of the wavelet phase after its reduction to [0, 2 pi)
@@ -168,54 +172,88 @@ __global__ void k_zero(T* p, size_t n) {
 // --------------------------------------------------------------- k_trace ---
 // Ray state layout: st[c * n_total + ray], c = px, py, pz, dx, dy, dz, opl, alive.
 // Checkpoint s (state entering surface s, s = 0..s_doe) at ck[(s * 8 + c) * n_total + ray].
+// One count per wave and cause: the lanes whose ray ended by that cause.
+__device__ __forceinline__ void count_cause(unsigned long long* stats, int mine) {
+  for (int c = RW_ST_NOHIT; c <= RW_ST_OUTSIDE; ++c) {
+    const unsigned long long m = __ballot(mine == c);
+    if (m && (threadIdx.x & 63) == 0) atomicAdd(&stats[c], (unsigned long long)__popcll(m));
+  }
+}
+
 template <class Tt>
 __global__ __launch_bounds__(256) void k_trace(const DevCfg* cfg, const DevPair* pairs,
                                                const DevLive* live, double* st, double* ck,
-                                               size_t n_total, int pair0, int npairs) {
+                                               size_t n_total, int pair0, int npairs,
+                                               unsigned long long* stats) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int R = cfg->R, R2 = cfg->R2;
-  if (idx >= (size_t)npairs * R2) return;
-  const int pair = pair0 + (int)(idx / R2);
-  const int r = (int)(idx % R2);
-  const size_t gid = (size_t)pair * R2 + r;
-  const DevPair& pr = pairs[pair];
-  const int ix = r % R, iy = r / R;
-  const double gx = ((ix + 0.5) / R) * 2.0 - 1.0, gy = ((iy + 0.5) / R) * 2.0 - 1.0;
-  Tt p[3] = {(Tt)(pr.lc[0] + gx * cfg->launch_half), (Tt)(pr.lc[1] + gy * cfg->launch_half),
-             (Tt)cfg->launch_z};
-  Tt d[3] = {(Tt)pr.dir[0], (Tt)pr.dir[1], (Tt)pr.dir[2]};
-  Tt opl = d[0] * p[0] + d[1] * p[1] + d[2] * p[2];
-  bool alive = true;
-  const int sd = cfg->s_doe;
-  for (int s = 0; s <= sd; ++s) {
-    double* c = ck + (size_t)s * 8 * n_total;
-    c[0 * n_total + gid] = p[0]; c[1 * n_total + gid] = p[1]; c[2 * n_total + gid] = p[2];
-    c[3 * n_total + gid] = d[0]; c[4 * n_total + gid] = d[1]; c[5 * n_total + gid] = d[2];
-    c[6 * n_total + gid] = opl; c[7 * n_total + gid] = alive ? 1.0 : 0.0;
-    if (!alive) break;
-    const DevSurf& ds = live->s[s];
-    const Surf<Tt> sf = surf_of<Tt>(ds);
-    Tt t;
-    if (!intersect(sf, p, d, t)) { alive = false; break; }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) p[i] += t * d[i];
-    opl += (Tt)pr.n_med[s] * t;
-    if (ds.semi_ap > 0 && (double)(p[0] * p[0] + p[1] * p[1]) > ds.semi_ap * ds.semi_ap) {
-      alive = false; break;
+  const bool in_range = idx < (size_t)npairs * R2;
+  int cause = -1;
+  if (in_range) {
+    const int pair = pair0 + (int)(idx / R2);
+    const int r = (int)(idx % R2);
+    const size_t gid = (size_t)pair * R2 + r;
+    const DevPair& pr = pairs[pair];
+    const int ix = r % R, iy = r / R;
+    const double gx = ((ix + 0.5) / R) * 2.0 - 1.0, gy = ((iy + 0.5) / R) * 2.0 - 1.0;
+    Tt p[3] = {(Tt)(pr.lc[0] + gx * cfg->launch_half), (Tt)(pr.lc[1] + gy * cfg->launch_half),
+               (Tt)cfg->launch_z};
+    Tt d[3] = {(Tt)pr.dir[0], (Tt)pr.dir[1], (Tt)pr.dir[2]};
+    Tt opl = d[0] * p[0] + d[1] * p[1] + d[2] * p[2];
+    bool alive = true;
+    const int sd = cfg->s_doe;
+    for (int s = 0; s <= sd; ++s) {
+      double* c = ck + (size_t)s * 8 * n_total;
+      c[0 * n_total + gid] = p[0]; c[1 * n_total + gid] = p[1]; c[2 * n_total + gid] = p[2];
+      c[3 * n_total + gid] = d[0]; c[4 * n_total + gid] = d[1]; c[5 * n_total + gid] = d[2];
+      c[6 * n_total + gid] = opl; c[7 * n_total + gid] = alive ? 1.0 : 0.0;
+      if (!alive) break;
+      const DevSurf& ds = live->s[s];
+      const Surf<Tt> sf = surf_of<Tt>(ds);
+      Tt t;
+      if (!intersect(sf, p, d, t)) { alive = false; cause = RW_ST_NOHIT; break; }
+  #pragma unroll
+      for (int i = 0; i < 3; ++i) p[i] += t * d[i];
+      opl += (Tt)pr.n_med[s] * t;
+      if (ds.semi_ap > 0 && (double)(p[0] * p[0] + p[1] * p[1]) > ds.semi_ap * ds.semi_ap) {
+        alive = false; cause = RW_ST_APER; break;
+      }
+      if (s == sd) break;
+      Tt nrm[3];
+      surface_normal(sf, p[0], p[1], nrm);
+      if (!refract(d, nrm, (Tt)(pr.n_med[s] / pr.n_med[s + 1]))) {
+        alive = false; cause = RW_ST_TIR; break;
+      }
     }
-    if (s == sd) break;
-    Tt nrm[3];
-    surface_normal(sf, p[0], p[1], nrm);
-    if (!refract(d, nrm, (Tt)(pr.n_med[s] / pr.n_med[s + 1]))) { alive = false; break; }
+    if (alive) {
+      const double fx = ((double)p[0] - cfg->x0) / cfg->pitch;
+      const double fy = ((double)p[1] - cfg->y0) / cfg->pitch;
+      alive = fx >= -0.5 && fx <= cfg->W - 0.5 && fy >= -0.5 && fy <= cfg->H - 0.5;
+      if (!alive) cause = RW_ST_OUTSIDE;
+    }
+    st[0 * n_total + gid] = p[0]; st[1 * n_total + gid] = p[1]; st[2 * n_total + gid] = p[2];
+    st[3 * n_total + gid] = d[0]; st[4 * n_total + gid] = d[1]; st[5 * n_total + gid] = d[2];
+    st[6 * n_total + gid] = opl; st[7 * n_total + gid] = alive ? 1.0 : 0.0;
   }
-  if (alive) {
-    const double fx = ((double)p[0] - cfg->x0) / cfg->pitch;
-    const double fy = ((double)p[1] - cfg->y0) / cfg->pitch;
-    alive = fx >= -0.5 && fx <= cfg->W - 0.5 && fy >= -0.5 && fy <= cfg->H - 0.5;
+  if (stats) count_cause(stats, cause);
+}
+
+// NaN / Inf anywhere in the inputs of a forward (flag[0] set to 1).
+static __global__ void k_check_finite(const float* a, size_t na, const float* b, size_t nb,
+                                      const float* c, size_t nc, const float* d, size_t nd,
+                                      unsigned int* flag) {
+  const size_t n = na + nb + nc + nd;
+  bool bad = false;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    float v;
+    if (i < na) v = a[i];
+    else if (i < na + nb) v = b[i - na];
+    else if (i < na + nb + nc) v = c[i - na - nb];
+    else v = d[i - na - nb - nc];
+    bad |= !isfinite(v);
   }
-  st[0 * n_total + gid] = p[0]; st[1 * n_total + gid] = p[1]; st[2 * n_total + gid] = p[2];
-  st[3 * n_total + gid] = d[0]; st[4 * n_total + gid] = d[1]; st[5 * n_total + gid] = d[2];
-  st[6 * n_total + gid] = opl; st[7 * n_total + gid] = alive ? 1.0 : 0.0;
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
 }
 
 // ------------------------------------------------------------- DOE stage ---
@@ -241,7 +279,8 @@ struct DoeArgs {
   // backward-only
   const void* adj;           // C2<Tg> adjoint grid
   void* gt;                  // C2<Tg> [H][W] cogradient of t
-  double* raygrad;           // [8][n_total] cogradients of the incident state
+  double* raygrad;           // [RW_RAYGRAD][n_total] cogradients of the incident state
+  double* lensg;             // per-surface sums of the lens-parameter cogradient
   int want_lens;
   void* acc;                 // C2<Tg> [blocks][acc_side][acc_side] block-private dL/dt
   int acc_side;

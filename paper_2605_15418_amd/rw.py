@@ -62,16 +62,20 @@ class rw_config(ctypes.Structure):
                 ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("grad", ctypes.c_int), ("tau", ctypes.c_double),
                 ("n_patch_class", ctypes.c_int), ("patch_class_p", ctypes.c_int * 3),
-                ("curv_eps", ctypes.c_double)]
+                ("curv_eps", ctypes.c_double), ("check_finite", ctypes.c_int)]
 
 
 class rw_profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * len(STAGES)), ("launches", ctypes.c_uint64 * len(STAGES))]
 
 
+STATS = ("rays_total", "rays_alive", "secondaries", "killed_no_hit", "killed_aperture",
+         "killed_tir", "killed_outside_doe", "secondaries_lost", "evanescent_bins",
+         "spectrum_bins")
+
+
 class rw_stats(ctypes.Structure):
-    _fields_ = [("rays_total", ctypes.c_uint64), ("rays_alive", ctypes.c_uint64),
-                ("secondaries", ctypes.c_uint64)]
+    _fields_ = [(name, ctypes.c_uint64) for name in STATS]
 
 
 _lib = None
@@ -142,7 +146,7 @@ class Plan:
     """
 
     def __init__(self, system, cfg, precision="mixed", batched=True, spread_width=0,
-                 device="cuda"):
+                 device="cuda", check_finite=False):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the ray-wave library runs on the GPU only")
@@ -206,6 +210,7 @@ class Plan:
         for i, q in enumerate(extra):
             c.patch_class_p[i] = q
         c.curv_eps = float(cfg.get("curv_eps", 0.1))
+        c.check_finite = int(bool(check_finite))
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
                                                  len(prm), ctypes.byref(c), ctypes.byref(h)))
@@ -274,8 +279,7 @@ class Plan:
     def stats(self):
         s = rw_stats()
         _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
-        return {"rays_total": s.rays_total, "rays_alive": s.rays_alive,
-                "secondaries": s.secondaries}
+        return {name: getattr(s, name) for name in STATS}
 
     def autotune(self):
         """Pick the fastest launch shape of the DOE kernels on the inputs of the last

@@ -335,3 +335,45 @@ def test_mixed_p64_own_draws_agree(rw):
     gi = idx.cpu().numpy()
     J = np.stack([aux[p]["J"] for p in sorted(aux)])
     assert (gi == J).mean() >= 0.97
+
+
+# ----------------------------------------------------- counters and checks ---
+def test_stats_count_ended_rays_by_cause_and_evanescent_bins(rw):
+    """Rays launched past the lens aperture and past the DOE map end by those
+    causes; the other counters against the oracle: alive rays equal, and the
+    evanescent bins of the alive rays' spectra equal the oracle's count (FP64
+    form: its propagation test is the same FP64 comparison)."""
+    system, cfg, maps = small_singlet(sampling="full", rays=32, P=8)
+    cfg["launch_half"] *= 10.0                 # well past the map, corners past the lens rim
+    plan, psf, _ = _run(rw, system, cfg, maps, "fp64")
+    st = plan.stats()
+    ref, aux = oracle_psf(system, cfg, maps, values=oracle_param_values(system), keep=True)
+    alive = aux[0]["alive"].numpy()
+    prop = aux[0]["prop"].numpy()
+    print(st)
+    assert st["rays_alive"] == int(alive.sum())
+    assert st["killed_aperture"] > 0 and st["killed_outside_doe"] > 0
+    assert st["rays_total"] == (st["rays_alive"] + st["killed_no_hit"] + st["killed_aperture"] +
+                                st["killed_tir"] + st["killed_outside_doe"])
+    M = cfg["patch_p"] * cfg["pad"]
+    assert st["spectrum_bins"] == int(alive.sum()) * M * M
+    assert st["evanescent_bins"] == int(alive.sum()) * M * M - int(prop.sum())
+    # FULL mode: every propagating bin becomes a secondary or is lost on the way
+    assert st["secondaries"] + st["secondaries_lost"] == int(prop.sum())
+
+
+def test_check_finite_refuses_nan_inputs(rw):
+    system, cfg, maps = small_singlet(rays=4)
+    plan = rw.Plan(system, cfg, precision="fp64", check_finite=True)
+    vals, ph, am = gpu_inputs(system, maps)
+    plan.forward(vals, ph, am)                                   # clean inputs pass
+    bad = ph.clone()
+    bad[3, 5] = float("nan")
+    with pytest.raises(rw.RWError, match="RW_ERR_NONFINITE"):
+        plan.forward(vals, bad, am)
+    am2 = am.clone()
+    am2[0, 0] = float("inf")
+    with pytest.raises(rw.RWError, match="RW_ERR_NONFINITE"):
+        plan.forward(vals, ph, am2)
+    with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
+        plan.backward(torch.ones((1, 1, plan.Q, plan.Q), device="cuda"))

@@ -289,15 +289,24 @@ def paraxial_pupil(surfs, z_stop, lam):
 # ----------------------------------------------------------------------------
 def conformal_sphere(rays_side=128, H=2048, pitch=0.0005, P=128, classes=(64, 32), N=256,
                      Q=256, psf_pitch=0.001, n_lambda=31, n_field_side=5, max_deg=20.0,
-                     sampling="mag", curv_eps=0.0082, A4=0.2, seed=0, cfg_id=4):
+                     sampling="mag", curv_eps=0.0082, A4=0.2, seed=0, with_params=False,
+                     cfg_id=4):
     R, ct = 30.0, 4.0
     surfs = [surface(0.0, c=1 / R, A=(A4, 0.0, 0.0, 0.0), semi_ap=6.0, medium=BK7, doe=True),
              surface(ct, medium=AIR)]
     surfs[0]["kind"] = "asphere"
     n_d = BK7[0] + BK7[1] / (LAM_D * 1e3) ** 2
     bfl = R / (n_d - 1) - ct / n_d
+    params = []
+    if with_params:        # the DOE surface's shape, the rear face's curvature, both gaps
+        r_fp = 0.5 * H * pitch
+        params = [{"surface": 0, "field": "curv", "scale": 1 / R},
+                  {"surface": 0, "field": "A4", "scale": LAM_D / r_fp ** 4},
+                  {"surface": 1, "field": "curv", "scale": 1 / R},
+                  {"surface": 0, "field": "gap", "scale": 1.0},
+                  {"surface": 1, "field": "gap", "scale": 1.0}]
     system = {"surfaces": surfs, "sensor_z": ct + bfl, "doe": doe_desc(H, H, pitch),
-              "params": []}
+              "params": params}
     lambdas = list(np.linspace(400e-6, 700e-6, n_lambda)) if n_lambda > 1 else [LAM_D]
     fields = field_grid(max_deg, n_field_side)
     half = 0.5 * H * pitch * (1 - 1.0 / rays_side)
@@ -380,6 +389,49 @@ def two_lens_hybrid(rays_side=512, H=4096, pitch=0.0005, P=128, classes=(64,), N
                 target[l, f] = airy_target(Q, psf_pitch, lambdas[l], NA, (0.0, 0.0),
                                            rng_t.uniform(-8, 8, 2))
     maps = {"phase": phase.astype(np.float32), "amp": amp.astype(np.float32), "target": target}
+    return system, cfg, maps
+
+
+# ----------------------------------------------------------------------------
+# DOE upstream of refractive optics (the benchmark's System 1 shape): a planar
+# blazed linear grating of period `period_px` pixels at 6.3 um pitch, the stop,
+# 3 mm before a BK7 plano-convex of f = 50 mm (R 25.8 convex side first, CT
+# 5.3, the catalogue LA1131 shape), sensor at the back focus; 0.7 um light,
+# collimated on axis.  Every secondary ray crosses both lens surfaces.
+# Lens parameters: the front curvature, the DOE-lens gap, CT and back distance.
+# ----------------------------------------------------------------------------
+def grating_before_lens(rays_side=64, H=512, pitch=0.0063, period_px=35, lam=700e-6, P=32, N=256,
+                        Q=128, psf_pitch=0.002, sampling="mag", field_deg=0.0, seed=0,
+                        with_target=True, cfg_id=6):
+    R, ct, gap = 25.8, 5.3, 3.0
+    surfs = [surface(0.0, doe=True),
+             surface(gap, c=1 / R, semi_ap=12.7, medium=BK7),
+             surface(gap + ct, semi_ap=12.7, medium=AIR)]
+    n = BK7[0] + BK7[1] / (lam * 1e3) ** 2
+    bfl = R / (n - 1) - ct / n
+    system = {"surfaces": surfs, "sensor_z": gap + ct + bfl, "doe": doe_desc(H, H, pitch),
+              "params": [{"surface": 1, "field": "curv", "scale": 1 / R},
+                         {"surface": 0, "field": "gap", "scale": 1.0},
+                         {"surface": 1, "field": "gap", "scale": 1.0},
+                         {"surface": 2, "field": "gap", "scale": 1.0}]}
+    t = math.tan(math.radians(field_deg))
+    fields = [[t, 0.0]]
+    half = 0.5 * H * pitch * (1 - 1.0 / rays_side)
+    efl = R / (n - 1)
+    cfg = _cfg([lam], fields, 0.0, -1.0, half, rays_side, Q, psf_pitch, 0.0, P, N, sampling,
+               seed=seed)
+    # sensor window on the first diffraction order (the blaze puts the light there)
+    cfg["psf_center"] = [[[efl * math.tan(math.asin(lam / (period_px * pitch)) + math.atan(t)),
+                           0.0]]]
+    x = system["doe"]["x0"] + np.arange(H) * pitch
+    phase = np.mod(2 * math.pi * x / (period_px * pitch), 2 * math.pi)
+    phase = np.broadcast_to(phase[None, :], (H, H)).astype(np.float32).copy()
+    target = None
+    if with_target:
+        rng_t = np.random.default_rng(20260200 + cfg_id)
+        target = airy_target(Q, psf_pitch, lam, 0.5 * H * pitch / bfl, (0.0, 0.0),
+                             rng_t.uniform(-4, 4, 2))[None, None].astype(np.float32)
+    maps = {"phase": phase, "amp": np.ones((H, H), dtype=np.float32), "target": target}
     return system, cfg, maps
 
 
