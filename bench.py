@@ -1,22 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the forward + backward ray-wave hybrid PSF on one MI355X.
 
-Workload (synthetic, seeded): equiconvex BK7 even-asphere singlet (f = 25 mm,
-random A4/A6) followed by a planar 1024 x 1024 random holographic complex DOE
-at 1 um pitch; 3 wavelengths x 3 x 3 field angles (+-10 deg) x 256 x 256
-incident rays per pair; 64 x 64 DOE patches zero-padded to 128 x 128; 256
-secondary rays per incident ray (p ~ |U~|); 512 x 512 PSF per pair; Eq. 5
-loss against seeded Airy targets; gradients w.r.t. the 1024 x 1024 phase and
-amplitude maps and 6 lens parameters.
+Headline workload (synthetic, seeded; the largest configuration of the
+benchmark set, end-to-end hybrid design): BK7 and F2 even-asphere lenses with
+a 4096 x 4096 complex DOE at 0.5 um on the second lens's rear asphere (the
+stop); 8 wavelengths x 16 field angles (4 x 4 up to +-25 deg) x 512 x 512
+incident rays per pair; patch classes 128 / 64 by the curvature bound (Eq. 4),
+zero-padded to 256 / 128; 256 secondary rays per incident ray (p ~ |U~|);
+1024 x 1024 PSF per pair; Eq. 5 loss against seeded Airy targets; gradients
+w.r.t. the phase and amplitude maps and 14 lens parameters.
 
-One step = rw_forward (with the loss) + rw_backward over all 27 pairs, inputs
-resident in HBM.  value = incident rays traced per second (27 x 65536 per step).
+One step = rw_forward_backward (forward, Eq. 5 loss and backward, fused per
+launch group of pairs) over all 128 pairs, inputs resident in HBM, batched
+MIXED form (persistent launches over all pairs, launch shapes from the
+autotuner, the whole sequence replayed as a HIP graph).  value = incident
+rays traced per second (128 x 512^2 per step).
 
-Also reported: the plain FP32 form (same kernels, FP32 everywhere, one launch
-per pair), the PSF / gradient error of the measured form against the FP64 form
-on the same sample indices, per-stage kernel time from HIP events, the
-roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+Beside it, on the asphere-singlet + 1024^2 hologram system (27 pairs x 256^2
+rays, P 64, N 256, Q 512): the same step with the per-kernel rooflines, the
+plain FP32 comparator (same kernels, FP32 everywhere, one launch per pair),
+the error of the measured form against the FP64 form on the same draws, the
+Gumbel-softmax straight-through gradient, and forward-only rates of the
+other workloads.  The FP64 CPU oracle is timed on bounded samples of the
+headline and of the singlet system on the host cores.
 """
 import argparse
 import hashlib
@@ -36,7 +42,7 @@ CSRC = os.path.join(ROOT, "paper_2605_15418_amd", "csrc")
 # sources compiled into the MIXED DOE kernels
 DOE_SOURCES = ("rw_common.h", "rw_fft.h", "rw_kernels.h", "rw_backward.h", "rw_doe.h",
                "rw_doe_mixed.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "doe_bwd_traffic_asphere_hologram.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def doe_source_hash():
@@ -47,19 +53,20 @@ def doe_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (already scaled by the copy-kernel calibration), if they
-    were taken on the current kernel sources; else None."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (profiles/<kernel>_traffic_<workload>.md, already scaled
+    by the copy-kernel calibration) if it was taken on the current kernel
+    sources; else None."""
+    path = os.path.join(PROFILES, f"{kernel}_traffic_{workload}.md")
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             text = f.read()
     except OSError:
         return None
     m_src = re.search(r"kernel sources sha256\[:16\]: `([0-9a-f]+)`", text)
-    m_k = re.search(r"kernel: `([a-z_]+)`", text)
     m_b = re.search(r"HBM bytes per launch \(calibrated\): `([0-9.eE+]+)`", text)
-    if not (m_src and m_k and m_b) or m_k.group(1) != kernel or m_src.group(1) != doe_source_hash():
+    if not (m_src and m_b) or m_src.group(1) != doe_source_hash():
         return None
     return float(m_b.group(1))
 
@@ -79,37 +86,74 @@ def copy_calibration(nbytes):
           flush=True)
 
 
-def doe_fwd_flops_per_ray(P, M, N):
-    """Algorithmic flops of the ray-wave interface for one incident ray: the
-    zero-padded 2-D FFT, bilinear patch gather, |U~| / cut / CDF, N draws,
-    N emissions with their FP64 phase and free-space step."""
-    return (5 * M * M * math.log2(M * M) + 14 * P * P + 8 * M * M
-            + N * (40 + math.log2(M * M)) + 120 * N)
-
-
-def doe_bwd_flops_per_ray(P, M, N, w):
-    """Recomputed forward FFT (the draws and their normaliser are the
-    forward's, not recomputed), the inverse FFT of the spectrum cogradient,
-    bilinear adjoint, and per draw the type-2 interpolation of the value and
-    its two frequency derivatives."""
-    return (2 * 5 * M * M * math.log2(M * M) + 2 * 14 * P * P
-            + 240 * N + N * 3 * 8 * w * w)
-
-
-def spread_flops_per_record(w):
+# ----------------------------------------------------- algorithmic work ---
+# Per incident ray, the forward's algorithmic flops F of the hot-path model:
+#   5 M^2 log2 M^2 (patch FFT) + 14 P^2 (bilinear gather) + 8 M^2 (|U~|, cut,
+#   CDF) + N (40 + log2 M^2) (draws) + 120 N (emission, FP64 phase, free-space
+#   step) + N (8 w^2 + 20 w) (ES-kernel spreading);
+# the backward is 1.1 F (inverse FFT, type-2 interpolation, bilinear scatter).
+# Kernels: the forward DOE kernel does F without the spreading, the spreading
+# kernel 8 w^2 + 20 w per record, the tiled interpolation the same per record
+# (the backward's share of the type-2 NUFFT), and the DOE adjoint 1.1 F minus
+# that interpolation share.  Recomputations (the adjoint redoes the forward
+# transform) are not the method's work and are not counted.
+def spread_flops(w):
     return 8 * w * w + 20 * w
+
+
+def forward_flops_per_ray(P, M, N, w):
+    return (5 * M * M * math.log2(M * M) + 14 * P * P + 8 * M * M
+            + N * (40 + math.log2(M * M)) + 120 * N + N * spread_flops(w))
+
+
+def kernel_flops(stats, classes, pad, N, w):
+    """Algorithmic flops per launch of the DOE forward, DOE adjoint, spreading and
+    interpolation kernels, summed over the patch classes (alive rays per class)."""
+    fwd = bwd = 0.0
+    for c, P in enumerate(classes):
+        n = stats["rays_by_class"][c]
+        F = forward_flops_per_ray(P, pad * P, N, w)
+        fwd += n * (F - N * spread_flops(w))
+        bwd += n * (1.1 * F - N * spread_flops(w))
+    rec = stats["secondaries"]
+    return {"doe_fwd": fwd, "doe_bwd": bwd, "spread": rec * spread_flops(w),
+            "interp": rec * spread_flops(w)}
+
+
+def rooflines(prof, steps, flops):
+    """Achieved algorithmic TFLOP/s of each kernel over its mean launch time (HIP
+    events on the plan's stream) against the FP32 vector peak."""
+    out = {}
+    for k, f in flops.items():
+        ms, n = prof[k]
+        if n == 0 or ms <= 0:
+            continue
+        per_launch_ms = ms / n
+        launches_per_step = n / steps
+        ach = f / launches_per_step / (per_launch_ms * 1e-3) / 1e12
+        out[k] = {"launch_ms": round(per_launch_ms, 3), "achieved": round(ach, 3),
+                  "frac": round(ach / PEAK_FP32_VECTOR_TFLOPS, 4),
+                  "algorithmic_flop_per_launch": f / launches_per_step}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--steps", type=int, default=1, help="timed steps of the headline")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="two_lens_hybrid",
+                    choices=("two_lens_hybrid", "asphere_hologram"))
+    ap.add_argument("--side-steps", type=int, default=3, help="timed steps of the side system")
+    ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--g2-steps", type=int, default=1,
                     help="fwd+bwd steps timed with the Gumbel-softmax straight-through gradient")
+    ap.add_argument("--no-side", action="store_true", help="headline only")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 error check")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forward-only", action="store_true",
+                    help="skip the forward-only rates of the other workloads")
+    ap.add_argument("--no-graph", action="store_true", help="eager launches (no HIP graphs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -131,124 +175,204 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    system, cfg, maps = W.asphere_hologram()
-    L, F = len(cfg["lambdas"]), len(cfg["fields"])
-    n_rays = L * F * cfg["rays_side"] ** 2
-    P, M, N, Q = cfg["patch_p"], cfg["patch_p"] * cfg["pad"], cfg["n_ssr"], cfg["psf_q"]
-    from_params = []
-    for ref in system["params"]:
-        s, f = ref["surface"], ref["field"]
-        surf = system["surfaces"][s]
-        phys = surf["c"] if f == "curv" else surf["A"][("A4", "A6", "A8", "A10").index(f)]
-        from_params.append(phys / ref["scale"])
-    vals = torch.tensor(np.array(from_params, dtype=np.float32), device=dev)
-    ph = torch.tensor(maps["phase"], device=dev)
-    am = torch.tensor(maps["amp"], device=dev)
-    tg = torch.tensor(maps["target"], device=dev)
 
-    def step(plan, replay=None):
-        plan.forward(vals, ph, am, target=tg, replay=replay)
-        return plan.backward()
+    def inputs(system, maps):
+        vals = []
+        for ref in system["params"]:
+            s, f = ref["surface"], ref["field"]
+            surf = system["surfaces"][s]
+            if f == "curv":
+                phys = surf["c"]
+            elif f == "gap":
+                znext = (system["surfaces"][s + 1]["z"] if s + 1 < len(system["surfaces"])
+                         else system["sensor_z"])
+                phys = znext - surf["z"]
+            else:
+                phys = surf["A"][("A4", "A6", "A8", "A10").index(f)]
+            vals.append(phys / ref["scale"])
+        v = torch.tensor(np.array(vals, dtype=np.float32), device=dev)
+        ph = torch.tensor(maps["phase"], device=dev)
+        am = torch.tensor(maps["amp"], device=dev)
+        tg = None if maps["target"] is None else torch.tensor(maps["target"], device=dev)
+        return v, ph, am, tg
 
-    # ---------------------------------------------------------------- batched
-    log("building the batched MIXED plan")
-    plan = rw.Plan(system, cfg, precision="mixed", batched=True)
-    for _ in range(args.warmup):
-        step(plan)
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(plan)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = plan.profile()
-    plan.set_profiling(False)
-    stats = plan.stats()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n_rays * args.steps / (t1 - t0)
-    log(f"batched MIXED: {ms_per_step:.1f} ms/step, {value:.3e} rays/s")
+    def classes_of(cfg):
+        return sorted({int(cfg["patch_p"])} | {int(q) for q in cfg.get("patch_classes", [])},
+                      reverse=True)
 
-    # roofline of the dominant kernel (algorithmic flops / measured kernel time)
-    w = 7
-    alive = stats["rays_alive"]
-    records = stats["secondaries"]
-    flops = {
-        "doe_fwd": alive * doe_fwd_flops_per_ray(P, M, N),
-        "doe_bwd": alive * doe_bwd_flops_per_ray(P, M, N, w),
-        "spread": records * spread_flops_per_record(w),
-    }
-    per_launch_ms = {k: prof[k][0] / max(prof[k][1], 1) for k in prof}
-    dom = max(flops, key=lambda k: per_launch_ms[k])
-    achieved = flops[dom] / (per_launch_ms[dom] * 1e-3) / 1e12
-    traffic = measured_traffic(dom)
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": traffic,
-                "kernel_sources": doe_source_hash(),
-                "launch_ms": round(per_launch_ms[dom], 3),
-                "algorithmic_flop_per_launch": flops[dom]}
+    def measured_step(name, system, cfg, maps, steps, warmup):
+        """Batched MIXED fwd+bwd: autotuned launch shapes (cached per arch and
+        geometry), one eager profiled warm-up step (per-stage HIP events), then
+        the timed steps replayed as HIP graphs."""
+        v, ph, am, tg = inputs(system, maps)
+        L, F = len(cfg["lambdas"]), len(cfg["fields"])
+        n_rays = L * F * cfg["rays_side"] ** 2
+        plan = rw.Plan(system, cfg, precision="mixed", batched=True)
+        log(f"{name}: workspace {plan.ws_bytes / 2**30:.1f} GiB; autotune")
+        plan.forward(v, ph, am, target=tg)
+        shape = plan.autotune(cache=rw.rw.AUTOTUNE_CACHE)
+        bufs = {"psf": torch.empty((L, F, cfg["psf_q"], cfg["psf_q"]), device=dev),
+                "loss": torch.empty(1, device=dev), "dp": torch.empty_like(ph),
+                "da": torch.empty_like(am), "dl": torch.empty_like(v)}
 
-    # ------------------------------------------------------------ plain FP32
-    plain, plain_rec = None, None
-    if args.plain_steps > 0:
-        log("plain FP32 form (one launch per pair)")
-        plain = rw.Plan(system, cfg, precision="fp32", batched=False)
-        step(plain)
+        def step():                               # rw_forward_backward: the fused step
+            plan.step(v, ph, am, tg, psf_out=bufs["psf"], loss_out=bufs["loss"],
+                      d_phase=bufs["dp"], d_amp=bufs["da"], d_lens=bufs["dl"])
+
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        t0 = time.perf_counter()
+        step()                                     # eager, profiled: the per-kernel times
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t0) * 1e3
+        prof = plan.profile()
+        plan.set_profiling(False)
+        stats = plan.stats()
+        if not args.no_graph:
+            plan.set_graph(True)
+        for _ in range(max(0, warmup - 1) + (0 if args.no_graph else 1)):
+            step()                                 # records the graphs, then replays
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / steps
+        value = n_rays * steps / (t1 - t0)
+        w = 7
+        cls = classes_of(cfg)
+        flops = kernel_flops(stats, cls, cfg["pad"], cfg["n_ssr"], w)
+        roof = rooflines(prof, 1, flops)
+        log(f"{name}: {ms:.1f} ms/step ({value:.3e} rays/s), eager profiled step {eager_ms:.1f} ms")
+        rec = {"value": value, "unit": "rays/s", "ms_per_step": ms, "steps": steps,
+               "eager_profiled_ms_per_step": eager_ms, "launch_shape": list(shape),
+               "incident_rays_per_step": n_rays, "secondary_rays_per_step": stats["secondaries"],
+               "secondary_rays_per_s": stats["secondaries"] / (ms * 1e-3),
+               "stages_ms_per_step": {k: round(v_[0], 3) for k, v_ in prof.items()},
+               "kernel_rooflines": roof, "stats": stats}
+        return plan, rec, (v, ph, am, tg)
+
+    # ----------------------------------------------------------- headline
+    log(f"building the {args.workload} workload")
+    system, cfg, maps = W.workload(args.workload)
+    plan, head, head_in = measured_step(args.workload, system, cfg, maps, args.steps,
+                                        args.warmup)
+    roof = head["kernel_rooflines"]
+    dom = max(roof, key=lambda k: roof[k]["launch_ms"])
+    roofline = {"bound": "alu", "kernel": dom, "achieved": roof[dom]["achieved"],
+                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": roof[dom]["frac"],
+                "traffic": measured_traffic(dom, args.workload),
+                "kernel_sources": doe_source_hash(), "launch_ms": roof[dom]["launch_ms"],
+                "algorithmic_flop_per_launch": roof[dom]["algorithmic_flop_per_launch"],
+                "per_kernel": {k: {"frac": r["frac"], "achieved": r["achieved"],
+                                   "launch_ms": r["launch_ms"]} for k, r in roof.items()},
+                "launch_ms_from": "HIP events on the plan's stream, eager profiled step"}
+    del plan
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------ the asphere-hologram system
+    side = None
+    if not args.no_side and args.workload != "asphere_hologram":
+        s3, c3, m3 = W.asphere_hologram()
+        p3, side, (v3, ph3, am3, tg3) = measured_step("asphere_hologram", s3, c3, m3,
+                                                      args.side_steps, 1)
+        side["workload"] = ("asphere singlet f=25 mm + 1024^2 random complex DOE @1 um; "
+                            "3 lambda x 3x3 fields (+-10 deg) x 256^2 rays; P=64 (M=128), "
+                            "N=256 (p_mag), Q=512; Eq. 5 loss; fwd+bwd (G1)")
+        n3 = len(c3["lambdas"]) * len(c3["fields"]) * c3["rays_side"] ** 2
+
+        def step(pl, replay=None):
+            pl.forward(v3, ph3, am3, target=tg3, replay=replay)
+            return pl.backward()
+
+        if args.plain_steps > 0:
+            log("plain FP32 form (one launch per pair)")
+            plain = rw.Plan(s3, c3, precision="fp32", batched=False)
             step(plain)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        plain_value = n_rays * args.plain_steps / (t1 - t0)
-        plain_rec = {"value": plain_value, "ms_per_step": (t1 - t0) * 1e3 / args.plain_steps,
-                     "speedup_batched_mixed": value / plain_value}
-        log(f"plain FP32: {plain_rec['ms_per_step']:.1f} ms/step")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                step(plain)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pv = n3 * args.plain_steps / (t1 - t0)
+            side["plain_fp32"] = {"value": pv, "ms_per_step": (t1 - t0) * 1e3 / args.plain_steps,
+                                  "speedup_batched_mixed": side["value"] / pv}
+        else:
+            plain = None
+        if not args.no_check:
+            log("FP64 reference form on the same workload")
+            p64 = rw.Plan(s3, c3, precision="fp64", batched=True)
+            psf64, _, idx = p64.forward(v3, ph3, am3, target=tg3, want_idx=True)
+            g64 = [g.double() for g in p64.backward()]
+            psf64 = psf64.double()
 
-    # ------------------------------------------------ G2 (straight-through)
-    g2_rec = None
-    if args.g2_steps > 0:
-        log("G2 (Gumbel-softmax straight-through) backward, batched MIXED")
-        p2 = rw.Plan(system, dict(cfg, grad="G2", tau=1.0), precision="mixed", batched=True)
-        p2.set_profiling(True)
+            def errs(pl):
+                psf, _, _ = pl.forward(v3, ph3, am3, target=tg3, replay=idx)
+                g = pl.backward()
+                d = (psf.double() - psf64).flatten(2).norm(dim=2) / psf64.flatten(2).norm(dim=2)
+                ge = [float((a.double() - b).norm() / b.norm()) for a, b in zip(g, g64)]
+                return {"psf_rel_l2_worst_pair": float(d.max()),
+                        "grad_rel_l2": {"phase": ge[0], "amp": ge[1], "lens": ge[2]}}
+
+            p3.set_graph(False)
+            side["error_vs_fp64"] = {
+                "mixed": errs(p3), "plain_fp32": errs(plain) if plain else None,
+                "note": "same sample indices (FP64 draws replayed); relative L2 per pair / group"}
+            del p64
+        del plain
+        if args.g2_steps > 0:
+            log("G2 (Gumbel-softmax straight-through) backward, batched MIXED")
+            p2 = rw.Plan(s3, dict(c3, grad="G2", tau=1.0), precision="mixed", batched=True)
+            p2.set_profiling(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.g2_steps):
+                step(p2)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pr2 = p2.profile()
+            side["g2_straight_through"] = {
+                "value": n3 * args.g2_steps / (t1 - t0), "unit": "rays/s",
+                "ms_per_step": (t1 - t0) * 1e3 / args.g2_steps, "steps": args.g2_steps,
+                "tau": 1.0, "doe_bwd_ms_per_step": round(pr2["doe_bwd"][0] / args.g2_steps, 1)}
+            del p2
+        # forward only (the benchmark's holographic forward configuration)
+        p3.set_graph(False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.g2_steps):
-            step(p2)
+        for _ in range(args.side_steps):
+            p3.forward(v3, ph3, am3)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pr2 = p2.profile()
-        g2_rec = {"value": n_rays * args.g2_steps / (t1 - t0), "unit": "rays/s",
-                  "ms_per_step": (t1 - t0) * 1e3 / args.g2_steps, "steps": args.g2_steps,
-                  "tau": 1.0,
-                  "doe_bwd_ms_per_step": round(pr2["doe_bwd"][0] / args.g2_steps, 1)}
-        del p2
-        log(f"G2: {g2_rec['ms_per_step']:.0f} ms/step")
+        side["forward_only"] = {"value": n3 * args.side_steps / (time.perf_counter() - t0),
+                                "unit": "rays/s"}
+        del p3
+        torch.cuda.empty_cache()
 
-    # ---------------------------------------------- error against FP64 form
-    check = None
-    if not args.no_check:
-        log("FP64 reference form on the same workload")
-        p64 = rw.Plan(system, cfg, precision="fp64", batched=True)
-        psf64, _, idx = p64.forward(vals, ph, am, target=tg, want_idx=True)
-        g64 = p64.backward()
-        psf64 = psf64.double()
-        g64 = [g.double() for g in g64]
-
-        def errs(pl):
-            psf, _, _ = pl.forward(vals, ph, am, target=tg, replay=idx)
-            g = pl.backward()
-            d = (psf.double() - psf64).flatten(2).norm(dim=2) / psf64.flatten(2).norm(dim=2)
-            ge = [float((a.double() - b).norm() / b.norm()) for a, b in zip(g, g64)]
-            return {"psf_rel_l2_worst_pair": float(d.max()), "grad_rel_l2":
-                    {"phase": ge[0], "amp": ge[1], "lens": ge[2]}}
-
-        check = {"mixed": errs(plan), "plain_fp32": errs(plain) if plain else None,
-                 "note": "same sample indices (FP64 draws replayed); relative L2 per pair / per group"}
-        del p64
-        log(f"errors vs FP64: {json.dumps(check)}")
+    # ---------------------------------------- forward-only other workloads
+    fwd_only = None
+    if not args.no_forward_only:
+        fwd_only = {}
+        for name, prec in (("conformal_sphere", "mixed"), ("singlet_zoneplate", "fp64")):
+            s_, c_, m_ = W.workload(name)
+            v_, ph_, am_, _ = inputs(s_, m_)
+            pl = rw.Plan(s_, c_, precision=prec, batched=True)
+            pl.forward(v_, ph_, am_)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl.forward(v_, ph_, am_)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            n_ = len(c_["lambdas"]) * len(c_["fields"]) * c_["rays_side"] ** 2
+            st = pl.stats()
+            fwd_only[name] = {"value": n_ / dt, "unit": "rays/s", "ms": dt * 1e3,
+                              "precision": prec, "incident_rays": n_,
+                              "secondaries": st["secondaries"], "rays_by_class":
+                              st["rays_by_class"][:len(classes_of(c_))]}
+            log(f"{name} forward ({prec}): {dt * 1e3:.1f} ms")
+            del pl
+            torch.cuda.empty_cache()
 
     # -------------------------------------------------------- CPU baseline
     cpu = None
@@ -256,50 +380,59 @@ def main():
         from oracle import rw_oracle as O
         nthreads = torch.get_num_threads()
         R = cfg["rays_side"]
-        side = 48
-        c0 = R // 2 - side // 2
-        subset = [(c0 + iy) * R + (c0 + ix) for iy in range(side) for ix in range(side)]
-        l_idx, f_idx = 1, F // 2
+        side_n = 16
+        c0 = R // 2 - side_n // 2
+        subset = [(c0 + iy) * R + (c0 + ix) for iy in range(side_n) for ix in range(side_n)]
+        F = len(cfg["fields"])
+        pr = F * (len(cfg["lambdas"]) // 2) + F // 2
+        l_idx, f_idx = pr // F, pr % F
+        vals = head_in[0].cpu().numpy().astype(np.float64)
         t0 = time.perf_counter()
         phd = torch.tensor(maps["phase"].astype(np.float64), requires_grad=True)
         amd = torch.tensor(maps["amp"].astype(np.float64), requires_grad=True)
-        vd = torch.tensor(vals.cpu().numpy().astype(np.float64), requires_grad=True)
+        vd = torch.tensor(vals, requires_grad=True)
         r = O.pair_forward(system, cfg, O.transmission(phd, amd), l_idx, f_idx, vd,
                            ray_subset=subset)
-        loss = O.eq5_loss(r["psf"], torch.tensor(maps["target"][l_idx, f_idx], dtype=torch.float64))
+        loss = O.eq5_loss(r["psf"], torch.tensor(maps["target"][l_idx, f_idx],
+                                                 dtype=torch.float64))
         loss.backward()
         t1 = time.perf_counter()
         cpu = {"value": len(subset) / (t1 - t0), "unit": "rays/s", "cores": nthreads,
                "kind": "oracle",
-               "sample": f"1 pair (587.6 nm, on axis) x {len(subset)} central rays of {R * R}, "
-                         f"full P/M/N/Q, forward + Eq. 5 loss + autograd backward, "
-                         f"{t1 - t0:.1f} s"}
+               "sample": f"1 pair (lambda {cfg['lambdas'][l_idx] * 1e6:.0f} nm, field {f_idx}) x "
+                         f"{len(subset)} central rays of {R * R}, full map, classes, N and Q, "
+                         f"forward + Eq. 5 loss + autograd backward, {t1 - t0:.1f} s"}
         log(f"CPU oracle: {cpu['value']:.2f} rays/s on {nthreads} threads")
 
+    desc = {"two_lens_hybrid": "two even-asphere lenses (BK7, F2) + 4096^2 complex DOE @0.5 um on "
+                               "L2's rear asphere; 8 lambda x 4x4 fields (+-25 deg) x 512^2 rays; "
+                               "patch classes P=128/64 (M=256/128, Eq. 4), N=256 (p_mag), Q=1024; "
+                               "Eq. 5 loss; fwd+bwd (G1) w.r.t. phase, amplitude, 14 lens params",
+            "asphere_hologram": side["workload"] if side else
+            "asphere singlet + 1024^2 random complex DOE; 27 pairs x 256^2 rays; P=64, N=256, "
+            "Q=512; Eq. 5 loss; fwd+bwd (G1)"}
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "rays/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "asphere singlet f=25 mm + 1024^2 random complex DOE @1 um; "
-                               "3 lambda x 3x3 fields (+-10 deg) x 256^2 rays; P=64 (M=128), "
-                               "N=256 (p_mag), Q=512; Eq. 5 loss; fwd+bwd (G1)",
-                   "form": "batched MIXED (FP32 FFT/grids, FP64 trace and phases)",
-                   "incident_rays_per_step": n_rays,
-                   "secondary_rays_per_step": records,
-                   "secondary_rays_per_s": records * args.steps / (ms_per_step * args.steps / 1e3)},
-        "plain_fp32": plain_rec,
-        "g2_straight_through": g2_rec,
-        "error_vs_fp64": check,
-        "stages_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in prof.items()},
+        "config": {"workload": desc[args.workload],
+                   "form": "batched MIXED (FP32 FFT/grids/trace, FP64 OPL, phases and Newton "
+                           "refinement), autotuned launch shapes, HIP-graph replays",
+                   "incident_rays_per_step": head["incident_rays_per_step"],
+                   "secondary_rays_per_step": head["secondary_rays_per_step"],
+                   "secondary_rays_per_s": head["secondary_rays_per_s"]},
+        "headline": head,
+        "asphere_hologram": side,
+        "forward_only": fwd_only,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -143,6 +143,11 @@ typedef struct {
    * first (one reduction kernel and a synchronisation of the stream) and returns
    * RW_ERR_NONFINITE without running the pass; 0: no check. */
   int check_finite;
+  /* Device bytes for the secondary-ray records of one launch group of pairs (the
+   * records as produced, after the super-bin pass and sorted, plus the tiled
+   * interpolation's slots and results); 0 = 96 GiB.  Pairs whose records exceed
+   * it run in several groups. */
+  uint64_t record_budget_bytes;
 } rw_config;
 
 typedef struct rw_plan rw_plan;
@@ -160,6 +165,7 @@ typedef struct {
   uint64_t secondaries_lost;    /* drawn secondaries that failed between DOE and sensor  */
   uint64_t evanescent_bins;     /* evanescent bins of the alive rays' spectra ...        */
   uint64_t spectrum_bins;       /* ... out of this many (M^2 per alive ray)              */
+  uint64_t rays_by_class[4];    /* alive rays per patch class (largest side first)       */
 } rw_stats;
 
 /* Creates a plan: validates shapes, builds constant tables (wavelength-dependent
@@ -225,6 +231,24 @@ rw_status rw_forward_static(rw_plan* plan, const float* lens_params, const float
 rw_status rw_backward(rw_plan* plan, const float* dL_dpsf, float* d_phase, float* d_amp,
                       float* d_lens, void* workspace, size_t workspace_bytes, void* stream);
 
+/* One training step on the loss of Eq. 5 (a target is required): the forward and
+ * the backward of rw_forward + rw_backward with dL/dpsf from the loss, fused per
+ * launch group of pairs -- each pair's loss and cogradient depend on its own PSF
+ * only, so a group's backward runs right after its forward while the group's
+ * binned records are still resident, and every group takes the tiled type-2
+ * interpolation (with rw_backward only a plan whose records fit one group does).
+ * Arguments as in rw_forward / rw_backward (psf_out, loss_out, d_phase, d_amp
+ * written; d_lens written when the plan has lens parameters and it is not NULL);
+ * the workspace must hold fwd + bwd bytes.  Afterwards rw_backward may still be
+ * called on the same workspace (it recomputes the records it needs).  Recorded as
+ * one HIP graph under rw_set_graph.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_STATE (workspace), RW_ERR_UNSUPPORTED (lens
+ *         gradients through more than 4 surfaces after the DOE), RW_ERR_HIP. */
+rw_status rw_forward_backward(rw_plan* plan, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, const float* target, float* psf_out,
+                              float* loss_out, float* d_phase, float* d_amp, float* d_lens,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
 /* Counters of the last forward (synchronises the stream of that forward). */
 rw_status rw_get_stats(rw_plan* plan, rw_stats* out_host);
 
@@ -244,7 +268,8 @@ rw_status rw_get_profile(rw_plan* plan, rw_profile* out_host);
 
 /* Launch-shape autotuning of the ray-wave kernels.  Times the forward and the
  * backward DOE kernels on the inputs of the preceding rw_forward (same plan and
- * workspace) for persistent workgroups in {256, 512, 1024, 2048} x spatial ray
+ * workspace; the first pairs, about 2^19 rays) for persistent workgroups in
+ * {256, 512, 1024, 2048} x spatial ray
  * blocks of {4, 8, 16}^2 rays, keeps the fastest shape of each direction in the
  * plan, and writes it to shape_out[4] (forward workgroups, forward block side,
  * backward workgroups, backward block side) if not NULL.  Synchronises the stream.
@@ -253,6 +278,13 @@ rw_status rw_get_profile(rw_plan* plan, rw_profile* out_host);
  * Errors: RW_ERR_INVALID_ARG, RW_ERR_STATE (no forward on this workspace), RW_ERR_HIP. */
 rw_status rw_autotune(rw_plan* plan, void* workspace, size_t workspace_bytes, int* shape_out,
                       void* stream);
+
+/* Applies a launch shape (as rw_autotune writes it: forward workgroups, forward
+ * ray-block side, backward workgroups, backward ray-block side), e.g. one cached
+ * from an earlier rw_autotune on the same GPU architecture and plan geometry.
+ * Recorded graphs are dropped.  Errors: RW_ERR_INVALID_ARG (workgroups outside
+ * [1, the plan's maximum], block side not 4, 8 or 16). */
+rw_status rw_set_launch_shape(rw_plan* plan, const int* shape_host);
 
 /* Captured launch sequences.  enable = 1: rw_forward and rw_backward record their
  * whole launch sequence into a HIP graph the first time they are called with a given

@@ -108,6 +108,8 @@ struct rw_plan {
   int emit;                 // record slots per ray
   int group_pairs;          // pairs per launch group (memory-bounded)
   bool g2;                  // straight-through gradient of p_mag draws in the backward
+  bool tiled_groups;        // several groups, each with room for its interpolated records
+                            // (rw_forward_backward interpolates them tile by tile)
   bool tiled_interp;        // one launch group: the backward interpolates the records
                             // of the forward tile by tile
   BinGeom bg;
@@ -145,7 +147,7 @@ struct rw_plan {
   // captured launch sequences (rw_set_graph)
   bool graph = false;
   bool capturing = false;
-  GraphState gfwd, gbwd;
+  GraphState gfwd, gbwd, gstep;
   hipStream_t cap_st = nullptr;
   // stage timing
   bool prof = false;
@@ -387,7 +389,7 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   unsigned int* work = (unsigned int*)(b + pl->off_work);
   hipLaunchKernelGGL(k_rec_scan, dim3(1), dim3(1024), 0, st, (const unsigned int*)cnt,
                      (size_t)npairs * g.keys, fpc, C, offs, cur, scur, work);
-  const bool slots = pl->tiled_interp && !pl->fwd_only;   // record slots for the backward
+  const bool slots = (pl->tiled_interp || pl->tiled_groups) && !pl->fwd_only;   // record slots
   unsigned int* tidx = slots ? (unsigned int*)(b + pl->off_tidx) : nullptr;
   const unsigned long long* offs_all = (const unsigned long long*)(b + pl->off_offs);
   hipLaunchKernelGGL((k_rec_place<Tg, true>), dim3((unsigned)((per_pair + C - 1) / C), npairs),
@@ -639,10 +641,19 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     const size_t nrec_pair = (size_t)pl->R2 * pl->emit;
     const size_t rec_bytes = nrec_pair * 3 * (pl->sz_cg + (dbl_g ? 16 : 8));
     const size_t tiled_bytes = rec_bytes + nrec_pair * (4 + 4 + kInterpStride * pl->sz_cg);
-    const size_t budget = (size_t)96 << 30;
+    const size_t budget = cfg->record_budget_bytes ? (size_t)cfg->record_budget_bytes
+                                                   : (size_t)96 << 30;
     pl->tiled_interp = cfg->batched && tiled_bytes * pl->n_pairs <= budget &&
                        nrec_pair * pl->n_pairs < ((size_t)1 << 32);
     size_t gp = std::max<size_t>(1, budget / std::max<size_t>(rec_bytes, 1));
+    // otherwise groups sized so that each holds its slots and interpolated
+    // records too: rw_forward_backward interpolates every group tile by tile
+    pl->tiled_groups = false;
+    if (!pl->tiled_interp && cfg->batched && tiled_bytes <= budget) {
+      gp = std::min(budget / tiled_bytes, (((size_t)1 << 32) - 1) / nrec_pair);
+      pl->tiled_groups = gp >= 1;
+      gp = std::max<size_t>(gp, 1);
+    }
     pl->group_pairs = (int)std::min<size_t>(gp, (size_t)pl->n_pairs);
     if (!cfg->batched) pl->group_pairs = 1;
     if (pl->tiled_interp) pl->group_pairs = pl->n_pairs;
@@ -812,8 +823,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->fwd_bytes = o;
   // state of the forward that only the backward reads
   pl->off_jdraw = take(cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t));
-  pl->off_tidx = take(pl->tiled_interp ? nrec * 4 : 0);
-  pl->off_sidx = take(pl->tiled_interp ? nrec * 4 : 0);
+  const bool tl = pl->tiled_interp || pl->tiled_groups;
+  pl->off_tidx = take(tl ? nrec * 4 : 0);
+  pl->off_sidx = take(tl ? nrec * 4 : 0);
   // the backward's own buffers
   pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
   pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
@@ -825,7 +837,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_raygrad = take((size_t)RW_RAYGRAD * nt * sizeof(double));
   pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
   pl->off_G = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
-  pl->off_interp = take(pl->tiled_interp ? nrec * kInterpStride * pl->sz_cg : 0);
+  pl->off_interp = take(tl ? nrec * kInterpStride * pl->sz_cg : 0);
   pl->total = o;
   *out = pl;
   return RW_OK;
@@ -851,6 +863,7 @@ rw_status rw_plan_destroy(rw_plan* pl) {
   for (auto& e : pl->ev_pool) (void)hipEventDestroy(e);
   pl->gfwd.reset();
   pl->gbwd.reset();
+  pl->gstep.reset();
   if (pl->cap_st) (void)hipStreamDestroy(pl->cap_st);
   delete pl;
   return RW_OK;
@@ -865,6 +878,7 @@ rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, vo
   char* b = (char*)ws;
   pl->gfwd.reset();
   pl->gbwd.reset();
+  pl->gstep.reset();
   const bool prof = pl->prof;
   pl->prof = false;
   DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
@@ -873,7 +887,9 @@ rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, vo
   a.g2 = pl->g2 ? (void*)(b + pl->off_g2) : nullptr;
   a.want_lens = 0;
   a.ray0 = 0;
-  const int ppg = pl->group_pairs;
+  // tune on the first pairs only, about 2^19 rays (the launch shape does not
+  // depend on which rays, only on how many per workgroup)
+  const int ppg = std::max(1, std::min(pl->group_pairs, (int)(((size_t)1 << 19) / pl->R2)));
   a.nray = (size_t)ppg * pl->R2;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -919,24 +935,41 @@ rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, vo
   return res;
 }
 
+rw_status rw_set_launch_shape(rw_plan* pl, const int* shape) {
+  if (!pl || !shape) return fail(RW_ERR_INVALID_ARG, "null argument");
+  for (int dir = 0; dir < 2; ++dir) {
+    const int nb = shape[2 * dir], rb = shape[2 * dir + 1];
+    if (nb < 1 || nb > pl->doe_blocks || (rb != 4 && rb != 8 && rb != 16))
+      return fail(RW_ERR_INVALID_ARG, "launch shape: workgroups in [1, " +
+                                          std::to_string(pl->doe_blocks) +
+                                          "], ray block side 4, 8 or 16");
+  }
+  pl->blocks_dir[0] = shape[0]; pl->rb_dir[0] = shape[1];
+  pl->blocks_dir[1] = shape[2]; pl->rb_dir[1] = shape[3];
+  pl->gfwd.reset();
+  pl->gbwd.reset();
+  pl->gstep.reset();
+  return RW_OK;
+}
+
 rw_status rw_set_graph(rw_plan* pl, int enable) {
   if (!pl) return fail(RW_ERR_INVALID_ARG, "null plan");
   pl->graph = enable != 0;
   if (!pl->graph) {
     pl->gfwd.reset();
     pl->gbwd.reset();
+    pl->gstep.reset();
   }
   return RW_OK;
 }
 
-// Every launch of one forward pass, in stream order.
-static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float* doe_phase,
-                             const float* doe_amp, const float* target, float* psf_out,
-                             float* loss_out, void* ws, const int32_t* replay_idx,
-                             int32_t* idx_out, hipStream_t st) {
+// The launches of one forward pass, in stream order: the prologue (live
+// prescription, transmission map, counters), each launch group of pairs, and the
+// loss of Eq. 5.
+static rw_status fwd_prologue(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, void* ws, hipStream_t st) {
   char* b = (char*)ws;
   const bool dbl_f = pl->cfg.precision == RW_PREC_FP64;
-  const bool dbl_g = pl->cfg.precision == RW_PREC_FP64;
   hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, pl->d_cfg, pl->d_base, pl->base_sensor_z,
                      pl->d_prm, lens_params, (DevLive*)(b + pl->off_live));
   const int nmap = pl->H * pl->W;
@@ -948,12 +981,16 @@ static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float*
                        doe_amp, (C2<float>*)(b + pl->off_tmap), nmap);
   HIPCHK(hipGetLastError());
   zero<unsigned long long>(b + pl->off_stats, RW_N_STATS, st);
+  return RW_OK;
+}
+
+static rw_status fwd_group(rw_plan* pl, void* ws, const int32_t* replay_idx, int32_t* idx_out,
+                           float* psf_out, int pair0, int ppg, hipStream_t st) {
+  char* b = (char*)ws;
   DoeArgs a = doe_args(pl, ws, replay_idx, idx_out);
-  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
-    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
-    const size_t nr = (size_t)ppg * pl->R2;
-    const int tb = (int)((nr + 255) / 256);
-    {
+  const size_t nr = (size_t)ppg * pl->R2;
+  const int tb = (int)((nr + 255) / 256);
+  {
     StageTimer tm_(pl, RW_STAGE_TRACE, st);
     if (pl->cfg.precision == RW_PREC_FP32)
       hipLaunchKernelGGL(k_trace<float>, dim3(tb), dim3(256), 0, st, pl->d_cfg, pl->d_pairs,
@@ -965,35 +1002,54 @@ static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float*
                          (const DevLive*)(b + pl->off_live), (double*)(b + pl->off_st),
                          (double*)(b + pl->off_ck), pl->n_total, pair0, ppg,
                          (unsigned long long*)(b + pl->off_stats));
-    }
-    HIPCHK(hipGetLastError());
-    a.ray0 = (size_t)pair0 * pl->R2;
-    a.nray = nr;
-    {
-      StageTimer tm_(pl, RW_STAGE_TRACE, st);
-      hipLaunchKernelGGL(k_ray_ctx, dim3(tb), dim3(256), 0, st, a);
-    }
-    HIPCHK(hipGetLastError());
-    rw_status s;
-    {
-      StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
-      s = doe_launch(pl, true, a, pair0, ppg, st);
-    }
-    if (s != RW_OK) return s;
-    s = bin_and_spread(pl, ws, st, pair0, ppg);
-    if (s != RW_OK) return s;
-    {
-      StageTimer tm_(pl, RW_STAGE_GRID_FWD, st);
-      s = grid_fwd(pl, ws, st, pair0, ppg, psf_out);
-    }
+  }
+  HIPCHK(hipGetLastError());
+  a.ray0 = (size_t)pair0 * pl->R2;
+  a.nray = nr;
+  {
+    StageTimer tm_(pl, RW_STAGE_TRACE, st);
+    hipLaunchKernelGGL(k_ray_ctx, dim3(tb), dim3(256), 0, st, a);
+  }
+  HIPCHK(hipGetLastError());
+  rw_status s;
+  {
+    StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
+    s = doe_launch(pl, true, a, pair0, ppg, st);
+  }
+  if (s != RW_OK) return s;
+  s = bin_and_spread(pl, ws, st, pair0, ppg);
+  if (s != RW_OK) return s;
+  StageTimer tm_(pl, RW_STAGE_GRID_FWD, st);
+  return grid_fwd(pl, ws, st, pair0, ppg, psf_out);
+}
+
+static void loss_pairs(rw_plan* pl, void* ws, const float* psf_out, const float* target,
+                       int pair0, int ppg, hipStream_t st) {
+  char* b = (char*)ws;
+  hipLaunchKernelGGL(k_loss_pairs, dim3(ppg), dim3(256), 0, st, psf_out, target, pl->Q * pl->Q,
+                     pair0, (double*)(b + pl->off_alpha), (double*)(b + pl->off_lossp));
+}
+
+static void loss_total(rw_plan* pl, void* ws, float* loss_out, hipStream_t st) {
+  char* b = (char*)ws;
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, (const double*)(b + pl->off_lossp),
+                     pl->n_pairs, loss_out);
+}
+
+static rw_status fwd_enqueue(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                             const float* doe_amp, const float* target, float* psf_out,
+                             float* loss_out, void* ws, const int32_t* replay_idx,
+                             int32_t* idx_out, hipStream_t st) {
+  rw_status s = fwd_prologue(pl, lens_params, doe_phase, doe_amp, ws, st);
+  if (s != RW_OK) return s;
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    s = fwd_group(pl, ws, replay_idx, idx_out, psf_out, pair0, ppg, st);
     if (s != RW_OK) return s;
   }
   if (target) {
-    hipLaunchKernelGGL(k_loss_pairs, dim3(pl->n_pairs), dim3(256), 0, st, psf_out, target,
-                       pl->Q * pl->Q, 0, (double*)(b + pl->off_alpha),
-                       (double*)(b + pl->off_lossp));
-    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(64), 0, st, (const double*)(b + pl->off_lossp),
-                       pl->n_pairs, loss_out);
+    loss_pairs(pl, ws, psf_out, target, 0, pl->n_pairs, st);
+    loss_total(pl, ws, loss_out, st);
     HIPCHK(hipGetLastError());
   }
   return RW_OK;
@@ -1170,6 +1226,7 @@ rw_status rw_get_stats(rw_plan* pl, rw_stats* out) {
   out->secondaries_lost = h[RW_ST_LOST];
   out->evanescent_bins = h[RW_ST_EVAN];
   out->spectrum_bins = h[RW_ST_BINS];
+  for (int c = 0; c < 4; ++c) out->rays_by_class[c] = h[RW_ST_CLASS0 + c];
   return RW_OK;
 }
 
@@ -1183,9 +1240,9 @@ rw_status rw_export_doe_hits(const rw_plan* pl, const void* ws, double* out, voi
   return RW_OK;
 }
 
-// Every launch of one backward pass, in stream order.
-static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
-                             float* d_lens, void* ws, bool want_lens, hipStream_t st) {
+// The launches of one backward pass, in stream order: clearing the gradient
+// accumulators, each launch group of pairs, and the final maps.
+static void bwd_prologue(rw_plan* pl, void* ws, bool want_lens, hipStream_t st) {
   char* b = (char*)ws;
   const bool dbl = pl->cfg.precision == RW_PREC_FP64;
   const size_t nmap = (size_t)pl->H * pl->W;
@@ -1193,58 +1250,65 @@ static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, 
   else zero<float>(b + pl->off_gt, 2 * nmap, st);
   zero<double>(b + pl->off_lensg, RW_LENSG_SLOTS, st);
   if (want_lens) zero<double>(b + pl->off_raygrad, (size_t)RW_RAYGRAD * pl->n_total, st);
-  {
-    const size_t nacc = (size_t)pl->blocks_dir[1] * pl->acc_side * pl->acc_side * 2;
-    if (dbl) zero<double>(b + pl->off_acc, nacc, st);
-    else zero<float>(b + pl->off_acc, nacc, st);
-  }
+  const size_t nacc = (size_t)pl->blocks_dir[1] * pl->acc_side * pl->acc_side * 2;
+  if (dbl) zero<double>(b + pl->off_acc, nacc, st);
+  else zero<float>(b + pl->off_acc, nacc, st);
+}
+
+// tiled: the group's binned records of the forward are still in the workspace
+static rw_status bwd_group(rw_plan* pl, const float* dL_dpsf, void* ws, bool want_lens,
+                           bool tiled, int pair0, int ppg, hipStream_t st) {
+  char* b = (char*)ws;
   DoeArgs a = doe_args(pl, ws, pl->fwd_replay, nullptr);
   a.adj = b + pl->off_grid;
-  a.interp = pl->tiled_interp ? (const void*)(b + pl->off_interp) : nullptr;
+  a.interp = tiled ? (const void*)(b + pl->off_interp) : nullptr;
   a.g2 = pl->g2 ? (void*)(b + pl->off_g2) : nullptr;
   a.want_lens = want_lens ? 1 : 0;
   a.stats = nullptr;
-  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
-    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
-    rw_status s;
-    {
-      StageTimer tm_(pl, RW_STAGE_GRID_BWD, st);
-      s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
-    }
-    if (s != RW_OK) return s;
-    if (pl->tiled_interp) {
-      s = interp_tiles(pl, ws, st, pair0, ppg);
-      if (s != RW_OK) return s;
-    }
-    const size_t nr = (size_t)ppg * pl->R2;
-    a.ray0 = (size_t)pair0 * pl->R2;
-    a.nray = nr;
-    {
-      StageTimer tm_(pl, RW_STAGE_DOE_BWD, st);
-      s = doe_launch(pl, false, a, pair0, ppg, st);
-    }
-    if (s != RW_OK) return s;
-    if (want_lens && pl->has_post) {
-      StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
-      const unsigned nb = (unsigned)((nr + 3) / 4);
-      if (pl->cfg.precision == RW_PREC_FP64)
-        hipLaunchKernelGGL(k_post_bwd<double>, dim3(nb), dim3(256), 0, st, a);
-      else
-        hipLaunchKernelGGL(k_post_bwd<float>, dim3(nb), dim3(256), 0, st, a);
-      HIPCHK(hipGetLastError());
-    }
-    if (want_lens) {
-      StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
-      hipLaunchKernelGGL(k_trace_bwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
-                         pl->d_cfg, pl->d_pairs, (const DevLive*)(b + pl->off_live),
-                         (const double*)(b + pl->off_st), (const double*)(b + pl->off_ck),
-                         (const double*)(b + pl->off_raygrad), pl->n_total, a.ray0, nr,
-                         (double*)(b + pl->off_lensg));
-      HIPCHK(hipGetLastError());
-    }
+  rw_status s;
+  {
+    StageTimer tm_(pl, RW_STAGE_GRID_BWD, st);
+    s = grid_bwd(pl, ws, st, pair0, ppg, dL_dpsf);
   }
-  const int n = (int)nmap;
-  if (dbl)
+  if (s != RW_OK) return s;
+  if (tiled) {
+    s = interp_tiles(pl, ws, st, pair0, ppg);
+    if (s != RW_OK) return s;
+  }
+  const size_t nr = (size_t)ppg * pl->R2;
+  a.ray0 = (size_t)pair0 * pl->R2;
+  a.nray = nr;
+  {
+    StageTimer tm_(pl, RW_STAGE_DOE_BWD, st);
+    s = doe_launch(pl, false, a, pair0, ppg, st);
+  }
+  if (s != RW_OK) return s;
+  if (want_lens && pl->has_post) {
+    StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
+    const unsigned nb = (unsigned)((nr + 3) / 4);
+    if (pl->cfg.precision == RW_PREC_FP64)
+      hipLaunchKernelGGL(k_post_bwd<double>, dim3(nb), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_post_bwd<float>, dim3(nb), dim3(256), 0, st, a);
+    HIPCHK(hipGetLastError());
+  }
+  if (want_lens) {
+    StageTimer tm_(pl, RW_STAGE_TRACE_BWD, st);
+    hipLaunchKernelGGL(k_trace_bwd, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st,
+                       pl->d_cfg, pl->d_pairs, (const DevLive*)(b + pl->off_live),
+                       (const double*)(b + pl->off_st), (const double*)(b + pl->off_ck),
+                       (const double*)(b + pl->off_raygrad), pl->n_total, a.ray0, nr,
+                       (double*)(b + pl->off_lensg));
+    HIPCHK(hipGetLastError());
+  }
+  return RW_OK;
+}
+
+static rw_status bwd_epilogue(rw_plan* pl, void* ws, float* d_phase, float* d_amp, float* d_lens,
+                              bool want_lens, hipStream_t st) {
+  char* b = (char*)ws;
+  const int n = pl->H * pl->W;
+  if (pl->cfg.precision == RW_PREC_FP64)
     hipLaunchKernelGGL(k_dmaps<double>, dim3((n + 255) / 256), dim3(256), 0, st,
                        (const float*)pl->fwd_phase, (const float*)pl->fwd_amp,
                        (const C2<double>*)(b + pl->off_gt), d_phase, d_amp, n);
@@ -1257,6 +1321,41 @@ static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, 
                        (const double*)(b + pl->off_lensg), d_lens);
   HIPCHK(hipGetLastError());
   return RW_OK;
+}
+
+static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
+                             float* d_lens, void* ws, bool want_lens, hipStream_t st) {
+  bwd_prologue(pl, ws, want_lens, st);
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    const rw_status s = bwd_group(pl, dL_dpsf, ws, want_lens, pl->tiled_interp, pair0, ppg, st);
+    if (s != RW_OK) return s;
+  }
+  return bwd_epilogue(pl, ws, d_phase, d_amp, d_lens, want_lens, st);
+}
+
+// One training step on the loss of Eq. 5: the pairs' losses and cogradients are
+// independent, so each launch group runs its backward right after its forward,
+// while its binned records are still in the workspace (tiled interpolation in
+// every group), then the maps and the loss are finished.
+static rw_status step_enqueue(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, const float* target, float* psf_out,
+                              float* loss_out, float* d_phase, float* d_amp, float* d_lens,
+                              void* ws, bool want_lens, hipStream_t st) {
+  rw_status s = fwd_prologue(pl, lens_params, doe_phase, doe_amp, ws, st);
+  if (s != RW_OK) return s;
+  bwd_prologue(pl, ws, want_lens, st);
+  const bool tiled = pl->tiled_interp || pl->tiled_groups;
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    s = fwd_group(pl, ws, nullptr, nullptr, psf_out, pair0, ppg, st);
+    if (s != RW_OK) return s;
+    loss_pairs(pl, ws, psf_out, target, pair0, ppg, st);
+    s = bwd_group(pl, nullptr, ws, want_lens, tiled, pair0, ppg, st);
+    if (s != RW_OK) return s;
+  }
+  loss_total(pl, ws, loss_out, st);
+  return bwd_epilogue(pl, ws, d_phase, d_amp, d_lens, want_lens, st);
 }
 
 rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
@@ -1285,6 +1384,55 @@ rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* 
     });
   }
   return bwd_enqueue(pl, dL_dpsf, d_phase, d_amp, d_lens, ws, want_lens, st);
+}
+
+rw_status rw_forward_backward(rw_plan* pl, const float* lens_params, const float* doe_phase,
+                              const float* doe_amp, const float* target, float* psf_out,
+                              float* loss_out, float* d_phase, float* d_amp, float* d_lens,
+                              void* ws, size_t ws_bytes, void* stream) {
+  const rw_status a = forward_args(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                                   nullptr);
+  if (a != RW_OK) return a;
+  if (!target || !loss_out || !d_phase || !d_amp || !ws)
+    return fail(RW_ERR_INVALID_ARG, "null required argument (target, loss_out, d_phase, d_amp, "
+                                    "workspace)");
+  if (ws_bytes < pl->total) return fail(RW_ERR_STATE, "workspace smaller than fwd + bwd bytes");
+  if (((uintptr_t)ws & 255) != 0) return fail(RW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const bool want_lens = pl->prm.size() > 0 && d_lens != nullptr;
+  const bool tiled = pl->tiled_interp || pl->tiled_groups;
+  if (want_lens && pl->has_post && (!tiled || pl->n_surf - pl->s_doe - 1 > kPostMax))
+    return fail(RW_ERR_UNSUPPORTED,
+                "lens-parameter gradients through surfaces after the DOE need a batched plan "
+                "and at most 4 such surfaces");
+  hipStream_t st = (hipStream_t)stream;
+  pl->fwd_done = false;
+  pl->fwd_only = false;
+  // the backward half reads the forward's state of this call
+  pl->fwd_target = target;
+  pl->fwd_replay = nullptr;
+  pl->fwd_phase = doe_phase;
+  pl->fwd_psf = psf_out;
+  pl->fwd_amp = doe_amp;
+  rw_status r;
+  if (pl->graph) {
+    const GraphKey key = {{(const void*)lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
+                           d_phase, d_amp, d_lens, ws}};
+    r = graph_run(pl, pl->gstep, key, st, [&](hipStream_t cs) {
+      return step_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, d_phase,
+                          d_amp, d_lens, ws, want_lens, cs);
+    });
+  } else {
+    r = step_enqueue(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, d_phase,
+                     d_amp, d_lens, ws, want_lens, st);
+  }
+  if (r != RW_OK) return r;
+  // the draws and every pair's ray state are the forward's: a later rw_backward
+  // recomputes what it needs (records of earlier groups are gone)
+  pl->fwd_done = true;
+  pl->fwd_full = true;
+  pl->fwd_ws = ws;
+  pl->fwd_stream = st;
+  return RW_OK;
 }
 
 }  // extern "C"

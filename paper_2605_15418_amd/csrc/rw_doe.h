@@ -207,8 +207,18 @@ template <class Tf> struct DrawEnt {
 };
 constexpr int kDrawLds = 256;   // draws per ray whose terms stay in LDS
 
+// 256-point line transforms (M = 256, whose spectrum lives in a global buffer):
+// batches of kLines256 lines staged in LDS, element i of a line at i + i / 16
+// (one element of skew per 16) in lines kLS256 apart, so that the 16 lanes of
+// a quarter-wave hit 16 distinct 8-byte bank slots in both passes and in the
+// transposed column loads.
+constexpr int kLines256 = 64;
+constexpr int kLS256 = 273;
+__device__ __forceinline__ int sk256(int i) { return i + (i >> 4); }
+
 template <class Tf, int M, bool kLDS> struct DoeLds {
   C2<Tf> buf[kLDS ? DoeGeom<M>::SIZE : 1];
+  C2<Tf> ls[M == 256 ? kLines256 * kLS256 : 1];   // staged lines (M = 256)
   C2<Tf> tw[M];
   double pref[DoeGeom<M>::NCH + 1];
   double red[16];
@@ -335,6 +345,96 @@ __device__ __forceinline__ void line_fft2(C2<Tf>* buf, const C2<Tf>* tw, int nl,
   __syncthreads();
 }
 
+// Copies between the global patch buffer (M = 256) and the staged lines, KB
+// elements per lane in flight: every load of a batch is issued before its
+// stores (one workgroup per CU leaves eight waves to hide the memory latency).
+// Rows: staged line l <- buffer row r0 + l (elements m < nm of a line, zeros up
+// to zl).  Columns: staged line l <- buffer column c0 + l (rows r < nr, zeros up
+// to zl).
+template <class Tf, bool kCols>
+__device__ __forceinline__ void stage_lines256(C2<Tf>* ls, const C2<Tf>* buf, int sm, int o0,
+                                               int nl, int nk, int zl) {
+  constexpr int KB = 16;
+  const int tid = opaque_tid();
+  const int n = kCols ? zl * kLines256 : nl * 256;
+  for (int i0 = tid; i0 < n; i0 += kDoeThreads * KB) {
+    C2<Tf> v[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = i0 + k * kDoeThreads;
+      const int l = kCols ? (i & 63) : (i >> 8), e = kCols ? (i >> 6) : (i & 255);
+      v[k] = C2<Tf>{Tf(0), Tf(0)};
+      if (i < n && e < nk && l < nl)
+        v[k] = kCols ? buf[(size_t)e * sm + o0 + l] : buf[(size_t)(o0 + l) * sm + e];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = i0 + k * kDoeThreads;
+      const int l = kCols ? (i & 63) : (i >> 8), e = kCols ? (i >> 6) : (i & 255);
+      if (i < n && e < zl && l < nl) ls[l * kLS256 + sk256(e)] = v[k];
+    }
+  }
+}
+
+// 256-point transforms of nl staged lines in place (natural order in and out),
+// n = a + 16 b, k = k1 + 16 k2: pass A, per (line, a), the 16-point DFT over b
+// times W_256^(a k1), back into slots a + 16 k1; pass B, per (line, k1), the
+// 16-point DFT over the slots a + 16 k1, stored to k1 + 16 k2 after a barrier.
+// half: inputs 128.. are zero (the zero-padded half of a patch line).  Starts
+// and ends with every lane's LDS traffic ordered.
+template <class Tf, int DIR>
+__device__ __forceinline__ void lds_fft256(C2<Tf>* ls, const C2<Tf>* tw, int nl, bool half) {
+  const int tid = opaque_tid();
+  __syncthreads();
+  for (int t = tid; t < nl * 16; t += kDoeThreads) {
+    C2<Tf>* L = ls + (t >> 4) * kLS256;
+    const int a = t & 15;
+    C2<Tf> x[16];
+    if (half) {
+#pragma unroll
+      for (int b = 0; b < 16; ++b) x[b] = b < 8 ? L[sk256(a + 16 * b)] : C2<Tf>{Tf(0), Tf(0)};
+      reg_fft<Tf, 16, DIR, true>(x);
+    } else {
+#pragma unroll
+      for (int b = 0; b < 16; ++b) x[b] = L[sk256(a + 16 * b)];
+      reg_fft<Tf, 16, DIR>(x);
+    }
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) {
+      const C2<Tf> w0 = tw[(a * k1) & 255];
+      x[k1] = x[k1] * C2<Tf>{w0.re, DIR > 0 ? -w0.im : w0.im};
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) L[sk256(a + 16 * k1)] = x[k1];
+  }
+  __syncthreads();
+  constexpr int NT = kLines256 * 16 / kDoeThreads;     // pass-B tasks per lane
+  C2<Tf> z[NT][16];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int t = tid + j * kDoeThreads;
+    if (t < nl * 16) {
+      const C2<Tf>* L = ls + (t >> 4) * kLS256;
+      const int k1 = t & 15;
+#pragma unroll
+      for (int a = 0; a < 16; ++a) z[j][a] = L[sk256(a + 16 * k1)];
+      reg_fft<Tf, 16, DIR>(z[j]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int t = tid + j * kDoeThreads;
+    if (t < nl * 16) {
+      C2<Tf>* L = ls + (t >> 4) * kLS256;
+      const int k1 = t & 15;
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) L[sk256(k1 + 16 * k2)] = z[j][k2];
+    }
+  }
+  __syncthreads();
+}
+
 // Spectrum of the ray's patch into buf (natural order) and the per-chunk sums of
 // the sampling density into s.pref[chunk] (before the scan).  Returns lastpos
 // candidates through *lastpos (block maximum taken by the caller).
@@ -342,13 +442,101 @@ template <class Tf, int M, bool kCdf = true>
 __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
                                              const C2<Tf>* tm, C2<Tf>* buf, const C2<Tf>* tw,
                                              double* chunk, Span* span, int sampling,
-                                             int* lastpos) {
+                                             int* lastpos, C2<Tf>* ls) {
   using Gm = DoeGeom<M>;
   constexpr int L = Gm::L, E = Gm::E, G = Gm::G, SM = Gm::SM;
   const int tid = opaque_tid();
   const int g = tid / L, gl = tid % L;
   const int br = bitrev(gl, Gm::LB);
   const int P = c.P;
+  if constexpr (M == 256) {
+    // rows: batches of the P nonzero rows, samples straight into the staged lines,
+    // the transformed rows to buf; columns: batches of columns (rows < P in),
+    // chunk sums from the staged outputs, the spectrum to buf
+    const TileRef tr = tile_of(cfg, c);
+    const bool half = 2 * P == M;
+    const int lgP = __builtin_ctz(P);
+    for (int r0 = 0; r0 < P; r0 += kLines256) {
+      const int nr = min(kLines256, P - r0);
+      // bilinear samples, KS per lane with their map reads issued together
+      constexpr int KS = 8;
+      for (int i0 = tid; i0 < nr * P; i0 += kDoeThreads * KS) {
+        C2<Tf> q[KS][4];
+        Tf wx[KS], wy[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int i = i0 + k * kDoeThreads;
+          const int n = r0 + (i >> lgP), m = i & (P - 1);
+          const double sm_ = (m - (P - 1) * 0.5) * cfg.pitch, sn_ = (n - (P - 1) * 0.5) * cfg.pitch;
+          const double fx = (c.p[0] + sm_ * c.u[0] + sn_ * c.v[0] - cfg.x0) * cfg.inv_pitch;
+          const double fy = (c.p[1] + sm_ * c.u[1] + sn_ * c.v[1] - cfg.y0) * cfg.inv_pitch;
+          const double flx = floor(fx), fly = floor(fy);
+          const int ix = (int)flx, iy = (int)fly;
+          wx[k] = (Tf)(fx - flx);
+          wy[k] = (Tf)(fy - fly);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int x = ix + (j & 1), y = iy + (j >> 1);
+            q[k][j] = (i < nr * P && x >= 0 && x < cfg.W && y >= 0 && y < cfg.H)
+                          ? tm[(size_t)y * cfg.W + x] : C2<Tf>{Tf(0), Tf(0)};
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+          const int i = i0 + k * kDoeThreads;
+          if (i >= nr * P) break;
+          ls[(i >> lgP) * kLS256 + sk256(i & (P - 1))] =
+              (q[k][0] * (Tf(1) - wx[k]) + q[k][1] * wx[k]) * (Tf(1) - wy[k]) +
+              (q[k][2] * (Tf(1) - wx[k]) + q[k][3] * wx[k]) * wy[k];
+        }
+      }
+      if (!half)
+        for (int i = tid; i < nr * M; i += kDoeThreads)
+          if ((i & 255) >= P) ls[(i >> 8) * kLS256 + sk256(i & 255)] = C2<Tf>{Tf(0), Tf(0)};
+      lds_fft256<Tf, -1>(ls, tw, nr, half);
+      for (int i = tid; i < nr * M; i += kDoeThreads) {
+        const int l = i >> 8, k = i & 255;
+        buf[Gm::row(r0 + l) + k] = ls[l * kLS256 + sk256(k)];
+      }
+    }
+    for (int i = tid; i < M; i += kDoeThreads) span[i] = prop_span(c, i - M / 2, M);
+    int lp = -1;
+    for (int c0 = 0; c0 < M; c0 += kLines256) {
+      __syncthreads();
+      stage_lines256<Tf, true>(ls, buf, SM, c0, kLines256, P, half ? P : M);
+      lds_fft256<Tf, -1>(ls, tw, kLines256, half);
+      if constexpr (kCdf) {
+        // chunk q of column col: E = 64 consecutive shifted rows, summed in the
+        // spectrum's type in shifted-row order (the order of the draws' rescan)
+        if (tid < kLines256 * (M / E)) {
+          const int cl = tid & 63, q = tid >> 6;
+          const int col = c0 + cl;
+          const int jx = col < M / 2 ? col : col - M;
+          const int jys0 = E * q, ky0 = (jys0 + M / 2) & (M - 1);
+          const Span sp = span[jx + M / 2];
+          Tf sum = Tf(0);
+          int last = -1;
+          for (int k2 = 0; k2 < E; ++k2) {
+            const int ky = ky0 + k2;
+            const int jy = ky < M / 2 ? ky : ky - M;
+            Tf wgt = Tf(0);
+            if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(ls[cl * kLS256 + sk256(ky)], sampling);
+            sum += wgt;
+            if (wgt > Tf(0)) last = k2;
+          }
+          const int ch = ((jx + M / 2) * M + jys0) / E;
+          chunk[ch] = (double)sum;
+          if (last >= 0) lp = max(lp, ch * E + last);
+        }
+      }
+      for (int i = tid; i < M * kLines256; i += kDoeThreads) {
+        const int k = i >> 6, cl = i & 63;
+        buf[Gm::row(k) + c0 + cl] = ls[cl * kLS256 + sk256(k)];
+      }
+    }
+    *lastpos = lp;
+    __syncthreads();
+  } else {
   // the map tile goes into rows P.. of buf, which the row pass leaves untouched
   const TileRef tr = tile_of(cfg, c);
   C2<Tf>* tile = Gm::SIZE - Gm::row(P) >= tr.tw * tr.tw ? buf + Gm::row(P) : nullptr;
@@ -476,6 +664,7 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   }
   *lastpos = lp;
   __syncthreads();
+  }
 }
 
 // Wave-level prefix operations with DPP row shifts (lanes whose source lies
@@ -692,7 +881,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const int t = opaque_tid();
       const int P = c.P;
       int lp;
-      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
+      doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp, s.ls);
       if (t < M) {
         const Span sp = s.span[t];
         n_evan += (unsigned long long)(M - (sp.hi >= sp.lo ? sp.hi - sp.lo + 1 : 0));
@@ -772,6 +961,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   }
   if (a.stats) {
     if (n_alive) atomicAdd(&a.stats[RW_ST_ALIVE], n_alive);
+    if (n_alive) atomicAdd(&a.stats[RW_ST_CLASS0 + a.cls], n_alive);
     if (n_sec) atomicAdd(&a.stats[RW_ST_SEC], n_sec);
     if (n_lost) atomicAdd(&a.stats[RW_ST_LOST], n_lost);
     if (n_evan) atomicAdd(&a.stats[RW_ST_EVAN], n_evan);
@@ -1142,7 +1332,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       // ray): no CDF here
       const int jpre = !kFull && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
       int lp = -1;
-      doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp);
+      doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp,
+                                 s.ls);
       IncAcc acc = {{0, 0, 0}, {0, 0}, 0, 0, {0, 0, 0}};
       double dLdS = 0.0;
       constexpr int LPD = kTiled ? 1 : 2;   // lanes per secondary ray
@@ -1322,6 +1513,30 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       if constexpr (Gm::kSkew) {
         line_fft2<Tf, M, +1, true>(buf, s.tw, M, M, P, false);
         line_fft2<Tf, M, +1, false>(buf, s.tw, P, M, P, true);
+      } else if constexpr (M == 256) {
+        // batches staged in LDS: columns (all rows in, rows < P out), then the
+        // rows < P (columns < P out, columns P and M - 1 as the zero border)
+        C2<Tf>* ls = s.ls;
+        for (int c0 = 0; c0 < M; c0 += kLines256) {
+          stage_lines256<Tf, true>(ls, buf, SM, c0, kLines256, M, M);
+          lds_fft256<Tf, +1>(ls, s.tw, kLines256, false);
+          for (int i = t; i < P * kLines256; i += kDoeThreads) {
+            const int r = i >> 6, cl = i & 63;
+            buf[Gm::row(r) + c0 + cl] = ls[cl * kLS256 + sk256(r)];
+          }
+          __syncthreads();
+        }
+        for (int r0 = 0; r0 < P; r0 += kLines256) {
+          const int nr = min(kLines256, P - r0);
+          stage_lines256<Tf, false>(ls, buf, SM, r0, nr, M, M);
+          lds_fft256<Tf, +1>(ls, s.tw, nr, false);
+          for (int i = t; i < nr * M; i += kDoeThreads) {
+            const int l = i >> 8, m = i & 255;
+            if (m < P) buf[Gm::row(r0 + l) + m] = ls[l * kLS256 + sk256(m)];
+            else if (m == P || m == M - 1) buf[Gm::row(r0 + l) + m] = C2<Tf>{Tf(0), Tf(0)};
+          }
+          __syncthreads();
+        }
       } else {
         for (int col = g; col < M; col += G) {
           C2<Tf> x[E];

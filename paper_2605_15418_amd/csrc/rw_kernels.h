@@ -18,9 +18,10 @@ namespace rw {
 constexpr int kThreads = 256;
 // Forward counters: alive rays, secondaries, rays ended by cause (no hit,
 // aperture, TIR, outside the DOE), secondaries lost after the DOE, evanescent
-// and total spectrum bins of the alive rays.
+// and total spectrum bins of the alive rays, alive rays per patch class.
 enum { RW_ST_ALIVE = 0, RW_ST_SEC = 1, RW_ST_NOHIT = 2, RW_ST_APER = 3, RW_ST_TIR = 4,
-       RW_ST_OUTSIDE = 5, RW_ST_LOST = 6, RW_ST_EVAN = 7, RW_ST_BINS = 8, RW_N_STATS = 9 };
+       RW_ST_OUTSIDE = 5, RW_ST_LOST = 6, RW_ST_EVAN = 7, RW_ST_BINS = 8, RW_ST_CLASS0 = 9,
+       RW_N_STATS = 13 };
 
 // Tt: trace; Tf: patch spectrum; Tp: optical path and wavelet phase; Tg: sensor
 // grid; Te: sine / cosine of the wavelet phase after its reduction to [0, 2 pi)

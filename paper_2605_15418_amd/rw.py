@@ -6,6 +6,7 @@ HIP stream.  There is no CPU fallback: if the library is missing, or no GPU
 is present, the calls raise.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -20,11 +21,12 @@ SAMPLING = {"mag": 0, "uni": 1, "full": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
 GRAD = {"G1": 0, "G2": 1}
 RW_STATIC_SCRATCH_BYTES = 256 << 20   # workspace of rw_forward_static (include/rw.h)
+AUTOTUNE_CACHE = os.path.join(_HERE, "autotune_cache.json")   # launch shapes by arch + geometry
 STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",
           4: "RW_ERR_NONFINITE", 5: "RW_ERR_OOM", 6: "RW_ERR_HIP", 7: "RW_ERR_UNSUPPORTED"}
 
 EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
-            "rw_backward",
+            "rw_backward", "rw_forward_backward", "rw_set_launch_shape",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
             "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph",
             "rw_autotune")
@@ -62,7 +64,8 @@ class rw_config(ctypes.Structure):
                 ("spread_width", ctypes.c_int), ("seed", ctypes.c_uint64),
                 ("grad", ctypes.c_int), ("tau", ctypes.c_double),
                 ("n_patch_class", ctypes.c_int), ("patch_class_p", ctypes.c_int * 3),
-                ("curv_eps", ctypes.c_double), ("check_finite", ctypes.c_int)]
+                ("curv_eps", ctypes.c_double), ("check_finite", ctypes.c_int),
+                ("record_budget_bytes", ctypes.c_uint64)]
 
 
 class rw_profile(ctypes.Structure):
@@ -75,7 +78,8 @@ STATS = ("rays_total", "rays_alive", "secondaries", "killed_no_hit", "killed_ape
 
 
 class rw_stats(ctypes.Structure):
-    _fields_ = [(name, ctypes.c_uint64) for name in STATS]
+    _fields_ = [(name, ctypes.c_uint64) for name in STATS] + \
+        [("rays_by_class", ctypes.c_uint64 * 4)]
 
 
 _lib = None
@@ -97,6 +101,7 @@ def load_library(path=LIB_PATH):
     lib.rw_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.rw_forward_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.rw_backward.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.rw_forward_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.rw_get_stats.argtypes = [vp, ctypes.POINTER(rw_stats)]
     lib.rw_export_doe_hits.argtypes = [vp, vp, vp, vp]
     lib.rw_plan_destroy.argtypes = [vp]
@@ -104,13 +109,14 @@ def load_library(path=LIB_PATH):
     lib.rw_get_profile.argtypes = [vp, ctypes.POINTER(rw_profile)]
     lib.rw_set_graph.argtypes = [vp, ctypes.c_int]
     lib.rw_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_int), vp]
+    lib.rw_set_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
     for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
-                 "rw_backward",
+                 "rw_backward", "rw_forward_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
-                 "rw_get_profile", "rw_set_graph", "rw_autotune"):
+                 "rw_get_profile", "rw_set_graph", "rw_autotune", "rw_set_launch_shape"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,6 +217,7 @@ class Plan:
             c.patch_class_p[i] = q
         c.curv_eps = float(cfg.get("curv_eps", 0.1))
         c.check_finite = int(bool(check_finite))
+        c.record_budget_bytes = int(cfg.get("record_budget_bytes", 0))
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
                                                  len(prm), ctypes.byref(c), ctypes.byref(h)))
@@ -229,6 +236,7 @@ class Plan:
         self.n_rays = self.L * self.F * cfg["rays_side"] ** 2
         self.N = cfg["n_ssr"]
         self.M = cfg["patch_p"] * cfg["pad"]
+        self.precision = precision
         self.generation = 0        # forwards run on this plan (HybridPSF checks it)
 
     def __del__(self):
@@ -276,19 +284,75 @@ class Plan:
         _check(self.lib, st)
         return dp, da, dl
 
+    def step(self, lens_params, phase, amp, target, psf_out=None, loss_out=None, d_phase=None,
+             d_amp=None, d_lens=None):
+        """One fused forward + backward on the Eq. 5 loss (rw_forward_backward):
+        returns (psf, loss, d_phase, d_amp, d_lens)."""
+        d = self.system["doe"]
+        dev = self.device
+        psf = psf_out if psf_out is not None else torch.empty(
+            (self.L, self.F, self.Q, self.Q), dtype=torch.float32, device=dev)
+        loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=dev)
+        dp = d_phase if d_phase is not None else torch.empty((d["H"], d["W"]), dtype=torch.float32,
+                                                             device=dev)
+        da = d_amp if d_amp is not None else torch.empty_like(dp)
+        dl = d_lens
+        if dl is None and self.n_params:
+            dl = torch.empty(self.n_params, dtype=torch.float32, device=dev)
+        self._fwd_keep = (lens_params, phase, amp, target, None)
+        self.generation += 1
+        st = self.lib.rw_forward_backward(self.handle, _dptr(lens_params), _dptr(phase), _dptr(amp),
+                                          _dptr(target), _dptr(psf), _dptr(loss), _dptr(dp),
+                                          _dptr(da), _dptr(dl), _dptr(self.ws), self.ws_bytes,
+                                          self._stream())
+        _check(self.lib, st)
+        return psf, loss, dp, da, dl
+
     def stats(self):
         s = rw_stats()
         _check(self.lib, self.lib.rw_get_stats(self.handle, ctypes.byref(s)))
-        return {name: getattr(s, name) for name in STATS}
+        out = {name: getattr(s, name) for name in STATS}
+        out["rays_by_class"] = list(s.rays_by_class)
+        return out
 
-    def autotune(self):
-        """Pick the fastest launch shape of the DOE kernels on the inputs of the last
-        forward; returns (fwd workgroups, fwd ray block, bwd workgroups, bwd ray block).
-        Run forward again before backward."""
+    def tune_key(self):
+        """What a launch shape depends on: the GPU architecture and the plan's
+        geometry (precision, patch classes, draws, PSF, rays per pair, pairs)."""
+        c = self.cfg
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        classes = sorted({int(c["patch_p"])} | {int(q) for q in c.get("patch_classes", [])})
+        return "|".join(str(x) for x in (arch, self.precision, c["pad"], classes, c["sampling"],
+                                         self.N, self.Q, c["rays_side"], self.L * self.F))
+
+    def autotune(self, cache=None):
+        """Fastest launch shape of the DOE kernels, returned as (fwd workgroups, fwd
+        ray block, bwd workgroups, bwd ray block).  With `cache` (a JSON file path) a
+        shape stored there under tune_key() is applied without timing; otherwise
+        rw_autotune times the candidates on the inputs of the last forward (run the
+        forward again before a backward) and the result is stored in the cache."""
+        key = self.tune_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                self.set_launch_shape(table[key])
+                return tuple(table[key])
         shape = (ctypes.c_int * 4)()
         _check(self.lib, self.lib.rw_autotune(self.handle, _dptr(self.ws), self.ws_bytes, shape,
                                               self._stream()))
+        if cache:
+            table[key] = list(shape)
+            try:
+                with open(cache, "w") as f:
+                    json.dump(table, f, indent=1, sort_keys=True)
+            except OSError:
+                pass
         return tuple(shape)
+
+    def set_launch_shape(self, shape):
+        arr = (ctypes.c_int * 4)(*[int(x) for x in shape])
+        _check(self.lib, self.lib.rw_set_launch_shape(self.handle, arr))
 
     def set_graph(self, enable=True):
         """Record the forward / backward launch sequences as HIP graphs and replay them."""
