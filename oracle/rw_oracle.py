@@ -87,6 +87,7 @@ def build_surfaces(system, values=None):
     out = []
     for i, s in enumerate(surfs):
         out.append(dict(kind=s["kind"], z=z[i], c=c[i], k=kk[i], A=A[i],
+                        gh=_t(s.get("gh", 0.0)), gw=_t(s.get("gw", 0.0)),
                         semi_ap=s["semi_ap"], nA=s["nA"], nB=s["nB"],
                         doe=bool(s.get("doe", False))))
     return out, sensor_z
@@ -113,9 +114,21 @@ def initial_param_values(system):
 
 # ----------------------------------------------------------------------------
 # Even-asphere sag z(r) = c r^2 / (1 + sqrt(1 - (1+k) c^2 r^2)) + A4 r^4 + ...
+# plus, for the Gaussian-like substrate of the conformal DOE demonstration
+# (Fig. 6b), gh (exp(-r^2 / gw^2) - 1) when gw > 0 (zero at the vertex).
 # Conventional ray tracing of refractive surfaces (Formalism, first paragraph;
 # Benchmark section, "propagated ... via conventional ray tracing").
 # ----------------------------------------------------------------------------
+def _gauss_terms(surf, rho):
+    """The Gaussian term g(rho) and its first two rho-derivatives (zeros if gw = 0)."""
+    gh, gw = surf.get("gh", 0.0), surf.get("gw", 0.0)
+    if not (float(gw) > 0):
+        z = torch.zeros_like(rho)
+        return z, z, z
+    e = torch.exp(-rho / (gw * gw))
+    return gh * (e - 1.0), -gh / (gw * gw) * e, gh / (gw ** 4) * e
+
+
 def sag_and_grad(surf, x, y):
     """Returns (sag, dsag/dx, dsag/dy, valid)."""
     rho = x * x + y * y
@@ -125,9 +138,11 @@ def sag_and_grad(surf, x, y):
     valid = arg > 0
     arg_s = torch.where(valid, arg, torch.ones_like(arg))
     sq = torch.sqrt(arg_s)
-    sag = c * rho / (1.0 + sq) + A4 * rho ** 2 + A6 * rho ** 3 + A8 * rho ** 4 + A10 * rho ** 5
+    g0, g1, _ = _gauss_terms(surf, rho)
+    sag = c * rho / (1.0 + sq) + A4 * rho ** 2 + A6 * rho ** 3 + A8 * rho ** 4 + A10 * rho ** 5 \
+        + g0
     dsdrho = c / (2.0 * sq) + 2.0 * A4 * rho + 3.0 * A6 * rho ** 2 + 4.0 * A8 * rho ** 3 \
-        + 5.0 * A10 * rho ** 4
+        + 5.0 * A10 * rho ** 4 + g1
     return sag, 2.0 * x * dsdrho, 2.0 * y * dsdrho, valid
 
 
@@ -273,7 +288,12 @@ def cis(x):
     return torch.complex(torch.cos(x), torch.sin(x))
 
 
-def transmission(phase, amp):
+def transmission(phase, amp, field="amp_phase"):
+    """Complex transmission of the DOE map: A exp(i phi) (Formalism, second
+    paragraph), or the two-phase field exp(i phi1) + exp(i phi2) of the
+    beam-splitting demonstration (the second map then holds phi2)."""
+    if field == "two_phase":
+        return torch.complex(torch.cos(phase) + torch.cos(amp), torch.sin(phase) + torch.sin(amp))
     return torch.complex(amp * torch.cos(phase), amp * torch.sin(phase))
 
 
@@ -379,9 +399,16 @@ def draw_bins(mag, prop, u, sampling):
 # READING: dr = n_s d . (X - r_s) (plane-wave tilt across the sensor),
 # <n, d> = |d_z|, point samples at pixel centres X = X_c + (m, n) pitch.
 # ----------------------------------------------------------------------------
-def trace_post_doe(surfs, s_doe, lam, p, d, opl, sensor_z):
+def trace_post_doe(surfs, s_doe, lam, p, d, opl, sensor_z, reflective=False):
+    """Secondaries from the DOE hit through the surfaces after it to the sensor;
+    after a reflective DOE they travel back through the incident medium (no
+    surface between the DOE and the sensor)."""
     alive = torch.ones(p.shape[0], dtype=torch.bool)
-    n_before = medium_index(surfs, s_doe, lam)
+    n_before = medium_index(surfs, s_doe - 1 if reflective else s_doe, lam)
+    if reflective:
+        t = (sensor_z - p[:, 2]) / d[:, 2]
+        alive = alive & (t > 0)
+        return p + t[:, None] * d, d, opl + n_before * t, alive, n_before
     for s in range(s_doe + 1, len(surfs)):
         surf = surfs[s]
         t, ok = intersect(surf, p, d)
@@ -432,10 +459,11 @@ def local_radius(surf, x, y):
     A4, A6, A8, A10 = surf["A"]
     arg = 1.0 - (1.0 + k) * c * c * rho
     sq = torch.sqrt(torch.where(arg > 0, arg, torch.ones_like(arg)))
+    _, g1, g2 = _gauss_terms(surf, rho)
     d1 = c / (2.0 * sq) + 2.0 * A4 * rho + 3.0 * A6 * rho ** 2 + 4.0 * A8 * rho ** 3 \
-        + 5.0 * A10 * rho ** 4                                     # dz/d(rho)
+        + 5.0 * A10 * rho ** 4 + g1                                # dz/d(rho)
     d2 = c * (1.0 + k) * c * c / (4.0 * sq ** 3) + 2.0 * A4 + 6.0 * A6 * rho \
-        + 12.0 * A8 * rho ** 2 + 20.0 * A10 * rho ** 3             # d2z/d(rho)2
+        + 12.0 * A8 * rho ** 2 + 20.0 * A10 * rho ** 3 + g2        # d2z/d(rho)2
     zp = 2.0 * r * d1
     zpp = 2.0 * d1 + 4.0 * rho * d2
     km = zpp / (1.0 + zp * zp) ** 1.5
@@ -501,8 +529,10 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
                    opl_doe=opl.detach().clone(), alive=alive.clone(), ray_ids=ray_ids)
     amp_in = alive.to(DT)          # READING: unit amplitude per live ray
     surf_doe = surfs[s_doe]
+    reflective = bool(doe.get("reflective", False))
     n_in = medium_index(surfs, s_doe - 1, lam)
-    n_out = medium_index(surfs, s_doe, lam)
+    # READING: a reflective DOE sends its secondaries back into the incident medium
+    n_out = n_in if reflective else medium_index(surfs, s_doe, lam)
     k_out = k0 * n_out
     u, v, nrm = tangent_frame(surf_doe, p)
     k_in_t = k0 * n_in * torch.stack([(d * u).sum(-1), (d * v).sum(-1)], dim=-1)
@@ -530,9 +560,10 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     w = torch.cat([part["w"] for _, part in parts])
     Kus = torch.cat([part["Kus"] for _, part in parts])
     Kvs = torch.cat([part["Kvs"] for _, part in parts])
-    ds = emit_direction(Kus, Kvs, u[rr], v[rr], nrm[rr], k_out)
+    ds = emit_direction(Kus, Kvs, u[rr], v[rr], nrm[rr], k_out, -1.0 if reflective else 1.0)
     a_s = amp_in[rr] * w
-    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z)
+    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s_doe, lam, p[rr], ds, opl[rr], sensor_z,
+                                             reflective)
     a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
     lc = cfg["psf_center"][lam_idx][f_idx]
     Xc = torch.stack([_t(lc[0]), _t(lc[1]), sensor_z * torch.ones((), dtype=DT)])
@@ -550,14 +581,15 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     return out
 
 
-def emit_direction(Ku, Kv, u, v, nrm, k_out):
+def emit_direction(Ku, Kv, u, v, nrm, k_out, sign=1.0):
     """Unit direction of the plane wave with tangential wavevector (Ku, Kv) in
     the frame (u, v, n) leaving the DOE into the medium of wavenumber k_out
-    (Formalism, second paragraph): (Ku u + Kv v + sqrt(k_out^2 - |K|^2) n) / k_out,
-    the forward-going (+n) root."""
+    (Formalism, second paragraph): (Ku u + Kv v + sign sqrt(k_out^2 - |K|^2) n) / k_out,
+    the forward-going root (sign +1) for a transmissive DOE, the backward one
+    (sign -1, the normal component flipped) for a reflective DOE."""
     kz2 = k_out * k_out - Ku * Ku - Kv * Kv
     kz = torch.sqrt(torch.where(kz2 > 0, kz2, torch.ones_like(kz2)))
-    return (Ku[:, None] * u + Kv[:, None] * v + kz[:, None] * nrm) / k_out
+    return (Ku[:, None] * u + Kv[:, None] * v + sign * kz[:, None] * nrm) / k_out
 
 
 def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, nrm, k_in_t,
@@ -716,7 +748,7 @@ def psf_stack(system, cfg, phase, amp, values=None, replays=None, pairs=None, ke
     L = len(cfg["lambdas"])
     F = len(cfg["fields"])
     Q = cfg["psf_q"]
-    tmap = transmission(_t(phase), _t(amp))
+    tmap = transmission(_t(phase), _t(amp), system["doe"].get("field", "amp_phase"))
     vals = None if values is None else _t(values)
     out = np.zeros((L, F, Q, Q))
     aux = {}
@@ -748,7 +780,7 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
     for l in range(L):
         for f in range(F):
             pr = l * F + f
-            tmap = transmission(ph, am)
+            tmap = transmission(ph, am, system["doe"].get("field", "amp_phase"))
             rep = None if replays is None else replays.get(pr)
             r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=True)
             Lp = eq5_loss(r["psf"], _t(target[l, f]))

@@ -32,11 +32,14 @@ LAM_C = 656.3e-6
 PARAM_FIELDS = ("curv", "conic", "A4", "A6", "A8", "A10", "gap")
 
 
-def surface(z, c=0.0, k=0.0, A=(0.0, 0.0, 0.0, 0.0), semi_ap=0.0, medium=AIR, doe=False):
-    return {"kind": "plane" if (c == 0.0 and not any(A)) else "asphere",
-            "z": float(z), "c": float(c), "k": float(k), "A": [float(a) for a in A],
+def surface(z, c=0.0, k=0.0, A=(0.0, 0.0, 0.0, 0.0), semi_ap=0.0, medium=AIR, doe=False,
+            gh=0.0, gw=0.0):
+    """Even asphere (plane when c = 0 and no A); gh, gw > 0 add the Gaussian-like
+    term gh (exp(-r^2 / gw^2) - 1) to the sag."""
+    kind = "gauss" if gw > 0 else ("plane" if (c == 0.0 and not any(A)) else "asphere")
+    return {"kind": kind, "z": float(z), "c": float(c), "k": float(k), "A": [float(a) for a in A],
             "semi_ap": float(semi_ap), "nA": float(medium[0]), "nB": float(medium[1]),
-            "doe": bool(doe)}
+            "doe": bool(doe), "gh": float(gh), "gw": float(gw)}
 
 
 def doe_desc(H, W, pitch, cx=0.0, cy=0.0):
@@ -435,6 +438,57 @@ def grating_before_lens(rays_side=64, H=512, pitch=0.0063, period_px=35, lam=700
     return system, cfg, maps
 
 
+# ----------------------------------------------------------------------------
+# Reflective conformal DOE (the curvilinear-DOE demonstration, Fig. 6): a
+# reflective DOE on a Gaussian-like substrate sag gh (exp(-r^2/gw^2) - 1) whose
+# smallest radius of curvature, gw^2 / (2 |gh|) at the vertex, is about 506
+# wavelengths; a circular aperture of 501 pixels at lambda / 2 pitch, 1 um
+# light, NA 0.5 (sensor before the DOE at the aperture radius / tan(asin 0.5)),
+# collimated along the axis.  The field is exp(i phi1) + exp(i phi2) (the
+# beam-splitting design; the amplitude map holds phi2); the maps are the
+# point-focus phases of two spots 0.1 mm apart on the sensor (for a flat DOE:
+# the substrate's sag is left for the design to compensate).
+# Patch side 128 (64 lambda, curvature bound 0.063 rad), N = 2048 draws.
+# ----------------------------------------------------------------------------
+def reflective_conformal(rays_side=64, H=501, lam=1e-3, P=128, N=2048, Q=512, psf_pitch=0.0005,
+                         sampling="mag", classes=(), curv_eps=0.1, r_min_waves=506.0,
+                         gw=0.15, sep=0.1, random_phase=0.0, na=0.5, seed=0, with_target=True,
+                         cfg_id=8):
+    pitch = lam / 2
+    r_ap = 0.5 * H * pitch
+    gh = -gw * gw / (2 * r_min_waves * lam) if gw > 0 else 0.0   # concave towards the light
+    f = r_ap / math.tan(math.asin(na))
+    surfs = [surface(0.0, semi_ap=r_ap, medium=AIR, doe=True, gh=gh, gw=gw)]
+    doe = doe_desc(H, H, pitch)
+    doe["reflective"] = True
+    doe["field"] = "two_phase"
+    system = {"surfaces": surfs, "sensor_z": -f, "doe": doe, "params": []}
+    cfg = _cfg([lam], [[0.0, 0.0]], 0.0, -2.0 * f, r_ap * (1 - 1.0 / rays_side), rays_side, Q,
+               psf_pitch, 0.0, P, N, sampling, seed=seed)
+    cfg["psf_center"] = [[[0.0, 0.0]]]
+    cfg["patch_classes"] = [int(q) for q in classes]
+    cfg["curv_eps"] = float(curv_eps)
+    x = doe["x0"] + np.arange(H) * pitch
+    y = doe["y0"] + np.arange(H) * pitch
+    # point-focus phases of the two spots (x = +-sep/2 on the sensor plane, a
+    # distance f in front of a flat DOE): -k0 |(x, y, 0) - (xs, 0, -f)|
+    k0 = 2 * math.pi / lam
+    phi1 = np.mod(-k0 * np.sqrt((x[None, :] - 0.5 * sep) ** 2 + y[:, None] ** 2 + f * f), 2 * math.pi)
+    phi2 = np.mod(-k0 * np.sqrt((x[None, :] + 0.5 * sep) ** 2 + y[:, None] ** 2 + f * f), 2 * math.pi)
+    if random_phase > 0:
+        rng = np.random.default_rng(20260000 + cfg_id)
+        phi1 = phi1 + random_phase * bandlimited_uniform(H, H, 0.25, rng)
+        phi2 = phi2 + random_phase * bandlimited_uniform(H, H, 0.25, rng)
+    target = None
+    if with_target:
+        NA = na
+        target = (airy_target(Q, psf_pitch, lam, NA, (sep / 2 / psf_pitch, 0.0), (0.0, 0.0)) +
+                  airy_target(Q, psf_pitch, lam, NA, (-sep / 2 / psf_pitch, 0.0), (0.0, 0.0)))
+        target = (target / target.sum())[None, None].astype(np.float32)
+    maps = {"phase": phi1.astype(np.float32), "amp": phi2.astype(np.float32), "target": target}
+    return system, cfg, maps
+
+
 def workload(name):
     """Named full-size workloads."""
     if name == "singlet_zoneplate":
@@ -445,4 +499,8 @@ def workload(name):
         return conformal_sphere()
     if name == "two_lens_hybrid":
         return two_lens_hybrid()
+    if name == "grating_before_lens":
+        return grating_before_lens()
+    if name == "reflective_conformal":
+        return reflective_conformal()
     raise KeyError(name)
