@@ -57,7 +57,7 @@ typedef enum {
   RW_ERR_UNSUPPORTED = 7    /* a valid request outside what the kernels cover */
 } rw_status;
 
-enum { RW_SURF_ASPHERE = 0, RW_SURF_PLANE = 1 };
+enum { RW_SURF_ASPHERE = 0, RW_SURF_PLANE = 1, RW_SURF_GAUSS = 2 };
 
 /* One refractive surface of the sequential system (even asphere or plane):
  * sag z(r) = c r^2 / (1 + sqrt(1 - (1 + conic) c^2 r^2)) + A4 r^4 + A6 r^6 + A8 r^8 + A10 r^10
@@ -74,14 +74,27 @@ typedef struct {
   double asph[4];           /* A4, A6, A8, A10 */
   double semi_aperture;
   double n_A, n_B;
+  /* gauss_width > 0 (kind RW_SURF_GAUSS): the Gaussian-like substrate of the conformal
+   * DOE demonstration (Fig. 6b) adds gauss_height (exp(-r^2 / gauss_width^2) - 1) to the
+   * sag (zero at the vertex; vertex radius gauss_width^2 / (2 |gauss_height|)). */
+  double gauss_height, gauss_width;
 } rw_surface;
 
 /* DOE map on the xy projection of its surface (the paper's conformal DOE is defined
  * "as projected to a flat xy-plane"); the map extent is the system stop. */
+enum { RW_FIELD_AMP_PHASE = 0, RW_FIELD_TWO_PHASE = 1 };
 typedef struct {
   int H, W;
   double pitch;
   double x0, y0;            /* centre of pixel (0, 0) */
+  /* 1: a reflective DOE (the conformal demonstration): the secondaries leave with
+   * the normal component of their direction flipped, back into the medium before
+   * the DOE surface, which must be the last surface; the sensor lies in front of it. */
+  int reflective;
+  /* RW_FIELD_AMP_PHASE: t = A exp(i phi) from the (doe_phase, doe_amp) maps;
+   * RW_FIELD_TWO_PHASE: t = exp(i phi1) + exp(i phi2) (the beam-splitting design),
+   * doe_phase holding phi1 and doe_amp phi2, and d_phase / d_amp their gradients. */
+  int field;
 } rw_doe_desc;
 
 enum { RW_PARAM_CURV = 0, RW_PARAM_CONIC = 1, RW_PARAM_A4 = 2, RW_PARAM_A6 = 3,

@@ -542,6 +542,10 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     return fail(RW_ERR_SHAPE, "n_ssr must be in [1, 2048]");
   if (doe->H < 1 || doe->W < 1 || !(doe->pitch > 0))
     return fail(RW_ERR_SHAPE, "bad DOE map description");
+  if (doe->field != RW_FIELD_AMP_PHASE && doe->field != RW_FIELD_TWO_PHASE)
+    return fail(RW_ERR_INVALID_ARG, "bad DOE field mode");
+  if (doe->reflective && s_doe != n_surf - 1)
+    return fail(RW_ERR_UNSUPPORTED, "a reflective DOE must be the last surface");
   if (cfg->precision == RW_PREC_FP64 && M > 128)
     return fail(RW_ERR_UNSUPPORTED, "FP64 supports M <= 128");
   if (cfg->n_patch_class < 0 || cfg->n_patch_class > 3)
@@ -591,7 +595,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->W = doe->W;
   pl->planar_doe = surfaces[s_doe].curvature == 0.0 && surfaces[s_doe].conic == 0.0 &&
                    surfaces[s_doe].asph[0] == 0.0 && surfaces[s_doe].asph[1] == 0.0 &&
-                   surfaces[s_doe].asph[2] == 0.0 && surfaces[s_doe].asph[3] == 0.0;
+                   surfaces[s_doe].asph[2] == 0.0 && surfaces[s_doe].asph[3] == 0.0 &&
+                   !(surfaces[s_doe].gauss_width > 0.0);
   for (int i = 0; i < n_params; ++i)
     if (params[i].surface == s_doe && params[i].field != RW_PARAM_GAP) pl->planar_doe = false;
   pl->has_post = s_doe + 1 < n_surf;
@@ -675,6 +680,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   dc.curv_eps = cfg->curv_eps;
   dc.tau = cfg->tau > 0.0 ? cfg->tau : 1.0;
   dc.planar = pl->planar_doe ? 1 : 0;
+  dc.reflective = doe->reflective ? 1 : 0;
+  dc.ns_idx = doe->reflective ? s_doe : n_surf;
   dc.launch_z = cfg->launch_z; dc.launch_half = cfg->launch_half; dc.psf_pitch = cfg->psf_pitch;
   dc.beta = pl->beta;
   dc.key0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -704,7 +711,9 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   for (int s = 0; s < n_surf; ++s) {
     const rw_surface& q = surfaces[s];
     base[s] = {q.z_vertex, q.curvature, q.conic, q.asph[0], q.asph[1], q.asph[2], q.asph[3],
-               q.semi_aperture, q.kind, q.carries_doe};
+               q.semi_aperture, q.kind, q.carries_doe,
+               q.gauss_width > 0.0 ? q.gauss_height : 0.0,
+               q.gauss_width > 0.0 ? q.gauss_width : 0.0};
   }
   std::vector<DevParam> prm(std::max(n_params, 1));
   for (int i = 0; i < n_params; ++i) prm[i] = {params[i].surface, params[i].field, params[i].scale};
@@ -975,10 +984,10 @@ static rw_status fwd_prologue(rw_plan* pl, const float* lens_params, const float
   const int nmap = pl->H * pl->W;
   if (dbl_f)
     hipLaunchKernelGGL(k_tmap<double>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
-                       doe_amp, (C2<double>*)(b + pl->off_tmap), nmap);
+                       doe_amp, (C2<double>*)(b + pl->off_tmap), nmap, pl->doe.field);
   else
     hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
-                       doe_amp, (C2<float>*)(b + pl->off_tmap), nmap);
+                       doe_amp, (C2<float>*)(b + pl->off_tmap), nmap, pl->doe.field);
   HIPCHK(hipGetLastError());
   zero<unsigned long long>(b + pl->off_stats, RW_N_STATS, st);
   return RW_OK;
@@ -1311,11 +1320,11 @@ static rw_status bwd_epilogue(rw_plan* pl, void* ws, float* d_phase, float* d_am
   if (pl->cfg.precision == RW_PREC_FP64)
     hipLaunchKernelGGL(k_dmaps<double>, dim3((n + 255) / 256), dim3(256), 0, st,
                        (const float*)pl->fwd_phase, (const float*)pl->fwd_amp,
-                       (const C2<double>*)(b + pl->off_gt), d_phase, d_amp, n);
+                       (const C2<double>*)(b + pl->off_gt), d_phase, d_amp, n, pl->doe.field);
   else
     hipLaunchKernelGGL(k_dmaps<float>, dim3((n + 255) / 256), dim3(256), 0, st,
                        (const float*)pl->fwd_phase, (const float*)pl->fwd_amp,
-                       (const C2<float>*)(b + pl->off_gt), d_phase, d_amp, n);
+                       (const C2<float>*)(b + pl->off_gt), d_phase, d_amp, n, pl->doe.field);
   if (want_lens)
     hipLaunchKernelGGL(k_lens_map, dim3(1), dim3(64), 0, st, pl->d_cfg, pl->d_prm,
                        (const double*)(b + pl->off_lensg), d_lens);

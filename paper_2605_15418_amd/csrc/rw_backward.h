@@ -117,7 +117,7 @@ __device__ __forceinline__ void direction_cograd(const DoeArgs& a, const RayCtx&
                                                  double gds[3]) {
   const DevCfg& cfg = *a.cfg;
   const DevPair& pr = a.pairs[c.pair];
-  const double ns = pr.n_med[cfg.n_surf];
+  const double ns = pr.n_med[cfg.ns_idx];
   const double k0 = c.k0;
   const double Xc[3] = {pr.pc[0], pr.pc[1], a.live->sensor_z};
   // phi0 = k0 (OPL + ns ds . (Xc - p)),  w = k0 ns psf_pitch (ds_x, ds_y)
@@ -128,13 +128,14 @@ __device__ __forceinline__ void direction_cograd(const DoeArgs& a, const RayCtx&
 }
 
 // dL/dK of the secondary's tangential wavevector from its direction cogradient:
-// ds = (Ku u + Kv v + kz n) / k_out, kz = sqrt(k_out^2 - Ku^2 - Kv^2).
+// ds = (Ku u + Kv v + sgn kz n) / k_out, kz = sqrt(k_out^2 - Ku^2 - Kv^2), sgn = -1
+// after a reflective DOE.
 __device__ __forceinline__ void wavevector_cograd(const RayCtx& c, const Secondary& sec,
                                                   const double gds[3], double& gKu,
                                                   double& gKv) {
   const double gu = gds[0] * c.u[0] + gds[1] * c.u[1] + gds[2] * c.u[2];
   const double gv = gds[0] * c.v[0] + gds[1] * c.v[1] + gds[2] * c.v[2];
-  const double gn = gds[0] * c.n[0] + gds[1] * c.n[1] + gds[2] * c.n[2];
+  const double gn = c.sgn * (gds[0] * c.n[0] + gds[1] * c.n[1] + gds[2] * c.n[2]);
   gKu = (gu - gn * sec.Ku / sec.kz) / c.k_out;
   gKv = (gv - gn * sec.Kv / sec.kz) / c.k_out;
 }
@@ -144,7 +145,7 @@ __device__ __forceinline__ void incident_from_wavelet(const DoeArgs& a, const Ra
                                                       const WaveletAdj& wa, IncAcc& acc) {
   const DevCfg& cfg = *a.cfg;
   const DevPair& pr = a.pairs[c.pair];
-  const double ns = pr.n_med[cfg.n_surf];
+  const double ns = pr.n_med[cfg.ns_idx];
   const double k0 = c.k0;
   const double ds[3] = {sec.dsx, sec.dsy, sec.dsz};
   acc.gopl += k0 * wa.g_phi0;
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_post_bwd(DoeArgs a) {
     const double kz = sqrt(c.k_out * c.k_out - Ku * Ku - Kv * Kv);
     double ds[3], p[3], d[3], pe[kPostMax][3], de[kPostMax][3];
     for (int q = 0; q < 3; ++q) {
-      ds[q] = (Ku * c.u[q] + Kv * c.v[q] + kz * c.n[q]) / c.k_out;
+      ds[q] = (Ku * c.u[q] + Kv * c.v[q] + c.sgn * kz * c.n[q]) / c.k_out;
       p[q] = c.p[q];
       d[q] = ds[q];
     }
@@ -280,6 +281,8 @@ __global__ __launch_bounds__(256) void k_post_bwd(DoeArgs a) {
       sf.A6 = dvar<kNT>(dsf.A6, 10);
       sf.A8 = dvar<kNT>(dsf.A8, 11);
       sf.A10 = dvar<kNT>(dsf.A10, 12);
+      sf.gh = dconst<kNT>(dsf.gh);
+      sf.gw = dconst<kNT>(dsf.gw);
       D tt;
       intersect(sf, pd, dd, tt);
       D qq[3];
@@ -459,13 +462,21 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
 // ---------------------------------------------------- dL/dt -> dphi, dA ---
 template <class Tg>
 __global__ void k_dmaps(const float* phase, const float* amp, const C2<Tg>* gt, float* dphi,
-                        float* damp, int n) {
+                        float* damp, int n, int two_phase) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s, c;
   sincos((double)phase[i], &s, &c);
-  const double a = amp[i];
   const double gr = gt[i].re, gi = gt[i].im;
+  if (two_phase) {
+    // t = e^{i phi1} + e^{i phi2}: dL/dphi_k = Im(conj(e^{i phi_k}) g)
+    double s2, c2;
+    sincos((double)amp[i], &s2, &c2);
+    dphi[i] = (float)(c * gi - s * gr);
+    damp[i] = (float)(c2 * gi - s2 * gr);
+    return;
+  }
+  const double a = amp[i];
   // t = A e^{i phi}: dL/dphi = Im(conj(t) g), dL/dA = Re(conj(e^{i phi}) g)
   dphi[i] = (float)(a * (c * gi - s * gr));
   damp[i] = (float)(c * gr + s * gi);
@@ -518,6 +529,8 @@ static __global__ __launch_bounds__(256) void k_trace_bwd(const DevCfg* cfg, con
       sf.A6 = dvar<kNT>(ds.A6, 10);
       sf.A8 = dvar<kNT>(ds.A8, 11);
       sf.A10 = dvar<kNT>(ds.A10, 12);
+      sf.gh = dconst<kNT>(ds.gh);
+      sf.gw = dconst<kNT>(ds.gw);
       D tt;
       if (!intersect(sf, p, d, tt)) break;
       D q[3];

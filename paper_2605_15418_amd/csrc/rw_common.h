@@ -103,6 +103,12 @@ template <int NT> __device__ __forceinline__ Dual<NT> operator*(const Dual<NT>& 
 template <int NT> __device__ __forceinline__ Dual<NT> operator*(double b, const Dual<NT>& a) { return a * b; }
 template <int NT> __device__ __forceinline__ Dual<NT> operator/(const Dual<NT>& a, double b) { return a * (1.0 / b); }
 template <int NT> __device__ __forceinline__ Dual<NT> operator/(double a, const Dual<NT>& b) { return dconst<NT>(a) / b; }
+template <int NT> __device__ __forceinline__ Dual<NT> exp(const Dual<NT>& a) {
+  Dual<NT> r; r.v = ::exp(a.v);
+#pragma unroll
+  for (int i = 0; i < NT; ++i) r.d[i] = a.d[i] * r.v;
+  return r;
+}
 template <int NT> __device__ __forceinline__ Dual<NT> sqrt(const Dual<NT>& a) {
   Dual<NT> r; r.v = ::sqrt(a.v); const double h = 0.5 / r.v;
 #pragma unroll
@@ -145,14 +151,16 @@ __device__ __forceinline__ double draw_uniform(uint32_t k0, uint32_t k1, uint32_
 struct DevSurf {            // live prescription after lens parameters are applied
   double z, c, k, A4, A6, A8, A10, semi_ap;
   int kind, doe;
+  double gh, gw;            // Gaussian-like term gh (exp(-r^2/gw^2) - 1) when gw > 0
 };
 
-template <class S> struct Surf { S z, c, k, A4, A6, A8, A10; };
+template <class S> struct Surf { S z, c, k, A4, A6, A8, A10, gh, gw; };
 
 template <class S>
 __device__ __forceinline__ Surf<S> surf_of(const DevSurf& s) {
   return {Lit<S>::of(s.z), Lit<S>::of(s.c), Lit<S>::of(s.k), Lit<S>::of(s.A4),
-          Lit<S>::of(s.A6), Lit<S>::of(s.A8), Lit<S>::of(s.A10)};
+          Lit<S>::of(s.A6), Lit<S>::of(s.A8), Lit<S>::of(s.A10), Lit<S>::of(s.gh),
+          Lit<S>::of(s.gw)};
 }
 
 // Even-asphere sag and its xy gradient; false where the conic root is imaginary.
@@ -169,6 +177,15 @@ __device__ __forceinline__ bool sag_grad(const Surf<S>& s, const S& x, const S& 
   const S ds = s.c / (Lit<S>::of(2.0) * sq) + Lit<S>::of(2.0) * s.A4 * rho +
                Lit<S>::of(3.0) * s.A6 * r2 + Lit<S>::of(4.0) * s.A8 * r2 * rho +
                Lit<S>::of(5.0) * s.A10 * r2 * r2;
+  if (val(s.gw) > 0.0) {
+    const S iw2 = Lit<S>::of(1.0) / (s.gw * s.gw);
+    const S e = exp(-(rho * iw2));
+    sag = sag + s.gh * (e - Lit<S>::of(1.0));
+    const S dg = -(s.gh * iw2 * e);
+    sx = Lit<S>::of(2.0) * x * (ds + dg);
+    sy = Lit<S>::of(2.0) * y * (ds + dg);
+    return true;
+  }
   sx = Lit<S>::of(2.0) * x * ds;
   sy = Lit<S>::of(2.0) * y * ds;
   return true;
@@ -214,10 +231,15 @@ __device__ __forceinline__ double local_radius(const Surf<double>& s, double x, 
   const double rho = x * x + y * y, r = sqrt(rho);
   const double arg = 1.0 - (1.0 + s.k) * s.c * s.c * rho;
   const double sq = sqrt(arg > 0.0 ? arg : 1.0);
-  const double d1 = s.c / (2.0 * sq) + 2.0 * s.A4 * rho + 3.0 * s.A6 * rho * rho +
-                    4.0 * s.A8 * rho * rho * rho + 5.0 * s.A10 * rho * rho * rho * rho;
-  const double d2 = s.c * (1.0 + s.k) * s.c * s.c / (4.0 * sq * sq * sq) + 2.0 * s.A4 +
-                    6.0 * s.A6 * rho + 12.0 * s.A8 * rho * rho + 20.0 * s.A10 * rho * rho * rho;
+  double d1 = s.c / (2.0 * sq) + 2.0 * s.A4 * rho + 3.0 * s.A6 * rho * rho +
+              4.0 * s.A8 * rho * rho * rho + 5.0 * s.A10 * rho * rho * rho * rho;
+  double d2 = s.c * (1.0 + s.k) * s.c * s.c / (4.0 * sq * sq * sq) + 2.0 * s.A4 +
+              6.0 * s.A6 * rho + 12.0 * s.A8 * rho * rho + 20.0 * s.A10 * rho * rho * rho;
+  if (s.gw > 0.0) {
+    const double iw2 = 1.0 / (s.gw * s.gw), e = exp(-rho * iw2);
+    d1 += -s.gh * iw2 * e;
+    d2 += s.gh * iw2 * iw2 * e;
+  }
   const double zp = 2.0 * r * d1, zpp = 2.0 * d1 + 4.0 * rho * d2;
   const double km = fabs(zpp) / pow(1.0 + zp * zp, 1.5);
   const double ks = r > 0.0 ? fabs(2.0 * d1) / sqrt(1.0 + zp * zp) : fabs(zpp);

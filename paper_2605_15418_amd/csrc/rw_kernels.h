@@ -58,6 +58,8 @@ struct DevCfg {
   int n_class;             // patch classes (1: every ray uses P)
   int class_p[4];          // candidate patch sides, largest first (class_p[0] = P)
   double curv_eps;         // curvature bound of the class rule
+  int reflective;          // secondaries leave back into the medium before the DOE
+  int ns_idx;              // n_med index of the medium at the sensor
 };
 
 struct DevPair {
@@ -154,11 +156,17 @@ static __global__ void k_params(const DevCfg* cfg, const DevSurf* base, double b
 
 // ---------------------------------------------------------------- k_tmap ---
 template <class Tf>
-__global__ void k_tmap(const float* phase, const float* amp, C2<Tf>* tmap, int n) {
+__global__ void k_tmap(const float* phase, const float* amp, C2<Tf>* tmap, int n, int two_phase) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Tf s, c;
   sincos_any((Tf)phase[i], &s, &c);
+  if (two_phase) {                     // e^{i phi1} + e^{i phi2}, phi2 in the second map
+    Tf s2, c2;
+    sincos_any((Tf)amp[i], &s2, &c2);
+    tmap[i] = {c + c2, s + s2};
+    return;
+  }
   const Tf a = (Tf)amp[i];
   tmap[i] = {a * c, a * s};
 }
@@ -302,6 +310,7 @@ struct RayCtx {
   double u[3], v[3], n[3];
   double kin_u, kin_v, k0, k_out, n_in, n_out, dk, k2out;
   double S;                 // sampling normaliser (sum of weights), set by the forward
+  double sgn;               // +1, or -1 after a reflective DOE (normal component flipped)
   int pair, r;
   int P, cls;               // patch side and class of this ray
   size_t gid;
@@ -329,7 +338,9 @@ __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c
   c.v[2] = c.n[0] * c.u[1] - c.n[1] * c.u[0];
   c.k0 = pr.k0;
   c.n_in = pr.n_med[cfg.s_doe];
-  c.n_out = pr.n_med[cfg.s_doe + 1];
+  // a reflective DOE sends its secondaries back into the medium before it
+  c.n_out = cfg.reflective ? c.n_in : pr.n_med[cfg.s_doe + 1];
+  c.sgn = cfg.reflective ? -1.0 : 1.0;
   c.k_out = c.k0 * c.n_out;
   c.kin_u = c.k0 * c.n_in * (c.d[0] * c.u[0] + c.d[1] * c.u[1] + c.d[2] * c.u[2]);
   c.kin_v = c.k0 * c.n_in * (c.d[0] * c.v[0] + c.d[1] * c.v[1] + c.d[2] * c.v[2]);
@@ -408,9 +419,10 @@ __device__ __forceinline__ bool secondary_to_sensor(const DoeArgs& a, const RayC
   const double kz = sqrt(kz2);
   const double ik = 1.0 / c.k_out;
   Tt d[3], p[3];
+  const double skz = c.sgn * kz;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    d[i] = (Tt)((Ku * c.u[i] + Kv * c.v[i] + kz * c.n[i]) * ik);
+    d[i] = (Tt)((Ku * c.u[i] + Kv * c.v[i] + skz * c.n[i]) * ik);
     p[i] = (Tt)c.p[i];
   }
   sec.Ku = Ku; sec.Kv = Kv; sec.kz = kz;
@@ -432,7 +444,7 @@ __device__ __forceinline__ bool secondary_to_sensor(const DoeArgs& a, const RayC
   const Tt zs = (Tt)a.live->sensor_z;
   const Tt t = (zs - p[2]) / d[2];
   if (!(t > Tt(0))) return false;
-  const Tt ns = (Tt)pr.n_med[cfg.n_surf];
+  const Tt ns = (Tt)pr.n_med[cfg.ns_idx];
 #pragma unroll
   for (int i = 0; i < 3; ++i) p[i] += t * d[i];
   opl += ns * t;

@@ -15,7 +15,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librw.so")
 
-RW_SURF_ASPHERE, RW_SURF_PLANE = 0, 1
+RW_SURF_ASPHERE, RW_SURF_PLANE, RW_SURF_GAUSS = 0, 1, 2
+FIELDS = {"amp_phase": 0, "two_phase": 1}
 PARAM_FIELDS = {"curv": 0, "conic": 1, "A4": 2, "A6": 3, "A8": 4, "A10": 5, "gap": 6}
 SAMPLING = {"mag": 0, "uni": 1, "full": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
@@ -39,12 +40,14 @@ class rw_surface(ctypes.Structure):
                 ("z_vertex", ctypes.c_double), ("curvature", ctypes.c_double),
                 ("conic", ctypes.c_double), ("asph", ctypes.c_double * 4),
                 ("semi_aperture", ctypes.c_double), ("n_A", ctypes.c_double),
-                ("n_B", ctypes.c_double)]
+                ("n_B", ctypes.c_double), ("gauss_height", ctypes.c_double),
+                ("gauss_width", ctypes.c_double)]
 
 
 class rw_doe_desc(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("pitch", ctypes.c_double),
-                ("x0", ctypes.c_double), ("y0", ctypes.c_double)]
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("reflective", ctypes.c_int),
+                ("field", ctypes.c_int)]
 
 
 class rw_param_ref(ctypes.Structure):
@@ -161,7 +164,10 @@ class Plan:
         surfs = system["surfaces"]
         arr = (rw_surface * len(surfs))()
         for i, s in enumerate(surfs):
-            arr[i].kind = RW_SURF_PLANE if s["kind"] == "plane" else RW_SURF_ASPHERE
+            arr[i].kind = {"plane": RW_SURF_PLANE, "gauss": RW_SURF_GAUSS}.get(s["kind"],
+                                                                             RW_SURF_ASPHERE)
+            arr[i].gauss_height = s.get("gh", 0.0)
+            arr[i].gauss_width = s.get("gw", 0.0)
             arr[i].carries_doe = int(bool(s.get("doe", False)))
             arr[i].z_vertex = s["z"]
             arr[i].curvature = s["c"]
@@ -172,7 +178,9 @@ class Plan:
             arr[i].n_A = s["nA"]
             arr[i].n_B = s["nB"]
         d = system["doe"]
-        doe = rw_doe_desc(d["H"], d["W"], d["pitch"], d["x0"], d["y0"])
+        doe = rw_doe_desc(d["H"], d["W"], d["pitch"], d["x0"], d["y0"],
+                          int(bool(d.get("reflective", False))),
+                          FIELDS[d.get("field", "amp_phase")])
         prm = system.get("params", [])
         parr = (rw_param_ref * max(1, len(prm)))()
         for i, p in enumerate(prm):
