@@ -498,6 +498,12 @@ def ray_patch_sides(surf, p, pitch, cfg):
     return out
 
 
+def detach_pdf(cfg):
+    """Gradient mode with the sampling density held constant (the unbiased variant
+    of the frozen-draw derivative of Eq. 1)."""
+    return bool(cfg.get("detach_pdf", False)) or cfg.get("grad", "G1") == "G1_DETACH"
+
+
 def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
                  keep=False, ray_subset=None):
     """Returns dict with field U [Q, Q] (complex, differentiable), PSF, and
@@ -626,12 +632,16 @@ def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, n
         zero = torch.zeros_like(UJ)
         if sampling == "mag":
             Sg = torch.where(propf, Utf.abs(), torch.zeros((), dtype=DT)).sum(1)
-            if cfg.get("detach_pdf", False):
-                Sg = Sg.detach()
             magJ = UJ.abs()
             ok = valid & (magJ > 0)
             magJ = torch.where(ok, magJ, torch.ones_like(magJ))
-            w = torch.where(ok, UJ * (Sg[rr] / (M * M * Nd * magJ)), zero)
+            scale = Sg[rr] / (M * M * Nd * magJ)             # 1 / (M^2 N p_J)
+            if detach_pdf(cfg):
+                # READING: the density p_J = |U~_J| / S enters as a constant; the
+                # gradient then flows through U~_J alone, and its mean over the
+                # draws is the FULL-mode gradient of any loss linear in the field
+                scale = scale.detach()
+            w = torch.where(ok, UJ * scale, zero)
         else:
             nprop = propf.sum(1).to(DT)
             w = torch.where(valid, UJ * (nprop[rr] / (M * M * Nd)), zero)
