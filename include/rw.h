@@ -113,12 +113,15 @@ enum { RW_SAMPLE_MAG = 0, RW_SAMPLE_UNI = 1, RW_SAMPLE_FULL = 2 };
 enum { RW_PREC_FP64 = 0, RW_PREC_MIXED = 1, RW_PREC_FP32 = 2 };
 /* Gradient of the Monte Carlo draws (reparameterised sampling, Fig. 1c):
  * G1: the a.e. derivative with the drawn bins held fixed;
+ * G1_DETACH: the same with the sampling density p held constant as well (only the
+ *     drawn bins' spectrum values carry the gradient); its mean over the draws is
+ *     the FULL-mode gradient of any loss linear in the sensor field;
  * G2: Gumbel-softmax straight-through -- per draw the hard one-hot sample keeps its
  *     value while the gradient flows through softmax((log p + z) / tau), z the
  *     replica's Gumbel perturbations regenerated conditioned on the drawn bin; both
  *     the weight and the wavevector are relaxed.  Differs from G1 only for p ~ |U~|
  *     (MAG); needs the sensor directly after the DOE. */
-enum { RW_GRAD_G1 = 0, RW_GRAD_G2 = 1 };
+enum { RW_GRAD_G1 = 0, RW_GRAD_G2 = 1, RW_GRAD_G1_DETACH = 2 };
 
 typedef struct {
   int n_lambda;

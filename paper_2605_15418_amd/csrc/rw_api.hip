@@ -534,7 +534,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
     return fail(RW_ERR_SHAPE, "empty ray grid, wavelength or field list");
   if (cfg->sampling < 0 || cfg->sampling > 2 || cfg->precision < 0 || cfg->precision > 2)
     return fail(RW_ERR_INVALID_ARG, "bad sampling or precision");
-  if (cfg->grad != RW_GRAD_G1 && cfg->grad != RW_GRAD_G2)
+  if (cfg->grad != RW_GRAD_G1 && cfg->grad != RW_GRAD_G2 && cfg->grad != RW_GRAD_G1_DETACH)
     return fail(RW_ERR_INVALID_ARG, "bad gradient mode");
   if (cfg->grad == RW_GRAD_G2 && !(cfg->tau > 0.0))
     return fail(RW_ERR_INVALID_ARG, "the G2 temperature must be positive");

@@ -376,6 +376,66 @@ __device__ __forceinline__ void stage_lines256(C2<Tf>* ls, const C2<Tf>* buf, in
   }
 }
 
+// Inverse column pass of the adjoint (M = 256): staged line l <- column c0 + l of
+// the spectrum cogradient, formed as the spectrum is loaded: the p_mag
+// normaliser term fS X / |X| (plus the G2 term (g / |X| - d2s) X / |X|) on
+// propagating bins, zero elsewhere; then the draws' terms of bins in these
+// columns are added in LDS (entries dl[0..N), bin index k = row * sm + column).
+template <class Tf>
+__device__ __forceinline__ void stage_cograd256(C2<Tf>* ls, const C2<Tf>* buf, int sm, int c0,
+                                                const Span* span, bool mag, Tf fS,
+                                                const float* dlg, Tf d2s,
+                                                const DrawEnt<Tf>* dl, int N) {
+  constexpr int KB = 16, M = 256;
+  const int tid = opaque_tid();
+  for (int i0 = tid; i0 < M * kLines256; i0 += kDoeThreads * KB) {
+    C2<Tf> v[KB];
+    float g[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = i0 + k * kDoeThreads;
+      const int l = i & 63, e = i >> 6;
+      v[k] = C2<Tf>{Tf(0), Tf(0)};
+      g[k] = 0.0f;
+      if (i < M * kLines256) {
+        v[k] = buf[(size_t)e * sm + c0 + l];
+        if (dlg) g[k] = dlg[e * M + c0 + l];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int i = i0 + k * kDoeThreads;
+      if (i >= M * kLines256) break;
+      const int l = i & 63, ky = i >> 6, kx = c0 + l;
+      const int jx = kx < M / 2 ? kx : kx - M, jy = ky < M / 2 ? ky : ky - M;
+      const Span sp = span[jx + M / 2];
+      C2<Tf> out = {Tf(0), Tf(0)};
+      if (mag && jy >= sp.lo && jy <= sp.hi) {
+        const C2<Tf> X = v[k];
+        const Tf m2 = X.re * X.re + X.im * X.im;
+        if (m2 > Tf(0)) {
+          const Tf im = inv_sqrt(m2);
+          Tf f = fS * im;
+          if (dlg) f += ((Tf)g[k] * im - d2s) * im;
+          out = {X.re * f, X.im * f};
+        }
+      }
+      ls[l * kLS256 + sk256(ky)] = out;
+    }
+  }
+  if (dl) {
+    __syncthreads();
+    for (int i = tid; i < N; i += kDoeThreads) {
+      const DrawEnt<Tf> e = dl[i];
+      if (e.k < 0) continue;
+      const int row = e.k / sm, col = e.k - row * sm;
+      if (col < c0 || col >= c0 + kLines256) continue;
+      atomicAdd(&ls[(col - c0) * kLS256 + sk256(row)].re, e.g.re);
+      atomicAdd(&ls[(col - c0) * kLS256 + sk256(row)].im, e.g.im);
+    }
+  }
+}
+
 // 256-point transforms of nl staged lines in place (natural order in and out),
 // n = a + 16 b, k = k1 + 16 k2: pass A, per (line, a), the 16-point DFT over b
 // times W_256^(a k1), back into slots a + 16 k1; pass B, per (line, k1), the
@@ -1340,6 +1400,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int h = kTiled ? 0 : (t & 1);
       const bool lead = kTiled || h == 0;   // writes the draw's entries
       const bool side = kTiled || h == 1;   // accumulates the incident-state cogradient
+      // M = 256: the normaliser and draw terms are formed as the inverse column
+      // pass stages the spectrum (no extra pass over the global buffer)
+      Tf fold_fS = Tf(0), fold_d2s = Tf(0);
+      const float* fold_dlg = nullptr;
+      const DrawEnt<Tf>* fold_dl = nullptr;
       if constexpr (!kFull) {
         const double S = c.S;
         DrawEnt<Tf>* gdl = (DrawEnt<Tf>*)a.dlist + (size_t)blockIdx.x * N;
@@ -1375,7 +1440,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                 ok = wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
               if (ok) {
                 C2<double> gU;
-                if (cfg.sampling == 0) {
+                if (cfg.sampling == 0 && cfg.grad == kGradG1Detach) {
+                  // p held constant: w = U scale / |X| with a constant factor
+                  gU = {wa.g_w.re * scale / mag, wa.g_w.im * scale / mag};
+                } else if (cfg.sampling == 0) {
                   const double hr = (double)U.re / mag, hi_ = (double)U.im / mag;
                   if (lead) dLdS += (wa.g_w.re * hr + wa.g_w.im * hi_) * inv_m2 / N;
                   const double gr = wa.g_w.re * scale, gi = wa.g_w.im * scale;
@@ -1430,52 +1498,59 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             dlg = dg;
           }
         }
-        // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins;
-        // each lane keeps one column (M divides the block size)
-        {
-          const int kx = t % M;
-          const int jx = kx < M / 2 ? kx : kx - M;
-          const Span sp = s.span[jx + M / 2];
-          const bool mag = cfg.sampling == 0;
-          const Tf fS = (Tf)dLdS;
-          // batches of SB rows: a lane's bins are distinct, so every load of a
-          // batch is issued before its stores
-          constexpr int RS = kDoeThreads / M, SB = M / RS >= 8 ? 8 : (M / RS >= 1 ? M / RS : 1);
-          for (int ky0 = t / M; ky0 < M; ky0 += SB * RS) {
-            C2<Tf> xv[SB];
+        if constexpr (M == 256) {
+          fold_fS = (Tf)dLdS;
+          fold_dlg = dlg;
+          fold_d2s = dlg ? (Tf)(D2 / S) : Tf(0);
+          fold_dl = S > 0.0 ? gdl : nullptr;
+        } else {
+          // S-term (p_mag): dL/dX_k = dL/dS X_k / |X_k| on propagating bins;
+          // each lane keeps one column (M divides the block size)
+          {
+            const int kx = t % M;
+            const int jx = kx < M / 2 ? kx : kx - M;
+            const Span sp = s.span[jx + M / 2];
+            const bool mag = cfg.sampling == 0;
+            const Tf fS = (Tf)dLdS;
+            // batches of SB rows: a lane's bins are distinct, so every load of a
+            // batch is issued before its stores
+            constexpr int RS = kDoeThreads / M, SB = M / RS >= 8 ? 8 : (M / RS >= 1 ? M / RS : 1);
+            for (int ky0 = t / M; ky0 < M; ky0 += SB * RS) {
+              C2<Tf> xv[SB];
 #pragma unroll
-            for (int q = 0; q < SB; ++q) {
-              const int ky = ky0 + q * RS;
-              xv[q] = ky < M ? buf[Gm::at(ky, kx)] : C2<Tf>{Tf(0), Tf(0)};
-            }
-#pragma unroll
-            for (int q = 0; q < SB; ++q) {
-              const int ky = ky0 + q * RS;
-              const int jy = ky < M / 2 ? ky : ky - M;
-              const C2<Tf> X = xv[q];
-              C2<Tf> v = {Tf(0), Tf(0)};
-              if (mag && jy >= sp.lo && jy <= sp.hi) {
-                const Tf m2 = X.re * X.re + X.im * X.im;
-                if (m2 > Tf(0)) {
-                  const Tf im = inv_sqrt(m2);
-                  Tf f = fS * im;
-                  if (kG2 && dlg) f += ((Tf)dlg[ky * M + kx] * im - (Tf)(D2 / S)) * im;
-                  v = {X.re * f, X.im * f};
-                }
+              for (int q = 0; q < SB; ++q) {
+                const int ky = ky0 + q * RS;
+                xv[q] = ky < M ? buf[Gm::at(ky, kx)] : C2<Tf>{Tf(0), Tf(0)};
               }
-              if (ky < M) buf[Gm::at(ky, kx)] = v;
+#pragma unroll
+              for (int q = 0; q < SB; ++q) {
+                const int ky = ky0 + q * RS;
+                const int jy = ky < M / 2 ? ky : ky - M;
+                const C2<Tf> X = xv[q];
+                C2<Tf> v = {Tf(0), Tf(0)};
+                if (mag && jy >= sp.lo && jy <= sp.hi) {
+                  const Tf m2 = X.re * X.re + X.im * X.im;
+                  if (m2 > Tf(0)) {
+                    const Tf im = inv_sqrt(m2);
+                    Tf f = fS * im;
+                    if (kG2 && dlg) f += ((Tf)dlg[ky * M + kx] * im - (Tf)(D2 / S)) * im;
+                    v = {X.re * f, X.im * f};
+                  }
+                }
+                if (ky < M) buf[Gm::at(ky, kx)] = v;
+              }
             }
           }
-        }
-        __syncthreads();
-        // draw terms: each entry is re-read by the lane that wrote it
-        if (S > 0.0 && lead) {
+          __syncthreads();
+          // draw terms: each entry is re-read by the lane that wrote it
+          if (S > 0.0 && lead) {
 #pragma unroll 1
-          for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
-            const DrawEnt<Tf> e = dl_lds ? s.dl[i] : gdl[i];
-            if (e.k >= 0) {
-              atomicAdd(&buf[e.k].re, e.g.re);
-              atomicAdd(&buf[e.k].im, e.g.im);
+            for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
+              const DrawEnt<Tf> e = dl_lds ? s.dl[i] : gdl[i];
+              if (e.k >= 0) {
+                atomicAdd(&buf[e.k].re, e.g.re);
+                atomicAdd(&buf[e.k].im, e.g.im);
+              }
             }
           }
         }
@@ -1518,7 +1593,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         // rows < P (columns < P out, columns P and M - 1 as the zero border)
         C2<Tf>* ls = s.ls;
         for (int c0 = 0; c0 < M; c0 += kLines256) {
-          stage_lines256<Tf, true>(ls, buf, SM, c0, kLines256, M, M);
+          if constexpr (kFull) stage_lines256<Tf, true>(ls, buf, SM, c0, kLines256, M, M);
+          else stage_cograd256<Tf>(ls, buf, SM, c0, s.span, cfg.sampling == 0, fold_fS, fold_dlg,
+                                   fold_d2s, fold_dl, N);
           lds_fft256<Tf, +1>(ls, s.tw, kLines256, false);
           for (int i = t; i < P * kLines256; i += kDoeThreads) {
             const int r = i >> 6, cl = i & 63;
@@ -1684,26 +1761,165 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         gpx *= inv_pitch;
         gpy *= inv_pitch;
       } else {
-      // general surface: LDS-tiled scatter of every sample's 2 x 2 stencil
-      C2<Tf>* tile = buf + Gm::row(P);
+      // general surface.  Sample (m, n) sits at the fractional map position
+      // f(m, n) = xy(p + s_m u + s_n v) / pitch, affine in (m, n), and feeds the
+      // pixels floor(f) + {0, 1} in each axis.  Gather form: every pixel of a
+      // T x T tile around the patch inverts that map, visits the few samples
+      // whose stencils contain it (each (pixel, sample) pair exactly once, with
+      // the forward's own position arithmetic) and adds their sum to the block
+      // accumulator with one read-modify-write; no atomics.  When the stencils
+      // leave the tile (or the map is degenerate) every sample scatters its
+      // stencil instead.
       const double cfx = (c.p[0] - cfg.x0) * cfg.inv_pitch, cfy = (c.p[1] - cfg.y0) * cfg.inv_pitch;
       const int tx0 = (int)floor(cfx) - T / 2, ty0 = (int)floor(cfy) - T / 2;
-      if (use_tile) {
-        for (int i = t; i < T * T; i += kDoeThreads) tile[i] = {Tf(0), Tf(0)};
-        __syncthreads();
-      }
-      for (int smp = t; smp < P * P; smp += kDoeThreads) {
-        const int m = smp % P, n = smp / P;
-        const C2<Tf> gu = buf[Gm::at(n, m)];
+      const double jxm = cfg.pitch * c.u[0] * cfg.inv_pitch, jxn = cfg.pitch * c.v[0] * cfg.inv_pitch;
+      const double jym = cfg.pitch * c.u[1] * cfg.inv_pitch, jyn = cfg.pitch * c.v[1] * cfg.inv_pitch;
+      const double hc = (P - 1) * 0.5;
+      const double ex = hc * (fabs(jxm) + fabs(jxn)), ey = hc * (fabs(jym) + fabs(jyn));
+      const double det = jxm * jyn - jxn * jym;
+      const bool gather = floor(cfx - ex - 1e-6) >= tx0 && floor(cfx + ex + 1e-6) + 1 < tx0 + T &&
+                          floor(cfy - ey - 1e-6) >= ty0 && floor(cfy + ey + 1e-6) + 1 < ty0 + T &&
+                          fabs(det) > 0.25;
+      const bool lens = a.want_lens != 0;
+      const int lgP = __builtin_ctz(P);
+      // sample position arithmetic of the forward gather
+      auto sample_pos = [&](int m, int n, double& fx, double& fy) {
         const double sm = (m - (P - 1) * 0.5) * cfg.pitch;
         const double sn = (n - (P - 1) * 0.5) * cfg.pitch;
         const double qx = c.p[0] + sm * c.u[0] + sn * c.v[0];
         const double qy = c.p[1] + sm * c.u[1] + sn * c.v[1];
-        const double fx = (qx - cfg.x0) * cfg.inv_pitch, fy = (qy - cfg.y0) * cfg.inv_pitch;
+        fx = (qx - cfg.x0) * cfg.inv_pitch;
+        fy = (qy - cfg.y0) * cfg.inv_pitch;
+      };
+      if (gather) {
+        if constexpr (M == 256) {
+          // the patch gradient (rows and columns < P of the global buffer) into
+          // the staged-line area, free after the inverse transforms
+          constexpr int KC = 8;
+          for (int i0 = t; i0 < P * P; i0 += kDoeThreads * KC) {
+            C2<Tf> v[KC];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+              const int i = i0 + k * kDoeThreads;
+              v[k] = i < P * P ? buf[Gm::row(i >> lgP) + (i & (P - 1))] : C2<Tf>{Tf(0), Tf(0)};
+            }
+#pragma unroll
+            for (int k = 0; k < KC; ++k)
+              if (i0 + k * kDoeThreads < P * P) s.ls[i0 + k * kDoeThreads] = v[k];
+          }
+          __syncthreads();
+        }
+        auto gpatch = [&](int n, int m) -> C2<Tf> {
+          if constexpr (M == 256) return s.ls[(n << lgP) + m];
+          else return buf[Gm::at(n, m)];
+        };
+        const double i11 = jyn / det, i12 = -jxn / det, i21 = -jym / det, i22 = jxm / det;
+        const double rm = fabs(i11) + fabs(i12) + 1e-7, rn = fabs(i21) + fabs(i22) + 1e-7;
+        const int lx0 = tx0 - ax0, ly0 = ty0 - ay0;
+        const bool inside = lx0 >= 0 && ly0 >= 0 && lx0 + T <= AS && ly0 + T <= AS;
+        if (inside && t == 0) {
+          atomicMin(&s_box[0], lx0); atomicMin(&s_box[1], ly0);
+          atomicMax(&s_box[2], lx0 + T); atomicMax(&s_box[3], ly0 + T);
+        }
+        double lx_ = 0.0, ly_ = 0.0, lux = 0.0, luy = 0.0, lvx = 0.0, lvy = 0.0;
+        // KB pixels per lane: their accumulator and map loads are issued first
+        constexpr int KB = 4;
+        const FDiv dT(T);
+        for (int i0 = t; i0 < T * T; i0 += kDoeThreads * KB) {
+          int li[KB];               // accumulator index; -1: off the map; -2: global atomics
+          C2<Tg> old[KB];
+          C2<Tf> tp[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            const int i = i0 + k * kDoeThreads;
+            li[k] = -1;
+            old[k] = {Tg(0), Tg(0)};
+            tp[k] = {Tf(0), Tf(0)};
+            if (i < T * T) {
+              const int yy = dT.div(i), xx = i - yy * T;
+              const int x = tx0 + xx, y = ty0 + yy;
+              if (x >= 0 && x < W && y >= 0 && y < H) {
+                li[k] = inside ? (ly0 + yy) * AS + lx0 + xx : -2;
+                if (inside) old[k] = accm[li[k]];
+                if (lens) tp[k] = tm[(size_t)y * W + x];
+              }
+            }
+          }
+          C2<Tf> vs[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            vs[k] = {Tf(0), Tf(0)};
+            if (li[k] == -1) continue;
+            const int i = i0 + k * kDoeThreads;
+            const int yy = dT.div(i), xx = i - yy * T;
+            const int X = tx0 + xx, Y = ty0 + yy;
+            // lattice coordinates of the pixel; its samples lie within (rm, rn)
+            const double dxp = X - cfx, dyp = Y - cfy;
+            const double mc = i11 * dxp + i12 * dyp + hc, nc = i21 * dxp + i22 * dyp + hc;
+            const int m0 = max(0, (int)ceil(mc - rm)), m1 = min(P - 1, (int)floor(mc + rm));
+            const int n0 = max(0, (int)ceil(nc - rn)), n1 = min(P - 1, (int)floor(nc + rn));
+            C2<Tf> v = {Tf(0), Tf(0)};
+            for (int n = n0; n <= n1; ++n) {
+              for (int m = m0; m <= m1; ++m) {
+                double fx, fy;
+                sample_pos(m, n, fx, fy);
+                const double flx = floor(fx), fly = floor(fy);
+                const int ddx = X - (int)flx, ddy = Y - (int)fly;
+                if ((unsigned)ddx > 1u || (unsigned)ddy > 1u) continue;
+                const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
+                const Tf ax = ddx ? wx : Tf(1) - wx, ay = ddy ? wy : Tf(1) - wy;
+                const C2<Tf> g = gpatch(n, m);
+                v = v + g * (ax * ay);
+                if (lens) {
+                  // <g, t_pixel> times the derivative of this pixel's weight
+                  const double q = (double)g.re * tp[k].re + (double)g.im * tp[k].im;
+                  const double qx = q * (double)(ddx ? ay : -ay);
+                  const double qy = q * (double)(ddy ? ax : -ax);
+                  const double sm = (m - (P - 1) * 0.5) * cfg.pitch;
+                  const double sn = (n - (P - 1) * 0.5) * cfg.pitch;
+                  lx_ += qx; ly_ += qy;
+                  lux += sm * qx; luy += sm * qy;
+                  lvx += sn * qx; lvy += sn * qy;
+                }
+              }
+            }
+            vs[k] = v;
+          }
+          __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            if (li[k] >= 0) {
+              accm[li[k]] = {old[k].re + (Tg)vs[k].re, old[k].im + (Tg)vs[k].im};
+            } else if (li[k] == -2 && (vs[k].re != Tf(0) || vs[k].im != Tf(0))) {
+              const int i = i0 + k * kDoeThreads;
+              const int yy = dT.div(i), xx = i - yy * T;
+              atomicAdd(&gt[(size_t)(ty0 + yy) * W + tx0 + xx].re, (Tg)vs[k].re);
+              atomicAdd(&gt[(size_t)(ty0 + yy) * W + tx0 + xx].im, (Tg)vs[k].im);
+            }
+          }
+        }
+        const double ip = cfg.inv_pitch;
+        gpx += lx_ * ip; gpy += ly_ * ip;
+        gux += lux * ip; guy += luy * ip;
+        gvx += lvx * ip; gvy += lvy * ip;
+      } else {
+      // scatter of every sample's 2 x 2 stencil into an LDS tile (M = 128) or
+      // straight into dL/dt
+      C2<Tf>* tile = buf + Gm::row(P);
+      const bool tile_ok = M != 256 && use_tile;
+      if (tile_ok) {
+        for (int i = t; i < T * T; i += kDoeThreads) tile[i] = {Tf(0), Tf(0)};
+        __syncthreads();
+      }
+      for (int smp = t; smp < P * P; smp += kDoeThreads) {
+        const int m = smp & (P - 1), n = smp >> lgP;
+        const C2<Tf> gu = buf[Gm::at(n, m)];
+        double fx, fy;
+        sample_pos(m, n, fx, fy);
         const double flx = floor(fx), fly = floor(fy);
         const int ix = (int)flx, iy = (int)fly;
         const Tf wx = (Tf)(fx - flx), wy = (Tf)(fy - fly);
-        if (a.want_lens) {
+        if (lens) {
           // <g, dU/dq> with the bilinear interpolant's xy derivative at q
           auto at = [&](int y, int x) {
             return (x >= 0 && x < W && y >= 0 && y < H) ? tm[(size_t)y * W + x]
@@ -1713,6 +1929,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
                        t11 = at(iy + 1, ix + 1);
           const C2<Tf> dtx = (t01 - t00) * (Tf(1) - wy) + (t11 - t10) * wy;
           const C2<Tf> dty = (t10 - t00) * (Tf(1) - wx) + (t11 - t01) * wx;
+          const double sm = (m - (P - 1) * 0.5) * cfg.pitch;
+          const double sn = (n - (P - 1) * 0.5) * cfg.pitch;
           const double qx_ = ((double)gu.re * dtx.re + (double)gu.im * dtx.im) * cfg.inv_pitch;
           const double qy_ = ((double)gu.re * dty.re + (double)gu.im * dty.im) * cfg.inv_pitch;
           gpx += qx_; gpy += qy_;
@@ -1728,7 +1946,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             const Tf wgt = (dx ? wx : Tf(1) - wx) * (dy ? wy : Tf(1) - wy);
             const C2<Tf> v = gu * wgt;
             const int lx = x - tx0, ly = y - ty0;
-            if (use_tile && lx >= 0 && lx < T && ly >= 0 && ly < T) {
+            if (tile_ok && lx >= 0 && lx < T && ly >= 0 && ly < T) {
               atomicAdd(&tile[ly * T + lx].re, v.re);
               atomicAdd(&tile[ly * T + lx].im, v.im);
             } else {
@@ -1738,7 +1956,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           }
         }
       }
-      if (use_tile) {
+      if (tile_ok) {
         __syncthreads();
         const int lx0 = tx0 - ax0, ly0 = ty0 - ay0;
         const bool inside = lx0 >= 0 && ly0 >= 0 && lx0 + T <= AS && ly0 + T <= AS;
@@ -1760,6 +1978,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             atomicAdd(&gt[(size_t)y * W + x].im, (Tg)v.im);
           }
         }
+      }
       }
       }
       // lens: per-wave sums of the incident-state cogradient into s.acc; lanes

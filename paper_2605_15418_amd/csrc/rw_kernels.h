@@ -46,13 +46,18 @@ __device__ __forceinline__ C2<typename Prec::Tp> wavelet_cis(typename Prec::Tp p
   return {(Tp)c, (Tp)s};
 }
 
+// Gradient modes of the draws (the values of the C ABI's RW_GRAD_*): frozen
+// draws (G1), Gumbel-softmax straight-through (G2), frozen draws with the
+// sampling density held constant (G1 with p detached).
+enum { kGradG1 = 0, kGradG2 = 1, kGradG1Detach = 2 };
+
 struct DevCfg {
   int n_surf, s_doe, n_pairs, n_field, R, R2, P, M, N, Q, nf, w, sampling, H, W, n_params;
   int planar;              // DOE surface is a plane z = const: u = x, v = y, n = z
   double pitch, x0, y0, launch_z, launch_half, psf_pitch, beta;
   double inv_pitch;
   uint32_t key0, key1;
-  int grad;                // 0: frozen draws (G1), 1: Gumbel-softmax straight-through (G2)
+  int grad;                // gradient mode (kGrad*)
   double tau;              // G2 temperature
   int pad;                 // M / P
   int n_class;             // patch classes (1: every ray uses P)

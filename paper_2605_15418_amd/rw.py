@@ -20,7 +20,7 @@ FIELDS = {"amp_phase": 0, "two_phase": 1}
 PARAM_FIELDS = {"curv": 0, "conic": 1, "A4": 2, "A6": 3, "A8": 4, "A10": 5, "gap": 6}
 SAMPLING = {"mag": 0, "uni": 1, "full": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "fp32": 2}
-GRAD = {"G1": 0, "G2": 1}
+GRAD = {"G1": 0, "G2": 1, "G1_DETACH": 2}
 RW_STATIC_SCRATCH_BYTES = 256 << 20   # workspace of rw_forward_static (include/rw.h)
 AUTOTUNE_CACHE = os.path.join(_HERE, "autotune_cache.json")   # launch shapes by arch + geometry
 STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",

@@ -168,3 +168,22 @@ def test_mixed_p64_mc_gradients_with_oracle_indices(rw):
     idx = ref[3]
     rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
     _check(_gpu_grad(rw, system, cfg, maps, "mixed", replay=rep), ref, 1e-3)
+
+
+# ------------------------------------------------- density held constant ----
+def test_held_density_gradients_with_oracle_indices(rw):
+    """G1_DETACH: the draws' weights keep p_J as a constant (MIXED on the oracle's
+    indices within 1e-3; FP64 with its own draws within 1e-5), and the mode
+    differs from G1 (which also differentiates p)."""
+    system, cfg, maps = small_hologram(sampling="mag", N=48)
+    cfg_d = dict(cfg, grad="G1_DETACH")
+    ref = _oracle_grad(system, cfg_d, maps)
+    idx = ref[3]
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    gpu = _gpu_grad(rw, system, cfg_d, maps, "mixed", replay=rep)
+    _check(gpu, ref, 1e-3)
+    g1 = _gpu_grad(rw, system, cfg, maps, "mixed", replay=rep)
+    assert rel_l2(gpu[1], g1[1]) > 1e-2
+    s64, c64, m64 = small_hologram(sampling="mag", N=32, n_lambda=1, n_field_side=3)
+    c64 = dict(c64, grad="G1_DETACH")
+    _check(_gpu_grad(rw, s64, c64, m64, "fp64"), _oracle_grad(s64, c64, m64), 1e-5)
