@@ -576,13 +576,21 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
           const Span sp = span[jx + M / 2];
           Tf sum = Tf(0);
           int last = -1;
-          for (int k2 = 0; k2 < E; ++k2) {
-            const int ky = ky0 + k2;
-            const int jy = ky < M / 2 ? ky : ky - M;
-            Tf wgt = Tf(0);
-            if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(ls[cl * kLS256 + sk256(ky)], sampling);
-            sum += wgt;
-            if (wgt > Tf(0)) last = k2;
+          // groups of EB bins read before they are summed (in order)
+          constexpr int EB = 8;
+          for (int q0 = 0; q0 < E; q0 += EB) {
+            C2<Tf> xs[EB];
+#pragma unroll
+            for (int e = 0; e < EB; ++e) xs[e] = ls[cl * kLS256 + sk256(ky0 + q0 + e)];
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+              const int ky = ky0 + q0 + e;
+              const int jy = ky < M / 2 ? ky : ky - M;
+              Tf wgt = Tf(0);
+              if (jy >= sp.lo && jy <= sp.hi) wgt = samp_w(xs[e], sampling);
+              sum += wgt;
+              if (wgt > Tf(0)) last = q0 + e;
+            }
           }
           const int ch = ((jx + M / 2) * M + jys0) / E;
           chunk[ch] = (double)sum;
@@ -882,6 +890,28 @@ struct RayBlockIter {
   }
 };
 
+// Work items of a persistent DOE workgroup.  Workgroups are dispatched to the
+// eight XCDs in turn (XCD = blockIdx % 8), so XCD x takes the contiguous item
+// range [x q, (x + 1) q), q = ceil(n / 8), which its workgroups walk together:
+// the items in flight on one XCD are neighbouring ray blocks, whose patches
+// share map lines in that XCD's L2.  Other grid sizes keep the plain order.
+struct ItemOrder {
+  long long first, step, end;
+  __device__ __forceinline__ explicit ItemOrder(long long n) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G % 8 == 0 && n >= G) {
+      const long long q = (n + 7) / 8;
+      first = (long long)(b % 8) * q + b / 8;
+      step = G / 8;
+      end = min(n, (long long)(b % 8 + 1) * q);
+    } else {
+      first = b;
+      step = G;
+      end = n;
+    }
+  }
+};
+
 // ------------------------------------------------------------------ forward ---
 template <class Prec, int M, bool kLDS>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIter itr,
@@ -903,14 +933,15 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   // rays in work-list order; the class, alive flag and context word (thread
   // t < kCtxWords) of the next ray are loaded while the current one runs
   const int cnt = itr.count();
-  long long it_n = blockIdx.x;
+  const ItemOrder ord(n_items);
+  long long it_n = ord.first;
   int k_n = 0;
   long long gid_n = -1;
   int cls_n = -1;
   double alive_n = 0.0;
   uint32_t cw_n = 0;
   auto fetch = [&]() {
-    gid_n = it_n < n_items ? itr.ray(it_n, k_n, pair0) : -1;
+    gid_n = it_n < ord.end ? itr.ray(it_n, k_n, pair0) : -1;
     if (gid_n >= 0) {
       cls_n = a.ray_class[gid_n];
       alive_n = a.st[7 * a.n_total + gid_n];
@@ -918,13 +949,13 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
     }
   };
   fetch();
-  while (it_n < n_items) {                     // uniform over the workgroup
+  while (it_n < ord.end) {                     // uniform over the workgroup
     {
       const long long gid = gid_n;
       const int cls = cls_n;
       const double alive = alive_n;
       const uint32_t cw = cw_n;
-      if (++k_n == cnt) { k_n = 0; it_n += gridDim.x; }
+      if (++k_n == cnt) { k_n = 0; it_n += ord.step; }
       fetch();
       if (gid < 0 || cls != a.cls) continue;   // past the grid edge or other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
@@ -1340,7 +1371,8 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   static_assert(kDoeThreads % M == 0, "the S-term pass keeps one column per lane");
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
-  for (long long it = blockIdx.x; it < n_items; it += gridDim.x) {
+  const ItemOrder ord(n_items);
+  for (long long it = ord.first; it < ord.end; it += ord.step) {
     // anchor of the accumulator: the first live ray of the block
     if (t == 0) { s_box[0] = INT_MAX; s_box[1] = INT_MAX; s_box[2] = INT_MIN; s_box[3] = INT_MIN; }
     int ax0 = 0, ay0 = 0;
@@ -1823,7 +1855,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
         }
         double lx_ = 0.0, ly_ = 0.0, lux = 0.0, luy = 0.0, lvx = 0.0, lvy = 0.0;
         // KB pixels per lane: their accumulator and map loads are issued first
-        constexpr int KB = 4;
+        constexpr int KB = 6;
         const FDiv dT(T);
         for (int i0 = t; i0 < T * T; i0 += kDoeThreads * KB) {
           int li[KB];               // accumulator index; -1: off the map; -2: global atomics
