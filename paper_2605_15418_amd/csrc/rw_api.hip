@@ -125,7 +125,7 @@ struct rw_plan {
   double base_sensor_z;
   // workspace layout
   size_t off_live, off_tmap, off_st, off_ck, off_grid, off_t1, off_U, off_alpha, off_lossp,
-      off_stats, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
+      off_stats, off_wctr, off_scratch, off_gt, off_raygrad, off_lensg, off_G, off_rpos, off_rval,
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
       off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
@@ -270,6 +270,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.replay = replay;
   a.idx_out = idx_out;
   a.stats = (unsigned long long*)(b + pl->off_stats);
+  a.wctr = (unsigned long long*)(b + pl->off_wctr);
   a.gt = b + pl->off_gt;
   a.raygrad = (double*)(b + pl->off_raygrad);
   a.lensg = (double*)(b + pl->off_lensg);
@@ -284,6 +285,9 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
   a.cls = 0;
   return a;
 }
+
+template <class T>
+void zero(void* p, size_t n, hipStream_t st);
 
 // Ray-wave interface over whole blocks of rays (persistent workgroups).
 rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npairs,
@@ -300,6 +304,7 @@ rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npa
   for (int c = 0; c < pl->n_class; ++c) {
     DoeArgs ac = a;
     ac.cls = c;
+    zero<unsigned long long>(ac.wctr, 8, st);   // the work-item counters
     ac.tw = pl->d_tw_cls[c];
     const int M = pl->class_m[c];
     const bool lds = pl->class_lds[c];
@@ -814,6 +819,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_alpha = take(pl->n_pairs * sizeof(double));
   pl->off_lossp = take(pl->n_pairs * sizeof(double));
   pl->off_stats = take(RW_N_STATS * sizeof(unsigned long long));
+  pl->off_wctr = take(8 * sizeof(unsigned long long));
   pl->off_scratch =
       take(pl->lds_patch ? 0 : (size_t)pl->doe_blocks * doe_buf_elems(M) * pl->sz_cf);
   pl->off_ctx = take((size_t)nt * sizeof(RayCtx));

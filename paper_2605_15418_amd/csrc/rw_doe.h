@@ -890,25 +890,36 @@ struct RayBlockIter {
   }
 };
 
-// Work items of a persistent DOE workgroup.  Workgroups are dispatched to the
-// eight XCDs in turn (XCD = blockIdx % 8), so XCD x takes the contiguous item
-// range [x q, (x + 1) q), q = ceil(n / 8), which its workgroups walk together:
-// the items in flight on one XCD are neighbouring ray blocks, whose patches
-// share map lines in that XCD's L2.  Other grid sizes keep the plain order.
-struct ItemOrder {
-  long long first, step, end;
-  __device__ __forceinline__ explicit ItemOrder(long long n) {
-    const int G = gridDim.x, b = blockIdx.x;
+// Work items of the persistent DOE workgroups, taken dynamically.  Workgroups
+// are dispatched to the eight XCDs in turn (XCD = blockIdx % 8); XCD x owns the
+// contiguous item range [x q, (x + 1) q), q = ceil(n / 8), and its workgroups
+// take the next item of that range from a counter of their own (zeroed before
+// the launch): the items in flight on one XCD are neighbouring ray blocks, whose
+// patches share map lines in that XCD's L2, and the work balances itself.
+// Other grid sizes share one counter over [0, n).
+struct ItemQueue {
+  unsigned long long* ctr;
+  long long base, end;
+  __device__ __forceinline__ ItemQueue(unsigned long long* c, long long n) {
+    const int G = gridDim.x;
     if (G % 8 == 0 && n >= G) {
       const long long q = (n + 7) / 8;
-      first = (long long)(b % 8) * q + b / 8;
-      step = G / 8;
-      end = min(n, (long long)(b % 8 + 1) * q);
+      const int x = blockIdx.x % 8;
+      base = (long long)x * q;
+      end = min(n, base + q);
+      ctr = c + x;
     } else {
-      first = b;
-      step = G;
+      base = 0;
       end = n;
+      ctr = c;
     }
+  }
+  // the workgroup's next item (every thread calls it; two barriers)
+  __device__ __forceinline__ long long next(long long* slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = base + (long long)atomicAdd(ctr, 1ull);
+    __syncthreads();
+    return *slot;
   }
 };
 
@@ -933,15 +944,16 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   // rays in work-list order; the class, alive flag and context word (thread
   // t < kCtxWords) of the next ray are loaded while the current one runs
   const int cnt = itr.count();
-  const ItemOrder ord(n_items);
-  long long it_n = ord.first;
+  __shared__ long long s_item;
+  ItemQueue queue(a.wctr, n_items);
+  long long it_n = queue.next(&s_item);
   int k_n = 0;
   long long gid_n = -1;
   int cls_n = -1;
   double alive_n = 0.0;
   uint32_t cw_n = 0;
   auto fetch = [&]() {
-    gid_n = it_n < ord.end ? itr.ray(it_n, k_n, pair0) : -1;
+    gid_n = it_n < queue.end ? itr.ray(it_n, k_n, pair0) : -1;
     if (gid_n >= 0) {
       cls_n = a.ray_class[gid_n];
       alive_n = a.st[7 * a.n_total + gid_n];
@@ -949,13 +961,13 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
     }
   };
   fetch();
-  while (it_n < ord.end) {                     // uniform over the workgroup
+  while (it_n < queue.end) {                   // uniform over the workgroup
     {
       const long long gid = gid_n;
       const int cls = cls_n;
       const double alive = alive_n;
       const uint32_t cw = cw_n;
-      if (++k_n == cnt) { k_n = 0; it_n += ord.step; }
+      if (++k_n == cnt) { k_n = 0; it_n = queue.next(&s_item); }
       fetch();
       if (gid < 0 || cls != a.cls) continue;   // past the grid edge or other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
@@ -1371,8 +1383,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   static_assert(kDoeThreads % M == 0, "the S-term pass keeps one column per lane");
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
-  const ItemOrder ord(n_items);
-  for (long long it = ord.first; it < ord.end; it += ord.step) {
+  __shared__ long long s_item;
+  ItemQueue queue(a.wctr, n_items);
+  for (long long it = queue.next(&s_item); it < queue.end; it = queue.next(&s_item)) {
     // anchor of the accumulator: the first live ray of the block
     if (t == 0) { s_box[0] = INT_MAX; s_box[1] = INT_MAX; s_box[2] = INT_MIN; s_box[3] = INT_MIN; }
     int ax0 = 0, ay0 = 0;

@@ -289,6 +289,7 @@ struct DoeArgs {
   const int32_t* replay;
   int32_t* idx_out;
   unsigned long long* stats; // [0] alive rays, [1] secondaries
+  unsigned long long* wctr;  // DOE work-item counters, one per XCD (zero at launch)
   size_t ray0, nray;         // rays [ray0, ray0 + nray) of the global order
   // backward-only
   const void* adj;           // C2<Tg> adjoint grid
