@@ -380,7 +380,7 @@ def main():
         from oracle import rw_oracle as O
         nthreads = torch.get_num_threads()
         R = cfg["rays_side"]
-        side_n = 16
+        side_n = 32
         c0 = R // 2 - side_n // 2
         subset = [(c0 + iy) * R + (c0 + ix) for iy in range(side_n) for ix in range(side_n)]
         F = len(cfg["fields"])

@@ -510,15 +510,58 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
   const int br = bitrev(gl, Gm::LB);
   const int P = c.P;
   if constexpr (M == 256) {
-    // rows: batches of the P nonzero rows, samples straight into the staged lines,
-    // the transformed rows to buf; columns: batches of columns (rows < P in),
-    // chunk sums from the staged outputs, the spectrum to buf
-    const TileRef tr = tile_of(cfg, c);
+    // rows: batches of kRB of the P nonzero rows.  The map pixels under a batch's
+    // sample stencils (a band, from the affine sample map at the patch corners,
+    // one pixel wider on each side than rounding could move it) are staged in
+    // the upper lines of the staging area with coalesced loads, the samples read
+    // them from there into the lower lines, and the transformed rows go to buf;
+    // columns: batches of columns (rows < P in), chunk sums from the staged
+    // outputs, the spectrum to buf
     const bool half = 2 * P == M;
     const int lgP = __builtin_ctz(P);
-    for (int r0 = 0; r0 < P; r0 += kLines256) {
-      const int nr = min(kLines256, P - r0);
-      // bilinear samples, KS per lane with their map reads issued together
+    constexpr int kRB = 32;
+    constexpr int kBandCap = (kLines256 - kRB) * kLS256;
+    C2<Tf>* band = ls + kRB * kLS256;
+    for (int r0 = 0; r0 < P; r0 += kRB) {
+      const int nr = min(kRB, P - r0);
+      auto sample_f = [&](int m, int n, double& fx, double& fy) {
+        const double sm_ = (m - (P - 1) * 0.5) * cfg.pitch, sn_ = (n - (P - 1) * 0.5) * cfg.pitch;
+        fx = (c.p[0] + sm_ * c.u[0] + sn_ * c.v[0] - cfg.x0) * cfg.inv_pitch;
+        fy = (c.p[1] + sm_ * c.u[1] + sn_ * c.v[1] - cfg.y0) * cfg.inv_pitch;
+      };
+      double xl = 1e300, xh = -1e300, yl = 1e300, yh = -1e300;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        double fx, fy;
+        sample_f((cc & 1) ? P - 1 : 0, r0 + ((cc & 2) ? nr - 1 : 0), fx, fy);
+        xl = fmin(xl, fx); xh = fmax(xh, fx);
+        yl = fmin(yl, fy); yh = fmax(yh, fy);
+      }
+      const int bx0 = (int)floor(xl) - 1, by0 = (int)floor(yl) - 1;
+      const int bw = (int)floor(xh) + 3 - bx0, bh = (int)floor(yh) + 3 - by0;
+      const bool use_band = bw * bh <= kBandCap;
+      __syncthreads();      // the previous batch's lines and band are read out
+      if (use_band) {
+        constexpr int KB = 10;
+        const FDiv dW(bw);
+        for (int i0 = tid; i0 < bw * bh; i0 += kDoeThreads * KB) {
+          C2<Tf> v[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            const int i = i0 + k * kDoeThreads;
+            v[k] = C2<Tf>{Tf(0), Tf(0)};
+            if (i < bw * bh) {
+              const int yy = dW.div(i), x = bx0 + i - yy * bw, y = by0 + yy;
+              if (x >= 0 && x < cfg.W && y >= 0 && y < cfg.H) v[k] = tm[(size_t)y * cfg.W + x];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < KB; ++k)
+            if (i0 + k * kDoeThreads < bw * bh) band[i0 + k * kDoeThreads] = v[k];
+        }
+        __syncthreads();
+      }
+      // bilinear samples, KS per lane with their reads issued together
       constexpr int KS = 8;
       for (int i0 = tid; i0 < nr * P; i0 += kDoeThreads * KS) {
         C2<Tf> q[KS][4];
@@ -527,18 +570,25 @@ __device__ __forceinline__ void doe_spectrum(const DevCfg& cfg, const RayCtx& c,
         for (int k = 0; k < KS; ++k) {
           const int i = i0 + k * kDoeThreads;
           const int n = r0 + (i >> lgP), m = i & (P - 1);
-          const double sm_ = (m - (P - 1) * 0.5) * cfg.pitch, sn_ = (n - (P - 1) * 0.5) * cfg.pitch;
-          const double fx = (c.p[0] + sm_ * c.u[0] + sn_ * c.v[0] - cfg.x0) * cfg.inv_pitch;
-          const double fy = (c.p[1] + sm_ * c.u[1] + sn_ * c.v[1] - cfg.y0) * cfg.inv_pitch;
+          double fx, fy;
+          sample_f(m, n, fx, fy);
           const double flx = floor(fx), fly = floor(fy);
           const int ix = (int)flx, iy = (int)fly;
           wx[k] = (Tf)(fx - flx);
           wy[k] = (Tf)(fy - fly);
+          if (use_band) {
+            const int o = i < nr * P ? (iy - by0) * bw + (ix - bx0) : 0;
+            q[k][0] = band[o];
+            q[k][1] = band[o + 1];
+            q[k][2] = band[o + bw];
+            q[k][3] = band[o + bw + 1];
+          } else {
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int x = ix + (j & 1), y = iy + (j >> 1);
-            q[k][j] = (i < nr * P && x >= 0 && x < cfg.W && y >= 0 && y < cfg.H)
-                          ? tm[(size_t)y * cfg.W + x] : C2<Tf>{Tf(0), Tf(0)};
+            for (int j = 0; j < 4; ++j) {
+              const int x = ix + (j & 1), y = iy + (j >> 1);
+              q[k][j] = (i < nr * P && x >= 0 && x < cfg.W && y >= 0 && y < cfg.H)
+                            ? tm[(size_t)y * cfg.W + x] : C2<Tf>{Tf(0), Tf(0)};
+            }
           }
         }
 #pragma unroll

@@ -6,6 +6,7 @@ HIP stream.  There is no CPU fallback: if the library is missing, or no GPU
 is present, the calls raise.
 """
 import ctypes
+import hashlib
 import json
 import os
 
@@ -86,6 +87,7 @@ class rw_stats(ctypes.Structure):
 
 
 _lib = None
+_lib_id = None     # content hash of the loaded library (part of the autotune key)
 
 
 def load_library(path=LIB_PATH):
@@ -121,6 +123,9 @@ def load_library(path=LIB_PATH):
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
                  "rw_get_profile", "rw_set_graph", "rw_autotune", "rw_set_launch_shape"):
         getattr(lib, name).restype = ctypes.c_int
+    global _lib_id
+    with open(path, "rb") as f:
+        _lib_id = hashlib.sha256(f.read()).hexdigest()[:12]
     _lib = lib
     return lib
 
@@ -324,12 +329,14 @@ class Plan:
         return out
 
     def tune_key(self):
-        """What a launch shape depends on: the GPU architecture and the plan's
-        geometry (precision, patch classes, draws, PSF, rays per pair, pairs)."""
+        """What a launch shape depends on: the library build, the GPU architecture
+        and the plan's geometry (precision, patch classes, draws, PSF, rays per
+        pair, pairs)."""
         c = self.cfg
         arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         classes = sorted({int(c["patch_p"])} | {int(q) for q in c.get("patch_classes", [])})
-        return "|".join(str(x) for x in (arch, self.precision, c["pad"], classes, c["sampling"],
+        return "|".join(str(x) for x in (_lib_id, arch, self.precision, c["pad"], classes,
+                                         c["sampling"],
                                          self.N, self.Q, c["rays_side"], self.L * self.F))
 
     def autotune(self, cache=None):
@@ -350,6 +357,8 @@ class Plan:
         _check(self.lib, self.lib.rw_autotune(self.handle, _dptr(self.ws), self.ws_bytes, shape,
                                               self._stream()))
         if cache:
+            # entries of other library builds are dropped
+            table = {k: v for k, v in table.items() if k.startswith(f"{_lib_id}|")}
             table[key] = list(shape)
             try:
                 with open(cache, "w") as f:
