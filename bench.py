@@ -10,11 +10,12 @@ zero-padded to 256 / 128; 256 secondary rays per incident ray (p ~ |U~|);
 1024 x 1024 PSF per pair; Eq. 5 loss against seeded Airy targets; gradients
 w.r.t. the phase and amplitude maps and 14 lens parameters.
 
-One step = rw_forward_backward (forward, Eq. 5 loss and backward, fused per
-launch group of pairs) over all 128 pairs, inputs resident in HBM, batched
-MIXED form (persistent launches over all pairs, launch shapes from the
-autotuner, the whole sequence replayed as a HIP graph).  value = incident
-rays traced per second (128 x 512^2 per step).
+One step = one iteration of the design loop: rw_forward_backward (forward,
+Eq. 5 loss and backward, fused per launch group of pairs) over all 128 pairs,
+then the Adam update (rw_adam_step) of the phase and amplitude maps and the lens
+parameters; inputs resident in HBM, batched MIXED form (persistent launches,
+launch shapes from the autotuner, the fused sequence replayed as a HIP graph).
+value = incident rays traced per second (128 x 512^2 per step).
 
 Beside it, on the asphere-singlet + 1024^2 hologram system (27 pairs x 256^2
 rays, P 64, N 256, Q 512): the same step with the per-kernel rooflines, the
@@ -137,6 +138,70 @@ def rooflines(prof, steps, flops):
     return out
 
 
+def dft_compare(n_patches):
+    """The patch transform (M <= 64) three ways on the same batch of zero-padded
+    P = M / 2 patches: the DOE kernels' LDS FFT (rw_patch_dft), and the DFT as two
+    dense GEMMs per patch batch on the matrix cores through the library GEMMs
+    (FP32 and BF16 operands, real block form [Re | Im] x [[C, S], [-S, C]]).
+    Prints one JSON line: time per patch, achieved rate and accuracy against a
+    complex128 FFT of the first patches."""
+    import numpy as np
+    import torch
+    import paper_2605_15418_amd as rw
+    dev = torch.device("cuda:0")
+    out = {"metric": "patch DFT time per patch", "n_patches": n_patches, "results": {}}
+    for M in (32, 64):
+        P = M // 2
+        g = torch.Generator(device="cpu").manual_seed(M)
+        x = torch.complex(torch.randn((n_patches, P, P), generator=g),
+                          torch.randn((n_patches, P, P), generator=g)).to(dev)
+        ref = np.fft.fft2(np.pad(x[:64].cpu().numpy().astype(np.complex128),
+                                 ((0, 0), (0, M - P), (0, M - P))))
+        k = torch.arange(M, dtype=torch.float64)
+        j = torch.arange(P, dtype=torch.float64)
+        ang = -2 * np.pi * torch.outer(j, k) / M                  # [P, M]: x index j -> bin k
+        C, S = torch.cos(ang), torch.sin(ang)
+        res = {}
+
+        def timed(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                y = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return y, e0.elapsed_time(e1) / reps
+
+        y, ms = timed(lambda: rw.patch_dft(x, M))
+        e = float(np.linalg.norm(y[:64].cpu().numpy() - ref) / np.linalg.norm(ref))
+        res["lds_fft"] = {"ms": ms, "ns_per_patch": ms * 1e6 / n_patches, "rel_err": e,
+                          "flop_per_patch_fft": 5 * M * M * math.log2(M * M)}
+        for dt in (torch.float32, torch.bfloat16):
+            B1 = torch.cat([torch.cat([C, S], 1), torch.cat([-S, C], 1)], 0).to(dev, dt)   # [2P, 2M]
+            Ck, Sk = torch.cos(-2 * np.pi * torch.outer(k, k) / M), torch.sin(-2 * np.pi * torch.outer(k, k) / M)
+            B2 = torch.cat([torch.cat([Ck[:P], Sk[:P]], 1), torch.cat([-Sk[:P], Ck[:P]], 1)], 0).to(dev, dt)
+            xr = torch.cat([x.real, x.imag], 2).to(dt).reshape(n_patches * P, 2 * P)
+
+            def gemm_dft():
+                y1 = (xr @ B1).reshape(n_patches, P, 2 * M)          # rows: [Re | Im] over kx
+                y1 = torch.cat([y1[:, :, :M], y1[:, :, M:]], 1)      # [n, 2P, M]: Re rows, Im rows
+                y1 = y1.transpose(1, 2).reshape(n_patches * M, 2 * P)
+                y2 = (y1 @ B2).reshape(n_patches, M, 2 * M)          # [n, kx, (Re|Im) over ky]
+                return torch.complex(y2[:, :, :M].float(), y2[:, :, M:].float()).transpose(1, 2)
+
+            y, ms = timed(gemm_dft)
+            e = float(np.linalg.norm(y[:64].cpu().numpy() - ref) / np.linalg.norm(ref))
+            fl = 2 * (2 * P) * (2 * M) * P + 2 * (2 * P) * (2 * M) * M   # per patch, both GEMMs
+            name = "gemm_fp32" if dt == torch.float32 else "gemm_bf16"
+            res[name] = {"ms": ms, "ns_per_patch": ms * 1e6 / n_patches, "rel_err": e,
+                         "flop_per_patch": fl,
+                         "tflops": fl * n_patches / (ms * 1e-3) / 1e12}
+        out["results"][f"M{M}"] = res
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,11 +219,16 @@ def main():
     ap.add_argument("--no-forward-only", action="store_true",
                     help="skip the forward-only rates of the other workloads")
     ap.add_argument("--no-graph", action="store_true", help="eager launches (no HIP graphs)")
+    ap.add_argument("--dft-compare", type=int, default=0,
+                    help="only compare patch-transform methods on this many patches")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
+        return
+    if args.dft_compare:
+        dft_compare(args.dft_compare)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the single-GPU share is the measured unit); "
@@ -211,13 +281,11 @@ def main():
         log(f"{name}: workspace {plan.ws_bytes / 2**30:.1f} GiB; autotune")
         plan.forward(v, ph, am, target=tg)
         shape = plan.autotune(cache=rw.rw.AUTOTUNE_CACHE)
-        bufs = {"psf": torch.empty((L, F, cfg["psf_q"], cfg["psf_q"]), device=dev),
-                "loss": torch.empty(1, device=dev), "dp": torch.empty_like(ph),
-                "da": torch.empty_like(am), "dl": torch.empty_like(v)}
+        # one design-loop iteration: rw_forward_backward, then rw_adam_step
+        des = rw.Design(plan, v, ph, am, tg, lr=(1e-2, 1e-2, 1e-2))
 
-        def step():                               # rw_forward_backward: the fused step
-            plan.step(v, ph, am, tg, psf_out=bufs["psf"], loss_out=bufs["loss"],
-                      d_phase=bufs["dp"], d_amp=bufs["da"], d_lens=bufs["dl"])
+        def step():
+            des.step()
 
         torch.cuda.synchronize()
         plan.set_profiling(True)

@@ -310,6 +310,31 @@ rw_status rw_set_launch_shape(rw_plan* plan, const int* shape_host);
  * Errors: RW_ERR_INVALID_ARG, RW_ERR_HIP (from the call that records). */
 rw_status rw_set_graph(rw_plan* plan, int enable);
 
+/* One Adam update (Kingma & Ba, 2015) of n float parameters in place, stream-ordered,
+ * for the end-to-end design loop that descends the Eq. 5 loss (Demonstrations,
+ * Fig. 5).  With g = grads[i]:
+ *   m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   p -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * then p is clamped to [lo, hi] unless lo > hi.  params, grads, m, v: device
+ * arrays of n floats owned by the caller (m, v zero before the first step); t >= 1
+ * is the step number.  Allocates nothing.
+ * Errors: RW_ERR_INVALID_ARG (null array with n > 0, t < 1, beta outside [0, 1),
+ *         eps <= 0), RW_ERR_HIP. */
+rw_status rw_adam_step(float* params, const float* grads, float* m, float* v, size_t n,
+                       float lr, float beta1, float beta2, float eps, int t, float lo,
+                       float hi, void* stream);
+
+/* The DOE kernels' patch transform on its own (Formalism: the angular spectrum of
+ * a P x P patch zero-padded to M x M), for timing it against other ways of
+ * computing the same DFT: in [n][P][P] complex float (interleaved re, im, rows of
+ * P), out [n][M][M] complex float, X[ky][kx] = sum_{y,x < P} in[y][x]
+ * exp(-2 pi i (ky y + kx x) / M) in natural frequency order.  One 512-thread
+ * workgroup per patch with the lane-group LDS FFT of the DOE kernels for M <= 64.
+ * Device arrays owned by the caller; stream-ordered; allocates nothing.
+ * Errors: RW_ERR_INVALID_ARG, RW_ERR_SHAPE (M not in {16, 32, 64}, P outside
+ *         [1, M]), RW_ERR_HIP. */
+rw_status rw_patch_dft(int M, int P, long long n, const void* in, void* out, void* stream);
+
 /* Diagnostic export of the incident ray state at the DOE of the last forward:
  * out [n_rays_total][8] double = (px, py, pz, dx, dy, dz, opl, alive). */
 rw_status rw_export_doe_hits(const rw_plan* plan, const void* workspace, double* out,

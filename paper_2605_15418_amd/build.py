@@ -6,7 +6,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-UNITS = ["rw_api.hip", "rw_doe_mixed.hip", "rw_doe_fp32.hip", "rw_doe_fp64.hip"]
+UNITS = ["rw_api.hip", "rw_doe_mixed.hip", "rw_doe_fp32.hip", "rw_doe_fp64.hip", "rw_dft.hip"]
 OUT = os.path.join(HERE, "librw.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

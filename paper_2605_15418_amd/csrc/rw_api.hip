@@ -967,6 +967,49 @@ rw_status rw_set_launch_shape(rw_plan* pl, const int* shape) {
   return RW_OK;
 }
 
+// Adam update, one thread per parameter; the bias corrections are formed on the
+// host in double.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, float lo, float hi) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float q = p[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  if (lo <= hi) q = fminf(fmaxf(q, lo), hi);
+  p[i] = q;
+}
+
+rw_status rw_adam_step(float* params, const float* grads, float* m, float* v, size_t n,
+                       float lr, float beta1, float beta2, float eps, int t, float lo,
+                       float hi, void* stream) {
+  if (n == 0) return RW_OK;
+  if (!params || !grads || !m || !v) return fail(RW_ERR_INVALID_ARG, "null array");
+  if (t < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return fail(RW_ERR_INVALID_ARG, "bad Adam step number or hyper-parameters");
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, t)));
+  const unsigned int blocks = (unsigned int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(256), 0, (hipStream_t)stream, params, grads, m,
+                     v, n, lr, beta1, beta2, eps, c1, c2, lo, hi);
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
+rw_status rw_patch_dft(int M, int P, long long n, const void* in, void* out, void* stream) {
+  if (n < 0 || (n > 0 && (!in || !out))) return fail(RW_ERR_INVALID_ARG, "bad patch arrays");
+  if (!(M == 16 || M == 32 || M == 64) || P < 1 || P > M)
+    return fail(RW_ERR_SHAPE, "rw_patch_dft takes M in {16, 32, 64} and 1 <= P <= M");
+  if (n == 0) return RW_OK;
+  HIPCHK(launch_patch_dft(M, P, n, in, out, (hipStream_t)stream));
+  return RW_OK;
+}
+
 rw_status rw_set_graph(rw_plan* pl, int enable) {
   if (!pl) return fail(RW_ERR_INVALID_ARG, "null plan");
   pl->graph = enable != 0;

@@ -2119,15 +2119,30 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
     const int bx0 = s_box[0], by0 = s_box[1], bx1 = s_box[2], by1 = s_box[3];
     if (bx0 < bx1 && by0 < by1) {
       const int bw = bx1 - bx0, bh = by1 - by0;
-      for (int i = t; i < bw * bh; i += kDoeThreads) {
-        const int lx = bx0 + i % bw, ly = by0 + i / bw;
-        C2<Tg>& d = accm[(size_t)ly * AS + lx];
-        const C2<Tg> v = d;
-        if (v.re == Tg(0) && v.im == Tg(0)) continue;
-        d = {Tg(0), Tg(0)};
-        const int x = ax0 + lx, y = ay0 + ly;
-        atomicAdd(&gt[(size_t)y * W + x].re, v.re);
-        atomicAdd(&gt[(size_t)y * W + x].im, v.im);
+      // KF pixels per lane: their loads are all issued before any is used
+      constexpr int KF = 8;
+      const FDiv dW(bw);
+      for (int i0 = t; i0 < bw * bh; i0 += kDoeThreads * KF) {
+        C2<Tg> v[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+          const int i = i0 + k * kDoeThreads;
+          v[k] = {Tg(0), Tg(0)};
+          if (i < bw * bh) {
+            const int r = dW.div(i);
+            v[k] = accm[(size_t)(by0 + r) * AS + bx0 + i - r * bw];
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+          const int i = i0 + k * kDoeThreads;
+          if (i >= bw * bh || (v[k].re == Tg(0) && v[k].im == Tg(0))) continue;
+          const int r = dW.div(i), lx = bx0 + i - r * bw, ly = by0 + r;
+          accm[(size_t)ly * AS + lx] = {Tg(0), Tg(0)};
+          const int x = ax0 + lx, y = ay0 + ly;
+          atomicAdd(&gt[(size_t)y * W + x].re, v[k].re);
+          atomicAdd(&gt[(size_t)y * W + x].im, v[k].im);
+        }
       }
     }
     __syncthreads();

@@ -14,4 +14,6 @@ hipError_t launch_doe_mixed(bool fwd, int M, bool lds, const DoeArgs& a, const R
                             long long n_items, int pair0, int blocks, hipStream_t st, bool* supported);
 hipError_t launch_doe_fp32(bool fwd, int M, bool lds, const DoeArgs& a, const RayBlockIter& it,
                            long long n_items, int pair0, int blocks, hipStream_t st, bool* supported);
+// Batched 2-D DFT of zero-padded P x P patches to M x M (the DOE kernels' transform).
+hipError_t launch_patch_dft(int M, int P, long long n, const void* in, void* out, hipStream_t st);
 }  // namespace rw

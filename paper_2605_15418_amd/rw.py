@@ -31,7 +31,7 @@ EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forwa
             "rw_backward", "rw_forward_backward", "rw_set_launch_shape",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
             "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph",
-            "rw_autotune")
+            "rw_autotune", "rw_adam_step", "rw_patch_dft")
 STAGES = ("trace", "doe_fwd", "bin", "spread", "grid_fwd", "grid_bwd", "doe_bwd", "trace_bwd",
           "interp")
 
@@ -115,13 +115,17 @@ def load_library(path=LIB_PATH):
     lib.rw_set_graph.argtypes = [vp, ctypes.c_int]
     lib.rw_autotune.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_int), vp]
     lib.rw_set_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    f32 = ctypes.c_float
+    lib.rw_adam_step.argtypes = [vp, vp, vp, vp, sz, f32, f32, f32, f32, ctypes.c_int, f32, f32, vp]
+    lib.rw_patch_dft.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, vp, vp, vp]
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
     for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
                  "rw_backward", "rw_forward_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
-                 "rw_get_profile", "rw_set_graph", "rw_autotune", "rw_set_launch_shape"):
+                 "rw_get_profile", "rw_set_graph", "rw_autotune", "rw_set_launch_shape",
+                 "rw_adam_step", "rw_patch_dft"):
         getattr(lib, name).restype = ctypes.c_int
     global _lib_id
     with open(path, "rb") as f:
@@ -143,6 +147,37 @@ def _check(lib, st):
 
 def _dptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, bounds=None):
+    """rw_adam_step on float32 device tensors of one shape (params, m, v updated in
+    place on the current stream); bounds = (lo, hi) clamps the parameters."""
+    lib = load_library()
+    for x in (params, grads, m, v):
+        if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("adam_step takes contiguous float32 device tensors")
+        if x.numel() != params.numel():
+            raise ValueError("adam_step: shapes differ")
+    lo, hi = bounds if bounds is not None else (1.0, 0.0)
+    st = torch.cuda.current_stream(params.device).cuda_stream
+    _check(lib, lib.rw_adam_step(_dptr(params), _dptr(grads), _dptr(m), _dptr(v), params.numel(),
+                                 float(lr), float(beta1), float(beta2), float(eps), int(t),
+                                 float(lo), float(hi), ctypes.c_void_p(st)))
+
+
+def patch_dft(patches, M, out=None):
+    """rw_patch_dft: the DOE kernels' M x M transform of zero-padded patches
+    (complex64 device tensor [n, P, P] -> [n, M, M], natural frequency order)."""
+    lib = load_library()
+    if patches.dtype != torch.complex64 or not patches.is_cuda or not patches.is_contiguous():
+        raise ValueError("patch_dft takes a contiguous complex64 device tensor")
+    n, P = patches.shape[0], patches.shape[1]
+    if out is None:
+        out = torch.empty((n, M, M), dtype=torch.complex64, device=patches.device)
+    st = torch.cuda.current_stream(patches.device).cuda_stream
+    _check(lib, lib.rw_patch_dft(int(M), int(P), int(n), _dptr(patches), _dptr(out),
+                                 ctypes.c_void_p(st)))
+    return out
 
 
 def _dbl_array(vals):

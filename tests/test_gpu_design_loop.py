@@ -1,0 +1,150 @@
+"""The end-to-end design loop (Eq. 5; Demonstrations, Fig. 5): Adam updates
+(rw_adam_step) after fused forward + loss + backward steps (rw_forward_backward).
+
+* The update kernel against Adam written out from its definition (Kingma & Ba).
+* A short loop on the holographic-asphere system at test size (FULL sampling):
+  its first losses follow the same loop run on the FP64 oracle (1e-4), both
+  descend, and at the final parameters the PSF equals the oracle's (1e-4).
+* Save / resume restores the loop's state exactly.
+* On the end-to-end design workload (16^2 rays per pair), the oracle checks
+  the PSF of one pair at steps 0 and 3 on the GPU's draws.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import rw_oracle as O
+from rwcases import gpu_inputs, small_hologram, worst_pair_rel, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rw():
+    import paper_2605_15418_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.load_library()
+    return pkg
+
+
+def _adam_reference(p, g_seq, lr, b1, b2, eps, bounds):
+    p = p.astype(np.float64).copy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for t, g in enumerate(g_seq, start=1):
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+        if bounds is not None:
+            p = np.clip(p, bounds[0], bounds[1])
+    return p
+
+
+@pytest.mark.parametrize("bounds", [None, (-0.3, 0.4)])
+def test_adam_step_matches_its_definition(rw, bounds):
+    rng = np.random.default_rng(5)
+    n = 3001
+    p0 = rng.normal(0, 0.3, n).astype(np.float32)
+    gs = [rng.normal(0, 1e-3, n).astype(np.float32) for _ in range(4)]
+    p = torch.tensor(p0, device="cuda")
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    for t, g in enumerate(gs, start=1):
+        rw.adam_step(p, torch.tensor(g, device="cuda"), m, v, t, 0.01, bounds=bounds)
+    ref = _adam_reference(p0, [g.astype(np.float64) for g in gs], 0.01, 0.9, 0.999, 1e-8, bounds)
+    assert np.max(np.abs(p.cpu().numpy() - ref)) < 1e-6
+
+
+def _oracle_psf_on(system, cfg, des, idx, pairs=None):
+    reps = {pr: idx[pr // idx.shape[1], pr % idx.shape[1]].cpu().numpy() for pr in range(
+        idx.shape[0] * idx.shape[1]) if pairs is None or pr in pairs}
+    return O.psf_stack(system, cfg, des.p["phase"].double().cpu().numpy(),
+                       des.p["amp"].double().cpu().numpy(),
+                       values=des.p["lens"].double().cpu().numpy(), replays=reps, pairs=pairs)[0]
+
+
+def _oracle_adam_losses(system, cfg, maps, lr, steps):
+    """The same loop on the FP64 oracle: loss_and_grad, then Adam written out."""
+    from rwcases import oracle_param_values
+    P = {"phase": maps["phase"].astype(np.float64), "amp": maps["amp"].astype(np.float64),
+         "lens": oracle_param_values(system)}
+    mom = {k: np.zeros_like(x) for k, x in P.items()}
+    vel = {k: np.zeros_like(x) for k, x in P.items()}
+    losses = []
+    for t in range(1, steps + 1):
+        L, g, _, _ = O.loss_and_grad(system, cfg, P["phase"], P["amp"], P["lens"],
+                                     maps["target"].astype(np.float64))
+        losses.append(L)
+        for k, r in zip(("phase", "amp", "lens"), lr):
+            mom[k] = 0.9 * mom[k] + 0.1 * g[k]
+            vel[k] = 0.999 * vel[k] + 0.001 * g[k] ** 2
+            P[k] = P[k] - r * (mom[k] / (1 - 0.9 ** t)) / (np.sqrt(vel[k] / (1 - 0.999 ** t))
+                                                          + 1e-8)
+            if k == "amp":
+                P[k] = np.clip(P[k], 0.0, 1.0)
+    return losses
+
+
+def test_design_loop_follows_the_oracle_loop_and_resumes(rw, tmp_path):
+    """FULL sampling (no draw noise): the GPU loop's losses follow the oracle's
+    loop step by step and descend; the final PSF equals the oracle's; save /
+    resume reproduces the uninterrupted run."""
+    system, cfg, maps = small_hologram(sampling="full")
+    plan = rw.Plan(system, cfg, precision="mixed")
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    lr = (0.05, 0.02, 0.02)
+    steps = 8
+    des = rw.Design(plan, vals, ph, am, tg, lr=lr)
+    losses = des.run(steps)
+    ref = _oracle_adam_losses(system, cfg, maps, lr, steps)
+    print("GPU losses", losses)
+    print("oracle losses", ref)
+    # Adam moves a parameter whose gradient is near zero by about lr whichever
+    # side of zero the gradient rounds to, so two runs that agree to 1e-6 part
+    # after a few steps: the first five losses are compared, the descent of both
+    # runs over all eight
+    for a, b in zip(losses[:5], ref[:5]):
+        assert abs(a - b) < 1e-4 * b
+    assert losses[-1] < 0.97 * losses[0] and ref[-1] < 0.97 * ref[0]
+    psf, _, _ = plan.forward(des.p["lens"], des.p["phase"], des.p["amp"])
+    ref_psf = O.psf_stack(system, cfg, des.p["phase"].double().cpu().numpy(),
+                          des.p["amp"].double().cpu().numpy(),
+                          values=des.p["lens"].double().cpu().numpy())[0]
+    e = worst_pair_rel(psf.cpu().numpy(), ref_psf)
+    print("PSF at the final parameters vs oracle:", e)
+    assert e < 1e-4
+    # save after 4 steps and resume: the state comes back exactly, and the next
+    # step of both runs (from the same parameters) gives the same loss
+    d1 = rw.Design(plan, vals, ph, am, tg, lr=lr)
+    d1.run(4)
+    path = str(tmp_path / "design.pt")
+    d1.save(path)
+    d2 = rw.Design.resume(path, plan, tg, lr=lr)
+    assert d2.t == 4
+    for k in ("phase", "amp", "lens"):
+        for a, b in ((d2.p, d1.p), (d2.m, d1.m), (d2.v, d1.v)):
+            assert torch.equal(a[k], b[k]), k
+    l1 = float(d1.step().item())
+    l2 = float(d2.step().item())
+    assert abs(l1 - l2) < 1e-6 * l1, (l1, l2)
+
+
+def test_end_to_end_design_steps_against_the_oracle(rw):
+    system, cfg, maps = W.two_lens_hybrid(rays_side=16)
+    F = len(cfg["fields"])
+    pair = 4 * F + 6
+    plan = rw.Plan(system, cfg, precision="mixed")
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    des = rw.Design(plan, vals, ph, am, tg, lr=(0.02, 0.01, 0.01))
+    for k in range(2):
+        if k:
+            des.run(3)
+        psf, _, idx = plan.forward(des.p["lens"], des.p["phase"], des.p["amp"], want_idx=True)
+        idx = idx.view(psf.shape[0], psf.shape[1], *idx.shape[1:])
+        ref = _oracle_psf_on(system, cfg, des, idx, pairs={pair})
+        e = rel_l2(psf[pair // F, pair % F].cpu().numpy(), ref[pair // F, pair % F])
+        print("step", des.t, "PSF vs oracle", e)
+        assert e < 1e-4
