@@ -205,7 +205,7 @@ def dft_compare(n_patches):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1, help="timed steps of the headline")
+    ap.add_argument("--steps", type=int, default=2, help="timed steps of the headline")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="two_lens_hybrid",
                     choices=("two_lens_hybrid", "asphere_hologram"))
