@@ -338,6 +338,27 @@ def main():
                 "launch_ms_from": "HIP events on the plan's stream, eager profiled step"}
     del plan
     torch.cuda.empty_cache()
+    if args.plain_steps > 0 and not args.no_side:
+        # the plain FP32 comparator on the headline workload: the same kernels in
+        # FP32 everywhere, one launch per pair, no graph, default launch shapes
+        log(f"{args.workload}: plain FP32 form (one launch per pair)")
+        v, ph, am, tg = head_in
+        plain = rw.Plan(system, cfg, precision="fp32", batched=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain.forward(v, ph, am, target=tg)
+            plain.backward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pv = head["incident_rays_per_step"] * args.plain_steps / (t1 - t0)
+        head["plain_fp32"] = {"value": pv, "unit": "rays/s",
+                              "ms_per_step": (t1 - t0) * 1e3 / args.plain_steps,
+                              "speedup_batched_mixed": head["value"] / pv,
+                              "note": "forward + backward on the same inputs; no Adam update"}
+        log(f"{args.workload}: plain FP32 {(t1 - t0) * 1e3 / args.plain_steps:.1f} ms/step")
+        del plain
+        torch.cuda.empty_cache()
 
     # ------------------------------------------ the asphere-hologram system
     side = None
