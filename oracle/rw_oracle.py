@@ -623,7 +623,7 @@ def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, n
         if replay is not None:
             J = np.asarray(replay, dtype=np.int64).reshape(R, Nd)
         else:
-            uu = draw_uniforms(cfg["seed"], pair, ray_ids, Nd)
+            uu = draw_uniforms(cfg["seed"], pair, ray_ids, Nd, stream=cfg.get("draw_stream", 0))
             J, _ = draw_bins(mag, pn, uu, sampling)
         rr = torch.arange(R).repeat_interleave(Nd)
         jj = torch.as_tensor(np.maximum(J, 0).reshape(-1))
@@ -653,7 +653,7 @@ def _class_secondaries(cfg, tmap, doe, pair, ray_ids, P, p, opl, amp_in, u, v, n
     if sampling != "full" and cfg.get("grad", "G1") == "G2":
         w, Kus, Kvs = _straight_through(cfg, pair, ray_ids, J, Utf, propf, Ku, Kv, w, Kus, Kvs,
                                         rr, valid, sampling, M, Nd)
-    return dict(rr=rr, w=w, Kus=Kus, Kvs=Kvs, J=J, Ut=Ut, prop=prop)
+    return dict(rr=rr, jj=jj, w=w, Kus=Kus, Kvs=Kvs, J=J, Ut=Ut, prop=prop)
 
 
 # ----------------------------------------------------------------------------
@@ -805,6 +805,173 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
                  lens=(vals.grad.numpy().copy() if vals.grad is not None
                        else np.zeros(vals.shape)))
     return total, g, psfs, idx
+
+
+# ----------------------------------------------------------------------------
+# Two DOEs in sequence (Formalism, first paragraph: the construction extends to
+# systems with more than one DOE, since every secondary ray is propagated by
+# conventional ray tracing).  READING (cascade):
+# * a secondary of the first DOE is traced through the surfaces between the
+#   DOEs to the second DOE's surface, where it is an incident ray: a plane-wave
+#   wavelet whose complex amplitude is the Eq. 1 weight it left the first DOE
+#   with and whose phase is its optical path; the second map is the stop of
+#   these rays as the first map is of the launched ones;
+# * the second DOE applies the same patch, spectrum, draws and Eq. 1 weights
+#   to it, with n_ssr2 draws (MAG, UNI) or every propagating bin (FULL): the
+#   fan-out N1 N2 per launched ray is bounded by the choice of n_ssr2, and the
+#   nested estimator stays unbiased for any n_ssr2 >= 1;
+# * one patch side, pad factor and sampling mode for both DOEs;
+# * the secondaries of the first DOE form a grid of side R n1 (n1^2 = N1,
+#   n1 = M under FULL): secondary i of launched ray (iy, ix) is grid ray
+#   (iy n1 + i div n1, ix n1 + i mod n1), i the draw (MAG, UNI) or the linear
+#   bin index J (FULL); the second DOE's draws take that grid ray's id and
+#   Philox stream 1.
+# ----------------------------------------------------------------------------
+def trace_between(surfs, s_from, s_to, lam, p, d, opl):
+    """From the hit on surface s_from to the hit on surface s_to: the surfaces
+    in between refract (intersection, aperture clip, OPL += n t, vector Snell);
+    s_to is intersected and clipped only."""
+    alive = torch.ones(p.shape[0], dtype=torch.bool)
+    n_before = medium_index(surfs, s_from, lam)
+    for s in range(s_from + 1, s_to + 1):
+        surf = surfs[s]
+        t, ok = intersect(surf, p, d)
+        alive = alive & ok
+        t = torch.where(alive, t, torch.zeros_like(t))
+        p = p + t[:, None] * d
+        opl = opl + n_before * t
+        if surf["semi_ap"] > 0:
+            alive = alive & ((p[:, 0] ** 2 + p[:, 1] ** 2) <= surf["semi_ap"] ** 2)
+        if s == s_to:
+            break
+        n_after = medium_index(surfs, s, lam)
+        nrm = surface_normal(surf, p[:, 0], p[:, 1])
+        dn, ok = refract(d, nrm, n_before, n_after)
+        alive = alive & ok
+        d = torch.where(alive[:, None], dn, d)
+        n_before = n_after
+    return p, d, opl, alive
+
+
+def inside_map(p, doe, H, W):
+    """Hit inside the map (the stop): pixel coordinate within [-1/2, side - 1/2]."""
+    fx = (p[:, 0] - doe["x0"]) / doe["pitch"]
+    fy = (p[:, 1] - doe["y0"]) / doe["pitch"]
+    return (fx >= -0.5) & (fx <= W - 0.5) & (fy >= -0.5) & (fy <= H - 0.5)
+
+
+def cascade_side(cfg):
+    """n1: side of the block of grid rays that one launched ray's first-DOE
+    secondaries occupy."""
+    if cfg["sampling"] == "full":
+        return cfg["pad"] * cfg["patch_p"]
+    n1 = int(round(math.sqrt(cfg["n_ssr"])))
+    if n1 * n1 != cfg["n_ssr"]:
+        raise ValueError("a cascade needs n_ssr = n1^2")
+    return n1
+
+
+def _doe_stage(cfg, surfs, s_doe, doe, tmap, lam, pair, ray_ids, p, d, opl, alive, Nd, replay):
+    """Frame, spectrum, draws and Eq. 1 weights of the rays incident on one DOE
+    (one patch class), and the directions of their secondaries."""
+    k0 = TWO_PI / lam
+    n_in = medium_index(surfs, s_doe - 1, lam)
+    k_out = k0 * medium_index(surfs, s_doe, lam)
+    u, v, nrm = tangent_frame(surfs[s_doe], p)
+    k_in_t = k0 * n_in * torch.stack([(d * u).sum(-1), (d * v).sum(-1)], dim=-1)
+    part = _class_secondaries(cfg, tmap, doe, pair, ray_ids, cfg["patch_p"], p, opl,
+                              alive.to(DT), u, v, nrm, k_in_t, alive, k_out, replay,
+                              cfg["sampling"], Nd)
+    rr = part["rr"]
+    ds = emit_direction(part["Kus"], part["Kvs"], u[rr], v[rr], nrm[rr], k_out)
+    return part, ds
+
+
+def cascade_pair_forward(system, cfg, tmaps, lam_idx, f_idx, values=None, replays=(None, None),
+                         keep=False):
+    """One (wavelength, field) pair through two DOEs: system["does"] describes the
+    two maps (the surfaces flagged doe, in order), tmaps their transmissions,
+    cfg["n_ssr2"] the draws per ray at the second DOE.  replays: the first DOE's
+    indices [R^2, N1] and the second's [(R n1)^2, N2], or None."""
+    surfs, sensor_z = build_surfaces(system, values)
+    does = system["does"]
+    s1, s2 = [i for i, s in enumerate(surfs) if s["doe"]]
+    lam = cfg["lambdas"][lam_idx]
+    k0 = TWO_PI / lam
+    F = len(cfg["fields"])
+    pair = lam_idx * F + f_idx
+    R = cfg["rays_side"]
+    n1 = cascade_side(cfg)
+    Rg = R * n1
+    N1, N2 = cfg["n_ssr"], cfg["n_ssr2"]
+    H, W = tmaps[0].shape
+    # first DOE: the single-DOE steps up to the emission
+    p, d, opl = launch(cfg, f_idx)
+    p, d, opl, alive, s = trace_to_doe(surfs, lam, p, d, opl)
+    assert s == s1
+    alive = alive & inside_map(p, does[0], H, W)
+    part1, ds1 = _doe_stage(cfg, surfs, s1, does[0], tmaps[0], lam, pair, np.arange(R * R),
+                            p, d, opl, alive, N1, replays[0])
+    rr = part1["rr"]
+    slot = part1["jj"] if cfg["sampling"] == "full" else torch.arange(rr.shape[0]) % N1
+    # conventional trace to the second DOE, which is the stop of these rays
+    p2, d2, opl2, ok = trace_between(surfs, s1, s2, lam, p[rr], ds1, opl[rr])
+    ok = ok & inside_map(p2, does[1], H, W)
+    a2 = torch.where(ok, part1["w"], torch.zeros_like(part1["w"]))
+    # the second DOE's incident rays on the grid of side R n1
+    iy = torch.div(rr, R, rounding_mode="floor")
+    ix = rr % R
+    g = (iy * n1 + torch.div(slot, n1, rounding_mode="floor")) * Rg + ix * n1 + slot % n1
+    n2 = Rg * Rg
+    P2 = torch.zeros(n2, 3, dtype=DT).index_put((g,), p2)
+    D2 = torch.zeros(n2, 3, dtype=DT)
+    D2[:, 2] = 1.0
+    D2 = D2.index_put((g,), d2)
+    O2 = torch.zeros(n2, dtype=DT).index_put((g,), opl2)
+    A2 = torch.zeros(n2, dtype=CT).index_put((g,), a2)
+    alive2 = torch.zeros(n2, dtype=torch.bool).index_put((g,), ok)
+    # second DOE, then the conventional trace to the sensor and Eq. 2
+    cfg2 = dict(cfg, n_ssr=N2, draw_stream=1)
+    part2, ds2 = _doe_stage(cfg2, surfs, s2, does[1], tmaps[1], lam, pair, np.arange(n2),
+                            P2, D2, O2, alive2, N2, replays[1])
+    rr2 = part2["rr"]
+    a_s = A2[rr2] * part2["w"]
+    ps, dsn, opls, ok2, n_s = trace_post_doe(surfs, s2, lam, P2[rr2], ds2, O2[rr2], sensor_z)
+    a_s = torch.where(ok2, a_s, torch.zeros_like(a_s))
+    lc = cfg["psf_center"][lam_idx][f_idx]
+    Xc = torch.stack([_t(lc[0]), _t(lc[1]), sensor_z * torch.ones((), dtype=DT)])
+    phi0 = k0 * (opls + n_s * (dsn * (Xc[None, :] - ps)).sum(-1))
+    wx = k0 * n_s * cfg["psf_pitch"] * dsn[:, 0]
+    wy = k0 * n_s * cfg["psf_pitch"] * dsn[:, 1]
+    amp = a_s * dsn[:, 2].abs()
+    U = sensor_field(amp, phi0, wx, wy, cfg["psf_q"])
+    out = {"U": U, "psf": U.real ** 2 + U.imag ** 2}
+    if keep:
+        out.update(J1=part1["J"], J2=part2["J"], alive2=alive2, p2=P2.detach(),
+                   d2=D2.detach(), opl2=O2.detach(), a2=A2.detach())
+    return out
+
+
+def cascade_psf_stack(system, cfg, phases, amps, values=None, replays=None, keep=False):
+    """PSF stack [L, F, Q, Q] of a two-DOE system (maps [2, H, W]) plus per-pair
+    aux dicts; replays: {pair: (first DOE's indices, second DOE's)}."""
+    L = len(cfg["lambdas"])
+    F = len(cfg["fields"])
+    Q = cfg["psf_q"]
+    tmaps = [transmission(_t(phases[k]), _t(amps[k]), system["does"][k].get("field", "amp_phase"))
+             for k in range(2)]
+    vals = None if values is None else _t(values)
+    out = np.zeros((L, F, Q, Q))
+    aux = {}
+    with torch.no_grad():
+        for l in range(L):
+            for f in range(F):
+                pr = l * F + f
+                rep = (None, None) if replays is None else replays[pr]
+                r = cascade_pair_forward(system, cfg, tmaps, l, f, vals, rep, keep=keep)
+                out[l, f] = r["psf"].numpy()
+                aux[pr] = r
+    return out, aux
 
 
 # ----------------------------------------------------------------------------

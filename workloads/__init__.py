@@ -489,6 +489,41 @@ def reflective_conformal(rays_side=64, H=501, lam=1e-3, P=128, N=2048, Q=512, ps
     return system, cfg, maps
 
 
+# ----------------------------------------------------------------------------
+# Two DOEs in sequence: DOE 1 on a plane in air 1 mm before a BK7 plano-convex
+# (curved face R = 20 mm first, CT 1.5 mm), DOE 2 on the front face of a 1 mm
+# BK7 plate 1.5 mm behind the lens; sensor near the paraxial focus.  Both maps
+# are band-limited random holograms (phase uniform in [0, 2 pi), amplitude in
+# [0.5, 1]) on their own pitch, or, where `uniform` says so, a clear aperture
+# (phase 0, amplitude 1).  N draws per launched ray at DOE 1 (a square), N2 per
+# arriving secondary at DOE 2.
+# ----------------------------------------------------------------------------
+def two_doe_cascade(rays_side=8, H=64, pitch=(0.004, 0.02), P=16, pad=2, N=16, N2=8, Q=32,
+                    psf_pitch=0.02, sampling="mag", lambdas=(LAM_D,), fields=((0.0, 0.0),),
+                    cutoff=0.05, uniform=(False, False), seed=0):
+    rng = np.random.default_rng(seed)
+    z_doe2 = 4.0
+    surfs = [surface(0.0, doe=True),
+             surface(1.0, c=1.0 / 20.0, medium=BK7),
+             surface(2.5),
+             surface(z_doe2, medium=BK7, doe=True),
+             surface(5.0)]
+    does = [dict(doe_desc(H, H, pitch[k]), field="amp_phase") for k in range(2)]
+    phase = np.zeros((2, H, H), np.float32)
+    amp = np.ones((2, H, H), np.float32)
+    for k in range(2):
+        if not uniform[k]:
+            phase[k] = 2 * math.pi * bandlimited_uniform(H, H, cutoff, rng)
+            amp[k] = 0.5 + 0.5 * bandlimited_uniform(H, H, cutoff, rng)
+    system = {"surfaces": surfs, "sensor_z": 40.5, "does": does, "doe": does[0], "params": []}
+    fields = [list(f) for f in fields]
+    cfg = _cfg(lambdas, fields, 0.0, -1.0, 0.1, rays_side, Q, psf_pitch, 38.7, P, N,
+               sampling, pad=pad, seed=seed)
+    cfg["n_ssr2"] = int(N2)
+    maps = {"phase": phase, "amp": amp, "target": None}
+    return system, cfg, maps
+
+
 def workload(name):
     """Named full-size workloads."""
     if name == "singlet_zoneplate":
