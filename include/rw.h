@@ -192,6 +192,38 @@ rw_status rw_plan_create(const rw_surface* surfaces_host, int n_surf, const rw_d
                          const rw_param_ref* params_host, int n_params, const rw_config* cfg_host,
                          rw_plan** out_plan);
 
+/* Creates the plan of a system with two DOEs in sequence (Formalism, first
+ * paragraph: the ray-wave construction extends to several DOEs, since secondary
+ * rays are propagated by conventional ray tracing).  Exactly two surfaces carry a
+ * DOE: doe1_host describes the first map, doe2_host the second (same H and W, same
+ * field mode, neither reflective).  A secondary of the first DOE is traced through
+ * the surfaces between the two (which refract) to the second DOE's surface, where
+ * it is an incident ray: a plane-wave wavelet whose complex amplitude is its Eq. 1
+ * weight and whose phase is its optical path; the second map is its stop.  The
+ * second DOE applies the same patch (patch_p, pad_factor: one class), spectrum and
+ * sampling (cfg.sampling) and draws n_ssr2 secondaries per incident ray (MAG, UNI),
+ * which go on to the sensor: N1 n_ssr2 records per launched ray.
+ *  cfg.n_ssr = N1 = n1^2 draws per launched ray at the first DOE (under FULL every
+ *  bin: n1 = M).  Secondary i (the draw, or under FULL the bin J) of launched ray
+ *  (iy, ix) is ray (iy n1 + i / n1, ix n1 + i % n1) of the second DOE's ray grid of
+ *  side rays_side n1 (pair-major like the launch grid); the second DOE's draws take
+ *  that ray's index and Philox stream 1 (counter (i >> 2, ray, pair, 1)).
+ *  Maps: doe_phase, doe_amp of rw_forward are [2][H][W] (first DOE, then second).
+ *  Sample indices (replay_idx, idx_out): the first DOE's [n_pairs][rays_side^2][N1]
+ *  followed by the second DOE's [n_pairs][(rays_side n1)^2][n_ssr2]; none under FULL.
+ *  The plan runs rw_forward and rw_forward_static (always forward-only);
+ *  rw_backward, rw_forward_backward and rw_autotune return RW_ERR_UNSUPPORTED.
+ *  rw_get_stats counts the rays of both DOEs; rw_export_doe_hits gives the second
+ *  DOE's incident rays.
+ * Errors: as rw_plan_create; RW_ERR_INVALID_ARG (not two DOE surfaces, different
+ *         field modes), RW_ERR_SHAPE (different map sizes, n_ssr not a square, grid
+ *         side above 32768), RW_ERR_UNSUPPORTED (reflective DOE, patch classes,
+ *         M above 128 -- 64 in FP64). */
+rw_status rw_plan_create_cascade(const rw_surface* surfaces_host, int n_surf,
+                                 const rw_doe_desc* doe1_host, const rw_doe_desc* doe2_host,
+                                 int n_ssr2, const rw_param_ref* params_host, int n_params,
+                                 const rw_config* cfg_host, rw_plan** out_plan);
+
 /* Device workspace sizes (256-byte aligned buffers):
  *  *fwd_bytes        the workspace of a forward pass that is not followed by a backward;
  *  *bwd_extra_bytes  (may be NULL) what a forward must have on top of fwd_bytes to leave

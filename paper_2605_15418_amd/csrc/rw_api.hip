@@ -115,6 +115,14 @@ struct rw_plan {
   BinGeom bg;
   int rec_chunk;
   double beta;
+  // two-DOE cascade (rw_plan_create_cascade): the fields above describe the
+  // second DOE and its incident rays (the first DOE's secondaries); the first
+  // DOE's launch grid, map and ray state are these
+  bool casc = false;
+  int s_doe1 = -1, R1 = 0, R1sq = 0, N1 = 0;
+  size_t n1_total = 0;
+  DevCfg* d_cfg1 = nullptr;
+  size_t off_tmap1 = 0, off_st1 = 0, off_ck1 = 0, off_ctx1 = 0, off_rcls1 = 0;
   // device constant tables (owned by the plan)
   DevCfg* d_cfg = nullptr;
   DevPair* d_pairs = nullptr;
@@ -290,13 +298,15 @@ template <class T>
 void zero(void* p, size_t n, hipStream_t st);
 
 // Ray-wave interface over whole blocks of rays (persistent workgroups).
+// R: side of the launch grid of the rays (the plan's, or the first DOE's of a cascade).
 rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npairs,
-                     hipStream_t st) {
+                     hipStream_t st, int R = -1) {
+  if (R < 0) R = pl->R;
   RayBlockIter it;
   it.rb = pl->rb_dir[fwd ? 0 : 1];
-  it.nbx = (pl->R + it.rb - 1) / it.rb;
+  it.nbx = (R + it.rb - 1) / it.rb;
   it.per_pair = it.nbx * it.nbx;
-  it.R = pl->R;
+  it.R = R;
   const long long n_items = (long long)npairs * it.per_pair;
   const int blocks = (int)std::min<long long>(n_items, pl->blocks_dir[fwd ? 0 : 1]);
   // one launch per patch class, each over the whole work list (rays of other
@@ -506,9 +516,22 @@ const char* rw_status_string(rw_status s) {
 
 const char* rw_last_error(void) { return g_last_error.c_str(); }
 
-rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc* doe,
-                         const rw_param_ref* params, int n_params, const rw_config* cfg,
-                         rw_plan** out) {
+}  // extern "C"
+
+namespace {
+// The first DOE of a two-DOE cascade, as rw_plan_create_cascade hands it to the
+// plan builder (which sees the second DOE as the plan's DOE).
+struct CascSpec {
+  int s1;                 // surface of the first DOE
+  rw_doe_desc doe1;
+  int R1;                 // launch grid side
+  int n1;                 // side of each ray's block of relayed secondaries
+  int N1;                 // relayed secondaries per ray (n1^2)
+};
+
+rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc* doe,
+                      const rw_param_ref* params, int n_params, const rw_config* cfg,
+                      const CascSpec* cs, rw_plan** out) {
   if (!surfaces || !doe || !cfg || !out || (n_params > 0 && !params))
     return fail(RW_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
@@ -691,6 +714,34 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   dc.beta = pl->beta;
   dc.key0 = (uint32_t)(cfg->seed & 0xffffffffu);
   dc.key1 = (uint32_t)(cfg->seed >> 32);
+  dc.relay_n1 = 0;
+  DevCfg dc1 = dc;
+  if (cs) {
+    if (!pl->class_lds[0]) {
+      delete pl;
+      return fail(RW_ERR_UNSUPPORTED, "a DOE cascade needs M <= 128 (FP32, MIXED) or M <= 64 (FP64)");
+    }
+    const rw_surface& q = surfaces[cs->s1];
+    bool planar1 = q.curvature == 0.0 && q.conic == 0.0 && q.asph[0] == 0.0 &&
+                   q.asph[1] == 0.0 && q.asph[2] == 0.0 && q.asph[3] == 0.0 &&
+                   !(q.gauss_width > 0.0);
+    for (int i = 0; i < n_params; ++i)
+      if (params[i].surface == cs->s1 && params[i].field != RW_PARAM_GAP) planar1 = false;
+    pl->casc = true;
+    pl->s_doe1 = cs->s1;
+    pl->R1 = cs->R1;
+    pl->R1sq = cs->R1 * cs->R1;
+    pl->N1 = cs->N1;
+    pl->n1_total = (size_t)pl->n_pairs * pl->R1sq;
+    dc1.s_doe = cs->s1;
+    dc1.R = cs->R1;
+    dc1.R2 = pl->R1sq;
+    dc1.N = cs->N1;
+    dc1.pitch = cs->doe1.pitch; dc1.x0 = cs->doe1.x0; dc1.y0 = cs->doe1.y0;
+    dc1.inv_pitch = 1.0 / cs->doe1.pitch;
+    dc1.planar = planar1 ? 1 : 0;
+    dc1.relay_n1 = cs->n1;
+  }
 
   std::vector<DevPair> pairs(pl->n_pairs);
   for (int l = 0; l < pl->n_lambda; ++l)
@@ -785,6 +836,7 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   };
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up((void**)&pl->d_cfg, &dc, sizeof(dc));
+  if (e == hipSuccess && cs) e = up((void**)&pl->d_cfg1, &dc1, sizeof(dc1));
   if (e == hipSuccess) e = up((void**)&pl->d_pairs, pairs.data(), pairs.size() * sizeof(DevPair));
   if (e == hipSuccess) e = up((void**)&pl->d_base, base.data(), base.size() * sizeof(DevSurf));
   if (e == hipSuccess) e = up((void**)&pl->d_prm, prm.data(), prm.size() * sizeof(DevParam));
@@ -811,7 +863,8 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   const size_t nk = (size_t)pl->n_pairs * pl->bg.keys;
   pl->off_live = take(sizeof(DevLive));
   pl->off_tmap = take((size_t)doe->H * doe->W * pl->sz_cf);
-  pl->off_st = take(8 * nt * sizeof(double));
+  // a cascade's second DOE also keeps each incident ray's complex amplitude
+  pl->off_st = take((cs ? 10 : 8) * nt * sizeof(double));
   pl->off_ck = take((size_t)(s_doe + 1) * 8 * nt * sizeof(double));
   pl->off_grid = take((size_t)pl->n_pairs * pl->nf * pl->nf * pl->sz_cg);
   pl->off_t1 = take((size_t)pl->n_pairs * pl->Q * pl->nf * pl->sz_cg);
@@ -835,27 +888,95 @@ rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_de
   pl->off_cnt = take(nk * sizeof(unsigned int));
   pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
   pl->off_cur = take(nk * sizeof(unsigned long long));
+  if (cs) {
+    // the first DOE: its map, launched rays (state, checkpoints, contexts, classes)
+    const size_t n1t = pl->n1_total;
+    pl->off_tmap1 = take((size_t)doe->H * doe->W * pl->sz_cf);
+    pl->off_st1 = take(8 * n1t * sizeof(double));
+    pl->off_ck1 = take((size_t)(cs->s1 + 1) * 8 * n1t * sizeof(double));
+    pl->off_ctx1 = take(n1t * sizeof(RayCtx));
+    pl->off_rcls1 = take(n1t);
+  }
   pl->fwd_bytes = o;
+  // a cascade runs forward only: no backward state or buffers
+  const size_t bw = cs ? 0 : 1;
   // state of the forward that only the backward reads
-  pl->off_jdraw = take(cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t));
+  pl->off_jdraw = take(bw * (cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t)));
   const bool tl = pl->tiled_interp || pl->tiled_groups;
-  pl->off_tidx = take(tl ? nrec * 4 : 0);
-  pl->off_sidx = take(tl ? nrec * 4 : 0);
+  pl->off_tidx = take(bw * (tl ? nrec * 4 : 0));
+  pl->off_sidx = take(bw * (tl ? nrec * 4 : 0));
   // the backward's own buffers
-  pl->off_acc = take((size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
-  pl->off_g2 = take(pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
-                                 sizeof(float)
-                           : 0);
-  pl->off_dlist = take(cfg->sampling == RW_SAMPLE_FULL
-                           ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf);
-  pl->off_gt = take((size_t)doe->H * doe->W * pl->sz_cg);
-  pl->off_raygrad = take((size_t)RW_RAYGRAD * nt * sizeof(double));
-  pl->off_lensg = take(RW_LENSG_SLOTS * sizeof(double));
-  pl->off_G = take((size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
-  pl->off_interp = take(tl ? nrec * kInterpStride * pl->sz_cg : 0);
+  pl->off_acc = take(bw * (size_t)pl->doe_blocks * pl->acc_side * pl->acc_side * pl->sz_cg);
+  pl->off_g2 = take(bw * (pl->g2 ? (size_t)pl->doe_blocks * ((size_t)pl->N * kG2Rec + (size_t)M * M) *
+                                       sizeof(float)
+                                 : 0));
+  pl->off_dlist = take(bw * (cfg->sampling == RW_SAMPLE_FULL
+                                 ? 0 : (size_t)pl->doe_blocks * pl->N * 2 * pl->sz_cf));
+  pl->off_gt = take(bw * (size_t)doe->H * doe->W * pl->sz_cg);
+  pl->off_raygrad = take(bw * (size_t)RW_RAYGRAD * nt * sizeof(double));
+  pl->off_lensg = take(bw * RW_LENSG_SLOTS * sizeof(double));
+  pl->off_G = take(bw * (size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
+  pl->off_interp = take(bw * (tl ? nrec * kInterpStride * pl->sz_cg : 0));
   pl->total = o;
   *out = pl;
   return RW_OK;
+}
+}  // namespace
+
+extern "C" {
+
+rw_status rw_plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc* doe,
+                         const rw_param_ref* params, int n_params, const rw_config* cfg,
+                         rw_plan** out) {
+  return plan_create(surfaces, n_surf, doe, params, n_params, cfg, nullptr, out);
+}
+
+rw_status rw_plan_create_cascade(const rw_surface* surfaces, int n_surf, const rw_doe_desc* doe1,
+                                 const rw_doe_desc* doe2, int n_ssr2, const rw_param_ref* params,
+                                 int n_params, const rw_config* cfg, rw_plan** out) {
+  if (!surfaces || !doe1 || !doe2 || !cfg || !out || (n_params > 0 && !params))
+    return fail(RW_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (n_surf < 2 || n_surf > RW_MAX_SURF)
+    return fail(RW_ERR_SHAPE, "a cascade needs n_surf in [2, 8]");
+  int s1 = -1, s2 = -1;
+  for (int s = 0; s < n_surf; ++s)
+    if (surfaces[s].carries_doe) {
+      if (s1 < 0) s1 = s;
+      else if (s2 < 0) s2 = s;
+      else return fail(RW_ERR_UNSUPPORTED, "more than two DOE surfaces");
+    }
+  if (s2 < 0) return fail(RW_ERR_INVALID_ARG, "a cascade needs two surfaces that carry a DOE");
+  if (doe1->H != doe2->H || doe1->W != doe2->W || doe1->H < 1 || doe1->W < 1 ||
+      !(doe1->pitch > 0))
+    return fail(RW_ERR_SHAPE, "the two DOE maps must have the same H and W");
+  if (doe1->reflective || doe2->reflective)
+    return fail(RW_ERR_UNSUPPORTED, "a cascade of reflective DOEs is not built");
+  if (doe1->field != doe2->field)
+    return fail(RW_ERR_INVALID_ARG, "the two DOEs must share the field mode");
+  if (cfg->n_patch_class != 0)
+    return fail(RW_ERR_UNSUPPORTED, "a cascade takes one patch class");
+  const int M = cfg->patch_p * cfg->pad_factor;
+  int n1 = 0;
+  if (cfg->sampling == RW_SAMPLE_FULL) {
+    n1 = M;
+  } else {
+    while ((n1 + 1) * (n1 + 1) <= cfg->n_ssr) ++n1;
+    if (cfg->n_ssr < 1 || n1 * n1 != cfg->n_ssr)
+      return fail(RW_ERR_SHAPE, "a cascade needs n_ssr = n1^2 draws at the first DOE");
+  }
+  if (cfg->sampling != RW_SAMPLE_FULL && (n_ssr2 < 1 || n_ssr2 > 2048))
+    return fail(RW_ERR_SHAPE, "n_ssr2 must be in [1, 2048]");
+  if (cfg->rays_side < 1 || (long long)cfg->rays_side * n1 > 32768)
+    return fail(RW_ERR_SHAPE, "the second DOE's ray grid side rays_side * n1 exceeds 32768");
+  std::vector<rw_surface> sf(surfaces, surfaces + n_surf);
+  sf[s1].carries_doe = 0;
+  rw_config c2 = *cfg;
+  c2.rays_side = cfg->rays_side * n1;
+  c2.n_ssr = n_ssr2;
+  const CascSpec cs = {s1, *doe1, cfg->rays_side, n1,
+                       cfg->sampling == RW_SAMPLE_FULL ? M * M : cfg->n_ssr};
+  return plan_create(sf.data(), n_surf, doe2, params, n_params, &c2, &cs, out);
 }
 
 rw_status rw_plan_workspace_bytes(const rw_plan* pl, size_t* fwd_bytes, size_t* bwd_extra_bytes) {
@@ -868,6 +989,7 @@ rw_status rw_plan_workspace_bytes(const rw_plan* pl, size_t* fwd_bytes, size_t* 
 rw_status rw_plan_destroy(rw_plan* pl) {
   if (!pl) return RW_OK;
   (void)hipFree(pl->d_cfg);
+  (void)hipFree(pl->d_cfg1);
   (void)hipFree(pl->d_pairs);
   (void)hipFree(pl->d_base);
   (void)hipFree(pl->d_prm);
@@ -886,6 +1008,7 @@ rw_status rw_plan_destroy(rw_plan* pl) {
 
 rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, void* stream) {
   if (!pl || !ws) return fail(RW_ERR_INVALID_ARG, "null argument");
+  if (pl->casc) return fail(RW_ERR_UNSUPPORTED, "rw_autotune does not tune a DOE cascade");
   if (!pl->fwd_done || !pl->fwd_full || ws != pl->fwd_ws || ws_bytes < pl->total)
     return fail(RW_ERR_STATE, "rw_autotune needs a preceding rw_forward on this workspace "
                               "(of fwd + bwd bytes)");
@@ -1031,19 +1154,95 @@ static rw_status fwd_prologue(rw_plan* pl, const float* lens_params, const float
   hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, pl->d_cfg, pl->d_base, pl->base_sensor_z,
                      pl->d_prm, lens_params, (DevLive*)(b + pl->off_live));
   const int nmap = pl->H * pl->W;
-  if (dbl_f)
-    hipLaunchKernelGGL(k_tmap<double>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
-                       doe_amp, (C2<double>*)(b + pl->off_tmap), nmap, pl->doe.field);
-  else
-    hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase,
-                       doe_amp, (C2<float>*)(b + pl->off_tmap), nmap, pl->doe.field);
-  HIPCHK(hipGetLastError());
+  // a cascade's maps are [2][H][W]: the first DOE's, then the second's (the plan's)
+  for (int k = 0; k < (pl->casc ? 2 : 1); ++k) {
+    void* dst = b + (pl->casc && k == 0 ? pl->off_tmap1 : pl->off_tmap);
+    const size_t o = pl->casc ? (size_t)k * nmap : 0;
+    if (dbl_f)
+      hipLaunchKernelGGL(k_tmap<double>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase + o,
+                         doe_amp + o, (C2<double>*)dst, nmap, pl->doe.field);
+    else
+      hipLaunchKernelGGL(k_tmap<float>, dim3((nmap + 255) / 256), dim3(256), 0, st, doe_phase + o,
+                         doe_amp + o, (C2<float>*)dst, nmap, pl->doe.field);
+    HIPCHK(hipGetLastError());
+  }
   zero<unsigned long long>(b + pl->off_stats, RW_N_STATS, st);
   return RW_OK;
 }
 
+// A launch group of a two-DOE cascade: launched rays to the first DOE, its
+// patches, draws and relay of every secondary to the second DOE (the second
+// DOE's incident rays), their patches and draws, then the records' Eq. 2 sum.
+static rw_status fwd_group_cascade(rw_plan* pl, void* ws, const int32_t* replay_idx,
+                                   int32_t* idx_out, float* psf_out, int pair0, int ppg,
+                                   hipStream_t st) {
+  char* b = (char*)ws;
+  const DevLive* live = (const DevLive*)(b + pl->off_live);
+  // the second DOE's sample indices follow the first DOE's
+  const size_t off2 = pl->n1_total * (size_t)pl->N1;
+  DoeArgs a1 = doe_args(pl, ws, replay_idx, idx_out);
+  a1.cfg = pl->d_cfg1;
+  a1.st = (const double*)(b + pl->off_st1);
+  a1.n_total = pl->n1_total;
+  a1.tmap = b + pl->off_tmap1;
+  a1.ctx = (RayCtx*)(b + pl->off_ctx1);
+  a1.ray_class = (unsigned char*)(b + pl->off_rcls1);
+  a1.emit = pl->N1;
+  a1.rec_pos = nullptr;
+  a1.rec_val = nullptr;
+  a1.jdraw = nullptr;
+  a1.relay = (double*)(b + pl->off_st);
+  a1.relay_n = pl->n_total;
+  a1.cfg2 = pl->d_cfg;
+  const size_t nr1 = (size_t)ppg * pl->R1sq;
+  a1.ray0 = (size_t)pair0 * pl->R1sq;
+  a1.nray = nr1;
+  const int tb1 = (int)((nr1 + 255) / 256);
+  {
+    StageTimer tm_(pl, RW_STAGE_TRACE, st);
+    if (pl->cfg.precision == RW_PREC_FP32)
+      hipLaunchKernelGGL(k_trace<float>, dim3(tb1), dim3(256), 0, st, pl->d_cfg1, pl->d_pairs,
+                         live, (double*)(b + pl->off_st1), (double*)(b + pl->off_ck1),
+                         pl->n1_total, pair0, ppg, (unsigned long long*)(b + pl->off_stats));
+    else
+      hipLaunchKernelGGL(k_trace<double>, dim3(tb1), dim3(256), 0, st, pl->d_cfg1, pl->d_pairs,
+                         live, (double*)(b + pl->off_st1), (double*)(b + pl->off_ck1),
+                         pl->n1_total, pair0, ppg, (unsigned long long*)(b + pl->off_stats));
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_ray_ctx, dim3(tb1), dim3(256), 0, st, a1);
+    HIPCHK(hipGetLastError());
+  }
+  rw_status s;
+  {
+    StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
+    s = doe_launch(pl, true, a1, pair0, ppg, st, pl->R1);
+  }
+  if (s != RW_OK) return s;
+  DoeArgs a2 = doe_args(pl, ws, replay_idx ? replay_idx + off2 : nullptr,
+                        idx_out ? idx_out + off2 : nullptr);
+  a2.ain = (const double*)(b + pl->off_st) + 8 * pl->n_total;
+  const size_t nr2 = (size_t)ppg * pl->R2;
+  a2.ray0 = (size_t)pair0 * pl->R2;
+  a2.nray = nr2;
+  {
+    StageTimer tm_(pl, RW_STAGE_TRACE, st);
+    hipLaunchKernelGGL(k_ray_ctx, dim3((int)((nr2 + 255) / 256)), dim3(256), 0, st, a2);
+    HIPCHK(hipGetLastError());
+  }
+  {
+    StageTimer tm_(pl, RW_STAGE_DOE_FWD, st);
+    s = doe_launch(pl, true, a2, pair0, ppg, st);
+  }
+  if (s != RW_OK) return s;
+  s = bin_and_spread(pl, ws, st, pair0, ppg);
+  if (s != RW_OK) return s;
+  StageTimer tm_(pl, RW_STAGE_GRID_FWD, st);
+  return grid_fwd(pl, ws, st, pair0, ppg, psf_out);
+}
+
 static rw_status fwd_group(rw_plan* pl, void* ws, const int32_t* replay_idx, int32_t* idx_out,
                            float* psf_out, int pair0, int ppg, hipStream_t st) {
+  if (pl->casc) return fwd_group_cascade(pl, ws, replay_idx, idx_out, psf_out, pair0, ppg, st);
   char* b = (char*)ws;
   DoeArgs a = doe_args(pl, ws, replay_idx, idx_out);
   const size_t nr = (size_t)ppg * pl->R2;
@@ -1173,7 +1372,7 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
     hipStream_t st = (hipStream_t)stream;
     unsigned int* flag = (unsigned int*)((char*)ws + pl->off_stats);
     zero<unsigned int>(flag, 1, st);
-    const size_t nmap = (size_t)pl->H * pl->W;
+    const size_t nmap = (size_t)pl->H * pl->W * (pl->casc ? 2 : 1);
     const size_t nt = target ? (size_t)pl->n_pairs * pl->Q * pl->Q : 0;
     hipLaunchKernelGGL(k_check_finite, dim3(1024), dim3(256), 0, st, lens_params,
                        lens_params ? pl->prm.size() : (size_t)0, doe_phase, nmap, doe_amp, nmap,
@@ -1187,8 +1386,10 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
       return fail(RW_ERR_NONFINITE, "NaN or Inf in lens_params, doe_phase, doe_amp or target");
     }
   }
+  // a cascade always runs forward-only (no backward state)
   return forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
-                      ws_bytes < pl->total, pl->graph, replay_idx, idx_out, (hipStream_t)stream);
+                      ws_bytes < pl->total || pl->casc, pl->graph, replay_idx, idx_out,
+                      (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -1419,6 +1620,7 @@ static rw_status step_enqueue(rw_plan* pl, const float* lens_params, const float
 rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
                       float* d_lens, void* ws, size_t ws_bytes, void* stream) {
   if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (pl->casc) return fail(RW_ERR_UNSUPPORTED, "gradients through a DOE cascade are not built");
   if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
   if (ws != pl->fwd_ws || ws_bytes < pl->total)
     return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");
@@ -1448,6 +1650,8 @@ rw_status rw_forward_backward(rw_plan* pl, const float* lens_params, const float
                               const float* doe_amp, const float* target, float* psf_out,
                               float* loss_out, float* d_phase, float* d_amp, float* d_lens,
                               void* ws, size_t ws_bytes, void* stream) {
+  if (pl && pl->casc)
+    return fail(RW_ERR_UNSUPPORTED, "gradients through a DOE cascade are not built");
   const rw_status a = forward_args(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
                                    nullptr);
   if (a != RW_OK) return a;

@@ -974,7 +974,11 @@ struct ItemQueue {
 };
 
 // ------------------------------------------------------------------ forward ---
-template <class Prec, int M, bool kLDS>
+// Two-DOE cascade (kCasc): 1 = the first DOE, whose secondaries become the
+// second DOE's incident rays (relay records) instead of sensor records; 2 = the
+// second DOE, whose incident rays carry a complex amplitude and whose draws take
+// Philox stream 1; 0 = a single DOE.
+template <class Prec, int M, bool kLDS, int kCasc = 0>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
   using Tf = typename Prec::Tf;
@@ -1022,7 +1026,10 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       if (gid < 0 || cls != a.cls) continue;   // past the grid edge or other patch class
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)emit;
       if (alive == 0.0) {
-        for (int i = t; i < emit; i += kDoeThreads) put_none<Tg>(a, slot0 + i);
+        for (int i = t; i < emit; i += kDoeThreads) {
+          if constexpr (kCasc == 1) relay_none(a, (int)(gid / cfg.R2), (int)(gid % cfg.R2), i);
+          else put_none<Tg>(a, slot0 + i);
+        }
         if (a.idx_out && cfg.sampling != 2)
           for (int i = t; i < N; i += kDoeThreads) a.idx_out[gid * N + i] = -1;
         continue;
@@ -1033,6 +1040,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
       const int P = c.P;
+      // incident amplitude at the second DOE of a cascade (1 otherwise)
+      C2<Tp> ain = {Tp(1), Tp(0)};
+      if constexpr (kCasc == 2) ain = {(Tp)a.ain[gid], (Tp)a.ain[a.n_total + gid]};
       int lp;
       doe_spectrum<Tf, M>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp, s.ls);
       if (t < M) {
@@ -1042,23 +1052,39 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       n_bins += t == 0 ? (unsigned long long)M * M : 0ull;
       if (cfg.sampling == 2) {
         // slots beyond this class's M^2 bins (classes smaller than the largest)
-        for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_none<Tg>(a, slot0 + Lb);
+        if constexpr (kCasc != 1)
+          for (int Lb = M * M + t; Lb < emit; Lb += kDoeThreads) put_none<Tg>(a, slot0 + Lb);
         for (int Lb = t; Lb < M * M; Lb += kDoeThreads) {
           const int jx = Lb / M - M / 2, jy = Lb % M - M / 2;
-          Tp phi0, wx, wy; double dza; Secondary sec;
           const Span sp = s.span[jx + M / 2];
           const bool prop = jy >= sp.lo && jy <= sp.hi;
-          if (!prop || !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
-            n_lost += prop;
-            put_none<Tg>(a, slot0 + Lb);
+          if constexpr (kCasc == 1) {
+            if (!prop) {
+              relay_none(a, c.pair, c.r, Lb);
+              continue;
+            }
+            const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
+            const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+            const C2<Tp> w = C2<Tp>{(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2} * ain;
+            const bool ok = relay_secondary<Prec>(a, c, jx, jy, (double)w.re, (double)w.im, Lb);
+            n_sec += ok;
+            n_lost += !ok;
             continue;
+          } else {
+            Tp phi0, wx, wy; double dza; Secondary sec;
+            if (!prop || !secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec)) {
+              n_lost += prop;
+              put_none<Tg>(a, slot0 + Lb);
+              continue;
+            }
+            const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
+            const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
+            C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+            if constexpr (kCasc == 2) w = w * ain;
+            const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
+            put_record<Prec>(a, slot0 + Lb, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
+            ++n_sec;
           }
-          const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
-          const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-          const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
-          const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
-          put_record<Prec>(a, slot0 + Lb, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
-          ++n_sec;
         }
         __syncthreads();
         continue;
@@ -1074,7 +1100,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
             J = a.replay[gid * N + i];
           } else {
             const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
-                                          (uint32_t)c.pair, 0u) * S;
+                                          (uint32_t)c.pair, kCasc == 2 ? 1u : 0u) * S;
             J = draw_bin<Tf, M>(buf, s.pref, s.span, T, cfg.sampling, lastpos_all);
           }
         }
@@ -1096,6 +1122,17 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
             w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
           }
         }
+        if constexpr (kCasc == 1) {
+          if (!ok) {
+            relay_none(a, c.pair, c.r, i);
+            continue;
+          }
+          w = w * ain;
+          ok = relay_secondary<Prec>(a, c, jx, jy, (double)w.re, (double)w.im, i);
+          n_sec += ok;
+          n_lost += !ok;
+          continue;
+        }
         Tp phi0, wx, wy; double dza; Secondary sec;
         if (ok) {
           ok = secondary_to_sensor<Prec>(a, c, jx, jy, phi0, wx, wy, dza, sec);
@@ -1105,6 +1142,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           put_none<Tg>(a, slot0 + i);
           continue;
         }
+        if constexpr (kCasc == 2) w = w * ain;
         const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
         put_record<Prec>(a, slot0 + i, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
         ++n_sec;

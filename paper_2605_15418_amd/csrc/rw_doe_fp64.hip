@@ -7,7 +7,17 @@ namespace rw {
 template <int M, bool LDS>
 static void go(bool fwd, const DoeArgs& a, const RayBlockIter& it, long long n, int pair0,
                int blocks, hipStream_t st) {
-  if (fwd)
+  if (fwd && (a.relay || a.ain)) {
+    // the two DOEs of a cascade (built for the patch sizes that stay in LDS)
+    if constexpr (LDS) {
+      if (a.relay)
+        hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS, 1>), dim3(blocks), dim3(kDoeThreads), 0, st,
+                           a, it, n, pair0);
+      else
+        hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS, 2>), dim3(blocks), dim3(kDoeThreads), 0, st,
+                           a, it, n, pair0);
+    }
+  } else if (fwd)
     hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS>), dim3(blocks), dim3(kDoeThreads), 0, st, a, it,
                        n, pair0);
   else if (a.full && a.interp)

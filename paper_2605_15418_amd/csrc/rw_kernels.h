@@ -65,6 +65,8 @@ struct DevCfg {
   double curv_eps;         // curvature bound of the class rule
   int reflective;          // secondaries leave back into the medium before the DOE
   int ns_idx;              // n_med index of the medium at the sensor
+  int relay_n1;            // first DOE of a cascade: side of each ray's block of relayed
+                           // secondaries on the second DOE's ray grid (0: no cascade)
 };
 
 struct DevPair {
@@ -308,6 +310,12 @@ struct DoeArgs {
   int32_t* jdraw;            // [n_total][N] bins drawn by the forward (read by the backward)
   int full;                  // FULL sampling (every propagating bin, no draws)
   int cls;                   // class processed by this launch
+  // two-DOE cascade
+  double* relay;             // first DOE: ray state [10][relay_n] of the second DOE's
+                             // incident rays (p, d, opl, alive, amplitude re, im), or null
+  size_t relay_n;
+  const DevCfg* cfg2;        // first DOE: the second DOE's configuration
+  const double* ain;         // second DOE: incident amplitudes [2][n_total] (re, im), or null
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
@@ -462,6 +470,95 @@ __device__ __forceinline__ bool secondary_to_sensor(const DoeArgs& a, const RayC
   wy = k0 * (Tp)ns * (Tp)cfg.psf_pitch * (Tp)d[1];
   dz_abs = fabs((double)d[2]);
   sec.ok = true;
+  return true;
+}
+
+// ---------------------------------------------------------- DOE cascade ---
+// Two DOEs in sequence: a secondary of the first DOE is traced to the second
+// DOE's surface, where it is an incident ray whose complex amplitude is its
+// Eq. 1 weight and whose phase is its optical path.  Secondary i of ray
+// (iy, ix) of the first DOE's launch grid becomes ray
+// (iy n1 + i / n1, ix n1 + i % n1) of the second DOE's grid of side R n1.
+__device__ __forceinline__ size_t relay_gid(const DevCfg& cfg, const DevCfg& c2, int pair, int r,
+                                            int i) {
+  const int n1 = cfg.relay_n1;
+  const int iy = r / cfg.R, ix = r % cfg.R;
+  return (size_t)pair * c2.R2 + (size_t)(iy * n1 + i / n1) * c2.R + (size_t)(ix * n1 + i % n1);
+}
+
+__device__ __forceinline__ void relay_put(const DoeArgs& a, size_t g, const double* p,
+                                          const double* d, double opl, double are, double aim) {
+  double* st = a.relay;
+  const size_t n = a.relay_n;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { st[k * n + g] = p[k]; st[(3 + k) * n + g] = d[k]; }
+  st[6 * n + g] = opl;
+  st[7 * n + g] = 1.0;
+  st[8 * n + g] = are;
+  st[9 * n + g] = aim;
+}
+
+// A relay slot that carries no ray (dead incident ray, failed draw or trace).
+__device__ __forceinline__ void relay_none(const DoeArgs& a, int pair, int r, int i) {
+  const size_t g = relay_gid(*a.cfg, *a.cfg2, pair, r, i);
+  const size_t n = a.relay_n;
+  double* st = a.relay;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) st[k * n + g] = k == 5 ? 1.0 : 0.0;
+}
+
+// Emission of the first DOE's secondary (jx, jy) with weight w, conventional
+// trace through the surfaces between the DOEs (refracting) to the second DOE's
+// surface (intersected only; its map is the stop), and the relay record.
+template <class Prec>
+__device__ __forceinline__ bool relay_secondary(const DoeArgs& a, const RayCtx& c, int jx, int jy,
+                                                double wre, double wim, int i) {
+  using Tt = typename Prec::Tt;
+  const DevCfg& cfg = *a.cfg;
+  const DevCfg& c2 = *a.cfg2;
+  const DevPair& pr = a.pairs[c.pair];
+  const double Ku = c.kin_u + c.dk * jx, Kv = c.kin_v + c.dk * jy;
+  const double kz2 = c.k_out * c.k_out - Ku * Ku - Kv * Kv;
+  bool ok = kz2 > 0.0;
+  Tt d[3], p[3];
+  Tt opl = (Tt)c.opl;
+  if (ok) {
+    const double kz = sqrt(kz2), ik = 1.0 / c.k_out;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      d[k] = (Tt)((Ku * c.u[k] + Kv * c.v[k] + kz * c.n[k]) * ik);
+      p[k] = (Tt)c.p[k];
+    }
+    for (int s = cfg.s_doe + 1; s <= c2.s_doe; ++s) {
+      const DevSurf& ds = a.live->s[s];
+      const Surf<Tt> sf = surf_of<Tt>(ds);
+      Tt t;
+      if (!intersect(sf, p, d, t)) { ok = false; break; }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) p[k] += t * d[k];
+      opl += (Tt)pr.n_med[s] * t;
+      if (ds.semi_ap > 0 && (double)(p[0] * p[0] + p[1] * p[1]) > ds.semi_ap * ds.semi_ap) {
+        ok = false;
+        break;
+      }
+      if (s == c2.s_doe) break;
+      Tt nrm[3];
+      surface_normal(sf, p[0], p[1], nrm);
+      if (!refract(d, nrm, (Tt)(pr.n_med[s] / pr.n_med[s + 1]))) { ok = false; break; }
+    }
+    if (ok) {
+      const double fx = ((double)p[0] - c2.x0) / c2.pitch;
+      const double fy = ((double)p[1] - c2.y0) / c2.pitch;
+      ok = fx >= -0.5 && fx <= c2.W - 0.5 && fy >= -0.5 && fy <= c2.H - 0.5;
+    }
+  }
+  if (!ok) {
+    relay_none(a, c.pair, c.r, i);
+    return false;
+  }
+  const double pd[3] = {(double)p[0], (double)p[1], (double)p[2]};
+  const double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+  relay_put(a, relay_gid(cfg, c2, c.pair, c.r, i), pd, dd, (double)opl, wre, wim);
   return true;
 }
 

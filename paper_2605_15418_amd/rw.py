@@ -27,7 +27,7 @@ AUTOTUNE_CACHE = os.path.join(_HERE, "autotune_cache.json")   # launch shapes by
 STATUS = {0: "RW_OK", 1: "RW_ERR_INVALID_ARG", 2: "RW_ERR_SHAPE", 3: "RW_ERR_STATE",
           4: "RW_ERR_NONFINITE", 5: "RW_ERR_OOM", 6: "RW_ERR_HIP", 7: "RW_ERR_UNSUPPORTED"}
 
-EXPORTED = ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
+EXPORTED = ("rw_plan_create", "rw_plan_create_cascade", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
             "rw_backward", "rw_forward_backward", "rw_set_launch_shape",
             "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_status_string",
             "rw_last_error", "rw_set_profiling", "rw_get_profile", "rw_set_graph",
@@ -102,6 +102,11 @@ def load_library(path=LIB_PATH):
     lib.rw_plan_create.argtypes = [ctypes.POINTER(rw_surface), ctypes.c_int,
                                    ctypes.POINTER(rw_doe_desc), ctypes.POINTER(rw_param_ref),
                                    ctypes.c_int, ctypes.POINTER(rw_config), ctypes.POINTER(vp)]
+    lib.rw_plan_create_cascade.argtypes = [ctypes.POINTER(rw_surface), ctypes.c_int,
+                                           ctypes.POINTER(rw_doe_desc),
+                                           ctypes.POINTER(rw_doe_desc), ctypes.c_int,
+                                           ctypes.POINTER(rw_param_ref), ctypes.c_int,
+                                           ctypes.POINTER(rw_config), ctypes.POINTER(vp)]
     lib.rw_plan_workspace_bytes.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
     lib.rw_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.rw_forward_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -121,7 +126,8 @@ def load_library(path=LIB_PATH):
     lib.rw_status_string.argtypes = [ctypes.c_int]
     lib.rw_status_string.restype = ctypes.c_char_p
     lib.rw_last_error.restype = ctypes.c_char_p
-    for name in ("rw_plan_create", "rw_plan_workspace_bytes", "rw_forward", "rw_forward_static",
+    for name in ("rw_plan_create", "rw_plan_create_cascade", "rw_plan_workspace_bytes",
+                 "rw_forward", "rw_forward_static",
                  "rw_backward", "rw_forward_backward",
                  "rw_get_stats", "rw_export_doe_hits", "rw_plan_destroy", "rw_set_profiling",
                  "rw_get_profile", "rw_set_graph", "rw_autotune", "rw_set_launch_shape",
@@ -192,6 +198,10 @@ class Plan:
     system = {"surfaces", "sensor_z", "doe", "params"}, cfg = {"lambdas",
     "fields", "launch_center", "launch_z", "launch_half", "rays_side", "psf_q",
     "psf_pitch", "psf_center", "patch_p", "pad", "n_ssr", "sampling", "seed"}.
+    A system with "does" (two map descriptions, for the two surfaces flagged
+    "doe") and a cfg with "n_ssr2" make a two-DOE cascade plan (forward only):
+    its maps are [2, H, W] and its sample indices the first DOE's followed by
+    the second's (split_idx separates them).
     """
 
     def __init__(self, system, cfg, precision="mixed", batched=True, spread_width=0,
@@ -217,10 +227,12 @@ class Plan:
             arr[i].semi_aperture = s["semi_ap"]
             arr[i].n_A = s["nA"]
             arr[i].n_B = s["nB"]
-        d = system["doe"]
-        doe = rw_doe_desc(d["H"], d["W"], d["pitch"], d["x0"], d["y0"],
-                          int(bool(d.get("reflective", False))),
-                          FIELDS[d.get("field", "amp_phase")])
+        def desc(d):
+            return rw_doe_desc(d["H"], d["W"], d["pitch"], d["x0"], d["y0"],
+                               int(bool(d.get("reflective", False))),
+                               FIELDS[d.get("field", "amp_phase")])
+        self.cascade = "does" in system
+        doe = desc(system["does"][1] if self.cascade else system["doe"])
         prm = system.get("params", [])
         parr = (rw_param_ref * max(1, len(prm)))()
         for i, p in enumerate(prm):
@@ -267,8 +279,15 @@ class Plan:
         c.check_finite = int(bool(check_finite))
         c.record_budget_bytes = int(cfg.get("record_budget_bytes", 0))
         h = ctypes.c_void_p()
-        _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
-                                                 len(prm), ctypes.byref(c), ctypes.byref(h)))
+        if self.cascade:
+            doe1 = desc(system["does"][0])
+            _check(self.lib, self.lib.rw_plan_create_cascade(
+                arr, len(surfs), ctypes.byref(doe1), ctypes.byref(doe), int(cfg["n_ssr2"]), parr,
+                len(prm), ctypes.byref(c), ctypes.byref(h)))
+        else:
+            _check(self.lib, self.lib.rw_plan_create(arr, len(surfs), ctypes.byref(doe), parr,
+                                                     len(prm), ctypes.byref(c),
+                                                     ctypes.byref(h)))
         self.handle = h
         nf, nx = ctypes.c_size_t(), ctypes.c_size_t()
         _check(self.lib, self.lib.rw_plan_workspace_bytes(h, ctypes.byref(nf), ctypes.byref(nx)))
@@ -284,6 +303,11 @@ class Plan:
         self.n_rays = self.L * self.F * cfg["rays_side"] ** 2
         self.N = cfg["n_ssr"]
         self.M = cfg["patch_p"] * cfg["pad"]
+        if self.cascade:
+            # the second DOE's ray grid: side rays_side n1, n_ssr2 draws per ray
+            n1 = self.M if cfg["sampling"] == "full" else int(round(self.N ** 0.5))
+            self.casc_shape = ((self.L * self.F, cfg["rays_side"] ** 2, self.N),
+                               (self.L * self.F, (cfg["rays_side"] * n1) ** 2, cfg["n_ssr2"]))
         self.precision = precision
         self.generation = 0        # forwards run on this plan (HybridPSF checks it)
 
@@ -308,8 +332,12 @@ class Plan:
                                                                      device=dev)
         idx = idx_out
         if want_idx and idx is None:
-            idx = torch.empty((self.L * self.F, self.cfg["rays_side"] ** 2, self.N),
-                              dtype=torch.int32, device=dev)
+            if self.cascade:
+                idx = torch.empty(sum(int(np.prod(s)) for s in self.casc_shape),
+                                  dtype=torch.int32, device=dev)
+            else:
+                idx = torch.empty((self.L * self.F, self.cfg["rays_side"] ** 2, self.N),
+                                  dtype=torch.int32, device=dev)
         self._fwd_keep = (lens_params, phase, amp, target, replay)
         self.generation += 1
         st = self.lib.rw_forward(self.handle, _dptr(lens_params), _dptr(phase), _dptr(amp),
@@ -317,6 +345,16 @@ class Plan:
                                  self.ws_bytes, _dptr(replay), _dptr(idx), self._stream())
         _check(self.lib, st)
         return psf, loss, idx
+
+    def split_idx(self, idx):
+        """A cascade's sample indices as (first DOE [pairs, R^2, N1], second DOE
+        [pairs, (R n1)^2, N2]); join_idx is the inverse."""
+        n = int(np.prod(self.casc_shape[0]))
+        return idx[:n].reshape(self.casc_shape[0]), idx[n:].reshape(self.casc_shape[1])
+
+    @staticmethod
+    def join_idx(idx1, idx2):
+        return torch.cat([idx1.reshape(-1), idx2.reshape(-1)]).contiguous()
 
     def backward(self, dL_dpsf=None, d_phase=None, d_amp=None, d_lens=None):
         d = self.system["doe"]

@@ -1,0 +1,124 @@
+"""GPU two-DOE cascade vs the oracle's cascade (FP64), through the C ABI.
+
+A secondary of the first DOE is traced to the second DOE, where it is an
+incident wavelet whose amplitude is its Eq. 1 weight (Formalism, first
+paragraph: the construction extends to several DOEs).  Bars as for one DOE:
+  * FP64 form: both DOEs' sample indices bit-exact; PSF within 1e-6 (relative
+    L2 and element-wise against the peak; float32 output)
+  * MIXED form with the oracle's indices replayed, or FULL: PSF within 1e-4
+Launch grids of 9 x 9 rays (ragged against the 8 x 8 ray blocks), second-DOE
+grids of 36 x 36 (48 x 48 under FULL), four (wavelength, field) pairs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import rw_oracle as O
+from rwcases import elementwise_rel, gpu_inputs, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rw():
+    import paper_2605_15418_amd as pkg
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pkg.load_library()
+    return pkg
+
+
+def _case(sampling, rays=9, P=16, N=16, N2=8, **kw):
+    return W.two_doe_cascade(rays_side=rays, P=P, pad=2, N=N, N2=N2, Q=32, psf_pitch=0.02,
+                             sampling=sampling, lambdas=(W.LAM_D, W.LAM_F),
+                             fields=((0.0, 0.0), (0.004, -0.003)), **kw)
+
+
+def _oracle(system, cfg, maps, replays=None):
+    return O.cascade_psf_stack(system, cfg, maps["phase"].astype(np.float64),
+                               maps["amp"].astype(np.float64), replays=replays, keep=True)
+
+
+def _gpu(rw, system, cfg, maps, precision, replay=None):
+    plan = rw.Plan(system, cfg, precision=precision)
+    _, ph, am = gpu_inputs(system, maps)
+    psf, _, idx = plan.forward(None, ph, am, replay=replay, want_idx=cfg["sampling"] != "full")
+    torch.cuda.synchronize()
+    return plan, psf.cpu().numpy(), idx
+
+
+@pytest.mark.parametrize("sampling,pitch2", [("mag", 0.02), ("uni", 0.02), ("mag", 0.005)])
+def test_fp64_cascade_indices_exact_and_psf(rw, sampling, pitch2):
+    # pitch2 = 0.005: the second map (0.32 mm wide) stops part of the relayed rays
+    system, cfg, maps = _case(sampling, pitch=(0.004, pitch2))
+    print(f"cascade fp64 {sampling} {pitch2}", flush=True)
+    plan, psf, idx = _gpu(rw, system, cfg, maps, "fp64")
+    ref, aux = _oracle(system, cfg, maps)
+    i1, i2 = (x.cpu().numpy() for x in plan.split_idx(idx))
+    for pr, a in aux.items():
+        assert np.array_equal(i1[pr], a["J1"]), f"first DOE's indices differ (pair {pr})"
+        assert np.array_equal(i2[pr], a["J2"]), f"second DOE's indices differ (pair {pr})"
+        assert (a["J2"] >= 0).sum() > 0.3 * a["J2"].size
+    assert ref.max() > 0
+    assert rel_l2(psf, ref) < 1e-6
+    assert elementwise_rel(psf, ref) < 1e-6
+
+
+def test_mixed_cascade_with_oracle_draws(rw):
+    system, cfg, maps = _case("mag")
+    print("cascade mixed replay", flush=True)
+    ref, aux = _oracle(system, cfg, maps)
+    plan = rw.Plan(system, cfg, precision="mixed")
+    j1 = torch.tensor(np.stack([aux[p]["J1"] for p in sorted(aux)]), dtype=torch.int32)
+    j2 = torch.tensor(np.stack([aux[p]["J2"] for p in sorted(aux)]), dtype=torch.int32)
+    rep = plan.join_idx(j1, j2).cuda()
+    _, ph, am = gpu_inputs(system, maps)
+    psf, _, _ = plan.forward(None, ph, am, replay=rep)
+    torch.cuda.synchronize()
+    psf = psf.cpu().numpy()
+    assert rel_l2(psf, ref) < 1e-4
+    assert elementwise_rel(psf, ref) < 1e-4
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_full_cascade(rw, precision, bar):
+    # FULL at both DOEs: every propagating bin of every patch; M = 16, so the
+    # 3 x 3 launch grid relays to a 48 x 48 second-DOE grid
+    system, cfg, maps = _case("full", rays=3, P=8)
+    print(f"cascade full {precision}", flush=True)
+    _, psf, _ = _gpu(rw, system, cfg, maps, precision)
+    ref, _ = _oracle(system, cfg, maps)
+    assert ref.max() > 0
+    assert rel_l2(psf, ref) < bar
+    assert elementwise_rel(psf, ref) < bar
+
+
+def test_cascade_graph_replays_match_eager(rw):
+    system, cfg, maps = _case("mag")
+    print("cascade graph", flush=True)
+    plan, eager, _ = _gpu(rw, system, cfg, maps, "mixed")
+    plan.set_graph(True)
+    _, ph, am = gpu_inputs(system, maps)
+    out = torch.empty((plan.L, plan.F, plan.Q, plan.Q), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        plan.forward(None, ph, am, psf_out=out)
+        torch.cuda.synchronize()
+        assert rel_l2(out.cpu().numpy(), eager) < 1e-6
+
+
+def test_cascade_rejections(rw):
+    system, cfg, maps = _case("mag", N=12)
+    with pytest.raises(rw.RWError, match="RW_ERR_SHAPE"):
+        rw.Plan(system, cfg, precision="mixed")
+    system, cfg, maps = _case("mag")
+    cfg = dict(cfg, patch_classes=[8])
+    with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
+        rw.Plan(system, cfg, precision="mixed")
+    system, cfg, maps = _case("mag", P=64)
+    with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
+        rw.Plan(system, cfg, precision="fp64")       # M = 128 does not fit LDS in FP64
+    system, cfg, maps = _case("mag")
+    plan, _, _ = _gpu(rw, system, cfg, maps, "mixed")
+    with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
+        plan.backward(d_phase=torch.empty((2, 64, 64), device="cuda"),
+                      d_amp=torch.empty((2, 64, 64), device="cuda"))
