@@ -443,7 +443,8 @@ def main():
     fwd_only = None
     if not args.no_forward_only:
         fwd_only = {}
-        for name, prec in (("conformal_sphere", "mixed"), ("singlet_zoneplate", "fp64")):
+        for name, prec in (("conformal_sphere", "mixed"), ("singlet_zoneplate", "fp64"),
+                           ("two_doe_cascade", "mixed")):
             s_, c_, m_ = W.workload(name)
             v_, ph_, am_, _ = inputs(s_, m_)
             pl = rw.Plan(s_, c_, precision=prec, batched=True)

@@ -538,4 +538,10 @@ def workload(name):
         return grating_before_lens()
     if name == "reflective_conformal":
         return reflective_conformal()
+    if name == "two_doe_cascade":
+        # 3 wavelengths x 128^2 launched rays, 16 relayed secondaries each (a
+        # 512^2 second-DOE grid), 16 draws per arriving ray: 4.2e6 records a pair
+        return two_doe_cascade(rays_side=128, H=256, pitch=(0.001, 0.02), P=32, pad=2, N=16,
+                               N2=16, Q=256, psf_pitch=0.01, sampling="mag",
+                               lambdas=(LAM_F, LAM_D, LAM_C))
     raise KeyError(name)
