@@ -479,13 +479,67 @@ def patch_classes(cfg):
                   reverse=True)
 
 
-def ray_patch_sides(surf, p, pitch, cfg):
+# ----------------------------------------------------------------------------
+# Adaptive patch sizing (Conclusion: future work on adaptive patch sizing that
+# balances local diffraction accuracy against propagation cost).  READING Q31:
+# a patch resolves the diffraction orders of a locally periodic map when it
+# spans K local periods; the ray takes the smallest candidate side with
+# P pitch >= K Lambda_loc, Lambda_loc = 2 pi / |grad phi| at the map pixel
+# nearest the hit, and the largest side where the map is flatter than that.
+# The gradient is the mean of the two one-pixel differences of the phase, each
+# wrapped to [-pi, pi] (exact for linear and quadratic phases, valid for local
+# periods above two pixels, the map's Nyquist limit); the pixel is clamped one
+# away from the map edge.  Combined with Eq. 4, the ray takes the smaller side.
+# ----------------------------------------------------------------------------
+def wrap_phase(a):
+    """a - 2 pi round(a / 2 pi): the phase difference in [-pi, pi]."""
+    return a - TWO_PI * np.rint(a / TWO_PI)
+
+
+def local_phase_gradient2(phase, doe, x, y):
+    """|grad phi|^2 (rad^2/mm^2) at the map pixel nearest each (x, y)."""
+    H, W = phase.shape
+    pitch = doe["pitch"]
+    jx = np.clip(np.rint((x - doe["x0"]) / pitch), 1, W - 2).astype(np.int64)
+    jy = np.clip(np.rint((y - doe["y0"]) / pitch), 1, H - 2).astype(np.int64)
+    c = phase[jy, jx]
+    gx = (wrap_phase(phase[jy, jx + 1] - c) + wrap_phase(c - phase[jy, jx - 1])) / (2.0 * pitch)
+    gy = (wrap_phase(phase[jy + 1, jx] - c) + wrap_phase(c - phase[jy - 1, jx])) / (2.0 * pitch)
+    return gx * gx + gy * gy
+
+
+def bandwidth_sides(phase, doe, x, y, cands, K):
+    """Smallest candidate side spanning K local periods ((P pitch)^2 |grad phi|^2
+    >= (2 pi K)^2), else the largest; cands sorted largest first."""
+    g2 = local_phase_gradient2(phase, doe, x, y)
+    out = np.full(x.shape[0], cands[0], dtype=np.int64)
+    lim = (TWO_PI * K) ** 2
+    for i in range(x.shape[0]):
+        for P in reversed(cands):
+            D = P * doe["pitch"]
+            if D * D * g2[i] >= lim:
+                out[i] = P
+                break
+    return out
+
+
+def ray_patch_sides(surf, p, pitch, cfg, phase_map=None, doe=None):
     """Per-ray patch side by the curvature bound of Eq. 4: the largest candidate
     P with arcsin(P pitch / 2 R_loc) <= eps (READING: R_loc the smallest principal
-    radius at the hit); the smallest candidate when none qualifies."""
+    radius at the hit); the smallest candidate when none qualifies.  With
+    cfg["bw_periods"] = K > 0, the smaller of that side and the bandwidth side
+    (adaptive patch sizing, READING Q31) of the phase map."""
     cands = patch_classes(cfg)
     if len(cands) == 1:
         return np.full(p.shape[0], cands[0], dtype=np.int64)
+    K = float(cfg.get("bw_periods", 0.0))
+    if K > 0:
+        if phase_map is None:
+            raise ValueError("adaptive patch sizing needs the phase map")
+        xy = p[:, :2].detach().numpy()
+        bw = bandwidth_sides(np.asarray(phase_map, dtype=np.float64), doe, xy[:, 0], xy[:, 1],
+                             cands, K)
+        return np.minimum(ray_patch_sides(surf, p, pitch, dict(cfg, bw_periods=0.0)), bw)
     eps = float(cfg.get("curv_eps", 0.1))
     R = local_radius(surf, p[:, 0].detach(), p[:, 1].detach()).detach().numpy()
     out = np.full(p.shape[0], cands[-1], dtype=np.int64)
@@ -505,9 +559,10 @@ def detach_pdf(cfg):
 
 
 def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
-                 keep=False, ray_subset=None):
+                 keep=False, ray_subset=None, phase_map=None):
     """Returns dict with field U [Q, Q] (complex, differentiable), PSF, and
-    (if keep) intermediate quantities for stage-level comparison."""
+    (if keep) intermediate quantities for stage-level comparison.  phase_map:
+    the phase map (numpy), for adaptive patch sizing."""
     surfs, sensor_z = build_surfaces(system, values)
     doe = system["doe"]
     lam = cfg["lambdas"][lam_idx]
@@ -544,7 +599,7 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     k_in_t = k0 * n_in * torch.stack([(d * u).sum(-1), (d * v).sum(-1)], dim=-1)
 
     # patch classes (Eq. 4); one class unless cfg lists several candidate sides
-    sides = ray_patch_sides(surf_doe, p, doe["pitch"], cfg)
+    sides = ray_patch_sides(surf_doe, p, doe["pitch"], cfg, phase_map, doe)
     R = p.shape[0]
     J_all = np.full((R, Nd), -1, dtype=np.int64) if sampling != "full" else None
     parts = []
@@ -769,7 +824,8 @@ def psf_stack(system, cfg, phase, amp, values=None, replays=None, pairs=None, ke
                 if pairs is not None and pr not in pairs:
                     continue
                 rep = None if replays is None else replays.get(pr)
-                r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=keep)
+                r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=keep,
+                                 phase_map=phase)
                 out[l, f] = r["psf"].numpy()
                 aux[pr] = r
     return out, aux
@@ -792,7 +848,8 @@ def loss_and_grad(system, cfg, phase, amp, values, target, replays=None, want_gr
             pr = l * F + f
             tmap = transmission(ph, am, system["doe"].get("field", "amp_phase"))
             rep = None if replays is None else replays.get(pr)
-            r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=True)
+            r = pair_forward(system, cfg, tmap, l, f, vals, rep, keep=True,
+                             phase_map=phase)
             Lp = eq5_loss(r["psf"], _t(target[l, f]))
             if want_grad:
                 Lp.backward()
