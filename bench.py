@@ -464,6 +464,50 @@ def main():
             del pl
             torch.cuda.empty_cache()
 
+    # ------------------------------------- adaptive patch sizing (K local periods)
+    adaptive = None
+    if not args.no_forward_only:
+        adaptive = {}
+        s_, c_, m_ = W.workload("adaptive_zone_plate")
+        v_, ph_, am_, tg_ = inputs(s_, m_)
+        big = max(classes_of(c_))
+        forms = (("adaptive", c_), (f"fixed_P{big}", dict(c_, patch_classes=[], bw_periods=0.0)))
+        for tag, cc in forms:
+            # fwd + bwd (MAG, G1) at full size
+            pl = rw.Plan(s_, cc, precision="mixed", batched=True)
+            pl.step(v_, ph_, am_, tg_)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl.step(v_, ph_, am_, tg_)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            adaptive[tag] = {"ms_fwd_bwd": dt * 1e3,
+                             "rays_by_class": pl.stats()["rays_by_class"][:len(classes_of(cc))]}
+            del pl
+            torch.cuda.empty_cache()
+        # accuracy of the rule: FULL-mode PSFs on a 64^2 sub-grid of rays, against
+        # every ray at the largest patch
+        cf = dict(c_, sampling="full", rays_side=64,
+                  launch_half=c_["launch_half"] * (1 - 1 / 64) / (1 - 1 / c_["rays_side"]))
+        psfs = {}
+        for tag, cc in (("adaptive", cf), (f"P{big}", dict(cf, patch_classes=[], bw_periods=0.0)),
+                        *[(f"P{q}", dict(cf, patch_p=q, patch_classes=[], bw_periods=0.0))
+                          for q in classes_of(c_)[1:]]):
+            pl = rw.Plan(s_, cc, precision="mixed", batched=True)
+            psf_, _, _ = pl.forward(v_, ph_, am_)
+            torch.cuda.synchronize()
+            psfs[tag] = psf_.double().cpu().numpy()
+            del pl
+            torch.cuda.empty_cache()
+        ref_ = psfs[f"P{big}"]
+        adaptive["psf_rel_l2_vs_all_largest"] = {
+            t: float(np.linalg.norm(v - ref_) / np.linalg.norm(ref_)) for t, v in psfs.items()
+            if t != f"P{big}"}
+        adaptive["speedup"] = adaptive[f"fixed_P{big}"]["ms_fwd_bwd"] / adaptive["adaptive"]["ms_fwd_bwd"]
+        log(f"adaptive_zone_plate: fwd+bwd {adaptive['adaptive']['ms_fwd_bwd']:.1f} ms adaptive, "
+            f"{adaptive[f'fixed_P{big}']['ms_fwd_bwd']:.1f} ms at P = {big}; "
+            f"PSF vs all-P{big}: {adaptive['psf_rel_l2_vs_all_largest']}")
+
     # -------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu:
@@ -515,14 +559,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc[args.workload],
-                   "form": "batched MIXED (FP32 FFT/grids/trace, FP64 OPL, phases and Newton "
-                           "refinement), autotuned launch shapes, HIP-graph replays",
+                   "form": "batched MIXED (FP32 patch FFTs, spectra and grids; FP64 trace, "
+                           "OPL and phases), autotuned launch shapes, HIP-graph replays",
                    "incident_rays_per_step": head["incident_rays_per_step"],
                    "secondary_rays_per_step": head["secondary_rays_per_step"],
                    "secondary_rays_per_s": head["secondary_rays_per_s"]},
         "headline": head,
         "asphere_hologram": side,
         "forward_only": fwd_only,
+        "adaptive_patch_sizing": adaptive,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -164,6 +164,15 @@ typedef struct {
    * interpolation's slots and results); 0 = 96 GiB.  Pairs whose records exceed
    * it run in several groups. */
   uint64_t record_budget_bytes;
+  /* Adaptive patch sizing (the paper's future work; reading in the design notes):
+   * K > 0 local periods.  Each ray also takes the smallest patch class side P with
+   * (P pitch)^2 |grad phi|^2 >= (2 pi K)^2 -- the patch spans K periods of the map's
+   * local grating -- and the largest where the map is flatter; of this side and the
+   * curvature side of Eq. 4 the smaller wins.  |grad phi| at the map pixel nearest
+   * the hit (clamped one pixel from the edge): per axis the mean of the two
+   * one-pixel differences of doe_phase, each wrapped to [-pi, pi], over the pitch.
+   * Needs n_patch_class >= 1 and the amplitude-phase field.  0: off. */
+  double bandwidth_periods;
 } rw_config;
 
 typedef struct rw_plan rw_plan;

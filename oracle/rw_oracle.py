@@ -513,7 +513,7 @@ def bandwidth_sides(phase, doe, x, y, cands, K):
     >= (2 pi K)^2), else the largest; cands sorted largest first."""
     g2 = local_phase_gradient2(phase, doe, x, y)
     out = np.full(x.shape[0], cands[0], dtype=np.int64)
-    lim = (TWO_PI * K) ** 2
+    lim = (TWO_PI * K) * (TWO_PI * K)
     for i in range(x.shape[0]):
         for P in reversed(cands):
             D = P * doe["pitch"]

@@ -118,6 +118,7 @@ struct rw_plan {
   // two-DOE cascade (rw_plan_create_cascade): the fields above describe the
   // second DOE and its incident rays (the first DOE's secondaries); the first
   // DOE's launch grid, map and ray state are these
+  const float* cur_phase = nullptr;   // phase map of the forward being enqueued
   bool casc = false;
   int s_doe1 = -1, R1 = 0, R1sq = 0, N1 = 0;
   size_t n1_total = 0;
@@ -291,6 +292,7 @@ DoeArgs doe_args(rw_plan* pl, void* ws, const int32_t* replay, int32_t* idx_out)
                                                                  : (int32_t*)(b + pl->off_jdraw);
   a.full = pl->cfg.sampling == RW_SAMPLE_FULL;
   a.cls = 0;
+  a.phase = pl->cur_phase;
   return a;
 }
 
@@ -586,6 +588,12 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   }
   if (cfg->n_patch_class > 0 && !(cfg->curv_eps > 0.0))
     return fail(RW_ERR_INVALID_ARG, "curv_eps must be positive");
+  if (!(cfg->bandwidth_periods >= 0.0) || std::isinf(cfg->bandwidth_periods))
+    return fail(RW_ERR_INVALID_ARG, "bandwidth_periods must be finite and >= 0");
+  if (cfg->bandwidth_periods > 0.0 &&
+      (cfg->n_patch_class == 0 || doe->field != RW_FIELD_AMP_PHASE || doe->H < 3 || doe->W < 3))
+    return fail(RW_ERR_INVALID_ARG, "adaptive patch sizing needs patch classes, the amplitude-"
+                                    "phase field and a map of at least 3 x 3 pixels");
   for (int l = 0; l < cfg->n_lambda; ++l)
     if (!(cfg->lambda_host[l] > 0)) return fail(RW_ERR_INVALID_ARG, "wavelength must be > 0");
 
@@ -706,6 +714,9 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   dc.n_class = pl->n_class;
   for (int i = 0; i < pl->n_class; ++i) dc.class_p[i] = pl->class_p[i];
   dc.curv_eps = cfg->curv_eps;
+  dc.bw_k2 = cfg->bandwidth_periods > 0.0
+                 ? (2.0 * M_PI * cfg->bandwidth_periods) * (2.0 * M_PI * cfg->bandwidth_periods)
+                 : 0.0;
   dc.tau = cfg->tau > 0.0 ? cfg->tau : 1.0;
   dc.planar = pl->planar_doe ? 1 : 0;
   dc.reflective = doe->reflective ? 1 : 0;
@@ -1151,6 +1162,7 @@ static rw_status fwd_prologue(rw_plan* pl, const float* lens_params, const float
                               const float* doe_amp, void* ws, hipStream_t st) {
   char* b = (char*)ws;
   const bool dbl_f = pl->cfg.precision == RW_PREC_FP64;
+  pl->cur_phase = doe_phase;
   hipLaunchKernelGGL(k_params, dim3(1), dim3(1), 0, st, pl->d_cfg, pl->d_base, pl->base_sensor_z,
                      pl->d_prm, lens_params, (DevLive*)(b + pl->off_live));
   const int nmap = pl->H * pl->W;

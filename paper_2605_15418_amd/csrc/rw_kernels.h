@@ -63,6 +63,7 @@ struct DevCfg {
   int n_class;             // patch classes (1: every ray uses P)
   int class_p[4];          // candidate patch sides, largest first (class_p[0] = P)
   double curv_eps;         // curvature bound of the class rule
+  double bw_k2;            // adaptive patch sizing: (2 pi K)^2 for K local periods (0: off)
   int reflective;          // secondaries leave back into the medium before the DOE
   int ns_idx;              // n_med index of the medium at the sensor
   int relay_n1;            // first DOE of a cascade: side of each ray's block of relayed
@@ -316,6 +317,7 @@ struct DoeArgs {
   size_t relay_n;
   const DevCfg* cfg2;        // first DOE: the second DOE's configuration
   const double* ain;         // second DOE: incident amplitudes [2][n_total] (re, im), or null
+  const float* phase;        // the phase map [H][W] (adaptive patch sizing)
 };
 
 // Frame and incident tangential wavevector at the DOE hit (double).
@@ -330,6 +332,31 @@ struct RayCtx {
   size_t gid;
 };
 constexpr int kCtxWords = (int)(sizeof(RayCtx) / 4);
+
+// Adaptive patch sizing: |grad phi|^2 at the map pixel nearest (x, y), the pixel
+// clamped one away from the edge; each axis takes the mean of its two one-pixel
+// phase differences wrapped to [-pi, pi].  Every operation is rounded on its own
+// (no contraction), so that the class decision is the oracle's.
+__device__ __forceinline__ double wrap_phase(double d) {
+  const double tp = 2.0 * RW_PI;
+  return __dsub_rn(d, __dmul_rn(tp, rint(__ddiv_rn(d, tp))));
+}
+
+__device__ __forceinline__ double local_phase_gradient2(const float* ph, const DevCfg& cfg,
+                                                        double x, double y) {
+  const int W = cfg.W, H = cfg.H;
+  const int jx = (int)fmin(fmax(rint(__ddiv_rn(__dsub_rn(x, cfg.x0), cfg.pitch)), 1.0), W - 2.0);
+  const int jy = (int)fmin(fmax(rint(__ddiv_rn(__dsub_rn(y, cfg.y0), cfg.pitch)), 1.0), H - 2.0);
+  const double c = ph[(size_t)jy * W + jx];
+  const double two_p = __dmul_rn(2.0, cfg.pitch);
+  const double gx = __ddiv_rn(__dadd_rn(wrap_phase(__dsub_rn((double)ph[(size_t)jy * W + jx + 1], c)),
+                                        wrap_phase(__dsub_rn(c, (double)ph[(size_t)jy * W + jx - 1]))),
+                              two_p);
+  const double gy = __ddiv_rn(__dadd_rn(wrap_phase(__dsub_rn((double)ph[(size_t)(jy + 1) * W + jx], c)),
+                                        wrap_phase(__dsub_rn(c, (double)ph[(size_t)(jy - 1) * W + jx]))),
+                              two_p);
+  return __dadd_rn(__dmul_rn(gx, gx), __dmul_rn(gy, gy));
+}
 
 __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c) {
   const DevCfg& cfg = *a.cfg;
@@ -370,6 +397,21 @@ __device__ __forceinline__ void make_ctx(const DoeArgs& a, size_t gid, RayCtx& c
         c.cls = k;
         break;
       }
+    }
+    if (cfg.bw_k2 > 0.0) {
+      // adaptive patch sizing: the smallest side spanning K local periods of the
+      // phase map (the largest where the map is flatter); the smaller side of
+      // this rule and the curvature bound wins
+      const double g2 = local_phase_gradient2(a.phase, cfg, c.p[0], c.p[1]);
+      int kb = 0;
+      for (int k = cfg.n_class - 1; k >= 0; --k) {
+        const double D = __dmul_rn((double)cfg.class_p[k], cfg.pitch);
+        if (__dmul_rn(__dmul_rn(D, D), g2) >= cfg.bw_k2) {
+          kb = k;
+          break;
+        }
+      }
+      if (kb > c.cls) c.cls = kb;
     }
   }
   c.P = cfg.class_p[c.cls];

@@ -69,7 +69,8 @@ class rw_config(ctypes.Structure):
                 ("grad", ctypes.c_int), ("tau", ctypes.c_double),
                 ("n_patch_class", ctypes.c_int), ("patch_class_p", ctypes.c_int * 3),
                 ("curv_eps", ctypes.c_double), ("check_finite", ctypes.c_int),
-                ("record_budget_bytes", ctypes.c_uint64)]
+                ("record_budget_bytes", ctypes.c_uint64),
+                ("bandwidth_periods", ctypes.c_double)]
 
 
 class rw_profile(ctypes.Structure):
@@ -278,6 +279,7 @@ class Plan:
         c.curv_eps = float(cfg.get("curv_eps", 0.1))
         c.check_finite = int(bool(check_finite))
         c.record_budget_bytes = int(cfg.get("record_budget_bytes", 0))
+        c.bandwidth_periods = float(cfg.get("bw_periods", 0.0))
         h = ctypes.c_void_p()
         if self.cascade:
             doe1 = desc(system["does"][0])

@@ -490,6 +490,31 @@ def reflective_conformal(rays_side=64, H=501, lam=1e-3, P=128, N=2048, Q=512, ps
 
 
 # ----------------------------------------------------------------------------
+# Adaptive patch sizing: a kinoform zone plate (focal length f at lam) on a
+# planar DOE in air under collimated light, with a band-limited amplitude in
+# [0.5, 1]; its local period lam f / r falls from the axis outwards, so the
+# K-period rule gives the largest patch near the axis and smaller ones further
+# out.  Sensor at the focus; Airy target of the aperture's NA with a seeded
+# offset of up to 2 px.
+# ----------------------------------------------------------------------------
+def adaptive_zone_plate(rays_side=256, H=1024, pitch=0.001, lam=0.5e-3, f=10.0, P=64,
+                        classes=(32, 16), K=2.0, N=256, Q=128, psf_pitch=0.001, sampling="mag",
+                        seed=0):
+    rng = np.random.default_rng(20260007 + seed)
+    doe = doe_desc(H, H, pitch)
+    phase = kinoform_zone_plate(doe, f, lam).astype(np.float32)
+    amp = (0.5 + 0.5 * bandlimited_uniform(H, H, 0.05, rng)).astype(np.float32)
+    system, cfg, maps = free_space_doe(phase, amp, pitch, f, lam, rays_side, P, Q, psf_pitch,
+                                       N=N, pad=2, sampling=sampling, seed=seed)
+    cfg["patch_classes"] = [int(c) for c in classes]
+    cfg["bw_periods"] = float(K)
+    NA = 0.5 * H * pitch / f
+    tgt = airy_target(Q, psf_pitch, lam, NA, (0.0, 0.0), rng.uniform(-2, 2, 2))
+    maps["target"] = tgt[None, None].astype(np.float32)
+    return system, cfg, maps
+
+
+# ----------------------------------------------------------------------------
 # Two DOEs in sequence: DOE 1 on a plane in air 1 mm before a BK7 plano-convex
 # (curved face R = 20 mm first, CT 1.5 mm), DOE 2 on the front face of a 1 mm
 # BK7 plate 1.5 mm behind the lens; sensor near the paraxial focus.  Both maps
@@ -538,6 +563,8 @@ def workload(name):
         return grating_before_lens()
     if name == "reflective_conformal":
         return reflective_conformal()
+    if name == "adaptive_zone_plate":
+        return adaptive_zone_plate()
     if name == "two_doe_cascade":
         # 3 wavelengths x 128^2 launched rays, 16 relayed secondaries each (a
         # 512^2 second-DOE grid), 16 draws per arriving ray: 4.2e6 records a pair
