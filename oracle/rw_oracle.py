@@ -588,7 +588,6 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     if keep:
         out.update(p_doe=p.detach().clone(), d_doe=d.detach().clone(),
                    opl_doe=opl.detach().clone(), alive=alive.clone(), ray_ids=ray_ids)
-    amp_in = alive.to(DT)          # READING: unit amplitude per live ray
     surf_doe = surfs[s_doe]
     reflective = bool(doe.get("reflective", False))
     n_in = medium_index(surfs, s_doe - 1, lam)
@@ -600,6 +599,12 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
 
     # patch classes (Eq. 4); one class unless cfg lists several candidate sides
     sides = ray_patch_sides(surf_doe, p, doe["pitch"], cfg, phase_map, doe)
+    # READING: unit amplitude per live ray, times (P_0 / P)^2 for a ray whose
+    # patch side P is below the largest candidate P_0: the rays' patches cover
+    # the DOE uniformly (Formalism), so on one ray grid every part of the DOE
+    # counts equally whatever the side of the patches that cover it
+    P0 = patch_classes(cfg)[0]
+    amp_in = alive.to(DT) * torch.as_tensor((P0 / sides.astype(np.float64)) ** 2)
     R = p.shape[0]
     J_all = np.full((R, Nd), -1, dtype=np.int64) if sampling != "full" else None
     parts = []

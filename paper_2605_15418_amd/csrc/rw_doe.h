@@ -1040,6 +1040,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const RayCtx& c = s.ctx;
       const int t = opaque_tid();
       const int P = c.P;
+      // class weight (P_0 / P)^2: on one ray grid every part of the DOE counts
+      // equally whatever the patch side that covers it (a power of two: exact)
+      const Tp fk = (Tp)class_weight(cfg, P);
       // incident amplitude at the second DOE of a cascade (1 otherwise)
       C2<Tp> ain = {Tp(1), Tp(0)};
       if constexpr (kCasc == 2) ain = {(Tp)a.ain[gid], (Tp)a.ain[a.n_total + gid]};
@@ -1079,7 +1082,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
             }
             const C2<Tf> X = buf[Gm::at(jy & (M - 1), jx & (M - 1))];
             const C2<Tf> U = X * centre_ref<Tf>(jx, jy, P, M);
-            C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
+            C2<Tp> w = {(Tp)U.re * (Tp)inv_m2 * fk, (Tp)U.im * (Tp)inv_m2 * fk};
             if constexpr (kCasc == 2) w = w * ain;
             const C2<Tp> cv = (w * wavelet_cis<Prec>(phi0)) * (Tp)dza;
             put_record<Prec>(a, slot0 + Lb, C2<Tg>{(Tg)cv.re, (Tg)cv.im}, wx, wy);
@@ -1117,9 +1120,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
             const Tf mag = cabs_rn(X);
             ok = mag > Tf(0);
             const Tp f = ok ? (Tp)(scale / (double)mag) : Tp(0);
-            w = {(Tp)U.re * f, (Tp)U.im * f};
+            w = {(Tp)U.re * f * fk, (Tp)U.im * f * fk};
           } else {
-            w = {(Tp)U.re * (Tp)scale, (Tp)U.im * (Tp)scale};
+            w = {(Tp)U.re * (Tp)scale * fk, (Tp)U.im * (Tp)scale * fk};
           }
         }
         if constexpr (kCasc == 1) {
@@ -1265,13 +1268,15 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
     else
       interp_adj_pair<Prec, 16>(cfg, (const C2<Tg>*)a.adj, c.pair, gx, gy, h, g0, dx, dy);
   }
-  const C2<double> cd = {(double)cv.re, (double)cv.im};
+  // the record carries the class weight (P_0 / P)^2 (exact power of two)
+  const double fk = class_weight(cfg, c.P);
+  const C2<double> cd = {(double)cv.re * fk, (double)cv.im * fk};
   const double cell = cfg.nf / (2.0 * RW_PI);
   wa.g_wx = -(cd.re * dx.re + cd.im * dx.im) * cell;
   wa.g_wy = -(cd.re * dy.re + cd.im * dy.im) * cell;
   wa.g_phi0 = -(g0.re * cd.im - g0.im * cd.re);
   wa.g_dz = (g0.re * cd.re + g0.im * cd.im) / dza;
-  const double er = (double)e.re * dza, ei = (double)e.im * dza;
+  const double er = (double)e.re * dza * fk, ei = (double)e.im * dza * fk;
   wa.g_w = {er * g0.re + ei * g0.im, er * g0.im - ei * g0.re};
   return true;
 }

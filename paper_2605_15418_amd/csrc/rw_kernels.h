@@ -320,6 +320,15 @@ struct DoeArgs {
   const float* phase;        // the phase map [H][W] (adaptive patch sizing)
 };
 
+// Amplitude of a ray whose patch side is P: (P_0 / P)^2, P_0 the largest patch
+// class side.  The rays' patches cover the DOE uniformly (Formalism), so on one
+// ray grid every part of the DOE counts equally whatever the side of the
+// patches over it.  A power of two (the sides are M / pad with M a power of two).
+__device__ __forceinline__ double class_weight(const DevCfg& cfg, int P) {
+  const double r = (double)cfg.class_p[0] / (double)P;
+  return r * r;
+}
+
 // Frame and incident tangential wavevector at the DOE hit (double).
 struct RayCtx {
   double p[3], d[3], opl;
