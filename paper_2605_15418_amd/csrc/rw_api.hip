@@ -138,7 +138,7 @@ struct rw_plan {
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
       off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
-      off_interp, off_g2, off_rcls, total;
+      off_interp, off_g2, off_rcls, off_slices, off_heavy, total;
   size_t fwd_bytes;        // workspace of a forward-only pass (a prefix of the layout)
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
@@ -310,6 +310,11 @@ rw_status doe_launch(rw_plan* pl, bool fwd, const DoeArgs& a, int pair0, int npa
   it.per_pair = it.nbx * it.nbx;
   it.R = R;
   const long long n_items = (long long)npairs * it.per_pair;
+  // XCD chunks: one contiguous eighth over 8 or more pairs (each eighth holds
+  // whole pairs, hence every patch class in like measure); below that, 32
+  // chunks per XCD, so that the rays of a class, which cluster in space, reach
+  // every XCD
+  it.chunk = npairs >= 8 ? (n_items + 7) / 8 : std::max<long long>(1, (n_items + 255) / 256);
   const int blocks = (int)std::min<long long>(n_items, pl->blocks_dir[fwd ? 0 : 1]);
   // one launch per patch class, each over the whole work list (rays of other
   // classes are skipped; dead rays belong to class 0)
@@ -434,11 +439,23 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   const void* sv = (const void*)(b + pl->off_sval);
   const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
   C2<Tg>* gr = (C2<Tg>*)(b + pl->off_grid);
+  // heavy tiles (records concentrated by a focusing system) in slices
+  unsigned char* sl = (unsigned char*)(b + pl->off_slices);
+  unsigned int* nh = (unsigned int*)(b + pl->off_heavy);
+  uint2* hv = (uint2*)(b + pl->off_heavy + 256);
+  zero<unsigned int>(nh, 1, st);
+  hipLaunchKernelGGL(k_spread_slices, dim3((unsigned)(((size_t)npairs * ntiles + 255) / 256)),
+                     dim3(256), 0, st, so, g, pair0, npairs, sl, hv, nh);
+  const dim3 hg(1024);
   switch (pl->w) {
 #define RW_SPREAD_CASE(W)                                                                     \
     case W:                                                                                   \
       hipLaunchKernelGGL((k_spread_tiles<Tg, W>), sg, dim3(256), lds, st, sp, sv, so, g,      \
-                         pl->beta, pair0, gr);                                                \
+                         pl->beta, pair0, gr, (const unsigned char*)sl, (const uint2*)nullptr, \
+                         (const unsigned int*)nullptr);                                       \
+      hipLaunchKernelGGL((k_spread_tiles<Tg, W>), hg, dim3(256), lds, st, sp, sv, so, g,      \
+                         pl->beta, pair0, gr, (const unsigned char*)sl, (const uint2*)hv,      \
+                         (const unsigned int*)nh);                                            \
       break;
     RW_SPREAD_CASE(4) RW_SPREAD_CASE(5) RW_SPREAD_CASE(6) RW_SPREAD_CASE(7) RW_SPREAD_CASE(8)
     RW_SPREAD_CASE(9) RW_SPREAD_CASE(10) RW_SPREAD_CASE(11) RW_SPREAD_CASE(12)
@@ -899,6 +916,14 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   pl->off_cnt = take(nk * sizeof(unsigned int));
   pl->off_offs = take((nk + 1) * sizeof(unsigned long long));
   pl->off_cur = take(nk * sizeof(unsigned long long));
+  {
+    // slices of the spreading tiles of one launch group, and the list of the
+    // heavy tiles' further slices (its length first)
+    const int tile = 4 * pl->bg.bin;
+    const size_t nt = (size_t)(pl->nf / tile) * (pl->nf / tile) * pl->group_pairs;
+    pl->off_slices = take(nt);
+    pl->off_heavy = take(256 + nt * (kSpreadSlices - 1) * sizeof(uint2));
+  }
   if (cs) {
     // the first DOE: its map, launched rays (state, checkpoints, contexts, classes)
     const size_t n1t = pl->n1_total;

@@ -928,6 +928,7 @@ __device__ __forceinline__ int draw_bin(const C2<Tf>* buf, const double* pref, c
 // Work item = block of rb x rb launch-grid rays of one pair.
 struct RayBlockIter {
   int rb, nbx, per_pair, R;
+  long long chunk;          // items per chunk of the XCD work distribution (ItemQueue)
   __device__ __forceinline__ int count() const { return rb * rb; }
   // global ray id of ray k of item it (or -1 past the grid edge)
   __device__ __forceinline__ long long ray(long long it, int k, int pair0) const {
@@ -941,33 +942,44 @@ struct RayBlockIter {
 };
 
 // Work items of the persistent DOE workgroups, taken dynamically.  Workgroups
-// are dispatched to the eight XCDs in turn (XCD = blockIdx % 8); XCD x owns the
-// contiguous item range [x q, (x + 1) q), q = ceil(n / 8), and its workgroups
-// take the next item of that range from a counter of their own (zeroed before
-// the launch): the items in flight on one XCD are neighbouring ray blocks, whose
-// patches share map lines in that XCD's L2, and the work balances itself.
-// Other grid sizes share one counter over [0, n).
+// are dispatched to the eight XCDs in turn (XCD = blockIdx % 8).  The item list
+// is cut into chunks of C consecutive items dealt to the XCDs in turn (chunk k
+// to XCD k % 8), and the workgroups of XCD x take the next item of its chunks,
+// in order, from a counter of their own (zeroed before the launch): the items
+// in flight on one XCD are neighbouring ray blocks, whose patches share map
+// lines in that XCD's L2, and the work balances itself within the XCD.  With
+// C = ceil(n / 8) each XCD owns one contiguous eighth (launches over many
+// pairs, whose eighths hold the same mix of work); smaller chunks spread a
+// single pair's rays of one patch class, which cluster in space, over all
+// XCDs.  Other grid sizes share one counter over [0, n).  Returns n when done.
 struct ItemQueue {
   unsigned long long* ctr;
-  long long base, end;
-  __device__ __forceinline__ ItemQueue(unsigned long long* c, long long n) {
+  long long end, C, count;
+  int x, xcd;
+  __device__ __forceinline__ ItemQueue(unsigned long long* c, long long n, long long chunk) {
     const int G = gridDim.x;
-    if (G % 8 == 0 && n >= G) {
-      const long long q = (n + 7) / 8;
-      const int x = blockIdx.x % 8;
-      base = (long long)x * q;
-      end = min(n, base + q);
+    end = n;
+    xcd = G % 8 == 0 && n >= G;
+    if (xcd) {
+      C = chunk < 1 ? 1 : chunk;
+      x = blockIdx.x % 8;
+      const long long nc = n / C, tail = n % C;
+      count = C * (nc / 8 + (x < nc % 8 ? 1 : 0)) + (tail > 0 && nc % 8 == x ? tail : 0);
       ctr = c + x;
     } else {
-      base = 0;
-      end = n;
+      C = n;
+      x = 0;
+      count = n;
       ctr = c;
     }
   }
   // the workgroup's next item (every thread calls it; two barriers)
   __device__ __forceinline__ long long next(long long* slot) {
     __syncthreads();
-    if (threadIdx.x == 0) *slot = base + (long long)atomicAdd(ctr, 1ull);
+    if (threadIdx.x == 0) {
+      const long long l = (long long)atomicAdd(ctr, 1ull);
+      *slot = l >= count ? end : xcd ? ((l / C) * 8 + x) * C + l % C : l;
+    }
     __syncthreads();
     return *slot;
   }
@@ -999,7 +1011,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   // t < kCtxWords) of the next ray are loaded while the current one runs
   const int cnt = itr.count();
   __shared__ long long s_item;
-  ItemQueue queue(a.wctr, n_items);
+  ItemQueue queue(a.wctr, n_items, itr.chunk);
   long long it_n = queue.next(&s_item);
   int k_n = 0;
   long long gid_n = -1;
@@ -1477,7 +1489,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
   __shared__ long long s_item;
-  ItemQueue queue(a.wctr, n_items);
+  ItemQueue queue(a.wctr, n_items, itr.chunk);
   for (long long it = queue.next(&s_item); it < queue.end; it = queue.next(&s_item)) {
     // anchor of the accumulator: the first live ray of the block
     if (t == 0) { s_box[0] = INT_MAX; s_box[1] = INT_MAX; s_box[2] = INT_MIN; s_box[3] = INT_MIN; }

@@ -947,8 +947,50 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kSpreadWaves = 4;      // waves per spreading block (256 threads)
+constexpr int kSpreadTarget = 65536; // records per slice of a heavy tile
+constexpr int kSpreadSlices = 32;    // most slices of one tile
 constexpr int kSpreadBatch = 32;     // queued records staged and added per round
 constexpr int kSpreadQueue = 96;     // queue capacity: a batch plus one scan step
+
+// Records in the 3 x 6 bins whose kernel footprints can reach bin row q of tile
+// (ty, tx): the records wave q of the tile's block scans.
+__device__ __forceinline__ unsigned long long strip_records(const unsigned long long* off,
+                                                            const BinGeom& g, int ty, int tx,
+                                                            int q) {
+  unsigned long long n = 0;
+  for (int i = 0; i < 18; ++i) {
+    const int by = i / 6 - 1, bx = i % 6 - 1;
+    const int bny = (ty * 4 + q + by + g.nb) % g.nb, bnx = (tx * 4 + bx + g.nb) % g.nb;
+    const int k = bin_key(bny, bnx, g);
+    n += off[k + 1] - off[k];
+  }
+  return n;
+}
+
+// Slices of every tile of a launch group (one thread per (pair, tile)): a tile
+// whose busiest strip scans more than kSpreadTarget records is cut into
+// S = ceil(records / kSpreadTarget) <= kSpreadSlices slices of its scan ranges.
+// slices[pair][tile] = S; slices 1 .. S - 1 of such tiles go to the list
+// (entry: pair * tiles + tile, slice), their count to *n_heavy (zero at launch).
+static __global__ __launch_bounds__(256) void k_spread_slices(const unsigned long long* offsets,
+                                                       BinGeom g, int pair0, int npairs,
+                                                       unsigned char* slices, uint2* heavy,
+                                                       unsigned int* n_heavy) {
+  const int tile = 4 * g.bin, ntx = g.nf / tile, nt = ntx * ntx;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)npairs * nt) return;
+  const int pl = (int)(i / nt), t = (int)(i % nt);
+  const unsigned long long* off = offsets + (size_t)(pair0 + pl) * g.keys;
+  unsigned long long nmax = 0;
+  for (int q = 0; q < 4; ++q) nmax = max(nmax, strip_records(off, g, t / ntx, t % ntx, q));
+  const int S = (int)min((unsigned long long)kSpreadSlices,
+                         max(1ull, (nmax + kSpreadTarget - 1) / kSpreadTarget));
+  slices[i] = (unsigned char)S;
+  if (S > 1) {
+    const unsigned int b = atomicAdd(n_heavy, (unsigned int)(S - 1));
+    for (int k = 1; k < S; ++k) heavy[b + k - 1] = make_uint2((unsigned int)i, (unsigned int)k);
+  }
+}
 
 // Static LDS of k_spread_tiles<Tg, w> besides the dynamic accumulator tile.
 __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
@@ -966,11 +1008,16 @@ __host__ __device__ constexpr size_t spread_static_lds(size_t sz_g, int w) {
 // with a plain LDS read-modify-write (the taps of one record are distinct
 // cells): no atomics.  Batches of 32 keep the block within a third of the LDS,
 // three blocks per CU.
+// A heavy tile (records concentrated by a focusing system) is cut into S
+// slices of every wave's scan range (k_spread_slices): the tile's own block
+// takes slice 0 and stores the tile; the blocks of the second launch (heavy
+// != null) take the listed slices 1 .. S - 1 afterwards and add their tiles to
+// the grid with atomics.
 template <class Tg, int w>
-__global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
-                                                      const unsigned long long* offsets,
-                                                      BinGeom g, double beta, int pair0,
-                                                      C2<Tg>* grid) {
+__device__ __forceinline__ void spread_tile(const void* srt_pos, const void* srt_val,
+                                            const unsigned long long* offsets, const BinGeom& g,
+                                            double beta, int pair, int tile_i, int slice, int S,
+                                            C2<Tg>* grid) {
   using U = typename RecPos<Tg>::T;
   constexpr int NW = kSpreadWaves, QN = kSpreadQueue, QB = kSpreadBatch;
   extern __shared__ unsigned char s_raw[];
@@ -989,10 +1036,10 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   C2<Tg>* acc = (C2<Tg>*)s_raw;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ntx = g.nf / tile;
-  const int pair = pair0 + blockIdx.y;
-  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  const int ty = tile_i / ntx, tx = tile_i % ntx;
   const int x0 = tx * tile, y0 = ty * tile;
   const int strip = g.bin, sy0 = wave * strip;  // tile rows owned by this wave
+  __syncthreads();                              // LDS reuse across the tiles of a block
   for (int i = threadIdx.x; i < tile * ts; i += blockDim.x) acc[i] = {Tg(0), Tg(0)};
   const U* pos = (const U*)srt_pos;
   const C2<Tg>* val = (const C2<Tg>*)srt_val;
@@ -1011,7 +1058,10 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   }
   __syncthreads();
   const Tg two_w = Tg(2.0 / w), bet = (Tg)beta;
-  const unsigned long long ntot = s_pre[wave][18];
+  // this slice's part of the wave's scan range
+  const unsigned long long nall = s_pre[wave][18];
+  const unsigned long long jlo = nall * (unsigned long long)slice / (unsigned long long)S;
+  const unsigned long long ntot = nall * (unsigned long long)(slice + 1) / (unsigned long long)S;
 
   // stage queue entries [0, n) and add their taps to the strip
   auto process = [&](int n) {
@@ -1084,8 +1134,8 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
       vn = val[r];
     }
   };
-  fetch(lane);
-  for (unsigned long long base = 0; base < ntot; base += 64) {
+  fetch(jlo + lane);
+  for (unsigned long long base = jlo; base < ntot; base += 64) {
     const unsigned long long j = base + lane;
     const U px = pxn, py = pyn;
     const C2<Tg> v = vn;
@@ -1119,7 +1169,39 @@ __global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const
   C2<Tg>* gp = grid + (size_t)pair * g.nf * g.nf;
   for (int i = threadIdx.x; i < tile * tile; i += blockDim.x) {
     const int cy = i / tile, cx = i % tile;
-    gp[(size_t)(y0 + cy) * g.nf + x0 + cx] = acc[cy * ts + cx];
+    C2<Tg>& d = gp[(size_t)(y0 + cy) * g.nf + x0 + cx];
+    const C2<Tg> v = acc[cy * ts + cx];
+    if (slice == 0) {
+      d = v;
+    } else {
+      atomicAdd(&d.re, v.re);
+      atomicAdd(&d.im, v.im);
+    }
+  }
+}
+
+// slices: S per (pair of the group, tile), or null (one slice each); heavy:
+// null for the launch over every tile (slice 0), else the list of further
+// slices and its length, taken in turn by the blocks of the second launch.
+template <class Tg, int w>
+__global__ __launch_bounds__(256) void k_spread_tiles(const void* srt_pos, const void* srt_val,
+                                                      const unsigned long long* offsets,
+                                                      BinGeom g, double beta, int pair0,
+                                                      C2<Tg>* grid, const unsigned char* slices,
+                                                      const uint2* heavy,
+                                                      const unsigned int* n_heavy) {
+  const int nt = (g.nf / (4 * g.bin)) * (g.nf / (4 * g.bin));
+  if (!heavy) {
+    const int S = slices ? slices[(size_t)blockIdx.y * nt + blockIdx.x] : 1;
+    spread_tile<Tg, w>(srt_pos, srt_val, offsets, g, beta, pair0 + blockIdx.y, blockIdx.x, 0, S,
+                       grid);
+    return;
+  }
+  const unsigned int n = *n_heavy;
+  for (unsigned int e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint2 h = heavy[e];
+    spread_tile<Tg, w>(srt_pos, srt_val, offsets, g, beta, pair0 + (int)(h.x / nt),
+                       (int)(h.x % nt), (int)h.y, slices[h.x], grid);
   }
 }
 

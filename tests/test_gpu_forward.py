@@ -377,3 +377,36 @@ def test_check_finite_refuses_nan_inputs(rw):
         plan.forward(vals, ph, am2)
     with pytest.raises(rw.RWError, match="RW_ERR_STATE"):
         plan.backward(torch.ones((1, 1, plan.Q, plan.Q), device="cuda"))
+
+
+def _busiest_tile_records(aux, cfg):
+    """Records of the busiest spreading tile (fine grid of 2Q cells, tiles of 4
+    bins) computed from the oracle's wavelet frequencies."""
+    Q = cfg["psf_q"]
+    nf = max(2 * Q, 64)
+    tile = 4 * (nf // min(64, nf // 8))
+    out = 0
+    for a in aux.values():
+        t = [(w.numpy() / (2 * np.pi)) % 1.0 * nf // tile for w in (a["wx"], a["wy"])]
+        ids = t[1].astype(np.int64) * (nf // tile) + t[0].astype(np.int64)
+        out = max(out, int(np.bincount(ids).max()))
+    return out
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_focused_records_split_heavy_tiles(rw, precision, bar):
+    """A zone plate at its focus sends a million records into four tiles: the
+    spreading cuts each into slices (slice 0 stored, the rest added) and must
+    still give the oracle's PSF."""
+    import workloads as W
+    system, cfg, maps = W.adaptive_zone_plate(rays_side=64, H=256, pitch=0.002, f=5.0, P=16,
+                                              classes=(), N=256, Q=32, psf_pitch=0.002,
+                                              sampling="mag")
+    cfg = dict(cfg, patch_classes=[], bw_periods=0.0)
+    print(f"heavy tiles {precision}", flush=True)
+    ref, aux = oracle_psf(system, cfg, maps, keep=True)
+    assert _busiest_tile_records(aux, cfg) > 4 * 65536
+    rep = torch.tensor(np.stack([aux[p]["J"] for p in sorted(aux)]), dtype=torch.int32,
+                       device="cuda")
+    _, psf, _ = _run(rw, system, cfg, maps, precision, replay=rep)
+    assert rel_l2(psf, ref) < bar
