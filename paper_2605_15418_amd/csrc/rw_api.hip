@@ -668,7 +668,9 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   // (double spectra), as the precision units instantiate the DOE kernels
   auto in_lds = [&](int m) { return m <= (dbl_f ? 64 : 128); };
   pl->lds_patch = in_lds(M);
-  pl->ray_block = 8;
+  // 8 x 8-ray blocks; 4 x 4 over few pairs, where the items of one class launch
+  // (patch classes cluster in space) are too few to balance the workgroups
+  pl->ray_block = pl->n_pairs < 8 ? 4 : 8;
   pl->acc_side = 256;
   // several workgroups per CU fit from M = 64 down
   pl->doe_blocks = M <= 64 ? 2048 : 1024;
