@@ -552,6 +552,17 @@ def ray_patch_sides(surf, p, pitch, cfg, phase_map=None, doe=None):
     return out
 
 
+def class_draws(cfg, P):
+    """Draws per ray of patch side P.  Adaptive ray sampling (READING Q32):
+    with cfg["class_draws"], N (P / P_0)^2 rounded down (at least one), the Monte
+    Carlo budget per spectrum bin kept across classes; else N."""
+    N = int(cfg["n_ssr"])
+    if not cfg.get("class_draws", False):
+        return N
+    P0 = patch_classes(cfg)[0]
+    return max(1, (N * P * P) // (P0 * P0))
+
+
 def detach_pdf(cfg):
     """Gradient mode with the sampling density held constant (the unbiased variant
     of the frozen-draw derivative of Eq. 1)."""
@@ -611,14 +622,15 @@ def pair_forward(system, cfg, tmap, lam_idx, f_idx, values=None, replay=None,
     for P in sorted(set(sides.tolist()), reverse=True):
         sel = np.nonzero(sides == P)[0]
         rsel = torch.as_tensor(sel)
+        Nk = class_draws(cfg, P) if sampling != "full" else Nd
         rep = None
         if replay is not None:
-            rep = np.asarray(replay, dtype=np.int64).reshape(R, Nd)[sel]
+            rep = np.asarray(replay, dtype=np.int64).reshape(R, Nd)[sel][:, :Nk]
         part = _class_secondaries(cfg, tmap, doe, pair, ray_ids[sel], P, p[rsel], opl[rsel],
                                   amp_in[rsel], u[rsel], v[rsel], nrm[rsel], k_in_t[rsel],
-                                  alive[rsel], k_out, rep, sampling, Nd)
+                                  alive[rsel], k_out, rep, sampling, Nk)
         if J_all is not None:
-            J_all[sel] = part["J"]
+            J_all[sel, :Nk] = part["J"]
         parts.append((sel, part))
         if keep and len(parts) == 1 and len(set(sides.tolist())) == 1:
             out.update(spectrum=part["Ut"].detach(), prop=part["prop"])

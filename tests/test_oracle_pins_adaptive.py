@@ -11,6 +11,8 @@ periods of the phase map, the largest where the map is flatter).
   ray whose nearest pixel lies at radius r takes the smallest P with
   P pitch r >= K lambda f -- closed-form class radii.
 * Where the curvature bound of Eq. 4 asks for a smaller side, the ray takes it.
+* Adaptive ray sampling (a class of side P draws N (P / P_0)^2 secondaries)
+  keeps the Monte Carlo field unbiased.
 """
 import math
 
@@ -88,3 +90,36 @@ def test_curvature_bound_wins_where_it_is_smaller():
     assert np.all(sides == 16)
     cfg0 = dict(cfg, curv_eps=1.0)                   # no curvature limit: the flat map's side
     assert np.all(O.ray_patch_sides(surfs[0], p, pitch, cfg0, flat, doe) == 64)
+
+
+def test_class_draws_keep_the_estimator_unbiased():
+    """Adaptive ray sampling: a ray of patch side P draws N (P / P_0)^2 secondaries
+    (Eq. 1 divides by that count).  The Monte Carlo field still averages to the
+    FULL-mode field of the same classes within its standard error (a weight
+    normalised by N instead of the class's count biases the small-patch rays 4x)."""
+    s, c, m = W.adaptive_zone_plate(rays_side=6, H=96, pitch=0.002, f=1.0, P=16, classes=(8,),
+                                    K=2.0, N=16, Q=16, psf_pitch=0.004, sampling="full")
+    tm = O.transmission(O._t(m["phase"].astype(np.float64)), O._t(m["amp"].astype(np.float64)))
+    with torch.no_grad():
+        r = O.pair_forward(s, c, tm, 0, 0, keep=True, phase_map=m["phase"])
+    sides = r["sides"]
+    assert set(sides.tolist()) == {16, 8}
+    Uf = r["U"].numpy()
+    c = dict(c, sampling="mag", class_draws=True)
+    S = 400
+    Us = []
+    with torch.no_grad():
+        for k in range(S):
+            c["seed"] = 500 + k
+            rk = O.pair_forward(s, c, tm, 0, 0, keep=k == 0, phase_map=m["phase"])
+            if k == 0:
+                # 16 draws for the 16-px rays, 16 (8/16)^2 = 4 for the 8-px ones
+                J = rk["J"]
+                assert np.all(J[sides == 16] >= 0)
+                assert np.all(J[sides == 8][:, :4] >= 0) and np.all(J[sides == 8][:, 4:] == -1)
+            Us.append(rk["U"].numpy())
+    Us = np.array(Us)
+    mean = Us.mean(0)
+    var = (np.abs(Us - mean) ** 2).sum(0) / (S - 1)
+    T = np.sum(np.abs(mean - Uf) ** 2) / np.sum(var / S)
+    assert T < 2.0, T
