@@ -173,6 +173,12 @@ typedef struct {
    * one-pixel differences of doe_phase, each wrapped to [-pi, pi], over the pitch.
    * Needs n_patch_class >= 1 and the amplitude-phase field.  0: off. */
   double bandwidth_periods;
+  /* Adaptive ray sampling (the paper's future work; reading in the design notes):
+   * 1 = a ray of patch class side P_k draws N_k = max(1, floor(n_ssr P_k^2 / P_0^2))
+   * secondaries instead of n_ssr (the Monte Carlo budget per spectrum bin kept across
+   * classes; Eq. 1 divides by N_k).  Sample indices keep n_ssr slots per ray, -1
+   * beyond N_k.  Needs patch classes and MAG or UNI sampling.  0: n_ssr for every ray. */
+  int class_draws;
 } rw_config;
 
 typedef struct rw_plan rw_plan;

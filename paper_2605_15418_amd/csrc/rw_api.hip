@@ -605,6 +605,8 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   }
   if (cfg->n_patch_class > 0 && !(cfg->curv_eps > 0.0))
     return fail(RW_ERR_INVALID_ARG, "curv_eps must be positive");
+  if (cfg->class_draws && (cfg->n_patch_class == 0 || cfg->sampling == RW_SAMPLE_FULL))
+    return fail(RW_ERR_INVALID_ARG, "class_draws needs patch classes and MAG or UNI sampling");
   if (!(cfg->bandwidth_periods >= 0.0) || std::isinf(cfg->bandwidth_periods))
     return fail(RW_ERR_INVALID_ARG, "bandwidth_periods must be finite and >= 0");
   if (cfg->bandwidth_periods > 0.0 &&
@@ -731,7 +733,13 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   dc.grad = cfg->grad;
   dc.pad = pad;
   dc.n_class = pl->n_class;
-  for (int i = 0; i < pl->n_class; ++i) dc.class_p[i] = pl->class_p[i];
+  for (int i = 0; i < pl->n_class; ++i) {
+    dc.class_p[i] = pl->class_p[i];
+    // draws per ray: N, or N (P_k / P_0)^2 (at least one) with class_draws
+    const long long nk = (long long)pl->N * pl->class_p[i] * pl->class_p[i] /
+                         ((long long)pl->class_p[0] * pl->class_p[0]);
+    dc.class_n[i] = cfg->class_draws ? (int)std::max(1LL, nk) : pl->N;
+  }
   dc.curv_eps = cfg->curv_eps;
   dc.bw_k2 = cfg->bandwidth_periods > 0.0
                  ? (2.0 * M_PI * cfg->bandwidth_periods) * (2.0 * M_PI * cfg->bandwidth_periods)
@@ -767,6 +775,7 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
     dc1.R = cs->R1;
     dc1.R2 = pl->R1sq;
     dc1.N = cs->N1;
+    dc1.class_n[0] = cs->N1;
     dc1.pitch = cs->doe1.pitch; dc1.x0 = cs->doe1.x0; dc1.y0 = cs->doe1.y0;
     dc1.inv_pitch = 1.0 / cs->doe1.pitch;
     dc1.planar = planar1 ? 1 : 0;

@@ -1004,7 +1004,9 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
   const C2<Tf>* tm = (const C2<Tf>*)a.tmap;
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
-  const int N = cfg.N, t = threadIdx.x, emit = a.emit;
+  // NS: sample slots per ray (the stride of the index arrays); N: draws of this
+  // launch's patch class (NS unless the draws are scaled by class)
+  const int NS = cfg.N, N = cfg.class_n[a.cls], t = threadIdx.x, emit = a.emit;
   const double inv_m2 = 1.0 / ((double)M * M);
   unsigned long long n_sec = 0, n_alive = 0, n_lost = 0, n_evan = 0, n_bins = 0;
   // rays in work-list order; the class, alive flag and context word (thread
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
           else put_none<Tg>(a, slot0 + i);
         }
         if (a.idx_out && cfg.sampling != 2)
-          for (int i = t; i < N; i += kDoeThreads) a.idx_out[gid * N + i] = -1;
+          for (int i = t; i < NS; i += kDoeThreads) a.idx_out[gid * NS + i] = -1;
         continue;
       }
       n_alive += (t == 0);
@@ -1108,19 +1110,26 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_fwd2(DoeArgs a, RayBlockIte
       const double S = chunk_scan<M>(s.pref, s.red, lp, s.redi, lastpos_all);
       const double scale = S * inv_m2 / N;               // S or |Pi| over M^2 N
       if (t == 0) a.ctx[gid].S = S;                      // for the backward
+      // slots beyond this class's draws carry nothing
+      for (int i = N + t; i < NS; i += kDoeThreads) {
+        if (a.idx_out) a.idx_out[gid * NS + i] = -1;
+        if (a.jdraw) a.jdraw[gid * NS + i] = -1;
+        if constexpr (kCasc == 1) relay_none(a, c.pair, c.r, i);
+        else put_none<Tg>(a, slot0 + i);
+      }
       for (int i = t; i < N; i += kDoeThreads) {
         int J = -1;
         if (S > 0.0) {
           if (a.replay) {
-            J = a.replay[gid * N + i];
+            J = a.replay[gid * NS + i];
           } else {
             const double T = draw_uniform(cfg.key0, cfg.key1, (uint32_t)i, (uint32_t)c.r,
                                           (uint32_t)c.pair, kCasc == 2 ? 1u : 0u) * S;
             J = draw_bin<Tf, M>(buf, s.pref, s.span, T, cfg.sampling, lastpos_all);
           }
         }
-        if (a.idx_out) a.idx_out[gid * N + i] = J;
-        if (a.jdraw) a.jdraw[gid * N + i] = J;
+        if (a.idx_out) a.idx_out[gid * NS + i] = J;
+        if (a.jdraw) a.jdraw[gid * NS + i] = J;
         bool ok = J >= 0;
         C2<Tp> w = {Tp(0), Tp(0)};
         int jx = 0, jy = 0;
@@ -1484,7 +1493,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
   C2<Tg>* accm = (C2<Tg>*)a.acc + (size_t)blockIdx.x * AS * AS;
   for (int i = threadIdx.x; i < M; i += kDoeThreads) s.tw[i] = ((const C2<Tf>*)a.tw)[i];
   __syncthreads();
-  const int N = cfg.N, t = threadIdx.x;
+  const int NS = cfg.N, N = cfg.class_n[a.cls], t = threadIdx.x;
   static_assert(kDoeThreads % M == 0, "the S-term pass keeps one column per lane");
   const double inv_m2 = 1.0 / ((double)M * M);
   const int H = cfg.H, W = cfg.W;
@@ -1540,7 +1549,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
       // the forward's draws and normaliser (it records them for every sampled
       // ray): no CDF here
-      const int jpre = !kFull && t < N ? a.jdraw[gid * N + t] : -1;   // first draw of lane t
+      const int jpre = !kFull && t < N ? a.jdraw[gid * NS + t] : -1;  // first draw of lane t
       int lp = -1;
       doe_spectrum<Tf, M, false>(cfg, c, tm, buf, s.tw, s.pref, s.span, cfg.sampling, &lp,
                                  s.ls);
@@ -1563,7 +1572,7 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           const double scale = S * inv_m2 / N;
 #pragma unroll 1
           for (int i = t / LPD; i < N; i += kDoeThreads / LPD) {
-            const int J = i == t ? jpre : a.jdraw[gid * N + i];
+            const int J = i == t ? jpre : a.jdraw[gid * NS + i];
             DrawEnt<Tf> ent = {{Tf(0), Tf(0)}, -1};
             double g2r[5] = {0.0, 0.0, 0.0, 0.0, -1.0};      // A, B, J of the G2 record
             if (J >= 0) {

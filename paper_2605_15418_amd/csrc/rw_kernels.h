@@ -62,6 +62,7 @@ struct DevCfg {
   int pad;                 // M / P
   int n_class;             // patch classes (1: every ray uses P)
   int class_p[4];          // candidate patch sides, largest first (class_p[0] = P)
+  int class_n[4];          // draws per ray of each class (N, or N (P_k / P_0)^2)
   double curv_eps;         // curvature bound of the class rule
   double bw_k2;            // adaptive patch sizing: (2 pi K)^2 for K local periods (0: off)
   int reflective;          // secondaries leave back into the medium before the DOE

@@ -5,7 +5,8 @@ A kinoform zone plate's local period falls from the axis outwards, so the
 16 x 16 launch grid splits into three classes (patch sides 32, 16 and 8).  The
 class decision is taken in FP64 from the float32 phase map on both sides, so
 the per-class ray counts must agree exactly; bars otherwise as for fixed
-classes (FP64 indices bit-exact and PSF 1e-6; MIXED PSF 1e-4; gradients 1e-3).
+classes (FP64 indices bit-exact and PSF 1e-6; MIXED PSF 1e-4; gradients 1e-3),
+also with adaptive ray sampling (N (P / P_0)^2 draws for a ray of side P).
 """
 import numpy as np
 import pytest
@@ -88,3 +89,41 @@ def test_adaptive_sizing_rejections(rw):
         rw.Plan(system, dict(cfg, patch_classes=[]), precision="mixed")   # no classes to pick
     with pytest.raises(rw.RWError, match="RW_ERR_INVALID_ARG"):
         rw.Plan(system, dict(cfg, bw_periods=-1.0), precision="mixed")
+    with pytest.raises(rw.RWError, match="RW_ERR_INVALID_ARG"):
+        rw.Plan(system, dict(cfg, class_draws=True, sampling="full"), precision="mixed")
+
+
+def test_class_draws_fp64_indices_exact_and_psf(rw):
+    """Adaptive ray sampling: the 16- and 8-px rays draw 32 (16/32)^2 = 8 and
+    32 (8/32)^2 = 2 secondaries; the indices (-1 beyond a ray's count) match the
+    oracle's bit for bit, and the PSF within 1e-6."""
+    system, cfg, maps = _case()
+    cfg = dict(cfg, class_draws=True)
+    print("class draws fp64", flush=True)
+    plan, psf, idx = _forward(rw, system, cfg, maps, "fp64", want_idx=True)
+    ref, aux = oracle_psf(system, cfg, maps, keep=True)
+    J = aux[0]["J"]
+    sides = aux[0]["sides"]
+    assert np.all(J[sides == 16][:, 8:] == -1) and np.all(J[sides == 16][:, :8] >= 0)
+    assert np.array_equal(idx.cpu().numpy()[0], J)
+    assert plan.stats()["secondaries"] == int((J >= 0).sum())
+    assert worst_pair_rel(psf, ref) < 1e-6
+
+
+def test_class_draws_mixed_gradients_on_oracle_draws(rw):
+    system, cfg, maps = _case()
+    cfg = dict(cfg, class_draws=True)
+    print("class draws mixed gradients", flush=True)
+    L0, g, _, idx = O.loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                    maps["amp"].astype(np.float64), np.zeros(0),
+                                    maps["target"].astype(np.float64))
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    plan = rw.Plan(system, cfg, precision="mixed")
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    _, loss, _ = plan.forward(vals, ph, am, target=tg, replay=rep)
+    dp, da, _ = plan.backward()
+    torch.cuda.synchronize()
+    assert abs(float(loss) - L0) <= 1e-4 * abs(L0)
+    assert rel_l2(dp.cpu().numpy(), g["phase"]) < 1e-3
+    assert rel_l2(da.cpu().numpy(), g["amp"]) < 1e-3
