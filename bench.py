@@ -471,7 +471,8 @@ def main():
         s_, c_, m_ = W.workload("adaptive_zone_plate")
         v_, ph_, am_, tg_ = inputs(s_, m_)
         big = max(classes_of(c_))
-        forms = (("adaptive", c_), (f"fixed_P{big}", dict(c_, patch_classes=[], bw_periods=0.0)))
+        forms = (("adaptive", c_), ("adaptive_class_draws", dict(c_, class_draws=True)),
+                 (f"fixed_P{big}", dict(c_, patch_classes=[], bw_periods=0.0)))
         for tag, cc in forms:
             # fwd + bwd (MAG, G1) at full size
             pl = rw.Plan(s_, cc, precision="mixed", batched=True)
@@ -491,6 +492,8 @@ def main():
                   launch_half=c_["launch_half"] * (1 - 1 / 64) / (1 - 1 / c_["rays_side"]))
         psfs = {}
         for tag, cc in (("adaptive", cf), (f"P{big}", dict(cf, patch_classes=[], bw_periods=0.0)),
+                        ("adaptive_class_draws_mag", dict(cf, sampling="mag", class_draws=True)),
+                        (f"P{big}_mag", dict(cf, sampling="mag", patch_classes=[], bw_periods=0.0)),
                         *[(f"P{q}", dict(cf, patch_p=q, patch_classes=[], bw_periods=0.0))
                           for q in classes_of(c_)[1:]]):
             pl = rw.Plan(s_, cc, precision="mixed", batched=True)
@@ -508,8 +511,10 @@ def main():
         ref_ = psfs[f"P{big}"]
         adaptive["ncc_vs_all_largest"] = {t: ncc(v, ref_) for t, v in psfs.items()
                                           if t != f"P{big}"}
-        adaptive["speedup"] = adaptive[f"fixed_P{big}"]["ms_fwd_bwd"] / adaptive["adaptive"]["ms_fwd_bwd"]
+        adaptive["speedup"] = {t: adaptive[f"fixed_P{big}"]["ms_fwd_bwd"] / adaptive[t]["ms_fwd_bwd"]
+                               for t in ("adaptive", "adaptive_class_draws")}
         log(f"adaptive_zone_plate: fwd+bwd {adaptive['adaptive']['ms_fwd_bwd']:.1f} ms adaptive, "
+            f"{adaptive['adaptive_class_draws']['ms_fwd_bwd']:.1f} ms with class draws, "
             f"{adaptive[f'fixed_P{big}']['ms_fwd_bwd']:.1f} ms at P = {big}; "
             f"NCC with all-P{big}: {adaptive['ncc_vs_all_largest']}")
 

@@ -444,8 +444,11 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
   unsigned int* nh = (unsigned int*)(b + pl->off_heavy);
   uint2* hv = (uint2*)(b + pl->off_heavy + 256);
   zero<unsigned int>(nh, 1, st);
+  // a slice is at least kSpreadTarget records and about 1/1024 of the group's
+  const unsigned long long target =
+      std::max<unsigned long long>(kSpreadTarget, (unsigned long long)npairs * per_pair / 1024);
   hipLaunchKernelGGL(k_spread_slices, dim3((unsigned)(((size_t)npairs * ntiles + 255) / 256)),
-                     dim3(256), 0, st, so, g, pair0, npairs, sl, hv, nh);
+                     dim3(256), 0, st, so, g, pair0, npairs, target, sl, hv, nh);
   const dim3 hg(1024);
   switch (pl->w) {
 #define RW_SPREAD_CASE(W)                                                                     \

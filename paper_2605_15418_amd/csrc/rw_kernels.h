@@ -948,7 +948,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kSpreadWaves = 4;      // waves per spreading block (256 threads)
-constexpr int kSpreadTarget = 65536; // records per slice of a heavy tile
+constexpr int kSpreadTarget = 65536; // least records per slice of a heavy tile
 constexpr int kSpreadSlices = 32;    // most slices of one tile
 constexpr int kSpreadBatch = 32;     // queued records staged and added per round
 constexpr int kSpreadQueue = 96;     // queue capacity: a batch plus one scan step
@@ -969,12 +969,15 @@ __device__ __forceinline__ unsigned long long strip_records(const unsigned long 
 }
 
 // Slices of every tile of a launch group (one thread per (pair, tile)): a tile
-// whose busiest strip scans more than kSpreadTarget records is cut into
-// S = ceil(records / kSpreadTarget) <= kSpreadSlices slices of its scan ranges.
+// whose busiest strip scans more than `target` records is cut into
+// S = ceil(records / target) <= kSpreadSlices slices of its scan ranges.  The
+// host sets target to max(kSpreadTarget, the group's records / 1024), so that
+// only tiles far above their share of the launch are cut.
 // slices[pair][tile] = S; slices 1 .. S - 1 of such tiles go to the list
 // (entry: pair * tiles + tile, slice), their count to *n_heavy (zero at launch).
 static __global__ __launch_bounds__(256) void k_spread_slices(const unsigned long long* offsets,
                                                        BinGeom g, int pair0, int npairs,
+                                                       unsigned long long target,
                                                        unsigned char* slices, uint2* heavy,
                                                        unsigned int* n_heavy) {
   const int tile = 4 * g.bin, ntx = g.nf / tile, nt = ntx * ntx;
@@ -985,7 +988,7 @@ static __global__ __launch_bounds__(256) void k_spread_slices(const unsigned lon
   unsigned long long nmax = 0;
   for (int q = 0; q < 4; ++q) nmax = max(nmax, strip_records(off, g, t / ntx, t % ntx, q));
   const int S = (int)min((unsigned long long)kSpreadSlices,
-                         max(1ull, (nmax + kSpreadTarget - 1) / kSpreadTarget));
+                         max(1ull, (nmax + target - 1) / target));
   slices[i] = (unsigned char)S;
   if (S > 1) {
     const unsigned int b = atomicAdd(n_heavy, (unsigned int)(S - 1));
