@@ -1048,6 +1048,38 @@ def cascade_psf_stack(system, cfg, phases, amps, values=None, replays=None, keep
     return out, aux
 
 
+def cascade_loss_and_grad(system, cfg, phases, amps, target, replays=None, want_grad=True):
+    """Eq. 5 summed over the pairs of a two-DOE system and its gradient with
+    respect to both DOEs' maps (torch autograd in float64, frozen draws): the
+    relayed rays' positions and directions follow from the drawn bins alone, so
+    the maps act through the amplitudes.  Returns (loss, {"phase", "amp"} [2, H, W],
+    psfs, {pair: (J1, J2)})."""
+    L = len(cfg["lambdas"])
+    F = len(cfg["fields"])
+    ph = _t(np.asarray(phases)).clone().requires_grad_(want_grad)
+    am = _t(np.asarray(amps)).clone().requires_grad_(want_grad)
+    total = 0.0
+    psfs = np.zeros((L, F, cfg["psf_q"], cfg["psf_q"]))
+    idx = {}
+    for l in range(L):
+        for f in range(F):
+            pr = l * F + f
+            tmaps = [transmission(ph[k], am[k], system["does"][k].get("field", "amp_phase"))
+                     for k in range(2)]
+            rep = (None, None) if replays is None else replays[pr]
+            r = cascade_pair_forward(system, cfg, tmaps, l, f, None, rep, keep=True)
+            Lp = eq5_loss(r["psf"], _t(target[l, f]))
+            if want_grad:
+                Lp.backward()
+            total += float(Lp.detach())
+            psfs[l, f] = r["psf"].detach().numpy()
+            idx[pr] = (r["J1"], r["J2"])
+    g = None
+    if want_grad:
+        g = dict(phase=ph.grad.numpy().copy(), amp=am.grad.numpy().copy())
+    return total, g, psfs, idx
+
+
 # ----------------------------------------------------------------------------
 # Figures of merit (patch-size study).
 # ----------------------------------------------------------------------------

@@ -14,6 +14,8 @@ conventionally).
 * With both DOEs nontrivial, the Monte Carlo cascade is unbiased for the
   sensor field: its mean over independent draws is the FULL cascade's field,
   within the standard error (a wrong normalisation of either stage fails).
+* The autograd gradient of the Eq. 5 loss with respect to both maps matches
+  central differences.
 """
 import copy
 
@@ -80,3 +82,32 @@ def test_monte_carlo_cascade_is_unbiased():
     # error: about 1 when unbiased; a 20 % scale error of the mean gives about 3
     T = np.sum(np.abs(mean - Uf) ** 2) / np.sum(var / S)
     assert T < 2.0, T
+
+
+def test_cascade_map_gradients_match_central_differences():
+    """Gradient of the Eq. 5 loss with respect to both DOEs' maps (FULL: no draws)
+    against central differences of the loss, h = 1e-4 (reading Q18)."""
+    s, c, m = W.two_doe_cascade(rays_side=2, P=4, pad=2, N=4, N2=2, Q=16, psf_pitch=0.04,
+                                sampling="full", cutoff=0.05, seed=2)
+    rng = np.random.default_rng(8)
+    target = rng.uniform(0.0, 1.0, (1, 1, 16, 16))
+    ph = m["phase"].astype(np.float64)
+    am = m["amp"].astype(np.float64)
+    L0, g, _, _ = O.cascade_loss_and_grad(s, c, ph, am, target)
+    assert np.abs(g["phase"][0]).max() > 0 and np.abs(g["phase"][1]).max() > 0
+    h = 1e-4
+    for name, arr in (("phase", ph), ("amp", am)):
+        for k in range(2):
+            # the pixels with the largest gradient of each map
+            flat = np.argsort(-np.abs(g[name][k]).ravel())[:3]
+            for q in flat:
+                iy, ix = divmod(int(q), arr.shape[2])
+                hi, lo = arr.copy(), arr.copy()
+                hi[k, iy, ix] += h
+                lo[k, iy, ix] -= h
+                a, b = ((hi, am), (lo, am)) if name == "phase" else ((ph, hi), (ph, lo))
+                Lh = O.cascade_loss_and_grad(s, c, a[0], a[1], target, want_grad=False)[0]
+                Ll = O.cascade_loss_and_grad(s, c, b[0], b[1], target, want_grad=False)[0]
+                fd = (Lh - Ll) / (2 * h)
+                assert abs(fd - g[name][k][iy, ix]) <= 1e-5 * max(abs(fd), 1e-3 * abs(L0)), \
+                    (name, k, iy, ix, fd, g[name][k][iy, ix])
