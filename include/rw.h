@@ -223,11 +223,15 @@ rw_status rw_plan_create(const rw_surface* surfaces_host, int n_surf, const rw_d
  *  (iy, ix) is ray (iy n1 + i / n1, ix n1 + i % n1) of the second DOE's ray grid of
  *  side rays_side n1 (pair-major like the launch grid); the second DOE's draws take
  *  that ray's index and Philox stream 1 (counter (i >> 2, ray, pair, 1)).
- *  Maps: doe_phase, doe_amp of rw_forward are [2][H][W] (first DOE, then second).
+ *  Maps: doe_phase, doe_amp of rw_forward (and the gradients of rw_backward) are
+ *  [2][H][W] (first DOE, then second).
  *  Sample indices (replay_idx, idx_out): the first DOE's [n_pairs][rays_side^2][N1]
  *  followed by the second DOE's [n_pairs][(rays_side n1)^2][n_ssr2]; none under FULL.
- *  The plan runs rw_forward and rw_forward_static (always forward-only);
- *  rw_backward, rw_forward_backward and rw_autotune return RW_ERR_UNSUPPORTED.
+ *  rw_backward gives both maps' gradients (G1 or G1_DETACH with frozen draws) in
+ *  d_phase, d_amp [2][H][W]: the relayed rays' positions and directions follow from
+ *  the drawn bins, so the maps act through the wavelets' amplitudes.  Lens gradients
+ *  (d_lens with lens parameters), the G2 mode, rw_forward_backward and rw_autotune
+ *  return RW_ERR_UNSUPPORTED.
  *  rw_get_stats counts the rays of both DOEs; rw_export_doe_hits gives the second
  *  DOE's incident rays.
  * Errors: as rw_plan_create; RW_ERR_INVALID_ARG (not two DOE surfaces, different

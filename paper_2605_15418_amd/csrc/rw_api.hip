@@ -124,6 +124,7 @@ struct rw_plan {
   size_t n1_total = 0;
   DevCfg* d_cfg1 = nullptr;
   size_t off_tmap1 = 0, off_st1 = 0, off_ck1 = 0, off_ctx1 = 0, off_rcls1 = 0;
+  size_t off_jdraw1 = 0, off_gt1 = 0, off_gain = 0;   // the cascade's backward
   // device constant tables (owned by the plan)
   DevCfg* d_cfg = nullptr;
   DevPair* d_pairs = nullptr;
@@ -948,8 +949,7 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
     pl->off_rcls1 = take(n1t);
   }
   pl->fwd_bytes = o;
-  // a cascade runs forward only: no backward state or buffers
-  const size_t bw = cs ? 0 : 1;
+  const size_t bw = 1;
   // state of the forward that only the backward reads
   pl->off_jdraw = take(bw * (cfg->sampling == RW_SAMPLE_FULL ? 0 : (size_t)nt * pl->N * sizeof(int32_t)));
   const bool tl = pl->tiled_interp || pl->tiled_groups;
@@ -967,6 +967,13 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   pl->off_lensg = take(bw * RW_LENSG_SLOTS * sizeof(double));
   pl->off_G = take(bw * (size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
   pl->off_interp = take(bw * (tl ? nrec * kInterpStride * pl->sz_cg : 0));
+  if (cs) {
+    // the first DOE's draws (left by the forward), its dL/dt, and the second
+    // DOE's dL/d(incident amplitude) per ray
+    pl->off_jdraw1 = take(cfg->sampling == RW_SAMPLE_FULL ? 0 : pl->n1_total * cs->N1 * sizeof(int32_t));
+    pl->off_gt1 = take((size_t)doe->H * doe->W * pl->sz_cg);
+    pl->off_gain = take(2 * nt * sizeof(double));
+  }
   pl->total = o;
   *out = pl;
   return RW_OK;
@@ -1006,6 +1013,8 @@ rw_status rw_plan_create_cascade(const rw_surface* surfaces, int n_surf, const r
     return fail(RW_ERR_INVALID_ARG, "the two DOEs must share the field mode");
   if (cfg->n_patch_class != 0)
     return fail(RW_ERR_UNSUPPORTED, "a cascade takes one patch class");
+  if (cfg->grad == RW_GRAD_G2)
+    return fail(RW_ERR_UNSUPPORTED, "the G2 gradient of a cascade is not built");
   const int M = cfg->patch_p * cfg->pad_factor;
   int n1 = 0;
   if (cfg->sampling == RW_SAMPLE_FULL) {
@@ -1241,7 +1250,8 @@ static rw_status fwd_group_cascade(rw_plan* pl, void* ws, const int32_t* replay_
   a1.emit = pl->N1;
   a1.rec_pos = nullptr;
   a1.rec_val = nullptr;
-  a1.jdraw = nullptr;
+  a1.jdraw = pl->fwd_only || pl->cfg.sampling == RW_SAMPLE_FULL ? nullptr
+                                                                : (int32_t*)(b + pl->off_jdraw1);
   a1.relay = (double*)(b + pl->off_st);
   a1.relay_n = pl->n_total;
   a1.cfg2 = pl->d_cfg;
@@ -1437,10 +1447,8 @@ rw_status rw_forward(rw_plan* pl, const float* lens_params, const float* doe_pha
       return fail(RW_ERR_NONFINITE, "NaN or Inf in lens_params, doe_phase, doe_amp or target");
     }
   }
-  // a cascade always runs forward-only (no backward state)
   return forward_impl(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out, ws,
-                      ws_bytes < pl->total || pl->casc, pl->graph, replay_idx, idx_out,
-                      (hipStream_t)stream);
+                      ws_bytes < pl->total, pl->graph, replay_idx, idx_out, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -1575,6 +1583,11 @@ static rw_status bwd_group(rw_plan* pl, const float* dL_dpsf, void* ws, bool wan
   a.g2 = pl->g2 ? (void*)(b + pl->off_g2) : nullptr;
   a.want_lens = want_lens ? 1 : 0;
   a.stats = nullptr;
+  if (pl->casc) {
+    // the second DOE of a cascade: records carry the incident amplitude
+    a.ain = (const double*)(b + pl->off_st) + 8 * pl->n_total;
+    a.gain = (double*)(b + pl->off_gain);
+  }
   rw_status s;
   {
     StageTimer tm_(pl, RW_STAGE_GRID_BWD, st);
@@ -1633,8 +1646,70 @@ static rw_status bwd_epilogue(rw_plan* pl, void* ws, float* d_phase, float* d_am
   return RW_OK;
 }
 
+// Backward of a two-DOE cascade (map gradients; the relayed rays' geometry
+// follows from the drawn bins, so the maps act through the amplitudes alone):
+// the second DOE's adjoint, which also leaves dL/d(incident amplitude) per ray,
+// then the first DOE's, whose draws take those as their weight cogradients.
+static rw_status bwd_enqueue_cascade(rw_plan* pl, const float* dL_dpsf, float* d_phase,
+                                     float* d_amp, void* ws, hipStream_t st) {
+  char* b = (char*)ws;
+  bwd_prologue(pl, ws, false, st);
+  const size_t nmap = (size_t)pl->H * pl->W;
+  if (pl->cfg.precision == RW_PREC_FP64) zero<double>(b + pl->off_gt1, 2 * nmap, st);
+  else zero<float>(b + pl->off_gt1, 2 * nmap, st);
+  zero<double>(b + pl->off_gain, 2 * pl->n_total, st);
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    const rw_status s = bwd_group(pl, dL_dpsf, ws, false, pl->tiled_interp, pair0, ppg, st);
+    if (s != RW_OK) return s;
+  }
+  for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
+    const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
+    DoeArgs a1 = doe_args(pl, ws, nullptr, nullptr);
+    a1.cfg = pl->d_cfg1;
+    a1.st = (const double*)(b + pl->off_st1);
+    a1.n_total = pl->n1_total;
+    a1.tmap = b + pl->off_tmap1;
+    a1.ctx = (RayCtx*)(b + pl->off_ctx1);
+    a1.ray_class = (unsigned char*)(b + pl->off_rcls1);
+    a1.emit = pl->N1;
+    a1.rec_pos = nullptr;
+    a1.rec_val = nullptr;
+    a1.jdraw = pl->cfg.sampling == RW_SAMPLE_FULL ? nullptr : (int32_t*)(b + pl->off_jdraw1);
+    a1.gt = b + pl->off_gt1;
+    a1.relay = (double*)(b + pl->off_st);
+    a1.relay_n = pl->n_total;
+    a1.cfg2 = pl->d_cfg;
+    a1.gain = (double*)(b + pl->off_gain);
+    a1.want_lens = 0;
+    a1.stats = nullptr;
+    a1.ray0 = (size_t)pair0 * pl->R1sq;
+    a1.nray = (size_t)ppg * pl->R1sq;
+    StageTimer tm_(pl, RW_STAGE_DOE_BWD, st);
+    const rw_status s = doe_launch(pl, false, a1, pair0, ppg, st, pl->R1);
+    if (s != RW_OK) return s;
+  }
+  // maps: the first DOE's dL/dt, then the second's
+  const int n = (int)nmap;
+  for (int k = 0; k < 2; ++k) {
+    const size_t o = (size_t)k * nmap;
+    void* g = b + (k == 0 ? pl->off_gt1 : pl->off_gt);
+    if (pl->cfg.precision == RW_PREC_FP64)
+      hipLaunchKernelGGL(k_dmaps<double>, dim3((n + 255) / 256), dim3(256), 0, st,
+                         pl->fwd_phase + o, pl->fwd_amp + o, (const C2<double>*)g, d_phase + o,
+                         d_amp + o, n, pl->doe.field);
+    else
+      hipLaunchKernelGGL(k_dmaps<float>, dim3((n + 255) / 256), dim3(256), 0, st,
+                         pl->fwd_phase + o, pl->fwd_amp + o, (const C2<float>*)g, d_phase + o,
+                         d_amp + o, n, pl->doe.field);
+  }
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
 static rw_status bwd_enqueue(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
                              float* d_lens, void* ws, bool want_lens, hipStream_t st) {
+  if (pl->casc) return bwd_enqueue_cascade(pl, dL_dpsf, d_phase, d_amp, ws, st);
   bwd_prologue(pl, ws, want_lens, st);
   for (int pair0 = 0; pair0 < pl->n_pairs; pair0 += pl->group_pairs) {
     const int ppg = std::min(pl->group_pairs, pl->n_pairs - pair0);
@@ -1671,7 +1746,8 @@ static rw_status step_enqueue(rw_plan* pl, const float* lens_params, const float
 rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
                       float* d_lens, void* ws, size_t ws_bytes, void* stream) {
   if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
-  if (pl->casc) return fail(RW_ERR_UNSUPPORTED, "gradients through a DOE cascade are not built");
+  if (pl->casc && d_lens && !pl->prm.empty())
+    return fail(RW_ERR_UNSUPPORTED, "lens gradients through a DOE cascade are not built");
   if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
   if (ws != pl->fwd_ws || ws_bytes < pl->total)
     return fail(RW_ERR_STATE, "rw_backward must use the workspace of the forward");

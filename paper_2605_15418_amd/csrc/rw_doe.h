@@ -1261,10 +1261,14 @@ __device__ __forceinline__ void interp_adj_pair(const DevCfg& cfg,
 // of a pair with identical arguments.  The interpolation comes from the tiled
 // pass when it covered this record (record slot `slot`, non-zero forward value),
 // else it is done here.
-template <class Prec, bool kTiled>
+// kAmp (second DOE of a cascade): the record also carries the ray's incident
+// amplitude ain; g_a receives dL/d(ain) of this wavelet.
+template <class Prec, bool kTiled, bool kAmp = false>
 __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const RayCtx& c, int jx,
                                                      int jy, C2<typename Prec::Tp> w, int h,
-                                                     size_t slot, WaveletAdj& wa, Secondary& sec) {
+                                                     size_t slot, WaveletAdj& wa, Secondary& sec,
+                                                     C2<double> ain = {1.0, 0.0},
+                                                     C2<double>* g_a = nullptr) {
   using Tp = typename Prec::Tp;
   using Tg = typename Prec::Tg;
   const DevCfg& cfg = *a.cfg;
@@ -1291,14 +1295,35 @@ __device__ __forceinline__ bool wavelet_adjoint_pair(const DoeArgs& a, const Ray
   }
   // the record carries the class weight (P_0 / P)^2 (exact power of two)
   const double fk = class_weight(cfg, c.P);
-  const C2<double> cd = {(double)cv.re * fk, (double)cv.im * fk};
+  C2<double> cd = {(double)cv.re * fk, (double)cv.im * fk};
+  double er = (double)e.re * dza * fk, ei = (double)e.im * dza * fk;
+  if constexpr (kAmp) {
+    // record = ain w E, E = e |d_z| fk: dL/d(ain) = conj(w E) g0, dL/dw = conj(ain E) g0
+    const double wr = (double)w.re * er - (double)w.im * ei, wi = (double)w.re * ei + (double)w.im * er;
+    *g_a = {wr * g0.re + wi * g0.im, wr * g0.im - wi * g0.re};
+    cd = {cd.re * ain.re - cd.im * ain.im, cd.re * ain.im + cd.im * ain.re};
+    const double r2 = er * ain.re - ei * ain.im, i2 = er * ain.im + ei * ain.re;
+    er = r2;
+    ei = i2;
+  }
   const double cell = cfg.nf / (2.0 * RW_PI);
   wa.g_wx = -(cd.re * dx.re + cd.im * dx.im) * cell;
   wa.g_wy = -(cd.re * dy.re + cd.im * dy.im) * cell;
   wa.g_phi0 = -(g0.re * cd.im - g0.im * cd.re);
   wa.g_dz = (g0.re * cd.re + g0.im * cd.im) / dza;
-  const double er = (double)e.re * dza * fk, ei = (double)e.im * dza * fk;
   wa.g_w = {er * g0.re + ei * g0.im, er * g0.im - ei * g0.re};
+  return true;
+}
+
+// First DOE of a cascade: the weight cogradient of its secondary i is dL/d(ain)
+// of the second DOE's ray that the secondary became (the relay record); the
+// secondary's direction follows from its bin alone, so nothing else flows back.
+__device__ __forceinline__ bool relay_cograd(const DoeArgs& a, const RayCtx& c, int i,
+                                             WaveletAdj& wa) {
+  const size_t g = relay_gid(*a.cfg, *a.cfg2, c.pair, c.r, i);
+  wa.g_phi0 = wa.g_wx = wa.g_wy = wa.g_dz = 0.0;
+  if (a.relay[7 * a.relay_n + g] == 0.0) return false;
+  wa.g_w = {a.gain[g], a.gain[a.relay_n + g]};
   return true;
 }
 
@@ -1474,7 +1499,10 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
 // kTiled: the sensor-grid cogradient of every record comes from the tiled
 // interpolation pass (one lane per secondary ray); otherwise the kernel
 // interpolates it itself (two lanes per secondary ray share the kernel rows).
-template <class Prec, int M, bool kLDS, bool kG2, bool kTiled, bool kFull>
+// kCasc: 1 = the first DOE of a cascade (draws' weight cogradients from the
+// relayed rays), 2 = the second DOE (records carry the incident amplitude;
+// writes dL/d(ain) per ray), 0 = a single DOE.
+template <class Prec, int M, bool kLDS, bool kG2, bool kTiled, bool kFull, int kCasc = 0>
 __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIter itr,
                                                           long long n_items, int pair0) {
   using Tf = typename Prec::Tf;
@@ -1547,6 +1575,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
       const int T = P + 4;                                // bilinear tile side
       const bool use_tile = Gm::SIZE - Gm::row(P) >= T * T;
       const size_t slot0 = ((size_t)gid - a.ray0) * (size_t)a.emit;   // this ray's records
+      // second DOE of a cascade: the ray's incident amplitude, and the sum of
+      // dL/d(ain) over its wavelets
+      C2<double> ain = {1.0, 0.0};
+      if constexpr (kCasc == 2) ain = {a.ain[gid], a.ain[a.n_total + gid]};
+      double gar = 0.0, gai = 0.0;
       // the forward's draws and normaliser (it records them for every sampled
       // ray): no CDF here
       const int jpre = !kFull && t < N ? a.jdraw[gid * NS + t] : -1;  // first draw of lane t
@@ -1595,8 +1628,18 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
               }
               WaveletAdj wa;
               Secondary sec;
-              if (ok)
-                ok = wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
+              if (ok) {
+                if constexpr (kCasc == 1) {
+                  ok = relay_cograd(a, c, i, wa);
+                } else if constexpr (kCasc == 2) {
+                  C2<double> ga;
+                  ok = wavelet_adjoint_pair<Prec, kTiled, true>(a, c, jx, jy, w, h, slot0 + i, wa,
+                                                                sec, ain, &ga);
+                  if (ok && lead) { gar += ga.re; gai += ga.im; }
+                } else {
+                  ok = wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot0 + i, wa, sec);
+                }
+              }
               if (ok) {
                 C2<double> gU;
                 if (cfg.sampling == 0 && cfg.grad == kGradG1Detach) {
@@ -1645,6 +1688,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
           }
         }
         dLdS = block_sum_d(dLdS, s.red);     // orders every read of buf before the rewrite
+        if constexpr (kCasc == 2) {
+          gar = block_sum_d(gar, s.red);
+          gai = block_sum_d(gai, s.red);
+          if (t == 0) { a.gain[gid] = gar; a.gain[a.n_total + gid] = gai; }
+        }
         double D2 = 0.0;                      // G2: sum of dL/dlog p
         const float* dlg = nullptr;           // G2: dL/dlog p per bin, [ky][kx]
         if constexpr (kG2) {
@@ -1729,8 +1777,20 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             const C2<Tp> w = {(Tp)U.re * (Tp)inv_m2, (Tp)U.im * (Tp)inv_m2};
             WaveletAdj wa;
             Secondary sec;
-            const size_t slot = slot0 + (size_t)((jx + M / 2) * M + (jy + M / 2));
-            if (wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot, wa, sec)) {
+            const int Lb = (jx + M / 2) * M + (jy + M / 2);
+            const size_t slot = slot0 + (size_t)Lb;
+            bool okw;
+            if constexpr (kCasc == 1) {
+              okw = relay_cograd(a, c, Lb, wa);
+            } else if constexpr (kCasc == 2) {
+              C2<double> ga;
+              okw = wavelet_adjoint_pair<Prec, kTiled, true>(a, c, jx, jy, w, h, slot, wa, sec, ain,
+                                                             &ga);
+              if (okw && lead) { gar += ga.re; gai += ga.im; }
+            } else {
+              okw = wavelet_adjoint_pair<Prec, kTiled>(a, c, jx, jy, w, h, slot, wa, sec);
+            }
+            if (okw) {
               const double gr = wa.g_w.re * inv_m2, gi = wa.g_w.im * inv_m2;
               const double rr = (double)ref.re, ri = (double)ref.im;
               out = {(Tf)(rr * gr + ri * gi), (Tf)(rr * gi - ri * gr)};
@@ -1739,6 +1799,11 @@ __global__ __launch_bounds__(kDoeThreads) void k_doe_bwd2(DoeArgs a, RayBlockIte
             }
           }
           if (lead) buf[Gm::at(ky, kx)] = out;
+        }
+        if constexpr (kCasc == 2) {
+          gar = block_sum_d(gar, s.red);
+          gai = block_sum_d(gai, s.red);
+          if (t == 0) { a.gain[gid] = gar; a.gain[a.n_total + gid] = gai; }
         }
       }
       __syncthreads();

@@ -17,10 +17,32 @@ static void go(bool fwd, const DoeArgs& a, const RayBlockIter& it, long long n, 
         hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS, 2>), dim3(blocks), dim3(kDoeThreads), 0, st,
                            a, it, n, pair0);
     }
-  } else if (fwd)
+  } else if (fwd) {
     hipLaunchKernelGGL((k_doe_fwd2<PrecFP64, M, LDS>), dim3(blocks), dim3(kDoeThreads), 0, st, a, it,
                        n, pair0);
-  else if (a.full && a.interp)
+  } else if (a.gain) {
+    // the adjoints of a cascade's two DOEs (patch sizes that stay in LDS)
+    if constexpr (LDS) {
+      if (a.relay && a.full)
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, true, true, 1>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+      else if (a.relay)
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, true, false, 1>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+      else if (a.full && a.interp)
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, true, true, 2>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+      else if (a.full)
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, false, true, 2>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+      else if (a.interp)
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, true, false, 2>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+      else
+        hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, false, false, 2>), dim3(blocks),
+                           dim3(kDoeThreads), 0, st, a, it, n, pair0);
+    }
+  } else if (a.full && a.interp)
     hipLaunchKernelGGL((k_doe_bwd2<PrecFP64, M, LDS, false, true, true>), dim3(blocks),
                        dim3(kDoeThreads), 0, st, a, it, n, pair0);
   else if (a.full)

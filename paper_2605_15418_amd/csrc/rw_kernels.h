@@ -318,6 +318,9 @@ struct DoeArgs {
   size_t relay_n;
   const DevCfg* cfg2;        // first DOE: the second DOE's configuration
   const double* ain;         // second DOE: incident amplitudes [2][n_total] (re, im), or null
+  double* gain;              // backward: dL/d(incident amplitude) of the second DOE's rays
+                             // [2][n_total of the second DOE] (written by its adjoint, read
+                             // by the first DOE's as its draws' weight cogradients)
   const float* phase;        // the phase map [H][W] (adaptive patch sizing)
 };
 

@@ -360,10 +360,13 @@ class Plan:
         return torch.cat([idx1.reshape(-1), idx2.reshape(-1)]).contiguous()
 
     def backward(self, dL_dpsf=None, d_phase=None, d_amp=None, d_lens=None):
+        """Map (and lens) gradients of the preceding forward; a cascade's map
+        gradients are [2, H, W] (first DOE, then second)."""
         d = self.system["doe"]
         dev = self.device
-        dp = d_phase if d_phase is not None else torch.empty((d["H"], d["W"]),
-                                                             dtype=torch.float32, device=dev)
+        shape = (2, d["H"], d["W"]) if self.cascade else (d["H"], d["W"])
+        dp = d_phase if d_phase is not None else torch.empty(shape, dtype=torch.float32,
+                                                             device=dev)
         da = d_amp if d_amp is not None else torch.empty_like(dp)
         dl = d_lens
         if dl is None and self.n_params:

@@ -6,6 +6,7 @@ paragraph: the construction extends to several DOEs).  Bars as for one DOE:
   * FP64 form: both DOEs' sample indices bit-exact; PSF within 1e-6 (relative
     L2 and element-wise against the peak; float32 output)
   * MIXED form with the oracle's indices replayed, or FULL: PSF within 1e-4
+  * both maps' gradients of the Eq. 5 loss: FP64 1e-5, MIXED 1e-3 (relative L2)
 Launch grids of 9 x 9 rays (ragged against the 8 x 8 ray blocks), second-DOE
 grids of 36 x 36 (48 x 48 under FULL), four (wavelength, field) pairs.
 """
@@ -118,7 +119,72 @@ def test_cascade_rejections(rw):
     with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
         rw.Plan(system, cfg, precision="fp64")       # M = 128 does not fit LDS in FP64
     system, cfg, maps = _case("mag")
-    plan, _, _ = _gpu(rw, system, cfg, maps, "mixed")
     with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
-        plan.backward(d_phase=torch.empty((2, 64, 64), device="cuda"),
-                      d_amp=torch.empty((2, 64, 64), device="cuda"))
+        rw.Plan(system, dict(cfg, grad="G2"), precision="mixed")
+
+
+def _target(cfg, seed=3):
+    L, F, Q = len(cfg["lambdas"]), len(cfg["fields"]), cfg["psf_q"]
+    return np.random.default_rng(seed).uniform(0.0, 1.0, (L, F, Q, Q)).astype(np.float32)
+
+
+def _grads(rw, system, cfg, maps, precision, target, replay=None):
+    plan = rw.Plan(system, cfg, precision=precision)
+    _, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(target, device="cuda")
+    _, loss, idx = plan.forward(None, ph, am, target=tg, replay=replay,
+                                want_idx=cfg["sampling"] != "full")
+    dp, da, _ = plan.backward()
+    torch.cuda.synchronize()
+    return plan, float(loss), dp.cpu().numpy(), da.cpu().numpy(), idx
+
+
+def _check_grads(L, dp, da, L0, g, bar):
+    assert abs(L - L0) <= bar * abs(L0)
+    for k in range(2):          # each DOE's maps on their own
+        assert np.abs(g["phase"][k]).max() > 0
+        assert rel_l2(dp[k], g["phase"][k]) < bar, ("phase", k, rel_l2(dp[k], g["phase"][k]))
+        assert rel_l2(da[k], g["amp"][k]) < bar, ("amp", k, rel_l2(da[k], g["amp"][k]))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-5), ("mixed", 1e-3)])
+def test_cascade_map_gradients_full(rw, precision, bar):
+    system, cfg, maps = _case("full", rays=2, P=8)
+    cfg = dict(cfg, lambdas=cfg["lambdas"][:1], fields=cfg["fields"][:1],
+               launch_center=cfg["launch_center"][:1], psf_center=[cfg["psf_center"][0][:1]])
+    tgt = _target(cfg)
+    print(f"cascade gradients full {precision}", flush=True)
+    L0, g, _, _ = O.cascade_loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                          maps["amp"].astype(np.float64), tgt.astype(np.float64))
+    _, L, dp, da, _ = _grads(rw, system, cfg, maps, precision, tgt)
+    _check_grads(L, dp, da, L0, g, bar)
+
+
+def test_cascade_map_gradients_fp64_own_draws(rw):
+    system, cfg, maps = _case("mag")
+    tgt = _target(cfg)
+    print("cascade gradients fp64 mag", flush=True)
+    plan, L, dp, da, idx = _grads(rw, system, cfg, maps, "fp64", tgt)
+    L0, g, _, oidx = O.cascade_loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                             maps["amp"].astype(np.float64),
+                                             tgt.astype(np.float64))
+    i1, i2 = (x.cpu().numpy() for x in plan.split_idx(idx))
+    for pr, (j1, j2) in oidx.items():
+        assert np.array_equal(i1[pr], j1) and np.array_equal(i2[pr], j2)
+    _check_grads(L, dp, da, L0, g, 1e-5)
+
+
+@pytest.mark.parametrize("grad", ["G1", "G1_DETACH"])
+def test_cascade_map_gradients_mixed_on_oracle_draws(rw, grad):
+    system, cfg, maps = _case("mag")
+    cfg = dict(cfg, grad=grad)
+    tgt = _target(cfg)
+    print(f"cascade gradients mixed {grad}", flush=True)
+    L0, g, _, oidx = O.cascade_loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                             maps["amp"].astype(np.float64),
+                                             tgt.astype(np.float64))
+    j1 = torch.tensor(np.stack([oidx[p][0] for p in sorted(oidx)]), dtype=torch.int32)
+    j2 = torch.tensor(np.stack([oidx[p][1] for p in sorted(oidx)]), dtype=torch.int32)
+    rep = rw.Plan.join_idx(j1, j2).cuda()
+    _, L, dp, da, _ = _grads(rw, system, cfg, maps, "mixed", tgt, replay=rep)
+    _check_grads(L, dp, da, L0, g, 1e-3)
