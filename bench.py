@@ -464,6 +464,26 @@ def main():
             del pl
             torch.cuda.empty_cache()
 
+        # the cascade's forward + backward (both maps' gradients of Eq. 5)
+        s_, c_, m_ = W.workload("two_doe_cascade")
+        v_, ph_, am_, _ = inputs(s_, m_)
+        Lc, Fc, Qc = len(c_["lambdas"]), len(c_["fields"]), c_["psf_q"]
+        tg_ = torch.tensor(np.random.default_rng(20260300).uniform(0, 1, (Lc, Fc, Qc, Qc)),
+                           dtype=torch.float32, device=dev)
+        pl = rw.Plan(s_, c_, precision="mixed", batched=True)
+        pl.forward(v_, ph_, am_, target=tg_)
+        pl.backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl.forward(v_, ph_, am_, target=tg_)
+        pl.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fwd_only["two_doe_cascade"]["ms_fwd_bwd"] = dt * 1e3
+        log(f"two_doe_cascade forward + backward (mixed): {dt * 1e3:.1f} ms")
+        del pl
+        torch.cuda.empty_cache()
+
     # ------------------------------------- adaptive patch sizing (K local periods)
     adaptive = None
     if not args.no_forward_only:
