@@ -1404,7 +1404,7 @@ __device__ double g2_passes(const DoeArgs& a, const RayCtx& c,
                             float* gd, float* dlg, double* red, float* lrec) {
   using Tf = typename Prec::Tf;
   const DevCfg& cfg = *a.cfg;
-  const int N = cfg.N, P = c.P;
+  const int N = cfg.class_n[a.cls], P = c.P;   // this class's draws (records beyond are unused)
   const int t = opaque_tid(), lane = t & 63, wv = t >> 6;
   constexpr int NW = kDoeThreads / 64;
   const float Sf = (float)S;

@@ -127,3 +127,23 @@ def test_class_draws_mixed_gradients_on_oracle_draws(rw):
     assert abs(float(loss) - L0) <= 1e-4 * abs(L0)
     assert rel_l2(dp.cpu().numpy(), g["phase"]) < 1e-3
     assert rel_l2(da.cpu().numpy(), g["amp"]) < 1e-3
+
+
+def test_class_draws_g2_fp64_gradients(rw):
+    """The Gumbel-softmax straight-through gradient with per-class draw counts:
+    each class regenerates the perturbations of its own draws only."""
+    system, cfg, maps = _case()
+    cfg = dict(cfg, class_draws=True, grad="G2")
+    print("class draws g2 fp64", flush=True)
+    L0, g, _, _ = O.loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                  maps["amp"].astype(np.float64), np.zeros(0),
+                                  maps["target"].astype(np.float64))
+    plan = rw.Plan(system, cfg, precision="fp64")
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    _, loss, _ = plan.forward(vals, ph, am, target=tg)
+    dp, da, _ = plan.backward()
+    torch.cuda.synchronize()
+    assert abs(float(loss) - L0) <= 1e-6 * abs(L0)
+    assert rel_l2(dp.cpu().numpy(), g["phase"]) < 1e-4
+    assert rel_l2(da.cpu().numpy(), g["amp"]) < 1e-4

@@ -188,3 +188,26 @@ def test_cascade_map_gradients_mixed_on_oracle_draws(rw, grad):
     rep = rw.Plan.join_idx(j1, j2).cuda()
     _, L, dp, da, _ = _grads(rw, system, cfg, maps, "mixed", tgt, replay=rep)
     _check_grads(L, dp, da, L0, g, 1e-3)
+
+
+def test_cascade_backward_graph_replays_match_eager(rw):
+    system, cfg, maps = _case("mag")
+    tgt = torch.tensor(_target(cfg), device="cuda")
+    print("cascade backward graph", flush=True)
+    plan = rw.Plan(system, cfg, precision="mixed")
+    _, ph, am = gpu_inputs(system, maps)
+    plan.forward(None, ph, am, target=tgt)
+    dp0, da0, _ = plan.backward()
+    torch.cuda.synchronize()
+    dp0, da0 = dp0.cpu().numpy(), da0.cpu().numpy()
+    plan.set_graph(True)
+    psf = torch.empty((plan.L, plan.F, plan.Q, plan.Q), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    dp = torch.empty((2,) + ph.shape[1:], dtype=torch.float32, device="cuda")
+    da = torch.empty_like(dp)
+    for _ in range(3):
+        plan.forward(None, ph, am, target=tgt, psf_out=psf, loss_out=loss)
+        plan.backward(d_phase=dp, d_amp=da)
+        torch.cuda.synchronize()
+        assert rel_l2(dp.cpu().numpy(), dp0) < 1e-5
+        assert rel_l2(da.cpu().numpy(), da0) < 1e-5
