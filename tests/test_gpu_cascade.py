@@ -211,3 +211,28 @@ def test_cascade_backward_graph_replays_match_eager(rw):
         torch.cuda.synchronize()
         assert rel_l2(dp.cpu().numpy(), dp0) < 1e-5
         assert rel_l2(da.cpu().numpy(), da0) < 1e-5
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-5), ("mixed", 1e-3)])
+def test_cascade_on_curved_does(rw, precision, bar):
+    """Both DOEs on spheres (R = 5 mm and -8 mm): curved frames and patches at
+    each stage, the relay intersecting a curved surface; PSF and both maps'
+    gradients on the oracle's draws."""
+    system, cfg, maps = _case("mag", curvature=(0.2, -0.125))
+    tgt = _target(cfg)
+    print(f"cascade curved {precision}", flush=True)
+    L0, g, ref, oidx = O.cascade_loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                               maps["amp"].astype(np.float64),
+                                               tgt.astype(np.float64))
+    j1 = torch.tensor(np.stack([oidx[p][0] for p in sorted(oidx)]), dtype=torch.int32)
+    j2 = torch.tensor(np.stack([oidx[p][1] for p in sorted(oidx)]), dtype=torch.int32)
+    rep = rw.Plan.join_idx(j1, j2).cuda()
+    plan = rw.Plan(system, cfg, precision=precision)
+    _, ph, am = gpu_inputs(system, maps)
+    psf, loss, _ = plan.forward(None, ph, am, target=torch.tensor(tgt, device="cuda"),
+                                replay=rep)
+    dp, da, _ = plan.backward()
+    torch.cuda.synchronize()
+    psf_bar = 1e-6 if precision == "fp64" else 1e-4
+    assert rel_l2(psf.cpu().numpy(), ref) < psf_bar
+    _check_grads(float(loss), dp.cpu().numpy(), da.cpu().numpy(), L0, g, bar)

@@ -525,13 +525,14 @@ def adaptive_zone_plate(rays_side=256, H=1024, pitch=0.001, lam=0.5e-3, f=10.0, 
 # ----------------------------------------------------------------------------
 def two_doe_cascade(rays_side=8, H=64, pitch=(0.004, 0.02), P=16, pad=2, N=16, N2=8, Q=32,
                     psf_pitch=0.02, sampling="mag", lambdas=(LAM_D,), fields=((0.0, 0.0),),
-                    cutoff=0.05, uniform=(False, False), seed=0):
+                    cutoff=0.05, uniform=(False, False), curvature=(0.0, 0.0), seed=0):
+    """curvature: of the two DOE surfaces (0: planar)."""
     rng = np.random.default_rng(seed)
     z_doe2 = 4.0
-    surfs = [surface(0.0, doe=True),
+    surfs = [surface(0.0, c=curvature[0], doe=True),
              surface(1.0, c=1.0 / 20.0, medium=BK7),
              surface(2.5),
-             surface(z_doe2, medium=BK7, doe=True),
+             surface(z_doe2, c=curvature[1], medium=BK7, doe=True),
              surface(5.0)]
     does = [dict(doe_desc(H, H, pitch[k]), field="amp_phase") for k in range(2)]
     phase = np.zeros((2, H, H), np.float32)
