@@ -202,6 +202,39 @@ def dft_compare(n_patches):
     print(json.dumps(out), flush=True)
 
 
+def next_rows(iters=3):
+    """Forward + backward of the two-DOE cascade and of adaptive patch sizing with
+    class draw budgets (MIXED, batched), `iters` times each; one JSON line of the
+    last iteration's times."""
+    import numpy as np
+    import torch
+    import paper_2605_15418_amd as rw
+    import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    rng = np.random.default_rng(20260300)
+    for name, tweak in (("two_doe_cascade", {}), ("adaptive_zone_plate", {"class_draws": True})):
+        s, c, m = W.workload(name)
+        c = dict(c, **tweak)
+        L, F, Q = len(c["lambdas"]), len(c["fields"]), c["psf_q"]
+        tg = m["target"] if m["target"] is not None else rng.uniform(0, 1, (L, F, Q, Q))
+        tg = torch.tensor(tg, dtype=torch.float32, device=dev)
+        plan = rw.Plan(s, c, precision="mixed", batched=True)
+        ph = torch.tensor(m["phase"], device=dev)
+        am = torch.tensor(m["amp"], device=dev)
+        v = torch.zeros(0, device=dev)
+        for _ in range(iters):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.forward(v, ph, am, target=tg)
+            plan.backward()
+            torch.cuda.synchronize()
+            out[name] = (time.perf_counter() - t0) * 1e3
+        del plan
+        torch.cuda.empty_cache()
+    print(json.dumps({"ms_fwd_bwd": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,9 +256,15 @@ def main():
                     help="only compare patch-transform methods on this many patches")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--next-rows", action="store_true",
+                    help="only the forward + backward of the two-DOE cascade and of adaptive "
+                         "patch sizing with class draw budgets, three times each (for traces)")
     args = ap.parse_args()
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
+        return
+    if args.next_rows:
+        next_rows()
         return
     if args.dft_compare:
         dft_compare(args.dft_compare)
