@@ -236,3 +236,31 @@ def test_cascade_on_curved_does(rw, precision, bar):
     psf_bar = 1e-6 if precision == "fp64" else 1e-4
     assert rel_l2(psf.cpu().numpy(), ref) < psf_bar
     _check_grads(float(loss), dp.cpu().numpy(), da.cpu().numpy(), L0, g, bar)
+
+
+def test_cascade_in_several_launch_groups(rw):
+    """A record budget of one pair's records splits the four pairs into four
+    launch groups (forward and both DOEs' adjoints group by group): same PSF and
+    gradients as one group."""
+    system, cfg, maps = _case("mag")
+    tgt = _target(cfg)
+    print("cascade groups", flush=True)
+    one = _grads(rw, system, cfg, maps, "fp64", tgt)
+    rec = (9 * 4) ** 2 * 8 * 3 * 32          # ~ one pair's records in the FP64 form
+    many = _grads(rw, system, dict(cfg, record_budget_bytes=rec), maps, "fp64", tgt)
+    assert abs(one[1] - many[1]) <= 1e-9 * abs(one[1])
+    assert rel_l2(many[2], one[2]) < 1e-9 and rel_l2(many[3], one[3]) < 1e-9
+
+
+def test_cascade_uni_gradients_on_oracle_draws(rw):
+    system, cfg, maps = _case("uni")
+    tgt = _target(cfg)
+    print("cascade gradients uni", flush=True)
+    L0, g, _, oidx = O.cascade_loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                             maps["amp"].astype(np.float64),
+                                             tgt.astype(np.float64))
+    j1 = torch.tensor(np.stack([oidx[p][0] for p in sorted(oidx)]), dtype=torch.int32)
+    j2 = torch.tensor(np.stack([oidx[p][1] for p in sorted(oidx)]), dtype=torch.int32)
+    rep = rw.Plan.join_idx(j1, j2).cuda()
+    _, L, dp, da, _ = _grads(rw, system, cfg, maps, "mixed", tgt, replay=rep)
+    _check_grads(L, dp, da, L0, g, 1e-3)
