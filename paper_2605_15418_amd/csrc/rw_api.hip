@@ -139,7 +139,7 @@ struct rw_plan {
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
       off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
-      off_interp, off_g2, off_rcls, off_slices, off_heavy, total;
+      off_interp, off_g2, off_rcls, off_slices, off_heavy, off_islices, off_iheavy, total;
   size_t fwd_bytes;        // workspace of a forward-only pass (a prefix of the layout)
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
@@ -486,11 +486,26 @@ rw_status interp_tiles_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int n
   const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
   const C2<Tg>* adj = (const C2<Tg>*)(b + pl->off_grid);
   C2<Tg>* out = (C2<Tg>*)(b + pl->off_interp);
+  // blocks whose records a focusing system has concentrated, in slices
+  unsigned char* sl = (unsigned char*)(b + pl->off_islices);
+  unsigned int* nh = (unsigned int*)(b + pl->off_iheavy);
+  uint2* hv = (uint2*)(b + pl->off_iheavy + 256);
+  const size_t per_pair = (size_t)pl->R2 * pl->emit;
+  const unsigned long long target =
+      std::max<unsigned long long>(16384, (unsigned long long)npairs * per_pair / 2048);
+  zero<unsigned int>(nh, 1, st);
+  hipLaunchKernelGGL(k_interp_slices, dim3((unsigned)(((size_t)npairs * nsb * nsb + 255) / 256)),
+                     dim3(256), 0, st, so, g, pair0, npairs, target, sl, hv, nh);
+  const dim3 hg(1024);
   switch (pl->w) {
 #define RW_INTERP_CASE(W)                                                                     \
     case W:                                                                                   \
       hipLaunchKernelGGL((k_interp_tiles<Tg, W>), grid, dim3(256), lds, st, sp, si, so, g,   \
-                         pl->beta, pair0, adj, out);                                          \
+                         pl->beta, pair0, adj, out, (const unsigned char*)sl,                 \
+                         (const uint2*)nullptr, (const unsigned int*)nullptr);                \
+      hipLaunchKernelGGL((k_interp_tiles<Tg, W>), hg, dim3(256), lds, st, sp, si, so, g,     \
+                         pl->beta, pair0, adj, out, (const unsigned char*)sl, (const uint2*)hv,\
+                         (const unsigned int*)nh);                                            \
       break;
     RW_INTERP_CASE(4) RW_INTERP_CASE(5) RW_INTERP_CASE(6) RW_INTERP_CASE(7) RW_INTERP_CASE(8)
     RW_INTERP_CASE(9) RW_INTERP_CASE(10) RW_INTERP_CASE(11) RW_INTERP_CASE(12)
@@ -967,6 +982,13 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
   pl->off_lensg = take(bw * RW_LENSG_SLOTS * sizeof(double));
   pl->off_G = take(bw * (size_t)pl->n_pairs * pl->Q * pl->Q * pl->sz_cg);
   pl->off_interp = take(bw * (tl ? nrec * kInterpStride * pl->sz_cg : 0));
+  {
+    // slices of the tiled interpolation's blocks (2 x 2 bins) and the list of the
+    // heavy blocks' further slices (its length first)
+    const size_t nb2 = (size_t)(pl->bg.nb / 2) * (pl->bg.nb / 2) * pl->group_pairs;
+    pl->off_islices = take(tl ? nb2 : 0);
+    pl->off_iheavy = take(tl ? 256 + nb2 * (kInterpSlices - 1) * sizeof(uint2) : 0);
+  }
   if (cs) {
     // the first DOE's draws (left by the forward), its dL/dt, and the second
     // DOE's dL/d(incident amplitude) per ray

@@ -344,14 +344,42 @@ __global__ __launch_bounds__(256) void k_post_bwd(DoeArgs a) {
 // grid coordinate, and with the kernel's derivative along x and along y.  One
 // block per 2 x 2 bins stages every grid cell its records' footprints reach
 // in LDS; one lane per record; results go to the record's slot.
+// A block whose records a focusing system has concentrated takes a slice of
+// them: k_interp_slices cuts a block's records into S = ceil(records / target)
+// <= kInterpSlices slices (target about 1/2048 of the launch's); the block of
+// the first launch takes slice 0, the blocks of the second the listed slices
+// 1 .. S - 1 (each result goes to its own record's slot: no atomics).
 __host__ __device__ constexpr int interp_side(int bin, int w) { return 2 * bin + 2 * ((w + 1) / 2); }
+constexpr int kInterpSlices = 32;
+
+static __global__ __launch_bounds__(256) void k_interp_slices(const unsigned long long* offsets,
+                                                       BinGeom g, int pair0, int npairs,
+                                                       unsigned long long target,
+                                                       unsigned char* slices, uint2* heavy,
+                                                       unsigned int* n_heavy) {
+  const int nsb = g.nb / 2, nt = nsb * nsb;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)npairs * nt) return;
+  const int pl = (int)(i / nt), t = (int)(i % nt);
+  const unsigned long long* off = offsets + (size_t)(pair0 + pl) * g.keys;
+  unsigned long long n = 0;
+  for (int q = 0; q < 4; ++q) {
+    const int k = bin_key((t / nsb) * 2 + q / 2, (t % nsb) * 2 + q % 2, g);
+    n += off[k + 1] - off[k];
+  }
+  const int S = (int)min((unsigned long long)kInterpSlices, max(1ull, (n + target - 1) / target));
+  slices[i] = (unsigned char)S;
+  if (S > 1) {
+    const unsigned int b = atomicAdd(n_heavy, (unsigned int)(S - 1));
+    for (int k = 1; k < S; ++k) heavy[b + k - 1] = make_uint2((unsigned int)i, (unsigned int)k);
+  }
+}
 
 template <class Tg, int w>
-__global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
-                                                      const unsigned int* srt_idx,
-                                                      const unsigned long long* offsets,
-                                                      BinGeom g, double beta, int pair0,
-                                                      const C2<Tg>* adj, C2<Tg>* out) {
+__device__ __forceinline__ void interp_tile(const void* srt_pos, const unsigned int* srt_idx,
+                                            const unsigned long long* offsets, const BinGeom& g,
+                                            double beta, int pair, int tile_i, int slice, int S,
+                                            const C2<Tg>* adj, C2<Tg>* out) {
   using U = typename RecPos<Tg>::T;
   extern __shared__ unsigned char s_raw[];
   C2<Tg>* cells = (C2<Tg>*)s_raw;
@@ -359,10 +387,10 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   constexpr int half = (w + 1) / 2;
   const int side = interp_side(g.bin, w);
   const int nsb = g.nb / 2;
-  const int pair = pair0 + blockIdx.y;
-  const int sby = blockIdx.x / nsb, sbx = blockIdx.x % nsb;
+  const int sby = tile_i / nsb, sbx = tile_i % nsb;
   const int X0 = sbx * 2 * g.bin - half, Y0 = sby * 2 * g.bin - half;
   const C2<Tg>* gp = adj + (size_t)pair * g.nf * g.nf;
+  __syncthreads();                              // LDS reuse across the tiles of a block
   // cells staged 8 per lane at a time: the loads are issued before the stores
   for (int i0 = threadIdx.x; i0 < side * side; i0 += 8 * blockDim.x) {
     C2<Tg> v[8];
@@ -394,7 +422,10 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   __syncthreads();
   const U* pos = (const U*)srt_pos;
   const Tg tw = (Tg)(2.0 / w), bet = (Tg)beta;
-  const unsigned long long ntot = s_pre[4];
+  // this slice's records
+  const unsigned long long nall = s_pre[4];
+  const unsigned long long jlo = nall * (unsigned long long)slice / (unsigned long long)S;
+  const unsigned long long ntot = nall * (unsigned long long)(slice + 1) / (unsigned long long)S;
   // the position and slot of the next record are loaded before the current one
   // is interpolated
   int b = 0;                                        // monotonic over the lane's records
@@ -404,11 +435,11 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
   };
   U nx = 0, ny = 0;
   unsigned int nid = 0;
-  if (threadIdx.x < ntot) {
-    const unsigned long long r = rec_of(threadIdx.x);
+  if (jlo + threadIdx.x < ntot) {
+    const unsigned long long r = rec_of(jlo + threadIdx.x);
     nx = pos[2 * r]; ny = pos[2 * r + 1]; nid = srt_idx[r];
   }
-  for (unsigned long long j = threadIdx.x; j < ntot; j += blockDim.x) {
+  for (unsigned long long j = jlo + threadIdx.x; j < ntot; j += blockDim.x) {
     const U px = nx, py = ny;
     const unsigned int slot = nid;
     if (j + blockDim.x < ntot) {
@@ -456,6 +487,31 @@ __global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
     o[1] = {(Tg)dxr, (Tg)dxi};
     o[2] = {(Tg)dyr, (Tg)dyi};
     o[3] = {Tg(0), Tg(0)};
+  }
+}
+
+// slices: S per (pair of the group, block of 2 x 2 bins); heavy: null for the
+// launch over every block (slice 0), else the list of further slices.
+template <class Tg, int w>
+__global__ __launch_bounds__(256) void k_interp_tiles(const void* srt_pos,
+                                                      const unsigned int* srt_idx,
+                                                      const unsigned long long* offsets,
+                                                      BinGeom g, double beta, int pair0,
+                                                      const C2<Tg>* adj, C2<Tg>* out,
+                                                      const unsigned char* slices,
+                                                      const uint2* heavy,
+                                                      const unsigned int* n_heavy) {
+  const int nt = (g.nb / 2) * (g.nb / 2);
+  if (!heavy) {
+    interp_tile<Tg, w>(srt_pos, srt_idx, offsets, g, beta, pair0 + blockIdx.y, blockIdx.x, 0,
+                       slices[(size_t)blockIdx.y * nt + blockIdx.x], adj, out);
+    return;
+  }
+  const unsigned int n = *n_heavy;
+  for (unsigned int e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint2 h = heavy[e];
+    interp_tile<Tg, w>(srt_pos, srt_idx, offsets, g, beta, pair0 + (int)(h.x / nt),
+                       (int)(h.x % nt), (int)h.y, slices[h.x], adj, out);
   }
 }
 

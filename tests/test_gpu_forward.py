@@ -410,3 +410,27 @@ def test_focused_records_split_heavy_tiles(rw, precision, bar):
                        device="cuda")
     _, psf, _ = _run(rw, system, cfg, maps, precision, replay=rep)
     assert rel_l2(psf, ref) < bar
+
+
+def test_focused_records_gradients_split_interpolation(rw):
+    """At a zone plate's focus the tiled interpolation's few busy blocks are cut
+    into slices as well; the map gradients on the oracle's draws still match."""
+    import workloads as W
+    system, cfg, maps = W.adaptive_zone_plate(rays_side=64, H=256, pitch=0.002, f=5.0, P=16,
+                                              classes=(), N=64, Q=32, psf_pitch=0.002,
+                                              sampling="mag")
+    cfg = dict(cfg, patch_classes=[], bw_periods=0.0)
+    print("heavy interpolation gradients", flush=True)
+    L0, g, _, idx = O.loss_and_grad(system, cfg, maps["phase"].astype(np.float64),
+                                    maps["amp"].astype(np.float64), np.zeros(0),
+                                    maps["target"].astype(np.float64))
+    rep = torch.tensor(np.stack([idx[p] for p in sorted(idx)]), dtype=torch.int32, device="cuda")
+    plan = rw.Plan(system, cfg, precision="mixed")
+    vals, ph, am = gpu_inputs(system, maps)
+    tg = torch.tensor(maps["target"], device="cuda")
+    _, loss, _ = plan.forward(vals, ph, am, target=tg, replay=rep)
+    dp, da, _ = plan.backward()
+    torch.cuda.synchronize()
+    assert abs(float(loss) - L0) <= 1e-4 * abs(L0)
+    assert rel_l2(dp.cpu().numpy(), g["phase"]) < 1e-3
+    assert rel_l2(da.cpu().numpy(), g["amp"]) < 1e-3
