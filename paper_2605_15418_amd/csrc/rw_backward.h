@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void k_post_bwd(DoeArgs a) {
 // the first launch takes slice 0, the blocks of the second the listed slices
 // 1 .. S - 1 (each result goes to its own record's slot: no atomics).
 __host__ __device__ constexpr int interp_side(int bin, int w) { return 2 * bin + 2 * ((w + 1) / 2); }
-constexpr int kInterpSlices = 32;
+constexpr int kInterpSlices = 255;   // most slices of one block (a byte per block)
 
 static __global__ __launch_bounds__(256) void k_interp_slices(const unsigned long long* offsets,
                                                        BinGeom g, int pair0, int npairs,

@@ -951,8 +951,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 constexpr int kSpreadWaves = 4;      // waves per spreading block (256 threads)
-constexpr int kSpreadTarget = 65536; // least records per slice of a heavy tile
-constexpr int kSpreadSlices = 32;    // most slices of one tile
+constexpr int kSpreadTarget = 8192;  // least records per slice of a heavy tile
+constexpr int kSpreadSlices = 255;   // most slices of one tile (a byte per tile)
 constexpr int kSpreadBatch = 32;     // queued records staged and added per round
 constexpr int kSpreadQueue = 96;     // queue capacity: a batch plus one scan step
 
