@@ -179,6 +179,17 @@ typedef struct {
    * classes; Eq. 1 divides by N_k).  Sample indices keep n_ssr slots per ray, -1
    * beyond N_k.  Needs patch classes and MAG or UNI sampling.  0: n_ssr for every ray. */
   int class_draws;
+  /* 1: run-to-run reproducible forward.  The Eq. 2 records are spread as 64-bit
+   * fixed-point integers (each tap scaled by 2^s, s fixed by the largest record
+   * value and the record count of the launch group, and rounded; sums by integer
+   * atomics, exact in any order), so the PSF and the loss of two forwards on the
+   * same inputs agree bit for bit.  A tap is rounded to within about n 2^-61 of
+   * the largest record value, n the group's record slots.  The forward bytes of
+   * rw_plan_workspace_bytes grow by 16 nf^2 per pair of a launch group (nf the
+   * spreading grid's side); the records are not sorted.  rw_backward,
+   * rw_forward_backward and rw_autotune return RW_ERR_UNSUPPORTED for such a plan:
+   * their map- and lens-gradient sums are float atomics.  0: the tiled spreading. */
+  int deterministic;
 } rw_config;
 
 typedef struct rw_plan rw_plan;

@@ -10,6 +10,7 @@
 
 #include "../../include/rw.h"
 #include "rw_doe.h"
+#include "rw_det.h"
 #include "rw_launch.h"
 
 using namespace rw;
@@ -139,7 +140,8 @@ struct rw_plan {
       off_spos, off_sval, off_cnt, off_offs, off_cur, off_acc, off_ctx, off_dlist, off_sidx,
       off_scur, off_tpos, off_tval, off_tidx, off_work,
       off_jdraw,
-      off_interp, off_g2, off_rcls, off_slices, off_heavy, off_islices, off_iheavy, total;
+      off_interp, off_g2, off_rcls, off_slices, off_heavy, off_islices, off_iheavy, off_dacc,
+      total;
   size_t fwd_bytes;        // workspace of a forward-only pass (a prefix of the layout)
   size_t sz_cf, sz_cg;   // sizeof(C2<Tf>), sizeof(C2<Tg>)
   // state between forward and backward
@@ -390,8 +392,45 @@ rw_status grid_bwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
 template <class T>
 void zero(void* p, size_t n, hipStream_t st);
 
+// Deterministic mode: the records of the group spread as fixed-point integers
+// (no sort, no float atomics), then converted into the group's grids.
+template <class Tg>
+rw_status det_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  char* b = (char*)ws;
+  const size_t per_pair = (size_t)pl->R2 * pl->emit;
+  const size_t n = per_pair * (size_t)npairs;
+  const size_t ncells = (size_t)npairs * pl->nf * pl->nf;
+  unsigned long long* amax = (unsigned long long*)(b + pl->off_dacc);
+  unsigned long long* acc = (unsigned long long*)(b + pl->off_dacc + 256);
+  auto blocks = [](size_t m) { return dim3((unsigned)std::max<size_t>(1, std::min<size_t>((m + 255) / 256, 16384))); };
+  StageTimer ts_(pl, RW_STAGE_SPREAD, st);
+  zero<unsigned long long>(amax, 1, st);
+  zero<unsigned long long>(acc, 2 * ncells, st);
+  const void* rp = (const void*)(b + pl->off_rpos);
+  const void* rv = (const void*)(b + pl->off_rval);
+  hipLaunchKernelGGL(k_det_absmax<Tg>, blocks(n), dim3(256), 0, st, rv, n, amax);
+  switch (pl->w) {
+#define RW_DET_CASE(W)                                                                        \
+    case W:                                                                                   \
+      hipLaunchKernelGGL((k_det_spread<Tg, W>), blocks(n), dim3(256), 0, st, rp, rv, per_pair, \
+                         npairs, pl->nf, pl->beta, n, (const unsigned long long*)amax, acc);   \
+      break;
+    RW_DET_CASE(4) RW_DET_CASE(5) RW_DET_CASE(6) RW_DET_CASE(7) RW_DET_CASE(8)
+    RW_DET_CASE(9) RW_DET_CASE(10) RW_DET_CASE(11) RW_DET_CASE(12)
+    RW_DET_CASE(13) RW_DET_CASE(14) RW_DET_CASE(15) RW_DET_CASE(16)
+#undef RW_DET_CASE
+    default: return fail(RW_ERR_SHAPE, "spread_width must be in [4, 16]");
+  }
+  hipLaunchKernelGGL(k_det_store<Tg>, blocks(ncells), dim3(256), 0, st,
+                     (const unsigned long long*)acc, ncells, n, (const unsigned long long*)amax,
+                     (C2<Tg>*)(b + pl->off_grid) + (size_t)pair0 * pl->nf * pl->nf);
+  HIPCHK(hipGetLastError());
+  return RW_OK;
+}
+
 template <class Tg>
 rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
+  if (pl->cfg.deterministic) return det_spread_t<Tg>(pl, ws, st, pair0, npairs);
   char* b = (char*)ws;
   const BinGeom g = pl->bg;
   const size_t per_pair = (size_t)pl->R2 * pl->emit;
@@ -954,6 +993,10 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
     pl->off_slices = take(nt);
     pl->off_heavy = take(256 + nt * (kSpreadSlices - 1) * sizeof(uint2));
   }
+  // deterministic mode: the bound word, then the group's grids as (re, im) int64
+  pl->off_dacc = take(cfg->deterministic
+                          ? 256 + (size_t)pl->group_pairs * pl->nf * pl->nf * 2 * sizeof(long long)
+                          : 0);
   if (cs) {
     // the first DOE: its map, launched rays (state, checkpoints, contexts, classes)
     const size_t n1t = pl->n1_total;
@@ -1090,6 +1133,8 @@ rw_status rw_plan_destroy(rw_plan* pl) {
 rw_status rw_autotune(rw_plan* pl, void* ws, size_t ws_bytes, int* shape_out, void* stream) {
   if (!pl || !ws) return fail(RW_ERR_INVALID_ARG, "null argument");
   if (pl->casc) return fail(RW_ERR_UNSUPPORTED, "rw_autotune does not tune a DOE cascade");
+  if (pl->cfg.deterministic)
+    return fail(RW_ERR_UNSUPPORTED, "the deterministic mode is forward-only: nothing to tune");
   if (!pl->fwd_done || !pl->fwd_full || ws != pl->fwd_ws || ws_bytes < pl->total)
     return fail(RW_ERR_STATE, "rw_autotune needs a preceding rw_forward on this workspace "
                               "(of fwd + bwd bytes)");
@@ -1768,6 +1813,9 @@ static rw_status step_enqueue(rw_plan* pl, const float* lens_params, const float
 rw_status rw_backward(rw_plan* pl, const float* dL_dpsf, float* d_phase, float* d_amp,
                       float* d_lens, void* ws, size_t ws_bytes, void* stream) {
   if (!pl || !d_phase || !d_amp || !ws) return fail(RW_ERR_INVALID_ARG, "null required argument");
+  if (pl->cfg.deterministic)
+    return fail(RW_ERR_UNSUPPORTED, "the deterministic mode is forward-only (its gradient sums "
+                                    "are not ordered)");
   if (pl->casc && d_lens && !pl->prm.empty())
     return fail(RW_ERR_UNSUPPORTED, "lens gradients through a DOE cascade are not built");
   if (!pl->fwd_done) return fail(RW_ERR_STATE, "rw_backward needs a preceding rw_forward");
@@ -1801,6 +1849,9 @@ rw_status rw_forward_backward(rw_plan* pl, const float* lens_params, const float
                               void* ws, size_t ws_bytes, void* stream) {
   if (pl && pl->casc)
     return fail(RW_ERR_UNSUPPORTED, "gradients through a DOE cascade are not built");
+  if (pl && pl->cfg.deterministic)
+    return fail(RW_ERR_UNSUPPORTED, "the deterministic mode is forward-only (its gradient sums "
+                                    "are not ordered)");
   const rw_status a = forward_args(pl, lens_params, doe_phase, doe_amp, target, psf_out, loss_out,
                                    nullptr);
   if (a != RW_OK) return a;

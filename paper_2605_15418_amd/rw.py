@@ -70,7 +70,8 @@ class rw_config(ctypes.Structure):
                 ("n_patch_class", ctypes.c_int), ("patch_class_p", ctypes.c_int * 3),
                 ("curv_eps", ctypes.c_double), ("check_finite", ctypes.c_int),
                 ("record_budget_bytes", ctypes.c_uint64),
-                ("bandwidth_periods", ctypes.c_double), ("class_draws", ctypes.c_int)]
+                ("bandwidth_periods", ctypes.c_double), ("class_draws", ctypes.c_int),
+                ("deterministic", ctypes.c_int)]
 
 
 class rw_profile(ctypes.Structure):
@@ -281,6 +282,7 @@ class Plan:
         c.record_budget_bytes = int(cfg.get("record_budget_bytes", 0))
         c.bandwidth_periods = float(cfg.get("bw_periods", 0.0))
         c.class_draws = int(bool(cfg.get("class_draws", False)))
+        c.deterministic = int(bool(cfg.get("deterministic", False)))
         h = ctypes.c_void_p()
         if self.cascade:
             doe1 = desc(system["does"][0])
