@@ -186,7 +186,7 @@ typedef struct {
    * same inputs agree bit for bit.  A tap is rounded to within about n 2^-61 of
    * the largest record value, n the group's record slots.  The forward bytes of
    * rw_plan_workspace_bytes grow by 16 nf^2 per pair of a launch group (nf the
-   * spreading grid's side); the records are not sorted.  rw_backward,
+   * spreading grid's side) and a list of slices.  rw_backward,
    * rw_forward_backward and rw_autotune return RW_ERR_UNSUPPORTED for such a plan:
    * their map- and lens-gradient sums are float atomics.  0: the tiled spreading. */
   int deterministic;

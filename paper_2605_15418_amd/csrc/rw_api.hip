@@ -392,28 +392,65 @@ rw_status grid_bwd(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs,
 template <class T>
 void zero(void* p, size_t n, hipStream_t st);
 
-// Deterministic mode: the records of the group spread as fixed-point integers
-// (no sort, no float atomics), then converted into the group's grids.
+// Deterministic mode: the binned records of the group spread as fixed-point
+// integers by sub-tiles (LDS, then the group's integer grid), then converted
+// into the group's grids.  Byte offsets in the mode's buffer: the bound word,
+// the heavy-slice count, the integer grids, the slices per sub-tile, the list.
+struct DetLayout {
+  size_t grids, slices, heavy, total;
+};
+static DetLayout det_layout(const BinGeom& g, int group_pairs) {
+  const size_t tb = (size_t)det_tb(g), ns = (g.nb / tb) * (g.nb / tb) * group_pairs;
+  DetLayout d;
+  d.grids = 512;
+  d.slices = d.grids + align256((size_t)group_pairs * g.nf * g.nf * 2 * sizeof(long long));
+  d.heavy = d.slices + align256(ns);
+  d.total = d.heavy + ns * (kDetSlices - 1) * sizeof(uint2);
+  return d;
+}
+
 template <class Tg>
 rw_status det_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
   char* b = (char*)ws;
+  const BinGeom g = pl->bg;
   const size_t per_pair = (size_t)pl->R2 * pl->emit;
   const size_t n = per_pair * (size_t)npairs;
   const size_t ncells = (size_t)npairs * pl->nf * pl->nf;
-  unsigned long long* amax = (unsigned long long*)(b + pl->off_dacc);
-  unsigned long long* acc = (unsigned long long*)(b + pl->off_dacc + 256);
-  auto blocks = [](size_t m) { return dim3((unsigned)std::max<size_t>(1, std::min<size_t>((m + 255) / 256, 16384))); };
+  const DetLayout dl = det_layout(g, pl->group_pairs);
+  char* d0 = b + pl->off_dacc;
+  unsigned long long* amax = (unsigned long long*)d0;
+  unsigned int* nh = (unsigned int*)(d0 + 256);
+  unsigned long long* acc = (unsigned long long*)(d0 + dl.grids);
+  unsigned char* sl = (unsigned char*)(d0 + dl.slices);
+  uint2* hv = (uint2*)(d0 + dl.heavy);
+  const int tb = det_tb(g), side = tb * g.bin, ns = (g.nb / tb) * (g.nb / tb);
+  auto blocks = [](size_t m) {
+    return dim3((unsigned)std::max<size_t>(1, std::min<size_t>((m + 255) / 256, 16384)));
+  };
   StageTimer ts_(pl, RW_STAGE_SPREAD, st);
   zero<unsigned long long>(amax, 1, st);
+  zero<unsigned int>(nh, 1, st);
   zero<unsigned long long>(acc, 2 * ncells, st);
-  const void* rp = (const void*)(b + pl->off_rpos);
-  const void* rv = (const void*)(b + pl->off_rval);
-  hipLaunchKernelGGL(k_det_absmax<Tg>, blocks(n), dim3(256), 0, st, rv, n, amax);
+  hipLaunchKernelGGL(k_det_absmax<Tg>, blocks(n), dim3(256), 0, st,
+                     (const void*)(b + pl->off_rval), n, amax);
+  const unsigned long long target = std::max<unsigned long long>(kSpreadTarget, n / 1024);
+  const unsigned long long* so = (const unsigned long long*)(b + pl->off_offs);
+  hipLaunchKernelGGL(k_det_slices, blocks((size_t)npairs * ns), dim3(256), 0, st, so, g, pair0,
+                     npairs, target, sl, hv, nh);
+  const void* sp = (const void*)(b + pl->off_spos);
+  const void* sv = (const void*)(b + pl->off_sval);
+  const size_t lds = (size_t)side * side * 2 * sizeof(unsigned long long);
+  const dim3 sg(ns, npairs), hg(1024);
+  const unsigned long long* am = amax;
   switch (pl->w) {
 #define RW_DET_CASE(W)                                                                        \
     case W:                                                                                   \
-      hipLaunchKernelGGL((k_det_spread<Tg, W>), blocks(n), dim3(256), 0, st, rp, rv, per_pair, \
-                         npairs, pl->nf, pl->beta, n, (const unsigned long long*)amax, acc);   \
+      hipLaunchKernelGGL((k_det_tiles<Tg, W>), sg, dim3(256), lds, st, sp, sv, so, g,         \
+                         pl->beta, pair0, n, am, acc, (const unsigned char*)sl,               \
+                         (const uint2*)nullptr, (const unsigned int*)nullptr);                \
+      hipLaunchKernelGGL((k_det_tiles<Tg, W>), hg, dim3(256), lds, st, sp, sv, so, g,         \
+                         pl->beta, pair0, n, am, acc, (const unsigned char*)sl,               \
+                         (const uint2*)hv, (const unsigned int*)nh);                          \
       break;
     RW_DET_CASE(4) RW_DET_CASE(5) RW_DET_CASE(6) RW_DET_CASE(7) RW_DET_CASE(8)
     RW_DET_CASE(9) RW_DET_CASE(10) RW_DET_CASE(11) RW_DET_CASE(12)
@@ -422,7 +459,7 @@ rw_status det_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npa
     default: return fail(RW_ERR_SHAPE, "spread_width must be in [4, 16]");
   }
   hipLaunchKernelGGL(k_det_store<Tg>, blocks(ncells), dim3(256), 0, st,
-                     (const unsigned long long*)acc, ncells, n, (const unsigned long long*)amax,
+                     (const unsigned long long*)acc, ncells, n, am,
                      (C2<Tg>*)(b + pl->off_grid) + (size_t)pair0 * pl->nf * pl->nf);
   HIPCHK(hipGetLastError());
   return RW_OK;
@@ -430,7 +467,6 @@ rw_status det_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npa
 
 template <class Tg>
 rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int npairs) {
-  if (pl->cfg.deterministic) return det_spread_t<Tg>(pl, ws, st, pair0, npairs);
   char* b = (char*)ws;
   const BinGeom g = pl->bg;
   const size_t per_pair = (size_t)pl->R2 * pl->emit;
@@ -470,6 +506,7 @@ rw_status bin_and_spread_t(rw_plan* pl, void* ws, hipStream_t st, int pair0, int
                      (void*)(b + pl->off_sval),
                      slots ? (unsigned int*)(b + pl->off_sidx) : nullptr);
   delete tb_;
+  if (pl->cfg.deterministic) return det_spread_t<Tg>(pl, ws, st, pair0, npairs);
   const int tile = 4 * g.bin;
   const int ntiles = (g.nf / tile) * (g.nf / tile);
   StageTimer ts_(pl, RW_STAGE_SPREAD, st);
@@ -917,7 +954,13 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
                                hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);         \
     if (eb == hipSuccess)                                                                       \
       eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_tiles<double, W>),       \
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);         \
+    if (ea == hipSuccess)                                                                       \
+      ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_det_tiles<float, W>),           \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);          \
+    if (eb == hipSuccess)                                                                       \
+      eb = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_det_tiles<double, W>),          \
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     RW_ATTR(4) RW_ATTR(5) RW_ATTR(6) RW_ATTR(7) RW_ATTR(8) RW_ATTR(9) RW_ATTR(10) RW_ATTR(11)
     RW_ATTR(12) RW_ATTR(13) RW_ATTR(14) RW_ATTR(15) RW_ATTR(16)
 #undef RW_ATTR
@@ -993,10 +1036,9 @@ rw_status plan_create(const rw_surface* surfaces, int n_surf, const rw_doe_desc*
     pl->off_slices = take(nt);
     pl->off_heavy = take(256 + nt * (kSpreadSlices - 1) * sizeof(uint2));
   }
-  // deterministic mode: the bound word, then the group's grids as (re, im) int64
-  pl->off_dacc = take(cfg->deterministic
-                          ? 256 + (size_t)pl->group_pairs * pl->nf * pl->nf * 2 * sizeof(long long)
-                          : 0);
+  // deterministic mode: its bound and slice count, the group's grids as (re, im)
+  // int64, and its slices
+  pl->off_dacc = take(cfg->deterministic ? det_layout(pl->bg, pl->group_pairs).total : 0);
   if (cs) {
     // the first DOE: its map, launched rays (state, checkpoints, contexts, classes)
     const size_t n1t = pl->n1_total;

@@ -8,10 +8,11 @@
 // runs agree only to rounding.
 //
 // Here every tap is a fixed-point integer: value x kernel factor, scaled by a
-// power of two 2^s and rounded to the nearest integer, added with 64-bit
-// integer atomics into a per-pair grid of (re, im) integers.  Integer addition
-// is exact and associative, so the grid does not depend on the order of the
-// adds, and the records need no sort.  The scale comes from an order-free
+// power of two 2^s and rounded to the nearest integer.  A block adds the taps
+// of its sub-tile into LDS with 64-bit integer atomics, then its sub-tile into
+// the group's integer grid, again with integer atomics.  Integer addition is
+// exact and associative, so neither the order of the binned records nor the
+// order of the adds changes a bit of the grid.  The scale comes from an order-free
 // bound: every tap is at most A = max |re|, |im| over the group's records
 // (the ES kernel is at most 1), a cell holds at most n taps (n = the group's
 // record slots), so with 2^s n A <= 2^62 no sum leaves the int64 range.  A tap
@@ -51,28 +52,94 @@ __device__ __forceinline__ int det_scale_exp(const unsigned long long* amax, siz
   return 62 - e;
 }
 
-// One thread per record slot of the group: the w x w taps of its ES kernel
-// (the same footprint, kernel and periodic wrap as the tiled spreading) added
-// to acc[pair][y][x][re, im] as integers.
+// Sub-tiles of the deterministic spreading: TB x TB bins with TB = min(4, 64 /
+// BIN), at most 64 x 64 cells, so that a block's (re, im) int64 accumulator
+// takes at most 64 KiB of LDS.  A sub-tile's block scans the (TB + 2)^2 bins
+// around it (w / 2 <= BIN: one bin of border holds every record whose kernel
+// footprint reaches the sub-tile).
+__host__ __device__ __forceinline__ int det_tb(const BinGeom& g) {
+  return g.bin >= 64 ? 1 : (64 / g.bin < 4 ? 64 / g.bin : 4);
+}
+constexpr int kDetSlices = 255;      // most slices of one sub-tile
+
+__device__ __forceinline__ int det_bin_key(const BinGeom& g, int tb, int sy, int sx, int k) {
+  const int by = k / (tb + 2) - 1, bx = k % (tb + 2) - 1;
+  return bin_key((sy * tb + by + g.nb) % g.nb, (sx * tb + bx + g.nb) % g.nb, g);
+}
+
+// Slices per (pair of the group, sub-tile): S = ceil(records scanned / target),
+// at most kDetSlices; slices 1 .. S - 1 of a heavy sub-tile go to the list
+// (entry: pair * sub-tiles + sub-tile, slice), their count to *n_heavy (zero at
+// launch).  The list's order varies between runs; the integer sums do not.
+static __global__ __launch_bounds__(256) void k_det_slices(const unsigned long long* offsets,
+                                                    BinGeom g, int pair0, int npairs,
+                                                    unsigned long long target,
+                                                    unsigned char* slices, uint2* heavy,
+                                                    unsigned int* n_heavy) {
+  const int tb = det_tb(g), nsx = g.nb / tb, ns = nsx * nsx;
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)npairs * ns) return;
+  const int pl = (int)(i / ns), t = (int)(i % ns);
+  const unsigned long long* off = offsets + (size_t)(pair0 + pl) * g.keys;
+  unsigned long long n = 0;
+  for (int k = 0; k < (tb + 2) * (tb + 2); ++k) {
+    const int key = det_bin_key(g, tb, t / nsx, t % nsx, k);
+    n += off[key + 1] - off[key];
+  }
+  const int S = (int)min((unsigned long long)kDetSlices, max(1ull, (n + target - 1) / target));
+  slices[i] = (unsigned char)S;
+  if (S > 1) {
+    const unsigned int b = atomicAdd(n_heavy, (unsigned int)(S - 1));
+    for (int k = 1; k < S; ++k) heavy[b + k - 1] = make_uint2((unsigned int)i, (unsigned int)k);
+  }
+}
+
+// One slice of one sub-tile: each lane takes a record of the scan range, and
+// its taps that land in the sub-tile (the same footprint, ES kernel and periodic
+// wrap as the tiled spreading) are added to the LDS accumulator as integers;
+// the sub-tile is then added to the group's integer grid (nonzero cells only).
 template <class Tg, int w>
-__global__ __launch_bounds__(256) void k_det_spread(const void* rec_pos, const void* rec_val,
-                                                    size_t per_pair, int npairs, int nf,
-                                                    double beta, size_t n_bound,
-                                                    const unsigned long long* amax,
-                                                    unsigned long long* acc) {
+__device__ __forceinline__ void det_tile(const void* srt_pos, const void* srt_val,
+                                         const unsigned long long* offsets, const BinGeom& g,
+                                         double beta, int pair0, int pl, int t, int slice, int S,
+                                         double sc, unsigned long long* acc) {
   using U = typename RecPos<Tg>::T;
-  const U* pos = (const U*)rec_pos;
-  const C2<Tg>* val = (const C2<Tg>*)rec_val;
-  const double sc = ldexp(1.0, det_scale_exp(amax, n_bound));
+  extern __shared__ unsigned long long s_acc[];
+  __shared__ unsigned long long s_beg[36], s_pre[37];
+  const int tb = det_tb(g), nsx = g.nb / tb, side = tb * g.bin, nbins = (tb + 2) * (tb + 2);
+  const int sy = t / nsx, sx = t % nsx, x0 = sx * side, y0 = sy * side;
+  const int nf = g.nf, tid = threadIdx.x;
+  const U* pos = (const U*)srt_pos;
+  const C2<Tg>* val = (const C2<Tg>*)srt_val;
+  const unsigned long long* off = offsets + (size_t)(pair0 + pl) * g.keys;
+  __syncthreads();                              // LDS reuse across the entries of a block
+  for (int i = tid; i < 2 * side * side; i += blockDim.x) s_acc[i] = 0ull;
+  if (tid < nbins) {
+    const int key = det_bin_key(g, tb, sy, sx, tid);
+    s_beg[tid] = off[key];
+    s_pre[tid + 1] = off[key + 1] - off[key];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    s_pre[0] = 0;
+    for (int i = 1; i <= nbins; ++i) s_pre[i] += s_pre[i - 1];
+  }
+  __syncthreads();
+  const unsigned long long nall = s_pre[nbins];
+  const unsigned long long jlo = nall * (unsigned long long)slice / (unsigned long long)S;
+  const unsigned long long jhi = nall * (unsigned long long)(slice + 1) / (unsigned long long)S;
   const double two_w = 2.0 / w;
-  const size_t n = per_pair * (size_t)npairs;
-  for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
-       r += (size_t)gridDim.x * blockDim.x) {
+  int b = 0;                                    // bin of record j (j grows per lane)
+  for (unsigned long long j = jlo + tid; j < jhi; j += blockDim.x) {
+    while (j >= s_pre[b + 1]) ++b;
+    const unsigned long long r = s_beg[b] + (j - s_pre[b]);
     const C2<Tg> v = val[r];
     if (is_none(v)) continue;
-    const size_t pl = r / per_pair;
     const double gx = turns_to_cells(pos[2 * r], nf), gy = turns_to_cells(pos[2 * r + 1], nf);
     const int lx0 = (int)ceil(gx - 0.5 * w), ly0 = (int)ceil(gy - 0.5 * w);
+    // first tap relative to the sub-tile origin, in [-w, nf - w) (nf >= side + w)
+    const int dx = ((lx0 - x0 + w) & (nf - 1)) - w, dy = ((ly0 - y0 + w) & (nf - 1)) - w;
+    if (dx <= -w || dx >= side || dy <= -w || dy >= side) continue;
     double kx[w], ky[w];
 #pragma unroll
     for (int i = 0; i < w; ++i) {
@@ -80,19 +147,55 @@ __global__ __launch_bounds__(256) void k_det_spread(const void* rec_pos, const v
       ky[i] = es_kernel<double>((double)i - (gy - ly0), two_w, beta);
     }
     const double vr = (double)v.re * sc, vi = (double)v.im * sc;
-    unsigned long long* ap = acc + pl * (size_t)nf * nf * 2;
-    for (int j = 0; j < w; ++j) {
-      const size_t row = (size_t)((ly0 + j) & (nf - 1)) * nf;
+    for (int jj = 0; jj < w; ++jj) {
+      const int cy = dy + jj;
+      if ((unsigned)cy >= (unsigned)side) continue;
 #pragma unroll
       for (int i = 0; i < w; ++i) {
-        const double kk = kx[i] * ky[j];
-        if (kk == 0.0) continue;
+        const int cx = dx + i;
+        if ((unsigned)cx >= (unsigned)side) continue;
+        const double kk = kx[i] * ky[jj];
         const long long re = llrint(vr * kk), im = llrint(vi * kk);
-        unsigned long long* d = ap + (row + ((lx0 + i) & (nf - 1))) * 2;
+        unsigned long long* d = s_acc + 2 * (cy * side + cx);
         if (re) atomicAdd(d, (unsigned long long)re);
         if (im) atomicAdd(d + 1, (unsigned long long)im);
       }
     }
+  }
+  __syncthreads();
+  unsigned long long* ap = acc + (size_t)pl * nf * nf * 2;
+  for (int i = tid; i < side * side; i += blockDim.x) {
+    const int cy = i / side, cx = i % side;
+    const unsigned long long re = s_acc[2 * i], im = s_acc[2 * i + 1];
+    unsigned long long* d = ap + ((size_t)(y0 + cy) * nf + x0 + cx) * 2;
+    if (re) atomicAdd(d, re);
+    if (im) atomicAdd(d + 1, im);
+  }
+}
+
+// heavy == null: one block per (sub-tile, pair of the group), slice 0 of the
+// sub-tile's S; else the listed further slices, taken in turn by the blocks.
+template <class Tg, int w>
+__global__ __launch_bounds__(256) void k_det_tiles(const void* srt_pos, const void* srt_val,
+                                                   const unsigned long long* offsets, BinGeom g,
+                                                   double beta, int pair0, size_t n_bound,
+                                                   const unsigned long long* amax,
+                                                   unsigned long long* acc,
+                                                   const unsigned char* slices,
+                                                   const uint2* heavy,
+                                                   const unsigned int* n_heavy) {
+  const int tb = det_tb(g), ns = (g.nb / tb) * (g.nb / tb);
+  const double sc = ldexp(1.0, det_scale_exp(amax, n_bound));
+  if (!heavy) {
+    det_tile<Tg, w>(srt_pos, srt_val, offsets, g, beta, pair0, blockIdx.y, blockIdx.x, 0,
+                    slices[(size_t)blockIdx.y * ns + blockIdx.x], sc, acc);
+    return;
+  }
+  const unsigned int n = *n_heavy;
+  for (unsigned int e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint2 h = heavy[e];
+    det_tile<Tg, w>(srt_pos, srt_val, offsets, g, beta, pair0, (int)(h.x / ns), (int)(h.x % ns),
+                    (int)h.y, slices[h.x], sc, acc);
   }
 }
 
