@@ -127,3 +127,40 @@ def test_deterministic_refuses_gradients(rw):
     with pytest.raises(rw.RWError, match="RW_ERR_UNSUPPORTED"):
         plan.step(vals, ph, am, tg)
     torch.cuda.synchronize()
+
+
+def test_deterministic_plain_fp32_per_pair_launches(rw):
+    """FP32 everywhere, one launch per pair: the phase drift of the FP32 trace is
+    the tiled path's too, so the two PSFs agree to the taps' rounding."""
+    system, cfg, maps = small_hologram(rays=8)
+    print("deterministic plain fp32", flush=True)
+    det = dict(cfg, deterministic=True)
+    plan = rw.Plan(system, det, precision="fp32", batched=False)
+    p1, l1 = _fwd(plan, system, maps)
+    p2, l2 = _fwd(plan, system, maps)
+    assert torch.equal(p1, p2) and torch.equal(l1, l2)
+    tiled, _ = _fwd(rw.Plan(system, cfg, precision="fp32", batched=False), system, maps)
+    assert rel_l2(p1.cpu().numpy(), tiled.cpu().numpy()) < 1e-5
+
+
+def test_deterministic_class_draws_fp64(rw):
+    """Adaptive patch sizing with per-class draw counts: the slots beyond a ray's
+    count hold no record.  FP64 draws match the oracle's bit for bit, the PSF
+    within 1e-6."""
+    system, cfg, maps = W.adaptive_zone_plate(rays_side=16, H=256, pitch=0.002, f=5.0, P=32,
+                                              classes=(16, 8), N=32, Q=32, psf_pitch=0.002,
+                                              sampling="mag")
+    cfg = dict(cfg, class_draws=True, deterministic=True)
+    print("deterministic class draws fp64", flush=True)
+    plan = rw.Plan(system, cfg, precision="fp64")
+    vals, ph, am = gpu_inputs(system, maps)
+    psf, _, idx = plan.forward(vals, ph, am, want_idx=True)
+    torch.cuda.synchronize()
+    p1 = psf.clone()
+    p2, _ = _fwd(plan, system, maps, target=False)
+    assert torch.equal(p1, p2)
+    ref, aux = oracle_psf(system, cfg, maps, keep=True)
+    J = aux[0]["J"]
+    assert (J < 0).any()                                 # empty slots in play
+    assert np.array_equal(idx.cpu().numpy()[0], J)
+    assert worst_pair_rel(p1.cpu().numpy(), ref) < 1e-6
