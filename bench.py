@@ -235,6 +235,68 @@ def next_rows(iters=3):
     print(json.dumps({"ms_fwd_bwd": out}), flush=True)
 
 
+def lens_param_values(system):
+    """The system's lens parameters in the plan's normalised units (float32)."""
+    import numpy as np
+    vals = []
+    for ref in system["params"]:
+        s, f = ref["surface"], ref["field"]
+        surf = system["surfaces"][s]
+        if f == "curv":
+            phys = surf["c"]
+        elif f == "gap":
+            znext = (system["surfaces"][s + 1]["z"] if s + 1 < len(system["surfaces"])
+                     else system["sensor_z"])
+            phys = znext - surf["z"]
+        else:
+            phys = surf["A"][("A4", "A6", "A8", "A10").index(f)]
+        vals.append(phys / ref["scale"])
+    return np.array(vals, dtype=np.float32)
+
+
+def deterministic_forward(iters=4):
+    """Forward of the asphere-hologram workload (MIXED, batched) with the tiled
+    spreading and with the deterministic fixed-point spreading, `iters` timed
+    forwards each after one untimed: wall time per forward, the binning and
+    spreading stages (HIP events), whether the timed forwards repeat bit for bit,
+    and the relative L2 distance of the two PSFs.  One JSON line."""
+    import numpy as np
+    import torch
+    import paper_2605_15418_amd as rw
+    import workloads as W
+    dev = torch.device("cuda:0")
+    s, c, m = W.asphere_hologram()
+    v = torch.tensor(lens_param_values(s), device=dev)
+    ph = torch.tensor(m["phase"], device=dev)
+    am = torch.tensor(m["amp"], device=dev)
+    out, psfs = {}, {}
+    for name, det in (("tiled", False), ("deterministic", True)):
+        plan = rw.Plan(s, dict(c, deterministic=det), precision="mixed", batched=True)
+        psf = torch.empty((plan.L, plan.F, plan.Q, plan.Q), device=dev)
+        plan.forward(v, ph, am, psf_out=psf)
+        torch.cuda.synchronize()
+        plan.set_profiling(True)
+        ms, first, same = [], None, True
+        for _ in range(iters):
+            t0 = time.perf_counter()
+            plan.forward(v, ph, am, psf_out=psf)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            if first is None:
+                first = psf.clone()
+            else:
+                same = same and torch.equal(psf, first)
+        prof = plan.profile()
+        out[name] = {"ms_forward": round(min(ms), 2), "repeats_bitwise": bool(same),
+                     **{f"ms_{k}": round(prof[k][0] / iters, 2) for k in ("bin", "spread")}}
+        psfs[name] = first.cpu().numpy().astype(np.float64)
+        del plan
+        torch.cuda.empty_cache()
+    a, b = psfs["deterministic"], psfs["tiled"]
+    out["rel_l2_deterministic_vs_tiled"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print(json.dumps({"workload": "asphere_hologram", "forward": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,7 +321,13 @@ def main():
     ap.add_argument("--next-rows", action="store_true",
                     help="only the forward + backward of the two-DOE cascade and of adaptive "
                          "patch sizing with class draw budgets, three times each (for traces)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="only the forward of the asphere hologram with the tiled and with the "
+                         "deterministic spreading")
     args = ap.parse_args()
+    if args.deterministic:
+        deterministic_forward()
+        return
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
         return
@@ -286,20 +354,7 @@ def main():
     dev = torch.device("cuda:0")
 
     def inputs(system, maps):
-        vals = []
-        for ref in system["params"]:
-            s, f = ref["surface"], ref["field"]
-            surf = system["surfaces"][s]
-            if f == "curv":
-                phys = surf["c"]
-            elif f == "gap":
-                znext = (system["surfaces"][s + 1]["z"] if s + 1 < len(system["surfaces"])
-                         else system["sensor_z"])
-                phys = znext - surf["z"]
-            else:
-                phys = surf["A"][("A4", "A6", "A8", "A10").index(f)]
-            vals.append(phys / ref["scale"])
-        v = torch.tensor(np.array(vals, dtype=np.float32), device=dev)
+        v = torch.tensor(lens_param_values(system), device=dev)
         ph = torch.tensor(maps["phase"], device=dev)
         am = torch.tensor(maps["amp"], device=dev)
         tg = None if maps["target"] is None else torch.tensor(maps["target"], device=dev)
